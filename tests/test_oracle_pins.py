@@ -1,0 +1,425 @@
+"""Pins for the CPU oracle: closed forms, limits, invariants and library routines.
+
+None of these tests re-types the oracle's formulas: each one checks it against
+something the paper or the mathematics fixes independently (a quaternion
+sandwich product, an FD Jacobian, scipy's spherical harmonics, closed-form
+composites of one or two Gaussians, the in-air reduction, the veiling-light
+limit, torch's Adam).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2411_19588_amd import synth
+
+
+def _cam(w, h, f, cx=None, cy=None, R=None, t=None):
+    return synth.Camera(w, h, float(np.float32(f)), float(np.float32(f)),
+                        float(w / 2.0 if cx is None else cx), float(h / 2.0 if cy is None else cy),
+                        np.eye(3, dtype=np.float32) if R is None else np.asarray(R, np.float32),
+                        np.zeros(3, np.float32) if t is None else np.asarray(t, np.float32))
+
+
+def _scene(means, scales, quats, opacity, colors=None, sh=None, deg=0, medium=None, cams=None):
+    means = np.asarray(means, np.float64).T.astype(np.float32)
+    n = means.shape[1]
+    if sh is None:
+        colors = np.asarray(colors, np.float64).reshape(n, 3).T
+        sh = ((colors - 0.5) * 2.0 * math.sqrt(math.pi)).astype(np.float32)
+    med = np.zeros((1, 9), np.float32) if medium is None else np.asarray(medium, np.float32).reshape(1, 9)
+    return synth.Scene(means=means, log_scales=np.log(np.asarray(scales, np.float32).T),
+                       scales=np.asarray(scales, np.float32).T.copy(), quats=np.asarray(quats, np.float32).T.copy(),
+                       logits=np.zeros(n, np.float32), opacity=np.asarray(opacity, np.float32),
+                       sh=np.asarray(sh, np.float32), sh_degree=deg, cameras=cams or [], medium=med)
+
+
+def _qmul(a, b):
+    w1, x1, y1, z1 = a
+    w2, x2, y2, z2 = b
+    return np.array([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                     w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
+
+
+def _rot_sandwich(q):
+    """Rotation matrix whose columns are q e_k q* (quaternion sandwich)."""
+    q = np.asarray(q, np.float64) / np.linalg.norm(q)
+    qc = q * np.array([1, -1, -1, -1])
+    cols = [_qmul(_qmul(q, np.r_[0.0, e]), qc)[1:] for e in np.eye(3)]
+    return np.stack(cols, axis=1)
+
+
+# --------------------------------------------------------------------------- projection
+def test_projected_covariance_matches_sandwich_and_fd_jacobian(oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(5)
+    cam = synth.look_at((0.3, -0.2, -0.4), (0.2, 0.1, 5.0), 64, 48)
+    n = 40
+    means = np.c_[rng.uniform(-1, 1, n), rng.uniform(-1, 1, n), rng.uniform(2, 6, n)]
+    scales = np.exp(rng.normal(-2, 0.5, (n, 3)))
+    quats = rng.normal(size=(n, 4))
+    sc = _scene(means, scales, quats, np.full(n, 0.5), colors=np.full((n, 3), 0.5))
+    # the oracle works in FP64 on the FP32-rounded inputs
+    means = sc.means.T.astype(np.float64)
+    scales = sc.scales.T.astype(np.float64)
+    quats = sc.quats.T.astype(np.float64)
+    pr = O.project(sc, cam)
+    Rv = np.asarray(cam.R, np.float64)
+    tv = np.asarray(cam.t, np.float64)
+
+    def pi(t):
+        return np.array([cam.fx * t[0] / t[2] + cam.cx, cam.fy * t[1] / t[2] + cam.cy])
+
+    for i in range(n):
+        t = Rv @ means[i] + tv
+        h = 1e-5
+        J = np.stack([(pi(t + h * e) - pi(t - h * e)) / (2 * h) for e in np.eye(3)], axis=1)
+        Rq = _rot_sandwich(quats[i])
+        Sig = Rq @ np.diag(scales[i] ** 2) @ Rq.T
+        cov = J @ Rv @ Sig @ Rv.T @ J.T + 0.3 * np.eye(2)
+        np.testing.assert_allclose(pr["cov"][i], [cov[0, 0], cov[0, 1], cov[1, 1]], rtol=1e-7, atol=1e-9)
+        np.testing.assert_allclose(pr["mean2d"][i], pi(t), rtol=1e-12)
+        np.testing.assert_allclose(pr["depth"][i], t[2], rtol=1e-12)
+        a, b, c = pr["cov"][i]
+        Qm = np.linalg.inv(np.array([[a, b], [b, c]]))
+        np.testing.assert_allclose(pr["conic"][i], [Qm[0, 0], Qm[0, 1], Qm[1, 1]], rtol=1e-12)
+
+
+def test_isotropic_on_axis_closed_form(oracle_mod):
+    O = oracle_mod
+    f, d, s = 100.0, 3.0, 0.07
+    cam = _cam(32, 32, f)
+    sc = _scene([[0, 0, d]], [[s, s, s]], [[0.3, -0.5, 0.7, 0.1]], [0.8], colors=[[0.2, 0.4, 0.6]])
+    pr = O.project(sc, cam)
+    s32 = float(np.float32(s))
+    v = (f * s32 / d) ** 2 + float(np.float32(0.3))   # both sides use the FP32 value of the dilation
+    np.testing.assert_allclose(pr["cov"][0], [v, 0.0, v], rtol=1e-12, atol=1e-12)
+
+
+# --------------------------------------------------------------------------- spherical harmonics
+def test_sh_matches_scipy_real_basis(oracle_mod):
+    from scipy.special import sph_harm_y
+    O = oracle_mod
+    rng = np.random.default_rng(1)
+    dirs = rng.normal(size=(50, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    Y = O.sh_basis(3, dirs)
+    theta = np.arccos(np.clip(dirs[:, 2], -1, 1))
+    phi = np.arctan2(dirs[:, 1], dirs[:, 0])
+    for l in range(4):
+        for m in range(-l, l + 1):
+            k = l * l + l + m
+            if m == 0:
+                ref = sph_harm_y(l, 0, theta, phi).real
+            elif m > 0:
+                ref = math.sqrt(2) * sph_harm_y(l, m, theta, phi).real
+            else:
+                ref = math.sqrt(2) * sph_harm_y(l, -m, theta, phi).imag
+            np.testing.assert_allclose(Y[:, k], ref, atol=1e-12, err_msg=f"l={l} m={m}")
+
+
+def test_sh_orthonormal_by_quadrature(oracle_mod):
+    O = oracle_mod
+    xg, wg = np.polynomial.legendre.leggauss(12)
+    nphi = 24
+    phis = 2 * np.pi * np.arange(nphi) / nphi
+    ct, ph = np.meshgrid(xg, phis, indexing="ij")
+    st = np.sqrt(1 - ct ** 2)
+    dirs = np.stack([st * np.cos(ph), st * np.sin(ph), ct], -1).reshape(-1, 3)
+    w = (np.repeat(wg, nphi) * (2 * np.pi / nphi))
+    Y = O.sh_basis(3, dirs)
+    G = (Y * w[:, None]).T @ Y
+    np.testing.assert_allclose(G, np.eye(16), atol=1e-12)
+    # addition theorem: sum_m Y_lm^2 = (2l+1)/(4 pi) for every direction
+    for l in range(4):
+        s = np.sum(Y[:, l * l:(l + 1) ** 2] ** 2, axis=1)
+        np.testing.assert_allclose(s, (2 * l + 1) / (4 * np.pi), rtol=1e-12)
+
+
+# --------------------------------------------------------------------------- compositing closed forms
+def _colour_of(sc, i):
+    """Degree-0 colour 1/2 + Y00 k00 of Gaussian i, Y00 = 1/(2 sqrt(pi)), from the stored FP32 SH."""
+    return 0.5 + sc.sh[:3, i].astype(np.float64) / (2.0 * math.sqrt(math.pi))
+
+
+def _alpha_iso(o, f, s, d, r2):
+    v = (f * float(np.float32(s)) / d) ** 2 + float(np.float32(0.3))
+    return min(0.99, o * math.exp(-r2 / (2 * v)))
+
+
+def test_single_gaussian_closed_form(oracle_mod):
+    O = oracle_mod
+    f, d, s, o = 40.0, 2.5, 0.05, 0.7
+    c = np.array([0.3, 0.6, 0.9])
+    med = np.array([0.2, 0.3, 0.4, 0.1, 0.25, 0.45, 0.05, 0.15, 0.28], np.float32)
+    cam = _cam(24, 20, f, cx=12.0, cy=10.0)
+    sc = _scene([[0, 0, d]], [[s, s, s]], [[1, 0, 0, 0]], [o], colors=[c], medium=med)
+    out = O.render(sc, cam, med)
+    Bd, Bb, Binf = med[:3].astype(np.float64), med[3:6].astype(np.float64), med[6:].astype(np.float64)
+    cc = _colour_of(sc, 0)
+    n_in = 0
+    for k, (u, v) in enumerate(O.all_pixels(cam)):
+        r2 = (u + 0.5 - 12.0) ** 2 + (v + 0.5 - 10.0) ** 2
+        a = _alpha_iso(float(np.float32(o)), f, s, d, r2)
+        if a >= 1 / 255:
+            n_in += 1
+            ref = cc * a * np.exp(-Bd * d) + Binf * (1 - np.exp(-Bb * d))
+            np.testing.assert_allclose(out["rgb"][k], ref, rtol=1e-12, atol=1e-14)
+            assert out["depth"][k] == pytest.approx(d, rel=1e-13)
+            assert out["alpha"][k] == pytest.approx(a, rel=1e-13)
+        else:
+            np.testing.assert_allclose(out["rgb"][k], Binf, rtol=1e-15)   # empty pixel: infinite range
+            assert out["alpha"][k] == 0.0
+    assert n_in > 20
+
+
+def test_two_gaussians_closed_form_and_order_independence(oracle_mod):
+    O = oracle_mod
+    f = 30.0
+    cam = _cam(16, 16, f, cx=8.0, cy=8.0)
+    c1, c2 = np.array([0.9, 0.2, 0.1]), np.array([0.1, 0.8, 0.3])
+    med = np.array([0.3, 0.2, 0.1, 0.2, 0.3, 0.4, 0.1, 0.2, 0.3], np.float32)
+    d1, d2, s1, s2, o1, o2 = 2.0, 4.0, 0.1, 0.2, 0.6, 0.9
+    sa = _scene([[0, 0, d1], [0, 0, d2]], [[s1] * 3, [s2] * 3], [[1, 0, 0, 0]] * 2, [o1, o2], colors=[c1, c2],
+                medium=med)
+    sb = _scene([[0, 0, d2], [0, 0, d1]], [[s2] * 3, [s1] * 3], [[1, 0, 0, 0]] * 2, [o2, o1], colors=[c2, c1],
+                medium=med)
+    oa, ob = O.render(sa, cam, med), O.render(sb, cam, med)
+    for key in ("rgb", "depth", "alpha", "tfinal"):
+        np.testing.assert_allclose(oa[key], ob[key], rtol=1e-14, atol=0)
+    C1, C2 = _colour_of(sa, 0), _colour_of(sa, 1)
+    Bd, Bb, Binf = [med[i:i + 3].astype(np.float64) for i in (0, 3, 6)]
+    checked = 0
+    for k, (u, v) in enumerate(O.all_pixels(cam)):
+        r2 = (u + 0.5 - 8) ** 2 + (v + 0.5 - 8) ** 2
+        a1 = _alpha_iso(float(np.float32(o1)), f, s1, d1, r2)
+        a2 = _alpha_iso(float(np.float32(o2)), f, s2, d2, r2)
+        if a1 < 1 / 255 or a2 < 1 / 255:
+            continue
+        C = C1 * a1 + C2 * a2 * (1 - a1)
+        z = (d1 * a1 + d2 * a2 * (1 - a1)) / (a1 + a2 * (1 - a1))
+        ref = C * np.exp(-Bd * z) + Binf * (1 - np.exp(-Bb * z))
+        np.testing.assert_allclose(oa["rgb"][k], ref, rtol=1e-12)
+        assert oa["depth"][k] == pytest.approx(z, rel=1e-12)
+        checked += 1
+    assert checked > 10
+
+
+def test_termination_stacked_gaussians(oracle_mod):
+    """alpha = 0.95 stack: T = 1, .05, .0025, 1.25e-4; the 4th would give 6.25e-6 < 1e-4."""
+    O = oracle_mod
+    cam = _cam(16, 16, 30.0, cx=8.5, cy=8.5)
+    n = 6
+    ds = [2.0 + 0.5 * i for i in range(n)]
+    cols = [[0.1 * (i + 1), 0.5, 0.9 - 0.1 * i] for i in range(n)]
+    sc = _scene([[0, 0, d] for d in ds], [[0.05] * 3] * n, [[1, 0, 0, 0]] * n, [0.95] * n, colors=cols)
+    out = O.render(sc, cam, np.zeros(9), pixels=np.array([[8, 8]], np.int32))
+    assert out["ncontrib"][0] == 3
+    a = float(np.float32(0.95))
+    C = sum(_colour_of(sc, i) * a * (1 - a) ** i for i in range(3))
+    np.testing.assert_allclose(out["rgb"][0], C, rtol=1e-12)
+    assert out["tfinal"][0] == pytest.approx((1 - a) ** 3, rel=1e-12)
+
+
+def test_zero_medium_is_in_air_compositing(oracle_mod):
+    O = oracle_mod
+    sc = synth.make_scene(0, n=300, width=40, height=32)
+    cam = sc.cameras[0]
+    med0 = np.zeros(9)
+    out = O.render(sc, cam, med0)
+    np.testing.assert_array_equal(out["rgb"], out["cair"])   # exp(0) = 1 exactly
+    # and the medium never changes the in-air accumulators
+    out2 = O.render(sc, cam, sc.medium[0])
+    np.testing.assert_array_equal(out["cair"], out2["cair"])
+    np.testing.assert_array_equal(out["alpha"], out2["alpha"])
+
+
+def test_veiling_light_limit_and_affinity_in_binf(oracle_mod):
+    O = oracle_mod
+    f, d = 800.0, 60.0
+    cam = _cam(16, 16, f, cx=8.0, cy=8.0)
+    sc = _scene([[0, 0, d]], [[0.6] * 3], [[1, 0, 0, 0]], [0.9], colors=[[0.9, 0.8, 0.7]])
+    med = np.array([1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 0.2, 0.5, 0.7])
+    out = O.render(sc, cam, med, pixels=np.array([[8, 8]], np.int32))
+    assert out["depth"][0] == pytest.approx(d, rel=1e-12)
+    np.testing.assert_allclose(out["rgb"][0], med[6:], atol=1e-25)
+    # C_uw is affine in B_inf with slope 1 - exp(-B_b z)
+    med2 = np.array([0.01, 0.02, 0.03, 0.01, 0.015, 0.02, 0.0, 0.0, 0.0])
+    o0 = O.render(sc, cam, med2, pixels=np.array([[8, 8]], np.int32))["rgb"][0]
+    med2[6:] = [1.0, 2.0, 3.0]
+    o1 = O.render(sc, cam, med2, pixels=np.array([[8, 8]], np.int32))["rgb"][0]
+    slope = (o1 - o0) / np.array([1.0, 2.0, 3.0])
+    np.testing.assert_allclose(slope, 1 - np.exp(-med2[3:6] * d), rtol=1e-10)
+
+
+def test_invariants_config0(oracle_mod):
+    O = oracle_mod
+    sc = synth.make_scene(0)
+    cam = sc.cameras[0]
+    out = O.render(sc, cam, sc.medium[0])
+    T = out["tfinal"]
+    assert np.all(T > 0) and np.all(T <= 1)
+    assert np.all(T >= 1e-4 * (1 - 1e-12))          # termination keeps T >= t_min
+    np.testing.assert_allclose(out["alpha"] + T, 1.0, atol=1e-12)   # W = 1 - T_final
+    pr = O.project(sc, cam)
+    full = out["alpha"] > 0
+    dmin, dmax = pr["depth"].min(), pr["depth"].max()
+    assert np.all(out["depth"][full] >= dmin - 1e-12) and np.all(out["depth"][full] <= dmax + 1e-12)
+    # permutation of the input order changes nothing (ties are broken by the key path's FP32 depth,
+    # which is distinct here)
+    perm = np.random.default_rng(0).permutation(sc.n)
+    sp = synth.Scene(means=sc.means[:, perm], log_scales=sc.log_scales[:, perm], scales=sc.scales[:, perm],
+                     quats=sc.quats[:, perm], logits=sc.logits[perm], opacity=sc.opacity[perm],
+                     sh=sc.sh[:, perm], sh_degree=0, cameras=sc.cameras, medium=sc.medium)
+    dbits, _, culled = O.key_path(sc, cam)
+    assert len(np.unique(dbits[~culled])) == np.count_nonzero(~culled)
+    outp = O.render(sp, cam, sc.medium[0])
+    np.testing.assert_allclose(outp["rgb"], out["rgb"], rtol=0, atol=1e-13)
+
+
+def test_cair_linear_in_colour(oracle_mod):
+    O = oracle_mod
+    sc = synth.make_scene(0, n=200, width=32, height=32)
+    cam = sc.cameras[0]
+    base = O.render(sc, cam, np.zeros(9))
+    y00 = 0.5 / math.sqrt(math.pi)
+    col = 0.5 + sc.sh.astype(np.float64) * y00          # colours of the degree-0 scene
+    sh2 = (0.5 * col - 0.5) / y00                        # half the colour
+    half = O.render(sc, cam, np.zeros(9), sh=sh2)
+    np.testing.assert_allclose(half["cair"], 0.5 * base["cair"], rtol=1e-12, atol=1e-15)
+
+
+def test_logistic_depth_mode(oracle_mod):
+    O = oracle_mod
+    sc = synth.make_scene(0, n=200, width=32, height=32)
+    cam = sc.cameras[0]
+    a = O.render(sc, cam, sc.medium[0])
+    b = O.render(sc, cam, sc.medium[0], opts=O.Options(depth_mode=1))
+    full = a["alpha"] > 0
+    np.testing.assert_allclose(b["depth"][full], np.tanh(0.05 * a["depth"][full]), rtol=1e-12)
+    assert np.all((b["depth"] >= 0) & (b["depth"] < 1))
+
+
+# --------------------------------------------------------------------------- keys
+def test_keys_sorted_and_coverage(oracle_mod):
+    O = oracle_mod
+    sc = synth.make_scene(1, n=3000, width=100, height=70)
+    cam = sc.cameras[0]
+    k, v, counts = O.keys(sc)
+    assert np.all(np.diff(k.astype(np.uint64)) >= 0)
+    assert counts.sum() == k.size
+    tiles_x, tiles_y = O.tiles_of(cam)
+    assert counts.size == tiles_x * tiles_y
+    # equal keys keep ascending Gaussian order
+    same = np.nonzero(np.diff(k) == 0)[0]
+    assert np.all(v[same] < v[same + 1])
+    # coverage invariant: every (pixel, Gaussian) with FP64 alpha >= 1/255 is listed for the pixel's tile
+    pr = O.project(sc, cam)
+    dbits, rect, culled = O.key_path(sc, cam)
+    pix = O.all_pixels(cam)
+    px, py = pix[:, 0] + 0.5, pix[:, 1] + 0.5
+    for g in np.nonzero(~culled)[0]:
+        dx = px - pr["mean2d"][g, 0]
+        dy = py - pr["mean2d"][g, 1]
+        Q = pr["conic"][g]
+        q = Q[0] * dx * dx + 2 * Q[1] * dx * dy + Q[2] * dy * dy
+        a = np.minimum(0.99, sc.opacity[g] * np.exp(-0.5 * q))
+        hit = a >= 1 / 255
+        if not hit.any():
+            continue
+        tx, ty = pix[hit, 0] // 16, pix[hit, 1] // 16
+        x0, y0, x1, y1 = rect[g]
+        assert np.all((tx >= x0) & (tx <= x1) & (ty >= y0) & (ty <= y1)), g
+    # culled Gaussians are exactly those at or behind the near plane (FP32 depth)
+    fd = np.frombuffer(dbits.tobytes(), np.float32)
+    assert np.all(fd[~culled] > np.float32(0.2))
+
+
+# --------------------------------------------------------------------------- gradients vs central differences
+@pytest.mark.parametrize("depth_mode,with_gz,deg", [(0, False, 3), (0, True, 1), (1, True, 3)])
+def test_backward_matches_central_differences(oracle_mod, depth_mode, with_gz, deg):
+    O = oracle_mod
+    sc = synth.custom_scene(seed=11 + depth_mode + deg, n=25, sh_degree=deg, width=24, height=20, f=30.0,
+                            log_scale_mean=-2.0, sh_std=0.3)
+    cam = sc.cameras[0]
+    opts = O.Options(depth_mode=depth_mode)
+    rng = np.random.default_rng(3)
+    P = cam.width * cam.height
+    G = rng.normal(size=(P, 3))
+    Gz = rng.normal(size=P) if with_gz else None
+    med = sc.medium[0].astype(np.float64)
+    an = O.backward(sc, cam, med, G, Gz, opts)
+    checked = 0
+    fields = dict(means=(3,), scales=(3,), quats=(4,), opacity=(), sh=((deg + 1) ** 2 * 3,))
+    live = np.nonzero(np.any(an["g2d"] != 0, axis=1))[0]
+    assert live.size > 5
+    for g in live[:8]:
+        for field, shp in fields.items():
+            idxs = [(g,)] if not shp else [(r, g) for r in range(shp[0])]
+            for idx in idxs:
+                fd, ok = O.fd_grad(sc, cam, med, G, field, idx, Gz, opts)
+                if not ok:
+                    continue
+                a = an[field][idx]
+                assert abs(a - fd) <= 2e-6 * max(1.0, abs(fd)) + 1e-7 * np.max(np.abs(an[field])), \
+                    (field, idx, a, fd)
+                checked += 1
+    for j in range(9):
+        fd, ok = O.fd_grad(sc, cam, med, G, "medium", j, Gz, opts)
+        if ok:
+            assert abs(an["medium"][j] - fd) <= 2e-6 * max(1.0, abs(fd)), (j, an["medium"][j], fd)
+            checked += 1
+    assert checked > 100
+
+
+def test_backward_empty_pixels_medium_gradient(oracle_mod):
+    """A frame with no Gaussian in view: C_uw = B_inf where B_b > 0, so dL/dB_inf = sum G."""
+    O = oracle_mod
+    cam = _cam(8, 8, 10.0)
+    sc = _scene([[0, 0, -3.0]], [[0.1] * 3], [[1, 0, 0, 0]], [0.5], colors=[[0.5, 0.5, 0.5]])
+    G = np.random.default_rng(0).normal(size=(64, 3))
+    med = np.array([0.1, 0.2, 0.3, 0.2, 0.0, 0.1, 0.3, 0.2, 0.1])
+    an = O.backward(sc, cam, med, G)
+    np.testing.assert_allclose(an["medium"][6:], G.sum(0) * (med[3:6] > 0), rtol=1e-12)
+    np.testing.assert_array_equal(an["medium"][:6], 0.0)
+    for j in range(9):
+        fd, ok = O.fd_grad(sc, cam, med, G, "medium", j)
+        if med[3 + (j % 3)] == 0 and j >= 3:
+            continue   # B_b = 0 sits on the kink of the empty-pixel rule
+        assert ok and abs(an["medium"][j] - fd) < 1e-6, j
+
+
+# --------------------------------------------------------------------------- activation / loss / Adam
+def test_adam_matches_torch(oracle_mod):
+    import torch
+    O = oracle_mod
+    rng = np.random.default_rng(2)
+    p0 = rng.normal(size=50)
+    p = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([p], lr=0.01, betas=(0.9, 0.999), eps=1e-8)
+    m = np.zeros(50)
+    v = np.zeros(50)
+    x = p0.copy()
+    for step in range(1, 6):
+        g = rng.normal(size=50)
+        p.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        x, m, v = O.adam_step(x, g, m, v, 0.01, step)
+        np.testing.assert_allclose(x, p.detach().numpy(), rtol=1e-14, atol=1e-15)
+
+
+def test_activation_and_l1_match_torch(oracle_mod):
+    import torch
+    O = oracle_mod
+    rng = np.random.default_rng(4)
+    ls, lg = rng.normal(-3, 0.5, 100), rng.normal(0, 1, 100)
+    s, o = O.activate(ls, lg)
+    np.testing.assert_allclose(s, torch.exp(torch.tensor(ls)).numpy(), rtol=1e-15)
+    np.testing.assert_allclose(o, torch.sigmoid(torch.tensor(lg)).numpy(), rtol=1e-15)
+    pred, tgt = rng.uniform(size=(3, 5, 7)), rng.uniform(size=(3, 5, 7))
+    loss, grad = O.l1_loss_grad(pred, tgt)
+    tp = torch.tensor(pred, requires_grad=True)
+    tl = torch.nn.functional.l1_loss(tp, torch.tensor(tgt))
+    tl.backward()
+    assert loss == pytest.approx(tl.item(), rel=1e-15)
+    np.testing.assert_allclose(grad, tp.grad.numpy(), rtol=1e-15)
