@@ -1,0 +1,235 @@
+/*
+ * gsplash.h -- C ABI of the MI355X (gfx950) underwater Gaussian rasterizer.
+ *
+ * The library renders N anisotropic 3D Gaussians (Preliminaries, "3D Gaussian
+ * Splatting": mean, covariance factored as rotation x scale, SH colour,
+ * opacity) into one or more pinhole views with the underwater image formation
+ * model of eq. (3dgs_uw) -- the alpha composite of eq. (3dgs_orig) attenuated
+ * by exp(-B_d z) plus backscatter B_inf (1 - exp(-B_b z)), per RGB channel --
+ * evaluated at the alpha-weighted depth z of eq. (Depth), and computes the
+ * exact adjoint of that forward (appendix "Partial Derivatives", with the
+ * factor z in dL/dB_d, dL/dB_b and the dependence of z on alpha included).
+ *
+ * Conventions shared by every entry point:
+ *   - All array pointers are DEVICE pointers unless the parameter name starts
+ *     with host_.  Floating point is FP32.  Gaussian parameters are
+ *     structure-of-arrays planes: plane k of an [K][n] array starts at k * n.
+ *   - The caller owns every buffer, including the workspace and the `saved`
+ *     forward context; the library allocates and frees no device memory and
+ *     keeps no global mutable state.
+ *   - Every compute call only enqueues work on `stream` (a hipStream_t) and
+ *     never synchronises the host, so a forward/backward sequence can be
+ *     captured into a HIP graph.  gs_read_status is the only synchronising call.
+ *   - Synchronous errors are returned as GS_ERR_*; nothing is enqueued when an
+ *     error is returned.  Asynchronous conditions (pair-capacity overflow,
+ *     non-finite inputs) are recorded in a status word inside `saved`.
+ *   - Views are packed in order: view v's pixels start at pixel offset
+ *     P_v = sum_{u<v} width_u * height_u.  Per-view images are planar CHW:
+ *     out_rgb[3 * P_v + c * (W*H) + y * W + x]; depth and alpha are
+ *     [P_v + y * W + x].
+ */
+#ifndef GSPLASH_H
+#define GSPLASH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_OK                        0
+#define GS_ERR_INVALID_ARGUMENT     -1   /* null pointer, bad size or option value */
+#define GS_ERR_UNSUPPORTED          -2   /* valid but not implemented (e.g. tile shape) */
+#define GS_ERR_WORKSPACE_TOO_SMALL  -3   /* a caller buffer is smaller than gs_workspace_query says */
+#define GS_ERR_HIP                  -4   /* a HIP runtime call failed */
+
+#define GS_STATUS_PAIR_OVERFLOW      1u  /* more (Gaussian, tile) pairs than opts.max_pairs */
+#define GS_STATUS_NONFINITE_INPUT    2u  /* a Gaussian had a non-finite parameter (it was culled) */
+
+#define GS_MAX_VIEWS                64
+#define GS_MAX_PAIRS         4000000000LL /* pair indices are 32-bit */
+
+typedef void* gs_stream_t;               /* hipStream_t; NULL = the default stream */
+
+/* Pinhole camera (Preliminaries: "given the camera pose ... a pixel defines a
+ * ray").  World -> camera: x_c = R x_w + t, R row-major.  The camera looks
+ * down +z with image y pointing down; pixel (u, v) is sampled at its centre
+ * (u + 1/2, v + 1/2); projection m = (fx x_c/z_c + cx, fy y_c/z_c + cy).
+ * Gaussians whose camera-space depth is <= near_z are culled. */
+typedef struct gs_camera {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float R[9];
+    float t[3];
+    float near_z;
+} gs_camera;
+
+/* Medium coefficients of eq. (3dgs_uw), one set per view, per RGB channel:
+ * direct attenuation B_d, backscatter attenuation B_b, veiling light B_inf. */
+typedef struct gs_medium {
+    float Bd[3], Bb[3], Binf[3];
+} gs_medium;
+
+/* Gaussian parameters (Preliminaries, theta_i).  Activated values: scales > 0
+ * (the covariance is R(q) diag(s)^2 R(q)^T), opacity in (0, 1) (the sigmoid of
+ * eq. (opacity_impact) already applied, see gs_activate).  quats are (w,x,y,z),
+ * any non-zero length (normalised inside).  sh holds (sh_degree+1)^2 * 3 planes,
+ * plane index coef * 3 + channel; colour = max(0, 1/2 + sum_lm Y_lm(dir) k_lm)
+ * with real orthonormal SH (Condon-Shortley phase) of the unit direction from
+ * the camera centre to the mean. */
+typedef struct gs_gaussians {
+    int64_t n;
+    int32_t sh_degree;                   /* 0..3 */
+    int32_t reserved;
+    const float* means;                  /* [3][n] */
+    const float* scales;                 /* [3][n] */
+    const float* quats;                  /* [4][n] */
+    const float* opacity;                /* [n]    */
+    const float* sh;                     /* [(sh_degree+1)^2 * 3][n] */
+} gs_gaussians;
+
+/* Gradients w.r.t. the gs_gaussians fields, same layouts.  OVERWRITTEN (not
+ * accumulated) by gs_render_backward; every pointer must be non-NULL. */
+typedef struct gs_gaussian_grads {
+    float* means;
+    float* scales;
+    float* quats;
+    float* opacity;
+    float* sh;
+} gs_gaussian_grads;
+
+/* Rasterizer options.  gs_default_options fills the defaults noted here. */
+typedef struct gs_options {
+    int32_t tile_w, tile_h;              /* 16x16 (default) or 8x8 pixels per tile */
+    int32_t lds_batch;                   /* records staged in LDS per batch: 64, 128 or 256 (<= tile pixels) */
+    int32_t persistent;                  /* 0: one workgroup per tile; 1: persistent workgroups pull tiles from a queue */
+    float alpha_min;                     /* 1/255: a Gaussian with alpha < alpha_min is skipped at that pixel */
+    float alpha_max;                     /* 0.99: alpha = min(alpha_max, o exp(-q/2)) */
+    float t_min;                         /* 1e-4: stop before blending a Gaussian that would leave T < t_min */
+    float dilation;                      /* 0.3: added to the diagonal of the 2D covariance (EWA low-pass) */
+    float kappa;                         /* 11.1: tile rectangle = bounding box of q <= kappa (> 2 ln 255) */
+    int32_t depth_mode;                  /* 0: z = alpha-weighted depth; 1: z = 2/(1+exp(-0.1 z)) - 1 */
+    int64_t max_pairs;                   /* capacity of the (Gaussian, tile) pair list, <= GS_MAX_PAIRS */
+    void* timer;                         /* optional gs_timer* receiving per-kernel HIP events; NULL = none */
+} gs_options;
+
+/* Fill `opts` with the defaults above (max_pairs = 1 << 24). */
+void gs_default_options(gs_options* opts);
+
+/* Library version string (static storage). */
+const char* gs_version(void);
+
+/* Device bytes that gs_render_forward/backward need for these options, scene
+ * size and views (host_cams is a HOST array of n_views cameras).  `saved` is
+ * the forward context that must be kept unchanged until gs_render_backward;
+ * `workspace` is scratch for either call.  Touches no device; callable without
+ * a GPU.  Returns GS_ERR_INVALID_ARGUMENT for bad options or sizes. */
+int gs_workspace_query(const gs_options* opts, int64_t n, int32_t n_views, const gs_camera* host_cams,
+                       size_t* workspace_bytes, size_t* saved_bytes);
+
+/* Forward render (eq. 3dgs_orig, opacity_impact, 3dgs_uw, Depth) of all views.
+ *   host_cams  : HOST copy of the cameras; fixes the image sizes (and so the
+ *                launch shapes).
+ *   dev_cams   : DEVICE copy of the same cameras; the kernels read poses and
+ *                intrinsics from here (so a captured graph can be replayed
+ *                after the poses are updated in place; sizes must not change).
+ *   dev_medium : DEVICE [n_views] medium coefficients.
+ *   out_rgb    : [sum 3 W H] attenuated colour C_uw (CHW per view);
+ *   out_depth  : [sum W H] z (0 where no Gaussian contributes; such pixels are
+ *                treated as at infinite range: C_uw = B_inf where B_b > 0);
+ *   out_alpha  : [sum W H] accumulated opacity sum_i alpha_i T_i.
+ *   saved      : forward context (>= saved_bytes) used by gs_render_backward,
+ *                gs_read_status and gs_export_keys.
+ * Returns GS_OK or a GS_ERR_* code; capacity overflow is reported
+ * asynchronously through gs_read_status (outputs are then not valid). */
+int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_views,
+                      const gs_camera* host_cams, const gs_camera* dev_cams, const gs_medium* dev_medium,
+                      float* out_rgb, float* out_depth, float* out_alpha,
+                      void* saved, size_t saved_bytes, void* workspace, size_t workspace_bytes,
+                      gs_stream_t stream);
+
+/* Adjoint of gs_render_forward for L with upstream gradients grad_rgb (same
+ * layout as out_rgb) and grad_depth (same layout as out_depth, may be NULL).
+ * Transmittance is recomputed from the saved final transmittance rather than
+ * storing per-pixel Gaussian lists.  Writes gradients w.r.t. every Gaussian
+ * parameter (activated scales and opacity) into `grads` (overwritten) and
+ * grad_medium [n_views][9] = (dB_d[3], dB_b[3], dB_inf[3]) (overwritten).
+ * opts, g, n_views, cameras and medium must equal those of the forward call
+ * that produced `saved`. */
+int gs_render_backward(const gs_options* opts, const gs_gaussians* g, int32_t n_views,
+                       const gs_camera* host_cams, const gs_camera* dev_cams, const gs_medium* dev_medium,
+                       const float* grad_rgb, const float* grad_depth,
+                       const void* saved, size_t saved_bytes, gs_gaussian_grads* grads, float* grad_medium,
+                       void* workspace, size_t workspace_bytes, gs_stream_t stream);
+
+/* Synchronise `stream` and read the status word of a forward context:
+ * status_bits = OR of GS_STATUS_*, pairs_needed = pair count the last forward
+ * produced (compare with opts.max_pairs).  Either output may be NULL. */
+int gs_read_status(const void* saved, uint32_t* status_bits, int64_t* pairs_needed, gs_stream_t stream);
+
+/* Write the sorted (tile, depth) key list of the last forward into caller
+ * buffers: keys[k] = (global tile id << 32) | FP32 bits of the view depth,
+ * values[k] = view * n + Gaussian index, tile_ranges[2 t .. 2 t + 1] = [start,
+ * end) of global tile t (tiles numbered row-major within a view, views in
+ * order).  Buffers hold `capacity` pairs and gs_workspace_query's tile count;
+ * *pair_count (HOST) receives the number of pairs.  Synchronises `stream`.
+ * (Preliminaries, "Tiles"; depth order of eq. 3dgs_orig.) */
+int gs_export_keys(const gs_options* opts, int64_t n, int32_t n_views, const gs_camera* host_cams,
+                   const void* saved, size_t saved_bytes, uint64_t* keys, uint32_t* values,
+                   uint32_t* tile_ranges, int64_t capacity, int64_t* pair_count, gs_stream_t stream);
+
+/* Total number of tiles over the views for these options (host only). */
+int64_t gs_tile_count(const gs_options* opts, int32_t n_views, const gs_camera* host_cams);
+
+/* Parameter activation (eq. opacity_impact's sigmoid; exp scales):
+ * scales[i] = exp(log_scales[i]) for i < 3n, opacity[i] = 1/(1+exp(-logits[i])). */
+int gs_activate(int64_t n, const float* log_scales, const float* logits, float* scales, float* opacity,
+                gs_stream_t stream);
+
+/* Chain gradients through gs_activate: g_log_scales = g_scales * scales,
+ * g_logits = g_opacity * opacity * (1 - opacity) (scales/opacity activated). */
+int gs_activate_backward(int64_t n, const float* scales, const float* opacity, const float* g_scales,
+                         const float* g_opacity, float* g_log_scales, float* g_logits, gs_stream_t stream);
+
+/* L1 term of eq. (3DGSoriginalLoss): loss[0] = mean |pred - target| over
+ * `count` elements (loss may be NULL), grad[i] = sign(pred - target) / count
+ * (grad may be NULL). */
+int gs_l1_loss(int64_t count, const float* pred, const float* target, float* loss, float* grad,
+               gs_stream_t stream);
+
+/* One parameter group of the fused Adam step (Sec. Optimization: Adam with
+ * the 3DGS learning rates, medium at the colour learning rate). */
+typedef struct gs_adam_group {
+    float* param;                        /* raw parameter, updated in place */
+    const float* grad;                   /* gradient (see activation) */
+    float* m;                            /* first moment, updated */
+    float* v;                            /* second moment, updated */
+    float* activated;                    /* activation != 0: receives act(param) after the update */
+    int64_t count;
+    float lr;
+    int32_t activation;                  /* 0 none; 1 exp; 2 sigmoid.  With an activation, `grad` is the
+                                            gradient w.r.t. the ACTIVATED value and `activated` must hold the
+                                            activated value of the current param on entry. */
+    int32_t reserved;
+} gs_adam_group;
+
+/* Fused Adam update (beta1, beta2, eps, bias correction at `step` >= 1) over
+ * up to 8 groups in one launch. */
+int gs_adam_step(const gs_adam_group* host_groups, int32_t n_groups, float beta1, float beta2, float eps,
+                 int32_t step, gs_stream_t stream);
+
+/* Optional per-kernel timing with HIP events (used by benchmarks).  A timer
+ * records a start/stop event pair around each kernel it sees in opts.timer.
+ * gs_timer_read synchronises the recorded events and returns, for the kernel
+ * named `kernel`, the summed duration (ms) and the number of launches. */
+void* gs_timer_create(int32_t capacity);
+void gs_timer_destroy(void* timer);
+void gs_timer_reset(void* timer);
+int gs_timer_read(void* timer, const char* kernel, double* total_ms, int32_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSPLASH_H */

@@ -1,0 +1,413 @@
+// C ABI of libgsplash: argument validation, buffer layout and the launch
+// sequences of the forward and backward passes.  Host code only; every compute
+// step is one of the kernels declared in internal.h.
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace gs {
+
+namespace {
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Cursor {
+    size_t at = 0;
+    size_t take(size_t bytes) {
+        const size_t o = at;
+        at = align_up(at + bytes);
+        return o;
+    }
+};
+
+bool finite_pos(float x) { return x == x && x > 0.0f && x < 3.0e38f; }
+
+}  // namespace
+
+int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_camera* cams, Layout* L) {
+    if (!o || !cams || !L || n < 0 || n_views < 1 || n_views > GS_MAX_VIEWS) return GS_ERR_INVALID_ARGUMENT;
+    const bool t16 = o->tile_w == 16 && o->tile_h == 16;
+    const bool t8 = o->tile_w == 8 && o->tile_h == 8;
+    if (!t16 && !t8) {
+        const bool pow2 = o->tile_w > 0 && o->tile_h > 0 && (o->tile_w & (o->tile_w - 1)) == 0 &&
+                          (o->tile_h & (o->tile_h - 1)) == 0;
+        return pow2 ? GS_ERR_UNSUPPORTED : GS_ERR_INVALID_ARGUMENT;
+    }
+    if (t16 && o->lds_batch != 64 && o->lds_batch != 128 && o->lds_batch != 256) return GS_ERR_INVALID_ARGUMENT;
+    if (t8 && o->lds_batch != 64) return GS_ERR_INVALID_ARGUMENT;
+    if (!(o->alpha_min > 0.0f && o->alpha_min < o->alpha_max && o->alpha_max < 1.0f)) return GS_ERR_INVALID_ARGUMENT;
+    if (!finite_pos(o->t_min) || !(o->t_min < 1.0f)) return GS_ERR_INVALID_ARGUMENT;
+    if (!(o->dilation >= 0.0f && o->dilation < 1e30f) || !finite_pos(o->kappa)) return GS_ERR_INVALID_ARGUMENT;
+    if (o->depth_mode != 0 && o->depth_mode != 1) return GS_ERR_INVALID_ARGUMENT;
+    if (o->persistent != 0 && o->persistent != 1) return GS_ERR_INVALID_ARGUMENT;
+    if (o->max_pairs < 0 || o->max_pairs > GS_MAX_PAIRS) return GS_ERR_INVALID_ARGUMENT;
+    if (n * (int64_t)n_views >= (int64_t)0xFFFFFFFFLL) return GS_ERR_INVALID_ARGUMENT;
+
+    memset(L, 0, sizeof(*L));
+    L->n = n;
+    L->views = n_views;
+    L->nv = n * n_views;
+    L->max_pairs = o->max_pairs;
+    int64_t tiles = 0, pixels = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const gs_camera& c = cams[v];
+        if (c.width < 1 || c.height < 1 || c.width > 32768 || c.height > 32768) return GS_ERR_INVALID_ARGUMENT;
+        if (!finite_pos(c.fx) || !finite_pos(c.fy) || !(c.near_z > 0.0f)) return GS_ERR_INVALID_ARGUMENT;
+        ViewInfo& vi = L->table.v[v];
+        vi.width = c.width;
+        vi.height = c.height;
+        vi.tiles_x = (c.width + o->tile_w - 1) / o->tile_w;
+        vi.tiles_y = (c.height + o->tile_h - 1) / o->tile_h;
+        vi.tile_base = (uint32_t)tiles;
+        vi.n_tiles = (uint32_t)(vi.tiles_x * vi.tiles_y);
+        vi.pix_base = pixels;
+        tiles += (int64_t)vi.n_tiles;
+        pixels += (int64_t)c.width * c.height;
+    }
+    L->table.count = n_views;
+    if (tiles >= (1LL << 31)) return GS_ERR_INVALID_ARGUMENT;
+    L->tiles = tiles;
+    L->pixels = pixels;
+    int bits = 1;
+    while ((1LL << bits) < tiles) ++bits;
+    L->tile_bits = bits;
+    L->tile_passes = (bits + kRadixBits - 1) / kRadixBits;
+    auto parts_for = [](int64_t count) {
+        int64_t p = (count + 4 * (int64_t)kSortTile - 1) / (4 * (int64_t)kSortTile);
+        if (p < 1) p = 1;
+        if (p > kMaxSortParts) p = kMaxSortParts;
+        return (int)p;
+    };
+    L->pair_parts = parts_for(o->max_pairs);
+    L->depth_parts = parts_for(L->nv);
+
+    const size_t nv = (size_t)L->nv, P = (size_t)pixels, K = (size_t)o->max_pairs, T = (size_t)tiles;
+    Cursor s;
+    L->s_header = s.take(sizeof(SavedHeader) + sizeof(ViewInfo) * GS_MAX_VIEWS);
+    L->s_records = s.take(nv * sizeof(Record));
+    L->s_depth_keys = s.take(nv * 4);
+    L->s_ranges = s.take(T * 8);
+    L->s_tiles_a = s.take(K * 4);
+    L->s_vals_a = s.take(K * 4);
+    L->s_tiles_b = s.take(K * 4);
+    L->s_vals_b = s.take(K * 4);
+    L->s_tfinal = s.take(P * 4);
+    L->s_nlast = s.take(P * 4);
+    L->s_cair = s.take(3 * P * 4);
+    L->s_dsum = s.take(P * 4);
+    L->s_wsum = s.take(P * 4);
+    L->saved_bytes = s.at;
+
+    Cursor w;
+    const size_t nb = (nv + kBlock * 16 - 1) / (kBlock * 16) + 1;
+    const int parts = L->pair_parts > L->depth_parts ? L->pair_parts : L->depth_parts;
+    L->w_counts = w.take(nv * 4);
+    L->w_rects = w.take(nv * 8);
+    L->w_dkeys = w.take(nv * 4);
+    L->w_dvals = w.take(nv * 4);
+    L->w_dkeys2 = w.take(nv * 4);
+    L->w_dvals2 = w.take(nv * 4);
+    L->w_offsets = w.take((nv + 1) * 8);
+    L->w_blocksums = w.take(nb * 8);
+    L->w_hist = w.take((size_t)kRadix * parts * 4);
+    L->w_grad2d = w.take(nv * kGrad2D * 4);
+    L->w_medpart = w.take(T * 9 * 4 + 256);   // + persistent-mode tile counter of the backward
+    L->workspace_bytes = w.at;
+    return GS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Timer: a pool of HIP event pairs recorded around kernels.
+struct Timer {
+    struct Slot {
+        hipEvent_t start, stop;
+        std::string name;
+    };
+    std::vector<Slot> slots;
+    int used = 0;
+    int open = -1;
+};
+
+void timer_begin(void* timer, const char* name, hipStream_t s) {
+    Timer* t = static_cast<Timer*>(timer);
+    if (!t || t->used >= (int)t->slots.size()) return;
+    Timer::Slot& sl = t->slots[t->used];
+    sl.name = name;
+    (void)hipEventRecord(sl.start, s);
+    t->open = t->used;
+}
+
+void timer_end(void* timer, hipStream_t s) {
+    Timer* t = static_cast<Timer*>(timer);
+    if (!t || t->open < 0) return;
+    (void)hipEventRecord(t->slots[t->open].stop, s);
+    t->open = -1;
+    t->used++;
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+namespace {
+
+#define GS_TRY(call)                                  \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess) return GS_ERR_HIP;      \
+    } while (0)
+
+template <typename T>
+T* at(void* base, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+template <typename T>
+const T* at(const void* base, size_t off) {
+    return reinterpret_cast<const T*>(static_cast<const char*>(base) + off);
+}
+
+int check_gaussians(const gs_gaussians* g) {
+    if (!g || g->n < 0 || g->sh_degree < 0 || g->sh_degree > 3) return GS_ERR_INVALID_ARGUMENT;
+    if (g->n > 0 && (!g->means || !g->scales || !g->quats || !g->opacity || !g->sh)) return GS_ERR_INVALID_ARGUMENT;
+    return GS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void gs_default_options(gs_options* o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->tile_w = 16;
+    o->tile_h = 16;
+    o->lds_batch = 256;
+    o->persistent = 0;
+    o->alpha_min = 1.0f / 255.0f;
+    o->alpha_max = 0.99f;
+    o->t_min = 1e-4f;
+    o->dilation = 0.3f;
+    o->kappa = 11.1f;
+    o->depth_mode = 0;
+    o->max_pairs = 1LL << 24;
+    o->timer = nullptr;
+}
+
+const char* gs_version(void) { return "gsplash 0.1 (gfx950)"; }
+
+int gs_workspace_query(const gs_options* opts, int64_t n, int32_t n_views, const gs_camera* host_cams,
+                       size_t* workspace_bytes, size_t* saved_bytes) {
+    Layout L;
+    const int rc = compute_layout(opts, n, n_views, host_cams, &L);
+    if (rc != GS_OK) return rc;
+    if (workspace_bytes) *workspace_bytes = L.workspace_bytes;
+    if (saved_bytes) *saved_bytes = L.saved_bytes;
+    return GS_OK;
+}
+
+int64_t gs_tile_count(const gs_options* opts, int32_t n_views, const gs_camera* host_cams) {
+    Layout L;
+    if (compute_layout(opts, 0, n_views, host_cams, &L) != GS_OK) return -1;
+    return L.tiles;
+}
+
+int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_views, const gs_camera* host_cams,
+                      const gs_camera* dev_cams, const gs_medium* dev_medium, float* out_rgb, float* out_depth,
+                      float* out_alpha, void* saved, size_t saved_bytes, void* workspace, size_t workspace_bytes,
+                      gs_stream_t stream) {
+    int rc = check_gaussians(g);
+    if (rc != GS_OK) return rc;
+    Layout L;
+    rc = compute_layout(opts, g->n, n_views, host_cams, &L);
+    if (rc != GS_OK) return rc;
+    if (!dev_cams || !dev_medium || !out_rgb || !out_depth || !out_alpha || !saved || !workspace)
+        return GS_ERR_INVALID_ARGUMENT;
+    if (saved_bytes < L.saved_bytes || workspace_bytes < L.workspace_bytes) return GS_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const gs_options& o = *opts;
+    void* T = o.timer;
+
+    SavedHeader* hdr = at<SavedHeader>(saved, L.s_header);
+    ViewInfo* vt = reinterpret_cast<ViewInfo*>(hdr + 1);
+    Record* rec = at<Record>(saved, L.s_records);
+    uint32_t* depth_keys = at<uint32_t>(saved, L.s_depth_keys);
+    uint2* ranges = at<uint2>(saved, L.s_ranges);
+    uint32_t* tiles_a = at<uint32_t>(saved, L.s_tiles_a);
+    uint32_t* vals_a = at<uint32_t>(saved, L.s_vals_a);
+    uint32_t* tiles_b = at<uint32_t>(saved, L.s_tiles_b);
+    uint32_t* vals_b = at<uint32_t>(saved, L.s_vals_b);
+    uint32_t* counts = at<uint32_t>(workspace, L.w_counts);
+    uint2* rects = at<uint2>(workspace, L.w_rects);
+    uint32_t* dk = at<uint32_t>(workspace, L.w_dkeys);
+    uint32_t* dv = at<uint32_t>(workspace, L.w_dvals);
+    uint32_t* dk2 = at<uint32_t>(workspace, L.w_dkeys2);
+    uint32_t* dv2 = at<uint32_t>(workspace, L.w_dvals2);
+    uint64_t* offsets = at<uint64_t>(workspace, L.w_offsets);
+    uint64_t* blocksums = at<uint64_t>(workspace, L.w_blocksums);
+    uint32_t* hist = at<uint32_t>(workspace, L.w_hist);
+
+    GS_TRY(launch_view_table(L.table, vt, hdr, s));
+    timer_begin(T, "project_fwd", s);
+    GS_TRY(launch_project_fwd(*g, n_views, dev_cams, vt, o, rec, counts, rects, depth_keys, dk, dv, hdr, s));
+    timer_end(T, s);
+    // depth order of all (view, Gaussian) entries
+    int in_b = 0;
+    if (L.nv > 0)
+        GS_TRY(radix_sort_u32(dk, dv, dk2, dv2, nullptr, (uint32_t)L.nv, 0, 32, L.depth_parts, hist, &in_b, T, s));
+    const uint32_t* order = in_b ? dv2 : dv;
+    timer_begin(T, "count_scan", s);
+    GS_TRY(launch_count_scan(counts, order, L.nv, offsets, blocksums, hdr, L.max_pairs, s));
+    timer_end(T, s);
+    timer_begin(T, "emit", s);
+    GS_TRY(launch_emit(order, offsets, counts, rects, L.nv, L.n, vt, n_views, hdr, tiles_a, vals_a, s));
+    timer_end(T, s);
+    // stable sort of the pairs by tile id
+    int tb = 0;
+    if (L.max_pairs > 0)
+        GS_TRY(radix_sort_u32(tiles_a, vals_a, tiles_b, vals_b, &hdr->pair_count, 0, 0, L.tile_bits, L.pair_parts,
+                              hist, &tb, T, s));
+    const uint32_t* st = tb ? tiles_b : tiles_a;
+    const uint32_t* sv = tb ? vals_b : vals_a;
+    timer_begin(T, "ranges", s);
+    GS_TRY(launch_ranges(st, hdr, L.tiles, ranges, s));
+    timer_end(T, s);
+    timer_begin(T, "composite_fwd", s);
+    GS_TRY(launch_composite_fwd(o, L, vt, dev_medium, rec, ranges, sv, hdr, out_rgb, out_depth, out_alpha,
+                                at<float>(saved, L.s_tfinal), at<uint32_t>(saved, L.s_nlast),
+                                at<float>(saved, L.s_cair), at<float>(saved, L.s_dsum), at<float>(saved, L.s_wsum),
+                                s));
+    timer_end(T, s);
+    return GS_OK;
+}
+
+int gs_render_backward(const gs_options* opts, const gs_gaussians* g, int32_t n_views, const gs_camera* host_cams,
+                       const gs_camera* dev_cams, const gs_medium* dev_medium, const float* grad_rgb,
+                       const float* grad_depth, const void* saved, size_t saved_bytes, gs_gaussian_grads* grads,
+                       float* grad_medium, void* workspace, size_t workspace_bytes, gs_stream_t stream) {
+    int rc = check_gaussians(g);
+    if (rc != GS_OK) return rc;
+    Layout L;
+    rc = compute_layout(opts, g->n, n_views, host_cams, &L);
+    if (rc != GS_OK) return rc;
+    if (!dev_cams || !dev_medium || !grad_rgb || !saved || !grads || !grad_medium || !workspace)
+        return GS_ERR_INVALID_ARGUMENT;
+    if (g->n > 0 && (!grads->means || !grads->scales || !grads->quats || !grads->opacity || !grads->sh))
+        return GS_ERR_INVALID_ARGUMENT;
+    if (saved_bytes < L.saved_bytes || workspace_bytes < L.workspace_bytes) return GS_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const gs_options& o = *opts;
+    void* T = o.timer;
+    void* sv_ = const_cast<void*>(saved);
+    SavedHeader* hdr = at<SavedHeader>(sv_, L.s_header);
+    ViewInfo* vt = reinterpret_cast<ViewInfo*>(hdr + 1);
+    const bool in_b = (L.tile_passes % 2) == 1 && L.max_pairs > 0;
+    const uint32_t* sv = at<uint32_t>(saved, in_b ? L.s_vals_b : L.s_vals_a);
+    float* grad2d = at<float>(workspace, L.w_grad2d);
+    float* medpart = at<float>(workspace, L.w_medpart);
+
+    timer_begin(T, "zero_grad2d", s);
+    GS_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, L.nv * kGrad2D, s));
+    timer_end(T, s);
+    timer_begin(T, "composite_bwd", s);
+    GS_TRY(launch_composite_bwd(o, L, vt, dev_medium, at<Record>(saved, L.s_records), at<uint2>(saved, L.s_ranges),
+                                sv, hdr, grad_rgb, grad_depth, at<float>(saved, L.s_tfinal),
+                                at<uint32_t>(saved, L.s_nlast), at<float>(saved, L.s_cair),
+                                at<float>(saved, L.s_dsum), at<float>(saved, L.s_wsum), grad2d, medpart, s));
+    timer_end(T, s);
+    timer_begin(T, "medium_reduce", s);
+    GS_TRY(launch_medium_reduce(vt, n_views, medpart, grad_medium, s));
+    timer_end(T, s);
+    timer_begin(T, "project_bwd", s);
+    GS_TRY(launch_project_bwd(*g, n_views, dev_cams, o, grad2d, *grads, s));
+    timer_end(T, s);
+    return GS_OK;
+}
+
+int gs_read_status(const void* saved, uint32_t* status_bits, int64_t* pairs_needed, gs_stream_t stream) {
+    if (!saved) return GS_ERR_INVALID_ARGUMENT;
+    SavedHeader h;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GS_TRY(hipMemcpyAsync(&h, saved, sizeof(h), hipMemcpyDeviceToHost, s));
+    GS_TRY(hipStreamSynchronize(s));
+    if (status_bits) *status_bits = h.status;
+    if (pairs_needed) *pairs_needed = (int64_t)h.pairs_needed;
+    return GS_OK;
+}
+
+int gs_export_keys(const gs_options* opts, int64_t n, int32_t n_views, const gs_camera* host_cams,
+                   const void* saved, size_t saved_bytes, uint64_t* keys, uint32_t* values, uint32_t* tile_ranges,
+                   int64_t capacity, int64_t* pair_count, gs_stream_t stream) {
+    Layout L;
+    const int rc = compute_layout(opts, n, n_views, host_cams, &L);
+    if (rc != GS_OK) return rc;
+    if (!saved || !keys || !values || !tile_ranges || !pair_count || capacity < 0) return GS_ERR_INVALID_ARGUMENT;
+    if (saved_bytes < L.saved_bytes) return GS_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool in_b = (L.tile_passes % 2) == 1 && L.max_pairs > 0;
+    const SavedHeader* hdr = at<SavedHeader>(saved, L.s_header);
+    GS_TRY(launch_export_keys(at<uint32_t>(saved, in_b ? L.s_tiles_b : L.s_tiles_a),
+                              at<uint32_t>(saved, in_b ? L.s_vals_b : L.s_vals_a),
+                              at<uint32_t>(saved, L.s_depth_keys), hdr, capacity, keys, values, s));
+    if (L.tiles > 0)
+        GS_TRY(hipMemcpyAsync(tile_ranges, at<char>(saved, L.s_ranges), (size_t)L.tiles * 8,
+                              hipMemcpyDeviceToDevice, s));
+    SavedHeader h;
+    GS_TRY(hipMemcpyAsync(&h, hdr, sizeof(h), hipMemcpyDeviceToHost, s));
+    GS_TRY(hipStreamSynchronize(s));
+    *pair_count = (int64_t)h.pair_count;
+    return GS_OK;
+}
+
+void* gs_timer_create(int32_t capacity) {
+    if (capacity <= 0) return nullptr;
+    Timer* t = new Timer();
+    t->slots.resize((size_t)capacity);
+    for (auto& sl : t->slots) {
+        if (hipEventCreate(&sl.start) != hipSuccess || hipEventCreate(&sl.stop) != hipSuccess) {
+            delete t;
+            return nullptr;
+        }
+    }
+    return t;
+}
+
+void gs_timer_destroy(void* timer) {
+    Timer* t = static_cast<Timer*>(timer);
+    if (!t) return;
+    for (auto& sl : t->slots) {
+        (void)hipEventDestroy(sl.start);
+        (void)hipEventDestroy(sl.stop);
+    }
+    delete t;
+}
+
+void gs_timer_reset(void* timer) {
+    Timer* t = static_cast<Timer*>(timer);
+    if (t) {
+        t->used = 0;
+        t->open = -1;
+    }
+}
+
+int gs_timer_read(void* timer, const char* kernel, double* total_ms, int32_t* launches) {
+    Timer* t = static_cast<Timer*>(timer);
+    if (!t || !kernel) return GS_ERR_INVALID_ARGUMENT;
+    double sum = 0.0;
+    int cnt = 0;
+    for (int i = 0; i < t->used; ++i) {
+        if (t->slots[i].name != kernel) continue;
+        GS_TRY(hipEventSynchronize(t->slots[i].stop));
+        float ms = 0.f;
+        GS_TRY(hipEventElapsedTime(&ms, t->slots[i].start, t->slots[i].stop));
+        sum += ms;
+        ++cnt;
+    }
+    if (total_ms) *total_ms = sum;
+    if (launches) *launches = cnt;
+    return GS_OK;
+}
+
+}  // extern "C"

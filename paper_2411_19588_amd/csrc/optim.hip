@@ -1,0 +1,167 @@
+// Elementwise steps around the rasterizer: parameter activation (exp scales,
+// sigmoid opacity of eq. opacity_impact), the L1 term of eq. (3DGSoriginalLoss)
+// and the fused Adam update of Sec. Optimization.  All are HBM-bound streams
+// with grid-stride loops.
+#include <string.h>
+
+#include "internal.h"
+
+namespace gs {
+namespace {
+
+constexpr int kMaxGroups = 8;
+
+__device__ __forceinline__ float sigmoidf_(float x) { return 1.0f / (1.0f + expf(-x)); }
+
+__global__ __launch_bounds__(kBlock) void k_activate(int64_t n, const float* __restrict__ ls,
+                                                    const float* __restrict__ lg, float* __restrict__ s,
+                                                    float* __restrict__ o) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < 3 * n; i += stride) {
+        s[i] = expf(ls[i]);
+        if (i < n) o[i] = sigmoidf_(lg[i]);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_activate_bwd(int64_t n, const float* __restrict__ s,
+                                                        const float* __restrict__ o, const float* __restrict__ gs_,
+                                                        const float* __restrict__ go, float* __restrict__ gls,
+                                                        float* __restrict__ glg) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < 3 * n; i += stride) {
+        gls[i] = gs_[i] * s[i];
+        if (i < n) glg[i] = go[i] * o[i] * (1.0f - o[i]);
+    }
+}
+
+__global__ void k_zero1(float* p) { *p = 0.0f; }
+
+__global__ __launch_bounds__(kBlock) void k_l1(int64_t count, const float* __restrict__ p,
+                                              const float* __restrict__ t, float* loss, float* __restrict__ grad) {
+    __shared__ float red[kBlock / 64];
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const float inv = 1.0f / (float)count;
+    float acc = 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) {
+        const float d = p[i] - t[i];
+        acc += fabsf(d);
+        if (grad) grad[i] = d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f);
+    }
+    if (!loss) return;
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float s = 0.0f;
+        for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+        unsafeAtomicAdd(loss, s * inv);
+    }
+}
+
+struct AdamArgs {
+    gs_adam_group g[kMaxGroups];
+    int64_t start[kMaxGroups + 1];
+    int32_t count;
+    float b1, b2, eps, bc1, bc2;
+};
+
+__global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a) {
+    const int64_t total = a.start[a.count];
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += stride) {
+        int k = 0;
+        while (i >= a.start[k + 1]) ++k;
+        const gs_adam_group& G = a.g[k];
+        const int64_t j = i - a.start[k];
+        float g = G.grad[j];
+        const float p = G.param[j];
+        if (G.activation == 1) {
+            g *= G.activated[j];                       // d exp(p)/dp = exp(p)
+        } else if (G.activation == 2) {
+            const float o = G.activated[j];
+            g *= o * (1.0f - o);                       // d sigmoid(p)/dp
+        }
+        const float m = fmaf(a.b1, G.m[j], (1.0f - a.b1) * g);
+        const float v = fmaf(a.b2, G.v[j], (1.0f - a.b2) * g * g);
+        G.m[j] = m;
+        G.v[j] = v;
+        const float mh = m / a.bc1;
+        const float vh = v / a.bc2;
+        const float np = p - G.lr * mh / (sqrtf(vh) + a.eps);
+        G.param[j] = np;
+        if (G.activation == 1) G.activated[j] = expf(np);
+        else if (G.activation == 2) G.activated[j] = sigmoidf_(np);
+    }
+}
+
+unsigned grid_for(int64_t n) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > 8192) g = 8192;
+    return (unsigned)g;
+}
+
+}  // namespace
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" {
+
+int gs_activate(int64_t n, const float* log_scales, const float* logits, float* scales, float* opacity,
+                gs_stream_t stream) {
+    if (n < 0 || (n > 0 && (!log_scales || !logits || !scales || !opacity))) return GS_ERR_INVALID_ARGUMENT;
+    if (n == 0) return GS_OK;
+    hipLaunchKernelGGL(k_activate, dim3(grid_for(3 * n)), dim3(kBlock), 0, static_cast<hipStream_t>(stream), n,
+                       log_scales, logits, scales, opacity);
+    return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+int gs_activate_backward(int64_t n, const float* scales, const float* opacity, const float* g_scales,
+                         const float* g_opacity, float* g_log_scales, float* g_logits, gs_stream_t stream) {
+    if (n < 0 || (n > 0 && (!scales || !opacity || !g_scales || !g_opacity || !g_log_scales || !g_logits)))
+        return GS_ERR_INVALID_ARGUMENT;
+    if (n == 0) return GS_OK;
+    hipLaunchKernelGGL(k_activate_bwd, dim3(grid_for(3 * n)), dim3(kBlock), 0, static_cast<hipStream_t>(stream), n,
+                       scales, opacity, g_scales, g_opacity, g_log_scales, g_logits);
+    return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+int gs_l1_loss(int64_t count, const float* pred, const float* target, float* loss, float* grad,
+               gs_stream_t stream) {
+    if (count <= 0 || !pred || !target || (!loss && !grad)) return GS_ERR_INVALID_ARGUMENT;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (loss) hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, s, loss);
+    hipLaunchKernelGGL(k_l1, dim3(grid_for(count)), dim3(kBlock), 0, s, count, pred, target, loss, grad);
+    return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+int gs_adam_step(const gs_adam_group* host_groups, int32_t n_groups, float beta1, float beta2, float eps,
+                 int32_t step, gs_stream_t stream) {
+    if (!host_groups || n_groups < 1 || n_groups > kMaxGroups || step < 1) return GS_ERR_INVALID_ARGUMENT;
+    if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f))
+        return GS_ERR_INVALID_ARGUMENT;
+    AdamArgs a;
+    memset(&a, 0, sizeof(a));
+    a.count = n_groups;
+    a.start[0] = 0;
+    for (int k = 0; k < n_groups; ++k) {
+        const gs_adam_group& G = host_groups[k];
+        if (G.count < 0 || G.activation < 0 || G.activation > 2) return GS_ERR_INVALID_ARGUMENT;
+        if (G.count > 0 && (!G.param || !G.grad || !G.m || !G.v || (G.activation && !G.activated)))
+            return GS_ERR_INVALID_ARGUMENT;
+        a.g[k] = G;
+        a.start[k + 1] = a.start[k] + G.count;
+    }
+    a.b1 = beta1;
+    a.b2 = beta2;
+    a.eps = eps;
+    a.bc1 = (float)(1.0 - __builtin_pow((double)beta1, (double)step));
+    a.bc2 = (float)(1.0 - __builtin_pow((double)beta2, (double)step));
+    if (a.start[n_groups] == 0) return GS_OK;
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(a.start[n_groups])), dim3(kBlock), 0, static_cast<hipStream_t>(stream),
+                       a);
+    return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,445 @@
+// Projection of 3D Gaussians into the views (Preliminaries, 3DGS: covariance
+// from rotation and scale; EWA affine projection of the covariance; SH colour)
+// and its adjoint.  One thread per Gaussian loops over the views, so the
+// structure-of-arrays parameters are read once per launch with coalesced loads.
+//
+// The key path (view depth, 2D mean, diagonal of the 2D covariance, tile
+// rectangle) is a fixed sequence of separately rounded FP32 operations: this
+// file is compiled with -ffp-contract=off and uses no fused multiply-adds on
+// that path, with IEEE division and square root, so the sort keys are
+// reproducible bit for bit.
+#include "internal.h"
+
+namespace gs {
+
+namespace {
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kConicScale = -0.5f * kLog2e;   // A = kConicScale * Qxx, etc.
+
+// Real orthonormal SH, Condon-Shortley phase, k = l^2 + l + m.
+constexpr float kY0 = 0.28209479177387814f;
+constexpr float kY1 = 0.4886025119029199f;
+constexpr float kY2a = 1.0925484305920792f;
+constexpr float kY20 = 0.31539156525252005f;
+constexpr float kY22 = 0.5462742152960396f;
+constexpr float kY33 = 0.5900435899266435f;
+constexpr float kY32 = 2.890611442640554f;
+constexpr float kY31 = 0.4570457994644658f;
+constexpr float kY30 = 0.3731763325901154f;
+constexpr float kY322 = 1.445305721320277f;
+
+template <int DEG>
+__device__ __forceinline__ void sh_eval(float x, float y, float z, float* Y) {
+    Y[0] = kY0;
+    if constexpr (DEG >= 1) {
+        Y[1] = -kY1 * y;
+        Y[2] = kY1 * z;
+        Y[3] = -kY1 * x;
+    }
+    if constexpr (DEG >= 2) {
+        float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = kY2a * x * y;
+        Y[5] = -kY2a * y * z;
+        Y[6] = kY20 * (2.0f * zz - xx - yy);
+        Y[7] = -kY2a * x * z;
+        Y[8] = kY22 * (xx - yy);
+        if constexpr (DEG >= 3) {
+            Y[9] = -kY33 * y * (3.0f * xx - yy);
+            Y[10] = kY32 * x * y * z;
+            Y[11] = -kY31 * y * (4.0f * zz - xx - yy);
+            Y[12] = kY30 * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+            Y[13] = -kY31 * x * (4.0f * zz - xx - yy);
+            Y[14] = kY322 * z * (xx - yy);
+            Y[15] = -kY33 * x * (xx - 3.0f * yy);
+        }
+    }
+}
+
+// Gradient of sum_k w_k Y_k(x, y, z) w.r.t. (x, y, z) for the polynomial forms above.
+template <int DEG>
+__device__ __forceinline__ void sh_grad(float x, float y, float z, const float* w, float* g) {
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+    if constexpr (DEG >= 1) {
+        gy += -kY1 * w[1];
+        gz += kY1 * w[2];
+        gx += -kY1 * w[3];
+    }
+    if constexpr (DEG >= 2) {
+        gx += kY2a * y * w[4];            gy += kY2a * x * w[4];
+        gy += -kY2a * z * w[5];           gz += -kY2a * y * w[5];
+        gx += -2.f * kY20 * x * w[6];     gy += -2.f * kY20 * y * w[6];     gz += 4.f * kY20 * z * w[6];
+        gx += -kY2a * z * w[7];           gz += -kY2a * x * w[7];
+        gx += 2.f * kY22 * x * w[8];      gy += -2.f * kY22 * y * w[8];
+        if constexpr (DEG >= 3) {
+            float xx = x * x, yy = y * y, zz = z * z;
+            gx += -kY33 * 6.f * x * y * w[9];             gy += -kY33 * (3.f * xx - 3.f * yy) * w[9];
+            gx += kY32 * y * z * w[10];  gy += kY32 * x * z * w[10];  gz += kY32 * x * y * w[10];
+            gx += kY31 * 2.f * x * y * w[11];
+            gy += -kY31 * (4.f * zz - xx - 3.f * yy) * w[11];
+            gz += -kY31 * 8.f * y * z * w[11];
+            gx += -kY30 * 6.f * x * z * w[12];  gy += -kY30 * 6.f * y * z * w[12];
+            gz += kY30 * (6.f * zz - 3.f * xx - 3.f * yy) * w[12];
+            gx += -kY31 * (4.f * zz - 3.f * xx - yy) * w[13];
+            gy += kY31 * 2.f * x * y * w[13];
+            gz += -kY31 * 8.f * x * z * w[13];
+            gx += kY322 * 2.f * x * z * w[14];  gy += -kY322 * 2.f * y * z * w[14];
+            gz += kY322 * (xx - yy) * w[14];
+            gx += -kY33 * (3.f * xx - 3.f * yy) * w[15];  gy += kY33 * 6.f * x * y * w[15];
+        }
+    }
+    g[0] = gx; g[1] = gy; g[2] = gz;
+}
+
+struct Cam {
+    float R[9], t[3], fx, fy, cx, cy, near_z;
+    int W, H;
+};
+
+__device__ __forceinline__ Cam load_cam(const gs_camera* c) {
+    Cam k;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) k.R[i] = c->R[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) k.t[i] = c->t[i];
+    k.fx = c->fx; k.fy = c->fy; k.cx = c->cx; k.cy = c->cy; k.near_z = c->near_z;
+    k.W = c->width; k.H = c->height;
+    return k;
+}
+
+// Quantities of the FP32 key path (and what the rest of the projection reuses).
+struct Proj {
+    float t[3];          // camera-space mean
+    float qh[4];         // normalised quaternion
+    float Rq[9];         // rotation of the Gaussian
+    float V[9];          // Rv * Rq * diag(s)
+    float u, v, a, b;    // tx/tz, ty/tz, fx/tz, fy/tz
+    float T0[3], T1[3];  // 2x3 factor of the 2D covariance
+    float sxx, syy, px, py;
+    bool valid;
+};
+
+// Exact FP32 sequence shared with the key specification.  Returns valid=false
+// for culled / non-finite Gaussians.
+__device__ __forceinline__ void key_path(const Cam& c, float mx, float my, float mz, float s0, float s1,
+                                         float s2, float qw, float qx, float qy, float qz, float dil,
+                                         Proj& P) {
+    P.t[0] = ((c.R[0] * mx + c.R[1] * my) + c.R[2] * mz) + c.t[0];
+    P.t[1] = ((c.R[3] * mx + c.R[4] * my) + c.R[5] * mz) + c.t[1];
+    P.t[2] = ((c.R[6] * mx + c.R[7] * my) + c.R[8] * mz) + c.t[2];
+    float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+    P.valid = (P.t[2] > c.near_z) && (n2 > 0.0f) && isfinite(P.t[0]) && isfinite(P.t[1]) && isfinite(s0) &&
+              isfinite(s1) && isfinite(s2) && isfinite(n2);
+    float nrm = __builtin_sqrtf(n2);
+    float w = qw / nrm, x = qx / nrm, y = qy / nrm, z = qz / nrm;
+    P.qh[0] = w; P.qh[1] = x; P.qh[2] = y; P.qh[3] = z;
+    float xx = x * x, yy = y * y, zz = z * z;
+    float xy = x * y, xz = x * z, yz = y * z;
+    float wx = w * x, wy = w * y, wz = w * z;
+    float* Q = P.Rq;
+    Q[0] = 1.0f - 2.0f * (yy + zz); Q[1] = 2.0f * (xy - wz);        Q[2] = 2.0f * (xz + wy);
+    Q[3] = 2.0f * (xy + wz);        Q[4] = 1.0f - 2.0f * (xx + zz); Q[5] = 2.0f * (yz - wx);
+    Q[6] = 2.0f * (xz - wy);        Q[7] = 2.0f * (yz + wx);        Q[8] = 1.0f - 2.0f * (xx + yy);
+    float M[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        M[3 * r + 0] = Q[3 * r + 0] * s0;
+        M[3 * r + 1] = Q[3 * r + 1] * s1;
+        M[3 * r + 2] = Q[3 * r + 2] * s2;
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            P.V[3 * r + k] = (c.R[3 * r + 0] * M[k] + c.R[3 * r + 1] * M[3 + k]) + c.R[3 * r + 2] * M[6 + k];
+    float tz = P.t[2];
+    P.u = P.t[0] / tz;
+    P.v = P.t[1] / tz;
+    P.a = c.fx / tz;
+    P.b = c.fy / tz;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        P.T0[k] = P.a * (P.V[k] - P.u * P.V[6 + k]);
+        P.T1[k] = P.b * (P.V[3 + k] - P.v * P.V[6 + k]);
+    }
+    P.sxx = ((P.T0[0] * P.T0[0] + P.T0[1] * P.T0[1]) + P.T0[2] * P.T0[2]) + dil;
+    P.syy = ((P.T1[0] * P.T1[0] + P.T1[1] * P.T1[1]) + P.T1[2] * P.T1[2]) + dil;
+    P.px = c.fx * P.u + c.cx;
+    P.py = c.fy * P.v + c.cy;
+}
+
+__device__ __forceinline__ void camera_centre(const Cam& c, float* cc) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) cc[k] = -(c.R[k] * c.t[0] + c.R[3 + k] * c.t[1] + c.R[6 + k] * c.t[2]);
+}
+
+template <int DEG>
+__global__ __launch_bounds__(kBlock) void k_project_fwd(gs_gaussians g, int32_t views, const gs_camera* cams,
+                                                       const ViewInfo* vt, int tile_w, int tile_h, float kappa,
+                                                       float dil, Record* rec, uint32_t* counts, uint2* rects,
+                                                       uint32_t* depth_keys, uint32_t* dkeys_sort,
+                                                       uint32_t* dvals_sort, SavedHeader* hdr) {
+    constexpr int NC = (DEG + 1) * (DEG + 1);
+    const int64_t n = g.n;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float mx = g.means[i], my = g.means[n + i], mz = g.means[2 * n + i];
+    const float s0 = g.scales[i], s1 = g.scales[n + i], s2 = g.scales[2 * n + i];
+    const float qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
+    const float op = g.opacity[i];
+    float sh[NC * 3];
+    bool finite = isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(s0) && isfinite(s1) &&
+                  isfinite(s2) && isfinite(qw) && isfinite(qx) && isfinite(qy) && isfinite(qz) && isfinite(op);
+#pragma unroll
+    for (int k = 0; k < NC * 3; ++k) {
+        sh[k] = g.sh[(int64_t)k * n + i];
+        finite = finite && isfinite(sh[k]);
+    }
+    if (!finite) atomicOr(&hdr->status, GS_STATUS_NONFINITE_INPUT);
+    const float inv_tw = 1.0f / (float)tile_w;   // exact: tile sizes are powers of two
+    const float inv_th = 1.0f / (float)tile_h;
+    for (int v = 0; v < views; ++v) {
+        const int64_t e = (int64_t)v * n + i;
+        const Cam c = load_cam(cams + v);
+        const ViewInfo vi = vt[v];
+        Proj P;
+        key_path(c, mx, my, mz, s0, s1, s2, qw, qx, qy, qz, dil, P);
+        const float ex = __builtin_sqrtf(kappa * P.sxx);
+        const float ey = __builtin_sqrtf(kappa * P.syy);
+        const bool ok = finite && P.valid && isfinite(P.px) && isfinite(P.py) && isfinite(ex) && isfinite(ey);
+        uint32_t cnt = 0;
+        uint32_t dkey = 0xFFFFFFFFu;
+        uint2 rc = make_uint2(0xFFFFu, 0u);   // empty rectangle (x0 > x1)
+        if (ok) {
+            dkey = __float_as_uint(P.t[2]);
+            const float lx = __builtin_floorf((P.px - ex) * inv_tw);
+            const float hx = __builtin_floorf((P.px + ex) * inv_tw);
+            const float ly = __builtin_floorf((P.py - ey) * inv_th);
+            const float hy = __builtin_floorf((P.py + ey) * inv_th);
+            const float x0 = lx > 0.0f ? lx : 0.0f;
+            const float y0 = ly > 0.0f ? ly : 0.0f;
+            const float x1 = hx < (float)(vi.tiles_x - 1) ? hx : (float)(vi.tiles_x - 1);
+            const float y1 = hy < (float)(vi.tiles_y - 1) ? hy : (float)(vi.tiles_y - 1);
+            if (x0 <= x1 && y0 <= y1) {
+                const uint32_t ix0 = (uint32_t)x0, iy0 = (uint32_t)y0, ix1 = (uint32_t)x1, iy1 = (uint32_t)y1;
+                rc = make_uint2(ix0 | (iy0 << 16), ix1 | (iy1 << 16));
+                cnt = (ix1 - ix0 + 1) * (iy1 - iy0 + 1);
+            }
+            // Conic of the dilated 2D covariance, pre-scaled for exp2.
+            const float sxy = (P.T0[0] * P.T1[0] + P.T0[1] * P.T1[1]) + P.T0[2] * P.T1[2];
+            const float det = P.sxx * P.syy - sxy * sxy;
+            const float id = 1.0f / det;
+            const float A = kConicScale * (P.syy * id);
+            const float B = 2.0f * kConicScale * (-sxy * id);
+            const float C = kConicScale * (P.sxx * id);
+            // View-dependent colour.
+            float cc[3];
+            camera_centre(c, cc);
+            float dx = mx - cc[0], dy = my - cc[1], dz = mz - cc[2];
+            const float il = 1.0f / __builtin_sqrtf(dx * dx + dy * dy + dz * dz);
+            dx *= il; dy *= il; dz *= il;
+            float Y[16];
+            sh_eval<DEG>(dx, dy, dz, Y);
+            float col[3];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float acc = 0.5f;
+#pragma unroll
+                for (int k = 0; k < NC; ++k) acc = fmaf(Y[k], sh[3 * k + ch], acc);
+                col[ch] = acc > 0.0f ? acc : 0.0f;
+            }
+            Record r;
+            r.a = make_float4(P.px, P.py, A, B);
+            r.b = make_float4(C, op, col[0], col[1]);
+            r.c = make_float4(col[2], P.t[2], 0.0f, 0.0f);
+            rec[e] = r;
+        }
+        counts[e] = cnt;
+        rects[e] = rc;
+        depth_keys[e] = dkey;
+        dkeys_sort[e] = dkey;
+        dvals_sort[e] = (uint32_t)e;
+    }
+}
+
+// Adjoint of k_project_fwd.  grad2d[e][10] = d/d(m_x, m_y, A, B, C, opacity, r, g, b, depth)
+// of the record of entry e = v * n + i.  Gradients of all views are summed in registers and written
+// once (overwrite).
+template <int DEG>
+__global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t views, const gs_camera* cams,
+                                                       float dil, const float* __restrict__ grad2d,
+                                                       gs_gaussian_grads out) {
+    constexpr int NC = (DEG + 1) * (DEG + 1);
+    const int64_t n = g.n;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float mx = g.means[i], my = g.means[n + i], mz = g.means[2 * n + i];
+    const float s[3] = {g.scales[i], g.scales[n + i], g.scales[2 * n + i]};
+    const float qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
+    float gmu[3] = {0.f, 0.f, 0.f}, gsc[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, gop = 0.f;
+    float gsh[NC * 3];
+#pragma unroll
+    for (int k = 0; k < NC * 3; ++k) gsh[k] = 0.f;
+    for (int v = 0; v < views; ++v) {
+        const float* gg = grad2d + ((int64_t)v * n + i) * kGrad2D;
+        float G[kGrad2D];
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < kGrad2D; ++k) {
+            G[k] = gg[k];
+            any = any || (G[k] != 0.0f);
+        }
+        if (!any) continue;
+        const Cam c = load_cam(cams + v);
+        Proj P;
+        key_path(c, mx, my, mz, s[0], s[1], s[2], qw, qx, qy, qz, dil, P);
+        const float tx = P.t[0], ty = P.t[1], tz = P.t[2];
+        gop += G[5];
+        // pre-scaled conic (A, B, C) -> conic Q = inverse covariance
+        const float gQxx = kConicScale * G[2];
+        const float gQxy = 2.0f * kConicScale * G[3];
+        const float gQyy = kConicScale * G[4];
+        const float a = P.sxx, c2 = P.syy;
+        const float b = (P.T0[0] * P.T1[0] + P.T0[1] * P.T1[1]) + P.T0[2] * P.T1[2];
+        const float det = a * c2 - b * b;
+        const float id2 = 1.0f / (det * det);
+        const float ga = (-gQxx * c2 * c2 + gQxy * b * c2 - gQyy * b * b) * id2;
+        const float gb = (2.0f * gQxx * b * c2 - gQxy * (a * c2 + b * b) + 2.0f * gQyy * a * b) * id2;
+        const float gc = (-gQxx * b * b + gQxy * a * b - gQyy * a * a) * id2;
+        // covariance = T T^T + dil I, T = J V with J = [[a_, 0, -a_ u], [0, b_, -b_ v]]
+        const float J00 = P.a, J02 = -P.a * P.u, J11 = P.b, J12 = -P.b * P.v;
+        float gJ00 = 0.f, gJ02 = 0.f, gJ11 = 0.f, gJ12 = 0.f, gV[9];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float gT0 = 2.0f * ga * P.T0[k] + gb * P.T1[k];
+            const float gT1 = 2.0f * gc * P.T1[k] + gb * P.T0[k];
+            gJ00 += gT0 * P.V[k];
+            gJ02 += gT0 * P.V[6 + k];
+            gJ11 += gT1 * P.V[3 + k];
+            gJ12 += gT1 * P.V[6 + k];
+            gV[k] = gT0 * J00;
+            gV[3 + k] = gT1 * J11;
+            gV[6 + k] = gT0 * J02 + gT1 * J12;
+        }
+        // V = Rv M, M = Rq diag(s)
+        float gRq[9];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            float acc = 0.f;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const float gM = c.R[r] * gV[k] + c.R[3 + r] * gV[3 + k] + c.R[6 + r] * gV[6 + k];
+                acc += gM * P.Rq[3 * r + k];
+                gRq[3 * r + k] = gM * s[k];
+            }
+            gsc[k] += acc;
+        }
+        {
+            const float w = P.qh[0], x = P.qh[1], y = P.qh[2], z = P.qh[3];
+            const float* R = gRq;
+            const float gw = 2.f * (-z * R[1] + y * R[2] + z * R[3] - x * R[5] - y * R[6] + x * R[7]);
+            const float gx = 2.f * (y * R[1] + z * R[2] + y * R[3] - 2.f * x * R[4] - w * R[5] + z * R[6] +
+                                    w * R[7] - 2.f * x * R[8]);
+            const float gy = 2.f * (-2.f * y * R[0] + x * R[1] + w * R[2] + x * R[3] + z * R[5] - w * R[6] +
+                                    z * R[7] - 2.f * y * R[8]);
+            const float gz = 2.f * (-2.f * z * R[0] - w * R[1] + x * R[2] + w * R[3] - 2.f * z * R[4] +
+                                    y * R[5] + x * R[6] + y * R[7]);
+            const float dot = gw * w + gx * x + gy * y + gz * z;
+            const float in = 1.0f / __builtin_sqrtf(((qw * qw + qx * qx) + qy * qy) + qz * qz);
+            gq[0] += (gw - w * dot) * in;
+            gq[1] += (gx - x * dot) * in;
+            gq[2] += (gy - y * dot) * in;
+            gq[3] += (gz - z * dot) * in;
+        }
+        // camera-space mean: through J, the 2D mean and the depth
+        const float itz = 1.0f / tz, itz2 = itz * itz, itz3 = itz2 * itz;
+        const float gtx = -gJ02 * c.fx * itz2 + G[0] * c.fx * itz;
+        const float gty = -gJ12 * c.fy * itz2 + G[1] * c.fy * itz;
+        const float gtz = -gJ00 * c.fx * itz2 + gJ02 * 2.f * c.fx * tx * itz3 - gJ11 * c.fy * itz2 +
+                          gJ12 * 2.f * c.fy * ty * itz3 - G[0] * c.fx * tx * itz2 - G[1] * c.fy * ty * itz2 +
+                          G[9];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gmu[k] += c.R[k] * gtx + c.R[3 + k] * gty + c.R[6 + k] * gtz;
+        // SH colour: colour = max(0, 1/2 + sum_k Y_k(dir) sh_k)
+        float cc[3];
+        camera_centre(c, cc);
+        float d0 = mx - cc[0], d1 = my - cc[1], d2 = mz - cc[2];
+        const float il = 1.0f / __builtin_sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+        d0 *= il; d1 *= il; d2 *= il;
+        float Y[16];
+        sh_eval<DEG>(d0, d1, d2, Y);
+        float wk[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) wk[k] = 0.f;
+        bool live = false;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float acc = 0.5f;
+#pragma unroll
+            for (int k = 0; k < NC; ++k) acc = fmaf(Y[k], g.sh[(int64_t)(3 * k + ch) * n + i], acc);
+            if (acc < 0.0f) continue;   // clamped channel: no gradient
+            const float gcol = G[6 + ch];
+            if (gcol == 0.0f) continue;
+            live = true;
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                gsh[3 * k + ch] += Y[k] * gcol;
+                wk[k] += gcol * g.sh[(int64_t)(3 * k + ch) * n + i];
+            }
+        }
+        if (DEG > 0 && live) {
+            float gd[3];
+            sh_grad<DEG>(d0, d1, d2, wk, gd);
+            const float dd = gd[0] * d0 + gd[1] * d1 + gd[2] * d2;
+            gmu[0] += (gd[0] - d0 * dd) * il;
+            gmu[1] += (gd[1] - d1 * dd) * il;
+            gmu[2] += (gd[2] - d2 * dd) * il;
+        }
+    }
+    out.means[i] = gmu[0]; out.means[n + i] = gmu[1]; out.means[2 * n + i] = gmu[2];
+    out.scales[i] = gsc[0]; out.scales[n + i] = gsc[1]; out.scales[2 * n + i] = gsc[2];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out.quats[(int64_t)k * n + i] = gq[k];
+    out.opacity[i] = gop;
+#pragma unroll
+    for (int k = 0; k < NC * 3; ++k) out.sh[(int64_t)k * n + i] = gsh[k];
+}
+
+}  // namespace
+
+hipError_t launch_project_fwd(const gs_gaussians& g, int32_t views, const gs_camera* cams, const ViewInfo* vt,
+                              const gs_options& o, Record* rec, uint32_t* counts, uint2* rects,
+                              uint32_t* depth_keys, uint32_t* dkeys_sort, uint32_t* dvals_sort,
+                              SavedHeader* hdr, hipStream_t s) {
+    if (g.n == 0) return hipSuccess;
+    const unsigned grid = (unsigned)((g.n + kBlock - 1) / kBlock);
+#define GS_PF(D)                                                                                            \
+    hipLaunchKernelGGL(k_project_fwd<D>, dim3(grid), dim3(kBlock), 0, s, g, views, cams, vt, o.tile_w,      \
+                       o.tile_h, o.kappa, o.dilation, rec, counts, rects, depth_keys, dkeys_sort, dvals_sort, hdr)
+    switch (g.sh_degree) {
+        case 0: GS_PF(0); break;
+        case 1: GS_PF(1); break;
+        case 2: GS_PF(2); break;
+        default: GS_PF(3); break;
+    }
+#undef GS_PF
+    return hipGetLastError();
+}
+
+hipError_t launch_project_bwd(const gs_gaussians& g, int32_t views, const gs_camera* cams, const gs_options& o,
+                              const float* grad2d, gs_gaussian_grads grads, hipStream_t s) {
+    if (g.n == 0) return hipSuccess;
+    const unsigned grid = (unsigned)((g.n + kBlock - 1) / kBlock);
+#define GS_PB(D) \
+    hipLaunchKernelGGL(k_project_bwd<D>, dim3(grid), dim3(kBlock), 0, s, g, views, cams, o.dilation, grad2d, grads)
+    switch (g.sh_degree) {
+        case 0: GS_PB(0); break;
+        case 1: GS_PB(1); break;
+        case 2: GS_PB(2); break;
+        default: GS_PB(3); break;
+    }
+#undef GS_PB
+    return hipGetLastError();
+}
+
+}  // namespace gs

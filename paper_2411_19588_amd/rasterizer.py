@@ -1,0 +1,293 @@
+"""PyTorch front end of libgsplash: buffers, streams and autograd.
+
+Every computation happens in the HIP library; this module only allocates
+device memory with torch, passes pointers and the current HIP stream, and
+wires gs_render_forward / gs_render_backward into ``torch.autograd``.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+from . import _native as N
+
+
+@dataclasses.dataclass
+class RasterConfig:
+    """Rasterizer options (gs_options).  Defaults follow the readings of the
+    discrete rules the paper inherits from 3DGS: alpha skip 1/255, alpha clamp
+    0.99, termination at T < 1e-4, EWA dilation 0.3, extent kappa 11.1."""
+    tile: int = 16
+    lds_batch: int = 256
+    persistent: bool = False
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    t_min: float = 1e-4
+    dilation: float = 0.3
+    kappa: float = 11.1
+    depth_mode: int = 0
+    max_pairs: int = 1 << 22
+
+    def to_c(self, max_pairs: Optional[int] = None, timer=None) -> N.GsOptions:
+        o = N.default_options()
+        o.tile_w = o.tile_h = int(self.tile)
+        o.lds_batch = int(self.lds_batch)
+        o.persistent = 1 if self.persistent else 0
+        o.alpha_min = self.alpha_min
+        o.alpha_max = self.alpha_max
+        o.t_min = self.t_min
+        o.dilation = self.dilation
+        o.kappa = self.kappa
+        o.depth_mode = int(self.depth_mode)
+        o.max_pairs = int(self.max_pairs if max_pairs is None else max_pairs)
+        o.timer = timer
+        return o
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _f32(t: torch.Tensor) -> torch.Tensor:
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        t = t.to(torch.float32).contiguous()
+    return t
+
+
+@dataclasses.dataclass
+class ForwardContext:
+    saved: torch.Tensor
+    max_pairs: int
+    n: int
+    sh_degree: int
+
+
+class Rasterizer:
+    """Renders Gaussians into a fixed set of views (sizes fixed; poses may change).
+
+    Views are packed: view v's pixels start at ``pixel_offsets[v]``; ``rgb``
+    is [3 * total_pixels] with a CHW plane per view.
+    """
+
+    def __init__(self, cameras: Sequence, config: RasterConfig = RasterConfig(), device="cuda"):
+        if len(cameras) < 1 or len(cameras) > N.GS_MAX_VIEWS:
+            raise ValueError(f"1..{N.GS_MAX_VIEWS} views supported")
+        self.config = config
+        self.device = torch.device(device)
+        self.host_cams = N.camera_array(cameras)
+        self.n_views = len(cameras)
+        self.sizes = [(int(c.width), int(c.height)) for c in cameras]
+        offs = [0]
+        for w, h in self.sizes:
+            offs.append(offs[-1] + w * h)
+        self.pixel_offsets = offs
+        self.total_pixels = offs[-1]
+        self.dev_cams = torch.empty(ctypes.sizeof(self.host_cams), dtype=torch.uint8, device=self.device)
+        self.set_cameras(cameras)
+        self.max_pairs = int(config.max_pairs)
+        self._ws: Optional[torch.Tensor] = None
+        self.timer = None
+
+    # ---------------------------------------------------------------- cameras
+    def set_cameras(self, cameras: Sequence) -> None:
+        """Update the device copy of the poses/intrinsics in place (sizes must not change)."""
+        arr = N.camera_array(cameras)
+        for i, c in enumerate(cameras):
+            if (int(c.width), int(c.height)) != self.sizes[i]:
+                raise ValueError("view sizes are fixed for a Rasterizer")
+        self.host_cams = arr
+        buf = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8)
+        self.dev_cams.copy_(buf, non_blocking=False)
+
+    def tile_count(self) -> int:
+        return int(N.lib().gs_tile_count(ctypes.byref(self.config.to_c()), self.n_views, self.host_cams))
+
+    # ---------------------------------------------------------------- buffers
+    def sizes_for(self, n: int, max_pairs: int) -> Tuple[int, int]:
+        ws = ctypes.c_size_t()
+        sv = ctypes.c_size_t()
+        o = self.config.to_c(max_pairs)
+        N.check("gs_workspace_query", N.lib().gs_workspace_query(ctypes.byref(o), n, self.n_views, self.host_cams,
+                                                                 ctypes.byref(ws), ctypes.byref(sv)))
+        return ws.value, sv.value
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    # ---------------------------------------------------------------- forward / backward
+    def _gaussians(self, means, scales, quats, opacity, sh, sh_degree) -> N.GsGaussians:
+        n = means.shape[-1]
+        return N.GsGaussians(n, sh_degree, 0, _ptr(means), _ptr(scales), _ptr(quats), _ptr(opacity), _ptr(sh))
+
+    def forward(self, means, scales, quats, opacity, sh, sh_degree: int, medium: torch.Tensor,
+                check: bool = True, max_pairs: Optional[int] = None, stream=None):
+        """Render all views.  Returns (rgb, depth, alpha, ForwardContext).
+
+        With check=True the status word is read after the forward (one host
+        synchronisation); on pair-capacity overflow the capacity is grown to
+        what the forward needed and the render is repeated.
+        """
+        means, scales, quats, opacity, sh = map(_f32, (means, scales, quats, opacity, sh))
+        medium = _f32(medium)
+        n = int(means.shape[-1])
+        mp = int(self.max_pairs if max_pairs is None else max_pairs)
+        L = N.lib()
+        g = self._gaussians(means, scales, quats, opacity, sh, sh_degree)
+        while True:
+            ws_b, sv_b = self.sizes_for(n, mp)
+            ws = self.workspace(ws_b)
+            saved = torch.empty(sv_b, dtype=torch.uint8, device=self.device)
+            rgb = torch.empty(3 * self.total_pixels, dtype=torch.float32, device=self.device)
+            depth = torch.empty(self.total_pixels, dtype=torch.float32, device=self.device)
+            alpha = torch.empty(self.total_pixels, dtype=torch.float32, device=self.device)
+            o = self.config.to_c(mp, self.timer)
+            N.check("gs_render_forward", L.gs_render_forward(
+                ctypes.byref(o), ctypes.byref(g), self.n_views, self.host_cams, _ptr(self.dev_cams), _ptr(medium),
+                _ptr(rgb), _ptr(depth), _ptr(alpha), _ptr(saved), sv_b, _ptr(ws), ws_b, _stream(stream)))
+            if not check:
+                break
+            status, needed = self.read_status(saved, stream)
+            if status & N.GS_STATUS_PAIR_OVERFLOW:
+                if needed > N.GS_MAX_PAIRS:
+                    raise RuntimeError(f"{needed} (Gaussian, tile) pairs exceed the 32-bit pair index")
+                mp = min(N.GS_MAX_PAIRS, int(needed * 1.25) + 1024)
+                self.max_pairs = mp
+                continue
+            break
+        return rgb, depth, alpha, ForwardContext(saved, mp, n, sh_degree)
+
+    def backward(self, ctx: ForwardContext, means, scales, quats, opacity, sh, medium, grad_rgb,
+                 grad_depth=None, stream=None):
+        """Adjoint of forward(); returns (d_means, d_scales, d_quats, d_opacity, d_sh, d_medium)."""
+        means, scales, quats, opacity, sh = map(_f32, (means, scales, quats, opacity, sh))
+        medium = _f32(medium)
+        grad_rgb = _f32(grad_rgb)
+        grad_depth = None if grad_depth is None else _f32(grad_depth)
+        n = ctx.n
+        ws_b, sv_b = self.sizes_for(n, ctx.max_pairs)
+        ws = self.workspace(ws_b)
+        outs = [torch.empty_like(t) for t in (means, scales, quats, opacity, sh)]
+        gmed = torch.empty((self.n_views, 9), dtype=torch.float32, device=self.device)
+        g = self._gaussians(means, scales, quats, opacity, sh, ctx.sh_degree)
+        grads = N.GsGaussianGrads(*[_ptr(t) for t in outs])
+        o = self.config.to_c(ctx.max_pairs, self.timer)
+        N.check("gs_render_backward", N.lib().gs_render_backward(
+            ctypes.byref(o), ctypes.byref(g), self.n_views, self.host_cams, _ptr(self.dev_cams), _ptr(medium),
+            _ptr(grad_rgb), _ptr(grad_depth), _ptr(ctx.saved), sv_b, ctypes.byref(grads), _ptr(gmed), _ptr(ws),
+            ws_b, _stream(stream)))
+        return (*outs, gmed)
+
+    def read_status(self, saved: torch.Tensor, stream=None) -> Tuple[int, int]:
+        st = ctypes.c_uint32()
+        need = ctypes.c_int64()
+        N.check("gs_read_status", N.lib().gs_read_status(_ptr(saved), ctypes.byref(st), ctypes.byref(need),
+                                                         _stream(stream)))
+        return int(st.value), int(need.value)
+
+    def export_keys(self, ctx: ForwardContext, stream=None):
+        """Sorted (tile << 32 | depth bits) keys, values (view * n + index) and tile ranges of a forward."""
+        T = self.tile_count()
+        cap = ctx.max_pairs
+        keys = torch.empty(max(cap, 1), dtype=torch.int64, device=self.device)
+        vals = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+        ranges = torch.empty(max(2 * T, 2), dtype=torch.int32, device=self.device)
+        cnt = ctypes.c_int64()
+        o = self.config.to_c(ctx.max_pairs)
+        N.check("gs_export_keys", N.lib().gs_export_keys(
+            ctypes.byref(o), ctx.n, self.n_views, self.host_cams, _ptr(ctx.saved), ctx.saved.numel(), _ptr(keys),
+            _ptr(vals), _ptr(ranges), cap, ctypes.byref(cnt), _stream(stream)))
+        k = int(cnt.value)
+        return keys[:k], vals[:k], ranges[: 2 * T].view(T, 2)
+
+    # ---------------------------------------------------------------- views
+    def split(self, rgb: torch.Tensor, depth: torch.Tensor, alpha: torch.Tensor):
+        """Per-view (rgb (3,H,W), depth (H,W), alpha (H,W)) views of the packed outputs."""
+        out = []
+        for v, (w, h) in enumerate(self.sizes):
+            p0 = self.pixel_offsets[v]
+            out.append((rgb[3 * p0: 3 * p0 + 3 * w * h].view(3, h, w), depth[p0: p0 + w * h].view(h, w),
+                        alpha[p0: p0 + w * h].view(h, w)))
+        return out
+
+
+class _RenderFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, means, scales, quats, opacity, sh, medium, rast: Rasterizer, sh_degree: int):
+        rgb, depth, alpha, fctx = rast.forward(means, scales, quats, opacity, sh, sh_degree, medium)
+        ctx.save_for_backward(means, scales, quats, opacity, sh, medium)
+        ctx.rast = rast
+        ctx.fctx = fctx
+        ctx.mark_non_differentiable(alpha)
+        return rgb, depth, alpha
+
+    @staticmethod
+    def backward(ctx, g_rgb, g_depth, g_alpha):
+        means, scales, quats, opacity, sh, medium = ctx.saved_tensors
+        if g_rgb is None:
+            g_rgb = torch.zeros(3 * ctx.rast.total_pixels, dtype=torch.float32, device=means.device)
+        gm, gs_, gq, go, gsh, gmed = ctx.rast.backward(ctx.fctx, means, scales, quats, opacity, sh, medium,
+                                                       g_rgb, g_depth)
+        return gm, gs_, gq, go, gsh, gmed.view_as(medium), None, None
+
+
+class _ActivateFn(torch.autograd.Function):
+    """exp(log-scale), sigmoid(logit) via gs_activate / gs_activate_backward."""
+
+    @staticmethod
+    def forward(ctx, log_scales, logits):
+        log_scales = _f32(log_scales)
+        logits = _f32(logits)
+        n = int(logits.shape[-1])
+        s = torch.empty_like(log_scales)
+        o = torch.empty_like(logits)
+        N.check("gs_activate", N.lib().gs_activate(n, _ptr(log_scales), _ptr(logits), _ptr(s), _ptr(o), _stream()))
+        ctx.save_for_backward(s, o)
+        return s, o
+
+    @staticmethod
+    def backward(ctx, g_s, g_o):
+        s, o = ctx.saved_tensors
+        g_s = torch.zeros_like(s) if g_s is None else _f32(g_s)
+        g_o = torch.zeros_like(o) if g_o is None else _f32(g_o)
+        gls = torch.empty_like(s)
+        glg = torch.empty_like(o)
+        n = int(o.shape[-1])
+        N.check("gs_activate_backward", N.lib().gs_activate_backward(
+            n, _ptr(s), _ptr(o), _ptr(g_s), _ptr(g_o), _ptr(gls), _ptr(glg), _stream()))
+        return gls, glg
+
+
+def activate(log_scales: torch.Tensor, logits: torch.Tensor):
+    """Differentiable (scales, opacity) = (exp(log_scales), sigmoid(logits)) on the GPU."""
+    return _ActivateFn.apply(log_scales, logits)
+
+
+def render(means, scales, quats, opacity, sh, medium, rast: Rasterizer, sh_degree: int):
+    """Differentiable render of all views of `rast`.
+
+    means [3,N], scales [3,N] (activated), quats [4,N], opacity [N] (activated),
+    sh [(deg+1)^2*3, N], medium [V,9].  Returns packed (rgb, depth, alpha);
+    gradients flow to every input but alpha (non-differentiable output).
+    """
+    return _RenderFn.apply(means, scales, quats, opacity, sh, medium, rast, sh_degree)
+
+
+def l1_loss(pred: torch.Tensor, target: torch.Tensor, with_loss: bool = True):
+    """(loss [1] or None, grad) of mean |pred - target| via gs_l1_loss."""
+    pred = _f32(pred)
+    target = _f32(target)
+    grad = torch.empty_like(pred)
+    loss = torch.empty(1, dtype=torch.float32, device=pred.device) if with_loss else None
+    N.check("gs_l1_loss", N.lib().gs_l1_loss(pred.numel(), _ptr(pred), _ptr(target), _ptr(loss), _ptr(grad),
+                                              _stream()))
+    return loss, grad

@@ -1,0 +1,120 @@
+"""The C-ABI library loads and exports every declared symbol; host-only calls and
+argument validation work without a GPU (no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2411_19588_amd import _native as N
+from paper_2411_19588_amd import synth
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "gsplash.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(gs_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    L = N.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+        assert name in N.PROTOTYPES, f"{name} has no ctypes prototype"
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """sizeof/offsetof of every ABI struct, as a C compiler sees the header, equal the ctypes mirrors."""
+    structs = {"gs_camera": N.GsCamera, "gs_gaussians": N.GsGaussians, "gs_gaussian_grads": N.GsGaussianGrads,
+               "gs_options": N.GsOptions, "gs_adam_group": N.GsAdamGroup}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gsplash.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{cname}.{fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
+    out = dict(l.rsplit(" ", 1) for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for cname, cls in structs.items():
+        assert int(out[cname]) == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert int(out[f"{cname}.{fname}"]) == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_default_options_and_version():
+    o = N.default_options()
+    assert (o.tile_w, o.tile_h, o.lds_batch) == (16, 16, 256)
+    assert o.alpha_min == pytest.approx(1 / 255) and o.alpha_max == pytest.approx(0.99)
+    assert o.t_min == pytest.approx(1e-4) and o.kappa == pytest.approx(11.1)
+    assert b"gfx950" in N.lib().gs_version()
+
+
+def test_workspace_query_and_tile_count():
+    sc = synth.make_scene(3, n=1000, n_views=3, view_sizes=[(96, 64), (130, 77), (64, 64)])
+    cams = N.camera_array(sc.cameras)
+    o = N.default_options()
+    ws, sv = ctypes.c_size_t(), ctypes.c_size_t()
+    assert N.lib().gs_workspace_query(ctypes.byref(o), 1000, 3, cams, ctypes.byref(ws), ctypes.byref(sv)) == 0
+    assert ws.value > 0 and sv.value > o.max_pairs * 16
+    tiles = N.lib().gs_tile_count(ctypes.byref(o), 3, cams)
+    assert tiles == 6 * 4 + 9 * 5 + 4 * 4
+    o.tile_w = o.tile_h = 8
+    o.lds_batch = 64
+    assert N.lib().gs_tile_count(ctypes.byref(o), 3, cams) == 12 * 8 + 17 * 10 + 8 * 8
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("tile_w", 12, N.GS_ERR_INVALID_ARGUMENT), ("tile_w", 32, N.GS_ERR_UNSUPPORTED),
+    ("lds_batch", 100, N.GS_ERR_INVALID_ARGUMENT), ("alpha_max", 1.5, N.GS_ERR_INVALID_ARGUMENT),
+    ("depth_mode", 3, N.GS_ERR_INVALID_ARGUMENT), ("max_pairs", -1, N.GS_ERR_INVALID_ARGUMENT),
+    ("max_pairs", 5_000_000_000, N.GS_ERR_INVALID_ARGUMENT)])
+def test_bad_options_rejected(field, value, code):
+    sc = synth.make_scene(0, n=10)
+    cams = N.camera_array(sc.cameras)
+    o = N.default_options()
+    setattr(o, field, value)
+    ws, sv = ctypes.c_size_t(), ctypes.c_size_t()
+    assert N.lib().gs_workspace_query(ctypes.byref(o), 10, 1, cams, ctypes.byref(ws), ctypes.byref(sv)) == code
+
+
+def test_bad_arguments_rejected_before_any_device_work():
+    L = N.lib()
+    sc = synth.make_scene(0, n=10)
+    cams = N.camera_array(sc.cameras)
+    o = N.default_options()
+    g = N.GsGaussians(10, 0, 0, None, None, None, None, None)     # null parameter arrays
+    rc = L.gs_render_forward(ctypes.byref(o), ctypes.byref(g), 1, cams, None, None, None, None, None, None, 0,
+                             None, 0, None)
+    assert rc == N.GS_ERR_INVALID_ARGUMENT
+    g = N.GsGaussians(10, 4, 0, 1, 1, 1, 1, 1)                     # SH degree 4
+    rc = L.gs_render_forward(ctypes.byref(o), ctypes.byref(g), 1, cams, 1, 1, 1, 1, 1, 1, 1 << 40, 1, 1 << 40, None)
+    assert rc == N.GS_ERR_INVALID_ARGUMENT
+    g = N.GsGaussians(10, 0, 0, 1, 1, 1, 1, 1)
+    rc = L.gs_render_forward(ctypes.byref(o), ctypes.byref(g), 1, cams, 1, 1, 1, 1, 1, 1, 16, 1, 16, None)
+    assert rc == N.GS_ERR_WORKSPACE_TOO_SMALL
+    rc = L.gs_render_forward(ctypes.byref(o), ctypes.byref(g), 0, cams, 1, 1, 1, 1, 1, 1, 16, 1, 16, None)
+    assert rc == N.GS_ERR_INVALID_ARGUMENT
+    assert L.gs_read_status(None, None, None, None) == N.GS_ERR_INVALID_ARGUMENT
+    assert L.gs_activate(-1, None, None, None, None, None) == N.GS_ERR_INVALID_ARGUMENT
+    assert L.gs_l1_loss(0, None, None, None, None, None) == N.GS_ERR_INVALID_ARGUMENT
+    grp = (N.GsAdamGroup * 1)()
+    grp[0].count = 5
+    assert L.gs_adam_step(grp, 1, 0.9, 0.999, 1e-8, 1, None) == N.GS_ERR_INVALID_ARGUMENT
+    assert L.gs_adam_step(grp, 1, 0.9, 0.999, 1e-8, 0, None) == N.GS_ERR_INVALID_ARGUMENT
+    assert L.gs_adam_step(grp, 9, 0.9, 0.999, 1e-8, 1, None) == N.GS_ERR_INVALID_ARGUMENT
+
+
+def test_view_limit():
+    cams = N.camera_array([synth.make_scene(0, n=1).cameras[0]] * (N.GS_MAX_VIEWS + 1))
+    o = N.default_options()
+    assert N.lib().gs_tile_count(ctypes.byref(o), N.GS_MAX_VIEWS + 1, cams) == -1

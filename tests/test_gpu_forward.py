@@ -1,0 +1,156 @@
+"""GPU parity of the forward path: keys bit-exact, images within 1e-4 of the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2411_19588_amd import synth
+from paper_2411_19588_amd import _native as N
+from tests import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+
+
+def _keys_match(scene, rast, O, opts=None):
+    rgb, depth, alpha, ctx, _ = U.forward(scene, rast)
+    k, v, ranges = rast.export_keys(ctx)
+    k = k.cpu().numpy().view(np.uint64)
+    v = v.cpu().numpy().view(np.uint32)
+    ranges = ranges.cpu().numpy().astype(np.int64)
+    ok, ov, counts = O.keys(scene, opts=opts or O.Options(tile_w=rast.config.tile, tile_h=rast.config.tile))
+    assert k.size == ok.size, (k.size, ok.size)
+    np.testing.assert_array_equal(k, ok)
+    np.testing.assert_array_equal(v, ov)
+    np.testing.assert_array_equal(ranges[:, 1] - ranges[:, 0], counts)
+    starts = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    nz = counts > 0
+    np.testing.assert_array_equal(ranges[nz, 0], starts[nz])
+    return k.size
+
+
+def test_keys_bitexact_config0(oracle_mod):
+    sc = synth.make_scene(0)
+    U.say("keys config0")
+    K = _keys_match(sc, U.make_rast(sc), oracle_mod)
+    assert K > 1000
+
+
+@pytest.mark.parametrize("tile", [16, 8])
+def test_keys_bitexact_config1_small(oracle_mod, tile):
+    sc = synth.make_scene(1, n=20000, width=203, height=141)
+    U.say(f"keys config1 small tile {tile}")
+    K = _keys_match(sc, U.make_rast(sc, tile=tile, lds_batch=64 if tile == 8 else 256), oracle_mod)
+    assert K > 20000
+
+
+def test_keys_bitexact_multiview(oracle_mod):
+    sc = synth.make_scene(3, n=5000, n_views=3, view_sizes=[(96, 64), (130, 77), (64, 64)])
+    U.say("keys multiview")
+    _keys_match(sc, U.make_rast(sc), oracle_mod)
+
+
+def _image_match(scene, rast, O, opts=None, v=0):
+    rgb, depth, alpha, ctx, _ = U.forward(scene, rast)
+    st, _ = rast.read_status(ctx.saved)
+    assert st == 0
+    cam = scene.cameras[v]
+    pix = U.pixel_list(cam.width, cam.height)
+    orc = O.render(scene, cam, scene.medium[v], opts or O.Options(depth_mode=rast.config.depth_mode),
+                   pixels=pix, variants=4)
+    g = U.gather_view(rgb, depth, alpha, rast, v, pix)
+    return U.compare_pixels(*g, orc)
+
+
+def test_image_config0(oracle_mod):
+    sc = synth.make_scene(0)
+    U.say("image config0")
+    n_main, n_var, worst = _image_match(sc, U.make_rast(sc), oracle_mod)
+    U.say(f"  main {n_main} variant {n_var} worst {worst:.2e}")
+
+
+def test_image_config1_small(oracle_mod):
+    sc = synth.make_scene(1, n=20000, width=203, height=141)
+    U.say("image config1 small")
+    n_main, n_var, worst = _image_match(sc, U.make_rast(sc), oracle_mod)
+    U.say(f"  main {n_main} variant {n_var} worst {worst:.2e}")
+
+
+def test_image_logistic_depth(oracle_mod):
+    sc = synth.make_scene(1, n=8000, width=100, height=70)
+    U.say("image logistic depth")
+    _image_match(sc, U.make_rast(sc, depth_mode=1), oracle_mod, oracle_mod.Options(depth_mode=1))
+
+
+def test_image_multiview(oracle_mod):
+    sc = synth.make_scene(3, n=5000, n_views=3, view_sizes=[(96, 64), (130, 77), (64, 64)])
+    rast = U.make_rast(sc)
+    U.say("image multiview")
+    for v in range(3):
+        _image_match(sc, rast, oracle_mod, v=v)
+
+
+@pytest.mark.parametrize("cfg", [dict(lds_batch=64), dict(lds_batch=128), dict(persistent=True),
+                                 dict(tile=8, lds_batch=64), dict(tile=8, lds_batch=64, persistent=True)])
+def test_launch_variants_bitwise_equal(cfg):
+    """Every tile shape / batch / persistent variant walks each pixel's Gaussians in the same
+    order with the same operations, so the images are bitwise identical."""
+    sc = synth.make_scene(1, n=20000, width=203, height=141)
+    U.say(f"variant {cfg}")
+    base = U.forward(sc, U.make_rast(sc))[:3]
+    other = U.forward(sc, U.make_rast(sc, **cfg))[:3]
+    for a, b in zip(base, other):
+        assert torch.equal(a, b)
+
+
+def test_empty_scene_and_all_culled(oracle_mod):
+    sc = synth.make_scene(0, n=50, width=40, height=24)
+    rast = U.make_rast(sc)
+    med = torch.from_numpy(sc.medium).cuda()
+    z = torch.zeros((3, 0), device="cuda")
+    rgb, depth, alpha, ctx = rast.forward(z, z, torch.zeros((4, 0), device="cuda"), torch.zeros(0, device="cuda"),
+                                          torch.zeros((3, 0), device="cuda"), 0, med)
+    torch.cuda.synchronize()
+    binf = sc.medium[0, 6:9]
+    expect = np.where(sc.medium[0, 3:6] > 0, binf, 0.0).astype(np.float32)
+    r = rgb.view(3, -1).cpu().numpy()
+    np.testing.assert_array_equal(r, np.repeat(expect[:, None], r.shape[1], axis=1))
+    assert torch.count_nonzero(alpha) == 0 and torch.count_nonzero(depth) == 0
+    # all Gaussians behind the camera
+    means = sc.means.copy()
+    means[2] = -means[2]
+    sc2 = synth.Scene(**{**sc.__dict__, "means": means})
+    rgb2, _, alpha2, ctx2, _ = U.forward(sc2, rast)
+    assert torch.count_nonzero(alpha2) == 0
+    np.testing.assert_array_equal(rgb2.view(3, -1).cpu().numpy(), r)
+
+
+def test_pair_overflow_reported_and_recovered(oracle_mod):
+    sc = synth.make_scene(0)
+    rast = U.make_rast(sc, max_pairs=100)
+    d = U.to_dev(sc)
+    _, _, _, ctx = rast.forward(d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], 0, d["medium"],
+                                check=False)
+    st, need = rast.read_status(ctx.saved)
+    ok, _, _ = oracle_mod.keys(sc)
+    assert st & N.GS_STATUS_PAIR_OVERFLOW and need == ok.size
+    # the checked path grows the capacity and renders correctly
+    rgb, depth, alpha, ctx = rast.forward(d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], 0,
+                                          d["medium"])
+    assert ctx.max_pairs >= ok.size
+    ref = U.forward(sc, U.make_rast(sc))[:3]
+    assert torch.equal(rgb, ref[0])
+
+
+def test_nonfinite_input_flagged_and_culled(oracle_mod):
+    sc = synth.make_scene(0, n=300, width=64, height=64)
+    bad = synth.Scene(**{**sc.__dict__, "means": sc.means.copy()})
+    bad.means[0, 5] = np.nan
+    rast = U.make_rast(bad)
+    rgb, depth, alpha, ctx, _ = U.forward(bad, rast)
+    st, _ = rast.read_status(ctx.saved)
+    assert st & N.GS_STATUS_NONFINITE_INPUT
+    keep = np.arange(sc.n) != 5
+    ref_scene = synth.Scene(means=sc.means[:, keep], log_scales=sc.log_scales[:, keep], scales=sc.scales[:, keep],
+                            quats=sc.quats[:, keep], logits=sc.logits[keep], opacity=sc.opacity[keep],
+                            sh=sc.sh[:, keep], sh_degree=0, cameras=sc.cameras, medium=sc.medium)
+    ref = U.forward(ref_scene, U.make_rast(ref_scene))[:3]
+    assert torch.equal(rgb, ref[0])
