@@ -256,7 +256,8 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
     // depth order of all (view, Gaussian) entries
     int in_b = 0;
     if (L.nv > 0)
-        GS_TRY(radix_sort_u32(dk, dv, dk2, dv2, nullptr, (uint32_t)L.nv, 0, 32, L.depth_parts, hist, &in_b, T, s));
+        GS_TRY(radix_sort_u32(dk, dv, dk2, dv2, nullptr, (uint32_t)L.nv, 0, 32, L.depth_parts, hist, &in_b,
+                              "depth_sort", T, s));
     const uint32_t* order = in_b ? dv2 : dv;
     timer_begin(T, "count_scan", s);
     GS_TRY(launch_count_scan(counts, order, L.nv, offsets, blocksums, hdr, L.max_pairs, s));
@@ -268,7 +269,7 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
     int tb = 0;
     if (L.max_pairs > 0)
         GS_TRY(radix_sort_u32(tiles_a, vals_a, tiles_b, vals_b, &hdr->pair_count, 0, 0, L.tile_bits, L.pair_parts,
-                              hist, &tb, T, s));
+                              hist, &tb, "tile_sort", T, s));
     const uint32_t* st = tb ? tiles_b : tiles_a;
     const uint32_t* sv = tb ? vals_b : vals_a;
     timer_begin(T, "ranges", s);

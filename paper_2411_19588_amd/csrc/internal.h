@@ -75,7 +75,7 @@ hipError_t launch_project_bwd(const gs_gaussians& g, int32_t views, const gs_cam
 // (or n_host if n_dev is null).  Returns in *out_in_b whether the result sits in the B buffers.
 hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b,
                           const uint32_t* n_dev, uint32_t n_host, int bit0, int nbits, int parts,
-                          uint32_t* hist, int* result_in_b, void* timer, hipStream_t s);
+                          uint32_t* hist, int* result_in_b, const char* tag, void* timer, hipStream_t s);
 hipError_t launch_count_scan(const uint32_t* counts, const uint32_t* order, int64_t nv, uint64_t* offsets,
                              uint64_t* blocksums, SavedHeader* hdr, int64_t max_pairs, hipStream_t s);
 hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uint32_t* counts, const uint2* rects,

@@ -11,6 +11,8 @@
 //                 inside each wave64 with ballots (lanes with equal digits are
 //                 found by intersecting one ballot per digit bit), combines the
 //                 four waves through LDS and scatters.
+#include <string>
+
 #include "internal.h"
 
 namespace gs {
@@ -147,7 +149,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
 
 hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b,
                           const uint32_t* n_dev, uint32_t n_host, int bit0, int nbits, int parts,
-                          uint32_t* hist, int* result_in_b, void* timer, hipStream_t s) {
+                          uint32_t* hist, int* result_in_b, const char* tag, void* timer, hipStream_t s) {
+    const std::string th = std::string(tag) + "_hist", ts = std::string(tag) + "_scan",
+                      tc = std::string(tag) + "_scatter";
     int in_b = 0;
     for (int done = 0; done < nbits; done += kRadixBits) {
         const int bits = nbits - done < kRadixBits ? nbits - done : kRadixBits;
@@ -156,14 +160,14 @@ hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, 
         const uint32_t* vin = in_b ? vals_b : vals_a;
         uint32_t* kout = in_b ? keys_a : keys_b;
         uint32_t* vout = in_b ? vals_a : vals_b;
-        timer_begin(timer, "radix_hist", s);
+        timer_begin(timer, th.c_str(), s);
         hipLaunchKernelGGL(k_hist, dim3(parts), dim3(kBlock), 0, s, kin, n_dev, n_host, shift,
                            (1u << bits) - 1u, parts, hist);
         timer_end(timer, s);
-        timer_begin(timer, "radix_scan", s);
+        timer_begin(timer, ts.c_str(), s);
         hipLaunchKernelGGL(k_scan_table, dim3(1), dim3(1024), 0, s, hist, kRadix * parts);
         timer_end(timer, s);
-        timer_begin(timer, "radix_scatter", s);
+        timer_begin(timer, tc.c_str(), s);
         hipLaunchKernelGGL(k_scatter, dim3(parts), dim3(kBlock), 0, s, kin, vin, kout, vout, n_dev, n_host, shift,
                            bits, parts, hist);
         timer_end(timer, s);

@@ -167,8 +167,11 @@ class Rasterizer:
         return rgb, depth, alpha, ForwardContext(saved, mp, n, sh_degree)
 
     def backward(self, ctx: ForwardContext, means, scales, quats, opacity, sh, medium, grad_rgb,
-                 grad_depth=None, stream=None):
-        """Adjoint of forward(); returns (d_means, d_scales, d_quats, d_opacity, d_sh, d_medium)."""
+                 grad_depth=None, stream=None, out=None):
+        """Adjoint of forward(); returns (d_means, d_scales, d_quats, d_opacity, d_sh, d_medium).
+
+        `out` may supply those six tensors (contiguous float32, same shapes) to be overwritten.
+        """
         means, scales, quats, opacity, sh = map(_f32, (means, scales, quats, opacity, sh))
         medium = _f32(medium)
         grad_rgb = _f32(grad_rgb)
@@ -176,8 +179,14 @@ class Rasterizer:
         n = ctx.n
         ws_b, sv_b = self.sizes_for(n, ctx.max_pairs)
         ws = self.workspace(ws_b)
-        outs = [torch.empty_like(t) for t in (means, scales, quats, opacity, sh)]
-        gmed = torch.empty((self.n_views, 9), dtype=torch.float32, device=self.device)
+        if out is not None:
+            *outs, gmed = out
+            for o_, ref in zip(outs + [gmed], (means, scales, quats, opacity, sh, medium)):
+                if o_.dtype != torch.float32 or not o_.is_contiguous() or o_.numel() != ref.numel():
+                    raise ValueError("gradient buffers must be contiguous float32 of the parameter sizes")
+        else:
+            outs = [torch.empty_like(t) for t in (means, scales, quats, opacity, sh)]
+            gmed = torch.empty((self.n_views, 9), dtype=torch.float32, device=self.device)
         g = self._gaussians(means, scales, quats, opacity, sh, ctx.sh_degree)
         grads = N.GsGaussianGrads(*[_ptr(t) for t in outs])
         o = self.config.to_c(ctx.max_pairs, self.timer)

@@ -86,6 +86,24 @@ def gather_view(rgb, depth, alpha, rast, v, pix):
     return r[:, y, x].T.copy(), d[y, x].copy(), a[y, x].copy()
 
 
+def unambiguous(O, scene, v, G, opts=None, Gz=None):
+    """Zero the upstream gradient at pixels whose forward has a near-threshold decision.
+
+    At such pixels FP32 and FP64 may legitimately take different discrete
+    decisions (alpha vs 1/255, transmittance vs 1e-4), so their gradients are
+    not unique; both sides get the same masked upstream gradient.
+    """
+    cam = scene.cameras[v]
+    orc = O.render(scene, cam, scene.medium[v], opts or O.Options(), variants=1)
+    amb = orc["nvar"] > 0
+    G = np.array(G, copy=True)
+    G[amb] = 0.0
+    if Gz is not None:
+        Gz = np.array(Gz, copy=True)
+        Gz[amb] = 0.0
+    return G, Gz, int(amb.sum())
+
+
 def grad_close(got, ref, rel=1e-3, name=""):
     """Per-element |g - r| <= rel*|r| + rel*rms(r), and block ||g - r|| <= rel*||r||."""
     got = np.asarray(got, np.float64)

@@ -39,7 +39,8 @@ def test_grad_vs_oracle_small(oracle_mod, depth_mode, with_gz):
     rng = np.random.default_rng(7)
     G = rng.normal(size=(P, 3))
     Gz = rng.normal(size=P) if with_gz else None
-    U.say(f"grad small mode {depth_mode} gz {with_gz}")
+    G, Gz, n_amb = U.unambiguous(O, sc, 0, G, O.Options(depth_mode=depth_mode), Gz)
+    U.say(f"grad small mode {depth_mode} gz {with_gz} ambiguous pixels {n_amb}")
     got = _gpu_grads(sc, U.make_rast(sc, depth_mode=depth_mode), G, Gz)
     ref = O.backward(sc, cam, sc.medium[0], G, Gz, O.Options(depth_mode=depth_mode))
     _check_all(got, ref)
@@ -50,7 +51,8 @@ def test_grad_vs_oracle_sh_degree0_config0(oracle_mod):
     sc = synth.make_scene(0)
     cam = sc.cameras[0]
     G = np.random.default_rng(8).normal(size=(cam.width * cam.height, 3))
-    U.say("grad config0")
+    G, _, n_amb = U.unambiguous(O, sc, 0, G)
+    U.say(f"grad config0 ambiguous pixels {n_amb}")
     got = _gpu_grads(sc, U.make_rast(sc), G)
     _check_all(got, O.backward(sc, cam, sc.medium[0], G))
 
@@ -61,6 +63,7 @@ def test_grad_launch_variants(oracle_mod, cfg):
     sc = synth.make_scene(1, n=3000, width=96, height=64)
     cam = sc.cameras[0]
     G = np.random.default_rng(9).normal(size=(cam.width * cam.height, 3))
+    G, _, _ = U.unambiguous(O, sc, 0, G)
     U.say(f"grad variant {cfg}")
     got = _gpu_grads(sc, U.make_rast(sc, **cfg), G)
     _check_all(got, O.backward(sc, cam, sc.medium[0], G))
@@ -108,6 +111,7 @@ def test_autograd_function_and_activation(oracle_mod):
     scales, opacity = R.activate(ls, lg)
     rgb, depth, alpha = R.render(means, scales, quats, opacity, sh, med, rast, sc.sh_degree)
     G = np.random.default_rng(3).normal(size=(cam.width * cam.height, 3))
+    G, _, _ = U.unambiguous(O, sc, 0, G)
     Gt = torch.from_numpy(G.T.reshape(-1).astype(np.float32)).cuda()
     (rgb * Gt).sum().backward()
     U.say("autograd")
@@ -133,7 +137,7 @@ def test_multiview_grad_sums_views(oracle_mod):
     rast = U.make_rast(sc)
     rgb, depth, alpha, ctx, d = U.forward(sc, rast)
     rng = np.random.default_rng(5)
-    Gs = [rng.normal(size=(c.width * c.height, 3)) for c in sc.cameras]
+    Gs = [U.unambiguous(O, sc, v, rng.normal(size=(c.width * c.height, 3)))[0] for v, c in enumerate(sc.cameras)]
     g_rgb = torch.cat([torch.from_numpy(G.T.reshape(-1).astype(np.float32)) for G in Gs]).cuda()
     out = rast.backward(ctx, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["medium"], g_rgb)
     got = dict(zip(FIELDS + ("medium",), [t.cpu().numpy().astype(np.float64) for t in out]))
