@@ -75,8 +75,8 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     while ((1LL << bits) < tiles) ++bits;
     L->tile_bits = bits;
     L->tile_passes = (bits + kRadixBits - 1) / kRadixBits;
-    auto parts_for = [](int64_t count) {
-        int64_t p = (count + 4 * (int64_t)kSortTile - 1) / (4 * (int64_t)kSortTile);
+    auto parts_for = [](int64_t count) {   // one radix tile per partition up to kMaxSortParts partitions
+        int64_t p = (count + (int64_t)kSortTile - 1) / (int64_t)kSortTile;
         if (p < 1) p = 1;
         if (p > kMaxSortParts) p = kMaxSortParts;
         return (int)p;
@@ -112,7 +112,8 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     L->w_dvals2 = w.take(nv * 4);
     L->w_offsets = w.take((nv + 1) * 8);
     L->w_blocksums = w.take(nb * 8);
-    L->w_hist = w.take((size_t)kRadix * parts * 4);
+    L->w_emit_start = w.take(((size_t)o->max_pairs / 1024 + 2) * 4);   // first entry of each emission span
+    L->w_hist = w.take(((size_t)kRadix * parts + kRadix) * 4);   // + per-digit row totals
     L->w_grad2d = w.take(nv * kGrad2D * 4);
     L->w_medpart = w.take(T * 9 * 4 + 256);   // + persistent-mode tile counter of the backward
     L->workspace_bytes = w.at;
@@ -260,10 +261,12 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
                               "depth_sort", T, s));
     const uint32_t* order = in_b ? dv2 : dv;
     timer_begin(T, "count_scan", s);
-    GS_TRY(launch_count_scan(counts, order, L.nv, offsets, blocksums, hdr, L.max_pairs, s));
+    uint32_t* emit_start = at<uint32_t>(workspace, L.w_emit_start);
+    GS_TRY(launch_count_scan(counts, order, L.nv, offsets, blocksums, hdr, L.max_pairs, emit_start, s));
     timer_end(T, s);
     timer_begin(T, "emit", s);
-    GS_TRY(launch_emit(order, offsets, counts, rects, L.nv, L.n, vt, n_views, hdr, tiles_a, vals_a, s));
+    GS_TRY(launch_emit(order, offsets, emit_start, rects, L.nv, L.n, vt, n_views, hdr, L.max_pairs, tiles_a, vals_a,
+                       s));
     timer_end(T, s);
     // stable sort of the pairs by tile id
     int tb = 0;
@@ -273,7 +276,7 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
     const uint32_t* st = tb ? tiles_b : tiles_a;
     const uint32_t* sv = tb ? vals_b : vals_a;
     timer_begin(T, "ranges", s);
-    GS_TRY(launch_ranges(st, hdr, L.tiles, ranges, s));
+    GS_TRY(launch_ranges(st, hdr, L.tiles, L.max_pairs, ranges, s));
     timer_end(T, s);
     timer_begin(T, "composite_fwd", s);
     GS_TRY(launch_composite_fwd(o, L, vt, dev_medium, rec, ranges, sv, hdr, out_rgb, out_depth, out_alpha,

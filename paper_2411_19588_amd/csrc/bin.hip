@@ -78,10 +78,14 @@ __global__ __launch_bounds__(1024) void k_count_blocks(uint64_t* blocksums, int 
     }
 }
 
+constexpr int kEmitItems = 4;
+constexpr int kEmitSpan = kBlock * kEmitItems;
+
 __global__ __launch_bounds__(kBlock) void k_count_down(const uint32_t* __restrict__ counts,
                                                       const uint32_t* __restrict__ order, int64_t nv,
                                                       const uint64_t* __restrict__ blocksums,
-                                                      uint64_t* __restrict__ offsets) {
+                                                      uint64_t* __restrict__ offsets, uint32_t* __restrict__ emit_start,
+                                                      int64_t n_spans) {
     __shared__ uint64_t part[kBlock];
     const int tid = threadIdx.x;
     const int64_t b0 = (int64_t)blockIdx.x * kScanChunk + (int64_t)tid * 16;   // 16 consecutive per thread
@@ -105,35 +109,81 @@ __global__ __launch_bounds__(kBlock) void k_count_down(const uint32_t* __restric
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int64_t r = b0 + k;
-        if (r < nv) offsets[r] = run;
+        if (r < nv) {
+            offsets[r] = run;
+            // emission spans whose first pair falls inside this entry's pairs [run, run + c)
+            if (c[k]) {
+                for (int64_t b = (int64_t)((run + kEmitSpan - 1) / kEmitSpan);
+                     b * kEmitSpan < (int64_t)(run + c[k]) && b < n_spans; ++b)
+                    emit_start[b] = (uint32_t)r;
+            }
+        }
         run += c[k];
     }
 }
 
+// Pair emission.  Workgroup b writes output pairs [b*kEmitSpan, (b+1)*kEmitSpan): it
+// stages the entries (in depth order) whose tile lists overlap that span in LDS -- the
+// first one is emit_start[b], recorded by the scan -- and each thread produces
+// consecutive output slots, so writes are coalesced and every workgroup does the same
+// amount of work whatever the rectangle sizes.  Visible entries (count >= 1) precede the
+// others in the depth order, so offsets increase strictly over them.
 __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* __restrict__ order,
                                                 const uint64_t* __restrict__ offsets,
-                                                const uint32_t* __restrict__ counts, const uint2* __restrict__ rects,
-                                                int64_t nv, int64_t n, const ViewInfo* __restrict__ vt,
+                                                const uint32_t* __restrict__ emit_start,
+                                                const uint2* __restrict__ rects, int64_t nv, int64_t n,
+                                                const ViewInfo* __restrict__ vt,
                                                 const SavedHeader* __restrict__ hdr, uint32_t* __restrict__ tiles_out,
                                                 uint32_t* __restrict__ vals_out) {
-    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (r >= nv) return;
+    __shared__ int32_t s_off[kEmitSpan + 1];
+    __shared__ uint32_t s_e[kEmitSpan + 1], s_base[kEmitSpan + 1], s_w[kEmitSpan + 1], s_tx[kEmitSpan + 1];
+    __shared__ float s_iw[kEmitSpan + 1];
     const uint64_t K = hdr->pair_count;
-    if (K == 0) return;
-    const uint32_t e = order[r];
-    const uint32_t cnt = counts[e];
-    uint64_t off = offsets[r];
-    if (cnt == 0 || off + cnt > K) return;   // the second test never fires when the scan is consistent
-    const uint2 rc = rects[e];
-    const ViewInfo vi = vt[e / (uint64_t)n];
-    const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
-    for (uint32_t ty = y0; ty <= y1; ++ty) {
-        const uint32_t row = vi.tile_base + ty * (uint32_t)vi.tiles_x;
-        for (uint32_t tx = x0; tx <= x1; ++tx) {
-            tiles_out[off] = row + tx;
-            vals_out[off] = e;
-            ++off;
+    const uint64_t p0 = (uint64_t)blockIdx.x * kEmitSpan;
+    if (K == 0 || p0 >= K) return;
+    const uint64_t p1 = min(p0 + (uint64_t)kEmitSpan, K);
+    const int tid = threadIdx.x;
+    const int64_t r0 = emit_start[blockIdx.x];
+    // candidates r0 .. r0 + kEmitSpan: the owners of this span form a prefix of them
+    int nent = 0;
+    for (int i0 = 0; i0 < kEmitSpan + 1; i0 += kBlock) {
+        const int i = i0 + tid;
+        const int64_t r = r0 + i;
+        const bool own = i < kEmitSpan + 1 && r < nv && (i == 0 || offsets[r] < p1);
+        if (own) {
+            const uint32_t e = order[r];
+            const uint2 rc = rects[e];
+            const ViewInfo vi = vt[e / (uint64_t)n];
+            const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu;
+            const uint32_t w = x1 - x0 + 1;
+            s_off[i] = (int32_t)((int64_t)offsets[r] - (int64_t)p0);
+            s_e[i] = e;
+            s_base[i] = vi.tile_base + y0 * (uint32_t)vi.tiles_x + x0;
+            s_w[i] = w;
+            s_tx[i] = (uint32_t)vi.tiles_x;
+            s_iw[i] = 1.0f / (float)w;
         }
+        nent += __syncthreads_count(own);
+    }
+    const int span = (int)(p1 - p0);
+#pragma unroll
+    for (int k = 0; k < kEmitItems; ++k) {
+        const int q = k * kBlock + tid;
+        if (q >= span) break;
+        int lo = 0, hi = nent;   // last i with s_off[i] <= q
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_off[mid] <= q) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t j = (uint32_t)(q - s_off[lo]);
+        const uint32_t w = s_w[lo];
+        uint32_t row = (uint32_t)((float)j * s_iw[lo]);
+        if (row * w > j) --row;
+        else if ((row + 1) * w <= j) ++row;
+        const uint32_t col = j - row * w;
+        tiles_out[p0 + q] = s_base[lo] + row * s_tx[lo] + col;
+        vals_out[p0 + q] = s_e[lo];
     }
 }
 
@@ -146,12 +196,12 @@ __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t* __restrict__ 
                                                   const SavedHeader* __restrict__ hdr, uint32_t n_tiles,
                                                   uint2* __restrict__ ranges) {
     const uint32_t K = hdr->pair_count;
-    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < K; i += gridDim.x * kBlock) {
-        const uint32_t t = tiles[i];
-        if (t >= n_tiles) continue;   // tile ids are < n_tiles by construction
-        if (i == 0 || tiles[i - 1] != t) ranges[t].x = i;
-        if (i + 1 == K || tiles[i + 1] != t) ranges[t].y = i + 1;
-    }
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= K) return;
+    const uint32_t t = tiles[i];
+    if (t >= n_tiles) return;   // tile ids are < n_tiles by construction
+    if (i == 0 || tiles[i - 1] != t) ranges[t].x = i;
+    if (i + 1 == K || tiles[i + 1] != t) ranges[t].y = i + 1;
 }
 
 __global__ __launch_bounds__(kBlock) void k_export(const uint32_t* __restrict__ tiles,
@@ -175,21 +225,25 @@ hipError_t launch_view_table(const ViewTable& t, ViewInfo* dst, SavedHeader* hdr
 }
 
 hipError_t launch_count_scan(const uint32_t* counts, const uint32_t* order, int64_t nv, uint64_t* offsets,
-                             uint64_t* blocksums, SavedHeader* hdr, int64_t max_pairs, hipStream_t s) {
+                             uint64_t* blocksums, SavedHeader* hdr, int64_t max_pairs, uint32_t* emit_start,
+                             hipStream_t s) {
+    const int64_t n_spans = max_pairs / kEmitSpan + 2;
     const int nb = (int)((nv + kScanChunk - 1) / kScanChunk);
     if (nb > 0) hipLaunchKernelGGL(k_count_reduce, dim3(nb), dim3(kBlock), 0, s, counts, order, nv, blocksums);
     hipLaunchKernelGGL(k_count_blocks, dim3(1), dim3(1024), 0, s, blocksums, nb, hdr, max_pairs);
-    if (nb > 0) hipLaunchKernelGGL(k_count_down, dim3(nb), dim3(kBlock), 0, s, counts, order, nv, blocksums, offsets);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_count_down, dim3(nb), dim3(kBlock), 0, s, counts, order, nv, blocksums, offsets,
+                           emit_start, n_spans);
     return hipGetLastError();
 }
 
-hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uint32_t* counts, const uint2* rects,
+hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uint32_t* emit_start, const uint2* rects,
                        int64_t nv, int64_t n, const ViewInfo* vt, int32_t views, const SavedHeader* hdr,
-                       uint32_t* tiles_out, uint32_t* vals_out, hipStream_t s) {
+                       int64_t max_pairs, uint32_t* tiles_out, uint32_t* vals_out, hipStream_t s) {
     (void)views;
-    if (nv == 0) return hipSuccess;
-    const unsigned grid = (unsigned)((nv + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_emit, dim3(grid), dim3(kBlock), 0, s, order, offsets, counts, rects, nv, n, vt, hdr,
+    if (nv == 0 || max_pairs == 0) return hipSuccess;
+    const unsigned grid = (unsigned)((max_pairs + kEmitSpan - 1) / kEmitSpan);
+    hipLaunchKernelGGL(k_emit, dim3(grid), dim3(kBlock), 0, s, order, offsets, emit_start, rects, nv, n, vt, hdr,
                        tiles_out, vals_out);
     return hipGetLastError();
 }
@@ -202,11 +256,12 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_ranges(const uint32_t* sorted_tiles, const SavedHeader* hdr, int64_t tiles, uint2* ranges,
-                         hipStream_t s) {
+hipError_t launch_ranges(const uint32_t* sorted_tiles, const SavedHeader* hdr, int64_t tiles, int64_t max_pairs,
+                         uint2* ranges, hipStream_t s) {
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, tiles * 2, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ranges, dim3(4096), dim3(kBlock), 0, s, sorted_tiles, hdr, (uint32_t)tiles, ranges);
+    if (e != hipSuccess || max_pairs == 0) return e;
+    const unsigned grid = (unsigned)((max_pairs + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_ranges, dim3(grid), dim3(kBlock), 0, s, sorted_tiles, hdr, (uint32_t)tiles, ranges);
     return hipGetLastError();
 }
 

@@ -56,7 +56,7 @@ struct Layout {
     size_t s_header, s_records, s_depth_keys, s_ranges, s_tiles_a, s_vals_a, s_tiles_b, s_vals_b;
     size_t s_tfinal, s_nlast, s_cair, s_dsum, s_wsum, saved_bytes;
     // workspace offsets (bytes)
-    size_t w_counts, w_rects, w_dkeys, w_dvals, w_dkeys2, w_dvals2, w_offsets, w_blocksums, w_hist;
+    size_t w_counts, w_rects, w_dkeys, w_dvals, w_dkeys2, w_dvals2, w_offsets, w_blocksums, w_emit_start, w_hist;
     size_t w_grad2d, w_medpart, workspace_bytes;
 };
 
@@ -76,13 +76,16 @@ hipError_t launch_project_bwd(const gs_gaussians& g, int32_t views, const gs_cam
 hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b,
                           const uint32_t* n_dev, uint32_t n_host, int bit0, int nbits, int parts,
                           uint32_t* hist, int* result_in_b, const char* tag, void* timer, hipStream_t s);
+// Exclusive scan of counts[order[r]] into offsets (u64), total and overflow into hdr, and for each
+// emission span of 1024 pairs the entry that owns its first pair (emit_start).
 hipError_t launch_count_scan(const uint32_t* counts, const uint32_t* order, int64_t nv, uint64_t* offsets,
-                             uint64_t* blocksums, SavedHeader* hdr, int64_t max_pairs, hipStream_t s);
-hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uint32_t* counts, const uint2* rects,
+                             uint64_t* blocksums, SavedHeader* hdr, int64_t max_pairs, uint32_t* emit_start,
+                             hipStream_t s);
+hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uint32_t* emit_start, const uint2* rects,
                        int64_t nv, int64_t n, const ViewInfo* vt, int32_t views, const SavedHeader* hdr,
-                       uint32_t* tiles_out, uint32_t* vals_out, hipStream_t s);
-hipError_t launch_ranges(const uint32_t* sorted_tiles, const SavedHeader* hdr, int64_t tiles, uint2* ranges,
-                         hipStream_t s);
+                       int64_t max_pairs, uint32_t* tiles_out, uint32_t* vals_out, hipStream_t s);
+hipError_t launch_ranges(const uint32_t* sorted_tiles, const SavedHeader* hdr, int64_t tiles, int64_t max_pairs,
+                         uint2* ranges, hipStream_t s);
 hipError_t launch_composite_fwd(const gs_options& o, const Layout& L, const ViewInfo* vt, const gs_medium* med,
                                 const Record* rec, const uint2* ranges, const uint32_t* vals, SavedHeader* hdr,
                                 float* out_rgb, float* out_depth, float* out_alpha, float* tfinal, uint32_t* nlast,

@@ -60,37 +60,58 @@ __global__ __launch_bounds__(kBlock) void k_l1(int64_t count, const float* __res
 
 struct AdamArgs {
     gs_adam_group g[kMaxGroups];
-    int64_t start[kMaxGroups + 1];
     int32_t count;
     float b1, b2, eps, bc1, bc2;
 };
 
+__device__ __forceinline__ float adam_one(const AdamArgs& a, const gs_adam_group& G, float p, float g, float act,
+                                          float& m, float& v, float& new_act) {
+    if (G.activation == 1) g *= act;                        // d exp(p)/dp = exp(p)
+    else if (G.activation == 2) g *= act * (1.0f - act);    // d sigmoid(p)/dp
+    m = fmaf(a.b1, m, (1.0f - a.b1) * g);
+    v = fmaf(a.b2, v, (1.0f - a.b2) * g * g);
+    const float np = p - G.lr * (m / a.bc1) / (sqrtf(v / a.bc2) + a.eps);
+    if (G.activation == 1) new_act = expf(np);
+    else if (G.activation == 2) new_act = sigmoidf_(np);
+    return np;
+}
+
+// blockIdx.y selects the group; each thread updates 4 consecutive scalars with 16-byte
+// loads and stores when the group's arrays allow it.
 __global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a) {
-    const int64_t total = a.start[a.count];
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += stride) {
-        int k = 0;
-        while (i >= a.start[k + 1]) ++k;
-        const gs_adam_group& G = a.g[k];
-        const int64_t j = i - a.start[k];
-        float g = G.grad[j];
-        const float p = G.param[j];
-        if (G.activation == 1) {
-            g *= G.activated[j];                       // d exp(p)/dp = exp(p)
-        } else if (G.activation == 2) {
-            const float o = G.activated[j];
-            g *= o * (1.0f - o);                       // d sigmoid(p)/dp
+    const gs_adam_group G = a.g[blockIdx.y];
+    const int64_t n = G.count;
+    const int64_t stride = (int64_t)gridDim.x * kBlock * 4;
+    const bool vec = ((reinterpret_cast<uintptr_t>(G.param) | reinterpret_cast<uintptr_t>(G.grad) |
+                       reinterpret_cast<uintptr_t>(G.m) | reinterpret_cast<uintptr_t>(G.v) |
+                       reinterpret_cast<uintptr_t>(G.activated)) & 15) == 0;
+    for (int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * 4; i0 < n; i0 += stride) {
+        if (vec && i0 + 4 <= n) {
+            float4 p = *reinterpret_cast<const float4*>(G.param + i0);
+            const float4 g = *reinterpret_cast<const float4*>(G.grad + i0);
+            float4 m = *reinterpret_cast<const float4*>(G.m + i0);
+            float4 v = *reinterpret_cast<const float4*>(G.v + i0);
+            float4 ac = G.activation ? *reinterpret_cast<const float4*>(G.activated + i0) : make_float4(0, 0, 0, 0);
+            float4 na = ac;
+            p.x = adam_one(a, G, p.x, g.x, ac.x, m.x, v.x, na.x);
+            p.y = adam_one(a, G, p.y, g.y, ac.y, m.y, v.y, na.y);
+            p.z = adam_one(a, G, p.z, g.z, ac.z, m.z, v.z, na.z);
+            p.w = adam_one(a, G, p.w, g.w, ac.w, m.w, v.w, na.w);
+            *reinterpret_cast<float4*>(G.param + i0) = p;
+            *reinterpret_cast<float4*>(G.m + i0) = m;
+            *reinterpret_cast<float4*>(G.v + i0) = v;
+            if (G.activation) *reinterpret_cast<float4*>(G.activated + i0) = na;
+        } else {
+            for (int64_t j = i0; j < n && j < i0 + 4; ++j) {
+                float m = G.m[j], v = G.v[j];
+                float na = 0.0f;
+                const float act = G.activation ? G.activated[j] : 0.0f;
+                G.param[j] = adam_one(a, G, G.param[j], G.grad[j], act, m, v, na);
+                G.m[j] = m;
+                G.v[j] = v;
+                if (G.activation) G.activated[j] = na;
+            }
         }
-        const float m = fmaf(a.b1, G.m[j], (1.0f - a.b1) * g);
-        const float v = fmaf(a.b2, G.v[j], (1.0f - a.b2) * g * g);
-        G.m[j] = m;
-        G.v[j] = v;
-        const float mh = m / a.bc1;
-        const float vh = v / a.bc2;
-        const float np = p - G.lr * mh / (sqrtf(vh) + a.eps);
-        G.param[j] = np;
-        if (G.activation == 1) G.activated[j] = expf(np);
-        else if (G.activation == 2) G.activated[j] = sigmoidf_(np);
     }
 }
 
@@ -132,7 +153,10 @@ int gs_l1_loss(int64_t count, const float* pred, const float* target, float* los
     if (count <= 0 || !pred || !target || (!loss && !grad)) return GS_ERR_INVALID_ARGUMENT;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (loss) hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, s, loss);
-    hipLaunchKernelGGL(k_l1, dim3(grid_for(count)), dim3(kBlock), 0, s, count, pred, target, loss, grad);
+    // at most 512 workgroups: each adds one partial sum, so the atomic tail stays short
+    unsigned g = grid_for(count);
+    if (g > 512) g = 512;
+    hipLaunchKernelGGL(k_l1, dim3(g), dim3(kBlock), 0, s, count, pred, target, loss, grad);
     return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }
 
@@ -144,23 +168,25 @@ int gs_adam_step(const gs_adam_group* host_groups, int32_t n_groups, float beta1
     AdamArgs a;
     memset(&a, 0, sizeof(a));
     a.count = n_groups;
-    a.start[0] = 0;
+    int64_t largest = 0;
     for (int k = 0; k < n_groups; ++k) {
         const gs_adam_group& G = host_groups[k];
         if (G.count < 0 || G.activation < 0 || G.activation > 2) return GS_ERR_INVALID_ARGUMENT;
         if (G.count > 0 && (!G.param || !G.grad || !G.m || !G.v || (G.activation && !G.activated)))
             return GS_ERR_INVALID_ARGUMENT;
         a.g[k] = G;
-        a.start[k + 1] = a.start[k] + G.count;
+        if (G.count > largest) largest = G.count;
     }
     a.b1 = beta1;
     a.b2 = beta2;
     a.eps = eps;
     a.bc1 = (float)(1.0 - __builtin_pow((double)beta1, (double)step));
     a.bc2 = (float)(1.0 - __builtin_pow((double)beta2, (double)step));
-    if (a.start[n_groups] == 0) return GS_OK;
-    hipLaunchKernelGGL(k_adam, dim3(grid_for(a.start[n_groups])), dim3(kBlock), 0, static_cast<hipStream_t>(stream),
-                       a);
+    if (largest == 0) return GS_OK;
+    int64_t gx = (largest + 4 * kBlock - 1) / (4 * kBlock);
+    if (gx > 2048) gx = 2048;
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)gx, (unsigned)n_groups), dim3(kBlock), 0,
+                       static_cast<hipStream_t>(stream), a);
     return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }
 

@@ -257,7 +257,8 @@ __global__ __launch_bounds__(kBlock) void k_project_fwd(gs_gaussians g, int32_t 
         counts[e] = cnt;
         rects[e] = rc;
         depth_keys[e] = dkey;
-        dkeys_sort[e] = dkey;
+        // entries that touch no tile sort after every visible one (they emit nothing)
+        dkeys_sort[e] = cnt ? dkey : 0xFFFFFFFFu;
         dvals_sort[e] = (uint32_t)e;
     }
 }

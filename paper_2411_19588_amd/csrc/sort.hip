@@ -5,12 +5,17 @@
 // Each pass is reduce-then-scan over a FIXED number of partitions `parts`; the
 // element count is read from device memory, so the launch shapes never depend
 // on data and a whole forward can be captured into a graph.
-//   1. k_hist:    each partition counts its digits (per-wave LDS histograms).
-//   2. k_scan:    exclusive scan of the digit-major [radix][parts] table.
-//   3. k_scatter: each partition re-reads its range in order, ranks keys stably
-//                 inside each wave64 with ballots (lanes with equal digits are
-//                 found by intersecting one ballot per digit bit), combines the
-//                 four waves through LDS and scatters.
+//   1. k_hist:      each partition counts its digits.  Lanes of a wave64 that
+//                   share a digit are found by intersecting one ballot per
+//                   digit bit; one lane adds the group's count (no contention
+//                   on runs of equal keys).
+//   2. k_scan_rows: one workgroup per digit scans that digit's row of the
+//                   digit-major [radix][parts] table and records the row total.
+//   3. k_scatter:   each partition turns the row totals into digit bases, then
+//                   re-reads its range tile by tile (2048 keys), ranks keys
+//                   stably inside each wave with the same ballots, combines the
+//                   four waves through LDS, reorders the tile in LDS by digit and
+//                   writes it out in digit runs (coalesced).
 #include <string>
 
 #include "internal.h"
@@ -30,117 +35,190 @@ __device__ __forceinline__ void part_range(uint32_t n, int parts, int p, uint32_
     t1 = min(tiles, t0 + per);
 }
 
+// Mask of the lanes (among `active`) whose digit equals this lane's digit.
+__device__ __forceinline__ uint64_t match_digit(uint32_t digit, int nbits, uint64_t active) {
+    uint64_t m = active;
+    for (int b = 0; b < nbits; ++b) {
+        const bool bit = (digit >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        m &= bit ? bal : ~bal;
+    }
+    return m;
+}
+
 __global__ __launch_bounds__(kBlock) void k_hist(const uint32_t* __restrict__ keys, const uint32_t* n_dev,
-                                                uint32_t n_host, int shift, uint32_t mask, int parts,
+                                                uint32_t n_host, int shift, int nbits, int parts,
                                                 uint32_t* __restrict__ hist) {
-    __shared__ uint32_t h[4][kRadix];
-    const int tid = threadIdx.x, wave = tid >> 6;
-    for (int i = tid; i < 4 * kRadix; i += kBlock) (&h[0][0])[i] = 0;
+    __shared__ uint32_t h[kRadix];
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (int i = tid; i < kRadix; i += kBlock) h[i] = 0;
     __syncthreads();
+    const uint32_t mask = (1u << nbits) - 1u;
     const uint32_t n = load_n(n_dev, n_host);
     uint32_t t0, t1;
     part_range(n, parts, blockIdx.x, t0, t1);
     for (uint32_t t = t0; t < t1; ++t) {
         const uint32_t base = t * kSortTile;
+        uint32_t key[kSortItems];
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {   // all loads in flight before any ballot
+            const uint32_t idx = base + k * kBlock + tid;
+            key[k] = idx < n ? keys[idx] : 0u;
+        }
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
-            const uint32_t idx = base + k * kBlock + tid;
-            if (idx < n) atomicAdd(&h[wave][(keys[idx] >> shift) & mask], 1u);
+            const bool valid = base + k * kBlock + tid < n;
+            const uint32_t digit = (key[k] >> shift) & mask;
+            const uint64_t m = match_digit(digit, nbits, __ballot(valid));
+            if (valid && lane == __ffsll((unsigned long long)m) - 1) atomicAdd(&h[digit], (uint32_t)__popcll(m));
         }
     }
     __syncthreads();
-    for (int d = tid; d < kRadix; d += kBlock)
-        hist[(size_t)d * parts + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+    for (int d = tid; d < kRadix; d += kBlock) hist[(size_t)d * parts + blockIdx.x] = h[d];
 }
 
-// Exclusive scan of `count` u32 values in place by one workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void k_scan_table(uint32_t* __restrict__ a, int count) {
-    __shared__ uint32_t sums[1024];
+// Exclusive scan of row d (parts <= kMaxSortParts entries) in place; totals[d] = row sum.
+__global__ __launch_bounds__(kBlock) void k_scan_rows(uint32_t* __restrict__ hist, int parts,
+                                                     uint32_t* __restrict__ totals) {
+    __shared__ uint32_t s[kBlock];
     const int tid = threadIdx.x;
-    const int per = (count + 1023) / 1024;
-    const int b = tid * per, e = min(count, b + per);
-    uint32_t s = 0;
-    for (int i = b; i < e; ++i) s += a[i];
-    sums[tid] = s;
+    uint32_t* row = hist + (size_t)blockIdx.x * parts;
+    constexpr int PER = kMaxSortParts / kBlock;
+    uint32_t v[PER];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int i = tid * PER + k;
+        v[k] = i < parts ? row[i] : 0u;
+        sum += v[k];
+    }
+    s[tid] = sum;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = tid >= off ? sums[tid - off] : 0u;
+    for (int off = 1; off < kBlock; off <<= 1) {
+        const uint32_t x = tid >= off ? s[tid - off] : 0u;
         __syncthreads();
-        sums[tid] += v;
+        s[tid] += x;
         __syncthreads();
     }
-    uint32_t run = sums[tid] - s;
-    for (int i = b; i < e; ++i) {
-        const uint32_t v = a[i];
-        a[i] = run;
-        run += v;
+    uint32_t run = s[tid] - sum;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int i = tid * PER + k;
+        if (i < parts) row[i] = run;
+        run += v[k];
     }
+    if (tid == kBlock - 1) totals[blockIdx.x] = s[kBlock - 1];
+}
+
+// Block-wide exclusive scan of one u32 per thread (256 threads); returns the total.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s, uint32_t& total) {
+    const int tid = threadIdx.x;
+    s[tid] = x;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        const uint32_t y = tid >= off ? s[tid - off] : 0u;
+        __syncthreads();
+        s[tid] += y;
+        __syncthreads();
+    }
+    total = s[kBlock - 1];
+    const uint32_t r = s[tid] - x;
+    __syncthreads();
+    return r;
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                    const uint32_t* n_dev, uint32_t n_host, int shift, int nbits,
-                                                   int parts, const uint32_t* __restrict__ hist) {
-    __shared__ uint32_t run[kRadix];
-    __shared__ uint32_t wcnt[4][kRadix];
+                                                   int parts, const uint32_t* __restrict__ hist,
+                                                   const uint32_t* __restrict__ totals) {
+    static_assert(kRadix == kBlock, "one digit per thread in the block scans");
+    __shared__ uint32_t run[kRadix];        // global write base of each digit for the next tile
+    __shared__ uint32_t wcnt[4][kRadix];    // per-wave digit counts, then per-wave digit offsets in the tile
+    __shared__ uint32_t tstart[kRadix];     // first slot of each digit in the LDS-ordered tile
+    __shared__ uint32_t scan_tmp[kBlock];
+    __shared__ uint32_t sk[kSortTile], sv[kSortTile];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const uint32_t mask = (1u << nbits) - 1u;
     const uint32_t n = load_n(n_dev, n_host);
-    for (int d = tid; d < kRadix; d += kBlock) run[d] = hist[(size_t)d * parts + blockIdx.x];
+    {
+        uint32_t tot;
+        const uint32_t base = block_exclusive_scan(totals[tid], scan_tmp, tot);
+        run[tid] = base + hist[(size_t)tid * parts + blockIdx.x];
+    }
     uint32_t t0, t1;
     part_range(n, parts, blockIdx.x, t0, t1);
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (uint32_t t = t0; t < t1; ++t) {
         for (int i = tid; i < 4 * kRadix; i += kBlock) (&wcnt[0][0])[i] = 0;
         __syncthreads();
-        // wave w ranks elements [base + w*64*ITEMS, base + (w+1)*64*ITEMS) in order: item k, lane l.
-        const uint32_t base = t * kSortTile + (uint32_t)wave * 64u * kSortItems;
+        const uint32_t tbase = t * kSortTile;
+        const uint32_t tn = min((uint32_t)kSortTile, n - tbase);
+        // wave w ranks elements [tbase + w*512, tbase + (w+1)*512) in order: item k, lane l.
+        const uint32_t wbase = tbase + (uint32_t)wave * 64u * kSortItems;
         uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
 #pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {   // all loads in flight before the ranking
+            const uint32_t idx = wbase + k * 64 + lane;
+            key[k] = idx < n ? kin[idx] : 0u;
+            val[k] = idx < n ? vin[idx] : 0u;
+        }
+#pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
-            const uint32_t idx = base + k * 64 + lane;
+            const uint32_t idx = wbase + k * 64 + lane;
             const bool valid = idx < n;
-            key[k] = valid ? kin[idx] : 0u;
-            val[k] = valid ? vin[idx] : 0u;
             const uint32_t digit = (key[k] >> shift) & mask;
-            uint64_t match = __ballot(valid);
-            for (int b = 0; b < nbits; ++b) {
-                const bool bit = (digit >> b) & 1u;
-                const uint64_t bal = __ballot(bit);
-                match &= bit ? bal : ~bal;
-            }
+            const uint64_t match = match_digit(digit, nbits, __ballot(valid));
             const uint32_t before = wcnt[wave][digit];
-            const uint32_t cnt = __popcll(match);
-            const int leader = __ffsll((unsigned long long)match) - 1;
             rank[k] = before + __popcll(match & lt_mask);
-            if (valid && lane == leader) wcnt[wave][digit] = before + cnt;
+            if (valid && lane == __ffsll((unsigned long long)match) - 1)
+                wcnt[wave][digit] = before + (uint32_t)__popcll(match);
             __builtin_amdgcn_wave_barrier();
         }
         __syncthreads();
-        // per digit: offsets of the four waves, then advance the running base
-        for (int d = tid; d < kRadix; d += kBlock) {
-            uint32_t s = run[d];
+        // digit d = tid: wave offsets inside the digit, tile-local digit start, advance the global base
+        uint32_t cnt = 0;
 #pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                const uint32_t c = wcnt[w][d];
-                wcnt[w][d] = s;
-                s += c;
-            }
-            run[d] = s;
+        for (int w = 0; w < 4; ++w) {
+            const uint32_t c = wcnt[w][tid];
+            wcnt[w][tid] = cnt;
+            cnt += c;
         }
+        uint32_t tot;
+        const uint32_t ts = block_exclusive_scan(cnt, scan_tmp, tot);
+        tstart[tid] = ts;
+        const uint32_t gbase = run[tid];
         __syncthreads();
+        // reorder the tile in LDS by digit (stable)
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
-            const uint32_t idx = base + k * 64 + lane;
+            const uint32_t idx = wbase + k * 64 + lane;
             if (idx < n) {
                 const uint32_t digit = (key[k] >> shift) & mask;
-                const uint32_t pos = wcnt[wave][digit] + rank[k];
-                if (pos < n) {   // always true when the histogram and ranking agree
-                    kout[pos] = key[k];
-                    vout[pos] = val[k];
+                const uint32_t lp = tstart[digit] + wcnt[wave][digit] + rank[k];
+                if (lp < (uint32_t)kSortTile) {   // always true: lp < tile count
+                    sk[lp] = key[k];
+                    sv[lp] = val[k];
                 }
             }
         }
+        // LDS slot i of digit d goes to global slot (run[d] - tstart[d]) + i
+        run[tid] = gbase - ts;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {
+            const uint32_t i = k * kBlock + tid;
+            if (i < tn) {
+                const uint32_t kk = sk[i];
+                const uint32_t pos = run[(kk >> shift) & mask] + i;
+                if (pos < n) {   // always true when the histogram and ranking agree
+                    kout[pos] = kk;
+                    vout[pos] = sv[i];
+                }
+            }
+        }
+        __syncthreads();
+        run[tid] = gbase + cnt;
         __syncthreads();
     }
 }
@@ -152,6 +230,7 @@ hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, 
                           uint32_t* hist, int* result_in_b, const char* tag, void* timer, hipStream_t s) {
     const std::string th = std::string(tag) + "_hist", ts = std::string(tag) + "_scan",
                       tc = std::string(tag) + "_scatter";
+    uint32_t* totals = hist + (size_t)kRadix * parts;
     int in_b = 0;
     for (int done = 0; done < nbits; done += kRadixBits) {
         const int bits = nbits - done < kRadixBits ? nbits - done : kRadixBits;
@@ -161,15 +240,14 @@ hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, 
         uint32_t* kout = in_b ? keys_a : keys_b;
         uint32_t* vout = in_b ? vals_a : vals_b;
         timer_begin(timer, th.c_str(), s);
-        hipLaunchKernelGGL(k_hist, dim3(parts), dim3(kBlock), 0, s, kin, n_dev, n_host, shift,
-                           (1u << bits) - 1u, parts, hist);
+        hipLaunchKernelGGL(k_hist, dim3(parts), dim3(kBlock), 0, s, kin, n_dev, n_host, shift, bits, parts, hist);
         timer_end(timer, s);
         timer_begin(timer, ts.c_str(), s);
-        hipLaunchKernelGGL(k_scan_table, dim3(1), dim3(1024), 0, s, hist, kRadix * parts);
+        hipLaunchKernelGGL(k_scan_rows, dim3(kRadix), dim3(kBlock), 0, s, hist, parts, totals);
         timer_end(timer, s);
         timer_begin(timer, tc.c_str(), s);
         hipLaunchKernelGGL(k_scatter, dim3(parts), dim3(kBlock), 0, s, kin, vin, kout, vout, n_dev, n_host, shift,
-                           bits, parts, hist);
+                           bits, parts, hist, totals);
         timer_end(timer, s);
         in_b = !in_b;
     }
