@@ -48,7 +48,8 @@ extern "C" {
 #define GS_STATUS_NONFINITE_INPUT    2u  /* a Gaussian had a non-finite parameter (it was culled) */
 
 #define GS_MAX_VIEWS                64
-#define GS_MAX_PAIRS         4000000000LL /* pair indices are 32-bit */
+#define GS_MAX_PAIRS         2147483647LL /* pair indices are 31-bit */
+#define GS_MAX_PHASES                4
 
 typedef void* gs_stream_t;               /* hipStream_t; NULL = the default stream */
 
@@ -110,11 +111,16 @@ typedef struct gs_options {
     float dilation;                      /* 0.3: added to the diagonal of the 2D covariance (EWA low-pass) */
     float kappa;                         /* 11.1: tile rectangle = bounding box of q <= kappa (> 2 ln 255) */
     int32_t depth_mode;                  /* 0: z = alpha-weighted depth; 1: z = 2/(1+exp(-0.1 z)) - 1 */
-    int64_t max_pairs;                   /* capacity of the (Gaussian, tile) pair list, <= GS_MAX_PAIRS */
+    int32_t phases;                      /* depth-progressive binning: 1 = bin every (Gaussian, tile) pair at
+                                            once; 2..4 = bin the depth-sorted Gaussians in that many rank
+                                            ranges (nearest 1/32 | 1/8 | rest for 3) and, after each range,
+                                            only for tiles that still have a pixel above t_min (default 3).
+                                            Images are identical for every value. */
+    int64_t max_pairs;                   /* capacity of the stored (Gaussian, tile) pair list, <= GS_MAX_PAIRS */
     void* timer;                         /* optional gs_timer* receiving per-kernel HIP events; NULL = none */
 } gs_options;
 
-/* Fill `opts` with the defaults above (max_pairs = 1 << 24). */
+/* Fill `opts` with the defaults above (phases = 3, max_pairs = 1 << 24). */
 void gs_default_options(gs_options* opts);
 
 /* Library version string (static storage). */
@@ -168,16 +174,31 @@ int gs_render_backward(const gs_options* opts, const gs_gaussians* g, int32_t n_
  * produced (compare with opts.max_pairs).  Either output may be NULL. */
 int gs_read_status(const void* saved, uint32_t* status_bits, int64_t* pairs_needed, gs_stream_t stream);
 
-/* Write the sorted (tile, depth) key list of the last forward into caller
- * buffers: keys[k] = (global tile id << 32) | FP32 bits of the view depth,
- * values[k] = view * n + Gaussian index, tile_ranges[2 t .. 2 t + 1] = [start,
- * end) of global tile t (tiles numbered row-major within a view, views in
- * order).  Buffers hold `capacity` pairs and gs_workspace_query's tile count;
- * *pair_count (HOST) receives the number of pairs.  Synchronises `stream`.
+/* Write the (tile, depth) key list of the last forward into caller buffers:
+ * keys[k] = (global tile id << 32) | FP32 bits of the view depth, values[k] =
+ * view * n + Gaussian index (tiles numbered row-major within a view, views in
+ * order).  The list is stored phase by phase: within phase p it is sorted by
+ * key (ties in Gaussian index order), and tile_ranges[(p * tiles + t) * 2 ..]
+ * = [start, end) of tile t in phase p (tile_ranges holds GS_MAX_PHASES *
+ * gs_tile_count pairs of u32).  With opts.phases = 1 the whole list is one
+ * sorted run of every pair.  Buffers hold `capacity` pairs; *pair_count (HOST)
+ * receives the number stored.  Synchronises `stream`.
  * (Preliminaries, "Tiles"; depth order of eq. 3dgs_orig.) */
 int gs_export_keys(const gs_options* opts, int64_t n, int32_t n_views, const gs_camera* host_cams,
                    const void* saved, size_t saved_bytes, uint64_t* keys, uint32_t* values,
                    uint32_t* tile_ranges, int64_t capacity, int64_t* pair_count, gs_stream_t stream);
+
+/* Workload statistics of the last forward (synchronises `stream`):
+ *   stats[0] = K, the number of (Gaussian, tile) pairs;
+ *   stats[1] = E, the number of tile-list entries the pixels evaluated in total
+ *              (each pixel walks its tile's depth-ordered list up to and including
+ *              the entry that terminated it);
+ *   stats[2] = the number of list entries the compositing actually reached
+ *              (per tile, the furthest point any of its pixels reached);
+ *   stats[3] = the number of tiles with a non-empty list.
+ * `stats` is a HOST array of 4 entries. */
+int gs_forward_stats(const gs_options* opts, int64_t n, int32_t n_views, const gs_camera* host_cams,
+                     const void* saved, size_t saved_bytes, int64_t* stats, gs_stream_t stream);
 
 /* Total number of tiles over the views for these options (host only). */
 int64_t gs_tile_count(const gs_options* opts, int32_t n_views, const gs_camera* host_cams);

@@ -19,7 +19,8 @@ GS_ERR_HIP = -4
 GS_STATUS_PAIR_OVERFLOW = 1
 GS_STATUS_NONFINITE_INPUT = 2
 GS_MAX_VIEWS = 64
-GS_MAX_PAIRS = 4_000_000_000
+GS_MAX_PAIRS = 2_147_483_647
+GS_MAX_PHASES = 4
 
 _ERRORS = {GS_ERR_INVALID_ARGUMENT: "invalid argument", GS_ERR_UNSUPPORTED: "unsupported",
            GS_ERR_WORKSPACE_TOO_SMALL: "workspace too small", GS_ERR_HIP: "HIP runtime error"}
@@ -52,7 +53,8 @@ class GsOptions(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("lds_batch", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("t_min", ctypes.c_float), ("dilation", ctypes.c_float), ("kappa", ctypes.c_float),
-                ("depth_mode", ctypes.c_int32), ("max_pairs", ctypes.c_int64), ("timer", ctypes.c_void_p)]
+                ("depth_mode", ctypes.c_int32), ("phases", ctypes.c_int32), ("max_pairs", ctypes.c_int64),
+                ("timer", ctypes.c_void_p)]
 
 
 class GsAdamGroup(ctypes.Structure):
@@ -79,6 +81,8 @@ PROTOTYPES = {
     "gs_read_status": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_I64), _P]),
     "gs_export_keys": (ctypes.c_int, [ctypes.POINTER(GsOptions), _I64, _I32, ctypes.POINTER(GsCamera), _P, _SZ,
                                       _P, _P, _P, _I64, ctypes.POINTER(_I64), _P]),
+    "gs_forward_stats": (ctypes.c_int, [ctypes.POINTER(GsOptions), _I64, _I32, ctypes.POINTER(GsCamera), _P, _SZ,
+                                        ctypes.POINTER(_I64), _P]),
     "gs_tile_count": (_I64, [ctypes.POINTER(GsOptions), _I32, ctypes.POINTER(GsCamera)]),
     "gs_activate": (ctypes.c_int, [_I64, _P, _P, _P, _P, _P]),
     "gs_activate_backward": (ctypes.c_int, [_I64, _P, _P, _P, _P, _P, _P, _P]),

@@ -43,14 +43,18 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     if (!(o->dilation >= 0.0f && o->dilation < 1e30f) || !finite_pos(o->kappa)) return GS_ERR_INVALID_ARGUMENT;
     if (o->depth_mode != 0 && o->depth_mode != 1) return GS_ERR_INVALID_ARGUMENT;
     if (o->persistent != 0 && o->persistent != 1) return GS_ERR_INVALID_ARGUMENT;
+    if (o->phases < 0 || o->phases > GS_MAX_PHASES) return GS_ERR_INVALID_ARGUMENT;
     if (o->max_pairs < 0 || o->max_pairs > GS_MAX_PAIRS) return GS_ERR_INVALID_ARGUMENT;
     if (n * (int64_t)n_views >= (int64_t)0xFFFFFFFFLL) return GS_ERR_INVALID_ARGUMENT;
 
     memset(L, 0, sizeof(*L));
     L->n = n;
     L->views = n_views;
+    L->phases = o->phases == 0 ? kDefaultPhases : o->phases;
     L->nv = n * n_views;
     L->max_pairs = o->max_pairs;
+    L->tile_w = o->tile_w;
+    L->tile_h = o->tile_h;
     int64_t tiles = 0, pixels = 0;
     for (int v = 0; v < n_views; ++v) {
         const gs_camera& c = cams[v];
@@ -89,13 +93,12 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     L->s_header = s.take(sizeof(SavedHeader) + sizeof(ViewInfo) * GS_MAX_VIEWS);
     L->s_records = s.take(nv * sizeof(Record));
     L->s_depth_keys = s.take(nv * 4);
-    L->s_ranges = s.take(T * 8);
-    L->s_tiles_a = s.take(K * 4);
-    L->s_vals_a = s.take(K * 4);
-    L->s_tiles_b = s.take(K * 4);
-    L->s_vals_b = s.take(K * 4);
+    L->s_ranges = s.take((size_t)GS_MAX_PHASES * T * 8);
+    L->s_vals = s.take(K * 4);
+    L->s_alive = s.take(T * 4);
     L->s_tfinal = s.take(P * 4);
     L->s_nlast = s.take(P * 4);
+    L->s_done = s.take(P);
     L->s_cair = s.take(3 * P * 4);
     L->s_dsum = s.take(P * 4);
     L->s_wsum = s.take(P * 4);
@@ -110,9 +113,14 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     L->w_dvals = w.take(nv * 4);
     L->w_dkeys2 = w.take(nv * 4);
     L->w_dvals2 = w.take(nv * 4);
+    L->w_pcounts = w.take(nv * 4);
     L->w_offsets = w.take((nv + 1) * 8);
     L->w_blocksums = w.take(nb * 8);
     L->w_emit_start = w.take(((size_t)o->max_pairs / 1024 + 2) * 4);   // first entry of each emission span
+    L->w_tiles_a = w.take(K * 4);
+    L->w_vals_a = w.take(K * 4);
+    L->w_tiles_b = w.take(K * 4);
+    L->w_vals_b = w.take(K * 4);
     L->w_hist = w.take(((size_t)kRadix * parts + kRadix) * 4);   // + per-digit row totals
     L->w_grad2d = w.take(nv * kGrad2D * 4);
     L->w_medpart = w.take(T * 9 * 4 + 256);   // + persistent-mode tile counter of the backward
@@ -193,11 +201,12 @@ void gs_default_options(gs_options* o) {
     o->dilation = 0.3f;
     o->kappa = 11.1f;
     o->depth_mode = 0;
+    o->phases = kDefaultPhases;
     o->max_pairs = 1LL << 24;
     o->timer = nullptr;
 }
 
-const char* gs_version(void) { return "gsplash 0.1 (gfx950)"; }
+const char* gs_version(void) { return "gsplash 0.2 (gfx950)"; }
 
 int gs_workspace_query(const gs_options* opts, int64_t n, int32_t n_views, const gs_camera* host_cams,
                        size_t* workspace_bytes, size_t* saved_bytes) {
@@ -236,54 +245,67 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
     Record* rec = at<Record>(saved, L.s_records);
     uint32_t* depth_keys = at<uint32_t>(saved, L.s_depth_keys);
     uint2* ranges = at<uint2>(saved, L.s_ranges);
-    uint32_t* tiles_a = at<uint32_t>(saved, L.s_tiles_a);
-    uint32_t* vals_a = at<uint32_t>(saved, L.s_vals_a);
-    uint32_t* tiles_b = at<uint32_t>(saved, L.s_tiles_b);
-    uint32_t* vals_b = at<uint32_t>(saved, L.s_vals_b);
+    uint32_t* vals = at<uint32_t>(saved, L.s_vals);
+    uint32_t* alive = at<uint32_t>(saved, L.s_alive);
     uint32_t* counts = at<uint32_t>(workspace, L.w_counts);
     uint2* rects = at<uint2>(workspace, L.w_rects);
     uint32_t* dk = at<uint32_t>(workspace, L.w_dkeys);
     uint32_t* dv = at<uint32_t>(workspace, L.w_dvals);
     uint32_t* dk2 = at<uint32_t>(workspace, L.w_dkeys2);
     uint32_t* dv2 = at<uint32_t>(workspace, L.w_dvals2);
+    uint32_t* pcounts = at<uint32_t>(workspace, L.w_pcounts);
     uint64_t* offsets = at<uint64_t>(workspace, L.w_offsets);
     uint64_t* blocksums = at<uint64_t>(workspace, L.w_blocksums);
+    uint32_t* emit_start = at<uint32_t>(workspace, L.w_emit_start);
+    uint32_t* tiles_a = at<uint32_t>(workspace, L.w_tiles_a);
+    uint32_t* vals_a = at<uint32_t>(workspace, L.w_vals_a);
+    uint32_t* tiles_b = at<uint32_t>(workspace, L.w_tiles_b);
+    uint32_t* vals_b = at<uint32_t>(workspace, L.w_vals_b);
     uint32_t* hist = at<uint32_t>(workspace, L.w_hist);
 
-    GS_TRY(launch_view_table(L.table, vt, hdr, s));
+    GS_TRY(launch_view_table(L.table, L.phases, vt, hdr, s));
+    GS_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, (int64_t)GS_MAX_PHASES * L.tiles * 2, s));
     timer_begin(T, "project_fwd", s);
     GS_TRY(launch_project_fwd(*g, n_views, dev_cams, vt, o, rec, counts, rects, depth_keys, dk, dv, hdr, s));
     timer_end(T, s);
-    // depth order of all (view, Gaussian) entries
+    // depth order of all (view, Gaussian) entries; entries without tiles last
     int in_b = 0;
     if (L.nv > 0)
         GS_TRY(radix_sort_u32(dk, dv, dk2, dv2, nullptr, (uint32_t)L.nv, 0, 32, L.depth_parts, hist, &in_b,
                               "depth_sort", T, s));
     const uint32_t* order = in_b ? dv2 : dv;
-    timer_begin(T, "count_scan", s);
-    uint32_t* emit_start = at<uint32_t>(workspace, L.w_emit_start);
-    GS_TRY(launch_count_scan(counts, order, L.nv, offsets, blocksums, hdr, L.max_pairs, emit_start, s));
-    timer_end(T, s);
-    timer_begin(T, "emit", s);
-    GS_TRY(launch_emit(order, offsets, emit_start, rects, L.nv, L.n, vt, n_views, hdr, L.max_pairs, tiles_a, vals_a,
-                       s));
-    timer_end(T, s);
-    // stable sort of the pairs by tile id
-    int tb = 0;
-    if (L.max_pairs > 0)
-        GS_TRY(radix_sort_u32(tiles_a, vals_a, tiles_b, vals_b, &hdr->pair_count, 0, 0, L.tile_bits, L.pair_parts,
-                              hist, &tb, "tile_sort", T, s));
-    const uint32_t* st = tb ? tiles_b : tiles_a;
-    const uint32_t* sv = tb ? vals_b : vals_a;
-    timer_begin(T, "ranges", s);
-    GS_TRY(launch_ranges(st, hdr, L.tiles, L.max_pairs, ranges, s));
-    timer_end(T, s);
-    timer_begin(T, "composite_fwd", s);
-    GS_TRY(launch_composite_fwd(o, L, vt, dev_medium, rec, ranges, sv, hdr, out_rgb, out_depth, out_alpha,
-                                at<float>(saved, L.s_tfinal), at<uint32_t>(saved, L.s_nlast),
-                                at<float>(saved, L.s_cair), at<float>(saved, L.s_dsum), at<float>(saved, L.s_wsum),
-                                s));
-    timer_end(T, s);
+    GS_TRY(launch_visible(in_b ? dk2 : dk, L.nv, L.phases, hdr, s));
+    float* tfinal = at<float>(saved, L.s_tfinal);
+    uint32_t* nlast = at<uint32_t>(saved, L.s_nlast);
+    uint8_t* done = at<uint8_t>(saved, L.s_done);
+    float* cair = at<float>(saved, L.s_cair);
+    float* dsum = at<float>(saved, L.s_dsum);
+    float* wsum = at<float>(saved, L.s_wsum);
+    for (int ph = 0; ph < L.phases; ++ph) {
+        timer_begin(T, "phase_count", s);
+        GS_TRY(launch_phase_count(order, counts, rects, L.nv, L.n, vt, alive, hdr, ph, pcounts, s));
+        timer_end(T, s);
+        timer_begin(T, "count_scan", s);
+        GS_TRY(launch_count_scan(pcounts, L.nv, offsets, blocksums, hdr, ph, L.max_pairs, emit_start, s));
+        timer_end(T, s);
+        timer_begin(T, "emit", s);
+        GS_TRY(launch_emit(order, offsets, emit_start, pcounts, rects, L.nv, L.n, vt, alive, hdr, ph, L.max_pairs,
+                           tiles_a, vals_a, s));
+        timer_end(T, s);
+        // stable sort of the phase's pairs by tile id
+        int tb = 0;
+        if (L.max_pairs > 0)
+            GS_TRY(radix_sort_u32(tiles_a, vals_a, tiles_b, vals_b, &hdr->phase_count[ph], 0, 0, L.tile_bits,
+                                  L.pair_parts, hist, &tb, "tile_sort", T, s));
+        timer_begin(T, "commit", s);
+        GS_TRY(launch_commit(tb ? tiles_b : tiles_a, tb ? vals_b : vals_a, hdr, ph, L.tiles, L.max_pairs, vals,
+                             ranges, s));
+        timer_end(T, s);
+        timer_begin(T, "composite_fwd", s);
+        GS_TRY(launch_composite_fwd(o, L, ph, vt, dev_medium, rec, ranges, vals, hdr, alive, out_rgb, out_depth,
+                                    out_alpha, tfinal, nlast, done, cair, dsum, wsum, s));
+        timer_end(T, s);
+    }
     return GS_OK;
 }
 
@@ -304,11 +326,8 @@ int gs_render_backward(const gs_options* opts, const gs_gaussians* g, int32_t n_
     hipStream_t s = static_cast<hipStream_t>(stream);
     const gs_options& o = *opts;
     void* T = o.timer;
-    void* sv_ = const_cast<void*>(saved);
-    SavedHeader* hdr = at<SavedHeader>(sv_, L.s_header);
-    ViewInfo* vt = reinterpret_cast<ViewInfo*>(hdr + 1);
-    const bool in_b = (L.tile_passes % 2) == 1 && L.max_pairs > 0;
-    const uint32_t* sv = at<uint32_t>(saved, in_b ? L.s_vals_b : L.s_vals_a);
+    const SavedHeader* hdr = at<SavedHeader>(saved, L.s_header);
+    const ViewInfo* vt = reinterpret_cast<const ViewInfo*>(hdr + 1);
     float* grad2d = at<float>(workspace, L.w_grad2d);
     float* medpart = at<float>(workspace, L.w_medpart);
 
@@ -317,7 +336,7 @@ int gs_render_backward(const gs_options* opts, const gs_gaussians* g, int32_t n_
     timer_end(T, s);
     timer_begin(T, "composite_bwd", s);
     GS_TRY(launch_composite_bwd(o, L, vt, dev_medium, at<Record>(saved, L.s_records), at<uint2>(saved, L.s_ranges),
-                                sv, hdr, grad_rgb, grad_depth, at<float>(saved, L.s_tfinal),
+                                at<uint32_t>(saved, L.s_vals), grad_rgb, grad_depth, at<float>(saved, L.s_tfinal),
                                 at<uint32_t>(saved, L.s_nlast), at<float>(saved, L.s_cair),
                                 at<float>(saved, L.s_dsum), at<float>(saved, L.s_wsum), grad2d, medpart, s));
     timer_end(T, s);
@@ -350,18 +369,35 @@ int gs_export_keys(const gs_options* opts, int64_t n, int32_t n_views, const gs_
     if (!saved || !keys || !values || !tile_ranges || !pair_count || capacity < 0) return GS_ERR_INVALID_ARGUMENT;
     if (saved_bytes < L.saved_bytes) return GS_ERR_WORKSPACE_TOO_SMALL;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const bool in_b = (L.tile_passes % 2) == 1 && L.max_pairs > 0;
     const SavedHeader* hdr = at<SavedHeader>(saved, L.s_header);
-    GS_TRY(launch_export_keys(at<uint32_t>(saved, in_b ? L.s_tiles_b : L.s_tiles_a),
-                              at<uint32_t>(saved, in_b ? L.s_vals_b : L.s_vals_a),
-                              at<uint32_t>(saved, L.s_depth_keys), hdr, capacity, keys, values, s));
+    GS_TRY(launch_export_keys(L, at<uint2>(saved, L.s_ranges), at<uint32_t>(saved, L.s_vals),
+                              at<uint32_t>(saved, L.s_depth_keys), capacity, keys, values, s));
     if (L.tiles > 0)
-        GS_TRY(hipMemcpyAsync(tile_ranges, at<char>(saved, L.s_ranges), (size_t)L.tiles * 8,
+        GS_TRY(hipMemcpyAsync(tile_ranges, at<char>(saved, L.s_ranges), (size_t)GS_MAX_PHASES * L.tiles * 8,
                               hipMemcpyDeviceToDevice, s));
     SavedHeader h;
     GS_TRY(hipMemcpyAsync(&h, hdr, sizeof(h), hipMemcpyDeviceToHost, s));
     GS_TRY(hipStreamSynchronize(s));
     *pair_count = (int64_t)h.pair_count;
+    return GS_OK;
+}
+
+int gs_forward_stats(const gs_options* opts, int64_t n, int32_t n_views, const gs_camera* host_cams,
+                     const void* saved, size_t saved_bytes, int64_t* stats, gs_stream_t stream) {
+    Layout L;
+    const int rc = compute_layout(opts, n, n_views, host_cams, &L);
+    if (rc != GS_OK) return rc;
+    if (!saved || !stats) return GS_ERR_INVALID_ARGUMENT;
+    if (saved_bytes < L.saved_bytes) return GS_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // the result lands in the header's scratch words, then is copied to the host
+    SavedHeader* hdr = at<SavedHeader>(const_cast<void*>(saved), L.s_header);
+    GS_TRY(launch_forward_stats(L, reinterpret_cast<const ViewInfo*>(hdr + 1), at<uint2>(saved, L.s_ranges),
+                                at<uint32_t>(saved, L.s_nlast), at<uint8_t>(saved, L.s_done), hdr, hdr->stats, s));
+    unsigned long long host[4];
+    GS_TRY(hipMemcpyAsync(host, hdr->stats, sizeof(host), hipMemcpyDeviceToHost, s));
+    GS_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < 4; ++i) stats[i] = (int64_t)host[i];
     return GS_OK;
 }
 

@@ -1,17 +1,25 @@
 // Binning of projected Gaussians into tiles (Preliminaries, "Tiles": each
 // tile lists the Gaussians whose extent reaches it, in depth order).
 //
-// Pairs are emitted in depth order: entries (view, Gaussian) are first sorted
-// by FP32 depth (stable, so equal depths keep index order), the per-entry tile
-// counts are scanned in that order, and each entry writes its tiles.  A stable
-// sort of the pairs by tile id then yields, per tile, the Gaussians in
-// (depth, index) order -- the order of the key (tile << 32 | depth bits).
+// Depth-progressive binning.  All (view, Gaussian) entries are first sorted by
+// FP32 depth (stable, so equal depths keep index order); entries that touch no
+// tile sort last.  The visible entries are then taken in phases of increasing
+// depth rank.  Phase p emits the (tile, entry) pairs of its entries -- in phase
+// 0 for every tile of each rectangle, afterwards only for tiles where some
+// pixel has not yet terminated -- stable-sorts them by tile, and appends them
+// to the stored pair list with per-phase tile ranges.  Concatenating a tile's
+// phase ranges gives exactly the (depth, index)-ordered list of full binning,
+// cut after the phase in which the tile's last pixel terminated; compositing
+// never reads past that point, so the images are identical, while scenes whose
+// near Gaussians saturate the tiles skip sorting almost every pair.
 #include "internal.h"
 
 namespace gs {
 namespace {
 
 constexpr int kScanChunk = kBlock * 16;
+constexpr int kEmitItems = 4;
+constexpr int kEmitSpan = kBlock * kEmitItems;
 
 __global__ void k_view_table(ViewTable t, ViewInfo* dst, SavedHeader* hdr) {
     const int i = threadIdx.x;
@@ -20,19 +28,78 @@ __global__ void k_view_table(ViewTable t, ViewInfo* dst, SavedHeader* hdr) {
         hdr->status = 0;
         hdr->pair_count = 0;
         hdr->pairs_needed = 0;
-        hdr->queue = 0;
+        hdr->visible = 0;
+        hdr->stop = 0;
+        for (int p = 0; p <= GS_MAX_PHASES; ++p) {
+            hdr->phase_rank[p] = 0;
+            hdr->queue[p] = 0;
+        }
+        for (int p = 0; p < GS_MAX_PHASES; ++p) {
+            hdr->phase_base[p] = 0;
+            hdr->phase_count[p] = 0;
+            hdr->phase_alive[p] = 0;
+        }
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_count_reduce(const uint32_t* __restrict__ counts,
-                                                        const uint32_t* __restrict__ order, int64_t nv,
+// First index of 0xFFFFFFFF in the sorted depth keys = number of visible entries;
+// phase p covers ranks up to ceil(visible / 2^shift) with shifts from the table below.
+__global__ void k_visible(const uint32_t* __restrict__ keys, int64_t nv, int phases, SavedHeader* hdr) {
+    int64_t lo = 0, hi = nv;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (keys[mid] != 0xFFFFFFFFu) lo = mid + 1;
+        else hi = mid;
+    }
+    const uint32_t V = (uint32_t)lo;
+    hdr->visible = V;
+    // rank cut-offs as fractions of the visible entries: {1}, {1/32, 1}, {1/32, 1/8, 1}, {1/64, 1/16, 1/4, 1}
+    const int shifts[GS_MAX_PHASES + 1][GS_MAX_PHASES] = {
+        {0, 0, 0, 0}, {0, 0, 0, 0}, {5, 0, 0, 0}, {5, 3, 0, 0}, {6, 4, 2, 0}};
+    hdr->phase_rank[0] = 0;
+    for (int p = 0; p < phases; ++p) {
+        uint32_t r = V;
+        if (p + 1 < phases) r = (uint32_t)(((uint64_t)V + (1ull << shifts[phases][p]) - 1) >> shifts[phases][p]);
+        hdr->phase_rank[p + 1] = r;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restrict__ order,
+                                                       const uint32_t* __restrict__ counts,
+                                                       const uint2* __restrict__ rects, int64_t nv, int64_t n,
+                                                       const ViewInfo* __restrict__ vt,
+                                                       const uint32_t* __restrict__ alive,
+                                                       const SavedHeader* __restrict__ hdr, int phase,
+                                                       uint32_t* __restrict__ pcounts) {
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r >= nv) return;
+    const uint32_t r0 = hdr->phase_rank[phase], r1 = hdr->phase_rank[phase + 1];
+    uint32_t c = 0;
+    if ((uint64_t)r >= r0 && (uint64_t)r < r1 && !hdr->stop) {
+        const uint32_t e = order[r];
+        if (phase == 0) {
+            c = counts[e];
+        } else if (hdr->phase_alive[phase - 1] != 0) {
+            const uint2 rc = rects[e];
+            const ViewInfo vi = vt[e / (uint64_t)n];
+            const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
+            for (uint32_t ty = y0; ty <= y1; ++ty) {
+                const uint32_t row = vi.tile_base + ty * (uint32_t)vi.tiles_x;
+                for (uint32_t tx = x0; tx <= x1; ++tx) c += alive[row + tx] != 0u;
+            }
+        }
+    }
+    pcounts[r] = c;
+}
+
+__global__ __launch_bounds__(kBlock) void k_count_reduce(const uint32_t* __restrict__ pcounts, int64_t nv,
                                                         uint64_t* __restrict__ blocksums) {
     __shared__ uint64_t red[kBlock];
     const int64_t b0 = (int64_t)blockIdx.x * kScanChunk;
     uint64_t s = 0;
     for (int k = 0; k < 16; ++k) {
         const int64_t r = b0 + k * kBlock + threadIdx.x;
-        if (r < nv) s += counts[order[r]];
+        if (r < nv) s += pcounts[r];
     }
     red[threadIdx.x] = s;
     __syncthreads();
@@ -43,8 +110,8 @@ __global__ __launch_bounds__(kBlock) void k_count_reduce(const uint32_t* __restr
     if (threadIdx.x == 0) blocksums[blockIdx.x] = red[0];
 }
 
-// Exclusive scan of the block sums (one workgroup) and the overflow decision.
-__global__ __launch_bounds__(1024) void k_count_blocks(uint64_t* blocksums, int nb, SavedHeader* hdr,
+// Exclusive scan of the block sums (one workgroup), then the phase's base, count and capacity check.
+__global__ __launch_bounds__(1024) void k_count_blocks(uint64_t* blocksums, int nb, SavedHeader* hdr, int phase,
                                                       int64_t max_pairs) {
     __shared__ uint64_t sums[1024];
     const int tid = threadIdx.x;
@@ -66,23 +133,24 @@ __global__ __launch_bounds__(1024) void k_count_blocks(uint64_t* blocksums, int 
         blocksums[i] = run;
         run += v;
     }
-    if (tid == 1023) {
+    if (tid == 1023 && !hdr->stop) {   // after an overflow the header keeps what the failing phase needed
         const uint64_t total = sums[1023];
-        hdr->pairs_needed = total;
-        if (total > (uint64_t)max_pairs) {
+        const uint64_t base = hdr->pair_count;
+        hdr->phase_base[phase] = (uint32_t)base;
+        if (base + total > (uint64_t)max_pairs) {
             hdr->status |= GS_STATUS_PAIR_OVERFLOW;
-            hdr->pair_count = 0;
+            hdr->pairs_needed = base + total;
+            hdr->stop = 1;
+            hdr->phase_count[phase] = 0;
         } else {
-            hdr->pair_count = (uint32_t)total;
+            hdr->phase_count[phase] = (uint32_t)total;
+            hdr->pair_count = (uint32_t)(base + total);
+            hdr->pairs_needed = base + total;
         }
     }
 }
 
-constexpr int kEmitItems = 4;
-constexpr int kEmitSpan = kBlock * kEmitItems;
-
-__global__ __launch_bounds__(kBlock) void k_count_down(const uint32_t* __restrict__ counts,
-                                                      const uint32_t* __restrict__ order, int64_t nv,
+__global__ __launch_bounds__(kBlock) void k_count_down(const uint32_t* __restrict__ pcounts, int64_t nv,
                                                       const uint64_t* __restrict__ blocksums,
                                                       uint64_t* __restrict__ offsets, uint32_t* __restrict__ emit_start,
                                                       int64_t n_spans) {
@@ -94,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_count_down(const uint32_t* __restric
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int64_t r = b0 + k;
-        c[k] = r < nv ? counts[order[r]] : 0u;
+        c[k] = r < nv ? pcounts[r] : 0u;
         s += c[k];
     }
     part[tid] = s;
@@ -122,29 +190,29 @@ __global__ __launch_bounds__(kBlock) void k_count_down(const uint32_t* __restric
     }
 }
 
-// Pair emission.  Workgroup b writes output pairs [b*kEmitSpan, (b+1)*kEmitSpan): it
-// stages the entries (in depth order) whose tile lists overlap that span in LDS -- the
-// first one is emit_start[b], recorded by the scan -- and each thread produces
-// consecutive output slots, so writes are coalesced and every workgroup does the same
-// amount of work whatever the rectangle sizes.  Visible entries (count >= 1) precede the
-// others in the depth order, so offsets increase strictly over them.
-__global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* __restrict__ order,
-                                                const uint64_t* __restrict__ offsets,
-                                                const uint32_t* __restrict__ emit_start,
-                                                const uint2* __restrict__ rects, int64_t nv, int64_t n,
-                                                const ViewInfo* __restrict__ vt,
-                                                const SavedHeader* __restrict__ hdr, uint32_t* __restrict__ tiles_out,
-                                                uint32_t* __restrict__ vals_out) {
+// Phase-0 pair emission (every tile of each rectangle).  Workgroup b writes output pairs
+// [b*kEmitSpan, (b+1)*kEmitSpan): it stages the entries (in depth order) whose tile lists
+// overlap that span in LDS -- the first one is emit_start[b] -- and each thread produces
+// consecutive output slots, so writes are coalesced and every workgroup does the same amount
+// of work whatever the rectangle sizes.  Entries of phase 0 all have a non-empty rectangle,
+// so their offsets increase strictly and the owners of a span are a prefix of the candidates.
+__global__ __launch_bounds__(kBlock) void k_emit_rects(const uint32_t* __restrict__ order,
+                                                      const uint64_t* __restrict__ offsets,
+                                                      const uint32_t* __restrict__ emit_start,
+                                                      const uint2* __restrict__ rects, int64_t nv, int64_t n,
+                                                      const ViewInfo* __restrict__ vt,
+                                                      const SavedHeader* __restrict__ hdr, int phase,
+                                                      uint32_t* __restrict__ tiles_out,
+                                                      uint32_t* __restrict__ vals_out) {
     __shared__ int32_t s_off[kEmitSpan + 1];
     __shared__ uint32_t s_e[kEmitSpan + 1], s_base[kEmitSpan + 1], s_w[kEmitSpan + 1], s_tx[kEmitSpan + 1];
     __shared__ float s_iw[kEmitSpan + 1];
-    const uint64_t K = hdr->pair_count;
+    const uint64_t K = hdr->phase_count[phase];
     const uint64_t p0 = (uint64_t)blockIdx.x * kEmitSpan;
     if (K == 0 || p0 >= K) return;
     const uint64_t p1 = min(p0 + (uint64_t)kEmitSpan, K);
     const int tid = threadIdx.x;
     const int64_t r0 = emit_start[blockIdx.x];
-    // candidates r0 .. r0 + kEmitSpan: the owners of this span form a prefix of them
     int nent = 0;
     for (int i0 = 0; i0 < kEmitSpan + 1; i0 += kBlock) {
         const int i = i0 + tid;
@@ -187,64 +255,126 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* __restrict__ or
     }
 }
 
+// Later phases: one thread per entry writes the pairs of its rectangle's alive tiles.
+__global__ __launch_bounds__(kBlock) void k_emit_alive(const uint32_t* __restrict__ order,
+                                                      const uint64_t* __restrict__ offsets,
+                                                      const uint32_t* __restrict__ pcounts,
+                                                      const uint2* __restrict__ rects, int64_t nv, int64_t n,
+                                                      const ViewInfo* __restrict__ vt,
+                                                      const uint32_t* __restrict__ alive,
+                                                      const SavedHeader* __restrict__ hdr, int phase,
+                                                      uint32_t* __restrict__ tiles_out,
+                                                      uint32_t* __restrict__ vals_out) {
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r >= nv) return;
+    const uint64_t K = hdr->phase_count[phase];
+    const uint32_t c = pcounts[r];
+    if (K == 0 || c == 0) return;
+    uint64_t off = offsets[r];
+    if (off + c > K) return;   // cannot happen for a consistent scan
+    const uint32_t e = order[r];
+    const uint2 rc = rects[e];
+    const ViewInfo vi = vt[e / (uint64_t)n];
+    const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
+    const uint64_t end = off + c;
+    for (uint32_t ty = y0; ty <= y1 && off < end; ++ty) {
+        const uint32_t row = vi.tile_base + ty * (uint32_t)vi.tiles_x;
+        for (uint32_t tx = x0; tx <= x1 && off < end; ++tx) {
+            if (alive[row + tx] == 0u) continue;
+            tiles_out[off] = row + tx;
+            vals_out[off] = e;
+            ++off;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t* p, uint32_t value, int64_t count) {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock)
         p[i] = value;
 }
 
-__global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t* __restrict__ tiles,
-                                                  const SavedHeader* __restrict__ hdr, uint32_t n_tiles,
-                                                  uint2* __restrict__ ranges) {
-    const uint32_t K = hdr->pair_count;
+__global__ __launch_bounds__(kBlock) void k_commit(const uint32_t* __restrict__ tiles,
+                                                  const uint32_t* __restrict__ svals,
+                                                  const SavedHeader* __restrict__ hdr, int phase, uint32_t n_tiles,
+                                                  uint32_t* __restrict__ vals, uint2* __restrict__ ranges) {
+    const uint32_t K = hdr->phase_count[phase];
+    const uint32_t base = hdr->phase_base[phase];
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= K) return;
+    vals[base + i] = svals[i];
     const uint32_t t = tiles[i];
     if (t >= n_tiles) return;   // tile ids are < n_tiles by construction
-    if (i == 0 || tiles[i - 1] != t) ranges[t].x = i;
-    if (i + 1 == K || tiles[i + 1] != t) ranges[t].y = i + 1;
+    uint2* rg = ranges + (size_t)phase * n_tiles;
+    if (i == 0 || tiles[i - 1] != t) rg[t].x = base + i;
+    if (i + 1 == K || tiles[i + 1] != t) rg[t].y = base + i + 1;
 }
 
-__global__ __launch_bounds__(kBlock) void k_export(const uint32_t* __restrict__ tiles,
+// One workgroup per tile writes the keys of that tile's pairs in every phase.
+__global__ __launch_bounds__(kBlock) void k_export(const uint2* __restrict__ ranges, int phases, uint32_t n_tiles,
                                                   const uint32_t* __restrict__ vals,
-                                                  const uint32_t* __restrict__ depth_keys,
-                                                  const SavedHeader* __restrict__ hdr, int64_t capacity,
+                                                  const uint32_t* __restrict__ depth_keys, int64_t capacity,
                                                   uint64_t* __restrict__ keys, uint32_t* __restrict__ values) {
-    const int64_t K = min((int64_t)hdr->pair_count, capacity);
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < K; i += (int64_t)gridDim.x * kBlock) {
-        const uint32_t e = vals[i];
-        keys[i] = ((uint64_t)tiles[i] << 32) | (uint64_t)depth_keys[e];
-        values[i] = e;
+    const uint32_t t = blockIdx.x;
+    for (int p = 0; p < phases; ++p) {
+        const uint2 rg = ranges[(size_t)p * n_tiles + t];
+        for (uint32_t i = rg.x + threadIdx.x; i < rg.y; i += kBlock) {
+            if ((int64_t)i >= capacity) break;
+            const uint32_t e = vals[i];
+            keys[i] = ((uint64_t)t << 32) | (uint64_t)depth_keys[e];
+            values[i] = e;
+        }
     }
 }
 
 }  // namespace
 
-hipError_t launch_view_table(const ViewTable& t, ViewInfo* dst, SavedHeader* hdr, hipStream_t s) {
+hipError_t launch_view_table(const ViewTable& t, int phases, ViewInfo* dst, SavedHeader* hdr, hipStream_t s) {
+    (void)phases;
     hipLaunchKernelGGL(k_view_table, dim3(1), dim3(GS_MAX_VIEWS), 0, s, t, dst, hdr);
     return hipGetLastError();
 }
 
-hipError_t launch_count_scan(const uint32_t* counts, const uint32_t* order, int64_t nv, uint64_t* offsets,
-                             uint64_t* blocksums, SavedHeader* hdr, int64_t max_pairs, uint32_t* emit_start,
-                             hipStream_t s) {
-    const int64_t n_spans = max_pairs / kEmitSpan + 2;
-    const int nb = (int)((nv + kScanChunk - 1) / kScanChunk);
-    if (nb > 0) hipLaunchKernelGGL(k_count_reduce, dim3(nb), dim3(kBlock), 0, s, counts, order, nv, blocksums);
-    hipLaunchKernelGGL(k_count_blocks, dim3(1), dim3(1024), 0, s, blocksums, nb, hdr, max_pairs);
-    if (nb > 0)
-        hipLaunchKernelGGL(k_count_down, dim3(nb), dim3(kBlock), 0, s, counts, order, nv, blocksums, offsets,
-                           emit_start, n_spans);
+hipError_t launch_visible(const uint32_t* sorted_keys, int64_t nv, int phases, SavedHeader* hdr, hipStream_t s) {
+    hipLaunchKernelGGL(k_visible, dim3(1), dim3(1), 0, s, sorted_keys, nv, phases, hdr);
     return hipGetLastError();
 }
 
-hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uint32_t* emit_start, const uint2* rects,
-                       int64_t nv, int64_t n, const ViewInfo* vt, int32_t views, const SavedHeader* hdr,
-                       int64_t max_pairs, uint32_t* tiles_out, uint32_t* vals_out, hipStream_t s) {
-    (void)views;
+hipError_t launch_phase_count(const uint32_t* order, const uint32_t* counts, const uint2* rects, int64_t nv,
+                              int64_t n, const ViewInfo* vt, const uint32_t* alive, const SavedHeader* hdr,
+                              int phase, uint32_t* pcounts, hipStream_t s) {
+    if (nv == 0) return hipSuccess;
+    const unsigned grid = (unsigned)((nv + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_phase_count, dim3(grid), dim3(kBlock), 0, s, order, counts, rects, nv, n, vt, alive, hdr,
+                       phase, pcounts);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_scan(const uint32_t* pcounts, int64_t nv, uint64_t* offsets, uint64_t* blocksums,
+                             SavedHeader* hdr, int phase, int64_t max_pairs, uint32_t* emit_start, hipStream_t s) {
+    const int nb = (int)((nv + kScanChunk - 1) / kScanChunk);
+    const int64_t n_spans = max_pairs / kEmitSpan + 2;
+    if (nb > 0) hipLaunchKernelGGL(k_count_reduce, dim3(nb), dim3(kBlock), 0, s, pcounts, nv, blocksums);
+    hipLaunchKernelGGL(k_count_blocks, dim3(1), dim3(1024), 0, s, blocksums, nb, hdr, phase, max_pairs);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_count_down, dim3(nb), dim3(kBlock), 0, s, pcounts, nv, blocksums, offsets, emit_start,
+                           n_spans);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uint32_t* emit_start,
+                       const uint32_t* pcounts, const uint2* rects, int64_t nv, int64_t n, const ViewInfo* vt,
+                       const uint32_t* alive, const SavedHeader* hdr, int phase, int64_t max_pairs,
+                       uint32_t* tiles_out, uint32_t* vals_out, hipStream_t s) {
     if (nv == 0 || max_pairs == 0) return hipSuccess;
-    const unsigned grid = (unsigned)((max_pairs + kEmitSpan - 1) / kEmitSpan);
-    hipLaunchKernelGGL(k_emit, dim3(grid), dim3(kBlock), 0, s, order, offsets, emit_start, rects, nv, n, vt, hdr,
-                       tiles_out, vals_out);
+    if (phase == 0) {
+        const unsigned grid = (unsigned)((max_pairs + kEmitSpan - 1) / kEmitSpan);
+        hipLaunchKernelGGL(k_emit_rects, dim3(grid), dim3(kBlock), 0, s, order, offsets, emit_start, rects, nv, n, vt,
+                           hdr, phase, tiles_out, vals_out);
+    } else {
+        const unsigned grid = (unsigned)((nv + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_emit_alive, dim3(grid), dim3(kBlock), 0, s, order, offsets, pcounts, rects, nv, n, vt,
+                           alive, hdr, phase, tiles_out, vals_out);
+    }
     return hipGetLastError();
 }
 
@@ -256,20 +386,20 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_ranges(const uint32_t* sorted_tiles, const SavedHeader* hdr, int64_t tiles, int64_t max_pairs,
-                         uint2* ranges, hipStream_t s) {
-    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, tiles * 2, s);
-    if (e != hipSuccess || max_pairs == 0) return e;
+hipError_t launch_commit(const uint32_t* sorted_tiles, const uint32_t* sorted_vals, const SavedHeader* hdr,
+                         int phase, int64_t tiles, int64_t max_pairs, uint32_t* vals, uint2* ranges, hipStream_t s) {
+    if (max_pairs == 0) return hipSuccess;
     const unsigned grid = (unsigned)((max_pairs + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_ranges, dim3(grid), dim3(kBlock), 0, s, sorted_tiles, hdr, (uint32_t)tiles, ranges);
+    hipLaunchKernelGGL(k_commit, dim3(grid), dim3(kBlock), 0, s, sorted_tiles, sorted_vals, hdr, phase,
+                       (uint32_t)tiles, vals, ranges);
     return hipGetLastError();
 }
 
-hipError_t launch_export_keys(const uint32_t* tiles, const uint32_t* vals, const uint32_t* depth_keys,
-                              const SavedHeader* hdr, int64_t capacity, uint64_t* keys, uint32_t* values,
-                              hipStream_t s) {
-    hipLaunchKernelGGL(k_export, dim3(2048), dim3(kBlock), 0, s, tiles, vals, depth_keys, hdr, capacity, keys,
-                       values);
+hipError_t launch_export_keys(const Layout& L, const uint2* ranges, const uint32_t* vals, const uint32_t* depth_keys,
+                              int64_t capacity, uint64_t* keys, uint32_t* values, hipStream_t s) {
+    if (L.tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_export, dim3((unsigned)L.tiles), dim3(kBlock), 0, s, ranges, L.phases, (uint32_t)L.tiles,
+                       vals, depth_keys, capacity, keys, values);
     return hipGetLastError();
 }
 

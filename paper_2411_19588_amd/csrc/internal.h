@@ -15,6 +15,7 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kMaxSortParts = 1024;
 constexpr int kGrad2D = 10;              // per-(Gaussian, view) 2D gradient: m(2), conic'(3), o, rgb(3), depth
+constexpr int kDefaultPhases = 3;
 
 // Per-view layout derived from the host cameras.
 struct ViewInfo {
@@ -37,34 +38,40 @@ struct __align__(16) Record {
     float4 a, b, c;
 };
 
-// Header at the start of the saved context.
+// Header at the start of the saved context (device-side bookkeeping of a forward).
 struct SavedHeader {
     uint32_t status;                     // GS_STATUS_* bits
-    uint32_t pair_count;                 // pairs produced (0 if overflowed)
-    uint64_t pairs_needed;               // pairs the forward wanted
-    uint32_t final_buffer;               // which ping-pong buffer holds the sorted pairs (0 = A, 1 = B)
-    uint32_t queue;                      // persistent-mode tile counter
+    uint32_t pair_count;                 // pairs stored over all phases
+    uint64_t pairs_needed;               // pairs the forward wanted (a lower bound after an overflow)
+    uint32_t visible;                    // entries with at least one tile, first in the depth order
+    uint32_t stop;                       // set on overflow: later phases do nothing
+    uint32_t phase_rank[GS_MAX_PHASES + 1];   // phase p covers depth ranks [phase_rank[p], phase_rank[p+1])
+    uint32_t phase_base[GS_MAX_PHASES];       // first stored pair of phase p
+    uint32_t phase_count[GS_MAX_PHASES];      // pairs of phase p
+    uint32_t phase_alive[GS_MAX_PHASES];      // tiles with an unterminated pixel after phase p
+    uint32_t queue[GS_MAX_PHASES + 1];        // persistent-mode tile counters (forward phases)
+    unsigned long long stats[4];              // scratch of gs_forward_stats
     uint32_t pad[10];
 };
 
 struct Layout {
     int64_t n, nv, pixels, tiles, max_pairs;
-    int32_t views;
-    int32_t tile_bits, tile_passes, pair_parts, depth_parts;
+    int32_t views, phases;
+    int32_t tile_w, tile_h, tile_bits, tile_passes, pair_parts, depth_parts;
     ViewTable table;
     // saved context offsets (bytes)
-    size_t s_header, s_records, s_depth_keys, s_ranges, s_tiles_a, s_vals_a, s_tiles_b, s_vals_b;
-    size_t s_tfinal, s_nlast, s_cair, s_dsum, s_wsum, saved_bytes;
+    size_t s_header, s_records, s_depth_keys, s_ranges, s_vals, s_alive;
+    size_t s_tfinal, s_nlast, s_done, s_cair, s_dsum, s_wsum, saved_bytes;
     // workspace offsets (bytes)
-    size_t w_counts, w_rects, w_dkeys, w_dvals, w_dkeys2, w_dvals2, w_offsets, w_blocksums, w_emit_start, w_hist;
-    size_t w_grad2d, w_medpart, workspace_bytes;
+    size_t w_counts, w_rects, w_dkeys, w_dvals, w_dkeys2, w_dvals2, w_pcounts, w_offsets, w_blocksums, w_emit_start;
+    size_t w_tiles_a, w_vals_a, w_tiles_b, w_vals_b, w_hist, w_grad2d, w_medpart, workspace_bytes;
 };
 
 int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_camera* cams, Layout* L);
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (each enqueues on `s` and returns hipGetLastError()).
-hipError_t launch_view_table(const ViewTable& t, ViewInfo* dst, SavedHeader* hdr, hipStream_t s);
+hipError_t launch_view_table(const ViewTable& t, int phases, ViewInfo* dst, SavedHeader* hdr, hipStream_t s);
 hipError_t launch_project_fwd(const gs_gaussians& g, int32_t views, const gs_camera* cams, const ViewInfo* vt,
                               const gs_options& o, Record* rec, uint32_t* counts, uint2* rects,
                               uint32_t* depth_keys, uint32_t* dkeys_sort, uint32_t* dvals_sort,
@@ -76,31 +83,42 @@ hipError_t launch_project_bwd(const gs_gaussians& g, int32_t views, const gs_cam
 hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b,
                           const uint32_t* n_dev, uint32_t n_host, int bit0, int nbits, int parts,
                           uint32_t* hist, int* result_in_b, const char* tag, void* timer, hipStream_t s);
-// Exclusive scan of counts[order[r]] into offsets (u64), total and overflow into hdr, and for each
-// emission span of 1024 pairs the entry that owns its first pair (emit_start).
-hipError_t launch_count_scan(const uint32_t* counts, const uint32_t* order, int64_t nv, uint64_t* offsets,
-                             uint64_t* blocksums, SavedHeader* hdr, int64_t max_pairs, uint32_t* emit_start,
-                             hipStream_t s);
-hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uint32_t* emit_start, const uint2* rects,
-                       int64_t nv, int64_t n, const ViewInfo* vt, int32_t views, const SavedHeader* hdr,
-                       int64_t max_pairs, uint32_t* tiles_out, uint32_t* vals_out, hipStream_t s);
-hipError_t launch_ranges(const uint32_t* sorted_tiles, const SavedHeader* hdr, int64_t tiles, int64_t max_pairs,
-                         uint2* ranges, hipStream_t s);
-hipError_t launch_composite_fwd(const gs_options& o, const Layout& L, const ViewInfo* vt, const gs_medium* med,
-                                const Record* rec, const uint2* ranges, const uint32_t* vals, SavedHeader* hdr,
-                                float* out_rgb, float* out_depth, float* out_alpha, float* tfinal, uint32_t* nlast,
-                                float* cair, float* dsum, float* wsum, hipStream_t s);
+// Number of visible entries (depth-sorted keys before the first 0xFFFFFFFF) and the phase rank ranges.
+hipError_t launch_visible(const uint32_t* sorted_keys, int64_t nv, int phases, SavedHeader* hdr, hipStream_t s);
+// Per-entry pair counts of phase p (by depth rank): whole rectangles in phase 0, only the tiles
+// still alive in later phases, 0 outside the phase's ranks.
+hipError_t launch_phase_count(const uint32_t* order, const uint32_t* counts, const uint2* rects, int64_t nv,
+                              int64_t n, const ViewInfo* vt, const uint32_t* alive, const SavedHeader* hdr,
+                              int phase, uint32_t* pcounts, hipStream_t s);
+// Exclusive scan of pcounts into offsets (u64) and the phase's pair count and base in hdr (with the
+// capacity check), and for each emission span of 1024 pairs the entry that owns its first pair.
+hipError_t launch_count_scan(const uint32_t* pcounts, int64_t nv, uint64_t* offsets, uint64_t* blocksums,
+                             SavedHeader* hdr, int phase, int64_t max_pairs, uint32_t* emit_start, hipStream_t s);
+hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uint32_t* emit_start,
+                       const uint32_t* pcounts, const uint2* rects, int64_t nv, int64_t n, const ViewInfo* vt,
+                       const uint32_t* alive, const SavedHeader* hdr, int phase, int64_t max_pairs,
+                       uint32_t* tiles_out, uint32_t* vals_out, hipStream_t s);
+// Copy the phase's tile-sorted values behind the earlier phases' and record its tile ranges.
+hipError_t launch_commit(const uint32_t* sorted_tiles, const uint32_t* sorted_vals, const SavedHeader* hdr,
+                         int phase, int64_t tiles, int64_t max_pairs, uint32_t* vals, uint2* ranges, hipStream_t s);
+hipError_t launch_composite_fwd(const gs_options& o, const Layout& L, int phase, const ViewInfo* vt,
+                                const gs_medium* med, const Record* rec, const uint2* ranges, const uint32_t* vals,
+                                SavedHeader* hdr, uint32_t* alive, float* out_rgb, float* out_depth,
+                                float* out_alpha, float* tfinal, uint32_t* nlast, uint8_t* done, float* cair,
+                                float* dsum, float* wsum, hipStream_t s);
 hipError_t launch_composite_bwd(const gs_options& o, const Layout& L, const ViewInfo* vt, const gs_medium* med,
-                                const Record* rec, const uint2* ranges, const uint32_t* vals, SavedHeader* hdr,
-                                const float* grad_rgb, const float* grad_depth, const float* tfinal,
-                                const uint32_t* nlast, const float* cair, const float* dsum, const float* wsum,
-                                float* grad2d, float* medpart, hipStream_t s);
+                                const Record* rec, const uint2* ranges, const uint32_t* vals, const float* grad_rgb,
+                                const float* grad_depth, const float* tfinal, const uint32_t* nlast,
+                                const float* cair, const float* dsum, const float* wsum, float* grad2d,
+                                float* medpart, hipStream_t s);
 hipError_t launch_medium_reduce(const ViewInfo* vt, int32_t views, const float* medpart, float* grad_medium,
                                 hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
-hipError_t launch_export_keys(const uint32_t* tiles, const uint32_t* vals, const uint32_t* depth_keys,
-                              const SavedHeader* hdr, int64_t capacity, uint64_t* keys, uint32_t* values,
-                              hipStream_t s);
+hipError_t launch_export_keys(const Layout& L, const uint2* ranges, const uint32_t* vals, const uint32_t* depth_keys,
+                              int64_t capacity, uint64_t* keys, uint32_t* values, hipStream_t s);
+hipError_t launch_forward_stats(const Layout& L, const ViewInfo* vt, const uint2* ranges, const uint32_t* nlast,
+                                const uint8_t* done, const SavedHeader* hdr, unsigned long long* out,
+                                hipStream_t s);
 
 // Timer hooks (no-ops when timer == nullptr).
 void timer_begin(void* timer, const char* name, hipStream_t s);

@@ -29,6 +29,7 @@ class RasterConfig:
     dilation: float = 0.3
     kappa: float = 11.1
     depth_mode: int = 0
+    phases: int = 3
     max_pairs: int = 1 << 22
 
     def to_c(self, max_pairs: Optional[int] = None, timer=None) -> N.GsOptions:
@@ -42,6 +43,7 @@ class RasterConfig:
         o.dilation = self.dilation
         o.kappa = self.kappa
         o.depth_mode = int(self.depth_mode)
+        o.phases = int(self.phases)
         o.max_pairs = int(self.max_pairs if max_pairs is None else max_pairs)
         o.timer = timer
         return o
@@ -204,19 +206,29 @@ class Rasterizer:
         return int(st.value), int(need.value)
 
     def export_keys(self, ctx: ForwardContext, stream=None):
-        """Sorted (tile << 32 | depth bits) keys, values (view * n + index) and tile ranges of a forward."""
+        """Stored (tile << 32 | depth bits) keys, values (view * n + index) and per-phase tile ranges
+        [GS_MAX_PHASES, tiles, 2] of a forward (one sorted run per phase)."""
         T = self.tile_count()
         cap = ctx.max_pairs
         keys = torch.empty(max(cap, 1), dtype=torch.int64, device=self.device)
         vals = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
-        ranges = torch.empty(max(2 * T, 2), dtype=torch.int32, device=self.device)
+        ranges = torch.empty(max(2 * T * N.GS_MAX_PHASES, 2), dtype=torch.int32, device=self.device)
         cnt = ctypes.c_int64()
         o = self.config.to_c(ctx.max_pairs)
         N.check("gs_export_keys", N.lib().gs_export_keys(
             ctypes.byref(o), ctx.n, self.n_views, self.host_cams, _ptr(ctx.saved), ctx.saved.numel(), _ptr(keys),
             _ptr(vals), _ptr(ranges), cap, ctypes.byref(cnt), _stream(stream)))
         k = int(cnt.value)
-        return keys[:k], vals[:k], ranges[: 2 * T].view(T, 2)
+        return keys[:k], vals[:k], ranges[: 2 * T * N.GS_MAX_PHASES].view(N.GS_MAX_PHASES, T, 2)
+
+    def forward_stats(self, ctx: ForwardContext, stream=None):
+        """(K pairs, E walked list entries, list entries reached, non-empty tiles) of a forward."""
+        st = (ctypes.c_int64 * 4)()
+        o = self.config.to_c(ctx.max_pairs)
+        N.check("gs_forward_stats", N.lib().gs_forward_stats(ctypes.byref(o), ctx.n, self.n_views, self.host_cams,
+                                                             _ptr(ctx.saved), ctx.saved.numel(), st,
+                                                             _stream(stream)))
+        return tuple(int(x) for x in st)
 
     # ---------------------------------------------------------------- views
     def split(self, rgb: torch.Tensor, depth: torch.Tensor, alpha: torch.Tensor):

@@ -65,7 +65,7 @@ def test_workspace_query_and_tile_count():
     o = N.default_options()
     ws, sv = ctypes.c_size_t(), ctypes.c_size_t()
     assert N.lib().gs_workspace_query(ctypes.byref(o), 1000, 3, cams, ctypes.byref(ws), ctypes.byref(sv)) == 0
-    assert ws.value > 0 and sv.value > o.max_pairs * 16
+    assert ws.value > o.max_pairs * 16 and sv.value > o.max_pairs * 4   # sort scratch vs stored pair values
     tiles = N.lib().gs_tile_count(ctypes.byref(o), 3, cams)
     assert tiles == 6 * 4 + 9 * 5 + 4 * 4
     o.tile_w = o.tile_h = 8
