@@ -55,16 +55,20 @@ def parse():
     ap.add_argument("--lds-batch", type=int, default=256)
     ap.add_argument("--persistent", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-stride", type=int, default=8, help="oracle sample: every k-th pixel in x and y")
+    ap.add_argument("--cpu-stride", type=int, default=2, help="oracle sample: every k-th pixel in x and y")
     ap.add_argument("--no-timer", action="store_true", help="skip the per-kernel HIP event timer")
+    ap.add_argument("--phases", type=int, default=3, help="depth-progressive binning phases (1 = full binning)")
+    ap.add_argument("--eager", action="store_true", help="time eager launches only (no HIP graph replay)")
     return ap.parse_args()
 
 
-def kernel_bytes(name: str, n: int, views: int, K: int, P: int, tiles: int, ncoef: int):
-    """Algorithmic HBM bytes one launch of `name` must move (reads + writes).
+def kernel_bytes(name: str, n: int, views: int, K: int, P: int, tiles: int, ncoef: int, per_step: int = 1):
+    """Algorithmic HBM bytes one launch of `name` must move (reads + writes), averaged over the
+    `per_step` launches a step makes of it.
 
-    n Gaussians, views V, NV = n V entries, K (Gaussian, tile) pairs, P pixels.
+    n Gaussians, views V, NV = n V entries, K stored (Gaussian, tile) pairs (all phases), P pixels.
     """
+    per_step = max(1, per_step)
     NV = n * views
     param = n * (3 + 3 + 4 + 1 + 3 * ncoef) * 4
     table = {
@@ -72,13 +76,14 @@ def kernel_bytes(name: str, n: int, views: int, K: int, P: int, tiles: int, ncoe
         "project_fwd": param + NV * (48 + 4 + 8 + 4 + 8),
         "depth_sort_hist": NV * 4,
         "depth_sort_scatter": NV * 16,
-        "count_scan": NV * (8 + 8) + NV * 8,       # two gathered passes over (order, count), offsets write
-        "emit": K * 8 + NV * (4 + 8 + 4 + 8),
-        "tile_sort_hist": K * 4,
-        "tile_sort_scatter": K * 16,
-        "ranges": K * 4 + tiles * 8,
+        "phase_count": NV * 8,                     # per phase: order + count (or rectangle) per entry
+        "count_scan": NV * (4 + 4 + 8),            # per phase: two passes over the counts, offsets write
+        "emit": (K * 8) / per_step + NV * 4,
+        "tile_sort_hist": (K * 4) / per_step,
+        "tile_sort_scatter": (K * 16) / per_step,
+        "commit": (K * 12) / per_step,
         # outputs + saved state per pixel; the gathered records of traversed pairs are cache-resident
-        "composite_fwd": P * (12 + 4 + 4) + P * 28 + tiles * 8,
+        "composite_fwd": (P * (12 + 4 + 4) + P * 29 + tiles * 8) / per_step,
         "composite_bwd": P * (12 + 28) + NV * 40 + tiles * 36,
         "project_bwd": param + NV * 40 + param,
         "zero_grad2d": NV * 40,
@@ -128,6 +133,22 @@ def cpu_baseline(scene, target, stride: int):
                       f"{dt:.1f} s"}
 
 
+KERNELS = ["project_fwd", "depth_sort_hist", "depth_sort_scan", "depth_sort_scatter", "phase_count", "count_scan",
+           "emit", "tile_sort_hist", "tile_sort_scan", "tile_sort_scatter", "commit", "composite_fwd", "zero_grad2d",
+           "composite_bwd", "medium_reduce", "project_bwd"]
+
+
+def read_timer(N, timer):
+    out = {}
+    for nm in KERNELS:
+        tot = ctypes.c_double()
+        cnt = ctypes.c_int32()
+        N.check("gs_timer_read", N.lib().gs_timer_read(timer, nm.encode(), ctypes.byref(tot), ctypes.byref(cnt)))
+        if cnt.value:
+            out[nm] = {"ms_total": tot.value, "launches": cnt.value, "ms_avg": tot.value / cnt.value}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -139,8 +160,8 @@ def main():
     import torch
     from paper_2411_19588_amd import _native as N
     from paper_2411_19588_amd import rasterizer as R
-    from paper_2411_19588_amd import optim as OPT
     from paper_2411_19588_amd import synth
+    from paper_2411_19588_amd.trainer import TrainStep
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -152,100 +173,82 @@ def main():
     cam = sc.cameras[0]
     P = cam.width * cam.height
     ncoef = (sc.sh_degree + 1) ** 2
-    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-    target = t(sc.targets[0].reshape(-1))
-
-    groups = [OPT.Group("means", t(sc.means), OPT.LR["means"]),
-              OPT.Group("log_scales", t(sc.log_scales), OPT.LR["scales"], "exp"),
-              OPT.Group("quats", t(sc.quats), OPT.LR["quats"]),
-              OPT.Group("logits", t(sc.logits), OPT.LR["opacity"], "sigmoid"),
-              OPT.Group("sh", t(sc.sh), OPT.LR["sh"]),
-              OPT.Group("medium", t(sc.medium), OPT.LR["medium"])]
-    opt = OPT.FusedAdam(groups)
-    G = {g.name: g for g in groups}
-    # parameter activation (exp scales, sigmoid opacity) into the activated buffers
-    N.check("gs_activate", N.lib().gs_activate(sc.n, ctypes.c_void_p(G["log_scales"].param.data_ptr()),
-                                               ctypes.c_void_p(G["logits"].param.data_ptr()),
-                                               ctypes.c_void_p(G["log_scales"].activated.data_ptr()),
-                                               ctypes.c_void_p(G["logits"].activated.data_ptr()),
-                                               ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
-    cfg = R.RasterConfig(tile=args.tile, lds_batch=args.lds_batch, persistent=args.persistent)
-    rast = R.Rasterizer(sc.cameras, cfg, device=dev)
-    means, quats, sh, med = G["means"].param, G["quats"].param, G["sh"].param, G["medium"].param
-    scales, opac = G["log_scales"].activated, G["logits"].activated
-    grad_out = [G["means"].grad, G["log_scales"].grad, G["quats"].grad, G["logits"].grad, G["sh"].grad,
-                G["medium"].grad]
-    loss = torch.empty(1, dtype=torch.float32, device=dev)
-    grad_rgb = torch.empty(3 * P, dtype=torch.float32, device=dev)
-    sptr = lambda: ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-
-    # capacity: one checked forward sizes the pair list, with headroom for parameter drift
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a))
+    cfg = R.RasterConfig(tile=args.tile, lds_batch=args.lds_batch, persistent=args.persistent, phases=args.phases)
+    ts = TrainStep(t(sc.means), t(sc.log_scales), t(sc.quats), t(sc.logits), t(sc.sh), t(sc.medium), sc.sh_degree,
+                   sc.cameras, t(sc.targets[0]), cfg, device=dev)
     log("sizing the pair list")
-    _, _, _, ctx = rast.forward(means, scales, quats, opac, sh, sc.sh_degree, med)
-    _, K0 = rast.read_status(ctx.saved)
-    rast.max_pairs = min(N.GS_MAX_PAIRS, int(K0 * 1.2) + 4096)
-    del ctx
-    log(f"pairs K = {K0} (K/N = {K0 / sc.n:.1f}), capacity {rast.max_pairs}")
+    need = ts.size_capacity(1.25)
+    log(f"stored pairs {need}, capacity {ts.max_pairs}")
+    stream = torch.cuda.Stream(device=dev)          # default priority
+    torch.cuda.synchronize()
 
-    def step():
-        rgb, depth, alpha, fctx = rast.forward(means, scales, quats, opac, sh, sc.sh_degree, med, check=False)
-        N.check("gs_l1_loss", N.lib().gs_l1_loss(3 * P, ctypes.c_void_p(rgb.data_ptr()),
-                                                 ctypes.c_void_p(target.data_ptr()), ctypes.c_void_p(loss.data_ptr()),
-                                                 ctypes.c_void_p(grad_rgb.data_ptr()), sptr()))
-        rast.backward(fctx, means, scales, quats, opac, sh, med, grad_rgb, out=grad_out)
-        opt.step()
-        return fctx
+    # ---- eager steps, with HIP events around every kernel
+    with torch.cuda.stream(stream):
+        log(f"eager warmup {args.warmup}")
+        for _ in range(args.warmup):
+            ts.enqueue(stream)
+        torch.cuda.synchronize()
+        timer = None
+        if not args.no_timer:
+            timer = N.lib().gs_timer_create(80 * (args.steps + 1))
+            ts.timer = timer
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ts.enqueue(stream)
+        torch.cuda.synchronize()
+        eager_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        ts.timer = None
+        kernels = read_timer(N, timer) if timer is not None else {}
+        if timer is not None:
+            N.lib().gs_timer_destroy(timer)
+        log(f"eager: {eager_ms:.3f} ms/step")
 
-    log(f"warmup {args.warmup}")
-    for _ in range(args.warmup):
-        fctx = step()
-    torch.cuda.synchronize()
-    timer = None
-    if not args.no_timer:
-        timer = N.lib().gs_timer_create(40 * (args.steps + 1))
-        rast.timer = timer
-    log(f"timing {args.steps} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        fctx = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    rast.timer = None
-    ms = (t1 - t0) * 1e3 / args.steps
-    st, K = rast.read_status(fctx.saved)
+        # ---- the same step captured once into a HIP graph and replayed
+        ms = eager_ms
+        if not args.eager:
+            ts.capture(stream)
+            for _ in range(args.warmup):
+                ts.replay(stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                ts.replay(stream)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            log(f"graph: {ms:.3f} ms/step")
+    st, K = ts.status(stream)
     if st & N.GS_STATUS_PAIR_OVERFLOW:
-        raise SystemExit(f"pair capacity overflowed during the timed steps ({K} > {rast.max_pairs})")
-    log(f"{ms:.3f} ms/step, loss {loss.item():.5f}, K {K}")
+        raise SystemExit(f"pair capacity overflowed during the timed steps ({K} > {ts.max_pairs})")
+    stats = (ctypes.c_int64 * 4)()
+    N.check("gs_forward_stats", N.lib().gs_forward_stats(ctypes.byref(ts.opts), ts.n, 1, ts.rast.host_cams,
+                                                         ctypes.c_void_p(ts.saved.data_ptr()), ts.saved.numel(),
+                                                         stats, ctypes.c_void_p(stream.cuda_stream)))
+    # full (single-phase) binning pair count of the same scene, for K/N
+    full = R.Rasterizer(sc.cameras, R.RasterConfig(phases=1, max_pairs=int(K * 8)), device=dev)
+    g = ts.G
+    _, _, _, fctx = full.forward(g["means"].param, g["log_scales"].activated, g["quats"].param,
+                                 g["logits"].activated, g["sh"].param, sc.sh_degree, g["medium"].param)
+    _, K_full = full.read_status(fctx.saved)
+    del fctx, full
+    log(f"loss {ts.loss.item():.5f}; stored pairs {K}, full-binning pairs {K_full} (K/N {K_full / sc.n:.1f}), "
+        f"E/pixel {stats[1] / P:.1f}")
 
-    kernels = {}
-    if timer is not None:
-        names = ["project_fwd", "depth_sort_hist", "depth_sort_scan", "depth_sort_scatter", "count_scan", "emit",
-                 "tile_sort_hist", "tile_sort_scan", "tile_sort_scatter", "ranges", "composite_fwd", "zero_grad2d",
-                 "composite_bwd", "medium_reduce", "project_bwd"]
-        for nm in names:
-            tot = ctypes.c_double()
-            cnt = ctypes.c_int32()
-            N.check("gs_timer_read", N.lib().gs_timer_read(timer, nm.encode(), ctypes.byref(tot), ctypes.byref(cnt)))
-            if cnt.value:
-                kernels[nm] = {"ms_total": tot.value, "launches": cnt.value, "ms_avg": tot.value / cnt.value}
-        N.lib().gs_timer_destroy(timer)
-    tiles = rast.tile_count()
+    tiles = ts.rast.tile_count()
     roof = None
     if kernels:
-        dom = max(kernels, key=lambda k: kernels[k]["ms_total"] / args.steps)
+        dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
         for nm, kv in kernels.items():
-            b = kernel_bytes(nm, sc.n, 1, K, P, tiles, ncoef)
+            b = kernel_bytes(nm, sc.n, 1, K, P, tiles, ncoef, kv["launches"] // args.steps)
             if b is not None:
                 kv["alg_bytes"] = b
                 kv["gbs"] = b / (kv["ms_avg"] * 1e-3) / 1e9
         kd = kernels[dom]
         achieved = kd.get("gbs")
-        traffic = traffic_for(dom)
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                "traffic": traffic, "alg_bytes_per_launch": kd.get("alg_bytes"),
+                "traffic": traffic_for(dom), "alg_bytes_per_launch": kd.get("alg_bytes"),
                 "avg_launch_ms": round(kd["ms_avg"], 4)}
         log("per-kernel ms/step: " + ", ".join(f"{k} {v['ms_total'] / args.steps:.3f}" for k, v in kernels.items()))
 
@@ -272,7 +275,10 @@ def main():
                                "training step (forward + L1 + backward + fused Adam)",
                    "n_gaussians": sc.n, "sh_degree": sc.sh_degree, "width": cam.width, "height": cam.height,
                    "views": 1, "tile": args.tile, "lds_batch": args.lds_batch, "persistent": bool(args.persistent),
-                   "pairs": int(K), "pairs_per_gaussian": round(K / sc.n, 2)},
+                   "phases": cfg.phases, "mode": "eager" if args.eager else "hip_graph",
+                   "pairs_stored": int(K), "pairs_full_binning": int(K_full),
+                   "pairs_per_gaussian": round(K_full / sc.n, 2), "evals_per_pixel": round(stats[1] / P, 1)},
+        "eager_ms_per_step": round(eager_ms, 4),
         "roofline": roof,
         "cpu_baseline": cpu,
         "kernels_ms_per_step": {k: round(v["ms_total"] / args.steps, 4) for k, v in kernels.items()},

@@ -240,6 +240,23 @@ typedef struct gs_adam_group {
 int gs_adam_step(const gs_adam_group* host_groups, int32_t n_groups, float beta1, float beta2, float eps,
                  int32_t step, gs_stream_t stream);
 
+/* As gs_adam_step, for replay from a captured graph: the step number lives in
+ * device memory.  *step_counter (DEVICE int32) is incremented first and the
+ * incremented value is the step used for bias correction (start it at 0). */
+int gs_adam_step_device(const gs_adam_group* host_groups, int32_t n_groups, float beta1, float beta2, float eps,
+                        int32_t* step_counter, gs_stream_t stream);
+
+/* HIP graph capture of any sequence of the enqueue-only calls above (for
+ * callers that replay a fixed pipeline, e.g. a training step over fixed views).
+ * gs_graph_begin starts capturing `stream` (which must not be the default
+ * stream); gs_graph_end stops it and instantiates the graph into *graph;
+ * gs_graph_launch replays it on `stream`; gs_graph_destroy frees it.  Buffers
+ * referenced by the captured calls must stay allocated while the graph lives. */
+int gs_graph_begin(gs_stream_t stream);
+int gs_graph_end(gs_stream_t stream, void** graph);
+int gs_graph_launch(void* graph, gs_stream_t stream);
+int gs_graph_destroy(void* graph);
+
 /* Optional per-kernel timing with HIP events (used by benchmarks).  A timer
  * records a start/stop event pair around each kernel it sees in opts.timer.
  * gs_timer_read synchronises the recorded events and returns, for the kernel

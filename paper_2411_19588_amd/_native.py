@@ -89,6 +89,12 @@ PROTOTYPES = {
     "gs_l1_loss": (ctypes.c_int, [_I64, _P, _P, _P, _P, _P]),
     "gs_adam_step": (ctypes.c_int, [ctypes.POINTER(GsAdamGroup), _I32, ctypes.c_float, ctypes.c_float,
                                     ctypes.c_float, _I32, _P]),
+    "gs_adam_step_device": (ctypes.c_int, [ctypes.POINTER(GsAdamGroup), _I32, ctypes.c_float, ctypes.c_float,
+                                           ctypes.c_float, _P, _P]),
+    "gs_graph_begin": (ctypes.c_int, [_P]),
+    "gs_graph_end": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
+    "gs_graph_launch": (ctypes.c_int, [_P, _P]),
+    "gs_graph_destroy": (ctypes.c_int, [_P]),
     "gs_timer_create": (_P, [_I32]),
     "gs_timer_destroy": (None, [_P]),
     "gs_timer_reset": (None, [_P]),

@@ -62,7 +62,10 @@ struct AdamArgs {
     gs_adam_group g[kMaxGroups];
     int32_t count;
     float b1, b2, eps, bc1, bc2;
+    const int32_t* step_dev;   // if set, bias corrections come from this device step number
 };
+
+__global__ void k_step_inc(int32_t* step) { *step += 1; }
 
 __device__ __forceinline__ float adam_one(const AdamArgs& a, const gs_adam_group& G, float p, float g, float act,
                                           float& m, float& v, float& new_act) {
@@ -79,6 +82,11 @@ __device__ __forceinline__ float adam_one(const AdamArgs& a, const gs_adam_group
 // blockIdx.y selects the group; each thread updates 4 consecutive scalars with 16-byte
 // loads and stores when the group's arrays allow it.
 __global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a) {
+    if (a.step_dev) {
+        const float t = (float)*a.step_dev;
+        a.bc1 = 1.0f - powf(a.b1, t);
+        a.bc2 = 1.0f - powf(a.b2, t);
+    }
     const gs_adam_group G = a.g[blockIdx.y];
     const int64_t n = G.count;
     const int64_t stride = (int64_t)gridDim.x * kBlock * 4;
@@ -160,9 +168,10 @@ int gs_l1_loss(int64_t count, const float* pred, const float* target, float* los
     return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }
 
-int gs_adam_step(const gs_adam_group* host_groups, int32_t n_groups, float beta1, float beta2, float eps,
-                 int32_t step, gs_stream_t stream) {
-    if (!host_groups || n_groups < 1 || n_groups > kMaxGroups || step < 1) return GS_ERR_INVALID_ARGUMENT;
+static int adam_launch(const gs_adam_group* host_groups, int32_t n_groups, float beta1, float beta2, float eps,
+                       int32_t step, int32_t* step_dev, gs_stream_t stream) {
+    if (!host_groups || n_groups < 1 || n_groups > kMaxGroups || (!step_dev && step < 1))
+        return GS_ERR_INVALID_ARGUMENT;
     if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f))
         return GS_ERR_INVALID_ARGUMENT;
     AdamArgs a;
@@ -180,14 +189,61 @@ int gs_adam_step(const gs_adam_group* host_groups, int32_t n_groups, float beta1
     a.b1 = beta1;
     a.b2 = beta2;
     a.eps = eps;
-    a.bc1 = (float)(1.0 - __builtin_pow((double)beta1, (double)step));
-    a.bc2 = (float)(1.0 - __builtin_pow((double)beta2, (double)step));
-    if (largest == 0) return GS_OK;
-    int64_t gx = (largest + 4 * kBlock - 1) / (4 * kBlock);
-    if (gx > 2048) gx = 2048;
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)gx, (unsigned)n_groups), dim3(kBlock), 0,
-                       static_cast<hipStream_t>(stream), a);
+    a.step_dev = step_dev;
+    if (!step_dev) {
+        a.bc1 = (float)(1.0 - __builtin_pow((double)beta1, (double)step));
+        a.bc2 = (float)(1.0 - __builtin_pow((double)beta2, (double)step));
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (step_dev) hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(1), 0, s, step_dev);
+    if (largest > 0) {
+        int64_t gx = (largest + 4 * kBlock - 1) / (4 * kBlock);
+        if (gx > 2048) gx = 2048;
+        hipLaunchKernelGGL(k_adam, dim3((unsigned)gx, (unsigned)n_groups), dim3(kBlock), 0, s, a);
+    }
     return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+int gs_adam_step(const gs_adam_group* host_groups, int32_t n_groups, float beta1, float beta2, float eps,
+                 int32_t step, gs_stream_t stream) {
+    return adam_launch(host_groups, n_groups, beta1, beta2, eps, step, nullptr, stream);
+}
+
+int gs_adam_step_device(const gs_adam_group* host_groups, int32_t n_groups, float beta1, float beta2, float eps,
+                        int32_t* step_counter, gs_stream_t stream) {
+    if (!step_counter) return GS_ERR_INVALID_ARGUMENT;
+    return adam_launch(host_groups, n_groups, beta1, beta2, eps, 0, step_counter, stream);
+}
+
+int gs_graph_begin(gs_stream_t stream) {
+    if (!stream) return GS_ERR_INVALID_ARGUMENT;
+    return hipStreamBeginCapture(static_cast<hipStream_t>(stream), hipStreamCaptureModeThreadLocal) == hipSuccess
+               ? GS_OK
+               : GS_ERR_HIP;
+}
+
+int gs_graph_end(gs_stream_t stream, void** graph) {
+    if (!stream || !graph) return GS_ERR_INVALID_ARGUMENT;
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(static_cast<hipStream_t>(stream), &g) != hipSuccess || !g) return GS_ERR_HIP;
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return GS_ERR_HIP;
+    *graph = exec;
+    return GS_OK;
+}
+
+int gs_graph_launch(void* graph, gs_stream_t stream) {
+    if (!graph) return GS_ERR_INVALID_ARGUMENT;
+    return hipGraphLaunch(static_cast<hipGraphExec_t>(graph), static_cast<hipStream_t>(stream)) == hipSuccess
+               ? GS_OK
+               : GS_ERR_HIP;
+}
+
+int gs_graph_destroy(void* graph) {
+    if (!graph) return GS_ERR_INVALID_ARGUMENT;
+    return hipGraphExecDestroy(static_cast<hipGraphExec_t>(graph)) == hipSuccess ? GS_OK : GS_ERR_HIP;
 }
 
 }  // extern "C"

@@ -1,0 +1,155 @@
+"""A full training step over fixed views with every buffer allocated once.
+
+forward (projection, depth-progressive binning, compositing with the medium)
+-> L1 loss and its gradient -> adjoint -> fused Adam with the activation
+epilogue (Sec. Optimization), all enqueued on one stream through the C ABI with
+fixed pointers, so the whole step can be captured into a HIP graph and
+replayed.  Raw parameters: means, log-scales, quaternions, opacity logits, SH
+and the per-view medium coefficients.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import torch
+
+from . import _native as N
+from . import optim as OPT
+from .rasterizer import RasterConfig, Rasterizer
+
+
+def _vp(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class TrainStep:
+    def __init__(self, means, log_scales, quats, logits, sh, medium, sh_degree: int, cameras: Sequence,
+                 targets: torch.Tensor, config: RasterConfig = RasterConfig(), max_pairs: Optional[int] = None,
+                 lr: Optional[dict] = None, device="cuda"):
+        dev = torch.device(device)
+        lr = dict(OPT.LR, **(lr or {}))
+        f32 = lambda t: t.to(dev, torch.float32).contiguous()
+        self.groups = [OPT.Group("means", f32(means), lr["means"]),
+                       OPT.Group("log_scales", f32(log_scales), lr["scales"], "exp"),
+                       OPT.Group("quats", f32(quats), lr["quats"]),
+                       OPT.Group("logits", f32(logits), lr["opacity"], "sigmoid"),
+                       OPT.Group("sh", f32(sh), lr["sh"]),
+                       OPT.Group("medium", f32(medium), lr["medium"])]
+        self.G = {g.name: g for g in self.groups}
+        self.n = int(self.G["means"].param.shape[-1])
+        self.sh_degree = int(sh_degree)
+        self.rast = Rasterizer(cameras, config, device=dev)
+        self.device = dev
+        P = self.rast.total_pixels
+        self.target = f32(targets).reshape(-1)
+        if self.target.numel() != 3 * P:
+            raise ValueError("targets must hold 3 * total pixels values (CHW per view, views packed)")
+        self.rgb = torch.empty(3 * P, dtype=torch.float32, device=dev)
+        self.depth = torch.empty(P, dtype=torch.float32, device=dev)
+        self.alpha = torch.empty(P, dtype=torch.float32, device=dev)
+        self.grad_rgb = torch.empty(3 * P, dtype=torch.float32, device=dev)
+        self.loss = torch.empty(1, dtype=torch.float32, device=dev)
+        self.step_counter = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.graph = None
+        self.timer = None
+        # A0: activated scales and opacities for the first forward
+        s = torch.cuda.current_stream(dev)
+        N.check("gs_activate", N.lib().gs_activate(self.n, _vp(self.G["log_scales"].param),
+                                                   _vp(self.G["logits"].param), _vp(self.G["log_scales"].activated),
+                                                   _vp(self.G["logits"].activated), ctypes.c_void_p(s.cuda_stream)))
+        self._gauss = N.GsGaussians(self.n, self.sh_degree, 0, _vp(self.G["means"].param),
+                                    _vp(self.G["log_scales"].activated), _vp(self.G["quats"].param),
+                                    _vp(self.G["logits"].activated), _vp(self.G["sh"].param))
+        self._grads = N.GsGaussianGrads(_vp(self.G["means"].grad), _vp(self.G["log_scales"].grad),
+                                        _vp(self.G["quats"].grad), _vp(self.G["logits"].grad),
+                                        _vp(self.G["sh"].grad))
+        self._adam = (N.GsAdamGroup * len(self.groups))()
+        for i, g in enumerate(self.groups):
+            self._adam[i] = N.GsAdamGroup(g.param.data_ptr(), g.grad.data_ptr(), g.m.data_ptr(), g.v.data_ptr(),
+                                          g.activated.data_ptr() if g.activated is not None else None,
+                                          g.param.numel(), g.lr, OPT._ACT[g.activation], 0)
+        self.set_capacity(max_pairs if max_pairs is not None else config.max_pairs)
+
+    # ------------------------------------------------------------------ buffers
+    def set_capacity(self, max_pairs: int) -> None:
+        """(Re)allocate the workspace and forward context for `max_pairs` stored pairs (drops any graph)."""
+        self.destroy_graph()
+        self.max_pairs = int(max_pairs)
+        self.opts = self.rast.config.to_c(self.max_pairs)
+        ws, sv = self.rast.sizes_for(self.n, self.max_pairs)
+        self.ws = torch.empty(max(ws, 256), dtype=torch.uint8, device=self.device)
+        self.saved = torch.empty(max(sv, 256), dtype=torch.uint8, device=self.device)
+
+    def size_capacity(self, headroom: float = 1.25) -> int:
+        """Run one eager forward (growing the capacity until it fits) and leave `headroom` over its need."""
+        s = torch.cuda.current_stream(self.device)
+        while True:
+            self._forward(s)
+            st, need = self.rast.read_status(self.saved, s)
+            if st & N.GS_STATUS_PAIR_OVERFLOW:
+                self.set_capacity(min(N.GS_MAX_PAIRS, int(need * headroom) + 4096))
+                continue
+            break
+        want = min(N.GS_MAX_PAIRS, int(need * headroom) + 4096)
+        if want > self.max_pairs:
+            self.set_capacity(want)
+        return need
+
+    # ------------------------------------------------------------------ step
+    def _forward(self, stream) -> None:
+        sp = ctypes.c_void_p(stream.cuda_stream)
+        self.opts.timer = self.timer
+        N.check("gs_render_forward", N.lib().gs_render_forward(
+            ctypes.byref(self.opts), ctypes.byref(self._gauss), self.rast.n_views, self.rast.host_cams,
+            _vp(self.rast.dev_cams), _vp(self.G["medium"].param), _vp(self.rgb), _vp(self.depth), _vp(self.alpha),
+            _vp(self.saved), self.saved.numel(), _vp(self.ws), self.ws.numel(), sp))
+
+    def enqueue(self, stream=None) -> None:
+        """Enqueue one training step on `stream` (no host synchronisation)."""
+        stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        sp = ctypes.c_void_p(stream.cuda_stream)
+        L = N.lib()
+        self._forward(stream)
+        N.check("gs_l1_loss", L.gs_l1_loss(self.rgb.numel(), _vp(self.rgb), _vp(self.target), _vp(self.loss),
+                                           _vp(self.grad_rgb), sp))
+        N.check("gs_render_backward", L.gs_render_backward(
+            ctypes.byref(self.opts), ctypes.byref(self._gauss), self.rast.n_views, self.rast.host_cams,
+            _vp(self.rast.dev_cams), _vp(self.G["medium"].param), _vp(self.grad_rgb), None, _vp(self.saved),
+            self.saved.numel(), ctypes.byref(self._grads), _vp(self.G["medium"].grad), _vp(self.ws),
+            self.ws.numel(), sp))
+        N.check("gs_adam_step_device", L.gs_adam_step_device(self._adam, len(self.groups), 0.9, 0.999, 1e-8,
+                                                             _vp(self.step_counter), sp))
+
+    # ------------------------------------------------------------------ graph
+    def capture(self, stream: torch.cuda.Stream) -> None:
+        """Capture one step into a HIP graph on `stream` (a non-default stream)."""
+        self.destroy_graph()
+        if self.timer is not None:
+            raise RuntimeError("disable the timer while capturing")
+        sp = ctypes.c_void_p(stream.cuda_stream)
+        g = ctypes.c_void_p()
+        N.check("gs_graph_begin", N.lib().gs_graph_begin(sp))
+        try:
+            self.enqueue(stream)
+        finally:
+            rc = N.lib().gs_graph_end(sp, ctypes.byref(g))
+        N.check("gs_graph_end", rc)
+        self.graph = g
+
+    def replay(self, stream: torch.cuda.Stream) -> None:
+        N.check("gs_graph_launch", N.lib().gs_graph_launch(self.graph, ctypes.c_void_p(stream.cuda_stream)))
+
+    def destroy_graph(self) -> None:
+        if getattr(self, "graph", None) is not None:
+            N.lib().gs_graph_destroy(self.graph)
+            self.graph = None
+
+    def status(self, stream=None):
+        return self.rast.read_status(self.saved, stream)
+
+    def __del__(self):
+        try:
+            self.destroy_graph()
+        except Exception:
+            pass
