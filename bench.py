@@ -39,6 +39,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 VALU peak without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# Algorithmic FP32 flops of one (pixel, Gaussian) evaluation (FMA = 2): every walked entry
+# computes alpha (dx, dy, the quadratic form, exp, opacity, clamp); a blended one also
+# updates T and the colour / depth / weight sums (forward) or the adjoint terms (backward).
+FLOPS_ALPHA = 12
+FLOPS_BLEND_FWD = 12
+FLOPS_BLEND_BWD = 49
 
 
 def log(msg: str) -> None:
@@ -54,11 +62,21 @@ def parse():
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--lds-batch", type=int, default=256)
     ap.add_argument("--persistent", action="store_true")
+    ap.add_argument("--no-tile-cull", action="store_true", help="bin every tile of each rectangle")
+    ap.add_argument("--ppl", type=int, default=0, help="pixels per lane in compositing (0 = library default)")
+    ap.add_argument("--fetch", choices=["default", "lds", "scalar"], default="default",
+                    help="how compositing waves receive the records")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=2, help="oracle sample: every k-th pixel in x and y")
     ap.add_argument("--no-timer", action="store_true", help="skip the per-kernel HIP event timer")
     ap.add_argument("--phases", type=int, default=3, help="depth-progressive binning phases (1 = full binning)")
     ap.add_argument("--eager", action="store_true", help="time eager launches only (no HIP graph replay)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 24-view batched-vs-per-view forward+backward comparison")
+    ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (read MIB, write MIB) three times, to "
+                         "calibrate the HBM byte counters of a profiler, and exit")
     return ap.parse_args()
 
 
@@ -90,6 +108,15 @@ def kernel_bytes(name: str, n: int, views: int, K: int, P: int, tiles: int, ncoe
         "medium_reduce": tiles * 36,
     }
     return table.get(name)
+
+
+def kernel_flops(name: str, E: int, Cb: int):
+    """Algorithmic flops per step of the compositing kernels: E walked evaluations, Cb blended."""
+    if name == "composite_fwd":
+        return FLOPS_ALPHA * E + FLOPS_BLEND_FWD * Cb
+    if name == "composite_bwd":
+        return FLOPS_ALPHA * E + FLOPS_BLEND_BWD * Cb
+    return None
 
 
 def source_hash(path: str) -> str:
@@ -133,6 +160,91 @@ def cpu_baseline(scene, target, stride: int):
                       f"{dt:.1f} s"}
 
 
+def batched_compare(args, dev):
+    """24 views of uneven resolution (1M Gaussians, SH 3): forward + L1 + backward of all views
+    in one pipeline (persistent tile queue, launch shape from the autotuner, one HIP graph)
+    against one pipeline per view (24 forward + backward sequences in one HIP graph, same
+    shape).  The per-view side leaves the gradients per view (the batched side sums them over
+    the views in its projection adjoint), so it is timed doing less work than the batched one."""
+    import torch
+    from paper_2411_19588_amd import _native as N
+    from paper_2411_19588_amd import autotune as A
+    from paper_2411_19588_amd import rasterizer as R
+    from paper_2411_19588_amd import synth
+    from paper_2411_19588_amd.trainer import RenderStep
+
+    sc = synth.make_scene(3)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    params = dict(means=t(sc.means), scales=t(sc.scales), quats=t(sc.quats), opacity=t(sc.opacity), sh=t(sc.sh))
+    med = t(sc.medium)
+    tgts = [t(x).reshape(-1) for x in sc.targets]
+    tgt_all = torch.cat(tgts)
+    sizes = [(c.width, c.height) for c in sc.cameras]
+    P = sum(w * h for w, h in sizes)
+    log(f"batched: {len(sizes)} views, {P} pixels; autotuning the launch shape")
+    measure = A.render_step_timer(params, sc.sh_degree, sc.cameras, med, tgt_all, reps=3, device=dev)
+    t0 = time.perf_counter()
+    cfg = A.tune(measure, R.RasterConfig(), A.candidates(), log=log)
+    tune_s = time.perf_counter() - t0
+    shape = {k: getattr(cfg, k) for k in A.SHAPE_FIELDS}
+    log(f"autotuned shape {shape} ({tune_s:.1f} s)")
+    stream = torch.cuda.Stream(device=dev)
+    K = args.batched_steps
+
+    def time_graph(enqueue_all, warm):
+        with torch.cuda.stream(stream):
+            sp = ctypes.c_void_p(stream.cuda_stream)
+            g = ctypes.c_void_p()
+            N.check("gs_graph_begin", N.lib().gs_graph_begin(sp))
+            try:
+                enqueue_all(stream)
+            finally:
+                rc = N.lib().gs_graph_end(sp, ctypes.byref(g))
+            N.check("gs_graph_end", rc)
+            for _ in range(warm):
+                N.lib().gs_graph_launch(g, sp)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(K):
+                N.check("gs_graph_launch", N.lib().gs_graph_launch(g, sp))
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t1) * 1e3 / K
+            N.lib().gs_graph_destroy(g)
+        return ms
+
+    bs = RenderStep(params, sc.sh_degree, sc.cameras, med, tgt_all, cfg, device=dev)
+    with torch.cuda.stream(stream):
+        bs.size_capacity(1.25)
+    batched_ms = time_graph(lambda s_: bs.enqueue(s_), 2)
+    st, _ = bs.status(stream)
+    del bs
+    log(f"batched: {batched_ms:.3f} ms per forward+backward of {len(sizes)} views")
+    per = []
+    for v, cam in enumerate(sc.cameras):
+        rs = RenderStep(params, sc.sh_degree, [cam], med[v:v + 1], tgts[v], cfg, device=dev)
+        with torch.cuda.stream(stream):
+            rs.size_capacity(1.25)
+        per.append(rs)
+
+    def all_views(s_):
+        for rs in per:
+            rs.enqueue(s_)
+
+    per_ms = time_graph(all_views, 2)
+    st_pv = max(rs.status(stream)[0] for rs in per)
+    del per
+    torch.cuda.empty_cache()
+    log(f"per-view: {per_ms:.3f} ms; speedup {per_ms / batched_ms:.2f}x")
+    if st or st_pv:
+        raise SystemExit(f"batched comparison reported status {st} / {st_pv}")
+    return {"workload": f"{sc.n} Gaussians SH{sc.sh_degree}, {len(sizes)} views of uneven resolution "
+                        f"({P} pixels), forward + L1 + backward",
+            "views": len(sizes), "pixels": P, "batched_ms": round(batched_ms, 3), "per_view_ms": round(per_ms, 3),
+            "speedup": round(per_ms / batched_ms, 3), "batched_mpix_s": round(P / (batched_ms * 1e-3) / 1e6, 1),
+            "per_view_mpix_s": round(P / (per_ms * 1e-3) / 1e6, 1), "shape": shape,
+            "autotune_s": round(tune_s, 1)}
+
+
 KERNELS = ["project_fwd", "depth_sort_hist", "depth_sort_scan", "depth_sort_scatter", "phase_count", "count_scan",
            "emit", "tile_sort_hist", "tile_sort_scan", "tile_sort_scatter", "commit", "composite_fwd", "zero_grad2d",
            "composite_bwd", "medium_reduce", "project_bwd"]
@@ -166,6 +278,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        x = torch.rand(n, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 1.0, out=y)     # one elementwise kernel: reads n*4 bytes, writes n*4 bytes
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 3}))
+        return
     log(f"building scene (config {args.config})")
     sc = synth.make_scene(args.config)
     if sc.n_views != 1:
@@ -174,7 +295,8 @@ def main():
     P = cam.width * cam.height
     ncoef = (sc.sh_degree + 1) ** 2
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a))
-    cfg = R.RasterConfig(tile=args.tile, lds_batch=args.lds_batch, persistent=args.persistent, phases=args.phases)
+    cfg = R.RasterConfig(tile=args.tile, lds_batch=args.lds_batch, persistent=args.persistent, phases=args.phases,
+                         pixels_per_lane=args.ppl, record_fetch=args.fetch, tile_cull=not args.no_tile_cull)
     ts = TrainStep(t(sc.means), t(sc.log_scales), t(sc.quats), t(sc.logits), t(sc.sh), t(sc.medium), sc.sh_degree,
                    sc.cameras, t(sc.targets[0]), cfg, device=dev)
     log("sizing the pair list")
@@ -220,37 +342,52 @@ def main():
     st, K = ts.status(stream)
     if st & N.GS_STATUS_PAIR_OVERFLOW:
         raise SystemExit(f"pair capacity overflowed during the timed steps ({K} > {ts.max_pairs})")
-    stats = (ctypes.c_int64 * 4)()
+    stats = (ctypes.c_int64 * 5)()
     N.check("gs_forward_stats", N.lib().gs_forward_stats(ctypes.byref(ts.opts), ts.n, 1, ts.rast.host_cams,
                                                          ctypes.c_void_p(ts.saved.data_ptr()), ts.saved.numel(),
                                                          stats, ctypes.c_void_p(stream.cuda_stream)))
     # full (single-phase) binning pair count of the same scene, for K/N
-    full = R.Rasterizer(sc.cameras, R.RasterConfig(phases=1, max_pairs=int(K * 8)), device=dev)
+    # (the method's rectangle binning, no culling)
+    full = R.Rasterizer(sc.cameras, R.RasterConfig(phases=1, tile_cull=False, max_pairs=int(K * 8)), device=dev)
     g = ts.G
     _, _, _, fctx = full.forward(g["means"].param, g["log_scales"].activated, g["quats"].param,
                                  g["logits"].activated, g["sh"].param, sc.sh_degree, g["medium"].param)
     _, K_full = full.read_status(fctx.saved)
     del fctx, full
     log(f"loss {ts.loss.item():.5f}; stored pairs {K}, full-binning pairs {K_full} (K/N {K_full / sc.n:.1f}), "
-        f"E/pixel {stats[1] / P:.1f}")
+        f"E/pixel {stats[1] / P:.1f}, blended/pixel {stats[4] / P:.1f}, live pairs {stats[0]}")
 
     tiles = ts.rast.tile_count()
+    E, Cb, K_live = int(stats[1]), int(stats[4]), int(stats[0])
     roof = None
     if kernels:
         dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
         for nm, kv in kernels.items():
-            b = kernel_bytes(nm, sc.n, 1, K, P, tiles, ncoef, kv["launches"] // args.steps)
+            per_step = kv["launches"] // args.steps
+            f = kernel_flops(nm, E, Cb)
+            if f is not None:
+                kv["alg_flops"] = f / max(1, per_step)
+                kv["tflops"] = f / (kv["ms_total"] / args.steps * 1e-3) / 1e12
+                continue
+            b = kernel_bytes(nm, sc.n, 1, K_live, P, tiles, ncoef, per_step)
             if b is not None:
                 kv["alg_bytes"] = b
                 kv["gbs"] = b / (kv["ms_avg"] * 1e-3) / 1e9
         kd = kernels[dom]
-        achieved = kd.get("gbs")
-        roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                "traffic": traffic_for(dom), "alg_bytes_per_launch": kd.get("alg_bytes"),
-                "avg_launch_ms": round(kd["ms_avg"], 4)}
+        if "tflops" in kd:
+            roof = {"kernel": dom, "bound": "alu", "achieved": round(kd["tflops"], 2), "peak": VALU_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(kd["tflops"] / VALU_PEAK_TFLOPS, 4),
+                    "traffic": traffic_for(dom), "alg_flops_per_launch": kd["alg_flops"],
+                    "avg_launch_ms": round(kd["ms_avg"], 4)}
+        else:
+            achieved = kd.get("gbs")
+            roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                    "traffic": traffic_for(dom), "alg_bytes_per_launch": kd.get("alg_bytes"),
+                    "avg_launch_ms": round(kd["ms_avg"], 4)}
         log("per-kernel ms/step: " + ", ".join(f"{k} {v['ms_total'] / args.steps:.3f}" for k, v in kernels.items()))
+        log("compositing TFLOP/s: " + ", ".join(f"{k} {v['tflops']:.2f}" for k, v in kernels.items() if "tflops" in v))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -258,8 +395,14 @@ def main():
         cpu = cpu_baseline(sc, sc.targets[0], args.cpu_stride)
         log(f"oracle {cpu['value'] * 1e6:.0f} pix/s on {cpu['cores']} threads")
 
+    batched = None
+    if not args.no_batched:
+        del ts
+        torch.cuda.empty_cache()
+        batched = batched_compare(args, dev)
+
     rec = {
-        "metric": "fwd+bwd Mpix/s at 1M Gaussians 1080p",
+        "metric": "fwd+bwd Mpix/s at 1M Gaussians 1080p; batched-views vs per-view speedup",
         "value": round(P / (ms * 1e-3) / 1e6, 3),
         "unit": "Mpix/s",
         "n_gpus": 1,
@@ -275,12 +418,16 @@ def main():
                                "training step (forward + L1 + backward + fused Adam)",
                    "n_gaussians": sc.n, "sh_degree": sc.sh_degree, "width": cam.width, "height": cam.height,
                    "views": 1, "tile": args.tile, "lds_batch": args.lds_batch, "persistent": bool(args.persistent),
+                   "pixels_per_lane": args.ppl, "record_fetch": args.fetch,
                    "phases": cfg.phases, "mode": "eager" if args.eager else "hip_graph",
                    "pairs_stored": int(K), "pairs_full_binning": int(K_full),
-                   "pairs_per_gaussian": round(K_full / sc.n, 2), "evals_per_pixel": round(stats[1] / P, 1)},
+                   "pairs_per_gaussian": round(K_full / sc.n, 2), "pairs_live": int(stats[0]),
+                   "evals_per_pixel": round(stats[1] / P, 1), "blends_per_pixel": round(stats[4] / P, 1),
+                   "tile_cull": bool(cfg.tile_cull)},
         "eager_ms_per_step": round(eager_ms, 4),
         "roofline": roof,
         "cpu_baseline": cpu,
+        "batched": batched,
         "kernels_ms_per_step": {k: round(v["ms_total"] / args.steps, 4) for k, v in kernels.items()},
     }
     print(json.dumps(rec), flush=True)

@@ -101,16 +101,31 @@ typedef struct gs_gaussian_grads {
 } gs_gaussian_grads;
 
 /* Rasterizer options.  gs_default_options fills the defaults noted here. */
+/* gs_options.record_fetch */
+#define GS_FETCH_DEFAULT 0
+#define GS_FETCH_LDS 1
+#define GS_FETCH_SCALAR 2
+
 typedef struct gs_options {
     int32_t tile_w, tile_h;              /* 16x16 (default) or 8x8 pixels per tile */
     int32_t lds_batch;                   /* records staged in LDS per batch: 64, 128 or 256 (<= tile pixels) */
     int32_t persistent;                  /* 0: one workgroup per tile; 1: persistent workgroups pull tiles from a queue */
+    int32_t pixels_per_lane;             /* 16x16 tiles: pixels each lane blends, 1 (four waves per tile, 8x8
+                                            each), 2 (two waves, 16x8 each) or 4 (one wave); 8x8 tiles: 1;
+                                            0 = library default.  Images are identical for every value. */
+    int32_t record_fetch;                /* GS_FETCH_LDS: the workgroup stages batches of records in LDS;
+                                            GS_FETCH_SCALAR: each wave loads records through the scalar cache
+                                            (lds_batch is then unused); GS_FETCH_DEFAULT (0) = library default */
     float alpha_min;                     /* 1/255: a Gaussian with alpha < alpha_min is skipped at that pixel */
     float alpha_max;                     /* 0.99: alpha = min(alpha_max, o exp(-q/2)) */
     float t_min;                         /* 1e-4: stop before blending a Gaussian that would leave T < t_min */
     float dilation;                      /* 0.3: added to the diagonal of the 2D covariance (EWA low-pass) */
     float kappa;                         /* 11.1: tile rectangle = bounding box of q <= kappa (> 2 ln 255) */
     int32_t depth_mode;                  /* 0: z = alpha-weighted depth; 1: z = 2/(1+exp(-0.1 z)) - 1 */
+    int32_t tile_cull;                   /* 1 (default): drop a (Gaussian, tile) pair of the rectangle when no
+                                            pixel centre of the tile can reach alpha >= alpha_min (a bound
+                                            with a rounding margin; images are identical); 0: every tile of
+                                            the rectangle, as in the method's binning */
     int32_t phases;                      /* depth-progressive binning: 1 = bin every (Gaussian, tile) pair at
                                             once; 2..4 = bin the depth-sorted Gaussians in that many rank
                                             ranges (nearest 1/32 | 1/8 | rest for 3) and, after each range,
@@ -189,14 +204,17 @@ int gs_export_keys(const gs_options* opts, int64_t n, int32_t n_views, const gs_
                    uint32_t* tile_ranges, int64_t capacity, int64_t* pair_count, gs_stream_t stream);
 
 /* Workload statistics of the last forward (synchronises `stream`):
- *   stats[0] = K, the number of (Gaussian, tile) pairs;
+ *   stats[0] = K, the number of (Gaussian, tile) pairs in the tile lists (all
+ *              phases, culled pairs excluded);
  *   stats[1] = E, the number of tile-list entries the pixels evaluated in total
  *              (each pixel walks its tile's depth-ordered list up to and including
  *              the entry that terminated it);
  *   stats[2] = the number of list entries the compositing actually reached
  *              (per tile, the furthest point any of its pixels reached);
- *   stats[3] = the number of tiles with a non-empty list.
- * `stats` is a HOST array of 4 entries. */
+ *   stats[3] = the number of tiles with a non-empty list;
+ *   stats[4] = the number of those evaluations that blended (alpha >= alpha_min).
+ * `stats` is a HOST array of 5 entries.  Re-evaluates every walked entry: a
+ * diagnostic, slower than the forward itself. */
 int gs_forward_stats(const gs_options* opts, int64_t n, int32_t n_views, const gs_camera* host_cams,
                      const void* saved, size_t saved_bytes, int64_t* stats, gs_stream_t stream);
 

@@ -21,6 +21,9 @@ GS_STATUS_NONFINITE_INPUT = 2
 GS_MAX_VIEWS = 64
 GS_MAX_PAIRS = 2_147_483_647
 GS_MAX_PHASES = 4
+GS_FETCH_DEFAULT = 0
+GS_FETCH_LDS = 1
+GS_FETCH_SCALAR = 2
 
 _ERRORS = {GS_ERR_INVALID_ARGUMENT: "invalid argument", GS_ERR_UNSUPPORTED: "unsupported",
            GS_ERR_WORKSPACE_TOO_SMALL: "workspace too small", GS_ERR_HIP: "HIP runtime error"}
@@ -51,9 +54,11 @@ class GsGaussianGrads(ctypes.Structure):
 
 class GsOptions(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("lds_batch", ctypes.c_int32),
-                ("persistent", ctypes.c_int32), ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
+                ("persistent", ctypes.c_int32), ("pixels_per_lane", ctypes.c_int32),
+                ("record_fetch", ctypes.c_int32), ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("t_min", ctypes.c_float), ("dilation", ctypes.c_float), ("kappa", ctypes.c_float),
-                ("depth_mode", ctypes.c_int32), ("phases", ctypes.c_int32), ("max_pairs", ctypes.c_int64),
+                ("depth_mode", ctypes.c_int32), ("tile_cull", ctypes.c_int32),
+                ("phases", ctypes.c_int32), ("max_pairs", ctypes.c_int64),
                 ("timer", ctypes.c_void_p)]
 
 

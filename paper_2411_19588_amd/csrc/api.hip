@@ -43,6 +43,10 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     if (!(o->dilation >= 0.0f && o->dilation < 1e30f) || !finite_pos(o->kappa)) return GS_ERR_INVALID_ARGUMENT;
     if (o->depth_mode != 0 && o->depth_mode != 1) return GS_ERR_INVALID_ARGUMENT;
     if (o->persistent != 0 && o->persistent != 1) return GS_ERR_INVALID_ARGUMENT;
+    if (o->pixels_per_lane != 0 && o->pixels_per_lane != 1 && (t8 || (o->pixels_per_lane != 2 && o->pixels_per_lane != 4)))
+        return GS_ERR_INVALID_ARGUMENT;
+    if (o->record_fetch < GS_FETCH_DEFAULT || o->record_fetch > GS_FETCH_SCALAR) return GS_ERR_INVALID_ARGUMENT;
+    if (o->tile_cull != 0 && o->tile_cull != 1) return GS_ERR_INVALID_ARGUMENT;
     if (o->phases < 0 || o->phases > GS_MAX_PHASES) return GS_ERR_INVALID_ARGUMENT;
     if (o->max_pairs < 0 || o->max_pairs > GS_MAX_PAIRS) return GS_ERR_INVALID_ARGUMENT;
     if (n * (int64_t)n_views >= (int64_t)0xFFFFFFFFLL) return GS_ERR_INVALID_ARGUMENT;
@@ -75,8 +79,8 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     if (tiles >= (1LL << 31)) return GS_ERR_INVALID_ARGUMENT;
     L->tiles = tiles;
     L->pixels = pixels;
-    int bits = 1;
-    while ((1LL << bits) < tiles) ++bits;
+    int bits = 1;   // tile ids 0..tiles-1 plus the id `tiles` of culled pairs
+    while ((1LL << bits) <= tiles) ++bits;
     L->tile_bits = bits;
     L->tile_passes = (bits + kRadixBits - 1) / kRadixBits;
     auto parts_for = [](int64_t count) {   // one radix tile per partition up to kMaxSortParts partitions
@@ -195,6 +199,9 @@ void gs_default_options(gs_options* o) {
     o->tile_h = 16;
     o->lds_batch = 256;
     o->persistent = 0;
+    o->pixels_per_lane = 0;
+    o->record_fetch = GS_FETCH_DEFAULT;
+    o->tile_cull = 1;
     o->alpha_min = 1.0f / 255.0f;
     o->alpha_max = 0.99f;
     o->t_min = 1e-4f;
@@ -281,16 +288,17 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
     float* cair = at<float>(saved, L.s_cair);
     float* dsum = at<float>(saved, L.s_dsum);
     float* wsum = at<float>(saved, L.s_wsum);
+    const CullArgs cull{rec, log2f(o.alpha_min), o.tile_w, o.tile_h, o.tile_cull};
     for (int ph = 0; ph < L.phases; ++ph) {
         timer_begin(T, "phase_count", s);
-        GS_TRY(launch_phase_count(order, counts, rects, L.nv, L.n, vt, alive, hdr, ph, pcounts, s));
+        GS_TRY(launch_phase_count(order, counts, rects, L.nv, L.n, vt, alive, hdr, ph, cull, pcounts, s));
         timer_end(T, s);
         timer_begin(T, "count_scan", s);
         GS_TRY(launch_count_scan(pcounts, L.nv, offsets, blocksums, hdr, ph, L.max_pairs, emit_start, s));
         timer_end(T, s);
         timer_begin(T, "emit", s);
         GS_TRY(launch_emit(order, offsets, emit_start, pcounts, rects, L.nv, L.n, vt, alive, hdr, ph, L.max_pairs,
-                           tiles_a, vals_a, s));
+                           cull, (uint32_t)L.tiles, tiles_a, vals_a, s));
         timer_end(T, s);
         // stable sort of the phase's pairs by tile id
         int tb = 0;
@@ -392,12 +400,13 @@ int gs_forward_stats(const gs_options* opts, int64_t n, int32_t n_views, const g
     hipStream_t s = static_cast<hipStream_t>(stream);
     // the result lands in the header's scratch words, then is copied to the host
     SavedHeader* hdr = at<SavedHeader>(const_cast<void*>(saved), L.s_header);
-    GS_TRY(launch_forward_stats(L, reinterpret_cast<const ViewInfo*>(hdr + 1), at<uint2>(saved, L.s_ranges),
-                                at<uint32_t>(saved, L.s_nlast), at<uint8_t>(saved, L.s_done), hdr, hdr->stats, s));
-    unsigned long long host[4];
+    GS_TRY(launch_forward_stats(*opts, L, reinterpret_cast<const ViewInfo*>(hdr + 1), at<uint2>(saved, L.s_ranges),
+                                at<uint32_t>(saved, L.s_vals), at<Record>(const_cast<void*>(saved), L.s_records),
+                                at<uint32_t>(saved, L.s_nlast), at<uint8_t>(saved, L.s_done), hdr->stats, s));
+    unsigned long long host[5];
     GS_TRY(hipMemcpyAsync(host, hdr->stats, sizeof(host), hipMemcpyDeviceToHost, s));
     GS_TRY(hipStreamSynchronize(s));
-    for (int i = 0; i < 4; ++i) stats[i] = (int64_t)host[i];
+    for (int i = 0; i < 5; ++i) stats[i] = (int64_t)host[i];
     return GS_OK;
 }
 

@@ -12,6 +12,14 @@
 // cut after the phase in which the tile's last pixel terminated; compositing
 // never reads past that point, so the images are identical, while scenes whose
 // near Gaussians saturate the tiles skip sorting almost every pair.
+//
+// Exact tile culling (optional).  The rectangle bounds the ellipse q <= kappa,
+// but a Gaussian of opacity o only blends where o exp(-q/2) >= alpha_min, and the
+// ellipse covers only part of its rectangle.  A pair is dropped when an upper
+// bound of the alpha exponent over the tile's pixel centres, with a margin that
+// covers the FP32 rounding of the compositing kernel's own evaluation, stays
+// below log2(alpha_min / o): the compositing kernel would have skipped that
+// Gaussian at every pixel of the tile, so the images do not change.
 #include "internal.h"
 
 namespace gs {
@@ -20,6 +28,38 @@ namespace {
 constexpr int kScanChunk = kBlock * 16;
 constexpr int kEmitItems = 4;
 constexpr int kEmitSpan = kBlock * kEmitItems;
+
+// Whether the splat `r` may reach alpha >= alpha_min at a pixel centre of tile (tx, ty): false
+// only when the maximum of the (concave) exponent A dx^2 + B dx dy + C dy^2 over the
+// rectangle spanned by the tile's pixel centres, plus a rounding margin, is below
+// log2(alpha_min) - log2(o).  The maximum is at the mean when it lies inside, else on an
+// edge, where the exponent is a 1D concave quadratic maximised at its clamped vertex.
+// Anything non-finite or degenerate keeps the pair.
+__device__ __forceinline__ bool tile_may_contribute(const float4& ra, const float2& rb, const ViewInfo& vi,
+                                                    uint32_t tx, uint32_t ty, const CullArgs& cu) {
+    const float A = ra.z, B = ra.w, C = rb.x, o = rb.y;
+    if (!(A < 0.0f && C < 0.0f)) return true;
+    const float x0 = (float)(tx * (uint32_t)cu.tile_w) + 0.5f;
+    const float x1 = (float)min((tx + 1) * (uint32_t)cu.tile_w, (uint32_t)vi.width) - 0.5f;
+    const float y0 = (float)(ty * (uint32_t)cu.tile_h) + 0.5f;
+    const float y1 = (float)min((ty + 1) * (uint32_t)cu.tile_h, (uint32_t)vi.height) - 0.5f;
+    const float xl = x0 - ra.x, xr = x1 - ra.x, yl = y0 - ra.y, yr = y1 - ra.y;
+    auto expo = [&](float dx, float dy) { return fmaf(dy, fmaf(C, dy, B * dx), (A * dx) * dx); };
+    float best;
+    if (xl <= 0.0f && xr >= 0.0f && yl <= 0.0f && yr >= 0.0f) {
+        best = 0.0f;
+    } else {
+        const float hy = -0.5f * B / C, hx = -0.5f * B / A;   // vertex of the edge quadratics, per unit offset
+        best = expo(xl, fminf(fmaxf(hy * xl, yl), yr));
+        best = fmaxf(best, expo(xr, fminf(fmaxf(hy * xr, yl), yr)));
+        best = fmaxf(best, expo(fminf(fmaxf(hx * yl, xl), xr), yl));
+        best = fmaxf(best, expo(fminf(fmaxf(hx * yr, xl), xr), yr));
+    }
+    const float X = fmaxf(-xl, xr), Y = fmaxf(-yl, yr);
+    const float mag = -A * X * X + fabsf(B) * X * Y - C * Y * Y;
+    const float limit = cu.log2_amin - log2f(o);
+    return !(best + 4e-6f * mag + 1e-4f < limit);
+}
 
 __global__ void k_view_table(ViewTable t, ViewInfo* dst, SavedHeader* hdr) {
     const int i = threadIdx.x;
@@ -70,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restri
                                                        const ViewInfo* __restrict__ vt,
                                                        const uint32_t* __restrict__ alive,
                                                        const SavedHeader* __restrict__ hdr, int phase,
-                                                       uint32_t* __restrict__ pcounts) {
+                                                       CullArgs cull, uint32_t* __restrict__ pcounts) {
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (r >= nv) return;
     const uint32_t r0 = hdr->phase_rank[phase], r1 = hdr->phase_rank[phase + 1];
@@ -83,9 +123,16 @@ __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restri
             const uint2 rc = rects[e];
             const ViewInfo vi = vt[e / (uint64_t)n];
             const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
+            float4 ra = make_float4(0.f, 0.f, 0.f, 0.f);
+            float2 rb = make_float2(0.f, 0.f);
+            if (cull.enabled) {
+                ra = cull.rec[e].a;
+                rb = make_float2(cull.rec[e].b.x, cull.rec[e].b.y);
+            }
             for (uint32_t ty = y0; ty <= y1; ++ty) {
                 const uint32_t row = vi.tile_base + ty * (uint32_t)vi.tiles_x;
-                for (uint32_t tx = x0; tx <= x1; ++tx) c += alive[row + tx] != 0u;
+                for (uint32_t tx = x0; tx <= x1; ++tx)
+                    c += alive[row + tx] != 0u && (!cull.enabled || tile_may_contribute(ra, rb, vi, tx, ty, cull));
             }
         }
     }
@@ -202,10 +249,12 @@ __global__ __launch_bounds__(kBlock) void k_emit_rects(const uint32_t* __restric
                                                       const uint2* __restrict__ rects, int64_t nv, int64_t n,
                                                       const ViewInfo* __restrict__ vt,
                                                       const SavedHeader* __restrict__ hdr, int phase,
+                                                      CullArgs cull, uint32_t n_tiles,
                                                       uint32_t* __restrict__ tiles_out,
                                                       uint32_t* __restrict__ vals_out) {
     __shared__ int32_t s_off[kEmitSpan + 1];
     __shared__ uint32_t s_e[kEmitSpan + 1], s_base[kEmitSpan + 1], s_w[kEmitSpan + 1], s_tx[kEmitSpan + 1];
+    __shared__ uint32_t s_xy[kEmitSpan + 1];
     __shared__ float s_iw[kEmitSpan + 1];
     const uint64_t K = hdr->phase_count[phase];
     const uint64_t p0 = (uint64_t)blockIdx.x * kEmitSpan;
@@ -229,6 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_rects(const uint32_t* __restric
             s_base[i] = vi.tile_base + y0 * (uint32_t)vi.tiles_x + x0;
             s_w[i] = w;
             s_tx[i] = (uint32_t)vi.tiles_x;
+            s_xy[i] = rc.x;
             s_iw[i] = 1.0f / (float)w;
         }
         nent += __syncthreads_count(own);
@@ -250,8 +300,18 @@ __global__ __launch_bounds__(kBlock) void k_emit_rects(const uint32_t* __restric
         if (row * w > j) --row;
         else if ((row + 1) * w <= j) ++row;
         const uint32_t col = j - row * w;
-        tiles_out[p0 + q] = s_base[lo] + row * s_tx[lo] + col;
-        vals_out[p0 + q] = s_e[lo];
+        const uint32_t e = s_e[lo];
+        uint32_t tile = s_base[lo] + row * s_tx[lo] + col;
+        if (cull.enabled) {
+            const Record* rp = cull.rec + e;
+            const float4 ra = rp->a;
+            const float2 rb = make_float2(rp->b.x, rp->b.y);
+            const ViewInfo vi = vt[e / (uint64_t)n];
+            const uint32_t xy = s_xy[lo];
+            if (!tile_may_contribute(ra, rb, vi, (xy & 0xFFFFu) + col, (xy >> 16) + row, cull)) tile = n_tiles;
+        }
+        tiles_out[p0 + q] = tile;
+        vals_out[p0 + q] = e;
     }
 }
 
@@ -263,7 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_alive(const uint32_t* __restric
                                                       const ViewInfo* __restrict__ vt,
                                                       const uint32_t* __restrict__ alive,
                                                       const SavedHeader* __restrict__ hdr, int phase,
-                                                      uint32_t* __restrict__ tiles_out,
+                                                      CullArgs cull, uint32_t* __restrict__ tiles_out,
                                                       uint32_t* __restrict__ vals_out) {
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (r >= nv) return;
@@ -277,10 +337,17 @@ __global__ __launch_bounds__(kBlock) void k_emit_alive(const uint32_t* __restric
     const ViewInfo vi = vt[e / (uint64_t)n];
     const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
     const uint64_t end = off + c;
+    float4 ra = make_float4(0.f, 0.f, 0.f, 0.f);
+    float2 rb = make_float2(0.f, 0.f);
+    if (cull.enabled) {
+        ra = cull.rec[e].a;
+        rb = make_float2(cull.rec[e].b.x, cull.rec[e].b.y);
+    }
     for (uint32_t ty = y0; ty <= y1 && off < end; ++ty) {
         const uint32_t row = vi.tile_base + ty * (uint32_t)vi.tiles_x;
         for (uint32_t tx = x0; tx <= x1 && off < end; ++tx) {
             if (alive[row + tx] == 0u) continue;
+            if (cull.enabled && !tile_may_contribute(ra, rb, vi, tx, ty, cull)) continue;
             tiles_out[off] = row + tx;
             vals_out[off] = e;
             ++off;
@@ -341,11 +408,11 @@ hipError_t launch_visible(const uint32_t* sorted_keys, int64_t nv, int phases, S
 
 hipError_t launch_phase_count(const uint32_t* order, const uint32_t* counts, const uint2* rects, int64_t nv,
                               int64_t n, const ViewInfo* vt, const uint32_t* alive, const SavedHeader* hdr,
-                              int phase, uint32_t* pcounts, hipStream_t s) {
+                              int phase, const CullArgs& cull, uint32_t* pcounts, hipStream_t s) {
     if (nv == 0) return hipSuccess;
     const unsigned grid = (unsigned)((nv + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_phase_count, dim3(grid), dim3(kBlock), 0, s, order, counts, rects, nv, n, vt, alive, hdr,
-                       phase, pcounts);
+                       phase, cull, pcounts);
     return hipGetLastError();
 }
 
@@ -364,16 +431,17 @@ hipError_t launch_count_scan(const uint32_t* pcounts, int64_t nv, uint64_t* offs
 hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uint32_t* emit_start,
                        const uint32_t* pcounts, const uint2* rects, int64_t nv, int64_t n, const ViewInfo* vt,
                        const uint32_t* alive, const SavedHeader* hdr, int phase, int64_t max_pairs,
-                       uint32_t* tiles_out, uint32_t* vals_out, hipStream_t s) {
+                       const CullArgs& cull, uint32_t n_tiles, uint32_t* tiles_out, uint32_t* vals_out,
+                       hipStream_t s) {
     if (nv == 0 || max_pairs == 0) return hipSuccess;
     if (phase == 0) {
         const unsigned grid = (unsigned)((max_pairs + kEmitSpan - 1) / kEmitSpan);
         hipLaunchKernelGGL(k_emit_rects, dim3(grid), dim3(kBlock), 0, s, order, offsets, emit_start, rects, nv, n, vt,
-                           hdr, phase, tiles_out, vals_out);
+                           hdr, phase, cull, n_tiles, tiles_out, vals_out);
     } else {
         const unsigned grid = (unsigned)((nv + kBlock - 1) / kBlock);
         hipLaunchKernelGGL(k_emit_alive, dim3(grid), dim3(kBlock), 0, s, order, offsets, pcounts, rects, nv, n, vt,
-                           alive, hdr, phase, tiles_out, vals_out);
+                           alive, hdr, phase, cull, tiles_out, vals_out);
     }
     return hipGetLastError();
 }

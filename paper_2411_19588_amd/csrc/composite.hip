@@ -2,24 +2,29 @@
 // eq. opacity_impact), the underwater epilogue (eq. 3dgs_uw at the depth of
 // eq. Depth) and the exact adjoint.
 //
-// One wave64 renders one tile: a 16x16 tile gives every lane 4 pixels (rows
-// y, y+4, y+8, y+12 of its column), an 8x8 tile one pixel.  The tile's
-// depth-ordered records are staged in LDS in batches (one or more per lane)
-// and every lane reads the same record (broadcast), so the record loads, the
-// loop control, the early-exit vote and the adjoint's reduction are shared by
-// the lane's pixels.  A wave stops as soon as all of its pixels have
-// terminated.  With depth-progressive binning the forward runs once per phase:
-// per-pixel state (T, C, D, W, last contributor, terminated) carries over, and
-// a tile whose pixels have all terminated writes its outputs and is skipped by
-// later phases.  In persistent mode a fixed grid of waves pulls tile indices
-// from a device counter, so one launch serves every view.
+// A tile is split among the waves of one workgroup: at 16x16 a wave owns an 8x8
+// quadrant (one pixel per lane), a 16x8 half (two) or the whole tile (four pixels
+// per lane: rows y, y+4, y+8, y+12 of its column); an 8x8 tile is one wave.  Every
+// lane evaluates the same record at a time, which reaches the wave either from LDS
+// (the workgroup stages a batch of the tile's records, each lane reads the same
+// address) or through the scalar data cache (each wave fetches the record
+// indices of its tile and loads one record at a time into scalar registers, one
+// ahead of its use; no LDS and no workgroup barriers on the walk).  A wave stops as
+// soon as all of its pixels have terminated; a terminated pixel keeps -T in its
+// transmittance slot, so the blend needs no separate flag.  With depth-progressive
+// binning the forward runs once per phase: the per-pixel state (T, C, D, W, last
+// contributor, terminated) carries over, a wave whose pixels have all terminated
+// writes its outputs, and a tile none of whose pixels is alive is skipped by later
+// phases.  In persistent mode a fixed grid of workgroups pulls tile indices from a
+// device counter.
 //
-// The adjoint walks each pixel's contributors back to front (over the phases
-// in reverse) from its last contributor, recovering the transmittance by
-// T_i = T_{i+1} / (1 - alpha_i) instead of storing per-pixel lists; each lane
-// sums its pixels' terms for a Gaussian, the wave reduces the 10 terms with a
-// transpose reduction on cross-lane swaps (v_permlane32_swap, v_permlane16_swap,
-// DPP row mirrors and quad permutes), and 10 lanes issue one atomic add each.
+// The adjoint walks each pixel's contributors back to front (over the phases in
+// reverse) from its last contributor, recovering the transmittance by
+// T_i = T_{i+1} / (1 - alpha_i) instead of storing per-pixel lists; each lane sums
+// its pixels' terms for a Gaussian, the wave reduces the 10 terms with a transpose
+// reduction on cross-lane swaps (v_permlane32_swap, v_permlane16_swap, DPP row
+// mirrors and quad permutes), and the waves of a workgroup add their sums in LDS
+// before one atomic add per term (scalar-fetch mode: one per wave).
 #include "internal.h"
 
 namespace gs {
@@ -77,14 +82,50 @@ struct BwdArgs {
     int32_t depth_mode;
 };
 
+// Splat fields used by the blend, in registers (scalar registers in scalar-fetch mode).
+struct Splat {
+    float mx, my, A, B, C, o, r, g, b, d;
+};
+
 // alpha exponent of one splat at one pixel: log2 of exp(-q/2), with
-// q = (p - m)^T Q (p - m) and the conic pre-scaled by -log2(e)/2.
-// Forward and adjoint call this same sequence, so they take identical decisions.
-__device__ __forceinline__ float splat_power(const float4& ra, const float4& rb, float fpx, float fpy, float& dx,
-                                             float& dy) {
-    dx = fpx - ra.x;
-    dy = fpy - ra.y;
-    return fmaf(dx, fmaf(ra.z, dx, ra.w * dy), (rb.x * dy) * dy);
+// q = (p - m)^T Q (p - m) and the conic pre-scaled by -log2(e)/2 (A, C) and -log2(e) (B),
+// evaluated as A dx^2 + dy (B dx + C dy) so that a lane's pixels in one column share the
+// dx terms.  Forward and adjoint, and every launch shape, evaluate this same sequence
+// of (dx, dy), so they take identical decisions.
+struct ColTerms {
+    float dx, bdx, adx2;
+};
+
+__device__ __forceinline__ ColTerms col_terms(const Splat& s, float fpx) {
+    const float dx = fpx - s.mx;
+    return {dx, s.B * dx, (s.A * dx) * dx};
+}
+
+__device__ __forceinline__ float splat_power(const Splat& s, const ColTerms& c, float fpy, float& dy) {
+    dy = fpy - s.my;
+    return fmaf(dy, fmaf(s.C, dy, c.bdx), c.adx2);
+}
+
+typedef __attribute__((address_space(4))) const float ConstF;
+
+// Record `e` through the scalar data cache (the index must be wave-uniform): the loads
+// are from the constant address space, which the compiler emits as scalar loads.
+__device__ __forceinline__ Splat load_splat_scalar(const Record* rec, uint32_t e) {
+    const ConstF* p = (const ConstF*)(rec + e);
+    return {p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7], p[8], p[9]};
+}
+
+// Wait until a scalar-loaded splat has arrived (scalar loads complete out of order, so
+// the wait is placed here, before the next record's load is issued).
+__device__ __forceinline__ void splat_ready(const Splat& s) {
+    asm volatile("" ::"s"(s.mx), "s"(s.my), "s"(s.A), "s"(s.B), "s"(s.C), "s"(s.o), "s"(s.r), "s"(s.g), "s"(s.b),
+                 "s"(s.d));
+}
+
+__device__ __forceinline__ Splat splat_from_lds(const float4* sa, const float4* sb, const float2* sc, int j) {
+    const float4 ra = sa[j], rb = sb[j];
+    const float2 rc = sc[j];
+    return {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w, rc.x, rc.y};
 }
 
 __device__ __forceinline__ int find_view(const ViewInfo* vt, int views, uint32_t tile) {
@@ -158,181 +199,348 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
     return x;
 }
 
-// Next tile of this wave: its block index (one tile per workgroup), or the next value of the
-// persistent queue.  The index is made wave-uniform explicitly (lane 0's atomic result,
-// broadcast and read into a scalar register), so every branch on it is uniform and the loop
-// that pulls tiles has a uniform exit; a value >= the tile count ends the loop.
-template <bool PERSISTENT>
-__device__ __forceinline__ uint32_t fetch_tile(uint32_t* queue, uint32_t iter) {
-    if (!PERSISTENT) return iter == 0 ? (uint32_t)blockIdx.x : 0xFFFFFFFFu;
-    uint32_t t = 0;
-    if (threadIdx.x == 0) t = atomicAdd(queue, 1u);
-    return (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)t, 0));
+__device__ __forceinline__ uint32_t lane_index(uint32_t chunk, uint32_t j) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)chunk, (int)j);
 }
 
-template <int TW, int TH, int BATCH, bool PERSISTENT>
-__global__ __launch_bounds__(64) void k_composite_fwd(FwdArgs a) {
-    constexpr int PPL = TW * TH / 64;   // pixels per lane
-    constexpr int ROWS = 64 / TW;       // rows covered by one pass of the wave
-    static_assert(PPL >= 1 && TW * TH == 64 * PPL && BATCH % 64 == 0, "tile shape");
-    __shared__ float4 sa[BATCH], sb[BATCH], sc[BATCH];
-    const int lane = threadIdx.x;
+// How a tile is split among the waves of a workgroup: each wave owns a SW-wide block of
+// 64 * PPL pixels, lane l at column l % SW and rows l / SW + k * R (k < PPL).
+template <int TW, int TH, int PPL>
+struct Shape {
+    static constexpr int SW = (TW == 16 && PPL == 1) ? 8 : TW;
+    static constexpr int R = 64 / SW;
+    static constexpr int SH = R * PPL;
+    static constexpr int NWX = TW / SW;
+    static constexpr int NW = NWX * (TH / SH);
+    static constexpr int THREADS = 64 * NW;
+    static_assert(SW * R == 64 && TW % SW == 0 && TH % SH == 0 && NW >= 1 && NW <= 4, "tile split");
+};
+
+// Next tile of this workgroup: its block index (one tile per workgroup), or the next value
+// of the persistent queue.  The value is wave-uniform by construction (read into a scalar
+// register), so every branch on it is uniform and the loop that pulls tiles has a uniform
+// exit; a value >= the tile count ends the loop.
+template <int NW, bool PERSISTENT>
+__device__ __forceinline__ uint32_t fetch_tile(uint32_t* queue, uint32_t iter, uint32_t* s_tile) {
+    if (!PERSISTENT) return iter == 0 ? (uint32_t)blockIdx.x : 0xFFFFFFFFu;
+    if (NW == 1) {
+        uint32_t t = 0;
+        if (threadIdx.x == 0) t = atomicAdd(queue, 1u);
+        return (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)t, 0));
+    }
+    __syncthreads();   // every wave has read the previous value
+    if (threadIdx.x == 0) *s_tile = atomicAdd(queue, 1u);
+    __syncthreads();
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)*s_tile);
+}
+
+// OR of a per-wave flag over the workgroup (a barrier; `slot` must not be reused before
+// the next barrier).
+template <int NW>
+__device__ __forceinline__ bool block_any(bool wave_flag, uint32_t* slot) {
+    if (NW == 1) return wave_flag;
+    if ((threadIdx.x & 63) == 0) slot[threadIdx.x >> 6] = wave_flag ? 1u : 0u;
+    __syncthreads();
+    uint32_t any = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) any |= slot[w];
+    return any != 0;
+}
+
+template <int PPL>
+__device__ __forceinline__ bool lane_live(const float* T) {
+    bool live = false;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) live = live || T[k] > 0.0f;
+    return live;
+}
+
+// Front-to-back blend of one splat into a lane's pixels.  T < 0 marks a terminated pixel
+// (|T| is its final transmittance): its T(1 - alpha) is negative, so it neither blends nor
+// changes.  `idx1` is the splat's list position + 1.
+template <int PPL, int R>
+__device__ __forceinline__ void blend(const Splat& s, float fpx, float fpy0, uint32_t idx1, float* T, float* C0,
+                                      float* C1, float* C2, float* D, float* W, uint32_t* last, float amin,
+                                      float amax, float tmin) {
+    const ColTerms ct = col_terms(s, fpx);
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        float dy;
+        const float pw = splat_power(s, ct, fpy0 + (float)(k * R), dy);
+        const float alpha = fminf(amax, s.o * __builtin_amdgcn_exp2f(pw));
+        if (alpha >= amin) {
+            const float Tn = T[k] * (1.0f - alpha);
+            const bool use = Tn >= tmin;
+            const float w = use ? alpha * T[k] : 0.0f;
+            C0[k] = fmaf(w, s.r, C0[k]);
+            C1[k] = fmaf(w, s.g, C1[k]);
+            C2[k] = fmaf(w, s.b, C2[k]);
+            D[k] = fmaf(w, s.d, D[k]);
+            W[k] += w;
+            T[k] = use ? Tn : -fabsf(T[k]);
+            last[k] = use ? idx1 : last[k];
+        }
+    }
+}
+
+template <int TW, int TH, int PPL, int BATCH, bool SCALAR, bool PERSISTENT>
+__global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_fwd(FwdArgs a) {
+    using S = Shape<TW, TH, PPL>;
+    constexpr int NW = S::NW, THREADS = S::THREADS, R = S::R;
+    constexpr int LB = SCALAR ? 1 : BATCH;
+    static_assert(SCALAR || BATCH % THREADS == 0 || THREADS % BATCH == 0, "batch");
+    __shared__ float4 sa[LB], sb[LB];
+    __shared__ float2 sc[LB];
+    __shared__ uint32_t s_flag[3][NW];
+    __shared__ uint32_t s_tile;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ox = (wave % S::NWX) * S::SW, oy = (wave / S::NWX) * S::SH;
     for (uint32_t iter = 0;; ++iter) {
-        const uint32_t tile = fetch_tile<PERSISTENT>(a.queue, iter);
+        const uint32_t tile = fetch_tile<NW, PERSISTENT>(a.queue, iter, &s_tile);
         if (tile >= a.tiles) break;
         if (a.phase > 0 && a.alive[tile] == 0u) continue;   // every pixel terminated in an earlier phase
         const int v = find_view(a.vt, a.views, tile);
         const ViewInfo vi = a.vt[v];
         const uint32_t lt = tile - vi.tile_base;
-        const int px = (int)(lt % (uint32_t)vi.tiles_x) * TW + lane % TW;
-        const int py0 = (int)(lt / (uint32_t)vi.tiles_x) * TH + lane / TW;
-        const float fpx = (float)px + 0.5f;
+        const int px = (int)(lt % (uint32_t)vi.tiles_x) * TW + ox + lane % S::SW;
+        const int py0 = (int)(lt / (uint32_t)vi.tiles_x) * TH + oy + lane / S::SW;
+        const float fpx = (float)px + 0.5f, fpy0 = (float)py0 + 0.5f;
         const uint2 rg = a.ranges[tile];
         float T[PPL], C0[PPL], C1[PPL], C2[PPL], D[PPL], W[PPL];
         uint32_t last[PPL];
-        bool done[PPL], inside[PPL];
+        bool inside[PPL];
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
-            const int py = py0 + k * ROWS;
+            const int py = py0 + k * R;
             inside[k] = px < vi.width && py < vi.height;
             const int64_t p = vi.pix_base + (int64_t)py * vi.width + px;
-            T[k] = 1.0f;
+            T[k] = inside[k] ? 1.0f : -1.0f;
             C0[k] = C1[k] = C2[k] = D[k] = W[k] = 0.0f;
             last[k] = 0;
-            done[k] = !inside[k];
             if (a.phase > 0 && inside[k]) {
-                T[k] = a.tfinal[p];
+                const float tf = a.tfinal[p];
+                T[k] = a.done[p] ? -tf : tf;
                 C0[k] = a.cair[p];
                 C1[k] = a.cair[a.pixels + p];
                 C2[k] = a.cair[2 * a.pixels + p];
                 D[k] = a.dsum[p];
                 W[k] = a.wsum[p];
                 last[k] = a.nlast[p];
-                done[k] = a.done[p] != 0;
             }
         }
-        for (uint32_t b = rg.x; b < rg.y; b += BATCH) {
-            bool all_done = true;
-#pragma unroll
-            for (int k = 0; k < PPL; ++k) all_done = all_done && done[k];
-            if (__all(all_done)) break;
-            __syncthreads();   // the previous batch has been consumed
-#pragma unroll
-            for (int i = lane; i < BATCH; i += 64) {
-                const uint32_t idx = b + i;
-                if (idx < rg.y) {
-                    const Record r = a.rec[a.vals[idx]];
-                    sa[i] = r.a;
-                    sb[i] = r.b;
-                    sc[i] = r.c;
+        const bool entry_live = __any(lane_live<PPL>(T));
+        if (SCALAR) {
+            // each wave walks the list on its own; records arrive through the scalar cache two
+            // at a time, the next two in flight while the current two are blended
+            for (uint32_t b = rg.x; b < rg.y; b += 64) {
+                if (!__any(lane_live<PPL>(T))) break;
+                const uint32_t n = min(64u, rg.y - b), nm = n - 1;
+                const uint32_t chunk = (uint32_t)lane < n ? a.vals[b + lane] : 0u;
+                Splat p0 = load_splat_scalar(a.rec, lane_index(chunk, 0));
+                Splat p1 = load_splat_scalar(a.rec, lane_index(chunk, min(1u, nm)));
+                for (uint32_t j = 0; j < n; j += 4) {
+                    splat_ready(p0);
+                    splat_ready(p1);
+                    const Splat q0 = load_splat_scalar(a.rec, lane_index(chunk, min(j + 2, nm)));
+                    const Splat q1 = load_splat_scalar(a.rec, lane_index(chunk, min(j + 3, nm)));
+                    blend<PPL, R>(p0, fpx, fpy0, b + j + 1, T, C0, C1, C2, D, W, last, a.amin, a.amax, a.tmin);
+                    if (j + 1 < n)
+                        blend<PPL, R>(p1, fpx, fpy0, b + j + 2, T, C0, C1, C2, D, W, last, a.amin, a.amax, a.tmin);
+                    splat_ready(q0);
+                    splat_ready(q1);
+                    p0 = load_splat_scalar(a.rec, lane_index(chunk, min(j + 4, nm)));
+                    p1 = load_splat_scalar(a.rec, lane_index(chunk, min(j + 5, nm)));
+                    if (j + 2 < n)
+                        blend<PPL, R>(q0, fpx, fpy0, b + j + 3, T, C0, C1, C2, D, W, last, a.amin, a.amax, a.tmin);
+                    if (j + 3 < n)
+                        blend<PPL, R>(q1, fpx, fpy0, b + j + 4, T, C0, C1, C2, D, W, last, a.amin, a.amax, a.tmin);
+                    if ((j & 15) == 12 && !__any(lane_live<PPL>(T))) break;
                 }
             }
-            __syncthreads();
-            const int nb = min(BATCH, (int)(rg.y - b));
-            for (int j = 0; j < nb; ++j) {
-                const float4 ra = sa[j], rb = sb[j], rc = sc[j];
+        } else {
+            int slot = 0;
+            for (uint32_t b = rg.x; b < rg.y; b += BATCH) {
+                const bool wl = __any(lane_live<PPL>(T));
+                // the barrier inside also tells every wave that the previous batch has been consumed
+                if (!block_any<NW>(wl, s_flag[slot])) break;
+                slot = slot == 0 ? 1 : 0;
+                if (NW == 1) __syncthreads();
 #pragma unroll
-                for (int k = 0; k < PPL; ++k) {
-                    if (done[k]) continue;
-                    float dx, dy;
-                    const float pw = splat_power(ra, rb, fpx, (float)(py0 + k * ROWS) + 0.5f, dx, dy);
-                    const float alpha = fminf(a.amax, rb.y * __builtin_amdgcn_exp2f(pw));
-                    if (alpha < a.amin) continue;
-                    const float Tn = T[k] * (1.0f - alpha);
-                    if (Tn < a.tmin) {
-                        done[k] = true;
-                        continue;
+                for (int i = tid; i < BATCH; i += THREADS) {
+                    const uint32_t idx = b + i;
+                    if (idx < rg.y) {
+                        const Record r = a.rec[a.vals[idx]];
+                        sa[i] = r.a;
+                        sb[i] = r.b;
+                        sc[i] = make_float2(r.c.x, r.c.y);
                     }
-                    const float w = alpha * T[k];
-                    C0[k] = fmaf(w, rb.z, C0[k]);
-                    C1[k] = fmaf(w, rb.w, C1[k]);
-                    C2[k] = fmaf(w, rc.x, C2[k]);
-                    D[k] = fmaf(w, rc.y, D[k]);
-                    W[k] += w;
-                    T[k] = Tn;
-                    last[k] = b + j + 1;
+                }
+                __syncthreads();
+                if (wl) {
+                    // the next record is read from LDS while the current one is blended
+                    const int nb = min(BATCH, (int)(rg.y - b)), nm = nb - 1;
+                    Splat p = splat_from_lds(sa, sb, sc, 0);
+                    for (int j = 0; j < nb; j += 2) {
+                        const Splat q = splat_from_lds(sa, sb, sc, min(j + 1, nm));
+                        blend<PPL, R>(p, fpx, fpy0, b + j + 1, T, C0, C1, C2, D, W, last, a.amin, a.amax, a.tmin);
+                        p = splat_from_lds(sa, sb, sc, min(j + 2, nm));
+                        if (j + 1 < nb)
+                            blend<PPL, R>(q, fpx, fpy0, b + j + 2, T, C0, C1, C2, D, W, last, a.amin, a.amax,
+                                          a.tmin);
+                        if ((j & 15) == 14 && !__any(lane_live<PPL>(T))) break;
+                    }
                 }
             }
         }
-        bool mine_alive = false;
+        const bool wave_alive = __any(lane_live<PPL>(T));
+        if (entry_live) {
+            const gs_medium m = a.med[v];
+            const bool finish = !wave_alive || a.phase == a.last_phase;
 #pragma unroll
-        for (int k = 0; k < PPL; ++k) mine_alive = mine_alive || !done[k];
-        const bool any_alive = __any(mine_alive);
-        const gs_medium m = a.med[v];
-        const bool finish = !any_alive || a.phase == a.last_phase;
+            for (int k = 0; k < PPL; ++k) {
+                if (!inside[k]) continue;
+                const int py = py0 + k * R;
+                const int64_t p = vi.pix_base + (int64_t)py * vi.width + px;
+                a.tfinal[p] = fabsf(T[k]);
+                a.nlast[p] = last[k];
+                a.done[p] = T[k] < 0.0f ? 1 : 0;
+                a.cair[p] = C0[k];
+                a.cair[a.pixels + p] = C1[k];
+                a.cair[2 * a.pixels + p] = C2[k];
+                a.dsum[p] = D[k];
+                a.wsum[p] = W[k];
+                if (!finish) continue;
+                const int64_t plane = (int64_t)vi.width * vi.height;
+                float* rgb = a.out_rgb + 3 * vi.pix_base + (int64_t)py * vi.width + px;
+                float out[3], z;
+                if (W[k] > 0.0f) {
+                    const float zh = D[k] / W[k];
+                    z = depth_map(zh, a.depth_mode);
+                    const float Cc[3] = {C0[k], C1[k], C2[k]};
 #pragma unroll
-        for (int k = 0; k < PPL; ++k) {
-            if (!inside[k]) continue;
-            const int py = py0 + k * ROWS;
-            const int64_t p = vi.pix_base + (int64_t)py * vi.width + px;
-            a.tfinal[p] = T[k];
-            a.nlast[p] = last[k];
-            a.done[p] = done[k] ? 1 : 0;
-            a.cair[p] = C0[k];
-            a.cair[a.pixels + p] = C1[k];
-            a.cair[2 * a.pixels + p] = C2[k];
-            a.dsum[p] = D[k];
-            a.wsum[p] = W[k];
-            if (!finish) continue;
-            const int64_t plane = (int64_t)vi.width * vi.height;
-            float* rgb = a.out_rgb + 3 * vi.pix_base + (int64_t)py * vi.width + px;
-            float out[3], z;
-            if (W[k] > 0.0f) {
-                const float zh = D[k] / W[k];
-                z = depth_map(zh, a.depth_mode);
-                const float Cc[3] = {C0[k], C1[k], C2[k]};
+                    for (int c = 0; c < 3; ++c)
+                        out[c] = Cc[c] * expf(-m.Bd[c] * z) + m.Binf[c] * (1.0f - expf(-m.Bb[c] * z));
+                } else {
+                    z = 0.0f;
 #pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    out[c] = Cc[c] * expf(-m.Bd[c] * z) + m.Binf[c] * (1.0f - expf(-m.Bb[c] * z));
-            } else {
-                z = 0.0f;
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    out[c] = a.depth_mode == 1 ? m.Binf[c] * (1.0f - expf(-m.Bb[c]))
-                                               : (m.Bb[c] > 0.0f ? m.Binf[c] : 0.0f);
+                    for (int c = 0; c < 3; ++c)
+                        out[c] = a.depth_mode == 1 ? m.Binf[c] * (1.0f - expf(-m.Bb[c]))
+                                                   : (m.Bb[c] > 0.0f ? m.Binf[c] : 0.0f);
+                }
+                rgb[0] = out[0];
+                rgb[plane] = out[1];
+                rgb[2 * plane] = out[2];
+                a.out_depth[p] = z;
+                a.out_alpha[p] = W[k];
             }
-            rgb[0] = out[0];
-            rgb[plane] = out[1];
-            rgb[2 * plane] = out[2];
-            a.out_depth[p] = z;
-            a.out_alpha[p] = W[k];
         }
-        if (lane == 0) {
-            a.alive[tile] = any_alive ? 1u : 0u;
-            if (any_alive) atomicAdd(a.alive_count, 1u);
+        const bool tile_alive = block_any<NW>(wave_alive, s_flag[2]);
+        if (tid == 0) {
+            a.alive[tile] = tile_alive ? 1u : 0u;
+            if (tile_alive) atomicAdd(a.alive_count, 1u);
         }
     }
 }
 
-template <int TW, int TH, int BATCH, bool PERSISTENT>
-__global__ __launch_bounds__(64) void k_composite_bwd(BwdArgs a) {
-    constexpr int PPL = TW * TH / 64;
-    constexpr int ROWS = 64 / TW;
-    static_assert(PPL >= 1 && TW * TH == 64 * PPL && BATCH % 64 == 0, "tile shape");
-    __shared__ float4 sa[BATCH], sb[BATCH], sc[BATCH];
-    __shared__ uint32_t se[BATCH];
-    const int lane = threadIdx.x;
+// Adjoint of the blend of one splat for a lane's pixels, walking back to front: adds the
+// lane's terms to g10 = d/d(m_x, m_y, A, B, C, o, r, g, b, depth).  Returns whether any of
+// the lane's pixels was reached by the splat with alpha >= alpha_min.
+template <int PPL, int R>
+__device__ __forceinline__ bool blend_adjoint(const Splat& s, float fpx, float fpy0, uint32_t idx,
+                                              const uint32_t* my_last, float* T, float* S, const float* gC0,
+                                              const float* gC1, const float* gC2, const float* gD, const float* gW,
+                                              float* g10, float amin, float amax) {
+    const ColTerms ct = col_terms(s, fpx);
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+        if (idx >= my_last[k]) continue;
+        float dy;
+        const float pw = splat_power(s, ct, fpy0 + (float)(k * R), dy);
+        const float ev = __builtin_amdgcn_exp2f(pw);
+        const float araw = s.o * ev;
+        const float alpha = fminf(amax, araw);
+        if (alpha < amin) continue;
+        any = true;
+        const float rom = __builtin_amdgcn_rcpf(1.0f - alpha);
+        const float Ti = T[k] * rom;
+        const float w = alpha * Ti;
+        const float gf = gC0[k] * s.r + gC1[k] * s.g + gC2[k] * s.b + gD[k] * s.d + gW[k];
+        const float dalpha = Ti * gf - S[k] * rom;
+        S[k] = fmaf(gf, w, S[k]);
+        T[k] = Ti;
+        g10[6] += gC0[k] * w;
+        g10[7] += gC1[k] * w;
+        g10[8] += gC2[k] * w;
+        g10[9] += gD[k] * w;
+        if (araw <= amax) {
+            const float dx = ct.dx;
+            g10[5] += dalpha * ev;
+            const float dpw = dalpha * araw * kLn2;
+            g10[2] += dpw * dx * dx;
+            g10[3] += dpw * dx * dy;
+            g10[4] += dpw * dy * dy;
+            g10[0] -= dpw * (2.0f * s.A * dx + s.B * dy);
+            g10[1] -= dpw * (s.B * dx + 2.0f * s.C * dy);
+        }
+    }
+    return any;
+}
+
+// One splat of the scalar-fetch adjoint: the lanes' terms, the wave sum and one atomic add
+// per term into the splat's 2D gradient.
+template <int PPL, int R>
+__device__ __forceinline__ void adjoint_scalar(const BwdArgs& a, const Splat& s, uint32_t chunk, uint32_t b0, int j,
+                                               float fpx, float fpy0, int lane, const uint32_t* my_last, float* T,
+                                               float* Sx, const float* gC0, const float* gC1, const float* gC2,
+                                               const float* gD, const float* gW) {
+    float g10[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const bool any = blend_adjoint<PPL, R>(s, fpx, fpy0, b0 + (uint32_t)j, my_last, T, Sx, gC0, gC1, gC2, gD, gW,
+                                           g10, a.amin, a.amax);
+    if (__any(any)) {
+        int which;
+        const float t = wave_sum10(g10, lane, which);
+        const uint32_t e = lane_index(chunk, (uint32_t)j);
+        if (which >= 0) unsafeAtomicAdd(a.grad2d + (size_t)e * kGrad2D + which, t);
+    }
+}
+
+template <int TW, int TH, int PPL, int BATCH, bool SCALAR, bool PERSISTENT>
+__global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_bwd(BwdArgs a) {
+    using S = Shape<TW, TH, PPL>;
+    constexpr int NW = S::NW, THREADS = S::THREADS, R = S::R;
+    constexpr int LB = SCALAR ? 1 : BATCH;
+    constexpr int RED = (!SCALAR && NW > 1) ? 64 : 1;   // records per cross-wave reduction
+    __shared__ float4 sa[LB], sb[LB];
+    __shared__ float2 sc[LB];
+    __shared__ uint32_t se[LB];
+    __shared__ float red[NW][RED][kGrad2D];
+    __shared__ float s_med[NW][9];
+    __shared__ uint32_t s_last[NW];
+    __shared__ uint32_t s_tile;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ox = (wave % S::NWX) * S::SW, oy = (wave / S::NWX) * S::SH;
     for (uint32_t iter = 0;; ++iter) {
-        const uint32_t tile = fetch_tile<PERSISTENT>(a.queue, iter);
+        const uint32_t tile = fetch_tile<NW, PERSISTENT>(a.queue, iter, &s_tile);
         if (tile >= a.tiles) break;
         const int v = find_view(a.vt, a.views, tile);
         const ViewInfo vi = a.vt[v];
         const uint32_t lt = tile - vi.tile_base;
-        const int px = (int)(lt % (uint32_t)vi.tiles_x) * TW + lane % TW;
-        const int py0 = (int)(lt / (uint32_t)vi.tiles_x) * TH + lane / TW;
-        const float fpx = (float)px + 0.5f;
+        const int px = (int)(lt % (uint32_t)vi.tiles_x) * TW + ox + lane % S::SW;
+        const int py0 = (int)(lt / (uint32_t)vi.tiles_x) * TH + oy + lane / S::SW;
+        const float fpx = (float)px + 0.5f, fpy0 = (float)py0 + 0.5f;
         const gs_medium m = a.med[v];
         // ---- per-pixel upstream gradient through the medium and depth
         float pm[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        float gC0[PPL], gC1[PPL], gC2[PPL], gD[PPL], gW[PPL], T[PPL], S[PPL];
+        float gC0[PPL], gC1[PPL], gC2[PPL], gD[PPL], gW[PPL], T[PPL], Sx[PPL];
         uint32_t my_last[PPL];
         uint32_t lane_last = 0;
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
-            gC0[k] = gC1[k] = gC2[k] = gD[k] = gW[k] = S[k] = 0.0f;
+            gC0[k] = gC1[k] = gC2[k] = gD[k] = gW[k] = Sx[k] = 0.0f;
             T[k] = 1.0f;
             my_last[k] = 0;
-            const int py = py0 + k * ROWS;
+            const int py = py0 + k * R;
             if (!(px < vi.width && py < vi.height)) continue;
             const int64_t p = vi.pix_base + (int64_t)py * vi.width + px;
             const int64_t plane = (int64_t)vi.width * vi.height;
@@ -348,11 +556,11 @@ __global__ __launch_bounds__(64) void k_composite_bwd(BwdArgs a) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     A[c] = expf(-m.Bd[c] * z);
-                    const float Sx = expf(-m.Bb[c] * z);
+                    const float Sb = expf(-m.Bb[c] * z);
                     pm[c] += -G[c] * Cc[c] * z * A[c];
-                    pm[3 + c] += G[c] * m.Binf[c] * z * Sx;
-                    pm[6 + c] += G[c] * (1.0f - Sx);
-                    dz += G[c] * (m.Binf[c] * m.Bb[c] * Sx - m.Bd[c] * Cc[c] * A[c]);
+                    pm[3 + c] += G[c] * m.Binf[c] * z * Sb;
+                    pm[6 + c] += G[c] * (1.0f - Sb);
+                    dz += G[c] * (m.Binf[c] * m.Bb[c] * Sb - m.Bd[c] * Cc[c] * A[c]);
                 }
                 const float dzh = a.depth_mode == 1 ? dz * 0.05f * (1.0f - z * z) : dz;
                 gC0[k] = G[0] * A[0];
@@ -367,107 +575,226 @@ __global__ __launch_bounds__(64) void k_composite_bwd(BwdArgs a) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     if (a.depth_mode == 1) {
-                        const float Sx = expf(-m.Bb[c]);
-                        pm[6 + c] += G[c] * (1.0f - Sx);
-                        pm[3 + c] += G[c] * m.Binf[c] * Sx;
+                        const float Sb = expf(-m.Bb[c]);
+                        pm[6 + c] += G[c] * (1.0f - Sb);
+                        pm[3 + c] += G[c] * m.Binf[c] * Sb;
                     } else {
                         pm[6 + c] += m.Bb[c] > 0.0f ? G[c] : 0.0f;
                     }
                 }
             }
         }
-        // ---- medium partial sums of this tile
+        // ---- medium partial sums of this tile, and the furthest list position any pixel reached
+        const uint32_t wave_last = wave_max_u32(lane_last);
+        uint32_t block_last = wave_last;
         {
             int which;
             const float t = wave_sum10(pm, lane, which);
-            if (which >= 0 && which < 9) a.medpart[(int64_t)tile * 9 + which] = t;
-        }
-        const uint32_t block_last = wave_max_u32(lane_last);
-        // ---- reverse walk over the phases' ranges, last phase first
-        for (int ph = a.phases - 1; ph >= 0; --ph) {
-            const uint2 rg = a.ranges[(size_t)ph * a.tiles + tile];
-            if (rg.x >= rg.y || rg.x >= block_last) continue;
-            for (uint32_t b_end = min(rg.y, block_last); b_end > rg.x;) {
-                const uint32_t b0 = b_end - rg.x > (uint32_t)BATCH ? b_end - BATCH : rg.x;
-                const int cnt = (int)(b_end - b0);
-                __syncthreads();   // the previous batch has been consumed
-#pragma unroll
-                for (int i = lane; i < BATCH; i += 64) {
-                    if (i < cnt) {
-                        const uint32_t e = a.vals[b0 + i];
-                        const Record r = a.rec[e];
-                        sa[i] = r.a;
-                        sb[i] = r.b;
-                        sc[i] = r.c;
-                        se[i] = e;
-                    }
-                }
+            if (NW == 1) {
+                if (which >= 0 && which < 9) a.medpart[(int64_t)tile * 9 + which] = t;
+            } else {
+                if (which >= 0 && which < 9) s_med[wave][which] = t;
+                if (lane == 0) s_last[wave] = wave_last;
                 __syncthreads();
-                for (int j = cnt - 1; j >= 0; --j) {
-                    const float4 ra = sa[j], rb = sb[j], rc = sc[j];
-                    const uint32_t idx = b0 + (uint32_t)j;
-                    float g10[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                    bool any = false;
+                if (tid < 9) {
+                    float acc = 0.0f;
 #pragma unroll
-                    for (int k = 0; k < PPL; ++k) {
-                        if (idx >= my_last[k]) continue;
-                        float dx, dy;
-                        const float pw = splat_power(ra, rb, fpx, (float)(py0 + k * ROWS) + 0.5f, dx, dy);
-                        const float ev = __builtin_amdgcn_exp2f(pw);
-                        const float araw = rb.y * ev;
-                        const float alpha = fminf(a.amax, araw);
-                        if (alpha < a.amin) continue;
-                        any = true;
-                        const float rom = __builtin_amdgcn_rcpf(1.0f - alpha);
-                        const float Ti = T[k] * rom;
-                        const float w = alpha * Ti;
-                        const float gf = gC0[k] * rb.z + gC1[k] * rb.w + gC2[k] * rc.x + gD[k] * rc.y + gW[k];
-                        const float dalpha = Ti * gf - S[k] * rom;
-                        S[k] = fmaf(gf, w, S[k]);
-                        T[k] = Ti;
-                        g10[6] += gC0[k] * w;
-                        g10[7] += gC1[k] * w;
-                        g10[8] += gC2[k] * w;
-                        g10[9] += gD[k] * w;
-                        if (araw <= a.amax) {
-                            g10[5] += dalpha * ev;
-                            const float dpw = dalpha * araw * kLn2;
-                            g10[2] += dpw * dx * dx;
-                            g10[3] += dpw * dx * dy;
-                            g10[4] += dpw * dy * dy;
-                            g10[0] -= dpw * (2.0f * ra.z * dx + ra.w * dy);
-                            g10[1] -= dpw * (ra.w * dx + 2.0f * rb.x * dy);
+                    for (int w = 0; w < NW; ++w) acc += s_med[w][tid];
+                    a.medpart[(int64_t)tile * 9 + tid] = acc;
+                }
+                block_last = 0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) block_last = max(block_last, s_last[w]);
+            }
+        }
+        // ---- reverse walk over the phases' ranges, last phase first
+        if (SCALAR) {
+            for (int ph = a.phases - 1; ph >= 0; --ph) {
+                const uint2 rg = a.ranges[(size_t)ph * a.tiles + tile];
+                if (rg.x >= rg.y || rg.x >= wave_last) continue;
+                for (uint32_t b_end = min(rg.y, wave_last); b_end > rg.x;) {
+                    const uint32_t b0 = b_end - rg.x > 64u ? b_end - 64u : rg.x;
+                    const uint32_t n = b_end - b0;
+                    const uint32_t chunk = (uint32_t)lane < n ? a.vals[b0 + lane] : 0u;
+                    // records two at a time from the back, the next two in flight
+                    Splat p0 = load_splat_scalar(a.rec, lane_index(chunk, n - 1));
+                    Splat p1 = load_splat_scalar(a.rec, lane_index(chunk, n > 1 ? n - 2 : 0));
+                    for (int j = (int)n - 1; j >= 0; j -= 4) {
+                        splat_ready(p0);
+                        splat_ready(p1);
+                        const Splat q0 = load_splat_scalar(a.rec, lane_index(chunk, (uint32_t)max(j - 2, 0)));
+                        const Splat q1 = load_splat_scalar(a.rec, lane_index(chunk, (uint32_t)max(j - 3, 0)));
+                        adjoint_scalar<PPL, R>(a, p0, chunk, b0, j, fpx, fpy0, lane, my_last, T, Sx, gC0, gC1, gC2,
+                                               gD, gW);
+                        if (j >= 1)
+                            adjoint_scalar<PPL, R>(a, p1, chunk, b0, j - 1, fpx, fpy0, lane, my_last, T, Sx, gC0, gC1,
+                                                   gC2, gD, gW);
+                        splat_ready(q0);
+                        splat_ready(q1);
+                        p0 = load_splat_scalar(a.rec, lane_index(chunk, (uint32_t)max(j - 4, 0)));
+                        p1 = load_splat_scalar(a.rec, lane_index(chunk, (uint32_t)max(j - 5, 0)));
+                        if (j >= 2)
+                            adjoint_scalar<PPL, R>(a, q0, chunk, b0, j - 2, fpx, fpy0, lane, my_last, T, Sx, gC0, gC1,
+                                                   gC2, gD, gW);
+                        if (j >= 3)
+                            adjoint_scalar<PPL, R>(a, q1, chunk, b0, j - 3, fpx, fpy0, lane, my_last, T, Sx, gC0, gC1,
+                                                   gC2, gD, gW);
+                    }
+                    b_end = b0;
+                }
+            }
+        } else {
+            for (int ph = a.phases - 1; ph >= 0; --ph) {
+                const uint2 rg = a.ranges[(size_t)ph * a.tiles + tile];
+                if (rg.x >= rg.y || rg.x >= block_last) continue;
+                for (uint32_t b_end = min(rg.y, block_last); b_end > rg.x;) {
+                    const uint32_t b0 = b_end - rg.x > (uint32_t)BATCH ? b_end - BATCH : rg.x;
+                    const int cnt = (int)(b_end - b0);
+                    __syncthreads();   // the previous batch has been consumed
+#pragma unroll
+                    for (int i = tid; i < BATCH; i += THREADS) {
+                        if (i < cnt) {
+                            const uint32_t e = a.vals[b0 + i];
+                            const Record r = a.rec[e];
+                            sa[i] = r.a;
+                            sb[i] = r.b;
+                            sc[i] = make_float2(r.c.x, r.c.y);
+                            se[i] = e;
                         }
                     }
-                    if (__any(any)) {
-                        int which;
-                        const float t = wave_sum10(g10, lane, which);
-                        if (which >= 0) unsafeAtomicAdd(a.grad2d + (size_t)se[j] * kGrad2D + which, t);
+                    __syncthreads();
+                    for (int j = cnt - 1; j >= 0; --j) {
+                        const uint32_t idx = b0 + (uint32_t)j;
+                        float g10[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                        bool any = false;
+                        if (idx < wave_last) {
+                            const Splat s = splat_from_lds(sa, sb, sc, j);
+                            any = blend_adjoint<PPL, R>(s, fpx, fpy0, idx, my_last, T, Sx, gC0, gC1, gC2, gD, gW,
+                                                        g10, a.amin, a.amax);
+                        }
+                        if (NW == 1) {
+                            if (__any(any)) {
+                                int which;
+                                const float t = wave_sum10(g10, lane, which);
+                                if (which >= 0) unsafeAtomicAdd(a.grad2d + (size_t)se[j] * kGrad2D + which, t);
+                            }
+                        } else {
+                            const int slot = j & (RED - 1);
+                            if (__any(any)) {
+                                int which;
+                                const float t = wave_sum10(g10, lane, which);
+                                if (which >= 0) red[wave][slot][which] = t;
+                            } else if (lane < kGrad2D) {
+                                red[wave][slot][lane] = 0.0f;
+                            }
+                            if (slot == 0) {
+                                // add the waves' sums of records j .. j + nrec - 1, one atomic per term
+                                __syncthreads();
+                                const int nrec = min(RED, cnt - j);
+                                for (int i = tid; i < nrec * kGrad2D; i += THREADS) {
+                                    const int r = i / kGrad2D, c = i - r * kGrad2D;
+                                    float acc = 0.0f;
+#pragma unroll
+                                    for (int w = 0; w < NW; ++w) acc += red[w][r][c];
+                                    if (acc != 0.0f) unsafeAtomicAdd(a.grad2d + (size_t)se[j + r] * kGrad2D + c, acc);
+                                }
+                                __syncthreads();
+                            }
+                        }
                     }
+                    b_end = b0;
                 }
-                b_end = b0;
             }
         }
     }
 }
 
-template <int TW, int TH, int BATCH>
-hipError_t run_fwd(const FwdArgs& a, bool persistent, int grid, hipStream_t s) {
+template <int TW, int TH, int PPL, int BATCH, bool SCALAR, bool PERSISTENT>
+int occupancy_grid(bool fwd) {
+    static int cached[2] = {0, 0};
+    int& g = cached[fwd ? 1 : 0];
+    if (g == 0) {
+        int dev = 0, cus = 256, per_cu = 0;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            hipDeviceProp_t prop;
+            if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+                cus = prop.multiProcessorCount;
+        }
+        constexpr int threads = Shape<TW, TH, PPL>::THREADS;
+        const hipError_t e =
+            fwd ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &per_cu, reinterpret_cast<const void*>(k_composite_fwd<TW, TH, PPL, BATCH, SCALAR, PERSISTENT>),
+                      threads, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &per_cu, reinterpret_cast<const void*>(k_composite_bwd<TW, TH, PPL, BATCH, SCALAR, PERSISTENT>),
+                      threads, 0);
+        if (e != hipSuccess || per_cu < 1) per_cu = 16 / Shape<TW, TH, PPL>::NW;
+        g = cus * per_cu;
+    }
+    return g;
+}
+
+template <int TW, int TH, int PPL, int BATCH, bool SCALAR>
+hipError_t run_fwd(const FwdArgs& a, bool persistent, hipStream_t s) {
+    constexpr int threads = Shape<TW, TH, PPL>::THREADS;
     if (persistent)
-        hipLaunchKernelGGL((k_composite_fwd<TW, TH, BATCH, true>), dim3(grid), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((k_composite_fwd<TW, TH, PPL, BATCH, SCALAR, true>),
+                           dim3(occupancy_grid<TW, TH, PPL, BATCH, SCALAR, true>(true)), dim3(threads), 0, s, a);
     else
-        hipLaunchKernelGGL((k_composite_fwd<TW, TH, BATCH, false>), dim3(a.tiles), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((k_composite_fwd<TW, TH, PPL, BATCH, SCALAR, false>), dim3(a.tiles), dim3(threads), 0, s,
+                           a);
     return hipGetLastError();
 }
 
-template <int TW, int TH, int BATCH>
-hipError_t run_bwd(const BwdArgs& a, bool persistent, int grid, hipStream_t s) {
+template <int TW, int TH, int PPL, int BATCH, bool SCALAR>
+hipError_t run_bwd(const BwdArgs& a, bool persistent, hipStream_t s) {
+    constexpr int threads = Shape<TW, TH, PPL>::THREADS;
     if (persistent)
-        hipLaunchKernelGGL((k_composite_bwd<TW, TH, BATCH, true>), dim3(grid), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((k_composite_bwd<TW, TH, PPL, BATCH, SCALAR, true>),
+                           dim3(occupancy_grid<TW, TH, PPL, BATCH, SCALAR, true>(false)), dim3(threads), 0, s, a);
     else
-        hipLaunchKernelGGL((k_composite_bwd<TW, TH, BATCH, false>), dim3(a.tiles), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((k_composite_bwd<TW, TH, PPL, BATCH, SCALAR, false>), dim3(a.tiles), dim3(threads), 0, s,
+                           a);
     return hipGetLastError();
 }
+
+// Dispatch over the launch shape: tile, pixels per lane, LDS batch and record fetch.
+template <template <int, int, int, int, bool> class Run, typename Args>
+hipError_t dispatch_shape(const gs_options& o, const Args& a, bool pers, hipStream_t s) {
+    const int fetch = o.record_fetch != GS_FETCH_DEFAULT ? o.record_fetch : kDefaultRecordFetch;
+    const bool scalar = fetch == GS_FETCH_SCALAR;
+    if (o.tile_w == 8) return scalar ? Run<8, 8, 1, 64, true>::go(a, pers, s) : Run<8, 8, 1, 64, false>::go(a, pers, s);
+    const int ppl = o.pixels_per_lane != 0 ? o.pixels_per_lane : kDefaultPixelsPerLane;
+    if (scalar) {
+        if (ppl == 1) return Run<16, 16, 1, 64, true>::go(a, pers, s);
+        if (ppl == 2) return Run<16, 16, 2, 64, true>::go(a, pers, s);
+        return Run<16, 16, 4, 64, true>::go(a, pers, s);
+    }
+#define GS_BATCHES(P)                                                        \
+    switch (o.lds_batch) {                                                   \
+        case 64: return Run<16, 16, P, 64, false>::go(a, pers, s);          \
+        case 128: return Run<16, 16, P, 128, false>::go(a, pers, s);        \
+        default: return Run<16, 16, P, 256, false>::go(a, pers, s);         \
+    }
+    if (ppl == 1) GS_BATCHES(1)
+    if (ppl == 2) GS_BATCHES(2)
+    GS_BATCHES(4)
+#undef GS_BATCHES
+}
+
+template <int TW, int TH, int PPL, int BATCH, bool SCALAR>
+struct FwdRun {
+    static hipError_t go(const FwdArgs& a, bool pers, hipStream_t s) {
+        return run_fwd<TW, TH, PPL, BATCH, SCALAR>(a, pers, s);
+    }
+};
+
+template <int TW, int TH, int PPL, int BATCH, bool SCALAR>
+struct BwdRun {
+    static hipError_t go(const BwdArgs& a, bool pers, hipStream_t s) {
+        return run_bwd<TW, TH, PPL, BATCH, SCALAR>(a, pers, s);
+    }
+};
 
 __global__ __launch_bounds__(kBlock) void k_medium_reduce(const ViewInfo* __restrict__ vt,
                                                          const float* __restrict__ medpart,
@@ -492,17 +819,21 @@ __global__ __launch_bounds__(kBlock) void k_medium_reduce(const ViewInfo* __rest
     if (tid < 9) grad_medium[v * 9 + tid] = red[tid][0];
 }
 
-// Per tile: sum and max over pixels of the list entries walked (entries of the tile's
-// phase ranges before the pixel's last contributor, plus the entry that stopped the walk).
+// Per tile: sum and max over pixels of the list entries walked (entries of the tile's phase
+// ranges before the pixel's last contributor, plus the entry that stopped the walk), the
+// number of those entries that blended (alpha >= alpha_min, re-evaluated with the
+// compositing kernel's own sequence), and the live pairs of the tile.
 template <int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void k_forward_stats(const ViewInfo* __restrict__ vt, int32_t views,
                                                          int32_t phases, uint32_t n_tiles,
                                                          const uint2* __restrict__ ranges,
+                                                         const uint32_t* __restrict__ vals,
+                                                         const Record* __restrict__ rec,
                                                          const uint32_t* __restrict__ nlast,
-                                                         const uint8_t* __restrict__ done,
+                                                         const uint8_t* __restrict__ done, float amin, float amax,
                                                          unsigned long long* __restrict__ out) {
-    __shared__ unsigned long long s_sum;
-    __shared__ uint32_t s_max, s_any;
+    __shared__ unsigned long long s_sum, s_blend;
+    __shared__ uint32_t s_max;
     const int tid = threadIdx.x;
     const uint32_t tile = blockIdx.x;
     const int v = find_view(vt, views, tile);
@@ -512,46 +843,48 @@ __global__ __launch_bounds__(TW* TH) void k_forward_stats(const ViewInfo* __rest
     const int py = (int)(lt / (uint32_t)vi.tiles_x) * TH + tid / TW;
     if (tid == 0) {
         s_sum = 0;
+        s_blend = 0;
         s_max = 0;
-        s_any = 0;
     }
     __syncthreads();
+    uint32_t total = 0;
+    for (int ph = 0; ph < phases; ++ph) {
+        const uint2 rg = ranges[(size_t)ph * n_tiles + tile];
+        total += rg.y - rg.x;
+    }
     if (px < vi.width && py < vi.height) {
         const int64_t p = vi.pix_base + (int64_t)py * vi.width + px;
         const uint32_t last = nlast[p];
-        uint32_t walked = 0, total = 0;
+        const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+        uint32_t walked = 0, blended = 0;
         for (int ph = 0; ph < phases; ++ph) {
             const uint2 rg = ranges[(size_t)ph * n_tiles + tile];
-            total += rg.y - rg.x;
-            if (last > rg.x) walked += min(last, rg.y) - rg.x;
+            for (uint32_t i = rg.x; i < min(rg.y, last); ++i) {
+                const Record r = rec[vals[i]];
+                const Splat sp{r.a.x, r.a.y, r.a.z, r.a.w, r.b.x, r.b.y, r.b.z, r.b.w, r.c.x, r.c.y};
+                float dy;
+                const float pw = splat_power(sp, col_terms(sp, fpx), fpy, dy);
+                blended += fminf(amax, sp.o * __builtin_amdgcn_exp2f(pw)) >= amin;
+                ++walked;
+            }
         }
         if (done[p] && walked < total) walked += 1;
         atomicAdd(&s_sum, (unsigned long long)walked);
+        atomicAdd(&s_blend, (unsigned long long)blended);
         atomicMax(&s_max, walked);
-        if (total) s_any = 1;
     }
     __syncthreads();
     if (tid == 0) {
+        atomicAdd(&out[0], (unsigned long long)total);
         atomicAdd(&out[1], s_sum);
         atomicAdd(&out[2], (unsigned long long)s_max);
-        if (s_any) atomicAdd(&out[3], 1ull);
+        if (total) atomicAdd(&out[3], 1ull);
+        atomicAdd(&out[4], s_blend);
     }
 }
 
-__global__ void k_stats_init(unsigned long long* out, const SavedHeader* hdr) {
-    out[0] = hdr->pair_count;
-    out[1] = out[2] = out[3] = 0;
-}
-
-// Persistent grid: 16 single-wave workgroups per compute unit (4 per SIMD).
-int persistent_grid(int) {
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
-            cus = prop.multiProcessorCount;
-    }
-    return cus * 16;
+__global__ void k_stats_init(unsigned long long* out) {
+    for (int i = 0; i < 5; ++i) out[i] = 0;
 }
 
 }  // namespace
@@ -565,13 +898,7 @@ hipError_t launch_composite_fwd(const gs_options& o, const Layout& L, int phase,
     FwdArgs a{vt, L.views, (uint32_t)L.tiles, phase, L.phases - 1, med, rec, ranges + (size_t)phase * L.tiles, vals,
               &hdr->queue[phase], alive, &hdr->phase_alive[phase], out_rgb, out_depth, out_alpha, tfinal, nlast,
               done, cair, dsum, wsum, L.pixels, o.alpha_min, o.alpha_max, o.t_min, o.depth_mode};
-    const bool pers = o.persistent != 0;
-    if (o.tile_w == 8) return run_fwd<8, 8, 64>(a, pers, persistent_grid(64 * 4), s);
-    switch (o.lds_batch) {
-        case 64: return run_fwd<16, 16, 64>(a, pers, persistent_grid(64 * 4), s);
-        case 128: return run_fwd<16, 16, 128>(a, pers, persistent_grid(64 * 4), s);
-        default: return run_fwd<16, 16, 256>(a, pers, persistent_grid(64 * 4), s);
-    }
+    return dispatch_shape<FwdRun>(o, a, o.persistent != 0, s);
 }
 
 hipError_t launch_composite_bwd(const gs_options& o, const Layout& L, const ViewInfo* vt, const gs_medium* med,
@@ -590,12 +917,7 @@ hipError_t launch_composite_bwd(const gs_options& o, const Layout& L, const View
         hipError_t e = launch_fill_u32(a.queue, 0u, 1, s);
         if (e != hipSuccess) return e;
     }
-    if (o.tile_w == 8) return run_bwd<8, 8, 64>(a, pers, persistent_grid(64 * 4), s);
-    switch (o.lds_batch) {
-        case 64: return run_bwd<16, 16, 64>(a, pers, persistent_grid(64 * 4), s);
-        case 128: return run_bwd<16, 16, 128>(a, pers, persistent_grid(64 * 4), s);
-        default: return run_bwd<16, 16, 256>(a, pers, persistent_grid(64 * 4), s);
-    }
+    return dispatch_shape<BwdRun>(o, a, pers, s);
 }
 
 hipError_t launch_medium_reduce(const ViewInfo* vt, int32_t views, const float* medpart, float* grad_medium,
@@ -604,17 +926,18 @@ hipError_t launch_medium_reduce(const ViewInfo* vt, int32_t views, const float* 
     return hipGetLastError();
 }
 
-hipError_t launch_forward_stats(const Layout& L, const ViewInfo* vt, const uint2* ranges, const uint32_t* nlast,
-                                const uint8_t* done, const SavedHeader* hdr, unsigned long long* out,
-                                hipStream_t s) {
-    hipLaunchKernelGGL(k_stats_init, dim3(1), dim3(1), 0, s, out, hdr);
+hipError_t launch_forward_stats(const gs_options& o, const Layout& L, const ViewInfo* vt, const uint2* ranges,
+                                const uint32_t* vals, const Record* rec, const uint32_t* nlast, const uint8_t* done,
+                                unsigned long long* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_stats_init, dim3(1), dim3(1), 0, s, out);
     if (L.tiles == 0) return hipGetLastError();
     if (L.tile_w == 8)
         hipLaunchKernelGGL((k_forward_stats<8, 8>), dim3((unsigned)L.tiles), dim3(64), 0, s, vt, L.views, L.phases,
-                           (uint32_t)L.tiles, ranges, nlast, done, out);
+                           (uint32_t)L.tiles, ranges, vals, rec, nlast, done, o.alpha_min, o.alpha_max, out);
     else
         hipLaunchKernelGGL((k_forward_stats<16, 16>), dim3((unsigned)L.tiles), dim3(256), 0, s, vt, L.views,
-                           L.phases, (uint32_t)L.tiles, ranges, nlast, done, out);
+                           L.phases, (uint32_t)L.tiles, ranges, vals, rec, nlast, done, o.alpha_min, o.alpha_max,
+                           out);
     return hipGetLastError();
 }
 

@@ -16,6 +16,8 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kMaxSortParts = 1024;
 constexpr int kGrad2D = 10;              // per-(Gaussian, view) 2D gradient: m(2), conic'(3), o, rgb(3), depth
 constexpr int kDefaultPhases = 3;
+constexpr int kDefaultPixelsPerLane = 2;      // 16x16 tiles: two waves per tile
+constexpr int kDefaultRecordFetch = GS_FETCH_LDS;
 
 // Per-view layout derived from the host cameras.
 struct ViewInfo {
@@ -50,8 +52,8 @@ struct SavedHeader {
     uint32_t phase_count[GS_MAX_PHASES];      // pairs of phase p
     uint32_t phase_alive[GS_MAX_PHASES];      // tiles with an unterminated pixel after phase p
     uint32_t queue[GS_MAX_PHASES + 1];        // persistent-mode tile counters (forward phases)
-    unsigned long long stats[4];              // scratch of gs_forward_stats
-    uint32_t pad[10];
+    unsigned long long stats[5];              // scratch of gs_forward_stats
+    uint32_t pad[8];
 };
 
 struct Layout {
@@ -87,17 +89,30 @@ hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, 
 hipError_t launch_visible(const uint32_t* sorted_keys, int64_t nv, int phases, SavedHeader* hdr, hipStream_t s);
 // Per-entry pair counts of phase p (by depth rank): whole rectangles in phase 0, only the tiles
 // still alive in later phases, 0 outside the phase's ranks.
+// Exact tile culling: a (Gaussian, tile) pair of the rectangle is dropped when no pixel centre
+// of the tile can reach alpha >= alpha_min (see tile_may_contribute).
+struct CullArgs {
+    const Record* rec;
+    float log2_amin;
+    int32_t tile_w, tile_h;
+    int32_t enabled;
+};
+
 hipError_t launch_phase_count(const uint32_t* order, const uint32_t* counts, const uint2* rects, int64_t nv,
                               int64_t n, const ViewInfo* vt, const uint32_t* alive, const SavedHeader* hdr,
-                              int phase, uint32_t* pcounts, hipStream_t s);
+                              int phase, const CullArgs& cull, uint32_t* pcounts, hipStream_t s);
 // Exclusive scan of pcounts into offsets (u64) and the phase's pair count and base in hdr (with the
 // capacity check), and for each emission span of 1024 pairs the entry that owns its first pair.
 hipError_t launch_count_scan(const uint32_t* pcounts, int64_t nv, uint64_t* offsets, uint64_t* blocksums,
                              SavedHeader* hdr, int phase, int64_t max_pairs, uint32_t* emit_start, hipStream_t s);
+// Phase 0 writes every pair of each rectangle, a culled pair with the tile id n_tiles (sorted
+// after every real tile and skipped by the commit); later phases write only the pairs of alive,
+// unculled tiles.
 hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uint32_t* emit_start,
                        const uint32_t* pcounts, const uint2* rects, int64_t nv, int64_t n, const ViewInfo* vt,
                        const uint32_t* alive, const SavedHeader* hdr, int phase, int64_t max_pairs,
-                       uint32_t* tiles_out, uint32_t* vals_out, hipStream_t s);
+                       const CullArgs& cull, uint32_t n_tiles, uint32_t* tiles_out, uint32_t* vals_out,
+                       hipStream_t s);
 // Copy the phase's tile-sorted values behind the earlier phases' and record its tile ranges.
 hipError_t launch_commit(const uint32_t* sorted_tiles, const uint32_t* sorted_vals, const SavedHeader* hdr,
                          int phase, int64_t tiles, int64_t max_pairs, uint32_t* vals, uint2* ranges, hipStream_t s);
@@ -116,9 +131,9 @@ hipError_t launch_medium_reduce(const ViewInfo* vt, int32_t views, const float* 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 hipError_t launch_export_keys(const Layout& L, const uint2* ranges, const uint32_t* vals, const uint32_t* depth_keys,
                               int64_t capacity, uint64_t* keys, uint32_t* values, hipStream_t s);
-hipError_t launch_forward_stats(const Layout& L, const ViewInfo* vt, const uint2* ranges, const uint32_t* nlast,
-                                const uint8_t* done, const SavedHeader* hdr, unsigned long long* out,
-                                hipStream_t s);
+hipError_t launch_forward_stats(const gs_options& o, const Layout& L, const ViewInfo* vt, const uint2* ranges,
+                                const uint32_t* vals, const Record* rec, const uint32_t* nlast, const uint8_t* done,
+                                unsigned long long* out, hipStream_t s);
 
 // Timer hooks (no-ops when timer == nullptr).
 void timer_begin(void* timer, const char* name, hipStream_t s);

@@ -23,12 +23,15 @@ class RasterConfig:
     tile: int = 16
     lds_batch: int = 256
     persistent: bool = False
+    pixels_per_lane: int = 0          # 0 = library default
+    record_fetch: str = "default"     # "default", "lds" or "scalar"
     alpha_min: float = 1.0 / 255.0
     alpha_max: float = 0.99
     t_min: float = 1e-4
     dilation: float = 0.3
     kappa: float = 11.1
     depth_mode: int = 0
+    tile_cull: bool = True            # drop (Gaussian, tile) pairs that cannot reach alpha_min
     phases: int = 3
     max_pairs: int = 1 << 22
 
@@ -37,12 +40,16 @@ class RasterConfig:
         o.tile_w = o.tile_h = int(self.tile)
         o.lds_batch = int(self.lds_batch)
         o.persistent = 1 if self.persistent else 0
+        o.pixels_per_lane = int(self.pixels_per_lane)
+        o.record_fetch = {"default": N.GS_FETCH_DEFAULT, "lds": N.GS_FETCH_LDS,
+                          "scalar": N.GS_FETCH_SCALAR}[self.record_fetch]
         o.alpha_min = self.alpha_min
         o.alpha_max = self.alpha_max
         o.t_min = self.t_min
         o.dilation = self.dilation
         o.kappa = self.kappa
         o.depth_mode = int(self.depth_mode)
+        o.tile_cull = 1 if self.tile_cull else 0
         o.phases = int(self.phases)
         o.max_pairs = int(self.max_pairs if max_pairs is None else max_pairs)
         o.timer = timer
@@ -222,8 +229,8 @@ class Rasterizer:
         return keys[:k], vals[:k], ranges[: 2 * T * N.GS_MAX_PHASES].view(N.GS_MAX_PHASES, T, 2)
 
     def forward_stats(self, ctx: ForwardContext, stream=None):
-        """(K pairs, E walked list entries, list entries reached, non-empty tiles) of a forward."""
-        st = (ctypes.c_int64 * 4)()
+        """(K pairs, E walked list entries, list entries reached, non-empty tiles, blended evaluations)."""
+        st = (ctypes.c_int64 * 5)()
         o = self.config.to_c(ctx.max_pairs)
         N.check("gs_forward_stats", N.lib().gs_forward_stats(ctypes.byref(o), ctx.n, self.n_views, self.host_cams,
                                                              _ptr(ctx.saved), ctx.saved.numel(), st,

@@ -153,3 +153,111 @@ class TrainStep:
             self.destroy_graph()
         except Exception:
             pass
+
+
+class RenderStep:
+    """Forward + L1 loss + backward over a fixed camera list with every buffer allocated once.
+
+    Parameters are taken as given (activated scales and opacities); gradients land in
+    `self.grads` and `self.grad_medium` (overwritten each step, summed over the views
+    inside the library).  Graph-capturable like TrainStep.  Used by the autotuner and to
+    time a batch of views rendered by one pipeline against one pipeline per view.
+    """
+
+    def __init__(self, params: dict, sh_degree: int, cameras: Sequence, medium: torch.Tensor, targets: torch.Tensor,
+                 config: RasterConfig = RasterConfig(), max_pairs: Optional[int] = None,
+                 grad_medium: Optional[torch.Tensor] = None, device="cuda"):
+        dev = torch.device(device)
+        self.device = dev
+        self.p = params
+        self.n = int(params["means"].shape[-1])
+        self.sh_degree = int(sh_degree)
+        self.rast = Rasterizer(cameras, config, device=dev)
+        self.medium = medium
+        P = self.rast.total_pixels
+        self.target = targets.reshape(-1)
+        if self.target.numel() != 3 * P:
+            raise ValueError("targets must hold 3 * total pixels values")
+        self.rgb = torch.empty(3 * P, dtype=torch.float32, device=dev)
+        self.depth = torch.empty(P, dtype=torch.float32, device=dev)
+        self.alpha = torch.empty(P, dtype=torch.float32, device=dev)
+        self.grad_rgb = torch.empty(3 * P, dtype=torch.float32, device=dev)
+        self.loss = torch.empty(1, dtype=torch.float32, device=dev)
+        self.grads = {k: torch.empty_like(params[k]) for k in ("means", "scales", "quats", "opacity", "sh")}
+        self.grad_medium = torch.empty(self.rast.n_views * 9, dtype=torch.float32, device=dev) \
+            if grad_medium is None else grad_medium
+        self.graph = None
+        self._gauss = N.GsGaussians(self.n, self.sh_degree, 0, *(_vp(params[k]) for k in
+                                                                 ("means", "scales", "quats", "opacity", "sh")))
+        self._grads = N.GsGaussianGrads(*(_vp(self.grads[k]) for k in ("means", "scales", "quats", "opacity", "sh")))
+        self.set_capacity(max_pairs if max_pairs is not None else config.max_pairs)
+
+    def set_capacity(self, max_pairs: int) -> None:
+        self.destroy_graph()
+        self.max_pairs = int(max_pairs)
+        self.opts = self.rast.config.to_c(self.max_pairs)
+        ws, sv = self.rast.sizes_for(self.n, self.max_pairs)
+        self.ws = torch.empty(max(ws, 256), dtype=torch.uint8, device=self.device)
+        self.saved = torch.empty(max(sv, 256), dtype=torch.uint8, device=self.device)
+
+    def size_capacity(self, headroom: float = 1.25) -> int:
+        s = torch.cuda.current_stream(self.device)
+        while True:
+            self._forward(s)
+            st, need = self.rast.read_status(self.saved, s)
+            if st & N.GS_STATUS_PAIR_OVERFLOW:
+                self.set_capacity(min(N.GS_MAX_PAIRS, int(need * headroom) + 4096))
+                continue
+            break
+        want = min(N.GS_MAX_PAIRS, int(need * headroom) + 4096)
+        if want > self.max_pairs:
+            self.set_capacity(want)
+        return need
+
+    def _forward(self, stream) -> None:
+        N.check("gs_render_forward", N.lib().gs_render_forward(
+            ctypes.byref(self.opts), ctypes.byref(self._gauss), self.rast.n_views, self.rast.host_cams,
+            _vp(self.rast.dev_cams), _vp(self.medium), _vp(self.rgb), _vp(self.depth), _vp(self.alpha),
+            _vp(self.saved), self.saved.numel(), _vp(self.ws), self.ws.numel(), ctypes.c_void_p(stream.cuda_stream)))
+
+    def enqueue(self, stream=None) -> None:
+        stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        sp = ctypes.c_void_p(stream.cuda_stream)
+        L = N.lib()
+        self._forward(stream)
+        N.check("gs_l1_loss", L.gs_l1_loss(self.rgb.numel(), _vp(self.rgb), _vp(self.target), _vp(self.loss),
+                                           _vp(self.grad_rgb), sp))
+        N.check("gs_render_backward", L.gs_render_backward(
+            ctypes.byref(self.opts), ctypes.byref(self._gauss), self.rast.n_views, self.rast.host_cams,
+            _vp(self.rast.dev_cams), _vp(self.medium), _vp(self.grad_rgb), None, _vp(self.saved),
+            self.saved.numel(), ctypes.byref(self._grads), _vp(self.grad_medium), _vp(self.ws), self.ws.numel(),
+            sp))
+
+    def capture(self, stream: torch.cuda.Stream) -> None:
+        self.destroy_graph()
+        sp = ctypes.c_void_p(stream.cuda_stream)
+        g = ctypes.c_void_p()
+        N.check("gs_graph_begin", N.lib().gs_graph_begin(sp))
+        try:
+            self.enqueue(stream)
+        finally:
+            rc = N.lib().gs_graph_end(sp, ctypes.byref(g))
+        N.check("gs_graph_end", rc)
+        self.graph = g
+
+    def replay(self, stream: torch.cuda.Stream) -> None:
+        N.check("gs_graph_launch", N.lib().gs_graph_launch(self.graph, ctypes.c_void_p(stream.cuda_stream)))
+
+    def destroy_graph(self) -> None:
+        if getattr(self, "graph", None) is not None:
+            N.lib().gs_graph_destroy(self.graph)
+            self.graph = None
+
+    def status(self, stream=None):
+        return self.rast.read_status(self.saved, stream)
+
+    def __del__(self):
+        try:
+            self.destroy_graph()
+        except Exception:
+            pass

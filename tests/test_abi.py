@@ -71,13 +71,18 @@ def test_workspace_query_and_tile_count():
     o.tile_w = o.tile_h = 8
     o.lds_batch = 64
     assert N.lib().gs_tile_count(ctypes.byref(o), 3, cams) == 12 * 8 + 17 * 10 + 8 * 8
+    o.pixels_per_lane = 2                                   # 8x8 tiles take one pixel per lane only
+    assert N.lib().gs_workspace_query(ctypes.byref(o), 1000, 3, cams, ctypes.byref(ws), ctypes.byref(sv)) == \
+        N.GS_ERR_INVALID_ARGUMENT
 
 
 @pytest.mark.parametrize("field,value,code", [
     ("tile_w", 12, N.GS_ERR_INVALID_ARGUMENT), ("tile_w", 32, N.GS_ERR_UNSUPPORTED),
     ("lds_batch", 100, N.GS_ERR_INVALID_ARGUMENT), ("alpha_max", 1.5, N.GS_ERR_INVALID_ARGUMENT),
     ("depth_mode", 3, N.GS_ERR_INVALID_ARGUMENT), ("max_pairs", -1, N.GS_ERR_INVALID_ARGUMENT),
-    ("max_pairs", 5_000_000_000, N.GS_ERR_INVALID_ARGUMENT)])
+    ("max_pairs", 5_000_000_000, N.GS_ERR_INVALID_ARGUMENT), ("pixels_per_lane", 3, N.GS_ERR_INVALID_ARGUMENT),
+    ("pixels_per_lane", 8, N.GS_ERR_INVALID_ARGUMENT), ("record_fetch", 3, N.GS_ERR_INVALID_ARGUMENT),
+    ("record_fetch", -1, N.GS_ERR_INVALID_ARGUMENT)])
 def test_bad_options_rejected(field, value, code):
     sc = synth.make_scene(0, n=10)
     cams = N.camera_array(sc.cameras)

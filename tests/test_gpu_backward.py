@@ -57,7 +57,13 @@ def test_grad_vs_oracle_sh_degree0_config0(oracle_mod):
     _check_all(got, O.backward(sc, cam, sc.medium[0], G))
 
 
-@pytest.mark.parametrize("cfg", [dict(lds_batch=64), dict(persistent=True), dict(tile=8, lds_batch=64)])
+@pytest.mark.parametrize("cfg", [dict(lds_batch=64), dict(persistent=True), dict(tile=8, lds_batch=64),
+                                 dict(pixels_per_lane=1), dict(pixels_per_lane=4),
+                                 dict(pixels_per_lane=1, persistent=True, lds_batch=64),
+                                 dict(record_fetch="scalar", pixels_per_lane=1),
+                                 dict(record_fetch="scalar", pixels_per_lane=2, persistent=True),
+                                 dict(record_fetch="scalar", pixels_per_lane=4),
+                                 dict(tile=8, lds_batch=64, record_fetch="scalar", persistent=True)])
 def test_grad_launch_variants(oracle_mod, cfg):
     O = oracle_mod
     sc = synth.make_scene(1, n=3000, width=96, height=64)

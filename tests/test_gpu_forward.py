@@ -32,7 +32,7 @@ def _keys_match(scene, rast, O, opts=None):
 def test_keys_bitexact_config0(oracle_mod):
     sc = synth.make_scene(0)
     U.say("keys config0")
-    K = _keys_match(sc, U.make_rast(sc, phases=1), oracle_mod)
+    K = _keys_match(sc, U.make_rast(sc, phases=1, tile_cull=False), oracle_mod)
     assert K > 1000
 
 
@@ -40,14 +40,15 @@ def test_keys_bitexact_config0(oracle_mod):
 def test_keys_bitexact_config1_small(oracle_mod, tile):
     sc = synth.make_scene(1, n=20000, width=203, height=141)
     U.say(f"keys config1 small tile {tile}")
-    K = _keys_match(sc, U.make_rast(sc, tile=tile, lds_batch=64 if tile == 8 else 256, phases=1), oracle_mod)
+    K = _keys_match(sc, U.make_rast(sc, tile=tile, lds_batch=64 if tile == 8 else 256, phases=1, tile_cull=False),
+                    oracle_mod)
     assert K > 20000
 
 
 def test_keys_bitexact_multiview(oracle_mod):
     sc = synth.make_scene(3, n=5000, n_views=3, view_sizes=[(96, 64), (130, 77), (64, 64)])
     U.say("keys multiview")
-    _keys_match(sc, U.make_rast(sc, phases=1), oracle_mod)
+    _keys_match(sc, U.make_rast(sc, phases=1, tile_cull=False), oracle_mod)
 
 
 @pytest.mark.parametrize("phases", [2, 3, 4])
@@ -57,7 +58,7 @@ def test_phased_lists_are_exact_prefixes(oracle_mod, phases):
     O = oracle_mod
     sc = synth.make_scene(1, n=20000, width=203, height=141)
     U.say(f"phased prefixes {phases}")
-    rast = U.make_rast(sc, phases=phases)
+    rast = U.make_rast(sc, phases=phases, tile_cull=False)
     rgb, depth, alpha, ctx, _ = U.forward(sc, rast)
     k, v, ranges = rast.export_keys(ctx)
     k = k.cpu().numpy().view(np.uint64)
@@ -79,6 +80,78 @@ def test_phased_lists_are_exact_prefixes(oracle_mod, phases):
     full = U.forward(sc, U.make_rast(sc, phases=1))[:3]
     for a, b in zip((rgb, depth, alpha), full):
         assert torch.equal(a, b)
+
+
+def _tile_max_alpha(O, scene, cam, tiles, gauss, tile_w):
+    """FP64 maximum over the pixel centres of each tile of alpha = o exp(-q/2) of the paired Gaussian."""
+    pr = O.project(scene, cam)
+    tx_n = -(-cam.width // tile_w)
+    out = np.zeros(tiles.size)
+    off = np.arange(tile_w) + 0.5
+    for s0 in range(0, tiles.size, 4096):
+        t = tiles[s0:s0 + 4096]
+        g = gauss[s0:s0 + 4096]
+        px = (t % tx_n)[:, None] * tile_w + off[None, :]          # (m, tile_w) pixel-centre columns
+        py = (t // tx_n)[:, None] * tile_w + off[None, :]
+        vx = px < cam.width
+        vy = py < cam.height
+        dx = px - pr["mean2d"][g, 0][:, None]
+        dy = py - pr["mean2d"][g, 1][:, None]
+        a, b, c = (pr["conic"][g, i][:, None, None] for i in range(3))
+        q = a * dx[:, None, :] ** 2 + 2 * b * dx[:, None, :] * dy[:, :, None] + c * dy[:, :, None] ** 2
+        al = scene.opacity[g].astype(np.float64)[:, None, None] * np.exp(-0.5 * q)
+        al = np.where(vy[:, :, None] & vx[:, None, :], al, 0.0)
+        out[s0:s0 + 4096] = al.reshape(al.shape[0], -1).max(axis=1)
+    return out
+
+
+@pytest.mark.parametrize("tile", [16, 8])
+def test_tile_cull_drops_only_non_contributing_pairs(oracle_mod, tile):
+    """With exact tile culling each tile keeps a subsequence of the oracle's (rectangle) list; every
+    dropped pair has alpha < alpha_min at all of the tile's pixel centres (FP64), few kept pairs
+    could have been dropped, and the images equal those without culling bit for bit."""
+    O = oracle_mod
+    sc = synth.make_scene(1, n=20000, width=203, height=141)
+    cam = sc.cameras[0]
+    U.say(f"tile cull tile {tile}")
+    lb = 64 if tile == 8 else 256
+    rast = U.make_rast(sc, tile=tile, lds_batch=lb, phases=1, tile_cull=True)
+    rgb, depth, alpha, ctx, _ = U.forward(sc, rast)
+    k, v, ranges = rast.export_keys(ctx)
+    k = k.cpu().numpy().view(np.uint64)
+    v = v.cpu().numpy().view(np.uint32).astype(np.int64)
+    ranges = ranges[0].cpu().numpy().astype(np.int64)
+    ok, ov, counts = O.keys(sc, opts=O.Options(tile_w=tile, tile_h=tile))
+    starts = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    dropped_t, dropped_g, kept_t, kept_g = [], [], [], []
+    for t in np.nonzero(counts)[0]:
+        full_k = ok[starts[t]: starts[t] + counts[t]]
+        full_v = ov[starts[t]: starts[t] + counts[t]].astype(np.int64)
+        a, b = ranges[t]
+        gk, gv = k[a:b], v[a:b]
+        # subsequence in the same order: keys are unique per (tile, depth, index) after the value
+        mask = np.isin(full_v, gv)
+        np.testing.assert_array_equal(full_v[mask], gv)
+        np.testing.assert_array_equal(full_k[mask], gk)
+        dropped_t.append(np.full(int((~mask).sum()), t))
+        dropped_g.append(full_v[~mask])
+        kept_t.append(np.full(gv.size, t))
+        kept_g.append(gv)
+    dt, dg = np.concatenate(dropped_t), np.concatenate(dropped_g)
+    kt, kg = np.concatenate(kept_t), np.concatenate(kept_g)
+    assert dt.size > 0.1 * ok.size, "culling should drop a sizeable share of the rectangle pairs"
+    amin = 1.0 / 255.0
+    dmax = _tile_max_alpha(O, sc, cam, dt, dg, tile)
+    assert np.all(dmax < amin), (dmax.max(), amin)
+    kmax = _tile_max_alpha(O, sc, cam, kt, kg, tile)
+    loose = int(np.sum(kmax < amin))
+    U.say(f"  rectangle pairs {ok.size}, kept {kt.size}, dropped {dt.size}, kept but below alpha_min {loose}")
+    assert loose <= 0.01 * kt.size
+    for phases in (1, 3):
+        ref = U.forward(sc, U.make_rast(sc, tile=tile, lds_batch=lb, phases=phases, tile_cull=False))[:3]
+        got = U.forward(sc, U.make_rast(sc, tile=tile, lds_batch=lb, phases=phases, tile_cull=True))[:3]
+        for x, y in zip(got, ref):
+            assert torch.equal(x, y)
 
 
 def _image_match(scene, rast, O, opts=None, v=0):
@@ -122,10 +195,18 @@ def test_image_multiview(oracle_mod):
 
 
 @pytest.mark.parametrize("cfg", [dict(lds_batch=64), dict(lds_batch=128), dict(persistent=True),
-                                 dict(tile=8, lds_batch=64), dict(tile=8, lds_batch=64, persistent=True)])
+                                 dict(pixels_per_lane=1), dict(pixels_per_lane=4, lds_batch=64),
+                                 dict(pixels_per_lane=1, persistent=True, lds_batch=128),
+                                 dict(pixels_per_lane=4, persistent=True),
+                                 dict(record_fetch="scalar", pixels_per_lane=1),
+                                 dict(record_fetch="scalar", pixels_per_lane=2),
+                                 dict(record_fetch="scalar", pixels_per_lane=4, persistent=True),
+                                 dict(record_fetch="scalar", pixels_per_lane=1, persistent=True),
+                                 dict(tile=8, lds_batch=64), dict(tile=8, lds_batch=64, persistent=True),
+                                 dict(tile=8, lds_batch=64, record_fetch="scalar")])
 def test_launch_variants_bitwise_equal(cfg):
-    """Every tile shape / batch / persistent variant walks each pixel's Gaussians in the same
-    order with the same operations, so the images are bitwise identical."""
+    """Every tile shape / split / batch / record fetch / persistent variant walks each pixel's
+    Gaussians in the same order with the same operations, so the images are bitwise identical."""
     sc = synth.make_scene(1, n=20000, width=203, height=141)
     U.say(f"variant {cfg}")
     base = U.forward(sc, U.make_rast(sc))[:3]

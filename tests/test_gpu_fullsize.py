@@ -1,0 +1,103 @@
+"""Parity at the full size of the 1M-Gaussian 1920x1080 workload, in the launch configuration
+the benchmark times: sampled pixels of the image against the FP64 oracle, and gradients of a
+loss on a 64x64 crop for 200 sampled Gaussians against the oracle's exact gradient and FP64
+central differences."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2411_19588_amd import rasterizer as R
+from paper_2411_19588_amd import synth
+from tests import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("means", "scales", "quats", "opacity", "sh")
+CROP = (912, 500, 64, 64)          # x0, y0, width, height
+
+
+@pytest.fixture(scope="module")
+def scene():
+    return synth.make_scene(2)
+
+
+def _bench_rast(sc):
+    return R.Rasterizer(sc.cameras, R.RasterConfig())    # the benchmark's default launch configuration
+
+
+def test_image_full_size_sampled(oracle_mod, scene):
+    O = oracle_mod
+    sc = scene
+    cam = sc.cameras[0]
+    rast = _bench_rast(sc)
+    rgb, depth, alpha, ctx, _ = U.forward(sc, rast)
+    st, _ = rast.read_status(ctx.saved)
+    assert st == 0
+    rng = np.random.default_rng(11)
+    pix = np.stack([rng.integers(0, cam.width, 6000), rng.integers(0, cam.height, 6000)], 1)
+    # plus the ragged last tile row and the frame corners
+    edge = np.stack([rng.integers(0, cam.width, 500), rng.integers(cam.height - 8, cam.height, 500)], 1)
+    corners = np.array([[0, 0], [cam.width - 1, 0], [0, cam.height - 1], [cam.width - 1, cam.height - 1]])
+    pix = np.ascontiguousarray(np.concatenate([pix, edge, corners]).astype(np.int32))
+    U.say(f"full-size image, {len(pix)} sampled pixels")
+    orc = O.render(sc, cam, sc.medium[0], pixels=pix, variants=4)
+    n_main, n_var, worst = U.compare_pixels(*U.gather_view(rgb, depth, alpha, rast, 0, pix), orc)
+    U.say(f"  main {n_main} variant {n_var} worst {worst:.2e}")
+
+
+def _crop_pixels():
+    x0, y0, w, h = CROP
+    ys, xs = np.meshgrid(np.arange(y0, y0 + h), np.arange(x0, x0 + w), indexing="ij")
+    return np.ascontiguousarray(np.stack([xs.ravel(), ys.ravel()], 1).astype(np.int32))
+
+
+def test_grad_full_size_crop(oracle_mod, scene):
+    O = oracle_mod
+    sc = scene
+    cam = sc.cameras[0]
+    pix = _crop_pixels()
+    rng = np.random.default_rng(12)
+    Gc = rng.normal(size=(len(pix), 3))
+    amb = O.render(sc, cam, sc.medium[0], pixels=pix, variants=1)["nvar"] > 0
+    Gc[amb] = 0.0
+    U.say(f"full-size crop gradient, ambiguous crop pixels {int(amb.sum())}")
+    # GPU: full-frame upstream gradient, zero outside the crop
+    G = np.zeros((cam.height, cam.width, 3))
+    G[pix[:, 1], pix[:, 0]] = Gc
+    rast = _bench_rast(sc)
+    rgb, depth, alpha, ctx, d = U.forward(sc, rast)
+    g_rgb = torch.from_numpy(np.ascontiguousarray(G.transpose(2, 0, 1)).astype(np.float32)).reshape(-1).cuda()
+    out = rast.backward(ctx, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["medium"], g_rgb, None)
+    torch.cuda.synchronize()
+    got = dict(zip(FIELDS + ("medium",), [t.cpu().numpy().astype(np.float64) for t in out]))
+    ref = O.backward(sc, cam, sc.medium[0], Gc, pixels=pix)
+    # 200 sampled Gaussians: every Gaussian that reaches the crop (about 100-150: the large
+    # near Gaussians saturate it), the rest drawn from those that do not (exact zeros)
+    live = np.nonzero(np.abs(ref["g2d"]).sum(axis=1) > 0)[0]
+    assert live.size >= 50, live.size
+    if live.size >= 200:
+        pick = np.sort(rng.choice(live, 200, replace=False))
+    else:
+        rest = rng.choice(np.setdiff1d(np.arange(sc.n), live), 200 - live.size, replace=False)
+        pick = np.sort(np.concatenate([live, rest]))
+    U.say(f"  {live.size} Gaussians reach the crop; checking 200")
+    for f in FIELDS:
+        U.grad_close(got[f][..., pick], ref[f][..., pick], 1e-3, f)
+    U.grad_close(got["medium"].reshape(-1), ref["medium"], 1e-3, "medium")
+    # Gaussians outside the crop's lists get exactly zero
+    dead = np.setdiff1d(np.arange(sc.n), live)[:5000]
+    assert np.all(got["opacity"][dead] == 0.0)
+    # FP64 central differences of the oracle forward for a few of the sampled Gaussians
+    med = sc.medium[0].astype(np.float64)
+    order = pick[np.argsort(-np.abs(ref["opacity"][pick]))][:5]
+    checked = 0
+    for g in order:
+        for f, idx in (("opacity", (g,)), ("means", (0, g)), ("sh", (0, g))):
+            fd, ok = O.fd_grad(sc, cam, med, Gc, f, idx, pixels=pix)
+            if not ok:
+                continue
+            scale = np.sqrt(np.mean(ref[f][..., pick] ** 2))
+            assert abs(got[f][idx] - fd) <= 1e-3 * abs(fd) + 1e-3 * scale, (f, idx, got[f][idx], fd)
+            checked += 1
+    U.say(f"  finite differences checked {checked}")
+    assert checked >= 8

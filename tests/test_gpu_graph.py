@@ -19,7 +19,8 @@ def _make(sc, lr_scale=0.0, **cfg):
                      sc.sh_degree, sc.cameras, tgt, R.RasterConfig(**cfg), lr=lr)
 
 
-@pytest.mark.parametrize("cfg", [dict(), dict(persistent=True), dict(phases=1)])
+@pytest.mark.parametrize("cfg", [dict(), dict(persistent=True), dict(phases=1),
+                                 dict(record_fetch="scalar", pixels_per_lane=1, persistent=True)])
 def test_graph_replay_matches_eager(cfg):
     sc = synth.make_scene(1, n=20000, width=203, height=141)
     ts = _make(sc, **cfg)
@@ -46,9 +47,10 @@ def test_graph_replay_matches_eager(cfg):
             assert torch.equal(ts.rgb, ref_rgb), rep
             assert torch.allclose(ts.loss, ref_loss, rtol=1e-5, atol=0), rep
             # gradients are accumulated with float atomics whose order varies between runs
-            # (persistent waves visit tiles in a different order): same bar as oracle parity
+            # (waves reach a Gaussian in a different order): each run is within the 1e-3 parity
+            # bar of the exact gradient, so two runs agree within twice that bar
             for g in ts.groups:
-                U.grad_close(g.grad.cpu().numpy(), ref_grads[g.name].cpu().numpy(), 1e-3, g.name)
+                U.grad_close(g.grad.cpu().numpy(), ref_grads[g.name].cpu().numpy(), 2e-3, g.name)
     assert int(ts.step_counter.item()) == 4
     st, _ = ts.status(stream)
     assert st == 0
