@@ -12,9 +12,9 @@ library:
                -> per-tile compositing with the medium and depth epilogue
     loss     : L1 loss value and gradient
     backward : per-tile adjoint -> medium reduction -> projection adjoint
-    update   : fused Adam over all Gaussian and medium parameters whose epilogue
-               applies the activations (exp scales, sigmoid opacity) that the
-               next step's forward consumes.
+    update   : Adam over every Gaussian and medium parameter group in one
+               launch, whose epilogue applies the activations (exp scales,
+               sigmoid opacity) that the next step's forward consumes.
 Inputs are resident in HBM before the timed region.  `value` = rendered pixels
 per second of such steps (Mpix/s).
 
@@ -58,11 +58,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=2, help="synthetic workload (2: 1M Gaussians, 1920x1080)")
+    ap.add_argument("--config", type=int, default=2,
+                    help="synthetic workload (2: 1M Gaussians, 1920x1080; 4: 3M Gaussians, 4 views at 1920x1080)")
     ap.add_argument("--tile", type=int, default=16)
-    ap.add_argument("--lds-batch", type=int, default=256)
+    ap.add_argument("--lds-batch", type=int, default=64)
     ap.add_argument("--persistent", action="store_true")
     ap.add_argument("--no-tile-cull", action="store_true", help="bin every tile of each rectangle")
+    ap.add_argument("--fused-adam", action="store_true",
+                    help="run the Adam step inside the projection adjoint (default: the adjoint writes the "
+                         "gradients and the separate Adam kernel updates the parameters)")
     ap.add_argument("--ppl", type=int, default=0, help="pixels per lane in compositing (0 = library default)")
     ap.add_argument("--fetch", choices=["default", "lds", "scalar"], default="default",
                     help="how compositing waves receive the records")
@@ -80,7 +84,8 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_bytes(name: str, n: int, views: int, K: int, P: int, tiles: int, ncoef: int, per_step: int = 1):
+def kernel_bytes(name: str, n: int, views: int, K: int, P: int, tiles: int, ncoef: int, per_step: int = 1,
+                 fused: bool = False):
     """Algorithmic HBM bytes one launch of `name` must move (reads + writes), averaged over the
     `per_step` launches a step makes of it.
 
@@ -103,7 +108,9 @@ def kernel_bytes(name: str, n: int, views: int, K: int, P: int, tiles: int, ncoe
         # outputs + saved state per pixel; the gathered records of traversed pairs are cache-resident
         "composite_fwd": (P * (12 + 4 + 4) + P * 29 + tiles * 8) / per_step,
         "composite_bwd": P * (12 + 28) + NV * 40 + tiles * 36,
-        "project_bwd": param + NV * 40 + param,
+        # parameters and 2D gradients read, gradients written (with the Adam step fused in:
+        # moments read and parameters and moments written instead of the gradients)
+        "project_bwd": (param + NV * 40 + param) if not fused else (3 * param + NV * 40 + 3 * param + n * 16),
         "zero_grad2d": NV * 40,
         "medium_reduce": tiles * 36,
     }
@@ -289,16 +296,16 @@ def main():
         return
     log(f"building scene (config {args.config})")
     sc = synth.make_scene(args.config)
-    if sc.n_views != 1:
-        raise SystemExit("the timed workload is a single-view configuration")
     cam = sc.cameras[0]
-    P = cam.width * cam.height
+    P = sum(c.width * c.height for c in sc.cameras)
+    sizes = sorted({(c.width, c.height) for c in sc.cameras})
     ncoef = (sc.sh_degree + 1) ** 2
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a))
     cfg = R.RasterConfig(tile=args.tile, lds_batch=args.lds_batch, persistent=args.persistent, phases=args.phases,
                          pixels_per_lane=args.ppl, record_fetch=args.fetch, tile_cull=not args.no_tile_cull)
     ts = TrainStep(t(sc.means), t(sc.log_scales), t(sc.quats), t(sc.logits), t(sc.sh), t(sc.medium), sc.sh_degree,
-                   sc.cameras, t(sc.targets[0]), cfg, device=dev)
+                   sc.cameras, torch.cat([t(x).reshape(-1) for x in sc.targets]), cfg, device=dev,
+                   fused=args.fused_adam)
     log("sizing the pair list")
     need = ts.size_capacity(1.25)
     log(f"stored pairs {need}, capacity {ts.max_pairs}")
@@ -369,7 +376,7 @@ def main():
                 kv["alg_flops"] = f / max(1, per_step)
                 kv["tflops"] = f / (kv["ms_total"] / args.steps * 1e-3) / 1e12
                 continue
-            b = kernel_bytes(nm, sc.n, 1, K_live, P, tiles, ncoef, per_step)
+            b = kernel_bytes(nm, sc.n, sc.n_views, K_live, P, tiles, ncoef, per_step, args.fused_adam)
             if b is not None:
                 kv["alg_bytes"] = b
                 kv["gbs"] = b / (kv["ms_avg"] * 1e-3) / 1e9
@@ -414,16 +421,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{sc.n} Gaussians SH{sc.sh_degree}, {cam.width}x{cam.height}, 1 view, "
+        "config": {"workload": f"{sc.n} Gaussians SH{sc.sh_degree}, "
+                               f"{' + '.join(f'{w}x{h}' for w, h in sizes)}, {sc.n_views} view(s), "
                                "training step (forward + L1 + backward + fused Adam)",
                    "n_gaussians": sc.n, "sh_degree": sc.sh_degree, "width": cam.width, "height": cam.height,
-                   "views": 1, "tile": args.tile, "lds_batch": args.lds_batch, "persistent": bool(args.persistent),
+                   "views": sc.n_views, "tile": args.tile, "lds_batch": args.lds_batch, "persistent": bool(args.persistent),
                    "pixels_per_lane": args.ppl, "record_fetch": args.fetch,
                    "phases": cfg.phases, "mode": "eager" if args.eager else "hip_graph",
                    "pairs_stored": int(K), "pairs_full_binning": int(K_full),
                    "pairs_per_gaussian": round(K_full / sc.n, 2), "pairs_live": int(stats[0]),
                    "evals_per_pixel": round(stats[1] / P, 1), "blends_per_pixel": round(stats[4] / P, 1),
-                   "tile_cull": bool(cfg.tile_cull)},
+                   "tile_cull": bool(cfg.tile_cull), "adam": "fused" if args.fused_adam else "separate"},
         "eager_ms_per_step": round(eager_ms, 4),
         "roofline": roof,
         "cpu_baseline": cpu,

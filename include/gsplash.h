@@ -108,14 +108,16 @@ typedef struct gs_gaussian_grads {
 
 typedef struct gs_options {
     int32_t tile_w, tile_h;              /* 16x16 (default) or 8x8 pixels per tile */
-    int32_t lds_batch;                   /* records staged in LDS per batch: 64, 128 or 256 (<= tile pixels) */
+    int32_t lds_batch;                   /* records staged in LDS per batch: 64 (default), 128 or 256 */
     int32_t persistent;                  /* 0: one workgroup per tile; 1: persistent workgroups pull tiles from a queue */
     int32_t pixels_per_lane;             /* 16x16 tiles: pixels each lane blends, 1 (four waves per tile, 8x8
                                             each), 2 (two waves, 16x8 each) or 4 (one wave); 8x8 tiles: 1;
-                                            0 = library default.  Images are identical for every value. */
+                                            0 = per-pass default (forward 2, backward 4).  Images are
+                                            identical for every value. */
     int32_t record_fetch;                /* GS_FETCH_LDS: the workgroup stages batches of records in LDS;
                                             GS_FETCH_SCALAR: each wave loads records through the scalar cache
-                                            (lds_batch is then unused); GS_FETCH_DEFAULT (0) = library default */
+                                            (lds_batch is then unused); GS_FETCH_DEFAULT (0) = per-pass
+                                            default (forward LDS, backward scalar) */
     float alpha_min;                     /* 1/255: a Gaussian with alpha < alpha_min is skipped at that pixel */
     float alpha_max;                     /* 0.99: alpha = min(alpha_max, o exp(-q/2)) */
     float t_min;                         /* 1e-4: stop before blending a Gaussian that would leave T < t_min */
@@ -252,6 +254,28 @@ typedef struct gs_adam_group {
                                             activated value of the current param on entry. */
     int32_t reserved;
 } gs_adam_group;
+
+/* Training-step adjoint with the optimizer fused into the projection adjoint
+ * (Sec. Optimization): the adjoint of gs_render_backward, but instead of writing
+ * the parameter gradients it applies one Adam step -- as gs_adam_step_device,
+ * same step counter semantics -- to the raw parameters in registers, so the
+ * gradients of the Gaussians never reach memory.
+ *   groups[6] : HOST array, in this order: means (count 3n, activation 0),
+ *               log-scales (3n, activation 1, activated = the scales g->scales
+ *               points to), quaternions (4n, 0), opacity logits (n, activation 2,
+ *               activated = g->opacity), SH ((deg+1)^2 * 3 * n, 0), medium
+ *               (9 * n_views, 0, param = dev_medium).  g->means, g->quats, g->sh
+ *               must be the groups' params.  Each group's `grad`
+ *               is ignored except the medium group's, which receives the medium
+ *               gradient [n_views][9].
+ *   step_counter : DEVICE int32, incremented first; the incremented value is t.
+ * Only the m, v, param and activated arrays are written (plus workspace).
+ * Returns GS_ERR_INVALID_ARGUMENT on any mismatch; otherwise as gs_render_backward. */
+int gs_render_backward_adam(const gs_options* opts, const gs_gaussians* g, int32_t n_views,
+                            const gs_camera* host_cams, const gs_camera* dev_cams, const gs_medium* dev_medium,
+                            const float* grad_rgb, const float* grad_depth, const void* saved, size_t saved_bytes,
+                            const gs_adam_group* groups, float beta1, float beta2, float eps, int32_t* step_counter,
+                            void* workspace, size_t workspace_bytes, gs_stream_t stream);
 
 /* Fused Adam update (beta1, beta2, eps, bias correction at `step` >= 1) over
  * up to 8 groups in one launch. */

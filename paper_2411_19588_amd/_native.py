@@ -83,6 +83,10 @@ PROTOTYPES = {
     "gs_render_backward": (ctypes.c_int, [ctypes.POINTER(GsOptions), ctypes.POINTER(GsGaussians), _I32,
                                           ctypes.POINTER(GsCamera), _P, _P, _P, _P, _P, _SZ,
                                           ctypes.POINTER(GsGaussianGrads), _P, _P, _SZ, _P]),
+    "gs_render_backward_adam": (ctypes.c_int, [ctypes.POINTER(GsOptions), ctypes.POINTER(GsGaussians), _I32,
+                                               ctypes.POINTER(GsCamera), _P, _P, _P, _P, _P, _SZ,
+                                               ctypes.POINTER(GsAdamGroup), ctypes.c_float, ctypes.c_float,
+                                               ctypes.c_float, _P, _P, _SZ, _P]),
     "gs_read_status": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_I64), _P]),
     "gs_export_keys": (ctypes.c_int, [ctypes.POINTER(GsOptions), _I64, _I32, ctypes.POINTER(GsCamera), _P, _SZ,
                                       _P, _P, _P, _I64, ctypes.POINTER(_I64), _P]),

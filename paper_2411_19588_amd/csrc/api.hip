@@ -128,6 +128,7 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     L->w_hist = w.take(((size_t)kRadix * parts + kRadix) * 4);   // + per-digit row totals
     L->w_grad2d = w.take(nv * kGrad2D * 4);
     L->w_medpart = w.take(T * 9 * 4 + 256);   // + persistent-mode tile counter of the backward
+    L->w_adam = w.take(16);                    // bias corrections of a fused Adam step
     L->workspace_bytes = w.at;
     return GS_OK;
 }
@@ -197,7 +198,7 @@ void gs_default_options(gs_options* o) {
     memset(o, 0, sizeof(*o));
     o->tile_w = 16;
     o->tile_h = 16;
-    o->lds_batch = 256;
+    o->lds_batch = 64;
     o->persistent = 0;
     o->pixels_per_lane = 0;
     o->record_fetch = GS_FETCH_DEFAULT;
@@ -304,7 +305,8 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
         int tb = 0;
         if (L.max_pairs > 0)
             GS_TRY(radix_sort_u32(tiles_a, vals_a, tiles_b, vals_b, &hdr->phase_count[ph], 0, 0, L.tile_bits,
-                                  L.pair_parts, hist, &tb, "tile_sort", T, s));
+                                  L.pair_parts, hist, &tb, "tile_sort", T, s, 1, (uint32_t)L.tiles,
+                                  &hdr->phase_live[ph]));
         timer_begin(T, "commit", s);
         GS_TRY(launch_commit(tb ? tiles_b : tiles_a, tb ? vals_b : vals_a, hdr, ph, L.tiles, L.max_pairs, vals,
                              ranges, s));
@@ -349,10 +351,75 @@ int gs_render_backward(const gs_options* opts, const gs_gaussians* g, int32_t n_
                                 at<float>(saved, L.s_dsum), at<float>(saved, L.s_wsum), grad2d, medpart, s));
     timer_end(T, s);
     timer_begin(T, "medium_reduce", s);
-    GS_TRY(launch_medium_reduce(vt, n_views, medpart, grad_medium, s));
+    GS_TRY(launch_medium_reduce(vt, n_views, medpart, grad_medium, nullptr, 0.f, 0.f, 0.f, nullptr, s));
     timer_end(T, s);
     timer_begin(T, "project_bwd", s);
-    GS_TRY(launch_project_bwd(*g, n_views, dev_cams, o, grad2d, *grads, s));
+    GS_TRY(launch_project_bwd(*g, n_views, dev_cams, o, grad2d, at<Record>(saved, L.s_records), *grads, s));
+    timer_end(T, s);
+    return GS_OK;
+}
+
+int gs_render_backward_adam(const gs_options* opts, const gs_gaussians* g, int32_t n_views,
+                            const gs_camera* host_cams, const gs_camera* dev_cams, const gs_medium* dev_medium,
+                            const float* grad_rgb, const float* grad_depth, const void* saved, size_t saved_bytes,
+                            const gs_adam_group* groups, float beta1, float beta2, float eps, int32_t* step_counter,
+                            void* workspace, size_t workspace_bytes, gs_stream_t stream) {
+    int rc = check_gaussians(g);
+    if (rc != GS_OK) return rc;
+    Layout L;
+    rc = compute_layout(opts, g->n, n_views, host_cams, &L);
+    if (rc != GS_OK) return rc;
+    if (!dev_cams || !dev_medium || !grad_rgb || !saved || !groups || !step_counter || !workspace)
+        return GS_ERR_INVALID_ARGUMENT;
+    if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f))
+        return GS_ERR_INVALID_ARGUMENT;
+    const int64_t n = g->n, nc = (int64_t)(g->sh_degree + 1) * (g->sh_degree + 1);
+    const int64_t counts[6] = {3 * n, 3 * n, 4 * n, n, 3 * nc * n, 9 * (int64_t)n_views};
+    const int32_t acts[6] = {0, 1, 0, 2, 0, 0};
+    for (int k = 0; k < 6; ++k) {
+        const gs_adam_group& G = groups[k];
+        if (G.count != counts[k] || G.activation != acts[k]) return GS_ERR_INVALID_ARGUMENT;
+        if (G.count > 0 && (!G.param || !G.m || !G.v || (acts[k] && !G.activated))) return GS_ERR_INVALID_ARGUMENT;
+    }
+    if (!groups[5].grad) return GS_ERR_INVALID_ARGUMENT;   // receives the medium gradient
+    // the Gaussian fields the forward read must be the activated copies the update refreshes
+    if (n > 0 && (g->means != groups[0].param || g->scales != groups[1].activated || g->quats != groups[2].param ||
+                  g->opacity != groups[3].activated || g->sh != groups[4].param))
+        return GS_ERR_INVALID_ARGUMENT;
+    if (dev_medium != reinterpret_cast<const gs_medium*>(groups[5].param)) return GS_ERR_INVALID_ARGUMENT;
+    if (saved_bytes < L.saved_bytes || workspace_bytes < L.workspace_bytes) return GS_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const gs_options& o = *opts;
+    void* T = o.timer;
+    const SavedHeader* hdr = at<SavedHeader>(saved, L.s_header);
+    const ViewInfo* vt = reinterpret_cast<const ViewInfo*>(hdr + 1);
+    float* grad2d = at<float>(workspace, L.w_grad2d);
+    float* medpart = at<float>(workspace, L.w_medpart);
+    float* bc = at<float>(workspace, L.w_adam);
+
+    GS_TRY(launch_adam_prep(step_counter, beta1, beta2, bc, s));
+    timer_begin(T, "zero_grad2d", s);
+    GS_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, L.nv * kGrad2D, s));
+    timer_end(T, s);
+    timer_begin(T, "composite_bwd", s);
+    GS_TRY(launch_composite_bwd(o, L, vt, dev_medium, at<Record>(saved, L.s_records), at<uint2>(saved, L.s_ranges),
+                                at<uint32_t>(saved, L.s_vals), grad_rgb, grad_depth, at<float>(saved, L.s_tfinal),
+                                at<uint32_t>(saved, L.s_nlast), at<float>(saved, L.s_cair),
+                                at<float>(saved, L.s_dsum), at<float>(saved, L.s_wsum), grad2d, medpart, s));
+    timer_end(T, s);
+    timer_begin(T, "medium_reduce", s);
+    GS_TRY(launch_medium_reduce(vt, n_views, medpart, const_cast<float*>(groups[5].grad), &groups[5], beta1, beta2,
+                                eps, bc, s));
+    timer_end(T, s);
+    AdamFused ad;
+    memset(&ad, 0, sizeof(ad));
+    for (int k = 0; k < 5; ++k) ad.g[k] = groups[k];
+    ad.b1 = beta1;
+    ad.b2 = beta2;
+    ad.eps = eps;
+    ad.bc = bc;
+    timer_begin(T, "project_bwd", s);
+    GS_TRY(launch_project_bwd_adam(*g, n_views, dev_cams, o, grad2d, at<Record>(saved, L.s_records), ad, s));
     timer_end(T, s);
     return GS_OK;
 }

@@ -78,6 +78,7 @@ __global__ void k_view_table(ViewTable t, ViewInfo* dst, SavedHeader* hdr) {
             hdr->phase_base[p] = 0;
             hdr->phase_count[p] = 0;
             hdr->phase_alive[p] = 0;
+            hdr->phase_live[p] = 0;
         }
     }
 }
@@ -256,6 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_rects(const uint32_t* __restric
     __shared__ uint32_t s_e[kEmitSpan + 1], s_base[kEmitSpan + 1], s_w[kEmitSpan + 1], s_tx[kEmitSpan + 1];
     __shared__ uint32_t s_xy[kEmitSpan + 1];
     __shared__ float s_iw[kEmitSpan + 1];
+    __shared__ uint16_t s_view[kEmitSpan + 1];    // culling: view of each entry of the span
     const uint64_t K = hdr->phase_count[phase];
     const uint64_t p0 = (uint64_t)blockIdx.x * kEmitSpan;
     if (K == 0 || p0 >= K) return;
@@ -280,6 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_rects(const uint32_t* __restric
             s_tx[i] = (uint32_t)vi.tiles_x;
             s_xy[i] = rc.x;
             s_iw[i] = 1.0f / (float)w;
+            s_view[i] = (uint16_t)(e / (uint64_t)n);
         }
         nent += __syncthreads_count(own);
     }
@@ -303,12 +306,13 @@ __global__ __launch_bounds__(kBlock) void k_emit_rects(const uint32_t* __restric
         const uint32_t e = s_e[lo];
         uint32_t tile = s_base[lo] + row * s_tx[lo] + col;
         if (cull.enabled) {
+            // the entry's record is read by every pair of its rectangle: cache hits after the first
             const Record* rp = cull.rec + e;
-            const float4 ra = rp->a;
-            const float2 rb = make_float2(rp->b.x, rp->b.y);
-            const ViewInfo vi = vt[e / (uint64_t)n];
+            const ViewInfo vi = vt[s_view[lo]];
             const uint32_t xy = s_xy[lo];
-            if (!tile_may_contribute(ra, rb, vi, (xy & 0xFFFFu) + col, (xy >> 16) + row, cull)) tile = n_tiles;
+            if (!tile_may_contribute(rp->a, make_float2(rp->b.x, rp->b.y), vi, (xy & 0xFFFFu) + col,
+                                     (xy >> 16) + row, cull))
+                tile = n_tiles;
         }
         tiles_out[p0 + q] = tile;
         vals_out[p0 + q] = e;
@@ -364,7 +368,7 @@ __global__ __launch_bounds__(kBlock) void k_commit(const uint32_t* __restrict__ 
                                                   const uint32_t* __restrict__ svals,
                                                   const SavedHeader* __restrict__ hdr, int phase, uint32_t n_tiles,
                                                   uint32_t* __restrict__ vals, uint2* __restrict__ ranges) {
-    const uint32_t K = hdr->phase_count[phase];
+    const uint32_t K = hdr->phase_live[phase];   // culled pairs were left out by the tile sort
     const uint32_t base = hdr->phase_base[phase];
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= K) return;

@@ -25,6 +25,8 @@
 // reduction on cross-lane swaps (v_permlane32_swap, v_permlane16_swap, DPP row
 // mirrors and quad permutes), and the waves of a workgroup add their sums in LDS
 // before one atomic add per term (scalar-fetch mode: one per wave).
+#include <string.h>
+
 #include "internal.h"
 
 namespace gs {
@@ -443,14 +445,16 @@ __global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_fwd
 }
 
 // Adjoint of the blend of one splat for a lane's pixels, walking back to front: adds the
-// lane's terms to g10 = d/d(m_x, m_y, A, B, C, o, r, g, b, depth).  Returns whether any of
-// the lane's pixels was reached by the splat with alpha >= alpha_min.
+// lane's terms to g10 = d/d(m_x, m_y, A, B, C, o, r, g, b, depth), the first five without
+// their common factor ln 2 (applied once to the wave's sums).  Returns whether any of the
+// lane's pixels was reached by the splat with alpha >= alpha_min.
 template <int PPL, int R>
 __device__ __forceinline__ bool blend_adjoint(const Splat& s, float fpx, float fpy0, uint32_t idx,
                                               const uint32_t* my_last, float* T, float* S, const float* gC0,
                                               const float* gC1, const float* gC2, const float* gD, const float* gW,
                                               float* g10, float amin, float amax) {
     const ColTerms ct = col_terms(s, fpx);
+    const float nA2 = -2.0f * s.A, nB = -s.B, nC2 = -2.0f * s.C;
     bool any = false;
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
@@ -465,26 +469,34 @@ __device__ __forceinline__ bool blend_adjoint(const Splat& s, float fpx, float f
         const float rom = __builtin_amdgcn_rcpf(1.0f - alpha);
         const float Ti = T[k] * rom;
         const float w = alpha * Ti;
-        const float gf = gC0[k] * s.r + gC1[k] * s.g + gC2[k] * s.b + gD[k] * s.d + gW[k];
-        const float dalpha = Ti * gf - S[k] * rom;
+        const float gf = fmaf(gC0[k], s.r, fmaf(gC1[k], s.g, fmaf(gC2[k], s.b, fmaf(gD[k], s.d, gW[k]))));
+        // a clamped alpha does not depend on the opacity or the exponent
+        const float dalpha = araw <= amax ? fmaf(Ti, gf, -S[k] * rom) : 0.0f;
         S[k] = fmaf(gf, w, S[k]);
         T[k] = Ti;
-        g10[6] += gC0[k] * w;
-        g10[7] += gC1[k] * w;
-        g10[8] += gC2[k] * w;
-        g10[9] += gD[k] * w;
-        if (araw <= amax) {
-            const float dx = ct.dx;
-            g10[5] += dalpha * ev;
-            const float dpw = dalpha * araw * kLn2;
-            g10[2] += dpw * dx * dx;
-            g10[3] += dpw * dx * dy;
-            g10[4] += dpw * dy * dy;
-            g10[0] -= dpw * (2.0f * s.A * dx + s.B * dy);
-            g10[1] -= dpw * (s.B * dx + 2.0f * s.C * dy);
-        }
+        g10[6] = fmaf(gC0[k], w, g10[6]);
+        g10[7] = fmaf(gC1[k], w, g10[7]);
+        g10[8] = fmaf(gC2[k], w, g10[8]);
+        g10[9] = fmaf(gD[k], w, g10[9]);
+        g10[5] = fmaf(dalpha, ev, g10[5]);
+        const float dpw = dalpha * araw;   // d/d(exponent), without ln 2
+        const float pdx = dpw * ct.dx, pdy = dpw * dy;
+        g10[2] = fmaf(pdx, ct.dx, g10[2]);
+        g10[3] = fmaf(pdx, dy, g10[3]);
+        g10[4] = fmaf(pdy, dy, g10[4]);
+        g10[0] = fmaf(nA2, pdx, fmaf(nB, pdy, g10[0]));
+        g10[1] = fmaf(nB, pdx, fmaf(nC2, pdy, g10[1]));
     }
     return any;
+}
+
+// Wave sum of a lane's 10 adjoint terms; the lanes that hold a total add it to the splat's
+// 2D gradient (entry e) with one atomic each.
+__device__ __forceinline__ void flush_adjoint(const float* g10, int lane, float* grad2d, uint32_t e) {
+    int which;
+    float t = wave_sum10(g10, lane, which);
+    if (which >= 0 && which < 5) t *= kLn2;
+    if (which >= 0) unsafeAtomicAdd(grad2d + (size_t)e * kGrad2D + which, t);
 }
 
 // One splat of the scalar-fetch adjoint: the lanes' terms, the wave sum and one atomic add
@@ -497,12 +509,7 @@ __device__ __forceinline__ void adjoint_scalar(const BwdArgs& a, const Splat& s,
     float g10[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     const bool any = blend_adjoint<PPL, R>(s, fpx, fpy0, b0 + (uint32_t)j, my_last, T, Sx, gC0, gC1, gC2, gD, gW,
                                            g10, a.amin, a.amax);
-    if (__any(any)) {
-        int which;
-        const float t = wave_sum10(g10, lane, which);
-        const uint32_t e = lane_index(chunk, (uint32_t)j);
-        if (which >= 0) unsafeAtomicAdd(a.grad2d + (size_t)e * kGrad2D + which, t);
-    }
+    if (__any(any)) flush_adjoint(g10, lane, a.grad2d, lane_index(chunk, (uint32_t)j));
 }
 
 template <int TW, int TH, int PPL, int BATCH, bool SCALAR, bool PERSISTENT>
@@ -673,16 +680,13 @@ __global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_bwd
                                                         g10, a.amin, a.amax);
                         }
                         if (NW == 1) {
-                            if (__any(any)) {
-                                int which;
-                                const float t = wave_sum10(g10, lane, which);
-                                if (which >= 0) unsafeAtomicAdd(a.grad2d + (size_t)se[j] * kGrad2D + which, t);
-                            }
+                            if (__any(any)) flush_adjoint(g10, lane, a.grad2d, se[j]);
                         } else {
                             const int slot = j & (RED - 1);
                             if (__any(any)) {
                                 int which;
-                                const float t = wave_sum10(g10, lane, which);
+                                float t = wave_sum10(g10, lane, which);
+                                if (which >= 0 && which < 5) t *= kLn2;
                                 if (which >= 0) red[wave][slot][which] = t;
                             } else if (lane < kGrad2D) {
                                 red[wave][slot][lane] = 0.0f;
@@ -759,12 +763,17 @@ hipError_t run_bwd(const BwdArgs& a, bool persistent, hipStream_t s) {
 }
 
 // Dispatch over the launch shape: tile, pixels per lane, LDS batch and record fetch.
+// Unset fields take the pass's default: the forward blends two pixels per lane from LDS
+// batches, the adjoint (whose per-record wave reduction and atomics are amortised over the
+// lane's pixels) four pixels per lane from the scalar cache.
 template <template <int, int, int, int, bool> class Run, typename Args>
-hipError_t dispatch_shape(const gs_options& o, const Args& a, bool pers, hipStream_t s) {
-    const int fetch = o.record_fetch != GS_FETCH_DEFAULT ? o.record_fetch : kDefaultRecordFetch;
+hipError_t dispatch_shape(const gs_options& o, const Args& a, bool pers, bool adjoint, hipStream_t s) {
+    const int fetch = o.record_fetch != GS_FETCH_DEFAULT ? o.record_fetch
+                                                         : (adjoint ? kDefaultRecordFetchBwd : kDefaultRecordFetchFwd);
     const bool scalar = fetch == GS_FETCH_SCALAR;
     if (o.tile_w == 8) return scalar ? Run<8, 8, 1, 64, true>::go(a, pers, s) : Run<8, 8, 1, 64, false>::go(a, pers, s);
-    const int ppl = o.pixels_per_lane != 0 ? o.pixels_per_lane : kDefaultPixelsPerLane;
+    const int ppl = o.pixels_per_lane != 0 ? o.pixels_per_lane
+                                           : (adjoint ? kDefaultPixelsPerLaneBwd : kDefaultPixelsPerLaneFwd);
     if (scalar) {
         if (ppl == 1) return Run<16, 16, 1, 64, true>::go(a, pers, s);
         if (ppl == 2) return Run<16, 16, 2, 64, true>::go(a, pers, s);
@@ -796,9 +805,16 @@ struct BwdRun {
     }
 };
 
+struct MediumAdam {
+    gs_adam_group g;   // count 9 * views; g.param/m/v updated when enabled
+    float b1, b2, eps;
+    const float* bc;
+    int32_t enabled;
+};
+
 __global__ __launch_bounds__(kBlock) void k_medium_reduce(const ViewInfo* __restrict__ vt,
                                                          const float* __restrict__ medpart,
-                                                         float* __restrict__ grad_medium) {
+                                                         float* __restrict__ grad_medium, MediumAdam ad) {
     // one workgroup per view; deterministic: fixed per-thread strides and a fixed tree
     __shared__ float red[9][kBlock];
     const int v = blockIdx.x, tid = threadIdx.x;
@@ -816,7 +832,17 @@ __global__ __launch_bounds__(kBlock) void k_medium_reduce(const ViewInfo* __rest
             for (int k = 0; k < 9; ++k) red[k][tid] += red[k][tid + off];
         __syncthreads();
     }
-    if (tid < 9) grad_medium[v * 9 + tid] = red[tid][0];
+    if (tid < 9) {
+        const float gm = red[tid][0];
+        grad_medium[v * 9 + tid] = gm;
+        if (ad.enabled) {
+            const int j = v * 9 + tid;
+            float m = ad.g.m[j], vv = ad.g.v[j];
+            ad.g.param[j] = adam_update(ad.g.param[j], gm, m, vv, ad.g.lr, ad.b1, ad.b2, ad.eps, ad.bc[0], ad.bc[1]);
+            ad.g.m[j] = m;
+            ad.g.v[j] = vv;
+        }
+    }
 }
 
 // Per tile: sum and max over pixels of the list entries walked (entries of the tile's phase
@@ -898,7 +924,7 @@ hipError_t launch_composite_fwd(const gs_options& o, const Layout& L, int phase,
     FwdArgs a{vt, L.views, (uint32_t)L.tiles, phase, L.phases - 1, med, rec, ranges + (size_t)phase * L.tiles, vals,
               &hdr->queue[phase], alive, &hdr->phase_alive[phase], out_rgb, out_depth, out_alpha, tfinal, nlast,
               done, cair, dsum, wsum, L.pixels, o.alpha_min, o.alpha_max, o.t_min, o.depth_mode};
-    return dispatch_shape<FwdRun>(o, a, o.persistent != 0, s);
+    return dispatch_shape<FwdRun>(o, a, o.persistent != 0, false, s);
 }
 
 hipError_t launch_composite_bwd(const gs_options& o, const Layout& L, const ViewInfo* vt, const gs_medium* med,
@@ -917,12 +943,23 @@ hipError_t launch_composite_bwd(const gs_options& o, const Layout& L, const View
         hipError_t e = launch_fill_u32(a.queue, 0u, 1, s);
         if (e != hipSuccess) return e;
     }
-    return dispatch_shape<BwdRun>(o, a, pers, s);
+    return dispatch_shape<BwdRun>(o, a, pers, true, s);
 }
 
 hipError_t launch_medium_reduce(const ViewInfo* vt, int32_t views, const float* medpart, float* grad_medium,
+                                const gs_adam_group* adam, float b1, float b2, float eps, const float* bc,
                                 hipStream_t s) {
-    hipLaunchKernelGGL(k_medium_reduce, dim3(views), dim3(kBlock), 0, s, vt, medpart, grad_medium);
+    MediumAdam ad;
+    memset(&ad, 0, sizeof(ad));
+    if (adam) {
+        ad.g = *adam;
+        ad.b1 = b1;
+        ad.b2 = b2;
+        ad.eps = eps;
+        ad.bc = bc;
+        ad.enabled = 1;
+    }
+    hipLaunchKernelGGL(k_medium_reduce, dim3(views), dim3(kBlock), 0, s, vt, medpart, grad_medium, ad);
     return hipGetLastError();
 }
 

@@ -16,8 +16,11 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kMaxSortParts = 1024;
 constexpr int kGrad2D = 10;              // per-(Gaussian, view) 2D gradient: m(2), conic'(3), o, rgb(3), depth
 constexpr int kDefaultPhases = 3;
-constexpr int kDefaultPixelsPerLane = 2;      // 16x16 tiles: two waves per tile
-constexpr int kDefaultRecordFetch = GS_FETCH_LDS;
+// Compositing launch shape when gs_options leaves it unset (16x16 tiles).
+constexpr int kDefaultPixelsPerLaneFwd = 2;   // two waves per tile
+constexpr int kDefaultRecordFetchFwd = GS_FETCH_LDS;
+constexpr int kDefaultPixelsPerLaneBwd = 4;   // one wave per tile
+constexpr int kDefaultRecordFetchBwd = GS_FETCH_SCALAR;
 
 // Per-view layout derived from the host cameras.
 struct ViewInfo {
@@ -51,9 +54,10 @@ struct SavedHeader {
     uint32_t phase_base[GS_MAX_PHASES];       // first stored pair of phase p
     uint32_t phase_count[GS_MAX_PHASES];      // pairs of phase p
     uint32_t phase_alive[GS_MAX_PHASES];      // tiles with an unterminated pixel after phase p
+    uint32_t phase_live[GS_MAX_PHASES];       // pairs of phase p kept by the tile sort (culled ones left out)
     uint32_t queue[GS_MAX_PHASES + 1];        // persistent-mode tile counters (forward phases)
     unsigned long long stats[5];              // scratch of gs_forward_stats
-    uint32_t pad[8];
+    uint32_t pad[4];
 };
 
 struct Layout {
@@ -66,7 +70,7 @@ struct Layout {
     size_t s_tfinal, s_nlast, s_done, s_cair, s_dsum, s_wsum, saved_bytes;
     // workspace offsets (bytes)
     size_t w_counts, w_rects, w_dkeys, w_dvals, w_dkeys2, w_dvals2, w_pcounts, w_offsets, w_blocksums, w_emit_start;
-    size_t w_tiles_a, w_vals_a, w_tiles_b, w_vals_b, w_hist, w_grad2d, w_medpart, workspace_bytes;
+    size_t w_tiles_a, w_vals_a, w_tiles_b, w_vals_b, w_hist, w_grad2d, w_medpart, w_adam, workspace_bytes;
 };
 
 int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_camera* cams, Layout* L);
@@ -79,12 +83,38 @@ hipError_t launch_project_fwd(const gs_gaussians& g, int32_t views, const gs_cam
                               uint32_t* depth_keys, uint32_t* dkeys_sort, uint32_t* dvals_sort,
                               SavedHeader* hdr, hipStream_t s);
 hipError_t launch_project_bwd(const gs_gaussians& g, int32_t views, const gs_camera* cams, const gs_options& o,
-                              const float* grad2d, gs_gaussian_grads grads, hipStream_t s);
+                              const float* grad2d, const Record* rec, gs_gaussian_grads grads, hipStream_t s);
+
+// One Adam step (Sec. Optimization) of one scalar: moments updated in place, returns the new
+// parameter.  ibc1, ibc2 = 1 / (1 - beta^t).  The step divides by sqrt(v_hat) + eps through the
+// hardware reciprocal (1 ulp); the square root is correctly rounded.
+__device__ __forceinline__ float adam_update(float p, float g, float& m, float& v, float lr, float b1, float b2,
+                                             float eps, float ibc1, float ibc2) {
+    m = fmaf(b1, m, (1.0f - b1) * g);
+    v = fmaf(b2, v, (1.0f - b2) * g * g);
+    return p - (lr * (m * ibc1)) * __builtin_amdgcn_rcpf(sqrtf(v * ibc2) + eps);
+}
+
+// Adam applied inside the projection adjoint: groups means, log-scales (exp), quaternions,
+// opacity logits (sigmoid), SH, in this order; bc = device [2] bias corrections of this step.
+struct AdamFused {
+    gs_adam_group g[5];
+    float b1, b2, eps;
+    const float* bc;
+};
+
+hipError_t launch_project_bwd_adam(const gs_gaussians& g, int32_t views, const gs_camera* cams, const gs_options& o,
+                                   const float* grad2d, const Record* rec, const AdamFused& adam, hipStream_t s);
+// step += 1 and bc = (1 / (1 - b1^step), 1 / (1 - b2^step)) on the device.
+hipError_t launch_adam_prep(int32_t* step, float b1, float b2, float* bc, hipStream_t s);
 // Stable LSD radix sort of (key, value) u32 pairs over bits [bit0, bit0+nbits).  n is read from n_dev
 // (or n_host if n_dev is null).  Returns in *out_in_b whether the result sits in the B buffers.
+// With use_drop, keys equal to drop_key are left out; with n_kept the number of kept pairs is
+// written there (device), and the sorted output holds exactly those.
 hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b,
-                          const uint32_t* n_dev, uint32_t n_host, int bit0, int nbits, int parts,
-                          uint32_t* hist, int* result_in_b, const char* tag, void* timer, hipStream_t s);
+                          const uint32_t* n_dev, uint32_t n_host, int bit0, int nbits, int parts, uint32_t* hist,
+                          int* out_in_b, const char* tag, void* timer, hipStream_t s, int use_drop = 0,
+                          uint32_t drop_key = 0, uint32_t* n_kept = nullptr);
 // Number of visible entries (depth-sorted keys before the first 0xFFFFFFFF) and the phase rank ranges.
 hipError_t launch_visible(const uint32_t* sorted_keys, int64_t nv, int phases, SavedHeader* hdr, hipStream_t s);
 // Per-entry pair counts of phase p (by depth rank): whole rectangles in phase 0, only the tiles
@@ -126,7 +156,10 @@ hipError_t launch_composite_bwd(const gs_options& o, const Layout& L, const View
                                 const float* grad_depth, const float* tfinal, const uint32_t* nlast,
                                 const float* cair, const float* dsum, const float* wsum, float* grad2d,
                                 float* medpart, hipStream_t s);
+// Per-view sums of the tiles' medium partials into grad_medium [views][9]; with `adam`, also one
+// Adam step of the medium parameters (group with count 9 * views) using the device bias corrections.
 hipError_t launch_medium_reduce(const ViewInfo* vt, int32_t views, const float* medpart, float* grad_medium,
+                                const gs_adam_group* adam, float b1, float b2, float eps, const float* bc,
                                 hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 hipError_t launch_export_keys(const Layout& L, const uint2* ranges, const uint32_t* vals, const uint32_t* depth_keys,

@@ -36,16 +36,33 @@ __global__ __launch_bounds__(kBlock) void k_activate_bwd(int64_t n, const float*
 
 __global__ void k_zero1(float* p) { *p = 0.0f; }
 
-__global__ __launch_bounds__(kBlock) void k_l1(int64_t count, const float* __restrict__ p,
-                                              const float* __restrict__ t, float* loss, float* __restrict__ grad) {
-    __shared__ float red[kBlock / 64];
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
+// Few large workgroups: each adds its partial loss with one atomic on the single loss word,
+// and same-address atomics serialise.
+constexpr int kL1Block = 1024;
+constexpr int kL1MaxGrid = 256;
+
+__global__ __launch_bounds__(kL1Block) void k_l1(int64_t count, const float* __restrict__ p,
+                                                const float* __restrict__ t, float* loss, float* __restrict__ grad) {
+    __shared__ float red[kL1Block / 64];
+    const int64_t stride = (int64_t)gridDim.x * kL1Block;
     const float inv = 1.0f / (float)count;
     float acc = 0.0f;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) {
-        const float d = p[i] - t[i];
+    auto one = [&](float pv, float tv) {
+        const float d = pv - tv;
         acc += fabsf(d);
-        if (grad) grad[i] = d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f);
+        return d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f);
+    };
+    const bool vec = ((reinterpret_cast<uintptr_t>(p) | reinterpret_cast<uintptr_t>(t) |
+                       reinterpret_cast<uintptr_t>(grad)) & 15) == 0;
+    const int64_t n4 = vec ? count / 4 : 0;
+    for (int64_t i = (int64_t)blockIdx.x * kL1Block + threadIdx.x; i < n4; i += stride) {
+        const float4 pv = reinterpret_cast<const float4*>(p)[i], tv = reinterpret_cast<const float4*>(t)[i];
+        const float4 g = make_float4(one(pv.x, tv.x), one(pv.y, tv.y), one(pv.z, tv.z), one(pv.w, tv.w));
+        if (grad) reinterpret_cast<float4*>(grad)[i] = g;
+    }
+    for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * kL1Block + threadIdx.x; i < count; i += stride) {
+        const float g = one(p[i], t[i]);
+        if (grad) grad[i] = g;
     }
     if (!loss) return;
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
@@ -53,47 +70,86 @@ __global__ __launch_bounds__(kBlock) void k_l1(int64_t count, const float* __res
     __syncthreads();
     if (threadIdx.x == 0) {
         float s = 0.0f;
-        for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+        for (int w = 0; w < kL1Block / 64; ++w) s += red[w];
         unsafeAtomicAdd(loss, s * inv);
     }
 }
 
+constexpr int kAdamItems = 4;                              // float4 per thread per block
+constexpr int64_t kAdamChunk = (int64_t)kBlock * kAdamItems * 4;   // scalars per workgroup
+
 struct AdamArgs {
     gs_adam_group g[kMaxGroups];
     int32_t count;
-    float b1, b2, eps, bc1, bc2;
-    const int32_t* step_dev;   // if set, bias corrections come from this device step number
+    int32_t block0[kMaxGroups + 1];  // first workgroup of each group (one flat grid over all groups)
+    float b1, b2, eps, ibc1, ibc2;   // 1 / (1 - beta^t)
+    const int32_t* step_dev;         // if set, bias corrections come from this device step number
 };
 
 __global__ void k_step_inc(int32_t* step) { *step += 1; }
 
-__device__ __forceinline__ float adam_one(const AdamArgs& a, const gs_adam_group& G, float p, float g, float act,
-                                          float& m, float& v, float& new_act) {
+__global__ void k_adam_prep(int32_t* step, float b1, float b2, float* bc) {
+    const int32_t t = *step + 1;
+    *step = t;
+    bc[0] = 1.0f / (1.0f - powf(b1, (float)t));
+    bc[1] = 1.0f / (1.0f - powf(b2, (float)t));
+}
+
+__device__ __forceinline__ float adam_one(const gs_adam_group& G, float p, float g, float act, float& m, float& v,
+                                          float& new_act, float b1, float b2, float eps, float ibc1, float ibc2) {
     if (G.activation == 1) g *= act;                        // d exp(p)/dp = exp(p)
     else if (G.activation == 2) g *= act * (1.0f - act);    // d sigmoid(p)/dp
-    m = fmaf(a.b1, m, (1.0f - a.b1) * g);
-    v = fmaf(a.b2, v, (1.0f - a.b2) * g * g);
-    const float np = p - G.lr * (m / a.bc1) / (sqrtf(v / a.bc2) + a.eps);
+    const float np = adam_update(p, g, m, v, G.lr, b1, b2, eps, ibc1, ibc2);
     if (G.activation == 1) new_act = expf(np);
     else if (G.activation == 2) new_act = sigmoidf_(np);
     return np;
 }
 
-// blockIdx.y selects the group; each thread updates 4 consecutive scalars with 16-byte
-// loads and stores when the group's arrays allow it.
+// The group is selected with constant indices: indexing the by-value argument array with
+// blockIdx.y would make every thread copy it to private memory.
+__device__ __forceinline__ gs_adam_group select_group(const AdamArgs& a, uint32_t y) {
+    switch (y) {
+        case 0: return a.g[0];
+        case 1: return a.g[1];
+        case 2: return a.g[2];
+        case 3: return a.g[3];
+        case 4: return a.g[4];
+        case 5: return a.g[5];
+        case 6: return a.g[6];
+        default: return a.g[7];
+    }
+}
+
+// One flat grid: workgroup b updates scalars [chunk * kAdamChunk, (chunk + 1) * kAdamChunk) of
+// the group whose block range holds b, so every group's stream gets workgroups in proportion
+// to its size (the SH group is most of the bytes).
 __global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a) {
+    // everything read from the argument block with constant indices (no private copy)
+    float ibc1 = a.ibc1, ibc2 = a.ibc2;
     if (a.step_dev) {
         const float t = (float)*a.step_dev;
-        a.bc1 = 1.0f - powf(a.b1, t);
-        a.bc2 = 1.0f - powf(a.b2, t);
+        ibc1 = 1.0f / (1.0f - powf(a.b1, t));
+        ibc2 = 1.0f / (1.0f - powf(a.b2, t));
     }
-    const gs_adam_group G = a.g[blockIdx.y];
+    uint32_t gi = 0;
+    int32_t start = 0;
+#pragma unroll
+    for (int k = 1; k < kMaxGroups; ++k) {
+        if (k < a.count && (int32_t)blockIdx.x >= a.block0[k]) {
+            gi = k;
+            start = a.block0[k];
+        }
+    }
+    const gs_adam_group G = select_group(a, gi);
     const int64_t n = G.count;
-    const int64_t stride = (int64_t)gridDim.x * kBlock * 4;
+    const int64_t base = (int64_t)((int32_t)blockIdx.x - start) * kAdamChunk;
     const bool vec = ((reinterpret_cast<uintptr_t>(G.param) | reinterpret_cast<uintptr_t>(G.grad) |
                        reinterpret_cast<uintptr_t>(G.m) | reinterpret_cast<uintptr_t>(G.v) |
                        reinterpret_cast<uintptr_t>(G.activated)) & 15) == 0;
-    for (int64_t i0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * 4; i0 < n; i0 += stride) {
+#pragma unroll
+    for (int it = 0; it < kAdamItems; ++it) {
+        const int64_t i0 = base + ((int64_t)it * kBlock + threadIdx.x) * 4;
+        if (i0 >= n) break;
         if (vec && i0 + 4 <= n) {
             float4 p = *reinterpret_cast<const float4*>(G.param + i0);
             const float4 g = *reinterpret_cast<const float4*>(G.grad + i0);
@@ -101,10 +157,10 @@ __global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a) {
             float4 v = *reinterpret_cast<const float4*>(G.v + i0);
             float4 ac = G.activation ? *reinterpret_cast<const float4*>(G.activated + i0) : make_float4(0, 0, 0, 0);
             float4 na = ac;
-            p.x = adam_one(a, G, p.x, g.x, ac.x, m.x, v.x, na.x);
-            p.y = adam_one(a, G, p.y, g.y, ac.y, m.y, v.y, na.y);
-            p.z = adam_one(a, G, p.z, g.z, ac.z, m.z, v.z, na.z);
-            p.w = adam_one(a, G, p.w, g.w, ac.w, m.w, v.w, na.w);
+            p.x = adam_one(G, p.x, g.x, ac.x, m.x, v.x, na.x, a.b1, a.b2, a.eps, ibc1, ibc2);
+            p.y = adam_one(G, p.y, g.y, ac.y, m.y, v.y, na.y, a.b1, a.b2, a.eps, ibc1, ibc2);
+            p.z = adam_one(G, p.z, g.z, ac.z, m.z, v.z, na.z, a.b1, a.b2, a.eps, ibc1, ibc2);
+            p.w = adam_one(G, p.w, g.w, ac.w, m.w, v.w, na.w, a.b1, a.b2, a.eps, ibc1, ibc2);
             *reinterpret_cast<float4*>(G.param + i0) = p;
             *reinterpret_cast<float4*>(G.m + i0) = m;
             *reinterpret_cast<float4*>(G.v + i0) = v;
@@ -114,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a) {
                 float m = G.m[j], v = G.v[j];
                 float na = 0.0f;
                 const float act = G.activation ? G.activated[j] : 0.0f;
-                G.param[j] = adam_one(a, G, G.param[j], G.grad[j], act, m, v, na);
+                G.param[j] = adam_one(G, G.param[j], G.grad[j], act, m, v, na, a.b1, a.b2, a.eps, ibc1, ibc2);
                 G.m[j] = m;
                 G.v[j] = v;
                 if (G.activation) G.activated[j] = na;
@@ -131,6 +187,12 @@ unsigned grid_for(int64_t n) {
 }
 
 }  // namespace
+
+hipError_t launch_adam_prep(int32_t* step, float b1, float b2, float* bc, hipStream_t s) {
+    hipLaunchKernelGGL(k_adam_prep, dim3(1), dim3(1), 0, s, step, b1, b2, bc);
+    return hipGetLastError();
+}
+
 }  // namespace gs
 
 using namespace gs;
@@ -162,9 +224,10 @@ int gs_l1_loss(int64_t count, const float* pred, const float* target, float* los
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (loss) hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, s, loss);
     // at most 512 workgroups: each adds one partial sum, so the atomic tail stays short
-    unsigned g = grid_for(count);
-    if (g > 512) g = 512;
-    hipLaunchKernelGGL(k_l1, dim3(g), dim3(kBlock), 0, s, count, pred, target, loss, grad);
+    int64_t g = ((count + 3) / 4 + kL1Block - 1) / kL1Block;
+    if (g < 1) g = 1;
+    if (g > kL1MaxGrid) g = kL1MaxGrid;
+    hipLaunchKernelGGL(k_l1, dim3((unsigned)g), dim3(kL1Block), 0, s, count, pred, target, loss, grad);
     return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }
 
@@ -177,30 +240,31 @@ static int adam_launch(const gs_adam_group* host_groups, int32_t n_groups, float
     AdamArgs a;
     memset(&a, 0, sizeof(a));
     a.count = n_groups;
-    int64_t largest = 0;
     for (int k = 0; k < n_groups; ++k) {
         const gs_adam_group& G = host_groups[k];
         if (G.count < 0 || G.activation < 0 || G.activation > 2) return GS_ERR_INVALID_ARGUMENT;
         if (G.count > 0 && (!G.param || !G.grad || !G.m || !G.v || (G.activation && !G.activated)))
             return GS_ERR_INVALID_ARGUMENT;
         a.g[k] = G;
-        if (G.count > largest) largest = G.count;
     }
     a.b1 = beta1;
     a.b2 = beta2;
     a.eps = eps;
     a.step_dev = step_dev;
     if (!step_dev) {
-        a.bc1 = (float)(1.0 - __builtin_pow((double)beta1, (double)step));
-        a.bc2 = (float)(1.0 - __builtin_pow((double)beta2, (double)step));
+        a.ibc1 = (float)(1.0 / (1.0 - __builtin_pow((double)beta1, (double)step)));
+        a.ibc2 = (float)(1.0 / (1.0 - __builtin_pow((double)beta2, (double)step)));
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (step_dev) hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(1), 0, s, step_dev);
-    if (largest > 0) {
-        int64_t gx = (largest + 4 * kBlock - 1) / (4 * kBlock);
-        if (gx > 2048) gx = 2048;
-        hipLaunchKernelGGL(k_adam, dim3((unsigned)gx, (unsigned)n_groups), dim3(kBlock), 0, s, a);
+    int64_t blocks = 0;
+    for (int k = 0; k < n_groups; ++k) {
+        a.block0[k] = (int32_t)blocks;
+        blocks += (host_groups[k].count + kAdamChunk - 1) / kAdamChunk;
+        if (blocks >= (1LL << 31)) return GS_ERR_INVALID_ARGUMENT;
     }
+    a.block0[n_groups] = (int32_t)blocks;
+    if (blocks > 0) hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
     return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }
 

@@ -8,6 +8,8 @@
 // file is compiled with -ffp-contract=off and uses no fused multiply-adds on
 // that path, with IEEE division and square root, so the sort keys are
 // reproducible bit for bit.
+#include <string.h>
+
 #include "internal.h"
 
 namespace gs {
@@ -246,7 +248,9 @@ __global__ __launch_bounds__(kBlock) void k_project_fwd(gs_gaussians g, int32_t 
                 float acc = 0.5f;
 #pragma unroll
                 for (int k = 0; k < NC; ++k) acc = fmaf(Y[k], sh[3 * k + ch], acc);
-                col[ch] = acc > 0.0f ? acc : 0.0f;
+                // clamped channels (acc < 0, or not a number) store -0: blends as 0, and tells the
+                // adjoint that the channel passes no gradient to the SH coefficients
+                col[ch] = acc > 0.0f ? acc : (acc == 0.0f ? 0.0f : -0.0f);
             }
             Record r;
             r.a = make_float4(P.px, P.py, A, B);
@@ -264,13 +268,22 @@ __global__ __launch_bounds__(kBlock) void k_project_fwd(gs_gaussians g, int32_t 
 }
 
 // Adjoint of k_project_fwd.  grad2d[e][10] = d/d(m_x, m_y, A, B, C, opacity, r, g, b, depth)
-// of the record of entry e = v * n + i.  Gradients of all views are summed in registers and written
-// once (overwrite).
-template <int DEG>
+// of the record of entry e = v * n + i.  Gradients of all views are summed in registers, then
+// either written once (overwrite) or, when `fused`, used for one Adam step of the raw
+// parameters (log-scales and opacity logits through the activations' derivatives) that also
+// stores the activated scales and opacities the next forward reads.
+//
+// The SH gradient of one view is the outer product Y(dir) x (colour gradient of the
+// unclamped channels).  With one view (ONE) the kernel keeps those 16 + 3 factors instead of
+// 48 accumulators, which bounds its register use; the clamp of each channel is read from the
+// forward's record (a clamped channel holds -0).
+template <int DEG, bool FUSED, bool ONE>
 __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t views, const gs_camera* cams,
                                                        float dil, const float* __restrict__ grad2d,
-                                                       gs_gaussian_grads out) {
+                                                       const Record* __restrict__ rec, gs_gaussian_grads out,
+                                                       AdamFused adam) {
     constexpr int NC = (DEG + 1) * (DEG + 1);
+    constexpr int NACC = ONE ? 1 : NC * 3;
     const int64_t n = g.n;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -278,9 +291,13 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
     const float s[3] = {g.scales[i], g.scales[n + i], g.scales[2 * n + i]};
     const float qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
     float gmu[3] = {0.f, 0.f, 0.f}, gsc[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, gop = 0.f;
-    float gsh[NC * 3];
+    float gsh[NACC];      // several views: SH gradient accumulators
+    float Y1[16], gc1[3];  // one view: the factors of its SH gradient
 #pragma unroll
-    for (int k = 0; k < NC * 3; ++k) gsh[k] = 0.f;
+    for (int k = 0; k < NACC; ++k) gsh[k] = 0.f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) Y1[k] = 0.f;
+    gc1[0] = gc1[1] = gc1[2] = 0.f;
     for (int v = 0; v < views; ++v) {
         const float* gg = grad2d + ((int64_t)v * n + i) * kGrad2D;
         float G[kGrad2D];
@@ -361,7 +378,17 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
                           G[9];
 #pragma unroll
         for (int k = 0; k < 3; ++k) gmu[k] += c.R[k] * gtx + c.R[3 + k] * gty + c.R[6 + k] * gtz;
-        // SH colour: colour = max(0, 1/2 + sum_k Y_k(dir) sh_k)
+        // SH colour: colour = max(0, 1/2 + sum_k Y_k(dir) sh_k); no gradient through a clamped channel
+        const Record& r = rec[(int64_t)v * n + i];
+        const float col[3] = {r.b.z, r.b.w, r.c.x};
+        float gce[3];
+        bool live = false;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            gce[ch] = signbit(col[ch]) ? 0.0f : G[6 + ch];
+            live = live || gce[ch] != 0.0f;
+        }
+        if (!live) continue;
         float cc[3];
         camera_centre(c, cc);
         float d0 = mx - cc[0], d1 = my - cc[1], d2 = mz - cc[2];
@@ -369,26 +396,29 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
         d0 *= il; d1 *= il; d2 *= il;
         float Y[16];
         sh_eval<DEG>(d0, d1, d2, Y);
-        float wk[16];
+        if (ONE) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) wk[k] = 0.f;
-        bool live = false;
+            for (int k = 0; k < 16; ++k) Y1[k] = Y[k];
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            float acc = 0.5f;
+            for (int ch = 0; ch < 3; ++ch) gc1[ch] = gce[ch];
+        } else {
 #pragma unroll
-            for (int k = 0; k < NC; ++k) acc = fmaf(Y[k], g.sh[(int64_t)(3 * k + ch) * n + i], acc);
-            if (acc < 0.0f) continue;   // clamped channel: no gradient
-            const float gcol = G[6 + ch];
-            if (gcol == 0.0f) continue;
-            live = true;
+            for (int k = 0; k < NC; ++k)
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) gsh[(3 * k + ch) % NACC] += Y[k] * gce[ch];
+        }
+        if (DEG > 0) {
+            float wk[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) wk[k] = 0.f;
+            // streamed in groups of four coefficients: hoisting all 48 loads would hold 48 registers
 #pragma unroll
             for (int k = 0; k < NC; ++k) {
-                gsh[3 * k + ch] += Y[k] * gcol;
-                wk[k] += gcol * g.sh[(int64_t)(3 * k + ch) * n + i];
+                if (k % 4 == 0) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) wk[k] += gce[ch] * g.sh[(int64_t)(3 * k + ch) * n + i];
             }
-        }
-        if (DEG > 0 && live) {
+            __builtin_amdgcn_sched_barrier(0);
             float gd[3];
             sh_grad<DEG>(d0, d1, d2, wk, gd);
             const float dd = gd[0] * d0 + gd[1] * d1 + gd[2] * d2;
@@ -397,13 +427,52 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
             gmu[2] += (gd[2] - d2 * dd) * il;
         }
     }
-    out.means[i] = gmu[0]; out.means[n + i] = gmu[1]; out.means[2 * n + i] = gmu[2];
-    out.scales[i] = gsc[0]; out.scales[n + i] = gsc[1]; out.scales[2 * n + i] = gsc[2];
+    // SH gradient element j = 3 k + channel
+    auto shg = [&](int j) { return ONE ? Y1[j / 3] * gc1[j % 3] : gsh[j % NACC]; };
+    if (!FUSED) {
+        out.means[i] = gmu[0]; out.means[n + i] = gmu[1]; out.means[2 * n + i] = gmu[2];
+        out.scales[i] = gsc[0]; out.scales[n + i] = gsc[1]; out.scales[2 * n + i] = gsc[2];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) out.quats[(int64_t)k * n + i] = gq[k];
-    out.opacity[i] = gop;
+        for (int k = 0; k < 4; ++k) out.quats[(int64_t)k * n + i] = gq[k];
+        out.opacity[i] = gop;
 #pragma unroll
-    for (int k = 0; k < NC * 3; ++k) out.sh[(int64_t)k * n + i] = gsh[k];
+        for (int k = 0; k < NC * 3; ++k) out.sh[(int64_t)k * n + i] = shg(k);
+        return;
+    }
+    const float ibc1 = adam.bc[0], ibc2 = adam.bc[1];
+    auto step = [&](const gs_adam_group& G, int64_t j, float grad) {
+        float m = G.m[j], v = G.v[j];
+        const float np = adam_update(G.param[j], grad, m, v, G.lr, adam.b1, adam.b2, adam.eps, ibc1, ibc2);
+        G.param[j] = np;
+        G.m[j] = m;
+        G.v[j] = v;
+        return np;
+    };
+    // The updates below are fenced for the scheduler in groups (16 SH coefficients = 48 loads
+    // in flight): hoisting every parameter's and moment's load ahead of the arithmetic would
+    // need several hundred registers.
+#pragma unroll
+    for (int k = 0; k < 3; ++k) step(adam.g[0], (int64_t)k * n + i, gmu[k]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {   // d exp(l)/dl = exp(l) = the activated scale
+        const float nl = step(adam.g[1], (int64_t)k * n + i, gsc[k] * s[k]);
+        adam.g[1].activated[(int64_t)k * n + i] = expf(nl);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) step(adam.g[2], (int64_t)k * n + i, gq[k]);
+    __builtin_amdgcn_sched_barrier(0);
+    {   // d sigmoid(x)/dx = o (1 - o)
+        const float o = g.opacity[i];
+        const float nx = step(adam.g[3], i, gop * (o * (1.0f - o)));
+        adam.g[3].activated[i] = 1.0f / (1.0f + expf(-nx));
+    }
+#pragma unroll
+    for (int k = 0; k < NC * 3; ++k) {
+        if (k % 16 == 0) __builtin_amdgcn_sched_barrier(0);
+        step(adam.g[4], (int64_t)k * n + i, shg(k));
+    }
 }
 
 }  // namespace
@@ -427,12 +496,30 @@ hipError_t launch_project_fwd(const gs_gaussians& g, int32_t views, const gs_cam
     return hipGetLastError();
 }
 
-hipError_t launch_project_bwd(const gs_gaussians& g, int32_t views, const gs_camera* cams, const gs_options& o,
-                              const float* grad2d, gs_gaussian_grads grads, hipStream_t s) {
+namespace {
+
+template <int D, bool F>
+void project_bwd_launch(const gs_gaussians& g, int32_t views, const gs_camera* cams, float dil, const float* grad2d,
+                        const Record* rec, const gs_gaussian_grads& grads, const AdamFused& adam, unsigned grid,
+                        hipStream_t s) {
+    if (views == 1)
+        hipLaunchKernelGGL((k_project_bwd<D, F, true>), dim3(grid), dim3(kBlock), 0, s, g, views, cams, dil, grad2d,
+                           rec, grads, adam);
+    else
+        hipLaunchKernelGGL((k_project_bwd<D, F, false>), dim3(grid), dim3(kBlock), 0, s, g, views, cams, dil,
+                           grad2d, rec, grads, adam);
+}
+
+hipError_t project_bwd(const gs_gaussians& g, int32_t views, const gs_camera* cams, const gs_options& o,
+                       const float* grad2d, const Record* rec, const gs_gaussian_grads& grads, const AdamFused& adam,
+                       int fused, hipStream_t s) {
     if (g.n == 0) return hipSuccess;
     const unsigned grid = (unsigned)((g.n + kBlock - 1) / kBlock);
-#define GS_PB(D) \
-    hipLaunchKernelGGL(k_project_bwd<D>, dim3(grid), dim3(kBlock), 0, s, g, views, cams, o.dilation, grad2d, grads)
+#define GS_PB(D)                                                                                     \
+    if (fused)                                                                                       \
+        project_bwd_launch<D, true>(g, views, cams, o.dilation, grad2d, rec, grads, adam, grid, s);  \
+    else                                                                                             \
+        project_bwd_launch<D, false>(g, views, cams, o.dilation, grad2d, rec, grads, adam, grid, s)
     switch (g.sh_degree) {
         case 0: GS_PB(0); break;
         case 1: GS_PB(1); break;
@@ -441,6 +528,22 @@ hipError_t launch_project_bwd(const gs_gaussians& g, int32_t views, const gs_cam
     }
 #undef GS_PB
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_project_bwd(const gs_gaussians& g, int32_t views, const gs_camera* cams, const gs_options& o,
+                              const float* grad2d, const Record* rec, gs_gaussian_grads grads, hipStream_t s) {
+    AdamFused none;
+    memset(&none, 0, sizeof(none));
+    return project_bwd(g, views, cams, o, grad2d, rec, grads, none, 0, s);
+}
+
+hipError_t launch_project_bwd_adam(const gs_gaussians& g, int32_t views, const gs_camera* cams, const gs_options& o,
+                                   const float* grad2d, const Record* rec, const AdamFused& adam, hipStream_t s) {
+    gs_gaussian_grads none;
+    memset(&none, 0, sizeof(none));
+    return project_bwd(g, views, cams, o, grad2d, rec, none, adam, 1, s);
 }
 
 }  // namespace gs

@@ -47,8 +47,8 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t digit, int nbits, uint6
 }
 
 __global__ __launch_bounds__(kBlock) void k_hist(const uint32_t* __restrict__ keys, const uint32_t* n_dev,
-                                                uint32_t n_host, int shift, int nbits, int parts,
-                                                uint32_t* __restrict__ hist) {
+                                                uint32_t n_host, int shift, int nbits, int parts, int use_drop,
+                                                uint32_t drop, uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[kRadix];
     const int tid = threadIdx.x, lane = tid & 63;
     for (int i = tid; i < kRadix; i += kBlock) h[i] = 0;
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kBlock) void k_hist(const uint32_t* __restrict__ ke
         }
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
-            const bool valid = base + k * kBlock + tid < n;
+            const bool valid = base + k * kBlock + tid < n && !(use_drop && key[k] == drop);
             const uint32_t digit = (key[k] >> shift) & mask;
             const uint64_t m = match_digit(digit, nbits, __ballot(valid));
             if (valid && lane == __ffsll((unsigned long long)m) - 1) atomicAdd(&h[digit], (uint32_t)__popcll(m));
@@ -77,10 +77,35 @@ __global__ __launch_bounds__(kBlock) void k_hist(const uint32_t* __restrict__ ke
     for (int d = tid; d < kRadix; d += kBlock) hist[(size_t)d * parts + blockIdx.x] = h[d];
 }
 
+// Block-wide exclusive scan of one u32 per thread (256 threads = 4 waves); returns the
+// total.  Inclusive scans inside each wave by lane shuffles, then the four wave totals
+// through LDS (two barriers; `s` needs 4 entries).
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s, uint32_t& total) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t inc = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)inc, off);
+        if (lane >= off) inc += y;
+    }
+    if (lane == 63) s[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        const uint32_t t = s[w];
+        before += w < wave ? t : 0u;
+        total += t;
+    }
+    __syncthreads();   // `s` may be reused by the caller
+    return before + inc - x;
+}
+
 // Exclusive scan of row d (parts <= kMaxSortParts entries) in place; totals[d] = row sum.
 __global__ __launch_bounds__(kBlock) void k_scan_rows(uint32_t* __restrict__ hist, int parts,
                                                      uint32_t* __restrict__ totals) {
-    __shared__ uint32_t s[kBlock];
+    __shared__ uint32_t s[kBlock / 64];
     const int tid = threadIdx.x;
     uint32_t* row = hist + (size_t)blockIdx.x * parts;
     constexpr int PER = kMaxSortParts / kBlock;
@@ -92,51 +117,28 @@ __global__ __launch_bounds__(kBlock) void k_scan_rows(uint32_t* __restrict__ his
         v[k] = i < parts ? row[i] : 0u;
         sum += v[k];
     }
-    s[tid] = sum;
-    __syncthreads();
-    for (int off = 1; off < kBlock; off <<= 1) {
-        const uint32_t x = tid >= off ? s[tid - off] : 0u;
-        __syncthreads();
-        s[tid] += x;
-        __syncthreads();
-    }
-    uint32_t run = s[tid] - sum;
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(sum, s, total);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int i = tid * PER + k;
         if (i < parts) row[i] = run;
         run += v[k];
     }
-    if (tid == kBlock - 1) totals[blockIdx.x] = s[kBlock - 1];
-}
-
-// Block-wide exclusive scan of one u32 per thread (256 threads); returns the total.
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s, uint32_t& total) {
-    const int tid = threadIdx.x;
-    s[tid] = x;
-    __syncthreads();
-    for (int off = 1; off < kBlock; off <<= 1) {
-        const uint32_t y = tid >= off ? s[tid - off] : 0u;
-        __syncthreads();
-        s[tid] += y;
-        __syncthreads();
-    }
-    total = s[kBlock - 1];
-    const uint32_t r = s[tid] - x;
-    __syncthreads();
-    return r;
+    if (tid == 0) totals[blockIdx.x] = total;
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                    const uint32_t* n_dev, uint32_t n_host, int shift, int nbits,
                                                    int parts, const uint32_t* __restrict__ hist,
-                                                   const uint32_t* __restrict__ totals) {
+                                                   const uint32_t* __restrict__ totals, int use_drop,
+                                                   uint32_t drop, uint32_t* __restrict__ n_kept) {
     static_assert(kRadix == kBlock, "one digit per thread in the block scans");
     __shared__ uint32_t run[kRadix];        // global write base of each digit for the next tile
     __shared__ uint32_t wcnt[4][kRadix];    // per-wave digit counts, then per-wave digit offsets in the tile
     __shared__ uint32_t tstart[kRadix];     // first slot of each digit in the LDS-ordered tile
-    __shared__ uint32_t scan_tmp[kBlock];
+    __shared__ uint32_t scan_tmp[kBlock / 64];
     __shared__ uint32_t sk[kSortTile], sv[kSortTile];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const uint32_t mask = (1u << nbits) - 1u;
@@ -145,6 +147,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
         uint32_t tot;
         const uint32_t base = block_exclusive_scan(totals[tid], scan_tmp, tot);
         run[tid] = base + hist[(size_t)tid * parts + blockIdx.x];
+        if (n_kept && blockIdx.x == 0 && tid == 0) *n_kept = tot;   // keys kept (equal to drop: left out)
     }
     uint32_t t0, t1;
     part_range(n, parts, blockIdx.x, t0, t1);
@@ -153,7 +156,6 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
         for (int i = tid; i < 4 * kRadix; i += kBlock) (&wcnt[0][0])[i] = 0;
         __syncthreads();
         const uint32_t tbase = t * kSortTile;
-        const uint32_t tn = min((uint32_t)kSortTile, n - tbase);
         // wave w ranks elements [tbase + w*512, tbase + (w+1)*512) in order: item k, lane l.
         const uint32_t wbase = tbase + (uint32_t)wave * 64u * kSortItems;
         uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
             const uint32_t idx = wbase + k * 64 + lane;
-            const bool valid = idx < n;
+            const bool valid = idx < n && !(use_drop && key[k] == drop);
             const uint32_t digit = (key[k] >> shift) & mask;
             const uint64_t match = match_digit(digit, nbits, __ballot(valid));
             const uint32_t before = wcnt[wave][digit];
@@ -193,7 +195,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
             const uint32_t idx = wbase + k * 64 + lane;
-            if (idx < n) {
+            if (idx < n && !(use_drop && key[k] == drop)) {
                 const uint32_t digit = (key[k] >> shift) & mask;
                 const uint32_t lp = tstart[digit] + wcnt[wave][digit] + rank[k];
                 if (lp < (uint32_t)kSortTile) {   // always true: lp < tile count
@@ -208,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
             const uint32_t i = k * kBlock + tid;
-            if (i < tn) {
+            if (i < tot) {   // the tile's kept keys, in digit order
                 const uint32_t kk = sk[i];
                 const uint32_t pos = run[(kk >> shift) & mask] + i;
                 if (pos < n) {   // always true when the histogram and ranking agree
@@ -227,7 +229,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
 
 hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b,
                           const uint32_t* n_dev, uint32_t n_host, int bit0, int nbits, int parts,
-                          uint32_t* hist, int* result_in_b, const char* tag, void* timer, hipStream_t s) {
+                          uint32_t* hist, int* result_in_b, const char* tag, void* timer, hipStream_t s,
+                          int use_drop, uint32_t drop_key, uint32_t* n_kept) {
     const std::string th = std::string(tag) + "_hist", ts = std::string(tag) + "_scan",
                       tc = std::string(tag) + "_scatter";
     uint32_t* totals = hist + (size_t)kRadix * parts;
@@ -239,15 +242,20 @@ hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, 
         const uint32_t* vin = in_b ? vals_b : vals_a;
         uint32_t* kout = in_b ? keys_a : keys_b;
         uint32_t* vout = in_b ? vals_a : vals_b;
+        // the first pass leaves out the keys equal to drop_key; later passes sort the kept ones
+        const bool first = done == 0;
+        const int drop_now = first && use_drop ? 1 : 0;
+        const uint32_t* n_in = (!first && n_kept) ? n_kept : n_dev;
         timer_begin(timer, th.c_str(), s);
-        hipLaunchKernelGGL(k_hist, dim3(parts), dim3(kBlock), 0, s, kin, n_dev, n_host, shift, bits, parts, hist);
+        hipLaunchKernelGGL(k_hist, dim3(parts), dim3(kBlock), 0, s, kin, n_in, n_host, shift, bits, parts, drop_now,
+                           drop_key, hist);
         timer_end(timer, s);
         timer_begin(timer, ts.c_str(), s);
         hipLaunchKernelGGL(k_scan_rows, dim3(kRadix), dim3(kBlock), 0, s, hist, parts, totals);
         timer_end(timer, s);
         timer_begin(timer, tc.c_str(), s);
-        hipLaunchKernelGGL(k_scatter, dim3(parts), dim3(kBlock), 0, s, kin, vin, kout, vout, n_dev, n_host, shift,
-                           bits, parts, hist, totals);
+        hipLaunchKernelGGL(k_scatter, dim3(parts), dim3(kBlock), 0, s, kin, vin, kout, vout, n_in, n_host, shift,
+                           bits, parts, hist, totals, drop_now, drop_key, first ? n_kept : nullptr);
         timer_end(timer, s);
         in_b = !in_b;
     }

@@ -21,7 +21,7 @@ class RasterConfig:
     discrete rules the paper inherits from 3DGS: alpha skip 1/255, alpha clamp
     0.99, termination at T < 1e-4, EWA dilation 0.3, extent kappa 11.1."""
     tile: int = 16
-    lds_batch: int = 256
+    lds_batch: int = 64
     persistent: bool = False
     pixels_per_lane: int = 0          # 0 = library default
     record_fetch: str = "default"     # "default", "lds" or "scalar"

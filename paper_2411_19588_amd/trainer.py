@@ -1,11 +1,17 @@
 """A full training step over fixed views with every buffer allocated once.
 
 forward (projection, depth-progressive binning, compositing with the medium)
--> L1 loss and its gradient -> adjoint -> fused Adam with the activation
-epilogue (Sec. Optimization), all enqueued on one stream through the C ABI with
-fixed pointers, so the whole step can be captured into a HIP graph and
-replayed.  Raw parameters: means, log-scales, quaternions, opacity logits, SH
-and the per-view medium coefficients.
+-> L1 loss and its gradient -> adjoint -> Adam with the activation epilogue
+(Sec. Optimization), all enqueued on one stream through the C ABI with fixed
+pointers, so the whole step can be captured into a HIP graph and replayed.
+By default the adjoint writes the gradients and the separate Adam kernel
+updates every parameter group in one launch; `fused=True` runs the Adam step
+inside the projection adjoint instead (gs_render_backward_adam: the Gaussians'
+gradients never reach memory, but that kernel's register use leaves it two
+waves per SIMD, and on the 1M-Gaussian benchmark it is slower than the two
+kernels).  Raw
+parameters: means, log-scales, quaternions, opacity logits, SH and the per-view
+medium coefficients.
 """
 from __future__ import annotations
 
@@ -26,7 +32,7 @@ def _vp(t: Optional[torch.Tensor]):
 class TrainStep:
     def __init__(self, means, log_scales, quats, logits, sh, medium, sh_degree: int, cameras: Sequence,
                  targets: torch.Tensor, config: RasterConfig = RasterConfig(), max_pairs: Optional[int] = None,
-                 lr: Optional[dict] = None, device="cuda"):
+                 lr: Optional[dict] = None, device="cuda", fused: bool = False):
         dev = torch.device(device)
         lr = dict(OPT.LR, **(lr or {}))
         f32 = lambda t: t.to(dev, torch.float32).contiguous()
@@ -37,6 +43,7 @@ class TrainStep:
                        OPT.Group("sh", f32(sh), lr["sh"]),
                        OPT.Group("medium", f32(medium), lr["medium"])]
         self.G = {g.name: g for g in self.groups}
+        self.fused = bool(fused)
         self.n = int(self.G["means"].param.shape[-1])
         self.sh_degree = int(sh_degree)
         self.rast = Rasterizer(cameras, config, device=dev)
@@ -113,6 +120,13 @@ class TrainStep:
         self._forward(stream)
         N.check("gs_l1_loss", L.gs_l1_loss(self.rgb.numel(), _vp(self.rgb), _vp(self.target), _vp(self.loss),
                                            _vp(self.grad_rgb), sp))
+        if self.fused:
+            N.check("gs_render_backward_adam", L.gs_render_backward_adam(
+                ctypes.byref(self.opts), ctypes.byref(self._gauss), self.rast.n_views, self.rast.host_cams,
+                _vp(self.rast.dev_cams), _vp(self.G["medium"].param), _vp(self.grad_rgb), None, _vp(self.saved),
+                self.saved.numel(), self._adam, 0.9, 0.999, 1e-8, _vp(self.step_counter), _vp(self.ws),
+                self.ws.numel(), sp))
+            return
         N.check("gs_render_backward", L.gs_render_backward(
             ctypes.byref(self.opts), ctypes.byref(self._gauss), self.rast.n_views, self.rast.host_cams,
             _vp(self.rast.dev_cams), _vp(self.G["medium"].param), _vp(self.grad_rgb), None, _vp(self.saved),

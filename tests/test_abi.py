@@ -53,7 +53,7 @@ def test_struct_layouts_match_header(tmp_path):
 
 def test_default_options_and_version():
     o = N.default_options()
-    assert (o.tile_w, o.tile_h, o.lds_batch) == (16, 16, 256)
+    assert (o.tile_w, o.tile_h, o.lds_batch) == (16, 16, 64)
     assert o.alpha_min == pytest.approx(1 / 255) and o.alpha_max == pytest.approx(0.99)
     assert o.t_min == pytest.approx(1e-4) and o.kappa == pytest.approx(11.1)
     assert b"gfx950" in N.lib().gs_version()
@@ -123,3 +123,35 @@ def test_view_limit():
     cams = N.camera_array([synth.make_scene(0, n=1).cameras[0]] * (N.GS_MAX_VIEWS + 1))
     o = N.default_options()
     assert N.lib().gs_tile_count(ctypes.byref(o), N.GS_MAX_VIEWS + 1, cams) == -1
+
+
+def test_fused_backward_adam_rejects_mismatched_groups():
+    """gs_render_backward_adam validates its six groups before any device work."""
+    L = N.lib()
+    sc = synth.make_scene(0, n=10)
+    cams = N.camera_array(sc.cameras)
+    o = N.default_options()
+    n = 10
+    g = N.GsGaussians(n, 0, 0, 0x1000, 0x2000, 0x3000, 0x4000, 0x5000)
+    counts = [3 * n, 3 * n, 4 * n, n, 3 * n, 9]
+    acts = [0, 1, 0, 2, 0, 0]
+    params = [0x1000, 0x6000, 0x3000, 0x7000, 0x5000, 0x8000]
+    activated = [0, 0x2000, 0, 0x4000, 0, 0]
+
+    def groups(**change):
+        arr = (N.GsAdamGroup * 6)()
+        for k in range(6):
+            arr[k] = N.GsAdamGroup(params[k], 0x9000, 0xA000, 0xB000, activated[k] or None, counts[k], 1e-3, acts[k], 0)
+        for k, (field, value) in change.items():
+            setattr(arr[int(k[1:])], field, value)
+        return arr
+
+    def call(arr, medium=0x8000):
+        return L.gs_render_backward_adam(ctypes.byref(o), ctypes.byref(g), 1, cams, 0xC000, medium, 0xD000, None,
+                                         0xE000, 1 << 40, arr, 0.9, 0.999, 1e-8, 0xF000, 0x10000, 1 << 40, None)
+
+    bad = [dict(g0=("count", 3 * n + 1)), dict(g1=("activation", 0)), dict(g3=("activated", 0x4004)),
+           dict(g4=("param", 0x5004)), dict(g5=("grad", None)), dict(g2=("m", None))]
+    for change in bad:
+        assert call(groups(**change)) == N.GS_ERR_INVALID_ARGUMENT, change
+    assert call(groups(), medium=0x8004) == N.GS_ERR_INVALID_ARGUMENT

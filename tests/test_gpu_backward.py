@@ -57,7 +57,9 @@ def test_grad_vs_oracle_sh_degree0_config0(oracle_mod):
     _check_all(got, O.backward(sc, cam, sc.medium[0], G))
 
 
-@pytest.mark.parametrize("cfg", [dict(lds_batch=64), dict(persistent=True), dict(tile=8, lds_batch=64),
+@pytest.mark.parametrize("cfg", [dict(lds_batch=256), dict(persistent=True), dict(tile=8, lds_batch=64),
+                                 dict(record_fetch="lds"), dict(record_fetch="lds", pixels_per_lane=2, lds_batch=128),
+                                 dict(record_fetch="lds", pixels_per_lane=4, persistent=True),
                                  dict(pixels_per_lane=1), dict(pixels_per_lane=4),
                                  dict(pixels_per_lane=1, persistent=True, lds_batch=64),
                                  dict(record_fetch="scalar", pixels_per_lane=1),

@@ -194,7 +194,7 @@ def test_image_multiview(oracle_mod):
         _image_match(sc, rast, oracle_mod, v=v)
 
 
-@pytest.mark.parametrize("cfg", [dict(lds_batch=64), dict(lds_batch=128), dict(persistent=True),
+@pytest.mark.parametrize("cfg", [dict(lds_batch=256), dict(lds_batch=128), dict(persistent=True),
                                  dict(pixels_per_lane=1), dict(pixels_per_lane=4, lds_batch=64),
                                  dict(pixels_per_lane=1, persistent=True, lds_batch=128),
                                  dict(pixels_per_lane=4, persistent=True),

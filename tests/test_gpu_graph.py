@@ -11,19 +11,21 @@ from tests import gpu_util as U
 pytestmark = pytest.mark.gpu
 
 
-def _make(sc, lr_scale=0.0, **cfg):
+def _make(sc, lr_scale=0.0, fused=True, **cfg):
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a))
     lr = {k: 0.0 for k in ("means", "scales", "quats", "opacity", "sh", "medium")} if lr_scale == 0.0 else None
     tgt = torch.cat([t(x).reshape(-1) for x in sc.targets])
     return TrainStep(t(sc.means), t(sc.log_scales), t(sc.quats), t(sc.logits), t(sc.sh), t(sc.medium),
-                     sc.sh_degree, sc.cameras, tgt, R.RasterConfig(**cfg), lr=lr)
+                     sc.sh_degree, sc.cameras, tgt, R.RasterConfig(**cfg), lr=lr, fused=fused)
 
 
 @pytest.mark.parametrize("cfg", [dict(), dict(persistent=True), dict(phases=1),
                                  dict(record_fetch="scalar", pixels_per_lane=1, persistent=True)])
 def test_graph_replay_matches_eager(cfg):
+    """Separate backward and Adam (so the gradients are visible); the fused step's replays are
+    covered by the trajectory tests below."""
     sc = synth.make_scene(1, n=20000, width=203, height=141)
-    ts = _make(sc, **cfg)
+    ts = _make(sc, fused=False, **cfg)
     ts.size_capacity()
     stream = torch.cuda.Stream()
     U.say(f"graph replay {cfg}")
@@ -46,11 +48,16 @@ def test_graph_replay_matches_eager(cfg):
             torch.cuda.synchronize()
             assert torch.equal(ts.rgb, ref_rgb), rep
             assert torch.allclose(ts.loss, ref_loss, rtol=1e-5, atol=0), rep
-            # gradients are accumulated with float atomics whose order varies between runs
-            # (waves reach a Gaussian in a different order): each run is within the 1e-3 parity
-            # bar of the exact gradient, so two runs agree within twice that bar
+            # the 2D gradients are accumulated with float atomics whose order varies between runs
+            # (waves reach a Gaussian in a different order); the projection adjoint then amplifies
+            # that rounding in elements that are small differences of large terms (quaternion
+            # components along the unit-norm direction).  Replays must agree with the eager step
+            # to twice the 1e-3 parity bar in norm, and element-wise up to 1e-2 of the field's rms.
             for g in ts.groups:
-                U.grad_close(g.grad.cpu().numpy(), ref_grads[g.name].cpu().numpy(), 2e-3, g.name)
+                got, ref = g.grad.cpu().numpy().astype(np.float64), ref_grads[g.name].cpu().numpy().astype(np.float64)
+                rms = float(np.sqrt(np.mean(ref ** 2)))
+                assert np.linalg.norm(got - ref) <= 2e-3 * np.linalg.norm(ref) + 1e-30, g.name
+                assert np.all(np.abs(got - ref) <= 2e-3 * np.abs(ref) + 1e-2 * rms + 1e-30), g.name
     assert int(ts.step_counter.item()) == 4
     st, _ = ts.status(stream)
     assert st == 0
@@ -72,6 +79,59 @@ def test_graph_training_steps_track_eager():
             b.replay(stream)
         torch.cuda.synchronize()
     U.say("graph training trajectory")
+    for ga, gb in zip(a.groups, b.groups):
+        d = (ga.param - gb.param).abs().max().item()
+        assert d <= 6 * ga.lr + 1e-6, (ga.name, d)
+    assert abs(a.loss.item() - b.loss.item()) <= 1e-4 * a.loss.item()
+
+
+def _state(ts):
+    return {g.name: [t.detach().clone() for t in (g.param, g.m, g.v) + ((g.activated,) if g.activated is not None
+                                                                         else ())] for g in ts.groups}
+
+
+def test_fused_adam_matches_separate_kernels():
+    """gs_render_backward_adam (Adam inside the projection adjoint) against gs_render_backward followed
+    by gs_adam_step_device.  One 16x16 tile rendered by one wave accumulates every 2D gradient in a
+    fixed order, so the two paths see identical gradients and must agree bit for bit."""
+    sc = synth.make_scene(1, n=400, width=16, height=16)
+    a = _make(sc, lr_scale=1.0)
+    b = TrainStepUnfused(sc)
+    a.size_capacity()
+    b.size_capacity()
+    stream = torch.cuda.Stream()
+    U.say("fused adam vs separate")
+    with torch.cuda.stream(stream):
+        for step in range(3):
+            a.enqueue(stream)
+            b.enqueue(stream)
+            torch.cuda.synchronize()
+            sa, sb = _state(a), _state(b)
+            for name in sa:
+                for x, y in zip(sa[name], sb[name]):
+                    assert torch.equal(x, y), (step, name)
+    assert int(a.step_counter.item()) == 3 and int(b.step_counter.item()) == 3
+
+
+def TrainStepUnfused(sc):
+    return _make(sc, lr_scale=1.0, fused=False)
+
+
+def test_fused_adam_trajectory_tracks_separate_kernels():
+    """On a multi-tile scene the atomics' order varies, so the paths agree up to Adam's sensitivity
+    to gradient rounding: within a few learning rates after three steps."""
+    sc = synth.make_scene(1, n=5000, width=96, height=64)
+    a = _make(sc, lr_scale=1.0)
+    b = TrainStepUnfused(sc)
+    a.size_capacity()
+    b.size_capacity()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            a.enqueue(stream)
+            b.enqueue(stream)
+        torch.cuda.synchronize()
+    U.say("fused adam trajectory")
     for ga, gb in zip(a.groups, b.groups):
         d = (ga.param - gb.param).abs().max().item()
         assert d <= 6 * ga.lr + 1e-6, (ga.name, d)
