@@ -73,7 +73,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=2, help="oracle sample: every k-th pixel in x and y")
     ap.add_argument("--no-timer", action="store_true", help="skip the per-kernel HIP event timer")
-    ap.add_argument("--phases", type=int, default=3, help="depth-progressive binning phases (1 = full binning)")
+    ap.add_argument("--phases", type=int, default=2, help="depth-progressive binning phases (1 = full binning)")
+    ap.add_argument("--phase0-shift", type=int, default=0,
+                    help="first depth phase = nearest 1/2^shift of the visible Gaussians (0 = library default)")
     ap.add_argument("--eager", action="store_true", help="time eager launches only (no HIP graph replay)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 24-view batched-vs-per-view forward+backward comparison")
@@ -169,9 +171,9 @@ def cpu_baseline(scene, target, stride: int):
 
 def batched_compare(args, dev):
     """24 views of uneven resolution (1M Gaussians, SH 3): forward + L1 + backward of all views
-    in one pipeline (persistent tile queue, launch shape from the autotuner, one HIP graph)
+    in one pipeline (launch shape and depth-phase schedule from the autotuner, one HIP graph)
     against one pipeline per view (24 forward + backward sequences in one HIP graph, same
-    shape).  The per-view side leaves the gradients per view (the batched side sums them over
+    configuration).  The per-view side leaves the gradients per view (the batched side sums them over
     the views in its projection adjoint), so it is timed doing less work than the batched one."""
     import torch
     from paper_2411_19588_amd import _native as N
@@ -191,9 +193,9 @@ def batched_compare(args, dev):
     log(f"batched: {len(sizes)} views, {P} pixels; autotuning the launch shape")
     measure = A.render_step_timer(params, sc.sh_degree, sc.cameras, med, tgt_all, reps=3, device=dev)
     t0 = time.perf_counter()
-    cfg = A.tune(measure, R.RasterConfig(), A.candidates(), log=log)
+    cfg = A.tune_all(measure, R.RasterConfig(), log=log)
     tune_s = time.perf_counter() - t0
-    shape = {k: getattr(cfg, k) for k in A.SHAPE_FIELDS}
+    shape = {k: getattr(cfg, k) for k in A.FIELDS}
     log(f"autotuned shape {shape} ({tune_s:.1f} s)")
     stream = torch.cuda.Stream(device=dev)
     K = args.batched_steps
@@ -302,6 +304,7 @@ def main():
     ncoef = (sc.sh_degree + 1) ** 2
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a))
     cfg = R.RasterConfig(tile=args.tile, lds_batch=args.lds_batch, persistent=args.persistent, phases=args.phases,
+                         phase0_shift=args.phase0_shift,
                          pixels_per_lane=args.ppl, record_fetch=args.fetch, tile_cull=not args.no_tile_cull)
     ts = TrainStep(t(sc.means), t(sc.log_scales), t(sc.quats), t(sc.logits), t(sc.sh), t(sc.medium), sc.sh_degree,
                    sc.cameras, torch.cat([t(x).reshape(-1) for x in sc.targets]), cfg, device=dev,
@@ -353,6 +356,11 @@ def main():
     N.check("gs_forward_stats", N.lib().gs_forward_stats(ctypes.byref(ts.opts), ts.n, 1, ts.rast.host_cams,
                                                          ctypes.c_void_p(ts.saved.data_ptr()), ts.saved.numel(),
                                                          stats, ctypes.c_void_p(stream.cuda_stream)))
+    # pairs per depth phase (from the stored per-phase tile ranges)
+    _, _, rng = ts.rast.export_keys(R.ForwardContext(ts.saved, ts.max_pairs, ts.n, sc.sh_degree), stream)
+    rng = rng.to(torch.int64)
+    phase_pairs = [int((rng[p, :, 1] - rng[p, :, 0]).sum().item()) for p in range(cfg.phases)]
+    log(f"live pairs per phase: {phase_pairs}")
     # full (single-phase) binning pair count of the same scene, for K/N
     # (the method's rectangle binning, no culling)
     full = R.Rasterizer(sc.cameras, R.RasterConfig(phases=1, tile_cull=False, max_pairs=int(K * 8)), device=dev)
@@ -423,13 +431,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{sc.n} Gaussians SH{sc.sh_degree}, "
                                f"{' + '.join(f'{w}x{h}' for w, h in sizes)}, {sc.n_views} view(s), "
-                               "training step (forward + L1 + backward + fused Adam)",
+                               "training step (forward + L1 + backward + Adam)",
                    "n_gaussians": sc.n, "sh_degree": sc.sh_degree, "width": cam.width, "height": cam.height,
                    "views": sc.n_views, "tile": args.tile, "lds_batch": args.lds_batch, "persistent": bool(args.persistent),
                    "pixels_per_lane": args.ppl, "record_fetch": args.fetch,
-                   "phases": cfg.phases, "mode": "eager" if args.eager else "hip_graph",
+                   "phases": cfg.phases, "phase0_shift": args.phase0_shift, "mode": "eager" if args.eager else "hip_graph",
                    "pairs_stored": int(K), "pairs_full_binning": int(K_full),
                    "pairs_per_gaussian": round(K_full / sc.n, 2), "pairs_live": int(stats[0]),
+                   "pairs_live_per_phase": phase_pairs,
                    "evals_per_pixel": round(stats[1] / P, 1), "blends_per_pixel": round(stats[4] / P, 1),
                    "tile_cull": bool(cfg.tile_cull), "adam": "fused" if args.fused_adam else "separate"},
         "eager_ms_per_step": round(eager_ms, 4),

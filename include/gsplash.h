@@ -130,14 +130,19 @@ typedef struct gs_options {
                                             the rectangle, as in the method's binning */
     int32_t phases;                      /* depth-progressive binning: 1 = bin every (Gaussian, tile) pair at
                                             once; 2..4 = bin the depth-sorted Gaussians in that many rank
-                                            ranges (nearest 1/32 | 1/8 | rest for 3) and, after each range,
-                                            only for tiles that still have a pixel above t_min (default 3).
-                                            Images are identical for every value. */
+                                            ranges (by default nearest 1/128 | rest for 2, nearest 1/128 |
+                                            1/32 | rest for 3) and, after each range, only for tiles that
+                                            still have a pixel above t_min, walking only the alive columns
+                                            of each tile row (default 2).  Images are identical for every
+                                            value. */
+    int32_t phase0_shift;                /* the first range is the nearest 1/2^shift of the visible
+                                            Gaussians, each later one (but the last) 4x wider: 1..20;
+                                            0 = default (7).  Images are identical for every value. */
     int64_t max_pairs;                   /* capacity of the stored (Gaussian, tile) pair list, <= GS_MAX_PAIRS */
     void* timer;                         /* optional gs_timer* receiving per-kernel HIP events; NULL = none */
 } gs_options;
 
-/* Fill `opts` with the defaults above (phases = 3, max_pairs = 1 << 24). */
+/* Fill `opts` with the defaults above (phases = 2, max_pairs = 1 << 24). */
 void gs_default_options(gs_options* opts);
 
 /* Library version string (static storage). */

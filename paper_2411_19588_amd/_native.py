@@ -58,7 +58,7 @@ class GsOptions(ctypes.Structure):
                 ("record_fetch", ctypes.c_int32), ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("t_min", ctypes.c_float), ("dilation", ctypes.c_float), ("kappa", ctypes.c_float),
                 ("depth_mode", ctypes.c_int32), ("tile_cull", ctypes.c_int32),
-                ("phases", ctypes.c_int32), ("max_pairs", ctypes.c_int64),
+                ("phases", ctypes.c_int32), ("phase0_shift", ctypes.c_int32), ("max_pairs", ctypes.c_int64),
                 ("timer", ctypes.c_void_p)]
 
 

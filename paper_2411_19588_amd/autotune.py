@@ -1,11 +1,12 @@
-"""Launch-shape autotuner for the rasterizer.
+"""Launch-shape and binning-schedule autotuner for the rasterizer.
 
 Times forward + L1 + backward over the caller's own workload (Gaussians, camera list,
 medium) for a set of launch shapes -- tile size, pixels per lane (waves per tile), how
 the compositing waves receive records (LDS batches or the scalar cache), LDS batch
-size, persistent tile queue -- and returns the fastest as a RasterConfig.  Every
-shape renders bit-identical images, so the choice only affects speed.  Results are
-cached in a JSON file keyed by the device and a coarse description of the workload.
+size, persistent tile queue -- and then for depth-phase schedules (number of phases,
+size of the first), and returns the fastest as a RasterConfig.  Every choice renders
+bit-identical images, so it only affects speed.  Results are cached in a JSON file
+keyed by the device and a coarse description of the workload.
 """
 from __future__ import annotations
 
@@ -19,6 +20,8 @@ from typing import Callable, Dict, Iterable, List, Optional, Sequence
 from .rasterizer import RasterConfig
 
 SHAPE_FIELDS = ("tile", "pixels_per_lane", "record_fetch", "lds_batch", "persistent")
+SCHEDULE_FIELDS = ("phases", "phase0_shift")
+FIELDS = SHAPE_FIELDS + SCHEDULE_FIELDS
 
 
 def candidates(tiles=(16, 8), persistent=(False, True)) -> List[dict]:
@@ -35,6 +38,11 @@ def candidates(tiles=(16, 8), persistent=(False, True)) -> List[dict]:
                     out.append(dict(tile=16, pixels_per_lane=ppl, record_fetch="lds", lds_batch=lb, persistent=pers))
                 out.append(dict(tile=16, pixels_per_lane=ppl, record_fetch="scalar", lds_batch=256, persistent=pers))
     return out
+
+
+def schedules() -> List[dict]:
+    """Depth-phase schedules worth timing: the nearest 1/2^shift of the Gaussians first."""
+    return [dict(phases=p, phase0_shift=sh) for p, sh in ((2, 5), (2, 6), (2, 7), (3, 5), (3, 6), (4, 6))]
 
 
 def workload_key(device_name: str, n: int, sh_degree: int, sizes: Sequence) -> str:
@@ -82,7 +90,7 @@ def store_cache(path: Optional[str], key: str, entry: dict) -> None:
 
 
 def apply(base: RasterConfig, shape: dict) -> RasterConfig:
-    return dataclasses.replace(base, **{k: shape[k] for k in SHAPE_FIELDS if k in shape})
+    return dataclasses.replace(base, **{k: shape[k] for k in FIELDS if k in shape})
 
 
 def tune(measure: Callable[[RasterConfig], float], base: RasterConfig = RasterConfig(),
@@ -113,6 +121,14 @@ def tune(measure: Callable[[RasterConfig], float], base: RasterConfig = RasterCo
         store_cache(cache_path, key, {"shape": shapes[best], "ms": timings[best],
                                       "timed": [[shapes[i], timings[i]] for i in sorted(timings)]})
     return apply(base, shapes[best])
+
+
+def tune_all(measure: Callable[[RasterConfig], float], base: RasterConfig = RasterConfig(),
+             cache_path: Optional[str] = None, key: Optional[str] = None,
+             log: Optional[Callable[[str], None]] = None) -> RasterConfig:
+    """Launch shape first (at the base schedule), then the depth-phase schedule at that shape."""
+    shape = tune(measure, base, candidates(), cache_path, None if key is None else key + "|shape", log)
+    return tune(measure, shape, schedules(), cache_path, None if key is None else key + "|schedule", log)
 
 
 def render_step_timer(params: dict, sh_degree: int, cameras: Sequence, medium, targets, reps: int = 3,

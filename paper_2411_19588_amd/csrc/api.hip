@@ -48,6 +48,7 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     if (o->record_fetch < GS_FETCH_DEFAULT || o->record_fetch > GS_FETCH_SCALAR) return GS_ERR_INVALID_ARGUMENT;
     if (o->tile_cull != 0 && o->tile_cull != 1) return GS_ERR_INVALID_ARGUMENT;
     if (o->phases < 0 || o->phases > GS_MAX_PHASES) return GS_ERR_INVALID_ARGUMENT;
+    if (o->phase0_shift < 0 || o->phase0_shift > 20) return GS_ERR_INVALID_ARGUMENT;
     if (o->max_pairs < 0 || o->max_pairs > GS_MAX_PAIRS) return GS_ERR_INVALID_ARGUMENT;
     if (n * (int64_t)n_views >= (int64_t)0xFFFFFFFFLL) return GS_ERR_INVALID_ARGUMENT;
 
@@ -55,11 +56,12 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     L->n = n;
     L->views = n_views;
     L->phases = o->phases == 0 ? kDefaultPhases : o->phases;
+    L->phase0_shift = o->phase0_shift != 0 ? o->phase0_shift : kDefaultPhase0Shift;
     L->nv = n * n_views;
     L->max_pairs = o->max_pairs;
     L->tile_w = o->tile_w;
     L->tile_h = o->tile_h;
-    int64_t tiles = 0, pixels = 0;
+    int64_t tiles = 0, pixels = 0, rows = 0;
     for (int v = 0; v < n_views; ++v) {
         const gs_camera& c = cams[v];
         if (c.width < 1 || c.height < 1 || c.width > 32768 || c.height > 32768) return GS_ERR_INVALID_ARGUMENT;
@@ -72,12 +74,16 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
         vi.tile_base = (uint32_t)tiles;
         vi.n_tiles = (uint32_t)(vi.tiles_x * vi.tiles_y);
         vi.pix_base = pixels;
+        vi.row_base = (uint32_t)rows;
+        vi.pad = 0;
+        rows += vi.tiles_y;
         tiles += (int64_t)vi.n_tiles;
         pixels += (int64_t)c.width * c.height;
     }
     L->table.count = n_views;
     if (tiles >= (1LL << 31)) return GS_ERR_INVALID_ARGUMENT;
     L->tiles = tiles;
+    L->rows = rows;
     L->pixels = pixels;
     int bits = 1;   // tile ids 0..tiles-1 plus the id `tiles` of culled pairs
     while ((1LL << bits) <= tiles) ++bits;
@@ -129,6 +135,7 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     L->w_grad2d = w.take(nv * kGrad2D * 4);
     L->w_medpart = w.take(T * 9 * 4 + 256);   // + persistent-mode tile counter of the backward
     L->w_adam = w.take(16);                    // bias corrections of a fused Adam step
+    L->w_rowspan = w.take(rows * 8);           // alive columns per tile row (later depth phases)
     L->workspace_bytes = w.at;
     return GS_OK;
 }
@@ -280,9 +287,9 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
     int in_b = 0;
     if (L.nv > 0)
         GS_TRY(radix_sort_u32(dk, dv, dk2, dv2, nullptr, (uint32_t)L.nv, 0, 32, L.depth_parts, hist, &in_b,
-                              "depth_sort", T, s));
+                              "depth_sort", T, s, 1, 0xFFFFFFFFu, &hdr->visible));   // entries with no tile left out
     const uint32_t* order = in_b ? dv2 : dv;
-    GS_TRY(launch_visible(in_b ? dk2 : dk, L.nv, L.phases, hdr, s));
+    GS_TRY(launch_visible(L.phases, L.phase0_shift, hdr, s));
     float* tfinal = at<float>(saved, L.s_tfinal);
     uint32_t* nlast = at<uint32_t>(saved, L.s_nlast);
     uint8_t* done = at<uint8_t>(saved, L.s_done);
@@ -290,16 +297,22 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
     float* dsum = at<float>(saved, L.s_dsum);
     float* wsum = at<float>(saved, L.s_wsum);
     const CullArgs cull{rec, log2f(o.alpha_min), o.tile_w, o.tile_h, o.tile_cull};
+    uint2* rowspan = at<uint2>(workspace, L.w_rowspan);
     for (int ph = 0; ph < L.phases; ++ph) {
+        if (ph > 0) {
+            timer_begin(T, "alive_rows", s);
+            GS_TRY(launch_alive_rows(vt, L.views, L.rows, alive, rowspan, s));
+            timer_end(T, s);
+        }
         timer_begin(T, "phase_count", s);
-        GS_TRY(launch_phase_count(order, counts, rects, L.nv, L.n, vt, alive, hdr, ph, cull, pcounts, s));
+        GS_TRY(launch_phase_count(order, counts, rects, L.nv, L.n, vt, alive, rowspan, hdr, ph, cull, pcounts, s));
         timer_end(T, s);
         timer_begin(T, "count_scan", s);
         GS_TRY(launch_count_scan(pcounts, L.nv, offsets, blocksums, hdr, ph, L.max_pairs, emit_start, s));
         timer_end(T, s);
         timer_begin(T, "emit", s);
-        GS_TRY(launch_emit(order, offsets, emit_start, pcounts, rects, L.nv, L.n, vt, alive, hdr, ph, L.max_pairs,
-                           cull, (uint32_t)L.tiles, tiles_a, vals_a, s));
+        GS_TRY(launch_emit(order, offsets, emit_start, pcounts, rects, L.nv, L.n, vt, alive, rowspan, hdr, ph,
+                           L.max_pairs, cull, (uint32_t)L.tiles, tiles_a, vals_a, s));
         timer_end(T, s);
         // stable sort of the phase's pairs by tile id
         int tb = 0;

@@ -83,24 +83,17 @@ __global__ void k_view_table(ViewTable t, ViewInfo* dst, SavedHeader* hdr) {
     }
 }
 
-// First index of 0xFFFFFFFF in the sorted depth keys = number of visible entries;
-// phase p covers ranks up to ceil(visible / 2^shift) with shifts from the table below.
-__global__ void k_visible(const uint32_t* __restrict__ keys, int64_t nv, int phases, SavedHeader* hdr) {
-    int64_t lo = 0, hi = nv;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (keys[mid] != 0xFFFFFFFFu) lo = mid + 1;
-        else hi = mid;
-    }
-    const uint32_t V = (uint32_t)lo;
-    hdr->visible = V;
-    // rank cut-offs as fractions of the visible entries: {1}, {1/32, 1}, {1/32, 1/8, 1}, {1/64, 1/16, 1/4, 1}
-    const int shifts[GS_MAX_PHASES + 1][GS_MAX_PHASES] = {
-        {0, 0, 0, 0}, {0, 0, 0, 0}, {5, 0, 0, 0}, {5, 3, 0, 0}, {6, 4, 2, 0}};
+// The depth sort left out the entries that touch no tile (key 0xFFFFFFFF) and wrote the number
+// of visible entries it kept; phase p < phases - 1 covers depth ranks up to
+// ceil(visible / 2^(shift - 2p)) (the whole range once the exponent reaches 0), the last phase
+// the rest.
+__global__ void k_visible(int phases, int shift, SavedHeader* hdr) {
+    const uint32_t V = hdr->visible;
     hdr->phase_rank[0] = 0;
     for (int p = 0; p < phases; ++p) {
+        const int e = shift - 2 * p;
         uint32_t r = V;
-        if (p + 1 < phases) r = (uint32_t)(((uint64_t)V + (1ull << shifts[phases][p]) - 1) >> shifts[phases][p]);
+        if (p + 1 < phases && e > 0) r = (uint32_t)(((uint64_t)V + (1ull << e) - 1) >> e);
         hdr->phase_rank[p + 1] = r;
     }
 }
@@ -110,6 +103,7 @@ __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restri
                                                        const uint2* __restrict__ rects, int64_t nv, int64_t n,
                                                        const ViewInfo* __restrict__ vt,
                                                        const uint32_t* __restrict__ alive,
+                                                       const uint2* __restrict__ rowspan,
                                                        const SavedHeader* __restrict__ hdr, int phase,
                                                        CullArgs cull, uint32_t* __restrict__ pcounts) {
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -131,8 +125,11 @@ __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restri
                 rb = make_float2(cull.rec[e].b.x, cull.rec[e].b.y);
             }
             for (uint32_t ty = y0; ty <= y1; ++ty) {
+                // only the alive part of the row: a later phase walks few tiles of most rectangles
+                const uint2 sp = rowspan[vi.row_base + ty];
+                const uint32_t lo = max(x0, sp.x), hi = min(x1, sp.y);
                 const uint32_t row = vi.tile_base + ty * (uint32_t)vi.tiles_x;
-                for (uint32_t tx = x0; tx <= x1; ++tx)
+                for (uint32_t tx = lo; tx <= hi; ++tx)
                     c += alive[row + tx] != 0u && (!cull.enabled || tile_may_contribute(ra, rb, vi, tx, ty, cull));
             }
         }
@@ -140,9 +137,19 @@ __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restri
     pcounts[r] = c;
 }
 
+// A later phase after which no tile was left alive emits nothing: the scan kernels skip it.
+__device__ __forceinline__ bool phase_empty(const SavedHeader* hdr, int phase) {
+    return phase > 0 && hdr->phase_alive[phase - 1] == 0;
+}
+
 __global__ __launch_bounds__(kBlock) void k_count_reduce(const uint32_t* __restrict__ pcounts, int64_t nv,
+                                                        const SavedHeader* __restrict__ hdr, int phase,
                                                         uint64_t* __restrict__ blocksums) {
     __shared__ uint64_t red[kBlock];
+    if (phase_empty(hdr, phase)) {
+        if (threadIdx.x == 0) blocksums[blockIdx.x] = 0;
+        return;
+    }
     const int64_t b0 = (int64_t)blockIdx.x * kScanChunk;
     uint64_t s = 0;
     for (int k = 0; k < 16; ++k) {
@@ -200,9 +207,11 @@ __global__ __launch_bounds__(1024) void k_count_blocks(uint64_t* blocksums, int 
 
 __global__ __launch_bounds__(kBlock) void k_count_down(const uint32_t* __restrict__ pcounts, int64_t nv,
                                                       const uint64_t* __restrict__ blocksums,
+                                                      const SavedHeader* __restrict__ hdr, int phase,
                                                       uint64_t* __restrict__ offsets, uint32_t* __restrict__ emit_start,
                                                       int64_t n_spans) {
     __shared__ uint64_t part[kBlock];
+    if (phase_empty(hdr, phase)) return;   // every count is 0: no entry reads its offset
     const int tid = threadIdx.x;
     const int64_t b0 = (int64_t)blockIdx.x * kScanChunk + (int64_t)tid * 16;   // 16 consecutive per thread
     uint32_t c[16];
@@ -326,6 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_alive(const uint32_t* __restric
                                                       const uint2* __restrict__ rects, int64_t nv, int64_t n,
                                                       const ViewInfo* __restrict__ vt,
                                                       const uint32_t* __restrict__ alive,
+                                                      const uint2* __restrict__ rowspan,
                                                       const SavedHeader* __restrict__ hdr, int phase,
                                                       CullArgs cull, uint32_t* __restrict__ tiles_out,
                                                       uint32_t* __restrict__ vals_out) {
@@ -348,8 +358,10 @@ __global__ __launch_bounds__(kBlock) void k_emit_alive(const uint32_t* __restric
         rb = make_float2(cull.rec[e].b.x, cull.rec[e].b.y);
     }
     for (uint32_t ty = y0; ty <= y1 && off < end; ++ty) {
+        const uint2 sp = rowspan[vi.row_base + ty];
+        const uint32_t lo = max(x0, sp.x), hi = min(x1, sp.y);
         const uint32_t row = vi.tile_base + ty * (uint32_t)vi.tiles_x;
-        for (uint32_t tx = x0; tx <= x1 && off < end; ++tx) {
+        for (uint32_t tx = lo; tx <= hi && off < end; ++tx) {
             if (alive[row + tx] == 0u) continue;
             if (cull.enabled && !tile_may_contribute(ra, rb, vi, tx, ty, cull)) continue;
             tiles_out[off] = row + tx;
@@ -357,6 +369,29 @@ __global__ __launch_bounds__(kBlock) void k_emit_alive(const uint32_t* __restric
             ++off;
         }
     }
+}
+
+// One wave per global tile row: the first and last column whose tile is still alive.
+__global__ __launch_bounds__(64) void k_alive_rows(const ViewInfo* __restrict__ vt, int32_t views,
+                                                  const uint32_t* __restrict__ alive, uint2* __restrict__ rowspan) {
+    const uint32_t r = blockIdx.x;
+    int v = 0;
+    while (v + 1 < views && r >= vt[v + 1].row_base) ++v;
+    const ViewInfo vi = vt[v];
+    const uint32_t ty = r - vi.row_base;
+    uint32_t lo = 0xFFFFFFFFu, hi = 0;
+    for (uint32_t tx = threadIdx.x; tx < (uint32_t)vi.tiles_x; tx += 64) {
+        if (alive[vi.tile_base + ty * (uint32_t)vi.tiles_x + tx] != 0u) {
+            lo = min(lo, tx);
+            hi = max(hi, tx);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = min(lo, (uint32_t)__shfl_xor((int)lo, off));
+        hi = max(hi, (uint32_t)__shfl_xor((int)hi, off));
+    }
+    if (threadIdx.x == 0) rowspan[r] = lo == 0xFFFFFFFFu ? make_uint2(1u, 0u) : make_uint2(lo, hi);
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t* p, uint32_t value, int64_t count) {
@@ -405,18 +440,26 @@ hipError_t launch_view_table(const ViewTable& t, int phases, ViewInfo* dst, Save
     return hipGetLastError();
 }
 
-hipError_t launch_visible(const uint32_t* sorted_keys, int64_t nv, int phases, SavedHeader* hdr, hipStream_t s) {
-    hipLaunchKernelGGL(k_visible, dim3(1), dim3(1), 0, s, sorted_keys, nv, phases, hdr);
+hipError_t launch_visible(int phases, int phase0_shift, SavedHeader* hdr, hipStream_t s) {
+    hipLaunchKernelGGL(k_visible, dim3(1), dim3(1), 0, s, phases, phase0_shift, hdr);
     return hipGetLastError();
 }
 
 hipError_t launch_phase_count(const uint32_t* order, const uint32_t* counts, const uint2* rects, int64_t nv,
-                              int64_t n, const ViewInfo* vt, const uint32_t* alive, const SavedHeader* hdr,
-                              int phase, const CullArgs& cull, uint32_t* pcounts, hipStream_t s) {
+                              int64_t n, const ViewInfo* vt, const uint32_t* alive, const uint2* rowspan,
+                              const SavedHeader* hdr, int phase, const CullArgs& cull, uint32_t* pcounts,
+                              hipStream_t s) {
     if (nv == 0) return hipSuccess;
     const unsigned grid = (unsigned)((nv + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_phase_count, dim3(grid), dim3(kBlock), 0, s, order, counts, rects, nv, n, vt, alive, hdr,
-                       phase, cull, pcounts);
+    hipLaunchKernelGGL(k_phase_count, dim3(grid), dim3(kBlock), 0, s, order, counts, rects, nv, n, vt, alive,
+                       rowspan, hdr, phase, cull, pcounts);
+    return hipGetLastError();
+}
+
+hipError_t launch_alive_rows(const ViewInfo* vt, int32_t views, int64_t rows, const uint32_t* alive, uint2* rowspan,
+                             hipStream_t s) {
+    if (rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_alive_rows, dim3((unsigned)rows), dim3(64), 0, s, vt, views, alive, rowspan);
     return hipGetLastError();
 }
 
@@ -424,19 +467,19 @@ hipError_t launch_count_scan(const uint32_t* pcounts, int64_t nv, uint64_t* offs
                              SavedHeader* hdr, int phase, int64_t max_pairs, uint32_t* emit_start, hipStream_t s) {
     const int nb = (int)((nv + kScanChunk - 1) / kScanChunk);
     const int64_t n_spans = max_pairs / kEmitSpan + 2;
-    if (nb > 0) hipLaunchKernelGGL(k_count_reduce, dim3(nb), dim3(kBlock), 0, s, pcounts, nv, blocksums);
+    if (nb > 0) hipLaunchKernelGGL(k_count_reduce, dim3(nb), dim3(kBlock), 0, s, pcounts, nv, hdr, phase, blocksums);
     hipLaunchKernelGGL(k_count_blocks, dim3(1), dim3(1024), 0, s, blocksums, nb, hdr, phase, max_pairs);
     if (nb > 0)
-        hipLaunchKernelGGL(k_count_down, dim3(nb), dim3(kBlock), 0, s, pcounts, nv, blocksums, offsets, emit_start,
-                           n_spans);
+        hipLaunchKernelGGL(k_count_down, dim3(nb), dim3(kBlock), 0, s, pcounts, nv, blocksums, hdr, phase, offsets,
+                           emit_start, n_spans);
     return hipGetLastError();
 }
 
 hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uint32_t* emit_start,
                        const uint32_t* pcounts, const uint2* rects, int64_t nv, int64_t n, const ViewInfo* vt,
-                       const uint32_t* alive, const SavedHeader* hdr, int phase, int64_t max_pairs,
-                       const CullArgs& cull, uint32_t n_tiles, uint32_t* tiles_out, uint32_t* vals_out,
-                       hipStream_t s) {
+                       const uint32_t* alive, const uint2* rowspan, const SavedHeader* hdr, int phase,
+                       int64_t max_pairs, const CullArgs& cull, uint32_t n_tiles, uint32_t* tiles_out,
+                       uint32_t* vals_out, hipStream_t s) {
     if (nv == 0 || max_pairs == 0) return hipSuccess;
     if (phase == 0) {
         const unsigned grid = (unsigned)((max_pairs + kEmitSpan - 1) / kEmitSpan);
@@ -445,7 +488,7 @@ hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uin
     } else {
         const unsigned grid = (unsigned)((nv + kBlock - 1) / kBlock);
         hipLaunchKernelGGL(k_emit_alive, dim3(grid), dim3(kBlock), 0, s, order, offsets, pcounts, rects, nv, n, vt,
-                           alive, hdr, phase, cull, tiles_out, vals_out);
+                           alive, rowspan, hdr, phase, cull, tiles_out, vals_out);
     }
     return hipGetLastError();
 }

@@ -15,7 +15,8 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kMaxSortParts = 1024;
 constexpr int kGrad2D = 10;              // per-(Gaussian, view) 2D gradient: m(2), conic'(3), o, rgb(3), depth
-constexpr int kDefaultPhases = 3;
+constexpr int kDefaultPhases = 2;
+constexpr int kDefaultPhase0Shift = 7;        // first depth phase: the nearest 1/128 of the visible Gaussians
 // Compositing launch shape when gs_options leaves it unset (16x16 tiles).
 constexpr int kDefaultPixelsPerLaneFwd = 2;   // two waves per tile
 constexpr int kDefaultRecordFetchFwd = GS_FETCH_LDS;
@@ -28,6 +29,8 @@ struct ViewInfo {
     uint32_t tile_base;                  // first global tile id of the view
     uint32_t n_tiles;
     int64_t pix_base;                    // first pixel of the view in the packed outputs
+    uint32_t row_base;                   // first global tile row of the view
+    uint32_t pad;
 };
 
 struct ViewTable {
@@ -61,8 +64,8 @@ struct SavedHeader {
 };
 
 struct Layout {
-    int64_t n, nv, pixels, tiles, max_pairs;
-    int32_t views, phases;
+    int64_t n, nv, pixels, tiles, rows, max_pairs;
+    int32_t views, phases, phase0_shift;
     int32_t tile_w, tile_h, tile_bits, tile_passes, pair_parts, depth_parts;
     ViewTable table;
     // saved context offsets (bytes)
@@ -70,7 +73,7 @@ struct Layout {
     size_t s_tfinal, s_nlast, s_done, s_cair, s_dsum, s_wsum, saved_bytes;
     // workspace offsets (bytes)
     size_t w_counts, w_rects, w_dkeys, w_dvals, w_dkeys2, w_dvals2, w_pcounts, w_offsets, w_blocksums, w_emit_start;
-    size_t w_tiles_a, w_vals_a, w_tiles_b, w_vals_b, w_hist, w_grad2d, w_medpart, w_adam, workspace_bytes;
+    size_t w_tiles_a, w_vals_a, w_tiles_b, w_vals_b, w_hist, w_grad2d, w_medpart, w_adam, w_rowspan, workspace_bytes;
 };
 
 int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_camera* cams, Layout* L);
@@ -115,8 +118,8 @@ hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, 
                           const uint32_t* n_dev, uint32_t n_host, int bit0, int nbits, int parts, uint32_t* hist,
                           int* out_in_b, const char* tag, void* timer, hipStream_t s, int use_drop = 0,
                           uint32_t drop_key = 0, uint32_t* n_kept = nullptr);
-// Number of visible entries (depth-sorted keys before the first 0xFFFFFFFF) and the phase rank ranges.
-hipError_t launch_visible(const uint32_t* sorted_keys, int64_t nv, int phases, SavedHeader* hdr, hipStream_t s);
+// Phase rank ranges from the number of visible entries the depth sort kept.
+hipError_t launch_visible(int phases, int phase0_shift, SavedHeader* hdr, hipStream_t s);
 // Per-entry pair counts of phase p (by depth rank): whole rectangles in phase 0, only the tiles
 // still alive in later phases, 0 outside the phase's ranks.
 // Exact tile culling: a (Gaussian, tile) pair of the rectangle is dropped when no pixel centre
@@ -129,8 +132,12 @@ struct CullArgs {
 };
 
 hipError_t launch_phase_count(const uint32_t* order, const uint32_t* counts, const uint2* rects, int64_t nv,
-                              int64_t n, const ViewInfo* vt, const uint32_t* alive, const SavedHeader* hdr,
-                              int phase, const CullArgs& cull, uint32_t* pcounts, hipStream_t s);
+                              int64_t n, const ViewInfo* vt, const uint32_t* alive, const uint2* rowspan,
+                              const SavedHeader* hdr, int phase, const CullArgs& cull, uint32_t* pcounts,
+                              hipStream_t s);
+// Per global tile row, the first and last alive tile column (x > y when the row has none).
+hipError_t launch_alive_rows(const ViewInfo* vt, int32_t views, int64_t rows, const uint32_t* alive, uint2* rowspan,
+                             hipStream_t s);
 // Exclusive scan of pcounts into offsets (u64) and the phase's pair count and base in hdr (with the
 // capacity check), and for each emission span of 1024 pairs the entry that owns its first pair.
 hipError_t launch_count_scan(const uint32_t* pcounts, int64_t nv, uint64_t* offsets, uint64_t* blocksums,
@@ -140,9 +147,9 @@ hipError_t launch_count_scan(const uint32_t* pcounts, int64_t nv, uint64_t* offs
 // unculled tiles.
 hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uint32_t* emit_start,
                        const uint32_t* pcounts, const uint2* rects, int64_t nv, int64_t n, const ViewInfo* vt,
-                       const uint32_t* alive, const SavedHeader* hdr, int phase, int64_t max_pairs,
-                       const CullArgs& cull, uint32_t n_tiles, uint32_t* tiles_out, uint32_t* vals_out,
-                       hipStream_t s);
+                       const uint32_t* alive, const uint2* rowspan, const SavedHeader* hdr, int phase,
+                       int64_t max_pairs, const CullArgs& cull, uint32_t n_tiles, uint32_t* tiles_out,
+                       uint32_t* vals_out, hipStream_t s);
 // Copy the phase's tile-sorted values behind the earlier phases' and record its tile ranges.
 hipError_t launch_commit(const uint32_t* sorted_tiles, const uint32_t* sorted_vals, const SavedHeader* hdr,
                          int phase, int64_t tiles, int64_t max_pairs, uint32_t* vals, uint2* ranges, hipStream_t s);

@@ -75,6 +75,7 @@ __global__ __launch_bounds__(kL1Block) void k_l1(int64_t count, const float* __r
     }
 }
 
+typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int kAdamItems = 4;                              // float4 per thread per block
 constexpr int64_t kAdamChunk = (int64_t)kBlock * kAdamItems * 4;   // scalars per workgroup
 
@@ -146,36 +147,48 @@ __global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a) {
     const bool vec = ((reinterpret_cast<uintptr_t>(G.param) | reinterpret_cast<uintptr_t>(G.grad) |
                        reinterpret_cast<uintptr_t>(G.m) | reinterpret_cast<uintptr_t>(G.v) |
                        reinterpret_cast<uintptr_t>(G.activated)) & 15) == 0;
+    if (vec && n - base >= kAdamChunk) {
+        // whole chunk: every load of the chunk issued before any arithmetic; streamed with
+        // non-temporal accesses (the arrays are far larger than the caches)
+        v4f p[kAdamItems], g[kAdamItems], m[kAdamItems], v[kAdamItems], ac[kAdamItems];
 #pragma unroll
-    for (int it = 0; it < kAdamItems; ++it) {
-        const int64_t i0 = base + ((int64_t)it * kBlock + threadIdx.x) * 4;
-        if (i0 >= n) break;
-        if (vec && i0 + 4 <= n) {
-            float4 p = *reinterpret_cast<const float4*>(G.param + i0);
-            const float4 g = *reinterpret_cast<const float4*>(G.grad + i0);
-            float4 m = *reinterpret_cast<const float4*>(G.m + i0);
-            float4 v = *reinterpret_cast<const float4*>(G.v + i0);
-            float4 ac = G.activation ? *reinterpret_cast<const float4*>(G.activated + i0) : make_float4(0, 0, 0, 0);
-            float4 na = ac;
-            p.x = adam_one(G, p.x, g.x, ac.x, m.x, v.x, na.x, a.b1, a.b2, a.eps, ibc1, ibc2);
-            p.y = adam_one(G, p.y, g.y, ac.y, m.y, v.y, na.y, a.b1, a.b2, a.eps, ibc1, ibc2);
-            p.z = adam_one(G, p.z, g.z, ac.z, m.z, v.z, na.z, a.b1, a.b2, a.eps, ibc1, ibc2);
-            p.w = adam_one(G, p.w, g.w, ac.w, m.w, v.w, na.w, a.b1, a.b2, a.eps, ibc1, ibc2);
-            *reinterpret_cast<float4*>(G.param + i0) = p;
-            *reinterpret_cast<float4*>(G.m + i0) = m;
-            *reinterpret_cast<float4*>(G.v + i0) = v;
-            if (G.activation) *reinterpret_cast<float4*>(G.activated + i0) = na;
-        } else {
-            for (int64_t j = i0; j < n && j < i0 + 4; ++j) {
-                float m = G.m[j], v = G.v[j];
-                float na = 0.0f;
-                const float act = G.activation ? G.activated[j] : 0.0f;
-                G.param[j] = adam_one(G, G.param[j], G.grad[j], act, m, v, na, a.b1, a.b2, a.eps, ibc1, ibc2);
-                G.m[j] = m;
-                G.v[j] = v;
-                if (G.activation) G.activated[j] = na;
-            }
+        for (int it = 0; it < kAdamItems; ++it) {
+            const int64_t i0 = base + ((int64_t)it * kBlock + threadIdx.x) * 4;
+            p[it] = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(G.param + i0));
+            g[it] = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(G.grad + i0));
+            m[it] = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(G.m + i0));
+            v[it] = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(G.v + i0));
+            ac[it] = G.activation ? __builtin_nontemporal_load(reinterpret_cast<const v4f*>(G.activated + i0))
+                                  : v4f{0.f, 0.f, 0.f, 0.f};
         }
+#pragma unroll
+        for (int it = 0; it < kAdamItems; ++it) {
+            const int64_t i0 = base + ((int64_t)it * kBlock + threadIdx.x) * 4;
+            v4f np, na;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                float mc = m[it][c], vc = v[it][c], nac = 0.0f;
+                np[c] = adam_one(G, p[it][c], g[it][c], ac[it][c], mc, vc, nac, a.b1, a.b2, a.eps, ibc1, ibc2);
+                m[it][c] = mc;
+                v[it][c] = vc;
+                na[c] = nac;
+            }
+            __builtin_nontemporal_store(np, reinterpret_cast<v4f*>(G.param + i0));
+            __builtin_nontemporal_store(m[it], reinterpret_cast<v4f*>(G.m + i0));
+            __builtin_nontemporal_store(v[it], reinterpret_cast<v4f*>(G.v + i0));
+            if (G.activation) __builtin_nontemporal_store(na, reinterpret_cast<v4f*>(G.activated + i0));
+        }
+        return;
+    }
+    // the group's last, partial chunk (or unaligned arrays): scalar loop with bounds checks
+    for (int64_t j = base + threadIdx.x; j < n && j < base + kAdamChunk; j += kBlock) {
+        float m = G.m[j], v = G.v[j];
+        float na = 0.0f;
+        const float act = G.activation ? G.activated[j] : 0.0f;
+        G.param[j] = adam_one(G, G.param[j], G.grad[j], act, m, v, na, a.b1, a.b2, a.eps, ibc1, ibc2);
+        G.m[j] = m;
+        G.v[j] = v;
+        if (G.activation) G.activated[j] = na;
     }
 }
 

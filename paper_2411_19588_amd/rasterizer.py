@@ -32,7 +32,8 @@ class RasterConfig:
     kappa: float = 11.1
     depth_mode: int = 0
     tile_cull: bool = True            # drop (Gaussian, tile) pairs that cannot reach alpha_min
-    phases: int = 3
+    phases: int = 2
+    phase0_shift: int = 0             # 0 = library default
     max_pairs: int = 1 << 22
 
     def to_c(self, max_pairs: Optional[int] = None, timer=None) -> N.GsOptions:
@@ -51,6 +52,7 @@ class RasterConfig:
         o.depth_mode = int(self.depth_mode)
         o.tile_cull = 1 if self.tile_cull else 0
         o.phases = int(self.phases)
+        o.phase0_shift = int(self.phase0_shift)
         o.max_pairs = int(self.max_pairs if max_pairs is None else max_pairs)
         o.timer = timer
         return o

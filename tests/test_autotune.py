@@ -54,3 +54,15 @@ def test_tune_skips_failing_shapes():
 
     assert A.tune(measure, RasterConfig(), shapes).pixels_per_lane == 4
     assert A.pick({0: None, 1: float("nan"), 2: 5.0, 3: 4.0}) == 3
+
+
+def test_tune_all_tunes_shape_then_schedule():
+    seen = []
+
+    def measure(cfg):
+        seen.append((cfg.pixels_per_lane, cfg.phases, cfg.phase0_shift))
+        return (cfg.pixels_per_lane != 2) + abs(cfg.phase0_shift - 6) + 0.1 * cfg.phases
+
+    got = A.tune_all(measure, RasterConfig())
+    assert (got.pixels_per_lane, got.phases, got.phase0_shift) == (2, 2, 6)
+    assert len(seen) == len(A.candidates()) + len(A.schedules())

@@ -51,14 +51,20 @@ def test_keys_bitexact_multiview(oracle_mod):
     _keys_match(sc, U.make_rast(sc, phases=1, tile_cull=False), oracle_mod)
 
 
-@pytest.mark.parametrize("phases", [2, 3, 4])
-def test_phased_lists_are_exact_prefixes(oracle_mod, phases):
+@pytest.mark.parametrize("phases,shift,views", [(2, 0, 1), (3, 0, 1), (4, 0, 1), (2, 8, 1), (3, 2, 1),
+                                                (2, 6, 3), (3, 3, 3)])
+def test_phased_lists_are_exact_prefixes(oracle_mod, phases, shift, views):
     """Depth-progressive binning stores, per tile, a prefix of the oracle's sorted list (bit-exact keys,
-    cut at a phase boundary), and the images equal those of full binning bit for bit."""
+    cut at a phase boundary), and the images equal those of full binning bit for bit.  Later phases
+    with few front Gaussians leave tiles partially alive, so rows are walked over their alive span;
+    the ragged three-view scene puts those rows at several view offsets."""
     O = oracle_mod
-    sc = synth.make_scene(1, n=20000, width=203, height=141)
-    U.say(f"phased prefixes {phases}")
-    rast = U.make_rast(sc, phases=phases, tile_cull=False)
+    if views == 1:
+        sc = synth.make_scene(1, n=20000, width=203, height=141)
+    else:
+        sc = synth.make_scene(3, n=20000, n_views=3, view_sizes=[(203, 141), (130, 77), (96, 160)])
+    U.say(f"phased prefixes {phases} shift {shift} views {views}")
+    rast = U.make_rast(sc, phases=phases, phase0_shift=shift, tile_cull=False)
     rgb, depth, alpha, ctx, _ = U.forward(sc, rast)
     k, v, ranges = rast.export_keys(ctx)
     k = k.cpu().numpy().view(np.uint64)
