@@ -95,17 +95,20 @@ def kernel_bytes(name: str, n: int, views: int, K: int, P: int, tiles: int, ncoe
     """
     per_step = max(1, per_step)
     NV = n * views
+    tile_passes = (int(tiles).bit_length() + 7) // 8   # radix passes over tile ids 0..tiles
     param = n * (3 + 3 + 4 + 1 + 3 * ncoef) * 4
     table = {
         # params once + per entry: record 48, count 4, rect 8, depth key 4 (saved) + sort key/value 8
         "project_fwd": param + NV * (48 + 4 + 8 + 4 + 8),
-        "depth_sort_hist": NV * 4,
-        "depth_sort_scatter": NV * 16,
+        "depth_sort_hist": NV * 4,                 # per digit pass: keys read
+        "depth_sort_scatter": NV * 16,             # per digit pass: keys and values read and written
+        "alive_rows": tiles * 4 + tiles // 4,      # alive flags read, a span per tile row written
         "phase_count": NV * 8,                     # per phase: order + count (or rectangle) per entry
         "count_scan": NV * (4 + 4 + 8),            # per phase: two passes over the counts, offsets write
         "emit": (K * 8) / per_step + NV * 4,
-        "tile_sort_hist": (K * 4) / per_step,
-        "tile_sort_scatter": (K * 16) / per_step,
+        # every digit pass of every phase's tile sort moves that phase's pairs
+        "tile_sort_hist": (K * 4 * tile_passes) / per_step,
+        "tile_sort_scatter": (K * 16 * tile_passes) / per_step,
         "commit": (K * 12) / per_step,
         # outputs + saved state per pixel; the gathered records of traversed pairs are cache-resident
         "composite_fwd": (P * (12 + 4 + 4) + P * 29 + tiles * 8) / per_step,
@@ -254,9 +257,9 @@ def batched_compare(args, dev):
             "autotune_s": round(tune_s, 1)}
 
 
-KERNELS = ["project_fwd", "depth_sort_hist", "depth_sort_scan", "depth_sort_scatter", "phase_count", "count_scan",
-           "emit", "tile_sort_hist", "tile_sort_scan", "tile_sort_scatter", "commit", "composite_fwd", "zero_grad2d",
-           "composite_bwd", "medium_reduce", "project_bwd"]
+KERNELS = ["project_fwd", "depth_sort_hist", "depth_sort_scan", "depth_sort_scatter", "alive_rows", "phase_count",
+           "count_scan", "emit", "tile_sort_hist", "tile_sort_scan", "tile_sort_scatter", "commit", "composite_fwd",
+           "zero_grad2d", "composite_bwd", "medium_reduce", "project_bwd"]
 
 
 def read_timer(N, timer):
@@ -294,7 +297,14 @@ def main():
         for _ in range(3):
             torch.mul(x, 1.0, out=y)     # one elementwise kernel: reads n*4 bytes, writes n*4 bytes
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 3}))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.mul(x, 1.0, out=y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 4,
+                          "copy_ms": round(ms, 4), "copy_gbs": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}))
         return
     log(f"building scene (config {args.config})")
     sc = synth.make_scene(args.config)

@@ -45,6 +45,15 @@ def test_keys_bitexact_config1_small(oracle_mod, tile):
     assert K > 20000
 
 
+def test_keys_bitexact_many_sort_tiles(oracle_mod):
+    """5.7e6 pairs at 1600x1067: the tile sort spans ~2800 tiles of 2048 keys, several per sort
+    workgroup, and its second digit pass covers 5 bits."""
+    sc = synth.make_scene(1, n=120000)
+    U.say("keys many sort tiles")
+    K = _keys_match(sc, U.make_rast(sc, phases=1, tile_cull=False, max_pairs=6_000_000), oracle_mod)
+    assert K > 5_000_000
+
+
 def test_keys_bitexact_multiview(oracle_mod):
     sc = synth.make_scene(3, n=5000, n_views=3, view_sizes=[(96, 64), (130, 77), (64, 64)])
     U.say("keys multiview")
