@@ -98,6 +98,11 @@ __global__ void k_visible(int phases, int shift, SavedHeader* hdr) {
     }
 }
 
+// A later phase after which no tile was left alive emits nothing: the scan kernels skip it.
+__device__ __forceinline__ bool phase_empty(const SavedHeader* hdr, int phase) {
+    return phase > 0 && hdr->phase_alive[phase - 1] == 0;
+}
+
 __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restrict__ order,
                                                        const uint32_t* __restrict__ counts,
                                                        const uint2* __restrict__ rects, int64_t nv, int64_t n,
@@ -106,6 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restri
                                                        const uint2* __restrict__ rowspan,
                                                        const SavedHeader* __restrict__ hdr, int phase,
                                                        CullArgs cull, uint32_t* __restrict__ pcounts) {
+    if (phase_empty(hdr, phase)) return;   // no tile left: nothing reads this phase's counts
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (r >= nv) return;
     const uint32_t r0 = hdr->phase_rank[phase], r1 = hdr->phase_rank[phase + 1];
@@ -137,10 +143,6 @@ __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restri
     pcounts[r] = c;
 }
 
-// A later phase after which no tile was left alive emits nothing: the scan kernels skip it.
-__device__ __forceinline__ bool phase_empty(const SavedHeader* hdr, int phase) {
-    return phase > 0 && hdr->phase_alive[phase - 1] == 0;
-}
 
 __global__ __launch_bounds__(kBlock) void k_count_reduce(const uint32_t* __restrict__ pcounts, int64_t nv,
                                                         const SavedHeader* __restrict__ hdr, int phase,
@@ -342,8 +344,9 @@ __global__ __launch_bounds__(kBlock) void k_emit_alive(const uint32_t* __restric
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (r >= nv) return;
     const uint64_t K = hdr->phase_count[phase];
+    if (K == 0) return;   // also every phase after which no tile was alive: its counts are not written
     const uint32_t c = pcounts[r];
-    if (K == 0 || c == 0) return;
+    if (c == 0) return;
     uint64_t off = offsets[r];
     if (off + c > K) return;   // cannot happen for a consistent scan
     const uint32_t e = order[r];
@@ -405,14 +408,14 @@ __global__ __launch_bounds__(kBlock) void k_commit(const uint32_t* __restrict__ 
                                                   uint32_t* __restrict__ vals, uint2* __restrict__ ranges) {
     const uint32_t K = hdr->phase_live[phase];   // culled pairs were left out by the tile sort
     const uint32_t base = hdr->phase_base[phase];
-    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= K) return;
-    vals[base + i] = svals[i];
-    const uint32_t t = tiles[i];
-    if (t >= n_tiles) return;   // tile ids are < n_tiles by construction
     uint2* rg = ranges + (size_t)phase * n_tiles;
-    if (i == 0 || tiles[i - 1] != t) rg[t].x = base + i;
-    if (i + 1 == K || tiles[i + 1] != t) rg[t].y = base + i + 1;
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < K; i += gridDim.x * kBlock) {
+        vals[base + i] = svals[i];
+        const uint32_t t = tiles[i];
+        if (t >= n_tiles) continue;   // tile ids are < n_tiles by construction
+        if (i == 0 || tiles[i - 1] != t) rg[t].x = base + i;
+        if (i + 1 == K || tiles[i + 1] != t) rg[t].y = base + i + 1;
+    }
 }
 
 // One workgroup per tile writes the keys of that tile's pairs in every phase.
@@ -504,7 +507,9 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream
 hipError_t launch_commit(const uint32_t* sorted_tiles, const uint32_t* sorted_vals, const SavedHeader* hdr,
                          int phase, int64_t tiles, int64_t max_pairs, uint32_t* vals, uint2* ranges, hipStream_t s) {
     if (max_pairs == 0) return hipSuccess;
-    const unsigned grid = (unsigned)((max_pairs + kBlock - 1) / kBlock);
+    constexpr int64_t kMaxCommitGrid = 4096;   // grid-stride beyond 1M pairs; an empty phase costs little
+    const int64_t want = (max_pairs + kBlock - 1) / kBlock;
+    const unsigned grid = (unsigned)(want < kMaxCommitGrid ? want : kMaxCommitGrid);
     hipLaunchKernelGGL(k_commit, dim3(grid), dim3(kBlock), 0, s, sorted_tiles, sorted_vals, hdr, phase,
                        (uint32_t)tiles, vals, ranges);
     return hipGetLastError();

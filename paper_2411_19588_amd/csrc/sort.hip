@@ -50,11 +50,12 @@ __global__ __launch_bounds__(kBlock) void k_hist(const uint32_t* __restrict__ ke
                                                 uint32_t n_host, int shift, int nbits, int parts, int use_drop,
                                                 uint32_t drop, uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[kRadix];
+    const uint32_t n = load_n(n_dev, n_host);
+    if (n == 0) return;   // nothing to sort (an empty phase): the scan and the scatter return too
     const int tid = threadIdx.x, lane = tid & 63;
     for (int i = tid; i < kRadix; i += kBlock) h[i] = 0;
     __syncthreads();
     const uint32_t mask = (1u << nbits) - 1u;
-    const uint32_t n = load_n(n_dev, n_host);
     uint32_t t0, t1;
     part_range(n, parts, blockIdx.x, t0, t1);
     for (uint32_t t = t0; t < t1; ++t) {
@@ -104,8 +105,10 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* s
 
 // Exclusive scan of row d (parts <= kMaxSortParts entries) in place; totals[d] = row sum.
 __global__ __launch_bounds__(kBlock) void k_scan_rows(uint32_t* __restrict__ hist, int parts,
-                                                     uint32_t* __restrict__ totals) {
+                                                     uint32_t* __restrict__ totals, const uint32_t* n_dev,
+                                                     uint32_t n_host) {
     __shared__ uint32_t s[kBlock / 64];
+    if (load_n(n_dev, n_host) == 0) return;
     const int tid = threadIdx.x;
     uint32_t* row = hist + (size_t)blockIdx.x * parts;
     constexpr int PER = kMaxSortParts / kBlock;
@@ -143,9 +146,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const uint32_t mask = (1u << nbits) - 1u;
     const uint32_t n = load_n(n_dev, n_host);
+    if (n == 0) {
+        if (n_kept && blockIdx.x == 0 && tid == 0) *n_kept = 0;
+        return;
+    }
     {
         uint32_t tot;
-        const uint32_t base = block_exclusive_scan(totals[tid], scan_tmp, tot);
+        // only the pass's 2^nbits digit rows were scanned
+        const uint32_t base = block_exclusive_scan((uint32_t)tid <= mask ? totals[tid] : 0u, scan_tmp, tot);
         run[tid] = base + hist[(size_t)tid * parts + blockIdx.x];
         if (n_kept && blockIdx.x == 0 && tid == 0) *n_kept = tot;   // keys kept (equal to drop: left out)
     }
@@ -251,7 +259,7 @@ hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, 
                            drop_key, hist);
         timer_end(timer, s);
         timer_begin(timer, ts.c_str(), s);
-        hipLaunchKernelGGL(k_scan_rows, dim3(kRadix), dim3(kBlock), 0, s, hist, parts, totals);
+        hipLaunchKernelGGL(k_scan_rows, dim3(1u << bits), dim3(kBlock), 0, s, hist, parts, totals, n_in, n_host);
         timer_end(timer, s);
         timer_begin(timer, tc.c_str(), s);
         hipLaunchKernelGGL(k_scatter, dim3(parts), dim3(kBlock), 0, s, kin, vin, kout, vout, n_in, n_host, shift,
