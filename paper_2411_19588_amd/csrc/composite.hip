@@ -455,6 +455,11 @@ __device__ __forceinline__ bool blend_adjoint(const Splat& s, float fpx, float f
                                               float* g10, float amin, float amax) {
     const ColTerms ct = col_terms(s, fpx);
     const float nA2 = -2.0f * s.A, nB = -s.B, nC2 = -2.0f * s.C;
+    // With several pixels per lane, the exponent's derivatives are gathered per lane as
+    // P = sum dpw, Q = sum dpw dy, U = sum dpw dy^2 (dx is the lane's column, the same for all
+    // its pixels) and turned into the five geometry terms once per splat.
+    constexpr bool kLaneSums = PPL >= 2;
+    float P = 0.0f, Q = 0.0f, U = 0.0f;
     bool any = false;
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
@@ -480,12 +485,27 @@ __device__ __forceinline__ bool blend_adjoint(const Splat& s, float fpx, float f
         g10[9] = fmaf(gD[k], w, g10[9]);
         g10[5] = fmaf(dalpha, ev, g10[5]);
         const float dpw = dalpha * araw;   // d/d(exponent), without ln 2
-        const float pdx = dpw * ct.dx, pdy = dpw * dy;
-        g10[2] = fmaf(pdx, ct.dx, g10[2]);
-        g10[3] = fmaf(pdx, dy, g10[3]);
-        g10[4] = fmaf(pdy, dy, g10[4]);
-        g10[0] = fmaf(nA2, pdx, fmaf(nB, pdy, g10[0]));
-        g10[1] = fmaf(nB, pdx, fmaf(nC2, pdy, g10[1]));
+        if constexpr (kLaneSums) {
+            const float qd = dpw * dy;
+            P += dpw;
+            Q += qd;
+            U = fmaf(qd, dy, U);
+        } else {
+            const float pdx = dpw * ct.dx, pdy = dpw * dy;
+            g10[2] = fmaf(pdx, ct.dx, g10[2]);
+            g10[3] = fmaf(pdx, dy, g10[3]);
+            g10[4] = fmaf(pdy, dy, g10[4]);
+            g10[0] = fmaf(nA2, pdx, fmaf(nB, pdy, g10[0]));
+            g10[1] = fmaf(nB, pdx, fmaf(nC2, pdy, g10[1]));
+        }
+    }
+    if constexpr (kLaneSums) {
+        const float X = ct.dx * P;   // sum over the lane's pixels of dpw dx
+        g10[2] = fmaf(ct.dx, X, g10[2]);
+        g10[3] = fmaf(ct.dx, Q, g10[3]);
+        g10[4] += U;
+        g10[0] = fmaf(nA2, X, fmaf(nB, Q, g10[0]));
+        g10[1] = fmaf(nB, X, fmaf(nC2, Q, g10[1]));
     }
     return any;
 }
