@@ -97,6 +97,7 @@ def kernel_bytes(name: str, n: int, views: int, K: int, P: int, tiles: int, ncoe
     NV = n * views
     tile_passes = (int(tiles).bit_length() + 7) // 8   # radix passes over tile ids 0..tiles
     param = n * (3 + 3 + 4 + 1 + 3 * ncoef) * 4
+    nsh0 = n * (3 + 3 + 4 + 1) * 4                     # the non-SH parameters
     table = {
         # params once + per entry: record 48, count 4, rect 8, depth key 4 (saved) + sort key/value 8
         "project_fwd": param + NV * (48 + 4 + 8 + 4 + 8),
@@ -113,9 +114,15 @@ def kernel_bytes(name: str, n: int, views: int, K: int, P: int, tiles: int, ncoe
         # outputs + saved state per pixel; the gathered records of traversed pairs are cache-resident
         "composite_fwd": (P * (12 + 4 + 4) + P * 29 + tiles * 8) / per_step,
         "composite_bwd": P * (12 + 28) + NV * 40 + tiles * 36,
-        # parameters and 2D gradients read, gradients written (with the Adam step fused in:
-        # moments read and parameters and moments written instead of the gradients)
-        "project_bwd": (param + NV * 40 + param) if not fused else (3 * param + NV * 40 + 3 * param + n * 16),
+        # parameters and 2D gradients read, gradients written.  With the Adam step fused in and several
+        # views: moments read, parameters and moments written instead of the gradients (+ 16 B of
+        # activated copies).  One view: only the 11 non-SH scalars are stepped there, and the 6 factors
+        # of the SH gradient are written for adam_sh.
+        "project_bwd": (param + NV * 40 + param) if not fused else (
+            (3 * param + NV * 40 + 3 * param + n * 16) if views > 1 else
+            (param + NV * 40 + 2 * nsh0 + 3 * nsh0 + n * 16 + n * 24)),
+        # SH parameters and moments read and written, 6 factors read
+        "adam_sh": n * (3 * ncoef * 24 + 24),
         "zero_grad2d": NV * 40,
         "medium_reduce": tiles * 36,
     }
@@ -259,7 +266,7 @@ def batched_compare(args, dev):
 
 KERNELS = ["project_fwd", "depth_sort_hist", "depth_sort_scan", "depth_sort_scatter", "alive_rows", "phase_count",
            "count_scan", "emit", "tile_sort_hist", "tile_sort_scan", "tile_sort_scatter", "commit", "composite_fwd",
-           "zero_grad2d", "composite_bwd", "medium_reduce", "project_bwd"]
+           "zero_grad2d", "composite_bwd", "medium_reduce", "project_bwd", "adam_sh"]
 
 
 def read_timer(N, timer):

@@ -264,7 +264,12 @@ typedef struct gs_adam_group {
  * (Sec. Optimization): the adjoint of gs_render_backward, but instead of writing
  * the parameter gradients it applies one Adam step -- as gs_adam_step_device,
  * same step counter semantics -- to the raw parameters in registers, so the
- * gradients of the Gaussians never reach memory.
+ * gradients of the Gaussians never reach memory.  With one view the SH gradient
+ * of a Gaussian is the outer product of the SH basis at its view direction and
+ * its colour gradient: the projection adjoint then steps the other groups and
+ * keeps those six factors in the workspace, and a second kernel steps the SH
+ * coefficients from them.  Results equal gs_render_backward followed by
+ * gs_adam_step_device bit for bit.
  *   groups[6] : HOST array, in this order: means (count 3n, activation 0),
  *               log-scales (3n, activation 1, activated = the scales g->scales
  *               points to), quaternions (4n, 0), opacity logits (n, activation 2,

@@ -136,6 +136,7 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     L->w_medpart = w.take(T * 9 * 4 + 256);   // + persistent-mode tile counter of the backward
     L->w_adam = w.take(16);                    // bias corrections of a fused Adam step
     L->w_rowspan = w.take(rows * 8);           // alive columns per tile row (later depth phases)
+    L->w_shf = w.take(n_views == 1 ? (size_t)n * 6 * 4 : 0);   // factors of the SH gradient (fused Adam)
     L->workspace_bytes = w.at;
     return GS_OK;
 }
@@ -431,9 +432,16 @@ int gs_render_backward_adam(const gs_options* opts, const gs_gaussians* g, int32
     ad.b2 = beta2;
     ad.eps = eps;
     ad.bc = bc;
+    // one view: the SH gradient is an outer product; its Adam step runs from the factors
+    ad.shf = n_views == 1 ? at<float>(workspace, L.w_shf) : nullptr;
     timer_begin(T, "project_bwd", s);
     GS_TRY(launch_project_bwd_adam(*g, n_views, dev_cams, o, grad2d, at<Record>(saved, L.s_records), ad, s));
     timer_end(T, s);
+    if (ad.shf) {
+        timer_begin(T, "adam_sh", s);
+        GS_TRY(launch_adam_sh(n, g->sh_degree, ad, s));
+        timer_end(T, s);
+    }
     return GS_OK;
 }
 

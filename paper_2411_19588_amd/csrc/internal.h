@@ -73,7 +73,7 @@ struct Layout {
     size_t s_tfinal, s_nlast, s_done, s_cair, s_dsum, s_wsum, saved_bytes;
     // workspace offsets (bytes)
     size_t w_counts, w_rects, w_dkeys, w_dvals, w_dkeys2, w_dvals2, w_pcounts, w_offsets, w_blocksums, w_emit_start;
-    size_t w_tiles_a, w_vals_a, w_tiles_b, w_vals_b, w_hist, w_grad2d, w_medpart, w_adam, w_rowspan, workspace_bytes;
+    size_t w_tiles_a, w_vals_a, w_tiles_b, w_vals_b, w_hist, w_grad2d, w_medpart, w_adam, w_rowspan, w_shf, workspace_bytes;
 };
 
 int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_camera* cams, Layout* L);
@@ -100,14 +100,21 @@ __device__ __forceinline__ float adam_update(float p, float g, float& m, float& 
 
 // Adam applied inside the projection adjoint: groups means, log-scales (exp), quaternions,
 // opacity logits (sigmoid), SH, in this order; bc = device [2] bias corrections of this step.
+// With shf set (one view only), the adjoint steps the first four groups and stores the factors
+// of the SH gradient, shf = [6][n] planes (view direction x, y, z; colour gradient of the
+// unclamped channels r, g, b), for launch_adam_sh.
 struct AdamFused {
     gs_adam_group g[5];
     float b1, b2, eps;
     const float* bc;
+    float* shf;
 };
 
 hipError_t launch_project_bwd_adam(const gs_gaussians& g, int32_t views, const gs_camera* cams, const gs_options& o,
                                    const float* grad2d, const Record* rec, const AdamFused& adam, hipStream_t s);
+// Adam step of the SH group from the factors launch_project_bwd_adam stored in adam.shf: the
+// gradient of coefficient k, channel c is Y_k(dir) gc_c, as the adjoint forms it.
+hipError_t launch_adam_sh(int64_t n, int sh_degree, const AdamFused& adam, hipStream_t s);
 // step += 1 and bc = (1 / (1 - b1^step), 1 / (1 - b2^step)) on the device.
 hipError_t launch_adam_prep(int32_t* step, float b1, float b2, float* bc, hipStream_t s);
 // Stable LSD radix sort of (key, value) u32 pairs over bits [bit0, bit0+nbits).  n is read from n_dev

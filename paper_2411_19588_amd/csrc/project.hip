@@ -292,12 +292,13 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
     const float qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
     float gmu[3] = {0.f, 0.f, 0.f}, gsc[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, gop = 0.f;
     float gsh[NACC];      // several views: SH gradient accumulators
-    float Y1[16], gc1[3];  // one view: the factors of its SH gradient
+    float Y1[16], gc1[3], dir1[3];  // one view: the factors of its SH gradient
 #pragma unroll
     for (int k = 0; k < NACC; ++k) gsh[k] = 0.f;
 #pragma unroll
     for (int k = 0; k < 16; ++k) Y1[k] = 0.f;
     gc1[0] = gc1[1] = gc1[2] = 0.f;
+    dir1[0] = dir1[1] = dir1[2] = 0.f;
     for (int v = 0; v < views; ++v) {
         const float* gg = grad2d + ((int64_t)v * n + i) * kGrad2D;
         float G[kGrad2D];
@@ -401,6 +402,9 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
             for (int k = 0; k < 16; ++k) Y1[k] = Y[k];
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) gc1[ch] = gce[ch];
+            dir1[0] = d0;
+            dir1[1] = d1;
+            dir1[2] = d2;
         } else {
 #pragma unroll
             for (int k = 0; k < NC; ++k)
@@ -468,6 +472,14 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
         const float nx = step(adam.g[3], i, gop * (o * (1.0f - o)));
         adam.g[3].activated[i] = 1.0f / (1.0f + expf(-nx));
     }
+    if (ONE && adam.shf) {   // the SH step runs in k_adam_sh from these six factors
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            adam.shf[(int64_t)k * n + i] = dir1[k];
+            adam.shf[(int64_t)(3 + k) * n + i] = gc1[k];
+        }
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < NC * 3; ++k) {
         if (k % 16 == 0) __builtin_amdgcn_sched_barrier(0);
@@ -475,7 +487,79 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
     }
 }
 
+// Adam step of the SH coefficients from the factors the one-view adjoint stored: the gradient
+// of coefficient k, channel c is Y_k(dir) gc_c (the same product the adjoint forms), so the 48
+// gradient planes are never written or read.  A thread steps W consecutive Gaussians (W = 4:
+// 16-byte accesses, which needs n % 4 == 0).
+template <int DEG, int W>
+__global__ __launch_bounds__(kBlock) void k_adam_sh(int64_t n, AdamFused adam) {
+    using VW = float __attribute__((ext_vector_type(W)));
+    constexpr int NC = (DEG + 1) * (DEG + 1);
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * W;
+    if (i0 >= n) return;
+    const float* f = adam.shf;
+    float Y[W][16], gc[W][3];
+    {
+        const VW dx = *reinterpret_cast<const VW*>(f + i0), dy = *reinterpret_cast<const VW*>(f + n + i0),
+                 dz = *reinterpret_cast<const VW*>(f + 2 * n + i0);
+        const VW c0 = *reinterpret_cast<const VW*>(f + 3 * n + i0), c1 = *reinterpret_cast<const VW*>(f + 4 * n + i0),
+                 c2 = *reinterpret_cast<const VW*>(f + 5 * n + i0);
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            gc[w][0] = c0[w];
+            gc[w][1] = c1[w];
+            gc[w][2] = c2[w];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) Y[w][k] = 0.f;
+            if (gc[w][0] != 0.0f || gc[w][1] != 0.0f || gc[w][2] != 0.0f) sh_eval<DEG>(dx[w], dy[w], dz[w], Y[w]);
+        }
+    }
+    const gs_adam_group& G = adam.g[4];
+    const float ibc1 = adam.bc[0], ibc2 = adam.bc[1];
+#pragma unroll
+    for (int k = 0; k < NC * 3; ++k) {
+        if (k % 4 == 0) __builtin_amdgcn_sched_barrier(0);
+        const int64_t j = (int64_t)k * n + i0;
+        VW p = __builtin_nontemporal_load(reinterpret_cast<const VW*>(G.param + j));
+        VW m = __builtin_nontemporal_load(reinterpret_cast<const VW*>(G.m + j));
+        VW v = __builtin_nontemporal_load(reinterpret_cast<const VW*>(G.v + j));
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            float mw = m[w], vw = v[w];
+            p[w] = adam_update(p[w], Y[w][k / 3] * gc[w][k % 3], mw, vw, G.lr, adam.b1, adam.b2, adam.eps, ibc1, ibc2);
+            m[w] = mw;
+            v[w] = vw;
+        }
+        __builtin_nontemporal_store(p, reinterpret_cast<VW*>(G.param + j));
+        __builtin_nontemporal_store(m, reinterpret_cast<VW*>(G.m + j));
+        __builtin_nontemporal_store(v, reinterpret_cast<VW*>(G.v + j));
+    }
+}
+
 }  // namespace
+
+hipError_t launch_adam_sh(int64_t n, int sh_degree, const AdamFused& adam, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (!adam.shf) return hipErrorInvalidValue;
+    // 16-byte accesses need every plane (offset k n) and the factor planes 16-byte aligned
+    const bool v4 = n % 4 == 0 && ((uintptr_t)adam.shf | (uintptr_t)adam.g[4].param | (uintptr_t)adam.g[4].m |
+                                   (uintptr_t)adam.g[4].v) % 16 == 0;
+    const int64_t per = v4 ? 4 : 1;
+    const unsigned grid = (unsigned)(((n + per - 1) / per + kBlock - 1) / kBlock);
+#define GS_ASH(D)                                                                                    \
+    if (v4)                                                                                          \
+        hipLaunchKernelGGL((k_adam_sh<D, 4>), dim3(grid), dim3(kBlock), 0, s, n, adam);              \
+    else                                                                                             \
+        hipLaunchKernelGGL((k_adam_sh<D, 1>), dim3(grid), dim3(kBlock), 0, s, n, adam)
+    switch (sh_degree) {
+        case 0: GS_ASH(0); break;
+        case 1: GS_ASH(1); break;
+        case 2: GS_ASH(2); break;
+        default: GS_ASH(3); break;
+    }
+#undef GS_ASH
+    return hipGetLastError();
+}
 
 hipError_t launch_project_fwd(const gs_gaussians& g, int32_t views, const gs_camera* cams, const ViewInfo* vt,
                               const gs_options& o, Record* rec, uint32_t* counts, uint2* rects,
