@@ -64,9 +64,10 @@ def parse():
     ap.add_argument("--lds-batch", type=int, default=64)
     ap.add_argument("--persistent", action="store_true")
     ap.add_argument("--no-tile-cull", action="store_true", help="bin every tile of each rectangle")
-    ap.add_argument("--fused-adam", action="store_true",
-                    help="run the Adam step inside the projection adjoint (default: the adjoint writes the "
-                         "gradients and the separate Adam kernel updates the parameters)")
+    ap.add_argument("--separate-adam", dest="fused_adam", action="store_false",
+                    help="the projection adjoint writes the gradients and the flat Adam kernel updates the "
+                         "parameters (default: Adam fused into the adjoint, the SH coefficients stepped from "
+                         "the two factors of their gradient)")
     ap.add_argument("--ppl", type=int, default=0, help="pixels per lane in compositing (0 = library default)")
     ap.add_argument("--fetch", choices=["default", "lds", "scalar"], default="default",
                     help="how compositing waves receive the records")
