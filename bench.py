@@ -117,13 +117,13 @@ def kernel_bytes(name: str, n: int, views: int, K: int, P: int, tiles: int, ncoe
         "composite_bwd": P * (12 + 28) + NV * 40 + tiles * 36,
         # parameters and 2D gradients read, gradients written.  With the Adam step fused in and several
         # views: moments read, parameters and moments written instead of the gradients (+ 16 B of
-        # activated copies).  One view: only the 11 non-SH scalars are stepped there, and the 6 factors
-        # of the SH gradient are written for adam_sh.
+        # activated copies).  One view: the non-SH parameters read; log-scales, quaternions and
+        # logits (8 scalars) stepped there; 10 planes written for adam_sh.
         "project_bwd": (param + NV * 40 + param) if not fused else (
             (3 * param + NV * 40 + 3 * param + n * 16) if views > 1 else
-            (param + NV * 40 + 2 * nsh0 + 3 * nsh0 + n * 16 + n * 24)),
-        # SH parameters and moments read and written, 6 factors read
-        "adam_sh": n * (3 * ncoef * 24 + 24),
+            (nsh0 + NV * 40 + n * 8 * 4 * 5 + n * 16 + n * 40)),
+        # SH coefficients and the means with their moments read and written, 10 planes read
+        "adam_sh": n * (3 * ncoef * 24 + 3 * 24 + 40),
         "zero_grad2d": NV * 40,
         "medium_reduce": tiles * 36,
     }

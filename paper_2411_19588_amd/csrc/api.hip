@@ -136,7 +136,7 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     L->w_medpart = w.take(T * 9 * 4 + 256);   // + persistent-mode tile counter of the backward
     L->w_adam = w.take(16);                    // bias corrections of a fused Adam step
     L->w_rowspan = w.take(rows * 8);           // alive columns per tile row (later depth phases)
-    L->w_shf = w.take(n_views == 1 ? (size_t)n * 6 * 4 : 0);   // factors of the SH gradient (fused Adam)
+    L->w_shf = w.take(n_views == 1 ? (size_t)n * kShf * 4 : 0);   // SH-gradient factors etc. (fused Adam)
     L->workspace_bytes = w.at;
     return GS_OK;
 }

@@ -100,9 +100,10 @@ __device__ __forceinline__ float adam_update(float p, float g, float& m, float& 
 
 // Adam applied inside the projection adjoint: groups means, log-scales (exp), quaternions,
 // opacity logits (sigmoid), SH, in this order; bc = device [2] bias corrections of this step.
-// With shf set (one view only), the adjoint steps the first four groups and stores the factors
-// of the SH gradient, shf = [6][n] planes (view direction x, y, z; colour gradient of the
-// unclamped channels r, g, b), for launch_adam_sh.
+// With shf set (one view only), the adjoint steps the log-scales, quaternions and opacity logits
+// and stores, for launch_adam_sh, shf = [kShf][n] planes: view direction x, y, z; colour
+// gradient of the unclamped channels r, g, b; inverse distance to the camera centre; the means'
+// gradient without its term through the SH colour.
 struct AdamFused {
     gs_adam_group g[5];
     float b1, b2, eps;
@@ -112,8 +113,10 @@ struct AdamFused {
 
 hipError_t launch_project_bwd_adam(const gs_gaussians& g, int32_t views, const gs_camera* cams, const gs_options& o,
                                    const float* grad2d, const Record* rec, const AdamFused& adam, hipStream_t s);
-// Adam step of the SH group from the factors launch_project_bwd_adam stored in adam.shf: the
-// gradient of coefficient k, channel c is Y_k(dir) gc_c, as the adjoint forms it.
+constexpr int kShf = 10;
+// Adam steps of the means and the SH group from what launch_project_bwd_adam stored in adam.shf:
+// the gradient of SH coefficient k, channel c is Y_k(dir) gc_c, as the adjoint forms it, and the
+// means' gradient gets its SH term here, from the coefficients before their update.
 hipError_t launch_adam_sh(int64_t n, int sh_degree, const AdamFused& adam, hipStream_t s);
 // step += 1 and bc = (1 / (1 - b1^step), 1 / (1 - b2^step)) on the device.
 hipError_t launch_adam_prep(int32_t* step, float b1, float b2, float* bc, hipStream_t s);

@@ -277,11 +277,12 @@ __global__ __launch_bounds__(kBlock) void k_project_fwd(gs_gaussians g, int32_t 
 // unclamped channels).  With one view (ONE) the kernel keeps those 16 + 3 factors instead of
 // 48 accumulators, which bounds its register use; the clamp of each channel is read from the
 // forward's record (a clamped channel holds -0).
-template <int DEG, bool FUSED, bool ONE>
+template <int DEG, bool FUSED, bool ONE, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t views, const gs_camera* cams,
                                                        float dil, const float* __restrict__ grad2d,
                                                        const Record* __restrict__ rec, gs_gaussian_grads out,
                                                        AdamFused adam) {
+    static_assert(!SPLIT || (FUSED && ONE), "the split Adam step exists for one view only");
     constexpr int NC = (DEG + 1) * (DEG + 1);
     constexpr int NACC = ONE ? 1 : NC * 3;
     const int64_t n = g.n;
@@ -292,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
     const float qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
     float gmu[3] = {0.f, 0.f, 0.f}, gsc[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, gop = 0.f;
     float gsh[NACC];      // several views: SH gradient accumulators
-    float Y1[16], gc1[3], dir1[3];  // one view: the factors of its SH gradient
+    float Y1[16], gc1[3], dir1[3], il1 = 0.f;  // one view: the factors of its SH gradient
 #pragma unroll
     for (int k = 0; k < NACC; ++k) gsh[k] = 0.f;
 #pragma unroll
@@ -405,13 +406,14 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
             dir1[0] = d0;
             dir1[1] = d1;
             dir1[2] = d2;
+            il1 = il;
         } else {
 #pragma unroll
             for (int k = 0; k < NC; ++k)
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) gsh[(3 * k + ch) % NACC] += Y[k] * gce[ch];
         }
-        if (DEG > 0) {
+        if (DEG > 0 && !SPLIT) {   // split: k_adam_sh adds this term, reading the SH coefficients once
             float wk[16];
 #pragma unroll
             for (int k = 0; k < 16; ++k) wk[k] = 0.f;
@@ -455,9 +457,11 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
     // The updates below are fenced for the scheduler in groups (16 SH coefficients = 48 loads
     // in flight): hoisting every parameter's and moment's load ahead of the arithmetic would
     // need several hundred registers.
+    if (!SPLIT) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) step(adam.g[0], (int64_t)k * n + i, gmu[k]);
-    __builtin_amdgcn_sched_barrier(0);
+        for (int k = 0; k < 3; ++k) step(adam.g[0], (int64_t)k * n + i, gmu[k]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {   // d exp(l)/dl = exp(l) = the activated scale
         const float nl = step(adam.g[1], (int64_t)k * n + i, gsc[k] * s[k]);
@@ -472,12 +476,14 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
         const float nx = step(adam.g[3], i, gop * (o * (1.0f - o)));
         adam.g[3].activated[i] = 1.0f / (1.0f + expf(-nx));
     }
-    if (ONE && adam.shf) {   // the SH step runs in k_adam_sh from these six factors
+    if (SPLIT) {   // the means' and the SH coefficients' steps run in k_adam_sh from these
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             adam.shf[(int64_t)k * n + i] = dir1[k];
             adam.shf[(int64_t)(3 + k) * n + i] = gc1[k];
+            adam.shf[(int64_t)(7 + k) * n + i] = gmu[k];
         }
+        adam.shf[(int64_t)6 * n + i] = il1;
         return;
     }
 #pragma unroll
@@ -487,10 +493,13 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
     }
 }
 
-// Adam step of the SH coefficients from the factors the one-view adjoint stored: the gradient
-// of coefficient k, channel c is Y_k(dir) gc_c (the same product the adjoint forms), so the 48
-// gradient planes are never written or read.  A thread steps W consecutive Gaussians (W = 4:
-// 16-byte accesses, which needs n % 4 == 0).
+// Adam steps of the means and the SH coefficients, one view, from what the split adjoint
+// stored (kShf planes: view direction, colour gradient of the unclamped channels, inverse
+// distance to the camera centre, the means' gradient without its SH term).  The gradient of SH
+// coefficient k, channel c is Y_k(dir) gc_c, as the adjoint forms it; the means' SH term goes
+// through the direction with the coefficients read here before their update, in the adjoint's
+// order, so the 48 gradient planes are never written and the coefficients are read once.  A
+// thread steps W consecutive Gaussians (W = 2: 8-byte accesses, which needs n even).
 template <int DEG, int W>
 __global__ __launch_bounds__(kBlock) void k_adam_sh(int64_t n, AdamFused adam) {
     using VW = float __attribute__((ext_vector_type(W)));
@@ -498,24 +507,27 @@ __global__ __launch_bounds__(kBlock) void k_adam_sh(int64_t n, AdamFused adam) {
     const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * W;
     if (i0 >= n) return;
     const float* f = adam.shf;
-    float Y[W][16], gc[W][3];
+    auto plane = [&](int q) { return *reinterpret_cast<const VW*>(f + (int64_t)q * n + i0); };
+    float Y[W][16], gc[W][3], dir[W][3], wk[W][16];
+    bool live[W];
     {
-        const VW dx = *reinterpret_cast<const VW*>(f + i0), dy = *reinterpret_cast<const VW*>(f + n + i0),
-                 dz = *reinterpret_cast<const VW*>(f + 2 * n + i0);
-        const VW c0 = *reinterpret_cast<const VW*>(f + 3 * n + i0), c1 = *reinterpret_cast<const VW*>(f + 4 * n + i0),
-                 c2 = *reinterpret_cast<const VW*>(f + 5 * n + i0);
+        const VW dx = plane(0), dy = plane(1), dz = plane(2), c0 = plane(3), c1 = plane(4), c2 = plane(5);
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             gc[w][0] = c0[w];
             gc[w][1] = c1[w];
             gc[w][2] = c2[w];
+            dir[w][0] = dx[w];
+            dir[w][1] = dy[w];
+            dir[w][2] = dz[w];
+            live[w] = gc[w][0] != 0.0f || gc[w][1] != 0.0f || gc[w][2] != 0.0f;
 #pragma unroll
-            for (int k = 0; k < 16; ++k) Y[w][k] = 0.f;
-            if (gc[w][0] != 0.0f || gc[w][1] != 0.0f || gc[w][2] != 0.0f) sh_eval<DEG>(dx[w], dy[w], dz[w], Y[w]);
+            for (int k = 0; k < 16; ++k) Y[w][k] = wk[w][k] = 0.f;
+            if (live[w]) sh_eval<DEG>(dir[w][0], dir[w][1], dir[w][2], Y[w]);
         }
     }
-    const gs_adam_group& G = adam.g[4];
     const float ibc1 = adam.bc[0], ibc2 = adam.bc[1];
+    const gs_adam_group& G = adam.g[4];
 #pragma unroll
     for (int k = 0; k < NC * 3; ++k) {
         if (k % 4 == 0) __builtin_amdgcn_sched_barrier(0);
@@ -525,6 +537,7 @@ __global__ __launch_bounds__(kBlock) void k_adam_sh(int64_t n, AdamFused adam) {
         VW v = __builtin_nontemporal_load(reinterpret_cast<const VW*>(G.v + j));
 #pragma unroll
         for (int w = 0; w < W; ++w) {
+            wk[w][k / 3] += gc[w][k % 3] * p[w];   // the coefficient before its update
             float mw = m[w], vw = v[w];
             p[w] = adam_update(p[w], Y[w][k / 3] * gc[w][k % 3], mw, vw, G.lr, adam.b1, adam.b2, adam.eps, ibc1, ibc2);
             m[w] = mw;
@@ -534,6 +547,43 @@ __global__ __launch_bounds__(kBlock) void k_adam_sh(int64_t n, AdamFused adam) {
         __builtin_nontemporal_store(m, reinterpret_cast<VW*>(G.m + j));
         __builtin_nontemporal_store(v, reinterpret_cast<VW*>(G.v + j));
     }
+    __builtin_amdgcn_sched_barrier(0);
+    // the means: gradient through the view direction added to the adjoint's part, then the step
+    float gmu[W][3];
+    {
+        const VW il = plane(6), m0 = plane(7), m1 = plane(8), m2 = plane(9);
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            gmu[w][0] = m0[w];
+            gmu[w][1] = m1[w];
+            gmu[w][2] = m2[w];
+            if (DEG > 0 && live[w]) {
+                float gd[3];
+                sh_grad<DEG>(dir[w][0], dir[w][1], dir[w][2], wk[w], gd);
+                const float dd = gd[0] * dir[w][0] + gd[1] * dir[w][1] + gd[2] * dir[w][2];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) gmu[w][q] += (gd[q] - dir[w][q] * dd) * il[w];
+            }
+        }
+    }
+    const gs_adam_group& M = adam.g[0];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int64_t j = (int64_t)q * n + i0;
+        VW p = *reinterpret_cast<const VW*>(M.param + j);
+        VW m = *reinterpret_cast<const VW*>(M.m + j);
+        VW v = *reinterpret_cast<const VW*>(M.v + j);
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            float mw = m[w], vw = v[w];
+            p[w] = adam_update(p[w], gmu[w][q], mw, vw, M.lr, adam.b1, adam.b2, adam.eps, ibc1, ibc2);
+            m[w] = mw;
+            v[w] = vw;
+        }
+        *reinterpret_cast<VW*>(M.param + j) = p;
+        *reinterpret_cast<VW*>(M.m + j) = m;
+        *reinterpret_cast<VW*>(M.v + j) = v;
+    }
 }
 
 }  // namespace
@@ -541,14 +591,16 @@ __global__ __launch_bounds__(kBlock) void k_adam_sh(int64_t n, AdamFused adam) {
 hipError_t launch_adam_sh(int64_t n, int sh_degree, const AdamFused& adam, hipStream_t s) {
     if (n == 0) return hipSuccess;
     if (!adam.shf) return hipErrorInvalidValue;
-    // 16-byte accesses need every plane (offset k n) and the factor planes 16-byte aligned
-    const bool v4 = n % 4 == 0 && ((uintptr_t)adam.shf | (uintptr_t)adam.g[4].param | (uintptr_t)adam.g[4].m |
-                                   (uintptr_t)adam.g[4].v) % 16 == 0;
-    const int64_t per = v4 ? 4 : 1;
+    // 8-byte accesses need every plane (offset k n) and the base pointers 8-byte aligned
+    const uintptr_t bases = (uintptr_t)adam.shf | (uintptr_t)adam.g[4].param | (uintptr_t)adam.g[4].m |
+                            (uintptr_t)adam.g[4].v | (uintptr_t)adam.g[0].param | (uintptr_t)adam.g[0].m |
+                            (uintptr_t)adam.g[0].v;
+    const bool v2 = n % 2 == 0 && bases % 8 == 0;
+    const int64_t per = v2 ? 2 : 1;
     const unsigned grid = (unsigned)(((n + per - 1) / per + kBlock - 1) / kBlock);
 #define GS_ASH(D)                                                                                    \
-    if (v4)                                                                                          \
-        hipLaunchKernelGGL((k_adam_sh<D, 4>), dim3(grid), dim3(kBlock), 0, s, n, adam);              \
+    if (v2)                                                                                          \
+        hipLaunchKernelGGL((k_adam_sh<D, 2>), dim3(grid), dim3(kBlock), 0, s, n, adam);              \
     else                                                                                             \
         hipLaunchKernelGGL((k_adam_sh<D, 1>), dim3(grid), dim3(kBlock), 0, s, n, adam)
     switch (sh_degree) {
@@ -586,11 +638,14 @@ template <int D, bool F>
 void project_bwd_launch(const gs_gaussians& g, int32_t views, const gs_camera* cams, float dil, const float* grad2d,
                         const Record* rec, const gs_gaussian_grads& grads, const AdamFused& adam, unsigned grid,
                         hipStream_t s) {
-    if (views == 1)
-        hipLaunchKernelGGL((k_project_bwd<D, F, true>), dim3(grid), dim3(kBlock), 0, s, g, views, cams, dil, grad2d,
-                           rec, grads, adam);
+    if (views == 1 && F && adam.shf)
+        hipLaunchKernelGGL((k_project_bwd<D, true, true, true>), dim3(grid), dim3(kBlock), 0, s, g, views, cams, dil,
+                           grad2d, rec, grads, adam);
+    else if (views == 1)
+        hipLaunchKernelGGL((k_project_bwd<D, F, true, false>), dim3(grid), dim3(kBlock), 0, s, g, views, cams, dil,
+                           grad2d, rec, grads, adam);
     else
-        hipLaunchKernelGGL((k_project_bwd<D, F, false>), dim3(grid), dim3(kBlock), 0, s, g, views, cams, dil,
+        hipLaunchKernelGGL((k_project_bwd<D, F, false, false>), dim3(grid), dim3(kBlock), 0, s, g, views, cams, dil,
                            grad2d, rec, grads, adam);
 }
 
