@@ -31,66 +31,86 @@ constexpr float kY31 = 0.4570457994644658f;
 constexpr float kY30 = 0.3731763325901154f;
 constexpr float kY322 = 1.445305721320277f;
 
-template <int DEG>
-__device__ __forceinline__ void sh_eval(float x, float y, float z, float* Y) {
-    Y[0] = kY0;
-    if constexpr (DEG >= 1) {
-        Y[1] = -kY1 * y;
-        Y[2] = kY1 * z;
-        Y[3] = -kY1 * x;
-    }
-    if constexpr (DEG >= 2) {
-        float xx = x * x, yy = y * y, zz = z * z;
-        Y[4] = kY2a * x * y;
-        Y[5] = -kY2a * y * z;
-        Y[6] = kY20 * (2.0f * zz - xx - yy);
-        Y[7] = -kY2a * x * z;
-        Y[8] = kY22 * (xx - yy);
-        if constexpr (DEG >= 3) {
-            Y[9] = -kY33 * y * (3.0f * xx - yy);
-            Y[10] = kY32 * x * y * z;
-            Y[11] = -kY31 * y * (4.0f * zz - xx - yy);
-            Y[12] = kY30 * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
-            Y[13] = -kY31 * x * (4.0f * zz - xx - yy);
-            Y[14] = kY322 * z * (xx - yy);
-            Y[15] = -kY33 * x * (xx - 3.0f * yy);
-        }
+// Real SH basis function k (0 <= k < (DEG+1)^2) at the unit direction (x, y, z); k is a
+// compile-time constant wherever the callers' loops are unrolled.
+__device__ __forceinline__ float sh_basis(int k, float x, float y, float z) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    switch (k) {
+        case 0: return kY0;
+        case 1: return -kY1 * y;
+        case 2: return kY1 * z;
+        case 3: return -kY1 * x;
+        case 4: return kY2a * x * y;
+        case 5: return -kY2a * y * z;
+        case 6: return kY20 * (2.0f * zz - xx - yy);
+        case 7: return -kY2a * x * z;
+        case 8: return kY22 * (xx - yy);
+        case 9: return -kY33 * y * (3.0f * xx - yy);
+        case 10: return kY32 * x * y * z;
+        case 11: return -kY31 * y * (4.0f * zz - xx - yy);
+        case 12: return kY30 * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+        case 13: return -kY31 * x * (4.0f * zz - xx - yy);
+        case 14: return kY322 * z * (xx - yy);
+        default: return -kY33 * x * (xx - 3.0f * yy);
     }
 }
 
-// Gradient of sum_k w_k Y_k(x, y, z) w.r.t. (x, y, z) for the polynomial forms above.
+template <int DEG>
+__device__ __forceinline__ void sh_eval(float x, float y, float z, float* Y) {
+#pragma unroll
+    for (int k = 0; k < (DEG + 1) * (DEG + 1); ++k) Y[k] = sh_basis(k, x, y, z);
+}
+
+// Adds w * grad Y_k(x, y, z) (of the polynomial forms above) to (gx, gy, gz).
+__device__ __forceinline__ void sh_grad_add(int k, float x, float y, float z, float w, float& gx, float& gy,
+                                            float& gz) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    switch (k) {
+        case 1: gy += -kY1 * w; break;
+        case 2: gz += kY1 * w; break;
+        case 3: gx += -kY1 * w; break;
+        case 4: gx += kY2a * y * w; gy += kY2a * x * w; break;
+        case 5: gy += -kY2a * z * w; gz += -kY2a * y * w; break;
+        case 6: gx += -2.f * kY20 * x * w; gy += -2.f * kY20 * y * w; gz += 4.f * kY20 * z * w; break;
+        case 7: gx += -kY2a * z * w; gz += -kY2a * x * w; break;
+        case 8: gx += 2.f * kY22 * x * w; gy += -2.f * kY22 * y * w; break;
+        case 9: gx += -kY33 * 6.f * x * y * w; gy += -kY33 * (3.f * xx - 3.f * yy) * w; break;
+        case 10: gx += kY32 * y * z * w; gy += kY32 * x * z * w; gz += kY32 * x * y * w; break;
+        case 11:
+            gx += kY31 * 2.f * x * y * w;
+            gy += -kY31 * (4.f * zz - xx - 3.f * yy) * w;
+            gz += -kY31 * 8.f * y * z * w;
+            break;
+        case 12:
+            gx += -kY30 * 6.f * x * z * w;
+            gy += -kY30 * 6.f * y * z * w;
+            gz += kY30 * (6.f * zz - 3.f * xx - 3.f * yy) * w;
+            break;
+        case 13:
+            gx += -kY31 * (4.f * zz - 3.f * xx - yy) * w;
+            gy += kY31 * 2.f * x * y * w;
+            gz += -kY31 * 8.f * x * z * w;
+            break;
+        case 14: gx += kY322 * 2.f * x * z * w; gy += -kY322 * 2.f * y * z * w; gz += kY322 * (xx - yy) * w; break;
+        case 15: gx += -kY33 * (3.f * xx - 3.f * yy) * w; gy += kY33 * 6.f * x * y * w; break;
+        default: break;   // Y_0 is constant
+    }
+}
+
+// Gradient of sum_k w_k Y_k(x, y, z) w.r.t. (x, y, z).  Summed in four interleaved partial sums
+// (k = s, s + 4, ... for s = 0..3, each in increasing k) combined as ((P0 + P1) + P2) + P3: the
+// order in which k_adam_sh forms it with four threads per group of Gaussians.
 template <int DEG>
 __device__ __forceinline__ void sh_grad(float x, float y, float z, const float* w, float* g) {
-    float gx = 0.f, gy = 0.f, gz = 0.f;
-    if constexpr (DEG >= 1) {
-        gy += -kY1 * w[1];
-        gz += kY1 * w[2];
-        gx += -kY1 * w[3];
+    float P[4][3];
+#pragma unroll
+    for (int sub = 0; sub < 4; ++sub) {
+        P[sub][0] = P[sub][1] = P[sub][2] = 0.f;
+#pragma unroll
+        for (int k = sub; k < (DEG + 1) * (DEG + 1); k += 4) sh_grad_add(k, x, y, z, w[k], P[sub][0], P[sub][1], P[sub][2]);
     }
-    if constexpr (DEG >= 2) {
-        gx += kY2a * y * w[4];            gy += kY2a * x * w[4];
-        gy += -kY2a * z * w[5];           gz += -kY2a * y * w[5];
-        gx += -2.f * kY20 * x * w[6];     gy += -2.f * kY20 * y * w[6];     gz += 4.f * kY20 * z * w[6];
-        gx += -kY2a * z * w[7];           gz += -kY2a * x * w[7];
-        gx += 2.f * kY22 * x * w[8];      gy += -2.f * kY22 * y * w[8];
-        if constexpr (DEG >= 3) {
-            float xx = x * x, yy = y * y, zz = z * z;
-            gx += -kY33 * 6.f * x * y * w[9];             gy += -kY33 * (3.f * xx - 3.f * yy) * w[9];
-            gx += kY32 * y * z * w[10];  gy += kY32 * x * z * w[10];  gz += kY32 * x * y * w[10];
-            gx += kY31 * 2.f * x * y * w[11];
-            gy += -kY31 * (4.f * zz - xx - 3.f * yy) * w[11];
-            gz += -kY31 * 8.f * y * z * w[11];
-            gx += -kY30 * 6.f * x * z * w[12];  gy += -kY30 * 6.f * y * z * w[12];
-            gz += kY30 * (6.f * zz - 3.f * xx - 3.f * yy) * w[12];
-            gx += -kY31 * (4.f * zz - 3.f * xx - yy) * w[13];
-            gy += kY31 * 2.f * x * y * w[13];
-            gz += -kY31 * 8.f * x * z * w[13];
-            gx += kY322 * 2.f * x * z * w[14];  gy += -kY322 * 2.f * y * z * w[14];
-            gz += kY322 * (xx - yy) * w[14];
-            gx += -kY33 * (3.f * xx - 3.f * yy) * w[15];  gy += kY33 * 6.f * x * y * w[15];
-        }
-    }
-    g[0] = gx; g[1] = gy; g[2] = gz;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) g[q] = ((P[0][q] + P[1][q]) + P[2][q]) + P[3][q];
 }
 
 struct Cam {
@@ -493,97 +513,127 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
     }
 }
 
-// Adam steps of the means and the SH coefficients, one view, from what the split adjoint
-// stored (kShf planes: view direction, colour gradient of the unclamped channels, inverse
-// distance to the camera centre, the means' gradient without its SH term).  The gradient of SH
-// coefficient k, channel c is Y_k(dir) gc_c, as the adjoint forms it; the means' SH term goes
-// through the direction with the coefficients read here before their update, in the adjoint's
-// order, so the 48 gradient planes are never written and the coefficients are read once.  A
-// thread steps W consecutive Gaussians (W = 2: 8-byte accesses, which needs n even).
-template <int DEG, int W>
-__global__ __launch_bounds__(kBlock) void k_adam_sh(int64_t n, AdamFused adam) {
+// One wave's share of k_adam_sh: SH coefficients k = SUB, SUB + 4, ... of its lane's W Gaussians
+// stepped, and that partial sum of the means' SH term accumulated into P.
+template <int DEG, int W, int SUB>
+__device__ __forceinline__ void adam_sh_sweep(const AdamFused& adam, int64_t n, int64_t i0,
+                                              const float (&dir)[3][W], const float (&gc)[3][W],
+                                              const bool (&live)[W], float (&P)[W][3]) {
     using VW = float __attribute__((ext_vector_type(W)));
     constexpr int NC = (DEG + 1) * (DEG + 1);
-    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * W;
-    if (i0 >= n) return;
-    const float* f = adam.shf;
-    auto plane = [&](int q) { return *reinterpret_cast<const VW*>(f + (int64_t)q * n + i0); };
-    float Y[W][16], gc[W][3], dir[W][3], wk[W][16];
-    bool live[W];
-    {
-        const VW dx = plane(0), dy = plane(1), dz = plane(2), c0 = plane(3), c1 = plane(4), c2 = plane(5);
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-            gc[w][0] = c0[w];
-            gc[w][1] = c1[w];
-            gc[w][2] = c2[w];
-            dir[w][0] = dx[w];
-            dir[w][1] = dy[w];
-            dir[w][2] = dz[w];
-            live[w] = gc[w][0] != 0.0f || gc[w][1] != 0.0f || gc[w][2] != 0.0f;
-#pragma unroll
-            for (int k = 0; k < 16; ++k) Y[w][k] = wk[w][k] = 0.f;
-            if (live[w]) sh_eval<DEG>(dir[w][0], dir[w][1], dir[w][2], Y[w]);
-        }
-    }
     const float ibc1 = adam.bc[0], ibc2 = adam.bc[1];
     const gs_adam_group& G = adam.g[4];
 #pragma unroll
-    for (int k = 0; k < NC * 3; ++k) {
-        if (k % 4 == 0) __builtin_amdgcn_sched_barrier(0);
-        const int64_t j = (int64_t)k * n + i0;
-        VW p = __builtin_nontemporal_load(reinterpret_cast<const VW*>(G.param + j));
-        VW m = __builtin_nontemporal_load(reinterpret_cast<const VW*>(G.m + j));
-        VW v = __builtin_nontemporal_load(reinterpret_cast<const VW*>(G.v + j));
+    for (int k = SUB; k < NC; k += 4) {
+        __builtin_amdgcn_sched_barrier(0);
+        float Yk[W], wk[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-            wk[w][k / 3] += gc[w][k % 3] * p[w];   // the coefficient before its update
-            float mw = m[w], vw = v[w];
-            p[w] = adam_update(p[w], Y[w][k / 3] * gc[w][k % 3], mw, vw, G.lr, adam.b1, adam.b2, adam.eps, ibc1, ibc2);
-            m[w] = mw;
-            v[w] = vw;
+            Yk[w] = live[w] ? sh_basis(k, dir[0][w], dir[1][w], dir[2][w]) : 0.f;
+            wk[w] = 0.f;
         }
-        __builtin_nontemporal_store(p, reinterpret_cast<VW*>(G.param + j));
-        __builtin_nontemporal_store(m, reinterpret_cast<VW*>(G.m + j));
-        __builtin_nontemporal_store(v, reinterpret_cast<VW*>(G.v + j));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t j = (int64_t)(3 * k + c) * n + i0;
+            VW p = __builtin_nontemporal_load(reinterpret_cast<const VW*>(G.param + j));
+            VW m = __builtin_nontemporal_load(reinterpret_cast<const VW*>(G.m + j));
+            VW v = __builtin_nontemporal_load(reinterpret_cast<const VW*>(G.v + j));
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                wk[w] += gc[c][w] * p[w];   // the coefficient before its update
+                float mw = m[w], vw = v[w];
+                p[w] = adam_update(p[w], Yk[w] * gc[c][w], mw, vw, G.lr, adam.b1, adam.b2, adam.eps, ibc1, ibc2);
+                m[w] = mw;
+                v[w] = vw;
+            }
+            __builtin_nontemporal_store(p, reinterpret_cast<VW*>(G.param + j));
+            __builtin_nontemporal_store(m, reinterpret_cast<VW*>(G.m + j));
+            __builtin_nontemporal_store(v, reinterpret_cast<VW*>(G.v + j));
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) sh_grad_add(k, dir[0][w], dir[1][w], dir[2][w], wk[w], P[w][0], P[w][1], P[w][2]);
     }
-    __builtin_amdgcn_sched_barrier(0);
-    // the means: gradient through the view direction added to the adjoint's part, then the step
-    float gmu[W][3];
-    {
-        const VW il = plane(6), m0 = plane(7), m1 = plane(8), m2 = plane(9);
+}
+
+// Adam steps of the means and the SH coefficients, one view, from what the split adjoint
+// stored (kShf planes: view direction, colour gradient of the unclamped channels, inverse
+// distance to the camera centre, the means' gradient without its SH term).  The gradient of SH
+// coefficient k, channel c is Y_k(dir) gc_c, as the adjoint forms it.  The means' SH term,
+// sum_k (sum_c gc_c sh_kc) grad Y_k, is formed from the coefficients read here before their
+// update, so the 48 gradient planes are never written and the coefficients are read once.
+// A workgroup's four waves share 64 groups of W Gaussians (W = 4: 16-byte accesses, which
+// needs n % 4 == 0): wave s steps coefficients s, s + 4, ... and keeps that partial sum of the
+// means' term; the partial sums meet in LDS and are combined in sh_grad's order, and wave
+// q < 3 steps coordinate q of the means.
+template <int DEG, int W>
+__global__ __launch_bounds__(kBlock) void k_adam_sh(int64_t n, AdamFused adam) {
+    using VW = float __attribute__((ext_vector_type(W)));
+    static_assert(kBlock == 256, "four waves per workgroup");
+    __shared__ float sP[4][3][W][64];
+    const int sub = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t i0 = ((int64_t)blockIdx.x * 64 + lane) * W;
+    const bool active = i0 < n;   // lanes past the end still meet the barrier
+    const float* f = adam.shf;
+    auto plane = [&](int q) { return *reinterpret_cast<const VW*>(f + (int64_t)q * n + i0); };
+    float dir[3][W], gc[3][W], P[W][3];
+    bool live[W];
+    if (active) {
 #pragma unroll
-        for (int w = 0; w < W; ++w) {
-            gmu[w][0] = m0[w];
-            gmu[w][1] = m1[w];
-            gmu[w][2] = m2[w];
-            if (DEG > 0 && live[w]) {
-                float gd[3];
-                sh_grad<DEG>(dir[w][0], dir[w][1], dir[w][2], wk[w], gd);
-                const float dd = gd[0] * dir[w][0] + gd[1] * dir[w][1] + gd[2] * dir[w][2];
+        for (int q = 0; q < 3; ++q) {
+            const VW d = plane(q), c = plane(3 + q);
 #pragma unroll
-                for (int q = 0; q < 3; ++q) gmu[w][q] += (gd[q] - dir[w][q] * dd) * il[w];
+            for (int w = 0; w < W; ++w) {
+                dir[q][w] = d[w];
+                gc[q][w] = c[w];
             }
         }
-    }
-    const gs_adam_group& M = adam.g[0];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const int64_t j = (int64_t)q * n + i0;
-        VW p = *reinterpret_cast<const VW*>(M.param + j);
-        VW m = *reinterpret_cast<const VW*>(M.m + j);
-        VW v = *reinterpret_cast<const VW*>(M.v + j);
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-            float mw = m[w], vw = v[w];
-            p[w] = adam_update(p[w], gmu[w][q], mw, vw, M.lr, adam.b1, adam.b2, adam.eps, ibc1, ibc2);
-            m[w] = mw;
-            v[w] = vw;
+            live[w] = gc[0][w] != 0.0f || gc[1][w] != 0.0f || gc[2][w] != 0.0f;
+            P[w][0] = P[w][1] = P[w][2] = 0.f;
         }
-        *reinterpret_cast<VW*>(M.param + j) = p;
-        *reinterpret_cast<VW*>(M.m + j) = m;
-        *reinterpret_cast<VW*>(M.v + j) = v;
+        switch (sub) {   // wave-uniform
+            case 0: adam_sh_sweep<DEG, W, 0>(adam, n, i0, dir, gc, live, P); break;
+            case 1: adam_sh_sweep<DEG, W, 1>(adam, n, i0, dir, gc, live, P); break;
+            case 2: adam_sh_sweep<DEG, W, 2>(adam, n, i0, dir, gc, live, P); break;
+            default: adam_sh_sweep<DEG, W, 3>(adam, n, i0, dir, gc, live, P); break;
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) sP[sub][q][w][lane] = P[w][q];
     }
+    __syncthreads();
+    if (!active || sub == 3) return;
+    // coordinate q = sub of the means: the SH colour's term (partial sums in sh_grad's order)
+    // added to the adjoint's part, then the step
+    const int q = sub;
+    const VW il = plane(6), gpart = plane(7 + q);
+    const gs_adam_group& M = adam.g[0];
+    const float ibc1 = adam.bc[0], ibc2 = adam.bc[1];
+    const int64_t j = (int64_t)q * n + i0;
+    VW p = *reinterpret_cast<const VW*>(M.param + j);
+    VW m = *reinterpret_cast<const VW*>(M.m + j);
+    VW v = *reinterpret_cast<const VW*>(M.v + j);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        float g = gpart[w];
+        if (DEG > 0 && live[w]) {
+            float gd[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+                gd[r] = ((sP[0][r][w][lane] + sP[1][r][w][lane]) + sP[2][r][w][lane]) + sP[3][r][w][lane];
+            const float dd = gd[0] * dir[0][w] + gd[1] * dir[1][w] + gd[2] * dir[2][w];
+            g += (gd[q] - dir[q][w] * dd) * il[w];
+        }
+        float mw = m[w], vw = v[w];
+        p[w] = adam_update(p[w], g, mw, vw, M.lr, adam.b1, adam.b2, adam.eps, ibc1, ibc2);
+        m[w] = mw;
+        v[w] = vw;
+    }
+    *reinterpret_cast<VW*>(M.param + j) = p;
+    *reinterpret_cast<VW*>(M.m + j) = m;
+    *reinterpret_cast<VW*>(M.v + j) = v;
 }
 
 }  // namespace
@@ -591,16 +641,16 @@ __global__ __launch_bounds__(kBlock) void k_adam_sh(int64_t n, AdamFused adam) {
 hipError_t launch_adam_sh(int64_t n, int sh_degree, const AdamFused& adam, hipStream_t s) {
     if (n == 0) return hipSuccess;
     if (!adam.shf) return hipErrorInvalidValue;
-    // 8-byte accesses need every plane (offset k n) and the base pointers 8-byte aligned
+    // 16-byte accesses need every plane (offset k n) and the base pointers 16-byte aligned
     const uintptr_t bases = (uintptr_t)adam.shf | (uintptr_t)adam.g[4].param | (uintptr_t)adam.g[4].m |
                             (uintptr_t)adam.g[4].v | (uintptr_t)adam.g[0].param | (uintptr_t)adam.g[0].m |
                             (uintptr_t)adam.g[0].v;
-    const bool v2 = n % 2 == 0 && bases % 8 == 0;
-    const int64_t per = v2 ? 2 : 1;
-    const unsigned grid = (unsigned)(((n + per - 1) / per + kBlock - 1) / kBlock);
+    const bool v4 = n % 4 == 0 && bases % 16 == 0;
+    const int64_t per = v4 ? 4 : 1;
+    const unsigned grid = (unsigned)(((n + per - 1) / per + 63) / 64);   // 64 groups of `per` per workgroup
 #define GS_ASH(D)                                                                                    \
-    if (v2)                                                                                          \
-        hipLaunchKernelGGL((k_adam_sh<D, 2>), dim3(grid), dim3(kBlock), 0, s, n, adam);              \
+    if (v4)                                                                                          \
+        hipLaunchKernelGGL((k_adam_sh<D, 4>), dim3(grid), dim3(kBlock), 0, s, n, adam);              \
     else                                                                                             \
         hipLaunchKernelGGL((k_adam_sh<D, 1>), dim3(grid), dim3(kBlock), 0, s, n, adam)
     switch (sh_degree) {
