@@ -371,7 +371,8 @@ def main():
     if st & N.GS_STATUS_PAIR_OVERFLOW:
         raise SystemExit(f"pair capacity overflowed during the timed steps ({K} > {ts.max_pairs})")
     stats = (ctypes.c_int64 * 5)()
-    N.check("gs_forward_stats", N.lib().gs_forward_stats(ctypes.byref(ts.opts), ts.n, 1, ts.rast.host_cams,
+    N.check("gs_forward_stats", N.lib().gs_forward_stats(ctypes.byref(ts.opts), ts.n, ts.rast.n_views,
+                                                         ts.rast.host_cams,
                                                          ctypes.c_void_p(ts.saved.data_ptr()), ts.saved.numel(),
                                                          stats, ctypes.c_void_p(stream.cuda_stream)))
     # pairs per depth phase (from the stored per-phase tile ranges)

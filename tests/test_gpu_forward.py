@@ -60,18 +60,31 @@ def test_keys_bitexact_multiview(oracle_mod):
     _keys_match(sc, U.make_rast(sc, phases=1, tile_cull=False), oracle_mod)
 
 
+def _large_splat_scene():
+    """6000 Gaussians at 203x141, three times the usual scale and fainter: about 200 entries whose
+    rectangles exceed 32 tiles fall behind the nearest 1/64, into a later depth phase."""
+    sc = synth.make_scene(1, n=6000, width=203, height=141)
+    ls = (sc.log_scales + np.float32(np.log(3.0))).astype(np.float32)
+    lg = (sc.logits - 2.0).astype(np.float32)
+    return synth.Scene(**{**sc.__dict__, "log_scales": ls, "scales": np.exp(ls).astype(np.float32), "logits": lg,
+                          "opacity": (1.0 / (1.0 + np.exp(-lg))).astype(np.float32)})
+
+
 @pytest.mark.parametrize("phases,shift,views", [(2, 0, 1), (3, 0, 1), (4, 0, 1), (2, 8, 1), (3, 2, 1),
-                                                (2, 6, 3), (3, 3, 3)])
+                                                (2, 6, 3), (3, 3, 3), (2, 6, "large"), (3, 4, "large")])
 def test_phased_lists_are_exact_prefixes(oracle_mod, phases, shift, views):
     """Depth-progressive binning stores, per tile, a prefix of the oracle's sorted list (bit-exact keys,
     cut at a phase boundary), and the images equal those of full binning bit for bit.  Later phases
     with few front Gaussians leave tiles partially alive, so rows are walked over their alive span;
-    the ragged three-view scene puts those rows at several view offsets."""
+    the ragged three-view scene puts those rows at several view offsets; the large-splat scene sends
+    rectangles of more than 32 tiles to later phases."""
     O = oracle_mod
     if views == 1:
         sc = synth.make_scene(1, n=20000, width=203, height=141)
-    else:
+    elif views == 3:
         sc = synth.make_scene(3, n=20000, n_views=3, view_sizes=[(203, 141), (130, 77), (96, 160)])
+    else:
+        sc = _large_splat_scene()
     U.say(f"phased prefixes {phases} shift {shift} views {views}")
     rast = U.make_rast(sc, phases=phases, phase0_shift=shift, tile_cull=False)
     rgb, depth, alpha, ctx, _ = U.forward(sc, rast)
@@ -94,6 +107,18 @@ def test_phased_lists_are_exact_prefixes(oracle_mod, phases, shift, views):
     assert stored == k.size
     full = U.forward(sc, U.make_rast(sc, phases=1))[:3]
     for a, b in zip((rgb, depth, alpha), full):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("phases,shift", [(2, 6), (3, 4)])
+def test_large_rectangles_in_later_phases_with_culling(phases, shift):
+    """Rectangles of more than 32 tiles in later phases, with the exact tile culling on: images equal
+    those of full binning without culling bit for bit."""
+    sc = _large_splat_scene()
+    U.say(f"large rectangles, culling, phases {phases} shift {shift}")
+    got = U.forward(sc, U.make_rast(sc, phases=phases, phase0_shift=shift, tile_cull=True))
+    ref = U.forward(sc, U.make_rast(sc, phases=1, tile_cull=False))
+    for a, b in zip(got[:3], ref[:3]):
         assert torch.equal(a, b)
 
 
