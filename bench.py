@@ -96,7 +96,7 @@ def kernel_bytes(name: str, n: int, views: int, K: int, P: int, tiles: int, ncoe
     """
     per_step = max(1, per_step)
     NV = n * views
-    tile_passes = (int(tiles).bit_length() + 7) // 8   # radix passes over tile ids 0..tiles
+    tile_passes = (int(tiles).bit_length() + 8) // 9   # radix passes (digits of at most 9 bits) over tile ids 0..tiles
     param = n * (3 + 3 + 4 + 1 + 3 * ncoef) * 4
     nsh0 = n * (3 + 3 + 4 + 1) * 4                     # the non-SH parameters
     table = {

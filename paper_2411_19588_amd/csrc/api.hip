@@ -88,7 +88,7 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     int bits = 1;   // tile ids 0..tiles-1 plus the id `tiles` of culled pairs
     while ((1LL << bits) <= tiles) ++bits;
     L->tile_bits = bits;
-    L->tile_passes = (bits + kRadixBits - 1) / kRadixBits;
+    L->tile_passes = (bits + kMaxRadixBits - 1) / kMaxRadixBits;
     auto parts_for = [](int64_t count) {   // one radix tile per partition up to kMaxSortParts partitions
         int64_t p = (count + (int64_t)kSortTile - 1) / (int64_t)kSortTile;
         if (p < 1) p = 1;
@@ -131,7 +131,7 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     L->w_vals_a = w.take(K * 4);
     L->w_tiles_b = w.take(K * 4);
     L->w_vals_b = w.take(K * 4);
-    L->w_hist = w.take(((size_t)kRadix * parts + kRadix) * 4);   // + per-digit row totals
+    L->w_hist = w.take(((size_t)kMaxRadix * parts + kMaxRadix) * 4);   // + per-digit row totals
     L->w_grad2d = w.take(nv * kGrad2D * 4);
     L->w_medpart = w.take(T * 9 * 4 + 256);   // + persistent-mode tile counter of the backward
     L->w_adam = w.take(16);                    // bias corrections of a fused Adam step

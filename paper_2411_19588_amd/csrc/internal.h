@@ -11,8 +11,10 @@ namespace gs {
 constexpr int kBlock = 256;              // threads per workgroup for 1D kernels (4 wave64)
 constexpr int kSortItems = 8;            // keys per thread per radix tile
 constexpr int kSortTile = kBlock * kSortItems;
-constexpr int kRadixBits = 8;
+constexpr int kRadixBits = 8;             // digit width of most radix passes
 constexpr int kRadix = 1 << kRadixBits;
+constexpr int kMaxRadixBits = 9;          // widest digit (a pass of a 17- or 18-bit key)
+constexpr int kMaxRadix = 1 << kMaxRadixBits;
 constexpr int kMaxSortParts = 1024;
 constexpr int kGrad2D = 10;              // per-(Gaussian, view) 2D gradient: m(2), conic'(3), o, rgb(3), depth
 constexpr int kDefaultPhases = 2;

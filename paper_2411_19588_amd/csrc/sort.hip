@@ -11,6 +11,9 @@
 //                   on runs of equal keys).
 //   2. k_scan_rows: one workgroup per digit scans that digit's row of the
 //                   digit-major [radix][parts] table and records the row total.
+// A key of b bits takes ceil(b / 9) passes of at most 9 bits, split evenly: 8-bit
+// digits use 256 counters, 9-bit digits 512 (two per thread in the block scans), so
+// 17-bit tile ids (up to 131071 tiles) take two passes instead of three.
 //   3. k_scatter:   each partition turns the row totals into digit bases, then
 //                   re-reads its range tile by tile (2048 keys), ranks keys
 //                   stably inside each wave with the same ballots, combines the
@@ -46,14 +49,15 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t digit, int nbits, uint6
     return m;
 }
 
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_hist(const uint32_t* __restrict__ keys, const uint32_t* n_dev,
                                                 uint32_t n_host, int shift, int nbits, int parts, int use_drop,
                                                 uint32_t drop, uint32_t* __restrict__ hist) {
-    __shared__ uint32_t h[kRadix];
+    __shared__ uint32_t h[D];
     const uint32_t n = load_n(n_dev, n_host);
     if (n == 0) return;   // nothing to sort (an empty phase): the scan and the scatter return too
     const int tid = threadIdx.x, lane = tid & 63;
-    for (int i = tid; i < kRadix; i += kBlock) h[i] = 0;
+    for (int i = tid; i < D; i += kBlock) h[i] = 0;
     __syncthreads();
     const uint32_t mask = (1u << nbits) - 1u;
     uint32_t t0, t1;
@@ -75,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_hist(const uint32_t* __restrict__ ke
         }
     }
     __syncthreads();
-    for (int d = tid; d < kRadix; d += kBlock) hist[(size_t)d * parts + blockIdx.x] = h[d];
+    for (int d = tid; d < D; d += kBlock) hist[(size_t)d * parts + blockIdx.x] = h[d];
 }
 
 // Block-wide exclusive scan of one u32 per thread (256 threads = 4 waves); returns the
@@ -131,16 +135,18 @@ __global__ __launch_bounds__(kBlock) void k_scan_rows(uint32_t* __restrict__ his
     if (tid == 0) totals[blockIdx.x] = total;
 }
 
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                    const uint32_t* n_dev, uint32_t n_host, int shift, int nbits,
                                                    int parts, const uint32_t* __restrict__ hist,
                                                    const uint32_t* __restrict__ totals, int use_drop,
                                                    uint32_t drop, uint32_t* __restrict__ n_kept) {
-    static_assert(kRadix == kBlock, "one digit per thread in the block scans");
-    __shared__ uint32_t run[kRadix];        // global write base of each digit for the next tile
-    __shared__ uint32_t wcnt[4][kRadix];    // per-wave digit counts, then per-wave digit offsets in the tile
-    __shared__ uint32_t tstart[kRadix];     // first slot of each digit in the LDS-ordered tile
+    constexpr int DPT = D / kBlock;   // digits per thread in the block scans: thread t owns t*DPT + j
+    static_assert(DPT * kBlock == D && (DPT == 1 || DPT == 2), "256 or 512 digits");
+    __shared__ uint32_t run[D];       // global write base of each digit for the next tile
+    __shared__ uint32_t wcnt[4][D];   // per-wave digit counts, then per-wave digit offsets in the tile
+    __shared__ uint32_t tstart[D];    // first slot of each digit in the LDS-ordered tile
     __shared__ uint32_t scan_tmp[kBlock / 64];
     __shared__ uint32_t sk[kSortTile], sv[kSortTile];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -151,17 +157,29 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
         return;
     }
     {
-        uint32_t tot;
         // only the pass's 2^nbits digit rows were scanned
-        const uint32_t base = block_exclusive_scan((uint32_t)tid <= mask ? totals[tid] : 0u, scan_tmp, tot);
-        run[tid] = base + hist[(size_t)tid * parts + blockIdx.x];
+        uint32_t tv[DPT], sum = 0;
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const uint32_t d = (uint32_t)(tid * DPT + j);
+            tv[j] = d <= mask ? totals[d] : 0u;
+            sum += tv[j];
+        }
+        uint32_t tot;
+        uint32_t b = block_exclusive_scan(sum, scan_tmp, tot);
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const int d = tid * DPT + j;
+            run[d] = b + hist[(size_t)d * parts + blockIdx.x];
+            b += tv[j];
+        }
         if (n_kept && blockIdx.x == 0 && tid == 0) *n_kept = tot;   // keys kept (equal to drop: left out)
     }
     uint32_t t0, t1;
     part_range(n, parts, blockIdx.x, t0, t1);
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (uint32_t t = t0; t < t1; ++t) {
-        for (int i = tid; i < 4 * kRadix; i += kBlock) (&wcnt[0][0])[i] = 0;
+        for (int i = tid; i < 4 * D; i += kBlock) (&wcnt[0][0])[i] = 0;
         __syncthreads();
         const uint32_t tbase = t * kSortTile;
         // wave w ranks elements [tbase + w*512, tbase + (w+1)*512) in order: item k, lane l.
@@ -186,18 +204,32 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
             __builtin_amdgcn_wave_barrier();
         }
         __syncthreads();
-        // digit d = tid: wave offsets inside the digit, tile-local digit start, advance the global base
-        uint32_t cnt = 0;
+        // the thread's digits: wave offsets inside each digit, tile-local digit starts, global bases
+        uint32_t cnt[DPT], csum = 0;
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            const uint32_t c = wcnt[w][tid];
-            wcnt[w][tid] = cnt;
-            cnt += c;
+        for (int j = 0; j < DPT; ++j) {
+            const int d = tid * DPT + j;
+            uint32_t c = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const uint32_t x = wcnt[w][d];
+                wcnt[w][d] = c;
+                c += x;
+            }
+            cnt[j] = c;
+            csum += c;
         }
         uint32_t tot;
-        const uint32_t ts = block_exclusive_scan(cnt, scan_tmp, tot);
-        tstart[tid] = ts;
-        const uint32_t gbase = run[tid];
+        uint32_t ts = block_exclusive_scan(csum, scan_tmp, tot);
+        uint32_t tsj[DPT], gbase[DPT];
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) {
+            const int d = tid * DPT + j;
+            tsj[j] = ts;
+            tstart[d] = ts;
+            ts += cnt[j];
+            gbase[j] = run[d];
+        }
         __syncthreads();
         // reorder the tile in LDS by digit (stable)
 #pragma unroll
@@ -213,7 +245,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
             }
         }
         // LDS slot i of digit d goes to global slot (run[d] - tstart[d]) + i
-        run[tid] = gbase - ts;
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) run[tid * DPT + j] = gbase[j] - tsj[j];
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
@@ -228,7 +261,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
             }
         }
         __syncthreads();
-        run[tid] = gbase + cnt;
+#pragma unroll
+        for (int j = 0; j < DPT; ++j) run[tid * DPT + j] = gbase[j] + cnt[j];
         __syncthreads();
     }
 }
@@ -239,33 +273,47 @@ hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, 
                           const uint32_t* n_dev, uint32_t n_host, int bit0, int nbits, int parts,
                           uint32_t* hist, int* result_in_b, const char* tag, void* timer, hipStream_t s,
                           int use_drop, uint32_t drop_key, uint32_t* n_kept) {
+    if (nbits < 1 || nbits > 32) return hipErrorInvalidValue;
     const std::string th = std::string(tag) + "_hist", ts = std::string(tag) + "_scan",
                       tc = std::string(tag) + "_scatter";
-    uint32_t* totals = hist + (size_t)kRadix * parts;
-    int in_b = 0;
-    for (int done = 0; done < nbits; done += kRadixBits) {
-        const int bits = nbits - done < kRadixBits ? nbits - done : kRadixBits;
+    uint32_t* totals = hist + (size_t)kMaxRadix * parts;
+    // ceil(nbits / 9) passes, the bits split as evenly as possible (at most 9 per pass)
+    const int passes = (nbits + kMaxRadixBits - 1) / kMaxRadixBits;
+    int in_b = 0, done = 0;
+    for (int q = 0; q < passes; ++q) {
+        const int bits = nbits / passes + (q < nbits % passes ? 1 : 0);
         const int shift = bit0 + done;
         const uint32_t* kin = in_b ? keys_b : keys_a;
         const uint32_t* vin = in_b ? vals_b : vals_a;
         uint32_t* kout = in_b ? keys_a : keys_b;
         uint32_t* vout = in_b ? vals_a : vals_b;
         // the first pass leaves out the keys equal to drop_key; later passes sort the kept ones
-        const bool first = done == 0;
+        const bool first = q == 0;
         const int drop_now = first && use_drop ? 1 : 0;
         const uint32_t* n_in = (!first && n_kept) ? n_kept : n_dev;
+        const bool wide = bits > kRadixBits;   // 512 digit counters
         timer_begin(timer, th.c_str(), s);
-        hipLaunchKernelGGL(k_hist, dim3(parts), dim3(kBlock), 0, s, kin, n_in, n_host, shift, bits, parts, drop_now,
-                           drop_key, hist);
+        if (wide)
+            hipLaunchKernelGGL(k_hist<kMaxRadix>, dim3(parts), dim3(kBlock), 0, s, kin, n_in, n_host, shift, bits,
+                               parts, drop_now, drop_key, hist);
+        else
+            hipLaunchKernelGGL(k_hist<kRadix>, dim3(parts), dim3(kBlock), 0, s, kin, n_in, n_host, shift, bits, parts,
+                               drop_now, drop_key, hist);
         timer_end(timer, s);
         timer_begin(timer, ts.c_str(), s);
         hipLaunchKernelGGL(k_scan_rows, dim3(1u << bits), dim3(kBlock), 0, s, hist, parts, totals, n_in, n_host);
         timer_end(timer, s);
         timer_begin(timer, tc.c_str(), s);
-        hipLaunchKernelGGL(k_scatter, dim3(parts), dim3(kBlock), 0, s, kin, vin, kout, vout, n_in, n_host, shift,
-                           bits, parts, hist, totals, drop_now, drop_key, first ? n_kept : nullptr);
+        if (wide)
+            hipLaunchKernelGGL(k_scatter<kMaxRadix>, dim3(parts), dim3(kBlock), 0, s, kin, vin, kout, vout, n_in,
+                               n_host, shift, bits, parts, hist, totals, drop_now, drop_key,
+                               first ? n_kept : nullptr);
+        else
+            hipLaunchKernelGGL(k_scatter<kRadix>, dim3(parts), dim3(kBlock), 0, s, kin, vin, kout, vout, n_in, n_host,
+                               shift, bits, parts, hist, totals, drop_now, drop_key, first ? n_kept : nullptr);
         timer_end(timer, s);
         in_b = !in_b;
+        done += bits;
     }
     *result_in_b = in_b;
     return hipGetLastError();

@@ -54,6 +54,25 @@ def test_keys_bitexact_many_sort_tiles(oracle_mod):
     assert K > 5_000_000
 
 
+def test_keys_bitexact_nine_bit_digit(oracle_mod):
+    """400x300 has 475 tiles: tile ids (with the culled id) need 9 bits, sorted in one pass of 512
+    digit counters."""
+    sc = synth.make_scene(1, n=20000, width=400, height=300)
+    U.say("keys nine-bit digit")
+    rast = U.make_rast(sc, phases=1, tile_cull=False)
+    assert rast.tile_count() == 475
+    _keys_match(sc, rast, oracle_mod)
+
+
+def test_keys_bitexact_seventeen_bit_tile_ids(oracle_mod):
+    """Nine 1920x1080 views: 73440 tiles, 17-bit tile ids sorted in two passes (9 + 8 bits)."""
+    sc = synth.make_scene(3, n=20000, n_views=9, view_sizes=[(1920, 1080)] * 9)
+    U.say("keys seventeen-bit tile ids")
+    rast = U.make_rast(sc, phases=1, tile_cull=False, max_pairs=8_000_000)
+    assert rast.tile_count() == 9 * 8160
+    _keys_match(sc, rast, oracle_mod)
+
+
 def test_keys_bitexact_multiview(oracle_mod):
     sc = synth.make_scene(3, n=5000, n_views=3, view_sizes=[(96, 64), (130, 77), (64, 64)])
     U.say("keys multiview")
