@@ -84,6 +84,9 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     if (tiles >= (1LL << 31)) return GS_ERR_INVALID_ARGUMENT;
     L->tiles = tiles;
     L->rows = rows;
+    int64_t max_tx = 1;
+    for (int v = 0; v < n_views; ++v) max_tx = L->table.v[v].tiles_x > max_tx ? L->table.v[v].tiles_x : max_tx;
+    L->row_words = (max_tx + 63) / 64;
     L->pixels = pixels;
     int bits = 1;   // tile ids 0..tiles-1 plus the id `tiles` of culled pairs
     while ((1LL << bits) <= tiles) ++bits;
@@ -136,6 +139,7 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     L->w_medpart = w.take(T * 9 * 4 + 256);   // + persistent-mode tile counter of the backward
     L->w_adam = w.take(16);                    // bias corrections of a fused Adam step
     L->w_rowspan = w.take(rows * 8);           // alive columns per tile row (later depth phases)
+    L->w_rowbits = w.take((size_t)rows * L->row_words * 8);   // and their bit masks
     L->w_shf = w.take(n_views == 1 ? (size_t)n * kShf * 4 : 0);   // SH-gradient factors etc. (fused Adam)
     L->workspace_bytes = w.at;
     return GS_OK;
@@ -298,21 +302,22 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
     float* dsum = at<float>(saved, L.s_dsum);
     float* wsum = at<float>(saved, L.s_wsum);
     const CullArgs cull{rec, log2f(o.alpha_min), o.tile_w, o.tile_h, o.tile_cull};
-    uint2* rowspan = at<uint2>(workspace, L.w_rowspan);
+    const AliveRows ar{at<uint2>(workspace, L.w_rowspan), at<uint64_t>(workspace, L.w_rowbits),
+                       (uint32_t)L.row_words};
     for (int ph = 0; ph < L.phases; ++ph) {
         if (ph > 0) {
             timer_begin(T, "alive_rows", s);
-            GS_TRY(launch_alive_rows(vt, L.views, L.rows, alive, rowspan, s));
+            GS_TRY(launch_alive_rows(vt, L.views, L.rows, alive, ar, s));
             timer_end(T, s);
         }
         timer_begin(T, "phase_count", s);
-        GS_TRY(launch_phase_count(order, counts, rects, L.nv, L.n, vt, alive, rowspan, hdr, ph, cull, pcounts, s));
+        GS_TRY(launch_phase_count(order, counts, rects, L.nv, L.n, vt, alive, ar, hdr, ph, cull, pcounts, s));
         timer_end(T, s);
         timer_begin(T, "count_scan", s);
         GS_TRY(launch_count_scan(pcounts, L.nv, offsets, blocksums, hdr, ph, L.max_pairs, emit_start, s));
         timer_end(T, s);
         timer_begin(T, "emit", s);
-        GS_TRY(launch_emit(order, offsets, emit_start, pcounts, rects, L.nv, L.n, vt, alive, rowspan, hdr, ph,
+        GS_TRY(launch_emit(order, offsets, emit_start, pcounts, rects, L.nv, L.n, vt, alive, ar, hdr, ph,
                            L.max_pairs, cull, (uint32_t)L.tiles, tiles_a, vals_a, s));
         timer_end(T, s);
         // stable sort of the phase's pairs by tile id

@@ -103,12 +103,28 @@ __device__ __forceinline__ bool phase_empty(const SavedHeader* hdr, int phase) {
     return phase > 0 && hdr->phase_alive[phase - 1] == 0;
 }
 
+// The alive columns of [lo, hi] in one tile row, from the row's bit masks: one load per 64 columns.
+template <typename F>
+__device__ __forceinline__ void for_alive_columns(const uint64_t* __restrict__ bits, uint32_t lo, uint32_t hi, F&& f) {
+    for (uint32_t w = lo >> 6; w <= (hi >> 6); ++w) {
+        uint64_t m = bits[w];
+        if (w == (lo >> 6)) m &= ~0ull << (lo & 63);
+        if (w == (hi >> 6) && (hi & 63) != 63) m &= (2ull << (hi & 63)) - 1ull;
+        while (m) {
+            const uint32_t tx = w * 64 + (uint32_t)__builtin_ctzll(m);
+            m &= m - 1ull;
+            if (!f(tx)) return;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restrict__ order,
                                                        const uint32_t* __restrict__ counts,
                                                        const uint2* __restrict__ rects, int64_t nv, int64_t n,
                                                        const ViewInfo* __restrict__ vt,
                                                        const uint32_t* __restrict__ alive,
                                                        const uint2* __restrict__ rowspan,
+                                                       const uint64_t* __restrict__ rowbits, uint32_t row_words,
                                                        const SavedHeader* __restrict__ hdr, int phase,
                                                        CullArgs cull, uint32_t* __restrict__ pcounts) {
     if (phase_empty(hdr, phase)) return;   // no tile left: nothing reads this phase's counts
@@ -131,12 +147,14 @@ __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restri
                 rb = make_float2(cull.rec[e].b.x, cull.rec[e].b.y);
             }
             for (uint32_t ty = y0; ty <= y1; ++ty) {
-                // only the alive part of the row: a later phase walks few tiles of most rectangles
+                // only the alive columns of the row: a later phase walks few tiles of most rectangles
                 const uint2 sp = rowspan[vi.row_base + ty];
                 const uint32_t lo = max(x0, sp.x), hi = min(x1, sp.y);
-                const uint32_t row = vi.tile_base + ty * (uint32_t)vi.tiles_x;
-                for (uint32_t tx = lo; tx <= hi; ++tx)
-                    c += alive[row + tx] != 0u && (!cull.enabled || tile_may_contribute(ra, rb, vi, tx, ty, cull));
+                if (lo > hi) continue;
+                for_alive_columns(rowbits + (size_t)(vi.row_base + ty) * row_words, lo, hi, [&](uint32_t tx) {
+                    c += !cull.enabled || tile_may_contribute(ra, rb, vi, tx, ty, cull);
+                    return true;
+                });
             }
         }
     }
@@ -338,6 +356,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_alive(const uint32_t* __restric
                                                       const ViewInfo* __restrict__ vt,
                                                       const uint32_t* __restrict__ alive,
                                                       const uint2* __restrict__ rowspan,
+                                                      const uint64_t* __restrict__ rowbits, uint32_t row_words,
                                                       const SavedHeader* __restrict__ hdr, int phase,
                                                       CullArgs cull, uint32_t* __restrict__ tiles_out,
                                                       uint32_t* __restrict__ vals_out) {
@@ -363,28 +382,33 @@ __global__ __launch_bounds__(kBlock) void k_emit_alive(const uint32_t* __restric
     for (uint32_t ty = y0; ty <= y1 && off < end; ++ty) {
         const uint2 sp = rowspan[vi.row_base + ty];
         const uint32_t lo = max(x0, sp.x), hi = min(x1, sp.y);
+        if (lo > hi) continue;
         const uint32_t row = vi.tile_base + ty * (uint32_t)vi.tiles_x;
-        for (uint32_t tx = lo; tx <= hi && off < end; ++tx) {
-            if (alive[row + tx] == 0u) continue;
-            if (cull.enabled && !tile_may_contribute(ra, rb, vi, tx, ty, cull)) continue;
+        for_alive_columns(rowbits + (size_t)(vi.row_base + ty) * row_words, lo, hi, [&](uint32_t tx) {
+            if (cull.enabled && !tile_may_contribute(ra, rb, vi, tx, ty, cull)) return true;
             tiles_out[off] = row + tx;
             vals_out[off] = e;
-            ++off;
-        }
+            return ++off < end;
+        });
     }
 }
 
 // One wave per global tile row: the first and last column whose tile is still alive.
 __global__ __launch_bounds__(64) void k_alive_rows(const ViewInfo* __restrict__ vt, int32_t views,
-                                                  const uint32_t* __restrict__ alive, uint2* __restrict__ rowspan) {
+                                                  const uint32_t* __restrict__ alive, uint2* __restrict__ rowspan,
+                                                  uint64_t* __restrict__ rowbits, uint32_t row_words) {
     const uint32_t r = blockIdx.x;
     int v = 0;
     while (v + 1 < views && r >= vt[v + 1].row_base) ++v;
     const ViewInfo vi = vt[v];
     const uint32_t ty = r - vi.row_base;
     uint32_t lo = 0xFFFFFFFFu, hi = 0;
-    for (uint32_t tx = threadIdx.x; tx < (uint32_t)vi.tiles_x; tx += 64) {
-        if (alive[vi.tile_base + ty * (uint32_t)vi.tiles_x + tx] != 0u) {
+    for (uint32_t w = 0; w < row_words; ++w) {   // bit b of word w: column 64 w + b is alive
+        const uint32_t tx = w * 64 + threadIdx.x;
+        const bool a = tx < (uint32_t)vi.tiles_x && alive[vi.tile_base + ty * (uint32_t)vi.tiles_x + tx] != 0u;
+        const uint64_t m = __ballot(a);
+        if (threadIdx.x == 0) rowbits[(size_t)r * row_words + w] = m;
+        if (a) {
             lo = min(lo, tx);
             hi = max(hi, tx);
         }
@@ -449,20 +473,21 @@ hipError_t launch_visible(int phases, int phase0_shift, SavedHeader* hdr, hipStr
 }
 
 hipError_t launch_phase_count(const uint32_t* order, const uint32_t* counts, const uint2* rects, int64_t nv,
-                              int64_t n, const ViewInfo* vt, const uint32_t* alive, const uint2* rowspan,
+                              int64_t n, const ViewInfo* vt, const uint32_t* alive, const AliveRows& ar,
                               const SavedHeader* hdr, int phase, const CullArgs& cull, uint32_t* pcounts,
                               hipStream_t s) {
     if (nv == 0) return hipSuccess;
     const unsigned grid = (unsigned)((nv + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_phase_count, dim3(grid), dim3(kBlock), 0, s, order, counts, rects, nv, n, vt, alive,
-                       rowspan, hdr, phase, cull, pcounts);
+                       ar.span, ar.bits, ar.words, hdr, phase, cull, pcounts);
     return hipGetLastError();
 }
 
-hipError_t launch_alive_rows(const ViewInfo* vt, int32_t views, int64_t rows, const uint32_t* alive, uint2* rowspan,
-                             hipStream_t s) {
+hipError_t launch_alive_rows(const ViewInfo* vt, int32_t views, int64_t rows, const uint32_t* alive,
+                             const AliveRows& ar, hipStream_t s) {
     if (rows == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_alive_rows, dim3((unsigned)rows), dim3(64), 0, s, vt, views, alive, rowspan);
+    hipLaunchKernelGGL(k_alive_rows, dim3((unsigned)rows), dim3(64), 0, s, vt, views, alive, ar.span, ar.bits,
+                       ar.words);
     return hipGetLastError();
 }
 
@@ -480,7 +505,7 @@ hipError_t launch_count_scan(const uint32_t* pcounts, int64_t nv, uint64_t* offs
 
 hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uint32_t* emit_start,
                        const uint32_t* pcounts, const uint2* rects, int64_t nv, int64_t n, const ViewInfo* vt,
-                       const uint32_t* alive, const uint2* rowspan, const SavedHeader* hdr, int phase,
+                       const uint32_t* alive, const AliveRows& ar, const SavedHeader* hdr, int phase,
                        int64_t max_pairs, const CullArgs& cull, uint32_t n_tiles, uint32_t* tiles_out,
                        uint32_t* vals_out, hipStream_t s) {
     if (nv == 0 || max_pairs == 0) return hipSuccess;
@@ -491,7 +516,7 @@ hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uin
     } else {
         const unsigned grid = (unsigned)((nv + kBlock - 1) / kBlock);
         hipLaunchKernelGGL(k_emit_alive, dim3(grid), dim3(kBlock), 0, s, order, offsets, pcounts, rects, nv, n, vt,
-                           alive, rowspan, hdr, phase, cull, tiles_out, vals_out);
+                           alive, ar.span, ar.bits, ar.words, hdr, phase, cull, tiles_out, vals_out);
     }
     return hipGetLastError();
 }

@@ -66,7 +66,7 @@ struct SavedHeader {
 };
 
 struct Layout {
-    int64_t n, nv, pixels, tiles, rows, max_pairs;
+    int64_t n, nv, pixels, tiles, rows, row_words, max_pairs;
     int32_t views, phases, phase0_shift;
     int32_t tile_w, tile_h, tile_bits, tile_passes, pair_parts, depth_parts;
     ViewTable table;
@@ -75,7 +75,7 @@ struct Layout {
     size_t s_tfinal, s_nlast, s_done, s_cair, s_dsum, s_wsum, saved_bytes;
     // workspace offsets (bytes)
     size_t w_counts, w_rects, w_dkeys, w_dvals, w_dkeys2, w_dvals2, w_pcounts, w_offsets, w_blocksums, w_emit_start;
-    size_t w_tiles_a, w_vals_a, w_tiles_b, w_vals_b, w_hist, w_grad2d, w_medpart, w_adam, w_rowspan, w_shf, workspace_bytes;
+    size_t w_tiles_a, w_vals_a, w_tiles_b, w_vals_b, w_hist, w_grad2d, w_medpart, w_adam, w_rowspan, w_rowbits, w_shf, workspace_bytes;
 };
 
 int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_camera* cams, Layout* L);
@@ -143,13 +143,19 @@ struct CullArgs {
     int32_t enabled;
 };
 
+// Per global tile row, after a phase: the first and last alive column (x > y when the row has
+// none), and bit masks of the alive columns (`words` 64-bit words per row).
+struct AliveRows {
+    uint2* span;
+    uint64_t* bits;
+    uint32_t words;
+};
 hipError_t launch_phase_count(const uint32_t* order, const uint32_t* counts, const uint2* rects, int64_t nv,
-                              int64_t n, const ViewInfo* vt, const uint32_t* alive, const uint2* rowspan,
+                              int64_t n, const ViewInfo* vt, const uint32_t* alive, const AliveRows& ar,
                               const SavedHeader* hdr, int phase, const CullArgs& cull, uint32_t* pcounts,
                               hipStream_t s);
-// Per global tile row, the first and last alive tile column (x > y when the row has none).
-hipError_t launch_alive_rows(const ViewInfo* vt, int32_t views, int64_t rows, const uint32_t* alive, uint2* rowspan,
-                             hipStream_t s);
+hipError_t launch_alive_rows(const ViewInfo* vt, int32_t views, int64_t rows, const uint32_t* alive,
+                             const AliveRows& ar, hipStream_t s);
 // Exclusive scan of pcounts into offsets (u64) and the phase's pair count and base in hdr (with the
 // capacity check), and for each emission span of 1024 pairs the entry that owns its first pair.
 hipError_t launch_count_scan(const uint32_t* pcounts, int64_t nv, uint64_t* offsets, uint64_t* blocksums,
@@ -159,7 +165,7 @@ hipError_t launch_count_scan(const uint32_t* pcounts, int64_t nv, uint64_t* offs
 // unculled tiles.
 hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uint32_t* emit_start,
                        const uint32_t* pcounts, const uint2* rects, int64_t nv, int64_t n, const ViewInfo* vt,
-                       const uint32_t* alive, const uint2* rowspan, const SavedHeader* hdr, int phase,
+                       const uint32_t* alive, const AliveRows& ar, const SavedHeader* hdr, int phase,
                        int64_t max_pairs, const CullArgs& cull, uint32_t n_tiles, uint32_t* tiles_out,
                        uint32_t* vals_out, hipStream_t s);
 // Copy the phase's tile-sorted values behind the earlier phases' and record its tile ranges.
