@@ -466,12 +466,14 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
         return;
     }
     const float ibc1 = adam.bc[0], ibc2 = adam.bc[1];
+    // parameters, moments and activated copies are streamed (non-temporal), as in the flat Adam kernel
     auto step = [&](const gs_adam_group& G, int64_t j, float grad) {
-        float m = G.m[j], v = G.v[j];
-        const float np = adam_update(G.param[j], grad, m, v, G.lr, adam.b1, adam.b2, adam.eps, ibc1, ibc2);
-        G.param[j] = np;
-        G.m[j] = m;
-        G.v[j] = v;
+        float m = __builtin_nontemporal_load(G.m + j), v = __builtin_nontemporal_load(G.v + j);
+        const float np = adam_update(__builtin_nontemporal_load(G.param + j), grad, m, v, G.lr, adam.b1, adam.b2,
+                                     adam.eps, ibc1, ibc2);
+        __builtin_nontemporal_store(np, G.param + j);
+        __builtin_nontemporal_store(m, G.m + j);
+        __builtin_nontemporal_store(v, G.v + j);
         return np;
     };
     // The updates below are fenced for the scheduler in groups (16 SH coefficients = 48 loads
@@ -485,7 +487,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
 #pragma unroll
     for (int k = 0; k < 3; ++k) {   // d exp(l)/dl = exp(l) = the activated scale
         const float nl = step(adam.g[1], (int64_t)k * n + i, gsc[k] * s[k]);
-        adam.g[1].activated[(int64_t)k * n + i] = expf(nl);
+        __builtin_nontemporal_store(expf(nl), adam.g[1].activated + (int64_t)k * n + i);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -494,7 +496,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
     {   // d sigmoid(x)/dx = o (1 - o)
         const float o = g.opacity[i];
         const float nx = step(adam.g[3], i, gop * (o * (1.0f - o)));
-        adam.g[3].activated[i] = 1.0f / (1.0f + expf(-nx));
+        __builtin_nontemporal_store(1.0f / (1.0f + expf(-nx)), adam.g[3].activated + i);
     }
     if (SPLIT) {   // the means' and the SH coefficients' steps run in k_adam_sh from these
 #pragma unroll
@@ -612,9 +614,9 @@ __global__ __launch_bounds__(kBlock) void k_adam_sh(int64_t n, AdamFused adam) {
     const gs_adam_group& M = adam.g[0];
     const float ibc1 = adam.bc[0], ibc2 = adam.bc[1];
     const int64_t j = (int64_t)q * n + i0;
-    VW p = *reinterpret_cast<const VW*>(M.param + j);
-    VW m = *reinterpret_cast<const VW*>(M.m + j);
-    VW v = *reinterpret_cast<const VW*>(M.v + j);
+    VW p = __builtin_nontemporal_load(reinterpret_cast<const VW*>(M.param + j));
+    VW m = __builtin_nontemporal_load(reinterpret_cast<const VW*>(M.m + j));
+    VW v = __builtin_nontemporal_load(reinterpret_cast<const VW*>(M.v + j));
 #pragma unroll
     for (int w = 0; w < W; ++w) {
         float g = gpart[w];
@@ -631,9 +633,9 @@ __global__ __launch_bounds__(kBlock) void k_adam_sh(int64_t n, AdamFused adam) {
         m[w] = mw;
         v[w] = vw;
     }
-    *reinterpret_cast<VW*>(M.param + j) = p;
-    *reinterpret_cast<VW*>(M.m + j) = m;
-    *reinterpret_cast<VW*>(M.v + j) = v;
+    __builtin_nontemporal_store(p, reinterpret_cast<VW*>(M.param + j));
+    __builtin_nontemporal_store(m, reinterpret_cast<VW*>(M.m + j));
+    __builtin_nontemporal_store(v, reinterpret_cast<VW*>(M.v + j));
 }
 
 }  // namespace
