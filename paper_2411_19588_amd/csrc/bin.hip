@@ -131,8 +131,11 @@ __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restri
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (r >= nv) return;
     const uint32_t r0 = hdr->phase_rank[phase], r1 = hdr->phase_rank[phase + 1];
+    // outside the phase's ranks nothing is written: the scans and the emission read counts only
+    // inside them
+    if ((uint64_t)r < r0 || (uint64_t)r >= r1) return;
     uint32_t c = 0;
-    if ((uint64_t)r >= r0 && (uint64_t)r < r1 && !hdr->stop) {
+    if (!hdr->stop) {
         const uint32_t e = order[r];
         if (phase == 0) {
             c = counts[e];
@@ -166,15 +169,16 @@ __global__ __launch_bounds__(kBlock) void k_count_reduce(const uint32_t* __restr
                                                         const SavedHeader* __restrict__ hdr, int phase,
                                                         uint64_t* __restrict__ blocksums) {
     __shared__ uint64_t red[kBlock];
-    if (phase_empty(hdr, phase)) {
+    const int64_t b0 = (int64_t)blockIdx.x * kScanChunk;
+    const int64_t r0 = hdr->phase_rank[phase], r1 = hdr->phase_rank[phase + 1];
+    if (phase_empty(hdr, phase) || b0 + kScanChunk <= r0 || b0 >= r1) {   // no count of the phase here
         if (threadIdx.x == 0) blocksums[blockIdx.x] = 0;
         return;
     }
-    const int64_t b0 = (int64_t)blockIdx.x * kScanChunk;
     uint64_t s = 0;
     for (int k = 0; k < 16; ++k) {
         const int64_t r = b0 + k * kBlock + threadIdx.x;
-        if (r < nv) s += pcounts[r];
+        if (r < nv && r >= r0 && r < r1) s += pcounts[r];
     }
     red[threadIdx.x] = s;
     __syncthreads();
@@ -232,14 +236,18 @@ __global__ __launch_bounds__(kBlock) void k_count_down(const uint32_t* __restric
                                                       int64_t n_spans) {
     __shared__ uint64_t part[kBlock];
     if (phase_empty(hdr, phase)) return;   // every count is 0: no entry reads its offset
+    // offsets are read inside the phase's ranks, and by the phase-0 emission up to one span past them
+    const int64_t r0 = hdr->phase_rank[phase], r1 = hdr->phase_rank[phase + 1];
+    const int64_t cb = (int64_t)blockIdx.x * kScanChunk;
+    if (cb + kScanChunk <= r0 || cb >= r1 + kEmitSpan + 1) return;
     const int tid = threadIdx.x;
-    const int64_t b0 = (int64_t)blockIdx.x * kScanChunk + (int64_t)tid * 16;   // 16 consecutive per thread
+    const int64_t b0 = cb + (int64_t)tid * 16;   // 16 consecutive per thread
     uint32_t c[16];
     uint64_t s = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int64_t r = b0 + k;
-        c[k] = r < nv ? pcounts[r] : 0u;
+        c[k] = r < nv && r >= r0 && r < r1 ? pcounts[r] : 0u;
         s += c[k];
     }
     part[tid] = s;
@@ -364,6 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_alive(const uint32_t* __restric
     if (r >= nv) return;
     const uint64_t K = hdr->phase_count[phase];
     if (K == 0) return;   // also every phase after which no tile was alive: its counts are not written
+    if ((uint64_t)r < hdr->phase_rank[phase] || (uint64_t)r >= hdr->phase_rank[phase + 1]) return;
     const uint32_t c = pcounts[r];
     if (c == 0) return;
     uint64_t off = offsets[r];

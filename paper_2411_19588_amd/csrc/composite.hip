@@ -832,28 +832,32 @@ struct MediumAdam {
     int32_t enabled;
 };
 
-__global__ __launch_bounds__(kBlock) void k_medium_reduce(const ViewInfo* __restrict__ vt,
-                                                         const float* __restrict__ medpart,
-                                                         float* __restrict__ grad_medium, MediumAdam ad) {
+constexpr int kMedThreads = 9 * 64;   // thread t always reads component t % 9 of the [tiles][9] partials
+
+__global__ __launch_bounds__(kMedThreads) void k_medium_reduce(const ViewInfo* __restrict__ vt,
+                                                              const float* __restrict__ medpart,
+                                                              float* __restrict__ grad_medium, MediumAdam ad) {
     // one workgroup per view; deterministic: fixed per-thread strides and a fixed tree
-    __shared__ float red[9][kBlock];
+    __shared__ float red[kMedThreads];
     const int v = blockIdx.x, tid = threadIdx.x;
     const ViewInfo vi = vt[v];
-    float acc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (uint32_t t = tid; t < vi.n_tiles; t += kBlock)
+    const float* p = medpart + (int64_t)vi.tile_base * 9;
+    const int64_t total = (int64_t)vi.n_tiles * 9;
+    float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int64_t i = tid;
+    for (; i + 7 * kMedThreads < total; i += 8 * kMedThreads)   // eight coalesced loads in flight
 #pragma unroll
-        for (int k = 0; k < 9; ++k) acc[k] += medpart[(int64_t)(vi.tile_base + t) * 9 + k];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) red[k][tid] = acc[k];
+        for (int u = 0; u < 8; ++u) a[u] += p[i + u * kMedThreads];
+    for (; i < total; i += kMedThreads) a[0] += p[i];
+    red[tid] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {
-        if (tid < off)
-#pragma unroll
-            for (int k = 0; k < 9; ++k) red[k][tid] += red[k][tid + off];
+    // component c sits at c + 9 j, j < 64: a tree over j
+    for (int off = 32; off > 0; off >>= 1) {
+        if (tid < 9 * off) red[tid] += red[tid + 9 * off];
         __syncthreads();
     }
     if (tid < 9) {
-        const float gm = red[tid][0];
+        const float gm = red[tid];
         grad_medium[v * 9 + tid] = gm;
         if (ad.enabled) {
             const int j = v * 9 + tid;
@@ -979,7 +983,7 @@ hipError_t launch_medium_reduce(const ViewInfo* vt, int32_t views, const float* 
         ad.bc = bc;
         ad.enabled = 1;
     }
-    hipLaunchKernelGGL(k_medium_reduce, dim3(views), dim3(kBlock), 0, s, vt, medpart, grad_medium, ad);
+    hipLaunchKernelGGL(k_medium_reduce, dim3(views), dim3(kMedThreads), 0, s, vt, medpart, grad_medium, ad);
     return hipGetLastError();
 }
 
