@@ -122,7 +122,6 @@ __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restri
                                                        const uint32_t* __restrict__ counts,
                                                        const uint2* __restrict__ rects, int64_t nv, int64_t n,
                                                        const ViewInfo* __restrict__ vt,
-                                                       const uint32_t* __restrict__ alive,
                                                        const uint2* __restrict__ rowspan,
                                                        const uint64_t* __restrict__ rowbits, uint32_t row_words,
                                                        const SavedHeader* __restrict__ hdr, int phase,
@@ -362,7 +361,6 @@ __global__ __launch_bounds__(kBlock) void k_emit_alive(const uint32_t* __restric
                                                       const uint32_t* __restrict__ pcounts,
                                                       const uint2* __restrict__ rects, int64_t nv, int64_t n,
                                                       const ViewInfo* __restrict__ vt,
-                                                      const uint32_t* __restrict__ alive,
                                                       const uint2* __restrict__ rowspan,
                                                       const uint64_t* __restrict__ rowbits, uint32_t row_words,
                                                       const SavedHeader* __restrict__ hdr, int phase,
@@ -482,13 +480,12 @@ hipError_t launch_visible(int phases, int phase0_shift, SavedHeader* hdr, hipStr
 }
 
 hipError_t launch_phase_count(const uint32_t* order, const uint32_t* counts, const uint2* rects, int64_t nv,
-                              int64_t n, const ViewInfo* vt, const uint32_t* alive, const AliveRows& ar,
+                              int64_t n, const ViewInfo* vt, const AliveRows& ar,
                               const SavedHeader* hdr, int phase, const CullArgs& cull, uint32_t* pcounts,
                               hipStream_t s) {
     if (nv == 0) return hipSuccess;
     const unsigned grid = (unsigned)((nv + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_phase_count, dim3(grid), dim3(kBlock), 0, s, order, counts, rects, nv, n, vt, alive,
-                       ar.span, ar.bits, ar.words, hdr, phase, cull, pcounts);
+    hipLaunchKernelGGL(k_phase_count, dim3(grid), dim3(kBlock), 0, s, order, counts, rects, nv, n, vt, ar.span, ar.bits, ar.words, hdr, phase, cull, pcounts);
     return hipGetLastError();
 }
 
@@ -514,7 +511,7 @@ hipError_t launch_count_scan(const uint32_t* pcounts, int64_t nv, uint64_t* offs
 
 hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uint32_t* emit_start,
                        const uint32_t* pcounts, const uint2* rects, int64_t nv, int64_t n, const ViewInfo* vt,
-                       const uint32_t* alive, const AliveRows& ar, const SavedHeader* hdr, int phase,
+                       const AliveRows& ar, const SavedHeader* hdr, int phase,
                        int64_t max_pairs, const CullArgs& cull, uint32_t n_tiles, uint32_t* tiles_out,
                        uint32_t* vals_out, hipStream_t s) {
     if (nv == 0 || max_pairs == 0) return hipSuccess;
@@ -525,7 +522,7 @@ hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uin
     } else {
         const unsigned grid = (unsigned)((nv + kBlock - 1) / kBlock);
         hipLaunchKernelGGL(k_emit_alive, dim3(grid), dim3(kBlock), 0, s, order, offsets, pcounts, rects, nv, n, vt,
-                           alive, ar.span, ar.bits, ar.words, hdr, phase, cull, tiles_out, vals_out);
+                           ar.span, ar.bits, ar.words, hdr, phase, cull, tiles_out, vals_out);
     }
     return hipGetLastError();
 }

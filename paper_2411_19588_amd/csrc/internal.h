@@ -151,7 +151,7 @@ struct AliveRows {
     uint32_t words;
 };
 hipError_t launch_phase_count(const uint32_t* order, const uint32_t* counts, const uint2* rects, int64_t nv,
-                              int64_t n, const ViewInfo* vt, const uint32_t* alive, const AliveRows& ar,
+                              int64_t n, const ViewInfo* vt, const AliveRows& ar,
                               const SavedHeader* hdr, int phase, const CullArgs& cull, uint32_t* pcounts,
                               hipStream_t s);
 hipError_t launch_alive_rows(const ViewInfo* vt, int32_t views, int64_t rows, const uint32_t* alive,
@@ -165,7 +165,7 @@ hipError_t launch_count_scan(const uint32_t* pcounts, int64_t nv, uint64_t* offs
 // unculled tiles.
 hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uint32_t* emit_start,
                        const uint32_t* pcounts, const uint2* rects, int64_t nv, int64_t n, const ViewInfo* vt,
-                       const uint32_t* alive, const AliveRows& ar, const SavedHeader* hdr, int phase,
+                       const AliveRows& ar, const SavedHeader* hdr, int phase,
                        int64_t max_pairs, const CullArgs& cull, uint32_t n_tiles, uint32_t* tiles_out,
                        uint32_t* vals_out, hipStream_t s);
 // Copy the phase's tile-sorted values behind the earlier phases' and record its tile ranges.
