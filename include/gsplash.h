@@ -49,7 +49,7 @@ extern "C" {
 
 #define GS_MAX_VIEWS                64
 #define GS_MAX_PAIRS         2147483647LL /* pair indices are 31-bit */
-#define GS_MAX_PHASES                4
+#define GS_MAX_PHASES                8
 
 typedef void* gs_stream_t;               /* hipStream_t; NULL = the default stream */
 
@@ -129,7 +129,7 @@ typedef struct gs_options {
                                             with a rounding margin; images are identical); 0: every tile of
                                             the rectangle, as in the method's binning */
     int32_t phases;                      /* depth-progressive binning: 1 = bin every (Gaussian, tile) pair at
-                                            once; 2..4 = bin the depth-sorted Gaussians in that many rank
+                                            once; 2..8 = bin the depth-sorted Gaussians in that many rank
                                             ranges (by default nearest 1/128 | rest for 2, nearest 1/128 |
                                             1/32 | rest for 3) and, after each range, only for tiles that
                                             still have a pixel above t_min, walking only the alive columns

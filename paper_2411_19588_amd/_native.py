@@ -20,7 +20,7 @@ GS_STATUS_PAIR_OVERFLOW = 1
 GS_STATUS_NONFINITE_INPUT = 2
 GS_MAX_VIEWS = 64
 GS_MAX_PAIRS = 2_147_483_647
-GS_MAX_PHASES = 4
+GS_MAX_PHASES = 8
 GS_FETCH_DEFAULT = 0
 GS_FETCH_LDS = 1
 GS_FETCH_SCALAR = 2

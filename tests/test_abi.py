@@ -83,7 +83,8 @@ def test_workspace_query_and_tile_count():
     ("max_pairs", 5_000_000_000, N.GS_ERR_INVALID_ARGUMENT), ("pixels_per_lane", 3, N.GS_ERR_INVALID_ARGUMENT),
     ("pixels_per_lane", 8, N.GS_ERR_INVALID_ARGUMENT), ("record_fetch", 3, N.GS_ERR_INVALID_ARGUMENT),
     ("record_fetch", -1, N.GS_ERR_INVALID_ARGUMENT), ("phase0_shift", 21, N.GS_ERR_INVALID_ARGUMENT),
-    ("phase0_shift", -1, N.GS_ERR_INVALID_ARGUMENT), ("tile_cull", 2, N.GS_ERR_INVALID_ARGUMENT)])
+    ("phase0_shift", -1, N.GS_ERR_INVALID_ARGUMENT), ("tile_cull", 2, N.GS_ERR_INVALID_ARGUMENT),
+    ("phases", 9, N.GS_ERR_INVALID_ARGUMENT), ("phases", -1, N.GS_ERR_INVALID_ARGUMENT)])
 def test_bad_options_rejected(field, value, code):
     sc = synth.make_scene(0, n=10)
     cams = N.camera_array(sc.cameras)

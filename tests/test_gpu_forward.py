@@ -90,7 +90,8 @@ def _large_splat_scene():
 
 
 @pytest.mark.parametrize("phases,shift,views", [(2, 0, 1), (3, 0, 1), (4, 0, 1), (2, 8, 1), (3, 2, 1),
-                                                (2, 6, 3), (3, 3, 3), (2, 6, "large"), (3, 4, "large")])
+                                                (2, 6, 3), (3, 3, 3), (2, 6, "large"), (3, 4, "large"),
+                                                (8, 14, 1), (6, 10, 3)])
 def test_phased_lists_are_exact_prefixes(oracle_mod, phases, shift, views):
     """Depth-progressive binning stores, per tile, a prefix of the oracle's sorted list (bit-exact keys,
     cut at a phase boundary), and the images equal those of full binning bit for bit.  Later phases
