@@ -285,7 +285,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+              "(the path runs on one GPU; sharding over views is not implemented)", file=sys.stderr)
         print(json.dumps({"error": "only --gpus 1 is supported", "n_gpus": args.gpus}))
         sys.exit(2)
 

@@ -1,5 +1,5 @@
-"""Resource use of the built kernels (no GPU): read the gfx950 code objects of this build's
-objects and check that no kernel uses private (scratch) memory or spills registers.  A by-value
+"""Resource use of the built kernels (no GPU): read the gfx950 code objects of the compiled
+sources and check that no kernel uses private (scratch) memory or spills registers.  A by-value
 kernel argument indexed with a run-time value, for instance, makes every thread copy it to
 scratch, which costs more than the kernel's own traffic."""
 import os
