@@ -45,6 +45,27 @@ def test_image_full_size_sampled(oracle_mod, scene):
     U.say(f"  main {n_main} variant {n_var} worst {worst:.2e}")
 
 
+def test_image_full_size_24_views_sampled(oracle_mod):
+    """The batched workload at full size (1M Gaussians, 24 views of uneven resolution, 29.5 Mpixel)
+    in the launch configuration the autotuner picks for it: 250 random pixels and the four corners
+    of every view against the FP64 oracle."""
+    O = oracle_mod
+    sc = synth.make_scene(3)
+    rast = R.Rasterizer(sc.cameras, R.RasterConfig(tile=16, pixels_per_lane=4, record_fetch="scalar",
+                                                   lds_batch=256, persistent=False, phases=4, phase0_shift=6))
+    rgb, depth, alpha, ctx, _ = U.forward(sc, rast)
+    st, _ = rast.read_status(ctx.saved)
+    assert st == 0
+    rng = np.random.default_rng(12)
+    U.say(f"full-size 24 views, {len(sc.cameras)} x 254 sampled pixels")
+    for v, cam in enumerate(sc.cameras):
+        pix = np.stack([rng.integers(0, cam.width, 250), rng.integers(0, cam.height, 250)], 1)
+        corners = np.array([[0, 0], [cam.width - 1, 0], [0, cam.height - 1], [cam.width - 1, cam.height - 1]])
+        pix = np.ascontiguousarray(np.concatenate([pix, corners]).astype(np.int32))
+        orc = O.render(sc, cam, sc.medium[v], pixels=pix, variants=4)
+        U.compare_pixels(*U.gather_view(rgb, depth, alpha, rast, v, pix), orc)
+
+
 def _crop_pixels():
     x0, y0, w, h = CROP
     ys, xs = np.meshgrid(np.arange(y0, y0 + h), np.arange(x0, x0 + w), indexing="ij")
