@@ -74,7 +74,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=2, help="oracle sample: every k-th pixel in x and y")
     ap.add_argument("--no-timer", action="store_true", help="skip the per-kernel HIP event timer")
-    ap.add_argument("--phases", type=int, default=2, help="depth-progressive binning phases (1 = full binning)")
+    ap.add_argument("--phases", type=int, default=0,
+                    help="depth-progressive binning phases (1 = full binning; 0 = automatic by view count)")
     ap.add_argument("--phase0-shift", type=int, default=0,
                     help="first depth phase = nearest 1/2^shift of the visible Gaussians (0 = library default)")
     ap.add_argument("--eager", action="store_true", help="time eager launches only (no HIP graph replay)")
@@ -378,7 +379,8 @@ def main():
     # pairs per depth phase (from the stored per-phase tile ranges)
     _, _, rng = ts.rast.export_keys(R.ForwardContext(ts.saved, ts.max_pairs, ts.n, sc.sh_degree), stream)
     rng = rng.to(torch.int64)
-    phase_pairs = [int((rng[p, :, 1] - rng[p, :, 0]).sum().item()) for p in range(cfg.phases)]
+    phases, shift = ts.rast.schedule()
+    phase_pairs = [int((rng[p, :, 1] - rng[p, :, 0]).sum().item()) for p in range(phases)]
     log(f"live pairs per phase: {phase_pairs}")
     # full (single-phase) binning pair count of the same scene, for K/N
     # (the method's rectangle binning, no culling)
@@ -454,7 +456,7 @@ def main():
                    "n_gaussians": sc.n, "sh_degree": sc.sh_degree, "width": cam.width, "height": cam.height,
                    "views": sc.n_views, "tile": args.tile, "lds_batch": args.lds_batch, "persistent": bool(args.persistent),
                    "pixels_per_lane": args.ppl, "record_fetch": args.fetch,
-                   "phases": cfg.phases, "phase0_shift": args.phase0_shift, "mode": "eager" if args.eager else "hip_graph",
+                   "phases": phases, "phase0_shift": shift, "mode": "eager" if args.eager else "hip_graph",
                    "pairs_stored": int(K), "pairs_full_binning": int(K_full),
                    "pairs_per_gaussian": round(K_full / sc.n, 2), "pairs_live": int(stats[0]),
                    "pairs_live_per_phase": phase_pairs,

@@ -130,19 +130,20 @@ typedef struct gs_options {
                                             the rectangle, as in the method's binning */
     int32_t phases;                      /* depth-progressive binning: 1 = bin every (Gaussian, tile) pair at
                                             once; 2..8 = bin the depth-sorted Gaussians in that many rank
-                                            ranges (by default nearest 1/128 | rest for 2, nearest 1/128 |
-                                            1/32 | rest for 3) and, after each range, only for tiles that
-                                            still have a pixel above t_min, walking only the alive columns
-                                            of each tile row (default 2).  Images are identical for every
-                                            value. */
+                                            ranges (e.g. nearest 1/128 | rest for 2 and shift 7) and, after
+                                            each range, only for tiles that still have a pixel above t_min,
+                                            walking only the alive columns of each tile row; 0 (default) =
+                                            automatic: 2 for one view, 4 for several (gs_schedule).  Images
+                                            are identical for every value. */
     int32_t phase0_shift;                /* the first range is the nearest 1/2^shift of the visible
                                             Gaussians, each later one (but the last) 4x wider: 1..20;
-                                            0 = default (7).  Images are identical for every value. */
+                                            0 (default) = automatic: 7 for one view, 6 for several.
+                                            Images are identical for every value. */
     int64_t max_pairs;                   /* capacity of the stored (Gaussian, tile) pair list, <= GS_MAX_PAIRS */
     void* timer;                         /* optional gs_timer* receiving per-kernel HIP events; NULL = none */
 } gs_options;
 
-/* Fill `opts` with the defaults above (phases = 2, max_pairs = 1 << 24). */
+/* Fill `opts` with the defaults above (phases and phase0_shift automatic, max_pairs = 1 << 24). */
 void gs_default_options(gs_options* opts);
 
 /* Library version string (static storage). */
@@ -224,6 +225,12 @@ int gs_export_keys(const gs_options* opts, int64_t n, int32_t n_views, const gs_
  * diagnostic, slower than the forward itself. */
 int gs_forward_stats(const gs_options* opts, int64_t n, int32_t n_views, const gs_camera* host_cams,
                      const void* saved, size_t saved_bytes, int64_t* stats, gs_stream_t stream);
+
+/* The depth-phase schedule these options give for n_views views (host only): the number of
+ * phases and the first phase's shift, with the automatic values (0) resolved.  Returns GS_OK
+ * or GS_ERR_INVALID_ARGUMENT as gs_workspace_query would. */
+int gs_schedule(const gs_options* opts, int32_t n_views, const gs_camera* host_cams, int32_t* phases,
+                int32_t* phase0_shift);
 
 /* Total number of tiles over the views for these options (host only). */
 int64_t gs_tile_count(const gs_options* opts, int32_t n_views, const gs_camera* host_cams);

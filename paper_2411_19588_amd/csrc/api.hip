@@ -55,8 +55,8 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     memset(L, 0, sizeof(*L));
     L->n = n;
     L->views = n_views;
-    L->phases = o->phases == 0 ? kDefaultPhases : o->phases;
-    L->phase0_shift = o->phase0_shift != 0 ? o->phase0_shift : kDefaultPhase0Shift;
+    L->phases = o->phases != 0 ? o->phases : (n_views == 1 ? kAutoPhasesOneView : kAutoPhasesViews);
+    L->phase0_shift = o->phase0_shift != 0 ? o->phase0_shift : (n_views == 1 ? kAutoShiftOneView : kAutoShiftViews);
     L->nv = n * n_views;
     L->max_pairs = o->max_pairs;
     L->tile_w = o->tile_w;
@@ -140,6 +140,7 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     L->w_adam = w.take(16);                    // bias corrections of a fused Adam step
     L->w_rowspan = w.take(rows * 8);           // alive columns per tile row (later depth phases)
     L->w_rowbits = w.take((size_t)rows * L->row_words * 8);   // and their bit masks
+    L->w_large = w.take(256 + nv * 4);         // later phases: count and ranks of the large rectangles
     L->w_shf = w.take(n_views == 1 ? (size_t)n * kShf * 4 : 0);   // SH-gradient factors etc. (fused Adam)
     L->workspace_bytes = w.at;
     return GS_OK;
@@ -221,7 +222,8 @@ void gs_default_options(gs_options* o) {
     o->dilation = 0.3f;
     o->kappa = 11.1f;
     o->depth_mode = 0;
-    o->phases = kDefaultPhases;
+    o->phases = 0;         // automatic, by view count
+    o->phase0_shift = 0;
     o->max_pairs = 1LL << 24;
     o->timer = nullptr;
 }
@@ -235,6 +237,16 @@ int gs_workspace_query(const gs_options* opts, int64_t n, int32_t n_views, const
     if (rc != GS_OK) return rc;
     if (workspace_bytes) *workspace_bytes = L.workspace_bytes;
     if (saved_bytes) *saved_bytes = L.saved_bytes;
+    return GS_OK;
+}
+
+int gs_schedule(const gs_options* opts, int32_t n_views, const gs_camera* host_cams, int32_t* phases,
+                int32_t* phase0_shift) {
+    Layout L;
+    const int rc = compute_layout(opts, 0, n_views, host_cams, &L);
+    if (rc != GS_OK) return rc;
+    if (phases) *phases = L.phases;
+    if (phase0_shift) *phase0_shift = L.phase0_shift;
     return GS_OK;
 }
 
@@ -303,7 +315,8 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
     float* wsum = at<float>(saved, L.s_wsum);
     const CullArgs cull{rec, log2f(o.alpha_min), o.tile_w, o.tile_h, o.tile_cull};
     const AliveRows ar{at<uint2>(workspace, L.w_rowspan), at<uint64_t>(workspace, L.w_rowbits),
-                       (uint32_t)L.row_words};
+                       (uint32_t)L.row_words, at<uint32_t>(workspace, L.w_large),
+                       at<uint32_t>(workspace, L.w_large + 256)};
     for (int ph = 0; ph < L.phases; ++ph) {
         if (ph > 0) {
             timer_begin(T, "alive_rows", s);
@@ -317,7 +330,7 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
         GS_TRY(launch_count_scan(pcounts, L.nv, offsets, blocksums, hdr, ph, L.max_pairs, emit_start, s));
         timer_end(T, s);
         timer_begin(T, "emit", s);
-        GS_TRY(launch_emit(order, offsets, emit_start, pcounts, rects, L.nv, L.n, vt, ar, hdr, ph,
+        GS_TRY(launch_emit(order, offsets, emit_start, pcounts, counts, rects, L.nv, L.n, vt, ar, hdr, ph,
                            L.max_pairs, cull, (uint32_t)L.tiles, tiles_a, vals_a, s));
         timer_end(T, s);
         // stable sort of the phase's pairs by tile id

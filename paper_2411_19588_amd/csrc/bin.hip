@@ -125,7 +125,9 @@ __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restri
                                                        const uint2* __restrict__ rowspan,
                                                        const uint64_t* __restrict__ rowbits, uint32_t row_words,
                                                        const SavedHeader* __restrict__ hdr, int phase,
-                                                       CullArgs cull, uint32_t* __restrict__ pcounts) {
+                                                       CullArgs cull, uint32_t* __restrict__ pcounts,
+                                                       uint32_t* __restrict__ large_count,
+                                                       uint32_t* __restrict__ large_rank) {
     if (phase_empty(hdr, phase)) return;   // no tile left: nothing reads this phase's counts
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (r >= nv) return;
@@ -134,11 +136,14 @@ __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restri
     // inside them
     if ((uint64_t)r < r0 || (uint64_t)r >= r1) return;
     uint32_t c = 0;
+    bool big = false;
     if (!hdr->stop) {
         const uint32_t e = order[r];
         if (phase == 0) {
             c = counts[e];
-        } else if (hdr->phase_alive[phase - 1] != 0) {
+        } else if (counts[e] > kLargeRect) {
+            big = true;   // counted by a whole wave in k_large_count
+        } else {
             const uint2 rc = rects[e];
             const ViewInfo vi = vt[e / (uint64_t)n];
             const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
@@ -160,7 +165,63 @@ __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restri
             }
         }
     }
-    pcounts[r] = c;
+    // wave-aggregated append of the large rectangles' ranks (the list's order is free: each entry
+    // writes at its own scanned offset)
+    const uint64_t bm = __ballot(big);
+    if (bm) {
+        const int lane = threadIdx.x & 63, leader = __ffsll((unsigned long long)bm) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(large_count, (uint32_t)__popcll(bm));
+        base = (uint32_t)__shfl((int)base, leader);
+        if (big) large_rank[base + (uint32_t)__popcll(bm & ((1ull << lane) - 1ull))] = (uint32_t)r;
+    }
+    if (!big) pcounts[r] = c;
+}
+
+// One lane's candidate of a large rectangle's row: column tx (<= hi) of row ty is alive (from the
+// row's bit masks) and the pair may contribute.
+__device__ __forceinline__ bool large_keep(uint32_t tx, uint32_t hi, uint32_t ty, const ViewInfo& vi,
+                                           const uint64_t* __restrict__ bits, const float4& ra, const float2& rb,
+                                           const CullArgs& cull) {
+    if (tx > hi || ((bits[tx >> 6] >> (tx & 63)) & 1ull) == 0ull) return false;
+    return !cull.enabled || tile_may_contribute(ra, rb, vi, tx, ty, cull);
+}
+
+// Later phases, rectangles of more than kLargeRect tiles: one wave per listed entry walks each
+// row's alive span 64 columns at a time and counts the pairs k_phase_count's loop would count.
+__global__ __launch_bounds__(kBlock) void k_large_count(const uint32_t* __restrict__ order,
+                                                       const uint2* __restrict__ rects, int64_t n,
+                                                       const ViewInfo* __restrict__ vt,
+                                                       const uint2* __restrict__ rowspan,
+                                                       const uint64_t* __restrict__ rowbits, uint32_t row_words,
+                                                       CullArgs cull, const uint32_t* __restrict__ large_count,
+                                                       const uint32_t* __restrict__ large_rank,
+                                                       uint32_t* __restrict__ pcounts) {
+    const uint32_t total = *large_count;
+    const int lane = threadIdx.x & 63;
+    const uint32_t nwaves = gridDim.x * (kBlock / 64);
+    for (uint32_t i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); i < total; i += nwaves) {
+        const uint32_t r = large_rank[i];
+        const uint32_t e = order[r];
+        const uint2 rc = rects[e];
+        const ViewInfo vi = vt[e / (uint64_t)n];
+        const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
+        float4 ra = make_float4(0.f, 0.f, 0.f, 0.f);
+        float2 rb = make_float2(0.f, 0.f);
+        if (cull.enabled) {
+            ra = cull.rec[e].a;
+            rb = make_float2(cull.rec[e].b.x, cull.rec[e].b.y);
+        }
+        uint32_t c = 0;
+        for (uint32_t ty = y0; ty <= y1; ++ty) {
+            const uint2 sp = rowspan[vi.row_base + ty];
+            const uint32_t lo = max(x0, sp.x), hi = min(x1, sp.y);
+            const uint64_t* bits = rowbits + (size_t)(vi.row_base + ty) * row_words;
+            for (uint32_t tx = lo; tx <= hi; tx += 64)
+                c += (uint32_t)__popcll(__ballot(large_keep(tx + lane, hi, ty, vi, bits, ra, rb, cull)));
+        }
+        if (lane == 0) pcounts[r] = c;
+    }
 }
 
 
@@ -363,6 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_alive(const uint32_t* __restric
                                                       const ViewInfo* __restrict__ vt,
                                                       const uint2* __restrict__ rowspan,
                                                       const uint64_t* __restrict__ rowbits, uint32_t row_words,
+                                                      const uint32_t* __restrict__ counts,
                                                       const SavedHeader* __restrict__ hdr, int phase,
                                                       CullArgs cull, uint32_t* __restrict__ tiles_out,
                                                       uint32_t* __restrict__ vals_out) {
@@ -376,6 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_alive(const uint32_t* __restric
     uint64_t off = offsets[r];
     if (off + c > K) return;   // cannot happen for a consistent scan
     const uint32_t e = order[r];
+    if (counts[e] > kLargeRect) return;   // emitted by k_large_emit
     const uint2 rc = rects[e];
     const ViewInfo vi = vt[e / (uint64_t)n];
     const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
@@ -400,11 +463,69 @@ __global__ __launch_bounds__(kBlock) void k_emit_alive(const uint32_t* __restric
     }
 }
 
+// Later phases, rectangles of more than kLargeRect tiles: one wave per listed entry writes its
+// pairs at its scanned offset in k_emit_alive's order (rows, then columns), the kept lanes of each
+// 64-column step placed by a ballot prefix.
+__global__ __launch_bounds__(kBlock) void k_large_emit(const uint32_t* __restrict__ order,
+                                                      const uint64_t* __restrict__ offsets,
+                                                      const uint32_t* __restrict__ pcounts,
+                                                      const uint2* __restrict__ rects, int64_t n,
+                                                      const ViewInfo* __restrict__ vt,
+                                                      const uint2* __restrict__ rowspan,
+                                                      const uint64_t* __restrict__ rowbits, uint32_t row_words,
+                                                      const SavedHeader* __restrict__ hdr, int phase, CullArgs cull,
+                                                      const uint32_t* __restrict__ large_count,
+                                                      const uint32_t* __restrict__ large_rank,
+                                                      uint32_t* __restrict__ tiles_out,
+                                                      uint32_t* __restrict__ vals_out) {
+    const uint64_t K = hdr->phase_count[phase];
+    if (K == 0) return;
+    const uint32_t total = *large_count;
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const uint32_t nwaves = gridDim.x * (kBlock / 64);
+    for (uint32_t i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); i < total; i += nwaves) {
+        const uint32_t r = large_rank[i];
+        const uint32_t c = pcounts[r];
+        uint64_t off = offsets[r];
+        if (c == 0 || off + c > K) continue;   // the second cannot happen for a consistent scan
+        const uint64_t end = off + c;
+        const uint32_t e = order[r];
+        const uint2 rc = rects[e];
+        const ViewInfo vi = vt[e / (uint64_t)n];
+        const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
+        float4 ra = make_float4(0.f, 0.f, 0.f, 0.f);
+        float2 rb = make_float2(0.f, 0.f);
+        if (cull.enabled) {
+            ra = cull.rec[e].a;
+            rb = make_float2(cull.rec[e].b.x, cull.rec[e].b.y);
+        }
+        for (uint32_t ty = y0; ty <= y1 && off < end; ++ty) {
+            const uint2 sp = rowspan[vi.row_base + ty];
+            const uint32_t lo = max(x0, sp.x), hi = min(x1, sp.y);
+            const uint64_t* bits = rowbits + (size_t)(vi.row_base + ty) * row_words;
+            const uint32_t row = vi.tile_base + ty * (uint32_t)vi.tiles_x;
+            for (uint32_t tx = lo; tx <= hi && off < end; tx += 64) {
+                const bool keep = large_keep(tx + lane, hi, ty, vi, bits, ra, rb, cull);
+                const uint64_t bm = __ballot(keep);
+                const uint64_t pos = off + (uint64_t)__popcll(bm & below);
+                if (keep && pos < end) {
+                    tiles_out[pos] = row + tx + lane;
+                    vals_out[pos] = e;
+                }
+                off += (uint64_t)__popcll(bm);
+            }
+        }
+    }
+}
+
 // One wave per global tile row: the first and last column whose tile is still alive.
 __global__ __launch_bounds__(64) void k_alive_rows(const ViewInfo* __restrict__ vt, int32_t views,
                                                   const uint32_t* __restrict__ alive, uint2* __restrict__ rowspan,
-                                                  uint64_t* __restrict__ rowbits, uint32_t row_words) {
+                                                  uint64_t* __restrict__ rowbits, uint32_t row_words,
+                                                  uint32_t* __restrict__ large_count) {
     const uint32_t r = blockIdx.x;
+    if (r == 0 && threadIdx.x == 0) *large_count = 0;   // the coming phase's list of large rectangles
     int v = 0;
     while (v + 1 < views && r >= vt[v + 1].row_base) ++v;
     const ViewInfo vi = vt[v];
@@ -466,6 +587,12 @@ __global__ __launch_bounds__(kBlock) void k_export(const uint2* __restrict__ ran
     }
 }
 
+// Workgroups of the one-wave-per-entry kernels: they loop over the list.
+unsigned large_grid(int64_t nv) {
+    const int64_t waves = nv < 4096 ? (nv > 0 ? nv : 1) : 4096;
+    return (unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64));
+}
+
 }  // namespace
 
 hipError_t launch_view_table(const ViewTable& t, int phases, ViewInfo* dst, SavedHeader* hdr, hipStream_t s) {
@@ -485,7 +612,10 @@ hipError_t launch_phase_count(const uint32_t* order, const uint32_t* counts, con
                               hipStream_t s) {
     if (nv == 0) return hipSuccess;
     const unsigned grid = (unsigned)((nv + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_phase_count, dim3(grid), dim3(kBlock), 0, s, order, counts, rects, nv, n, vt, ar.span, ar.bits, ar.words, hdr, phase, cull, pcounts);
+    hipLaunchKernelGGL(k_phase_count, dim3(grid), dim3(kBlock), 0, s, order, counts, rects, nv, n, vt, ar.span, ar.bits, ar.words, hdr, phase, cull, pcounts, ar.large_count, ar.large_rank);
+    if (phase > 0)
+        hipLaunchKernelGGL(k_large_count, dim3(large_grid(nv)), dim3(kBlock), 0, s, order, rects, n, vt, ar.span,
+                           ar.bits, ar.words, cull, ar.large_count, ar.large_rank, pcounts);
     return hipGetLastError();
 }
 
@@ -493,7 +623,7 @@ hipError_t launch_alive_rows(const ViewInfo* vt, int32_t views, int64_t rows, co
                              const AliveRows& ar, hipStream_t s) {
     if (rows == 0) return hipSuccess;
     hipLaunchKernelGGL(k_alive_rows, dim3((unsigned)rows), dim3(64), 0, s, vt, views, alive, ar.span, ar.bits,
-                       ar.words);
+                       ar.words, ar.large_count);
     return hipGetLastError();
 }
 
@@ -510,8 +640,8 @@ hipError_t launch_count_scan(const uint32_t* pcounts, int64_t nv, uint64_t* offs
 }
 
 hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uint32_t* emit_start,
-                       const uint32_t* pcounts, const uint2* rects, int64_t nv, int64_t n, const ViewInfo* vt,
-                       const AliveRows& ar, const SavedHeader* hdr, int phase,
+                       const uint32_t* pcounts, const uint32_t* counts, const uint2* rects, int64_t nv, int64_t n,
+                       const ViewInfo* vt, const AliveRows& ar, const SavedHeader* hdr, int phase,
                        int64_t max_pairs, const CullArgs& cull, uint32_t n_tiles, uint32_t* tiles_out,
                        uint32_t* vals_out, hipStream_t s) {
     if (nv == 0 || max_pairs == 0) return hipSuccess;
@@ -522,7 +652,10 @@ hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uin
     } else {
         const unsigned grid = (unsigned)((nv + kBlock - 1) / kBlock);
         hipLaunchKernelGGL(k_emit_alive, dim3(grid), dim3(kBlock), 0, s, order, offsets, pcounts, rects, nv, n, vt,
-                           ar.span, ar.bits, ar.words, hdr, phase, cull, tiles_out, vals_out);
+                           ar.span, ar.bits, ar.words, counts, hdr, phase, cull, tiles_out, vals_out);
+        hipLaunchKernelGGL(k_large_emit, dim3(large_grid(nv)), dim3(kBlock), 0, s, order, offsets, pcounts, rects, n,
+                           vt, ar.span, ar.bits, ar.words, hdr, phase, cull, ar.large_count, ar.large_rank,
+                           tiles_out, vals_out);
     }
     return hipGetLastError();
 }

@@ -32,8 +32,8 @@ class RasterConfig:
     kappa: float = 11.1
     depth_mode: int = 0
     tile_cull: bool = True            # drop (Gaussian, tile) pairs that cannot reach alpha_min
-    phases: int = 2
-    phase0_shift: int = 0             # 0 = library default
+    phases: int = 0                   # 0 = automatic by view count (the library's gs_schedule)
+    phase0_shift: int = 0             # 0 = automatic
     max_pairs: int = 1 << 22
 
     def to_c(self, max_pairs: Optional[int] = None, timer=None) -> N.GsOptions:
@@ -120,6 +120,13 @@ class Rasterizer:
 
     def tile_count(self) -> int:
         return int(N.lib().gs_tile_count(ctypes.byref(self.config.to_c()), self.n_views, self.host_cams))
+
+    def schedule(self):
+        """(phases, phase0_shift) the library uses for this configuration and these views."""
+        p, sh = ctypes.c_int32(), ctypes.c_int32()
+        N.check("gs_schedule", N.lib().gs_schedule(ctypes.byref(self.config.to_c()), self.n_views, self.host_cams,
+                                                   ctypes.byref(p), ctypes.byref(sh)))
+        return p.value, sh.value
 
     # ---------------------------------------------------------------- buffers
     def sizes_for(self, n: int, max_pairs: int) -> Tuple[int, int]:

@@ -59,6 +59,26 @@ def test_default_options_and_version():
     assert b"gfx950" in N.lib().gs_version()
 
 
+def test_schedule_automatic_and_explicit():
+    """phases / phase0_shift = 0 resolve by view count (2 phases from the nearest 1/128 for one view,
+    4 from the nearest 1/64 for several); explicit values pass through; out-of-range ones are rejected."""
+    sc = synth.make_scene(3, n=10, n_views=3, view_sizes=[(96, 64), (130, 77), (64, 64)])
+    cams = N.camera_array(sc.cameras)
+    o = N.default_options()
+    assert (o.phases, o.phase0_shift) == (0, 0)
+    p, sh = ctypes.c_int32(), ctypes.c_int32()
+    assert N.lib().gs_schedule(ctypes.byref(o), 1, cams, ctypes.byref(p), ctypes.byref(sh)) == 0
+    assert (p.value, sh.value) == (2, 7)
+    assert N.lib().gs_schedule(ctypes.byref(o), 3, cams, ctypes.byref(p), ctypes.byref(sh)) == 0
+    assert (p.value, sh.value) == (4, 6)
+    o.phases, o.phase0_shift = 3, 5
+    assert N.lib().gs_schedule(ctypes.byref(o), 3, cams, ctypes.byref(p), ctypes.byref(sh)) == 0
+    assert (p.value, sh.value) == (3, 5)
+    o.phases = 9
+    assert N.lib().gs_schedule(ctypes.byref(o), 3, cams, ctypes.byref(p), ctypes.byref(sh)) == \
+        N.GS_ERR_INVALID_ARGUMENT
+
+
 def test_workspace_query_and_tile_count():
     sc = synth.make_scene(3, n=1000, n_views=3, view_sizes=[(96, 64), (130, 77), (64, 64)])
     cams = N.camera_array(sc.cameras)

@@ -91,18 +91,21 @@ def _large_splat_scene():
 
 @pytest.mark.parametrize("phases,shift,views", [(2, 0, 1), (3, 0, 1), (4, 0, 1), (2, 8, 1), (3, 2, 1),
                                                 (2, 6, 3), (3, 3, 3), (2, 6, "large"), (3, 4, "large"),
-                                                (8, 14, 1), (6, 10, 3)])
+                                                (8, 14, 1), (6, 10, 3), (2, 7, "huge"), (4, 7, "huge")])
 def test_phased_lists_are_exact_prefixes(oracle_mod, phases, shift, views):
     """Depth-progressive binning stores, per tile, a prefix of the oracle's sorted list (bit-exact keys,
     cut at a phase boundary), and the images equal those of full binning bit for bit.  Later phases
     with few front Gaussians leave tiles partially alive, so rows are walked over their alive span;
     the ragged three-view scene puts those rows at several view offsets; the large-splat scene sends
-    rectangles of more than 32 tiles to later phases."""
+    rectangles of more than 32 tiles to later phases, and the full-resolution scene rectangles of
+    more than 256 tiles, which one wave each counts and emits."""
     O = oracle_mod
     if views == 1:
         sc = synth.make_scene(1, n=20000, width=203, height=141)
     elif views == 3:
         sc = synth.make_scene(3, n=20000, n_views=3, view_sizes=[(203, 141), (130, 77), (96, 160)])
+    elif views == "huge":
+        sc = synth.make_scene(1, n=20000)   # 1600x1067: ~370 rectangles of more than 256 tiles past phase 0
     else:
         sc = _large_splat_scene()
     U.say(f"phased prefixes {phases} shift {shift} views {views}")
@@ -130,11 +133,11 @@ def test_phased_lists_are_exact_prefixes(oracle_mod, phases, shift, views):
         assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("phases,shift", [(2, 6), (3, 4)])
-def test_large_rectangles_in_later_phases_with_culling(phases, shift):
-    """Rectangles of more than 32 tiles in later phases, with the exact tile culling on: images equal
-    those of full binning without culling bit for bit."""
-    sc = _large_splat_scene()
+@pytest.mark.parametrize("phases,shift,scene", [(2, 6, "large"), (3, 4, "large"), (2, 7, "huge"), (4, 7, "huge")])
+def test_large_rectangles_in_later_phases_with_culling(phases, shift, scene):
+    """Rectangles of more than 32 (and, at 1600x1067, more than 256) tiles in later phases, with the
+    exact tile culling on: images equal those of full binning without culling bit for bit."""
+    sc = _large_splat_scene() if scene == "large" else synth.make_scene(1, n=20000)
     U.say(f"large rectangles, culling, phases {phases} shift {shift}")
     got = U.forward(sc, U.make_rast(sc, phases=phases, phase0_shift=shift, tile_cull=True))
     ref = U.forward(sc, U.make_rast(sc, phases=1, tile_cull=False))
