@@ -324,7 +324,7 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
             timer_end(T, s);
         }
         timer_begin(T, "phase_count", s);
-        GS_TRY(launch_phase_count(order, counts, rects, L.nv, L.n, vt, ar, hdr, ph, cull, pcounts, s));
+        GS_TRY(launch_phase_count(order, counts, rects, L.nv, L.n, vt, ar, hdr, ph, pcounts, s));
         timer_end(T, s);
         timer_begin(T, "count_scan", s);
         GS_TRY(launch_count_scan(pcounts, L.nv, offsets, blocksums, hdr, ph, L.max_pairs, emit_start, s));

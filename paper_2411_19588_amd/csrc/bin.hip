@@ -118,6 +118,18 @@ __device__ __forceinline__ void for_alive_columns(const uint64_t* __restrict__ b
     }
 }
 
+// Number of alive columns of [lo, hi] in one tile row, from the row's bit masks.
+__device__ __forceinline__ uint32_t alive_in(const uint64_t* __restrict__ bits, uint32_t lo, uint32_t hi) {
+    uint32_t c = 0;
+    for (uint32_t w = lo >> 6; w <= (hi >> 6); ++w) {
+        uint64_t m = bits[w];
+        if (w == (lo >> 6)) m &= ~0ull << (lo & 63);
+        if (w == (hi >> 6) && (hi & 63) != 63) m &= (2ull << (hi & 63)) - 1ull;
+        c += (uint32_t)__popcll(m);
+    }
+    return c;
+}
+
 __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restrict__ order,
                                                        const uint32_t* __restrict__ counts,
                                                        const uint2* __restrict__ rects, int64_t nv, int64_t n,
@@ -125,7 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restri
                                                        const uint2* __restrict__ rowspan,
                                                        const uint64_t* __restrict__ rowbits, uint32_t row_words,
                                                        const SavedHeader* __restrict__ hdr, int phase,
-                                                       CullArgs cull, uint32_t* __restrict__ pcounts,
+                                                       uint32_t* __restrict__ pcounts,
                                                        uint32_t* __restrict__ large_count,
                                                        uint32_t* __restrict__ large_rank) {
     if (phase_empty(hdr, phase)) return;   // no tile left: nothing reads this phase's counts
@@ -141,28 +153,18 @@ __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restri
         const uint32_t e = order[r];
         if (phase == 0) {
             c = counts[e];
-        } else if (counts[e] > kLargeRect) {
-            big = true;   // counted by a whole wave in k_large_count
         } else {
+            // every alive tile of the rectangle (the emission marks the culled ones, as in phase 0):
+            // one popcount per 64 columns of each row's alive span
             const uint2 rc = rects[e];
             const ViewInfo vi = vt[e / (uint64_t)n];
             const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
-            float4 ra = make_float4(0.f, 0.f, 0.f, 0.f);
-            float2 rb = make_float2(0.f, 0.f);
-            if (cull.enabled) {
-                ra = cull.rec[e].a;
-                rb = make_float2(cull.rec[e].b.x, cull.rec[e].b.y);
-            }
             for (uint32_t ty = y0; ty <= y1; ++ty) {
-                // only the alive columns of the row: a later phase walks few tiles of most rectangles
                 const uint2 sp = rowspan[vi.row_base + ty];
                 const uint32_t lo = max(x0, sp.x), hi = min(x1, sp.y);
-                if (lo > hi) continue;
-                for_alive_columns(rowbits + (size_t)(vi.row_base + ty) * row_words, lo, hi, [&](uint32_t tx) {
-                    c += !cull.enabled || tile_may_contribute(ra, rb, vi, tx, ty, cull);
-                    return true;
-                });
+                if (lo <= hi) c += alive_in(rowbits + (size_t)(vi.row_base + ty) * row_words, lo, hi);
             }
+            big = counts[e] > kLargeRect && c > 0;   // emitted by a whole wave in k_large_emit
         }
     }
     // wave-aggregated append of the large rectangles' ranks (the list's order is free: each entry
@@ -175,55 +177,13 @@ __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restri
         base = (uint32_t)__shfl((int)base, leader);
         if (big) large_rank[base + (uint32_t)__popcll(bm & ((1ull << lane) - 1ull))] = (uint32_t)r;
     }
-    if (!big) pcounts[r] = c;
+    pcounts[r] = c;
 }
 
-// One lane's candidate of a large rectangle's row: column tx (<= hi) of row ty is alive (from the
-// row's bit masks) and the pair may contribute.
-__device__ __forceinline__ bool large_keep(uint32_t tx, uint32_t hi, uint32_t ty, const ViewInfo& vi,
-                                           const uint64_t* __restrict__ bits, const float4& ra, const float2& rb,
-                                           const CullArgs& cull) {
-    if (tx > hi || ((bits[tx >> 6] >> (tx & 63)) & 1ull) == 0ull) return false;
-    return !cull.enabled || tile_may_contribute(ra, rb, vi, tx, ty, cull);
+// One lane's candidate of a large rectangle's row: column tx (<= hi) of the row is alive.
+__device__ __forceinline__ bool large_alive(uint32_t tx, uint32_t hi, const uint64_t* __restrict__ bits) {
+    return tx <= hi && ((bits[tx >> 6] >> (tx & 63)) & 1ull) != 0ull;
 }
-
-// Later phases, rectangles of more than kLargeRect tiles: one wave per listed entry walks each
-// row's alive span 64 columns at a time and counts the pairs k_phase_count's loop would count.
-__global__ __launch_bounds__(kBlock) void k_large_count(const uint32_t* __restrict__ order,
-                                                       const uint2* __restrict__ rects, int64_t n,
-                                                       const ViewInfo* __restrict__ vt,
-                                                       const uint2* __restrict__ rowspan,
-                                                       const uint64_t* __restrict__ rowbits, uint32_t row_words,
-                                                       CullArgs cull, const uint32_t* __restrict__ large_count,
-                                                       const uint32_t* __restrict__ large_rank,
-                                                       uint32_t* __restrict__ pcounts) {
-    const uint32_t total = *large_count;
-    const int lane = threadIdx.x & 63;
-    const uint32_t nwaves = gridDim.x * (kBlock / 64);
-    for (uint32_t i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); i < total; i += nwaves) {
-        const uint32_t r = large_rank[i];
-        const uint32_t e = order[r];
-        const uint2 rc = rects[e];
-        const ViewInfo vi = vt[e / (uint64_t)n];
-        const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
-        float4 ra = make_float4(0.f, 0.f, 0.f, 0.f);
-        float2 rb = make_float2(0.f, 0.f);
-        if (cull.enabled) {
-            ra = cull.rec[e].a;
-            rb = make_float2(cull.rec[e].b.x, cull.rec[e].b.y);
-        }
-        uint32_t c = 0;
-        for (uint32_t ty = y0; ty <= y1; ++ty) {
-            const uint2 sp = rowspan[vi.row_base + ty];
-            const uint32_t lo = max(x0, sp.x), hi = min(x1, sp.y);
-            const uint64_t* bits = rowbits + (size_t)(vi.row_base + ty) * row_words;
-            for (uint32_t tx = lo; tx <= hi; tx += 64)
-                c += (uint32_t)__popcll(__ballot(large_keep(tx + lane, hi, ty, vi, bits, ra, rb, cull)));
-        }
-        if (lane == 0) pcounts[r] = c;
-    }
-}
-
 
 __global__ __launch_bounds__(kBlock) void k_count_reduce(const uint32_t* __restrict__ pcounts, int64_t nv,
                                                         const SavedHeader* __restrict__ hdr, int phase,
@@ -426,7 +386,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_alive(const uint32_t* __restric
                                                       const uint64_t* __restrict__ rowbits, uint32_t row_words,
                                                       const uint32_t* __restrict__ counts,
                                                       const SavedHeader* __restrict__ hdr, int phase,
-                                                      CullArgs cull, uint32_t* __restrict__ tiles_out,
+                                                      CullArgs cull, uint32_t n_tiles, uint32_t* __restrict__ tiles_out,
                                                       uint32_t* __restrict__ vals_out) {
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (r >= nv) return;
@@ -455,8 +415,9 @@ __global__ __launch_bounds__(kBlock) void k_emit_alive(const uint32_t* __restric
         if (lo > hi) continue;
         const uint32_t row = vi.tile_base + ty * (uint32_t)vi.tiles_x;
         for_alive_columns(rowbits + (size_t)(vi.row_base + ty) * row_words, lo, hi, [&](uint32_t tx) {
-            if (cull.enabled && !tile_may_contribute(ra, rb, vi, tx, ty, cull)) return true;
-            tiles_out[off] = row + tx;
+            // a culled pair gets the out-of-range tile id: the tile sort leaves it out
+            const bool keep = !cull.enabled || tile_may_contribute(ra, rb, vi, tx, ty, cull);
+            tiles_out[off] = keep ? row + tx : n_tiles;
             vals_out[off] = e;
             return ++off < end;
         });
@@ -464,7 +425,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_alive(const uint32_t* __restric
 }
 
 // Later phases, rectangles of more than kLargeRect tiles: one wave per listed entry writes its
-// pairs at its scanned offset in k_emit_alive's order (rows, then columns), the kept lanes of each
+// pairs at its scanned offset in k_emit_alive's order (rows, then columns), the alive lanes of each
 // 64-column step placed by a ballot prefix.
 __global__ __launch_bounds__(kBlock) void k_large_emit(const uint32_t* __restrict__ order,
                                                       const uint64_t* __restrict__ offsets,
@@ -474,7 +435,7 @@ __global__ __launch_bounds__(kBlock) void k_large_emit(const uint32_t* __restric
                                                       const uint2* __restrict__ rowspan,
                                                       const uint64_t* __restrict__ rowbits, uint32_t row_words,
                                                       const SavedHeader* __restrict__ hdr, int phase, CullArgs cull,
-                                                      const uint32_t* __restrict__ large_count,
+                                                      uint32_t n_tiles, const uint32_t* __restrict__ large_count,
                                                       const uint32_t* __restrict__ large_rank,
                                                       uint32_t* __restrict__ tiles_out,
                                                       uint32_t* __restrict__ vals_out) {
@@ -506,11 +467,12 @@ __global__ __launch_bounds__(kBlock) void k_large_emit(const uint32_t* __restric
             const uint64_t* bits = rowbits + (size_t)(vi.row_base + ty) * row_words;
             const uint32_t row = vi.tile_base + ty * (uint32_t)vi.tiles_x;
             for (uint32_t tx = lo; tx <= hi && off < end; tx += 64) {
-                const bool keep = large_keep(tx + lane, hi, ty, vi, bits, ra, rb, cull);
-                const uint64_t bm = __ballot(keep);
+                const bool a = large_alive(tx + lane, hi, bits);
+                const uint64_t bm = __ballot(a);
                 const uint64_t pos = off + (uint64_t)__popcll(bm & below);
-                if (keep && pos < end) {
-                    tiles_out[pos] = row + tx + lane;
+                if (a && pos < end) {
+                    const bool keep = !cull.enabled || tile_may_contribute(ra, rb, vi, tx + lane, ty, cull);
+                    tiles_out[pos] = keep ? row + tx + lane : n_tiles;   // culled: left out by the tile sort
                     vals_out[pos] = e;
                 }
                 off += (uint64_t)__popcll(bm);
@@ -608,14 +570,11 @@ hipError_t launch_visible(int phases, int phase0_shift, SavedHeader* hdr, hipStr
 
 hipError_t launch_phase_count(const uint32_t* order, const uint32_t* counts, const uint2* rects, int64_t nv,
                               int64_t n, const ViewInfo* vt, const AliveRows& ar,
-                              const SavedHeader* hdr, int phase, const CullArgs& cull, uint32_t* pcounts,
-                              hipStream_t s) {
+                              const SavedHeader* hdr, int phase, uint32_t* pcounts, hipStream_t s) {
     if (nv == 0) return hipSuccess;
     const unsigned grid = (unsigned)((nv + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_phase_count, dim3(grid), dim3(kBlock), 0, s, order, counts, rects, nv, n, vt, ar.span, ar.bits, ar.words, hdr, phase, cull, pcounts, ar.large_count, ar.large_rank);
-    if (phase > 0)
-        hipLaunchKernelGGL(k_large_count, dim3(large_grid(nv)), dim3(kBlock), 0, s, order, rects, n, vt, ar.span,
-                           ar.bits, ar.words, cull, ar.large_count, ar.large_rank, pcounts);
+    hipLaunchKernelGGL(k_phase_count, dim3(grid), dim3(kBlock), 0, s, order, counts, rects, nv, n, vt, ar.span,
+                       ar.bits, ar.words, hdr, phase, pcounts, ar.large_count, ar.large_rank);
     return hipGetLastError();
 }
 
@@ -652,9 +611,9 @@ hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uin
     } else {
         const unsigned grid = (unsigned)((nv + kBlock - 1) / kBlock);
         hipLaunchKernelGGL(k_emit_alive, dim3(grid), dim3(kBlock), 0, s, order, offsets, pcounts, rects, nv, n, vt,
-                           ar.span, ar.bits, ar.words, counts, hdr, phase, cull, tiles_out, vals_out);
+                           ar.span, ar.bits, ar.words, counts, hdr, phase, cull, n_tiles, tiles_out, vals_out);
         hipLaunchKernelGGL(k_large_emit, dim3(large_grid(nv)), dim3(kBlock), 0, s, order, offsets, pcounts, rects, n,
-                           vt, ar.span, ar.bits, ar.words, hdr, phase, cull, ar.large_count, ar.large_rank,
+                           vt, ar.span, ar.bits, ar.words, hdr, phase, cull, n_tiles, ar.large_count, ar.large_rank,
                            tiles_out, vals_out);
     }
     return hipGetLastError();

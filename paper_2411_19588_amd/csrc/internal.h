@@ -160,8 +160,7 @@ struct AliveRows {
 };
 hipError_t launch_phase_count(const uint32_t* order, const uint32_t* counts, const uint2* rects, int64_t nv,
                               int64_t n, const ViewInfo* vt, const AliveRows& ar,
-                              const SavedHeader* hdr, int phase, const CullArgs& cull, uint32_t* pcounts,
-                              hipStream_t s);
+                              const SavedHeader* hdr, int phase, uint32_t* pcounts, hipStream_t s);
 hipError_t launch_alive_rows(const ViewInfo* vt, int32_t views, int64_t rows, const uint32_t* alive,
                              const AliveRows& ar, hipStream_t s);
 // Exclusive scan of pcounts into offsets (u64) and the phase's pair count and base in hdr (with the
