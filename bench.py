@@ -379,7 +379,7 @@ def main():
     # pairs per depth phase (from the stored per-phase tile ranges)
     _, _, rng = ts.rast.export_keys(R.ForwardContext(ts.saved, ts.max_pairs, ts.n, sc.sh_degree), stream)
     rng = rng.to(torch.int64)
-    phases, shift = ts.rast.schedule()
+    phases, shift = ts.rast.schedule(ts.n)
     phase_pairs = [int((rng[p, :, 1] - rng[p, :, 0]).sum().item()) for p in range(phases)]
     log(f"live pairs per phase: {phase_pairs}")
     # full (single-phase) binning pair count of the same scene, for K/N

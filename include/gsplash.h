@@ -137,8 +137,10 @@ typedef struct gs_options {
                                             are identical for every value. */
     int32_t phase0_shift;                /* the first range is the nearest 1/2^shift of the visible
                                             Gaussians, each later one (but the last) 4x wider: 1..20;
-                                            0 (default) = automatic: 7 for one view, 6 for several.
-                                            Images are identical for every value. */
+                                            0 (default) = automatic: for one view log2 of the Gaussians
+                                            per tile, rounded and clamped to 2..12 (about one Gaussian
+                                            per tile first); 6 for several.  Images are identical for
+                                            every value. */
     int64_t max_pairs;                   /* capacity of the stored (Gaussian, tile) pair list, <= GS_MAX_PAIRS */
     void* timer;                         /* optional gs_timer* receiving per-kernel HIP events; NULL = none */
 } gs_options;
@@ -226,10 +228,11 @@ int gs_export_keys(const gs_options* opts, int64_t n, int32_t n_views, const gs_
 int gs_forward_stats(const gs_options* opts, int64_t n, int32_t n_views, const gs_camera* host_cams,
                      const void* saved, size_t saved_bytes, int64_t* stats, gs_stream_t stream);
 
-/* The depth-phase schedule these options give for n_views views (host only): the number of
- * phases and the first phase's shift, with the automatic values (0) resolved.  Returns GS_OK
- * or GS_ERR_INVALID_ARGUMENT as gs_workspace_query would. */
-int gs_schedule(const gs_options* opts, int32_t n_views, const gs_camera* host_cams, int32_t* phases,
+/* The depth-phase schedule these options give for n Gaussians and n_views views (host only):
+ * the number of phases and the first phase's shift, with the automatic values (0) resolved.
+ * `phases` and `phase0_shift` may be NULL.  Returns GS_OK or GS_ERR_INVALID_ARGUMENT as
+ * gs_workspace_query would. */
+int gs_schedule(const gs_options* opts, int64_t n, int32_t n_views, const gs_camera* host_cams, int32_t* phases,
                 int32_t* phase0_shift);
 
 /* Total number of tiles over the views for these options (host only). */

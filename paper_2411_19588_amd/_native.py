@@ -93,7 +93,7 @@ PROTOTYPES = {
     "gs_forward_stats": (ctypes.c_int, [ctypes.POINTER(GsOptions), _I64, _I32, ctypes.POINTER(GsCamera), _P, _SZ,
                                         ctypes.POINTER(_I64), _P]),
     "gs_tile_count": (_I64, [ctypes.POINTER(GsOptions), _I32, ctypes.POINTER(GsCamera)]),
-    "gs_schedule": (ctypes.c_int, [ctypes.POINTER(GsOptions), _I32, ctypes.POINTER(GsCamera),
+    "gs_schedule": (ctypes.c_int, [ctypes.POINTER(GsOptions), _I64, _I32, ctypes.POINTER(GsCamera),
                                    ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "gs_activate": (ctypes.c_int, [_I64, _P, _P, _P, _P, _P]),
     "gs_activate_backward": (ctypes.c_int, [_I64, _P, _P, _P, _P, _P, _P, _P]),

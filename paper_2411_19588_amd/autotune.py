@@ -43,7 +43,8 @@ def candidates(tiles=(16, 8), persistent=(False, True)) -> List[dict]:
 def schedules() -> List[dict]:
     """Depth-phase schedules worth timing: the nearest 1/2^shift of the Gaussians first."""
     return [dict(phases=p, phase0_shift=sh)
-            for p, sh in ((2, 5), (2, 6), (2, 7), (3, 5), (3, 6), (4, 6), (5, 8), (6, 10), (8, 14))]
+            for p, sh in ((2, 5), (2, 6), (2, 7), (3, 5), (3, 6), (4, 6), (4, 7), (5, 7), (5, 8), (6, 10),
+                          (8, 14))]
 
 
 def workload_key(device_name: str, n: int, sh_degree: int, sizes: Sequence) -> str:

@@ -3,6 +3,9 @@
 // step is one of the kernels declared in internal.h.
 #include <string.h>
 
+#include <algorithm>
+#include <cmath>
+
 #include <string>
 #include <vector>
 
@@ -55,8 +58,6 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     memset(L, 0, sizeof(*L));
     L->n = n;
     L->views = n_views;
-    L->phases = o->phases != 0 ? o->phases : (n_views == 1 ? kAutoPhasesOneView : kAutoPhasesViews);
-    L->phase0_shift = o->phase0_shift != 0 ? o->phase0_shift : (n_views == 1 ? kAutoShiftOneView : kAutoShiftViews);
     L->nv = n * n_views;
     L->max_pairs = o->max_pairs;
     L->tile_w = o->tile_w;
@@ -83,6 +84,18 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     L->table.count = n_views;
     if (tiles >= (1LL << 31)) return GS_ERR_INVALID_ARGUMENT;
     L->tiles = tiles;
+    // automatic schedule: one view bins first the nearest ~1 Gaussian per tile (shift = log2 of the
+    // Gaussians per tile, rounded); several views use a fixed 4-phase schedule
+    L->phases = o->phases != 0 ? o->phases : (n_views == 1 ? kAutoPhasesOneView : kAutoPhasesViews);
+    if (o->phase0_shift != 0) {
+        L->phase0_shift = o->phase0_shift;
+    } else if (n_views == 1) {
+        const double per_tile = (double)n / (double)tiles;
+        const long sh = per_tile > 1.0 ? std::lround(std::log2(per_tile)) : 0;
+        L->phase0_shift = (int)std::min<long>(kAutoShiftMax, std::max<long>(kAutoShiftMin, sh));
+    } else {
+        L->phase0_shift = kAutoShiftViews;
+    }
     L->rows = rows;
     int64_t max_tx = 1;
     for (int v = 0; v < n_views; ++v) max_tx = L->table.v[v].tiles_x > max_tx ? L->table.v[v].tiles_x : max_tx;
@@ -128,7 +141,7 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     L->w_dvals2 = w.take(nv * 4);
     L->w_pcounts = w.take(nv * 4);
     L->w_offsets = w.take((nv + 1) * 8);
-    L->w_blocksums = w.take(nb * 8);
+    L->w_blocksums = w.take((2 * nb + 1) * 8);   // chunk sums, chunk non-zero counts, list length
     L->w_emit_start = w.take(((size_t)o->max_pairs / 1024 + 2) * 4);   // first entry of each emission span
     L->w_tiles_a = w.take(K * 4);
     L->w_vals_a = w.take(K * 4);
@@ -140,7 +153,7 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     L->w_adam = w.take(16);                    // bias corrections of a fused Adam step
     L->w_rowspan = w.take(rows * 8);           // alive columns per tile row (later depth phases)
     L->w_rowbits = w.take((size_t)rows * L->row_words * 8);   // and their bit masks
-    L->w_large = w.take(256 + nv * 4);         // later phases: count and ranks of the large rectangles
+    L->w_nzr = w.take(nv * 4);                 // later phases: the entries with pairs, in depth order
     L->w_shf = w.take(n_views == 1 ? (size_t)n * kShf * 4 : 0);   // SH-gradient factors etc. (fused Adam)
     L->workspace_bytes = w.at;
     return GS_OK;
@@ -240,10 +253,10 @@ int gs_workspace_query(const gs_options* opts, int64_t n, int32_t n_views, const
     return GS_OK;
 }
 
-int gs_schedule(const gs_options* opts, int32_t n_views, const gs_camera* host_cams, int32_t* phases,
+int gs_schedule(const gs_options* opts, int64_t n, int32_t n_views, const gs_camera* host_cams, int32_t* phases,
                 int32_t* phase0_shift) {
     Layout L;
-    const int rc = compute_layout(opts, 0, n_views, host_cams, &L);
+    const int rc = compute_layout(opts, n, n_views, host_cams, &L);
     if (rc != GS_OK) return rc;
     if (phases) *phases = L.phases;
     if (phase0_shift) *phase0_shift = L.phase0_shift;
@@ -315,8 +328,7 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
     float* wsum = at<float>(saved, L.s_wsum);
     const CullArgs cull{rec, log2f(o.alpha_min), o.tile_w, o.tile_h, o.tile_cull};
     const AliveRows ar{at<uint2>(workspace, L.w_rowspan), at<uint64_t>(workspace, L.w_rowbits),
-                       (uint32_t)L.row_words, at<uint32_t>(workspace, L.w_large),
-                       at<uint32_t>(workspace, L.w_large + 256)};
+                       (uint32_t)L.row_words, at<uint32_t>(workspace, L.w_nzr)};
     for (int ph = 0; ph < L.phases; ++ph) {
         if (ph > 0) {
             timer_begin(T, "alive_rows", s);
@@ -327,11 +339,11 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
         GS_TRY(launch_phase_count(order, counts, rects, L.nv, L.n, vt, ar, hdr, ph, pcounts, s));
         timer_end(T, s);
         timer_begin(T, "count_scan", s);
-        GS_TRY(launch_count_scan(pcounts, L.nv, offsets, blocksums, hdr, ph, L.max_pairs, emit_start, s));
+        GS_TRY(launch_count_scan(pcounts, L.nv, offsets, blocksums, hdr, ph, L.max_pairs, emit_start, ar.nzr, s));
         timer_end(T, s);
         timer_begin(T, "emit", s);
-        GS_TRY(launch_emit(order, offsets, emit_start, pcounts, counts, rects, L.nv, L.n, vt, ar, hdr, ph,
-                           L.max_pairs, cull, (uint32_t)L.tiles, tiles_a, vals_a, s));
+        GS_TRY(launch_emit(order, offsets, emit_start, blocksums, rects, L.nv, L.n, vt, ar, hdr, ph, L.max_pairs,
+                           cull, (uint32_t)L.tiles, tiles_a, vals_a, s));
         timer_end(T, s);
         // stable sort of the phase's pairs by tile id
         int tb = 0;

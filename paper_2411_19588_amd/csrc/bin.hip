@@ -103,21 +103,6 @@ __device__ __forceinline__ bool phase_empty(const SavedHeader* hdr, int phase) {
     return phase > 0 && hdr->phase_alive[phase - 1] == 0;
 }
 
-// The alive columns of [lo, hi] in one tile row, from the row's bit masks: one load per 64 columns.
-template <typename F>
-__device__ __forceinline__ void for_alive_columns(const uint64_t* __restrict__ bits, uint32_t lo, uint32_t hi, F&& f) {
-    for (uint32_t w = lo >> 6; w <= (hi >> 6); ++w) {
-        uint64_t m = bits[w];
-        if (w == (lo >> 6)) m &= ~0ull << (lo & 63);
-        if (w == (hi >> 6) && (hi & 63) != 63) m &= (2ull << (hi & 63)) - 1ull;
-        while (m) {
-            const uint32_t tx = w * 64 + (uint32_t)__builtin_ctzll(m);
-            m &= m - 1ull;
-            if (!f(tx)) return;
-        }
-    }
-}
-
 // Number of alive columns of [lo, hi] in one tile row, from the row's bit masks.
 __device__ __forceinline__ uint32_t alive_in(const uint64_t* __restrict__ bits, uint32_t lo, uint32_t hi) {
     uint32_t c = 0;
@@ -137,9 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restri
                                                        const uint2* __restrict__ rowspan,
                                                        const uint64_t* __restrict__ rowbits, uint32_t row_words,
                                                        const SavedHeader* __restrict__ hdr, int phase,
-                                                       uint32_t* __restrict__ pcounts,
-                                                       uint32_t* __restrict__ large_count,
-                                                       uint32_t* __restrict__ large_rank) {
+                                                       uint32_t* __restrict__ pcounts) {
     if (phase_empty(hdr, phase)) return;   // no tile left: nothing reads this phase's counts
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (r >= nv) return;
@@ -148,7 +131,6 @@ __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restri
     // inside them
     if ((uint64_t)r < r0 || (uint64_t)r >= r1) return;
     uint32_t c = 0;
-    bool big = false;
     if (!hdr->stop) {
         const uint32_t e = order[r];
         if (phase == 0) {
@@ -164,74 +146,86 @@ __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restri
                 const uint32_t lo = max(x0, sp.x), hi = min(x1, sp.y);
                 if (lo <= hi) c += alive_in(rowbits + (size_t)(vi.row_base + ty) * row_words, lo, hi);
             }
-            big = counts[e] > kLargeRect && c > 0;   // emitted by a whole wave in k_large_emit
         }
-    }
-    // wave-aggregated append of the large rectangles' ranks (the list's order is free: each entry
-    // writes at its own scanned offset)
-    const uint64_t bm = __ballot(big);
-    if (bm) {
-        const int lane = threadIdx.x & 63, leader = __ffsll((unsigned long long)bm) - 1;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(large_count, (uint32_t)__popcll(bm));
-        base = (uint32_t)__shfl((int)base, leader);
-        if (big) large_rank[base + (uint32_t)__popcll(bm & ((1ull << lane) - 1ull))] = (uint32_t)r;
     }
     pcounts[r] = c;
 }
 
-// One lane's candidate of a large rectangle's row: column tx (<= hi) of the row is alive.
-__device__ __forceinline__ bool large_alive(uint32_t tx, uint32_t hi, const uint64_t* __restrict__ bits) {
-    return tx <= hi && ((bits[tx >> 6] >> (tx & 63)) & 1ull) != 0ull;
-}
-
+// Per chunk of kScanChunk ranks: the sum of the phase's counts (blocksums[b]) and the number of
+// non-zero ones (blocksums[nb + b]).
 __global__ __launch_bounds__(kBlock) void k_count_reduce(const uint32_t* __restrict__ pcounts, int64_t nv,
                                                         const SavedHeader* __restrict__ hdr, int phase,
-                                                        uint64_t* __restrict__ blocksums) {
+                                                        uint64_t* __restrict__ blocksums, int nb) {
     __shared__ uint64_t red[kBlock];
+    __shared__ uint32_t zred[kBlock];
     const int64_t b0 = (int64_t)blockIdx.x * kScanChunk;
     const int64_t r0 = hdr->phase_rank[phase], r1 = hdr->phase_rank[phase + 1];
     if (phase_empty(hdr, phase) || b0 + kScanChunk <= r0 || b0 >= r1) {   // no count of the phase here
-        if (threadIdx.x == 0) blocksums[blockIdx.x] = 0;
+        if (threadIdx.x == 0) {
+            blocksums[blockIdx.x] = 0;
+            blocksums[nb + blockIdx.x] = 0;
+        }
         return;
     }
     uint64_t s = 0;
+    uint32_t z = 0;
     for (int k = 0; k < 16; ++k) {
         const int64_t r = b0 + k * kBlock + threadIdx.x;
-        if (r < nv && r >= r0 && r < r1) s += pcounts[r];
+        if (r < nv && r >= r0 && r < r1) {
+            const uint32_t c = pcounts[r];
+            s += c;
+            z += c != 0u;
+        }
     }
     red[threadIdx.x] = s;
+    zred[threadIdx.x] = z;
     __syncthreads();
     for (int off = kBlock / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        if (threadIdx.x < off) {
+            red[threadIdx.x] += red[threadIdx.x + off];
+            zred[threadIdx.x] += zred[threadIdx.x + off];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) blocksums[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) {
+        blocksums[blockIdx.x] = red[0];
+        blocksums[nb + blockIdx.x] = zred[0];
+    }
 }
 
-// Exclusive scan of the block sums (one workgroup), then the phase's base, count and capacity check.
+// Exclusive scans of the block sums and of the block non-zero counts (one workgroup; the number
+// of non-zero counts goes to blocksums[2 nb]), then the phase's base, count and capacity check.
 __global__ __launch_bounds__(1024) void k_count_blocks(uint64_t* blocksums, int nb, SavedHeader* hdr, int phase,
                                                       int64_t max_pairs) {
-    __shared__ uint64_t sums[1024];
+    __shared__ uint64_t sums[1024], zsums[1024];
     const int tid = threadIdx.x;
     const int per = (nb + 1023) / 1024;
     const int b = tid * per, e = min(nb, b + per);
-    uint64_t s = 0;
-    for (int i = b; i < e; ++i) s += blocksums[i];
+    uint64_t s = 0, z = 0;
+    for (int i = b; i < e; ++i) {
+        s += blocksums[i];
+        z += blocksums[nb + i];
+    }
     sums[tid] = s;
+    zsums[tid] = z;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
         const uint64_t v = tid >= off ? sums[tid - off] : 0ull;
+        const uint64_t w = tid >= off ? zsums[tid - off] : 0ull;
         __syncthreads();
         sums[tid] += v;
+        zsums[tid] += w;
         __syncthreads();
     }
-    uint64_t run = sums[tid] - s;
+    uint64_t run = sums[tid] - s, zrun = zsums[tid] - z;
     for (int i = b; i < e; ++i) {
-        const uint64_t v = blocksums[i];
+        const uint64_t v = blocksums[i], w = blocksums[nb + i];
         blocksums[i] = run;
+        blocksums[nb + i] = zrun;
         run += v;
+        zrun += w;
     }
+    if (tid == 1023) blocksums[2 * nb] = zsums[1023];
     if (tid == 1023 && !hdr->stop) {   // after an overflow the header keeps what the failing phase needed
         const uint64_t total = sums[1023];
         const uint64_t base = hdr->pair_count;
@@ -253,8 +247,9 @@ __global__ __launch_bounds__(kBlock) void k_count_down(const uint32_t* __restric
                                                       const uint64_t* __restrict__ blocksums,
                                                       const SavedHeader* __restrict__ hdr, int phase,
                                                       uint64_t* __restrict__ offsets, uint32_t* __restrict__ emit_start,
-                                                      int64_t n_spans) {
+                                                      int64_t n_spans, int nb, uint32_t* __restrict__ nzr) {
     __shared__ uint64_t part[kBlock];
+    __shared__ uint32_t zpart[kBlock];
     if (phase_empty(hdr, phase)) return;   // every count is 0: no entry reads its offset
     // offsets are read inside the phase's ranks, and by the phase-0 emission up to one span past them
     const int64_t r0 = hdr->phase_rank[phase], r1 = hdr->phase_rank[phase + 1];
@@ -264,31 +259,41 @@ __global__ __launch_bounds__(kBlock) void k_count_down(const uint32_t* __restric
     const int64_t b0 = cb + (int64_t)tid * 16;   // 16 consecutive per thread
     uint32_t c[16];
     uint64_t s = 0;
+    uint32_t z = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int64_t r = b0 + k;
         c[k] = r < nv && r >= r0 && r < r1 ? pcounts[r] : 0u;
         s += c[k];
+        z += c[k] != 0u;
     }
     part[tid] = s;
+    zpart[tid] = z;
     __syncthreads();
     for (int off = 1; off < kBlock; off <<= 1) {
         const uint64_t v = tid >= off ? part[tid - off] : 0ull;
+        const uint32_t w = tid >= off ? zpart[tid - off] : 0u;
         __syncthreads();
         part[tid] += v;
+        zpart[tid] += w;
         __syncthreads();
     }
     uint64_t run = blocksums[blockIdx.x] + part[tid] - s;
+    uint32_t zrun = (uint32_t)blocksums[nb + blockIdx.x] + zpart[tid] - z;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int64_t r = b0 + k;
         if (r < nv) {
             offsets[r] = run;
-            // emission spans whose first pair falls inside this entry's pairs [run, run + c)
             if (c[k]) {
+                // later phases: the compact list of the entries with pairs, in depth order
+                if (phase > 0) nzr[zrun] = (uint32_t)r;
+                // emission spans whose first pair falls inside this entry's pairs [run, run + c):
+                // their first entry (a depth rank in phase 0, a position in the compact list later)
                 for (int64_t b = (int64_t)((run + kEmitSpan - 1) / kEmitSpan);
                      b * kEmitSpan < (int64_t)(run + c[k]) && b < n_spans; ++b)
-                    emit_start[b] = (uint32_t)r;
+                    emit_start[b] = phase == 0 ? (uint32_t)r : zrun;
+                ++zrun;
             }
         }
         run += c[k];
@@ -376,118 +381,166 @@ __global__ __launch_bounds__(kBlock) void k_emit_rects(const uint32_t* __restric
     }
 }
 
-// Later phases: one thread per entry writes the pairs of its rectangle's alive tiles.
-__global__ __launch_bounds__(kBlock) void k_emit_alive(const uint32_t* __restrict__ order,
-                                                      const uint64_t* __restrict__ offsets,
-                                                      const uint32_t* __restrict__ pcounts,
-                                                      const uint2* __restrict__ rects, int64_t nv, int64_t n,
-                                                      const ViewInfo* __restrict__ vt,
-                                                      const uint2* __restrict__ rowspan,
-                                                      const uint64_t* __restrict__ rowbits, uint32_t row_words,
-                                                      const uint32_t* __restrict__ counts,
-                                                      const SavedHeader* __restrict__ hdr, int phase,
-                                                      CullArgs cull, uint32_t n_tiles, uint32_t* __restrict__ tiles_out,
-                                                      uint32_t* __restrict__ vals_out) {
-    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (r >= nv) return;
-    const uint64_t K = hdr->phase_count[phase];
-    if (K == 0) return;   // also every phase after which no tile was alive: its counts are not written
-    if ((uint64_t)r < hdr->phase_rank[phase] || (uint64_t)r >= hdr->phase_rank[phase + 1]) return;
-    const uint32_t c = pcounts[r];
-    if (c == 0) return;
-    uint64_t off = offsets[r];
-    if (off + c > K) return;   // cannot happen for a consistent scan
-    const uint32_t e = order[r];
-    if (counts[e] > kLargeRect) return;   // emitted by k_large_emit
-    const uint2 rc = rects[e];
-    const ViewInfo vi = vt[e / (uint64_t)n];
-    const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
-    const uint64_t end = off + c;
-    float4 ra = make_float4(0.f, 0.f, 0.f, 0.f);
-    float2 rb = make_float2(0.f, 0.f);
-    if (cull.enabled) {
-        ra = cull.rec[e].a;
-        rb = make_float2(cull.rec[e].b.x, cull.rec[e].b.y);
-    }
-    for (uint32_t ty = y0; ty <= y1 && off < end; ++ty) {
-        const uint2 sp = rowspan[vi.row_base + ty];
-        const uint32_t lo = max(x0, sp.x), hi = min(x1, sp.y);
-        if (lo > hi) continue;
-        const uint32_t row = vi.tile_base + ty * (uint32_t)vi.tiles_x;
-        for_alive_columns(rowbits + (size_t)(vi.row_base + ty) * row_words, lo, hi, [&](uint32_t tx) {
-            // a culled pair gets the out-of-range tile id: the tile sort leaves it out
-            const bool keep = !cull.enabled || tile_may_contribute(ra, rb, vi, tx, ty, cull);
-            tiles_out[off] = keep ? row + tx : n_tiles;
-            vals_out[off] = e;
-            return ++off < end;
-        });
-    }
+// Position of the k-th (from 0) set bit of m; m has more than k set bits.
+__device__ __forceinline__ uint32_t select_bit(uint64_t m, uint32_t k) {
+    uint32_t pos = 0, c;
+    c = (uint32_t)__popc((uint32_t)m);
+    if (k >= c) { k -= c; m >>= 32; pos += 32; }
+    c = (uint32_t)__popc((uint32_t)m & 0xFFFFu);
+    if (k >= c) { k -= c; m >>= 16; pos += 16; }
+    c = (uint32_t)__popc((uint32_t)m & 0xFFu);
+    if (k >= c) { k -= c; m >>= 8; pos += 8; }
+    c = (uint32_t)__popc((uint32_t)m & 0xFu);
+    if (k >= c) { k -= c; m >>= 4; pos += 4; }
+    c = (uint32_t)__popc((uint32_t)m & 0x3u);
+    if (k >= c) { k -= c; m >>= 2; pos += 2; }
+    if (k >= ((uint32_t)m & 1u)) pos += 1;
+    return pos;
 }
 
-// Later phases, rectangles of more than kLargeRect tiles: one wave per listed entry writes its
-// pairs at its scanned offset in k_emit_alive's order (rows, then columns), the alive lanes of each
-// 64-column step placed by a ballot prefix.
-__global__ __launch_bounds__(kBlock) void k_large_emit(const uint32_t* __restrict__ order,
+// Column of the k-th (from 0) alive tile of [lo, hi] in one tile row (hi if there are fewer).
+__device__ __forceinline__ uint32_t kth_alive(const uint64_t* __restrict__ bits, uint32_t lo, uint32_t hi,
+                                              uint32_t k) {
+    for (uint32_t w = lo >> 6; w <= (hi >> 6); ++w) {
+        uint64_t m = bits[w];
+        if (w == (lo >> 6)) m &= ~0ull << (lo & 63);
+        if (w == (hi >> 6) && (hi & 63) != 63) m &= (2ull << (hi & 63)) - 1ull;
+        const uint32_t c = (uint32_t)__popcll(m);
+        if (k < c) return w * 64 + select_bit(m, k);
+        k -= c;
+    }
+    return hi;
+}
+
+// Later-phase pair emission (the alive tiles of each rectangle, rows then columns), balanced
+// over output pairs like the phase-0 emission: workgroup b writes pairs [b*kEmitSpan,
+// (b+1)*kEmitSpan).  It stages the entries with pairs in that span (from the compact list of the
+// entries with a non-zero count, starting at emit_start[b]), splits them into rows with alive
+// tiles -- one item per row, stored at its first pair in the span -- and gives each pair its row
+// by a running maximum over the item positions and its column as the k-th alive one of the row.
+__global__ __launch_bounds__(kBlock) void k_emit_spans(const uint32_t* __restrict__ order,
                                                       const uint64_t* __restrict__ offsets,
-                                                      const uint32_t* __restrict__ pcounts,
+                                                      const uint32_t* __restrict__ nzr,
+                                                      const uint64_t* __restrict__ nz_total,
+                                                      const uint32_t* __restrict__ emit_start,
                                                       const uint2* __restrict__ rects, int64_t n,
                                                       const ViewInfo* __restrict__ vt,
                                                       const uint2* __restrict__ rowspan,
                                                       const uint64_t* __restrict__ rowbits, uint32_t row_words,
-                                                      const SavedHeader* __restrict__ hdr, int phase, CullArgs cull,
-                                                      uint32_t n_tiles, const uint32_t* __restrict__ large_count,
-                                                      const uint32_t* __restrict__ large_rank,
+                                                      const SavedHeader* __restrict__ hdr, int phase,
+                                                      CullArgs cull, uint32_t n_tiles,
                                                       uint32_t* __restrict__ tiles_out,
                                                       uint32_t* __restrict__ vals_out) {
+    __shared__ int32_t s_off[kEmitSpan + 1];   // entry: first pair, relative to the span
+    __shared__ uint32_t s_e[kEmitSpan + 1];    // entry: (view, Gaussian) index
+    __shared__ int32_t s_cover[kEmitSpan];     // item position at its first pair, -1 elsewhere; then the running max
+    __shared__ int32_t s_ist[kEmitSpan];       // item: first pair, relative to the span (< 0 for a row begun before)
+    __shared__ uint32_t s_ilohi[kEmitSpan];    // item: column range lo | hi << 16
+    __shared__ uint32_t s_ijy[kEmitSpan];      // item: entry slot | tile row << 16
+    __shared__ int32_t s_wmax[kBlock / 64];
     const uint64_t K = hdr->phase_count[phase];
-    if (K == 0) return;
-    const uint32_t total = *large_count;
-    const int lane = threadIdx.x & 63;
-    const uint64_t below = (1ull << lane) - 1ull;
-    const uint32_t nwaves = gridDim.x * (kBlock / 64);
-    for (uint32_t i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); i < total; i += nwaves) {
-        const uint32_t r = large_rank[i];
-        const uint32_t c = pcounts[r];
-        uint64_t off = offsets[r];
-        if (c == 0 || off + c > K) continue;   // the second cannot happen for a consistent scan
-        const uint64_t end = off + c;
-        const uint32_t e = order[r];
+    const uint64_t p0 = (uint64_t)blockIdx.x * kEmitSpan;
+    if (K == 0 || p0 >= K) return;
+    const int span = (int)min((uint64_t)kEmitSpan, K - p0);
+    const uint64_t p1 = p0 + (uint64_t)span;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const uint64_t i0 = emit_start[blockIdx.x], nz = *nz_total;
+    // entries: every one after the first starts inside the span, and each has a pair, so at most
+    // kEmitSpan + 1 of them
+    int nent = 0;
+    for (int j0 = 0; j0 < kEmitSpan + 1; j0 += kBlock) {
+        const int j = j0 + tid;
+        const uint64_t idx = i0 + (uint64_t)j;
+        bool own = false;
+        if (j < kEmitSpan + 1 && idx < nz) {
+            const uint32_t r = nzr[idx];
+            const uint64_t off = offsets[r];
+            own = j == 0 || off < p1;
+            if (own) {
+                s_off[j] = (int32_t)((int64_t)off - (int64_t)p0);
+                s_e[j] = order[r];
+            }
+        }
+        nent += __syncthreads_count(own);
+    }
+    for (int q = tid; q < kEmitSpan; q += kBlock) s_cover[q] = -1;
+    __syncthreads();
+    // items: the rows with alive tiles of each entry that reach into the span
+    for (int j = tid; j < nent; j += kBlock) {
+        const uint32_t e = s_e[j];
         const uint2 rc = rects[e];
         const ViewInfo vi = vt[e / (uint64_t)n];
         const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
-        float4 ra = make_float4(0.f, 0.f, 0.f, 0.f);
-        float2 rb = make_float2(0.f, 0.f);
-        if (cull.enabled) {
-            ra = cull.rec[e].a;
-            rb = make_float2(cull.rec[e].b.x, cull.rec[e].b.y);
-        }
-        for (uint32_t ty = y0; ty <= y1 && off < end; ++ty) {
+        int32_t st = s_off[j];
+        for (uint32_t ty = y0; ty <= y1 && st < span; ++ty) {
             const uint2 sp = rowspan[vi.row_base + ty];
             const uint32_t lo = max(x0, sp.x), hi = min(x1, sp.y);
-            const uint64_t* bits = rowbits + (size_t)(vi.row_base + ty) * row_words;
-            const uint32_t row = vi.tile_base + ty * (uint32_t)vi.tiles_x;
-            for (uint32_t tx = lo; tx <= hi && off < end; tx += 64) {
-                const bool a = large_alive(tx + lane, hi, bits);
-                const uint64_t bm = __ballot(a);
-                const uint64_t pos = off + (uint64_t)__popcll(bm & below);
-                if (a && pos < end) {
-                    const bool keep = !cull.enabled || tile_may_contribute(ra, rb, vi, tx + lane, ty, cull);
-                    tiles_out[pos] = keep ? row + tx + lane : n_tiles;   // culled: left out by the tile sort
-                    vals_out[pos] = e;
-                }
-                off += (uint64_t)__popcll(bm);
+            if (lo > hi) continue;
+            const int32_t c = (int32_t)alive_in(rowbits + (size_t)(vi.row_base + ty) * row_words, lo, hi);
+            if (c == 0) continue;
+            if (st + c > 0) {
+                const int pos = max(st, 0);
+                s_ist[pos] = st;
+                s_ilohi[pos] = lo | (hi << 16);
+                s_ijy[pos] = (uint32_t)j | (ty << 16);
+                s_cover[pos] = pos;
             }
+            st += c;
         }
+    }
+    __syncthreads();
+    // running maximum over the span: each pair's item is the last one that starts at or before it
+    int v[kEmitItems];
+    int m = -1;
+#pragma unroll
+    for (int k = 0; k < kEmitItems; ++k) {
+        m = max(m, s_cover[tid * kEmitItems + k]);
+        v[k] = m;
+    }
+    int x = m;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d);
+        if (lane >= d) x = max(x, y);
+    }
+    if (lane == 63) s_wmax[tid >> 6] = x;
+    __syncthreads();
+    int before = __shfl_up(x, 1);
+    if (lane == 0) before = -1;
+    for (int w = 0; w < (tid >> 6); ++w) before = max(before, s_wmax[w]);
+#pragma unroll
+    for (int k = 0; k < kEmitItems; ++k) s_cover[tid * kEmitItems + k] = max(before, v[k]);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kEmitItems; ++k) {
+        const int q = k * kBlock + tid;
+        if (q >= span) break;
+        const int pos = s_cover[q];
+        if (pos < 0) {   // cannot happen: the first entry covers the span's first pair
+            tiles_out[p0 + q] = n_tiles;
+            vals_out[p0 + q] = 0u;
+            continue;
+        }
+        const uint32_t jy = s_ijy[pos], lohi = s_ilohi[pos];
+        const uint32_t e = s_e[jy & 0xFFFFu], ty = jy >> 16;
+        const ViewInfo vi = vt[e / (uint64_t)n];
+        const uint32_t tx = kth_alive(rowbits + (size_t)(vi.row_base + ty) * row_words, lohi & 0xFFFFu, lohi >> 16,
+                                      (uint32_t)(q - s_ist[pos]));
+        uint32_t tile = vi.tile_base + ty * (uint32_t)vi.tiles_x + tx;
+        if (cull.enabled) {   // a culled pair gets the out-of-range tile id: the tile sort leaves it out
+            const Record* rp = cull.rec + e;
+            if (!tile_may_contribute(rp->a, make_float2(rp->b.x, rp->b.y), vi, tx, ty, cull)) tile = n_tiles;
+        }
+        tiles_out[p0 + q] = tile;
+        vals_out[p0 + q] = e;
     }
 }
 
 // One wave per global tile row: the first and last column whose tile is still alive.
 __global__ __launch_bounds__(64) void k_alive_rows(const ViewInfo* __restrict__ vt, int32_t views,
                                                   const uint32_t* __restrict__ alive, uint2* __restrict__ rowspan,
-                                                  uint64_t* __restrict__ rowbits, uint32_t row_words,
-                                                  uint32_t* __restrict__ large_count) {
+                                                  uint64_t* __restrict__ rowbits, uint32_t row_words) {
     const uint32_t r = blockIdx.x;
-    if (r == 0 && threadIdx.x == 0) *large_count = 0;   // the coming phase's list of large rectangles
     int v = 0;
     while (v + 1 < views && r >= vt[v + 1].row_base) ++v;
     const ViewInfo vi = vt[v];
@@ -549,12 +602,6 @@ __global__ __launch_bounds__(kBlock) void k_export(const uint2* __restrict__ ran
     }
 }
 
-// Workgroups of the one-wave-per-entry kernels: they loop over the list.
-unsigned large_grid(int64_t nv) {
-    const int64_t waves = nv < 4096 ? (nv > 0 ? nv : 1) : 4096;
-    return (unsigned)((waves + kBlock / 64 - 1) / (kBlock / 64));
-}
-
 }  // namespace
 
 hipError_t launch_view_table(const ViewTable& t, int phases, ViewInfo* dst, SavedHeader* hdr, hipStream_t s) {
@@ -574,7 +621,7 @@ hipError_t launch_phase_count(const uint32_t* order, const uint32_t* counts, con
     if (nv == 0) return hipSuccess;
     const unsigned grid = (unsigned)((nv + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_phase_count, dim3(grid), dim3(kBlock), 0, s, order, counts, rects, nv, n, vt, ar.span,
-                       ar.bits, ar.words, hdr, phase, pcounts, ar.large_count, ar.large_rank);
+                       ar.bits, ar.words, hdr, phase, pcounts);
     return hipGetLastError();
 }
 
@@ -582,38 +629,40 @@ hipError_t launch_alive_rows(const ViewInfo* vt, int32_t views, int64_t rows, co
                              const AliveRows& ar, hipStream_t s) {
     if (rows == 0) return hipSuccess;
     hipLaunchKernelGGL(k_alive_rows, dim3((unsigned)rows), dim3(64), 0, s, vt, views, alive, ar.span, ar.bits,
-                       ar.words, ar.large_count);
+                       ar.words);
     return hipGetLastError();
 }
 
+int64_t count_scan_blocks(int64_t nv) { return (nv + kScanChunk - 1) / kScanChunk; }
+
 hipError_t launch_count_scan(const uint32_t* pcounts, int64_t nv, uint64_t* offsets, uint64_t* blocksums,
-                             SavedHeader* hdr, int phase, int64_t max_pairs, uint32_t* emit_start, hipStream_t s) {
-    const int nb = (int)((nv + kScanChunk - 1) / kScanChunk);
+                             SavedHeader* hdr, int phase, int64_t max_pairs, uint32_t* emit_start, uint32_t* nzr,
+                             hipStream_t s) {
+    const int nb = (int)count_scan_blocks(nv);
     const int64_t n_spans = max_pairs / kEmitSpan + 2;
-    if (nb > 0) hipLaunchKernelGGL(k_count_reduce, dim3(nb), dim3(kBlock), 0, s, pcounts, nv, hdr, phase, blocksums);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_count_reduce, dim3(nb), dim3(kBlock), 0, s, pcounts, nv, hdr, phase, blocksums, nb);
     hipLaunchKernelGGL(k_count_blocks, dim3(1), dim3(1024), 0, s, blocksums, nb, hdr, phase, max_pairs);
     if (nb > 0)
         hipLaunchKernelGGL(k_count_down, dim3(nb), dim3(kBlock), 0, s, pcounts, nv, blocksums, hdr, phase, offsets,
-                           emit_start, n_spans);
+                           emit_start, n_spans, nb, nzr);
     return hipGetLastError();
 }
 
 hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uint32_t* emit_start,
-                       const uint32_t* pcounts, const uint32_t* counts, const uint2* rects, int64_t nv, int64_t n,
-                       const ViewInfo* vt, const AliveRows& ar, const SavedHeader* hdr, int phase,
-                       int64_t max_pairs, const CullArgs& cull, uint32_t n_tiles, uint32_t* tiles_out,
-                       uint32_t* vals_out, hipStream_t s) {
+                       const uint64_t* blocksums, const uint2* rects, int64_t nv, int64_t n, const ViewInfo* vt,
+                       const AliveRows& ar, const SavedHeader* hdr, int phase, int64_t max_pairs,
+                       const CullArgs& cull, uint32_t n_tiles, uint32_t* tiles_out, uint32_t* vals_out,
+                       hipStream_t s) {
     if (nv == 0 || max_pairs == 0) return hipSuccess;
+    const unsigned grid = (unsigned)((max_pairs + kEmitSpan - 1) / kEmitSpan);
     if (phase == 0) {
-        const unsigned grid = (unsigned)((max_pairs + kEmitSpan - 1) / kEmitSpan);
         hipLaunchKernelGGL(k_emit_rects, dim3(grid), dim3(kBlock), 0, s, order, offsets, emit_start, rects, nv, n, vt,
                            hdr, phase, cull, n_tiles, tiles_out, vals_out);
     } else {
-        const unsigned grid = (unsigned)((nv + kBlock - 1) / kBlock);
-        hipLaunchKernelGGL(k_emit_alive, dim3(grid), dim3(kBlock), 0, s, order, offsets, pcounts, rects, nv, n, vt,
-                           ar.span, ar.bits, ar.words, counts, hdr, phase, cull, n_tiles, tiles_out, vals_out);
-        hipLaunchKernelGGL(k_large_emit, dim3(large_grid(nv)), dim3(kBlock), 0, s, order, offsets, pcounts, rects, n,
-                           vt, ar.span, ar.bits, ar.words, hdr, phase, cull, n_tiles, ar.large_count, ar.large_rank,
+        const uint64_t* nz_total = blocksums + 2 * count_scan_blocks(nv);
+        hipLaunchKernelGGL(k_emit_spans, dim3(grid), dim3(kBlock), 0, s, order, offsets, ar.nzr, nz_total,
+                           emit_start, rects, n, vt, ar.span, ar.bits, ar.words, hdr, phase, cull, n_tiles,
                            tiles_out, vals_out);
     }
     return hipGetLastError();

@@ -20,7 +20,7 @@ constexpr int kGrad2D = 10;              // per-(Gaussian, view) 2D gradient: m(
 // Automatic depth-phase schedule (options phases / phase0_shift = 0), chosen by measurement: one
 // view, 2 phases from the nearest 1/128 of the visible Gaussians; several views, 4 phases from
 // the nearest 1/64.
-constexpr int kAutoPhasesOneView = 2, kAutoShiftOneView = 7;
+constexpr int kAutoPhasesOneView = 2, kAutoShiftMin = 2, kAutoShiftMax = 12;
 constexpr int kAutoPhasesViews = 4, kAutoShiftViews = 6;
 // Compositing launch shape when gs_options leaves it unset (16x16 tiles).
 constexpr int kDefaultPixelsPerLaneFwd = 2;   // two waves per tile
@@ -78,7 +78,7 @@ struct Layout {
     size_t s_tfinal, s_nlast, s_done, s_cair, s_dsum, s_wsum, saved_bytes;
     // workspace offsets (bytes)
     size_t w_counts, w_rects, w_dkeys, w_dvals, w_dkeys2, w_dvals2, w_pcounts, w_offsets, w_blocksums, w_emit_start;
-    size_t w_tiles_a, w_vals_a, w_tiles_b, w_vals_b, w_hist, w_grad2d, w_medpart, w_adam, w_rowspan, w_rowbits, w_large, w_shf, workspace_bytes;
+    size_t w_tiles_a, w_vals_a, w_tiles_b, w_vals_b, w_hist, w_grad2d, w_medpart, w_adam, w_rowspan, w_rowbits, w_nzr, w_shf, workspace_bytes;
 };
 
 int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_camera* cams, Layout* L);
@@ -147,16 +147,13 @@ struct CullArgs {
 };
 
 // Per global tile row, after a phase: the first and last alive column (x > y when the row has
-// none), and bit masks of the alive columns (`words` 64-bit words per row).  Entries of a later
-// phase whose rectangle has more than kLargeRect tiles are counted and emitted by one wave each,
-// from a list of their depth ranks (`large_count` entries, emptied by launch_alive_rows).
-constexpr uint32_t kLargeRect = 256;
+// none), and bit masks of the alive columns (`words` 64-bit words per row); and the compact list
+// of a later phase's entries with pairs (depth ranks, in depth order).
 struct AliveRows {
     uint2* span;
     uint64_t* bits;
     uint32_t words;
-    uint32_t* large_count;
-    uint32_t* large_rank;   // [nv]
+    uint32_t* nzr;   // [nv]
 };
 hipError_t launch_phase_count(const uint32_t* order, const uint32_t* counts, const uint2* rects, int64_t nv,
                               int64_t n, const ViewInfo* vt, const AliveRows& ar,
@@ -164,17 +161,20 @@ hipError_t launch_phase_count(const uint32_t* order, const uint32_t* counts, con
 hipError_t launch_alive_rows(const ViewInfo* vt, int32_t views, int64_t rows, const uint32_t* alive,
                              const AliveRows& ar, hipStream_t s);
 // Exclusive scan of pcounts into offsets (u64) and the phase's pair count and base in hdr (with the
-// capacity check), and for each emission span of 1024 pairs the entry that owns its first pair.
+// capacity check); for each emission span of 1024 pairs the entry that owns its first pair (its
+// depth rank in phase 0, its position in the compact list `nzr` of entries with pairs later).
+// blocksums holds 2 count_scan_blocks(nv) + 1 values; the last is the length of that list.
+int64_t count_scan_blocks(int64_t nv);
 hipError_t launch_count_scan(const uint32_t* pcounts, int64_t nv, uint64_t* offsets, uint64_t* blocksums,
-                             SavedHeader* hdr, int phase, int64_t max_pairs, uint32_t* emit_start, hipStream_t s);
-// Phase 0 writes every pair of each rectangle, a culled pair with the tile id n_tiles (sorted
-// after every real tile and skipped by the commit); later phases write only the pairs of alive,
-// unculled tiles.
+                             SavedHeader* hdr, int phase, int64_t max_pairs, uint32_t* emit_start, uint32_t* nzr,
+                             hipStream_t s);
+// Phase 0 writes every pair of each rectangle, later phases the pairs of the alive tiles; a culled
+// pair gets the tile id n_tiles, which the tile sort's first pass leaves out.
 hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uint32_t* emit_start,
-                       const uint32_t* pcounts, const uint32_t* counts, const uint2* rects, int64_t nv, int64_t n,
-                       const ViewInfo* vt, const AliveRows& ar, const SavedHeader* hdr, int phase,
-                       int64_t max_pairs, const CullArgs& cull, uint32_t n_tiles, uint32_t* tiles_out,
-                       uint32_t* vals_out, hipStream_t s);
+                       const uint64_t* blocksums, const uint2* rects, int64_t nv, int64_t n, const ViewInfo* vt,
+                       const AliveRows& ar, const SavedHeader* hdr, int phase, int64_t max_pairs,
+                       const CullArgs& cull, uint32_t n_tiles, uint32_t* tiles_out, uint32_t* vals_out,
+                       hipStream_t s);
 // Copy the phase's tile-sorted values behind the earlier phases' and record its tile ranges.
 hipError_t launch_commit(const uint32_t* sorted_tiles, const uint32_t* sorted_vals, const SavedHeader* hdr,
                          int phase, int64_t tiles, int64_t max_pairs, uint32_t* vals, uint2* ranges, hipStream_t s);

@@ -32,7 +32,7 @@ class RasterConfig:
     kappa: float = 11.1
     depth_mode: int = 0
     tile_cull: bool = True            # drop (Gaussian, tile) pairs that cannot reach alpha_min
-    phases: int = 0                   # 0 = automatic by view count (the library's gs_schedule)
+    phases: int = 0                   # 0 = automatic (the library's gs_schedule)
     phase0_shift: int = 0             # 0 = automatic
     max_pairs: int = 1 << 22
 
@@ -121,11 +121,11 @@ class Rasterizer:
     def tile_count(self) -> int:
         return int(N.lib().gs_tile_count(ctypes.byref(self.config.to_c()), self.n_views, self.host_cams))
 
-    def schedule(self):
-        """(phases, phase0_shift) the library uses for this configuration and these views."""
+    def schedule(self, n: int):
+        """(phases, phase0_shift) the library uses for n Gaussians, this configuration and these views."""
         p, sh = ctypes.c_int32(), ctypes.c_int32()
-        N.check("gs_schedule", N.lib().gs_schedule(ctypes.byref(self.config.to_c()), self.n_views, self.host_cams,
-                                                   ctypes.byref(p), ctypes.byref(sh)))
+        N.check("gs_schedule", N.lib().gs_schedule(ctypes.byref(self.config.to_c()), int(n), self.n_views,
+                                                   self.host_cams, ctypes.byref(p), ctypes.byref(sh)))
         return p.value, sh.value
 
     # ---------------------------------------------------------------- buffers

@@ -60,22 +60,35 @@ def test_default_options_and_version():
 
 
 def test_schedule_automatic_and_explicit():
-    """phases / phase0_shift = 0 resolve by view count (2 phases from the nearest 1/128 for one view,
-    4 from the nearest 1/64 for several); explicit values pass through; out-of-range ones are rejected."""
+    """phases / phase0_shift = 0 resolve automatically: one view bins first the nearest ~1 Gaussian
+    per tile (shift = log2 of Gaussians per tile, rounded, clamped to 2..12) in 2 phases; several
+    views use 4 phases from the nearest 1/64.  Explicit values pass through; out-of-range ones are
+    rejected."""
     sc = synth.make_scene(3, n=10, n_views=3, view_sizes=[(96, 64), (130, 77), (64, 64)])
     cams = N.camera_array(sc.cameras)
     o = N.default_options()
     assert (o.phases, o.phase0_shift) == (0, 0)
     p, sh = ctypes.c_int32(), ctypes.c_int32()
-    assert N.lib().gs_schedule(ctypes.byref(o), 1, cams, ctypes.byref(p), ctypes.byref(sh)) == 0
-    assert (p.value, sh.value) == (2, 7)
-    assert N.lib().gs_schedule(ctypes.byref(o), 3, cams, ctypes.byref(p), ctypes.byref(sh)) == 0
-    assert (p.value, sh.value) == (4, 6)
+
+    def sched(n, views):
+        assert N.lib().gs_schedule(ctypes.byref(o), n, views, cams, ctypes.byref(p), ctypes.byref(sh)) == 0
+        return p.value, sh.value
+
+    tiles = 6 * 4   # the first view, 96x64 in 16x16 tiles
+    assert sched(tiles * 128, 1) == (2, 7)
+    assert sched(tiles * 45, 1) == (2, 5)          # log2(45) = 5.49
+    assert sched(tiles * 46, 1) == (2, 6)          # log2(46) = 5.52
+    assert sched(0, 1) == (2, 2) and sched(10, 1) == (2, 2)
+    assert sched(tiles << 20, 1) == (2, 12)
+    assert sched(10, 3) == (4, 6) and sched(1 << 24, 3) == (4, 6)
+    assert N.lib().gs_schedule(ctypes.byref(o), 100, 1, cams, None, None) == 0
     o.phases, o.phase0_shift = 3, 5
-    assert N.lib().gs_schedule(ctypes.byref(o), 3, cams, ctypes.byref(p), ctypes.byref(sh)) == 0
-    assert (p.value, sh.value) == (3, 5)
+    assert sched(tiles * 128, 1) == (3, 5) and sched(10, 3) == (3, 5)
     o.phases = 9
-    assert N.lib().gs_schedule(ctypes.byref(o), 3, cams, ctypes.byref(p), ctypes.byref(sh)) == \
+    assert N.lib().gs_schedule(ctypes.byref(o), 10, 3, cams, ctypes.byref(p), ctypes.byref(sh)) == \
+        N.GS_ERR_INVALID_ARGUMENT
+    o.phases, o.phase0_shift = 0, 0
+    assert N.lib().gs_schedule(ctypes.byref(o), -1, 1, cams, ctypes.byref(p), ctypes.byref(sh)) == \
         N.GS_ERR_INVALID_ARGUMENT
 
 
