@@ -116,15 +116,19 @@ def kernel_bytes(name: str, n: int, views: int, K: int, P: int, tiles: int, ncoe
         # outputs + saved state per pixel; the gathered records of traversed pairs are cache-resident
         "composite_fwd": (P * (12 + 4 + 4) + P * 29 + tiles * 8) / per_step,
         "composite_bwd": P * (12 + 28) + NV * 40 + tiles * 36,
-        # parameters and 2D gradients read, gradients written.  With the Adam step fused in and several
-        # views: moments read, parameters and moments written instead of the gradients (+ 16 B of
-        # activated copies).  One view: the non-SH parameters read; log-scales, quaternions and
-        # logits (8 scalars) stepped there; 10 planes written for adam_sh.
-        "project_bwd": (param + NV * 40 + param) if not fused else (
-            (3 * param + NV * 40 + 3 * param + n * 16) if views > 1 else
-            (nsh0 + NV * 40 + n * 8 * 4 * 5 + n * 16 + n * 40)),
+        # the parameters and the 2D gradients read.  One view without Adam: every gradient
+        # written.  With the Adam step fused in: log-scales, quaternions and logits (8 scalars)
+        # stepped there (+ 16 B of activated copies), and 10 planes written for adam_sh (one view;
+        # the SH coefficients are not read).  Several views: the SH part runs in sh_views; the
+        # non-SH parameters read, the 8 gradients (or steps) and 3 + 3 views planes written.
+        "project_bwd": (param + NV * 40 + param) if (not fused and views == 1) else (
+            (nsh0 + NV * 40 + (n * 8 * 4 * 5 + n * 16 if fused else n * 32) + n * (3 + 3 * views) * 4)
+            if views > 1 else (nsh0 + NV * 40 + n * 8 * 4 * 5 + n * 16 + n * 40)),
         # SH coefficients and the means with their moments read and written, 10 planes read
         "adam_sh": n * (3 * ncoef * 24 + 3 * 24 + 40),
+        # means and the 3 + 3 views planes read; SH coefficients and means with their moments read
+        # and written (fused), or the SH coefficients read and the SH and means gradients written
+        "sh_views": n * (12 + (3 + 3 * views) * 4 + (3 * ncoef * 24 + 3 * 24 if fused else 3 * ncoef * 8 + 12)),
         "zero_grad2d": NV * 40,
         "medium_reduce": tiles * 36,
     }
@@ -268,7 +272,7 @@ def batched_compare(args, dev):
 
 KERNELS = ["project_fwd", "depth_sort_hist", "depth_sort_scan", "depth_sort_scatter", "alive_rows", "phase_count",
            "count_scan", "emit", "tile_sort_hist", "tile_sort_scan", "tile_sort_scatter", "commit", "composite_fwd",
-           "zero_grad2d", "composite_bwd", "medium_reduce", "project_bwd", "adam_sh"]
+           "zero_grad2d", "composite_bwd", "medium_reduce", "project_bwd", "adam_sh", "sh_views"]
 
 
 def read_timer(N, timer):

@@ -154,7 +154,8 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     L->w_rowspan = w.take(rows * 8);           // alive columns per tile row (later depth phases)
     L->w_rowbits = w.take((size_t)rows * L->row_words * 8);   // and their bit masks
     L->w_nzr = w.take(nv * 4);                 // later phases: the entries with pairs, in depth order
-    L->w_shf = w.take(n_views == 1 ? (size_t)n * kShf * 4 : 0);   // SH-gradient factors etc. (fused Adam)
+    // the split SH adjoint's planes (one view: fused Adam only)
+    L->w_shf = w.take((size_t)n * (n_views == 1 ? kShf : 3 + 3 * (size_t)n_views) * 4);
     L->workspace_bytes = w.at;
     return GS_OK;
 }
@@ -398,8 +399,17 @@ int gs_render_backward(const gs_options* opts, const gs_gaussians* g, int32_t n_
     GS_TRY(launch_medium_reduce(vt, n_views, medpart, grad_medium, nullptr, 0.f, 0.f, 0.f, nullptr, s));
     timer_end(T, s);
     timer_begin(T, "project_bwd", s);
-    GS_TRY(launch_project_bwd(*g, n_views, dev_cams, o, grad2d, at<Record>(saved, L.s_records), *grads, s));
+    float* planes = at<float>(workspace, L.w_shf);
+    GS_TRY(launch_project_bwd(*g, n_views, dev_cams, o, grad2d, at<Record>(saved, L.s_records), *grads, planes, s));
     timer_end(T, s);
+    if (n_views > 1) {
+        AdamFused none;
+        memset(&none, 0, sizeof(none));
+        none.shf = planes;
+        timer_begin(T, "sh_views", s);
+        GS_TRY(launch_sh_views(*g, n_views, dev_cams, *grads, none, 0, s));
+        timer_end(T, s);
+    }
     return GS_OK;
 }
 
@@ -462,14 +472,20 @@ int gs_render_backward_adam(const gs_options* opts, const gs_gaussians* g, int32
     ad.b2 = beta2;
     ad.eps = eps;
     ad.bc = bc;
-    // one view: the SH gradient is an outer product; its Adam step runs from the factors
-    ad.shf = n_views == 1 ? at<float>(workspace, L.w_shf) : nullptr;
+    // the SH part of the adjoint and the SH and means steps run from planes the adjoint stores
+    ad.shf = at<float>(workspace, L.w_shf);
     timer_begin(T, "project_bwd", s);
     GS_TRY(launch_project_bwd_adam(*g, n_views, dev_cams, o, grad2d, at<Record>(saved, L.s_records), ad, s));
     timer_end(T, s);
-    if (ad.shf) {
+    if (n_views == 1) {
         timer_begin(T, "adam_sh", s);
         GS_TRY(launch_adam_sh(n, g->sh_degree, ad, s));
+        timer_end(T, s);
+    } else {
+        gs_gaussian_grads none;
+        memset(&none, 0, sizeof(none));
+        timer_begin(T, "sh_views", s);
+        GS_TRY(launch_sh_views(*g, n_views, dev_cams, none, ad, 1, s));
         timer_end(T, s);
     }
     return GS_OK;

@@ -9,7 +9,7 @@
 namespace gs {
 
 constexpr int kBlock = 256;              // threads per workgroup for 1D kernels (4 wave64)
-constexpr int kSortItems = 8;            // keys per thread per radix tile
+constexpr int kSortItems = 8;            // keys per thread per radix tile (16 or 32 measured slower)
 constexpr int kSortTile = kBlock * kSortItems;
 constexpr int kRadixBits = 8;             // digit width of most radix passes
 constexpr int kRadix = 1 << kRadixBits;
@@ -90,8 +90,11 @@ hipError_t launch_project_fwd(const gs_gaussians& g, int32_t views, const gs_cam
                               const gs_options& o, Record* rec, uint32_t* counts, uint2* rects,
                               uint32_t* depth_keys, uint32_t* dkeys_sort, uint32_t* dvals_sort,
                               SavedHeader* hdr, hipStream_t s);
+// The projection adjoint; with several views `planes` (3 + 3 views floats per Gaussian) receives
+// what launch_sh_views needs, and the means' and SH gradients are written by launch_sh_views.
 hipError_t launch_project_bwd(const gs_gaussians& g, int32_t views, const gs_camera* cams, const gs_options& o,
-                              const float* grad2d, const Record* rec, gs_gaussian_grads grads, hipStream_t s);
+                              const float* grad2d, const Record* rec, gs_gaussian_grads grads, float* planes,
+                              hipStream_t s);
 
 // One Adam step (Sec. Optimization) of one scalar: moments updated in place, returns the new
 // parameter.  ibc1, ibc2 = 1 / (1 - beta^t).  The step divides by sqrt(v_hat) + eps through the
@@ -105,10 +108,12 @@ __device__ __forceinline__ float adam_update(float p, float g, float& m, float& 
 
 // Adam applied inside the projection adjoint: groups means, log-scales (exp), quaternions,
 // opacity logits (sigmoid), SH, in this order; bc = device [2] bias corrections of this step.
-// With shf set (one view only), the adjoint steps the log-scales, quaternions and opacity logits
-// and stores, for launch_adam_sh, shf = [kShf][n] planes: view direction x, y, z; colour
-// gradient of the unclamped channels r, g, b; inverse distance to the camera centre; the means'
-// gradient without its term through the SH colour.
+// With shf set, the adjoint steps the log-scales, quaternions and opacity logits and stores:
+// one view, for launch_adam_sh, shf = [kShf][n] planes: view direction x, y, z; colour gradient
+// of the unclamped channels r, g, b; inverse distance to the camera centre; the means' gradient
+// without its term through the SH colour.  Several views, for launch_sh_views, shf = [3 + 3
+// views][n] planes: the means' gradient without its SH term, then per view the colour gradient
+// of the unclamped channels (zero where the Gaussian has no gradient in that view).
 struct AdamFused {
     gs_adam_group g[5];
     float b1, b2, eps;
@@ -123,6 +128,12 @@ constexpr int kShf = 10;
 // the gradient of SH coefficient k, channel c is Y_k(dir) gc_c, as the adjoint forms it, and the
 // means' gradient gets its SH term here, from the coefficients before their update.
 hipError_t launch_adam_sh(int64_t n, int sh_degree, const AdamFused& adam, hipStream_t s);
+// Several views: the SH part of the adjoint from adam.shf (see AdamFused).  fused: Adam steps of
+// the SH coefficients and the means; otherwise their gradients into grads.sh and grads.means.
+// Gaussians per lane when n and the bases allow 4 W-byte accesses (2 measured faster than 1 or 4)
+constexpr int kShViewsW = 2;
+hipError_t launch_sh_views(const gs_gaussians& g, int32_t views, const gs_camera* cams,
+                           const gs_gaussian_grads& grads, const AdamFused& adam, int fused, hipStream_t s);
 // step += 1 and bc = (1 / (1 - b1^step), 1 / (1 - b2^step)) on the device.
 hipError_t launch_adam_prep(int32_t* step, float b1, float b2, float* bc, hipStream_t s);
 // Stable LSD radix sort of (key, value) u32 pairs over bits [bit0, bit0+nbits).  n is read from n_dev

@@ -296,15 +296,18 @@ __global__ __launch_bounds__(kBlock) void k_project_fwd(gs_gaussians g, int32_t 
 // The SH gradient of one view is the outer product Y(dir) x (colour gradient of the
 // unclamped channels).  With one view (ONE) the kernel keeps those 16 + 3 factors instead of
 // 48 accumulators, which bounds its register use; the clamp of each channel is read from the
-// forward's record (a clamped channel holds -0).
+// forward's record (a clamped channel holds -0).  With several views the SH part runs in
+// k_sh_views: this kernel stores, in adam.shf, the means' gradient without its SH term and each
+// view's colour gradient of the unclamped channels (zero for a view the Gaussian misses).
 template <int DEG, bool FUSED, bool ONE, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t views, const gs_camera* cams,
                                                        float dil, const float* __restrict__ grad2d,
                                                        const Record* __restrict__ rec, gs_gaussian_grads out,
                                                        AdamFused adam) {
-    static_assert(!SPLIT || (FUSED && ONE), "the split Adam step exists for one view only");
+    static_assert(ONE || SPLIT, "several views: the SH part runs in k_sh_views");
+    static_assert(!(ONE && SPLIT) || FUSED, "one view: the split is the fused Adam path");
     constexpr int NC = (DEG + 1) * (DEG + 1);
-    constexpr int NACC = ONE ? 1 : NC * 3;
+    constexpr bool MULTI = !ONE;
     const int64_t n = g.n;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -312,10 +315,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
     const float s[3] = {g.scales[i], g.scales[n + i], g.scales[2 * n + i]};
     const float qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
     float gmu[3] = {0.f, 0.f, 0.f}, gsc[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, gop = 0.f;
-    float gsh[NACC];      // several views: SH gradient accumulators
     float Y1[16], gc1[3], dir1[3], il1 = 0.f;  // one view: the factors of its SH gradient
-#pragma unroll
-    for (int k = 0; k < NACC; ++k) gsh[k] = 0.f;
 #pragma unroll
     for (int k = 0; k < 16; ++k) Y1[k] = 0.f;
     gc1[0] = gc1[1] = gc1[2] = 0.f;
@@ -329,7 +329,13 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
             G[k] = gg[k];
             any = any || (G[k] != 0.0f);
         }
-        if (!any) continue;
+        if (!any) {
+            if (MULTI) {
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) adam.shf[(int64_t)(3 + 3 * v + ch) * n + i] = 0.0f;
+            }
+            continue;
+        }
         const Cam c = load_cam(cams + v);
         Proj P;
         key_path(c, mx, my, mz, s[0], s[1], s[2], qw, qx, qy, qz, dil, P);
@@ -410,6 +416,11 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
             gce[ch] = signbit(col[ch]) ? 0.0f : G[6 + ch];
             live = live || gce[ch] != 0.0f;
         }
+        if (MULTI) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) adam.shf[(int64_t)(3 + 3 * v + ch) * n + i] = gce[ch];
+            continue;
+        }
         if (!live) continue;
         float cc[3];
         camera_centre(c, cc);
@@ -418,21 +429,14 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
         d0 *= il; d1 *= il; d2 *= il;
         float Y[16];
         sh_eval<DEG>(d0, d1, d2, Y);
-        if (ONE) {
 #pragma unroll
-            for (int k = 0; k < 16; ++k) Y1[k] = Y[k];
+        for (int k = 0; k < 16; ++k) Y1[k] = Y[k];
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) gc1[ch] = gce[ch];
-            dir1[0] = d0;
-            dir1[1] = d1;
-            dir1[2] = d2;
-            il1 = il;
-        } else {
-#pragma unroll
-            for (int k = 0; k < NC; ++k)
-#pragma unroll
-                for (int ch = 0; ch < 3; ++ch) gsh[(3 * k + ch) % NACC] += Y[k] * gce[ch];
-        }
+        for (int ch = 0; ch < 3; ++ch) gc1[ch] = gce[ch];
+        dir1[0] = d0;
+        dir1[1] = d1;
+        dir1[2] = d2;
+        il1 = il;
         if (DEG > 0 && !SPLIT) {   // split: k_adam_sh adds this term, reading the SH coefficients once
             float wk[16];
 #pragma unroll
@@ -453,16 +457,24 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
             gmu[2] += (gd[2] - d2 * dd) * il;
         }
     }
-    // SH gradient element j = 3 k + channel
-    auto shg = [&](int j) { return ONE ? Y1[j / 3] * gc1[j % 3] : gsh[j % NACC]; };
+    // SH gradient element j = 3 k + channel (one view)
+    auto shg = [&](int j) { return Y1[j / 3] * gc1[j % 3]; };
+    if (MULTI) {   // k_sh_views adds the SH term
+#pragma unroll
+        for (int k = 0; k < 3; ++k) adam.shf[(int64_t)k * n + i] = gmu[k];
+    }
     if (!FUSED) {
-        out.means[i] = gmu[0]; out.means[n + i] = gmu[1]; out.means[2 * n + i] = gmu[2];
+        if (!MULTI) {
+            out.means[i] = gmu[0]; out.means[n + i] = gmu[1]; out.means[2 * n + i] = gmu[2];
+        }
         out.scales[i] = gsc[0]; out.scales[n + i] = gsc[1]; out.scales[2 * n + i] = gsc[2];
 #pragma unroll
         for (int k = 0; k < 4; ++k) out.quats[(int64_t)k * n + i] = gq[k];
         out.opacity[i] = gop;
+        if (!MULTI) {
 #pragma unroll
-        for (int k = 0; k < NC * 3; ++k) out.sh[(int64_t)k * n + i] = shg(k);
+            for (int k = 0; k < NC * 3; ++k) out.sh[(int64_t)k * n + i] = shg(k);
+        }
         return;
     }
     const float ibc1 = adam.bc[0], ibc2 = adam.bc[1];
@@ -498,6 +510,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
         const float nx = step(adam.g[3], i, gop * (o * (1.0f - o)));
         __builtin_nontemporal_store(1.0f / (1.0f + expf(-nx)), adam.g[3].activated + i);
     }
+    if (MULTI) return;   // the means' and the SH coefficients' steps run in k_sh_views
     if (SPLIT) {   // the means' and the SH coefficients' steps run in k_adam_sh from these
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -638,6 +651,153 @@ __global__ __launch_bounds__(kBlock) void k_adam_sh(int64_t n, AdamFused adam) {
     __builtin_nontemporal_store(v, reinterpret_cast<VW*>(M.v + j));
 }
 
+// Several views: the SH part of the adjoint and, when fused, the Adam steps of the SH
+// coefficients and the means, from what k_project_bwd stored in adam.shf (the means' gradient
+// without its SH term, then per view the colour gradient of the unclamped channels).  View v's
+// direction is formed again from the mean and the camera centre, as the adjoint forms it.  The
+// gradient of SH coefficient k, channel c is the sum over the views, in order, of Y_k(dir) gc_c;
+// the means' SH term is, per view, sum_k (sum_c gc_c sh_kc) grad Y_k(dir) projected on the plane
+// normal to dir and scaled by the inverse distance, with the coefficients before their update.
+// A workgroup's four waves share 64 groups of W Gaussians: wave s handles coefficients s, s + 4,
+// ... and that part of the means' term; the parts meet in LDS, ((0 + 1) + 2) + 3, and wave q < 3
+// finishes coordinate q of the means.  Without FUSED the gradients are written instead.
+template <int DEG, int W, bool FUSED>
+__global__ __launch_bounds__(kBlock) void k_sh_views(gs_gaussians g, int32_t views, const gs_camera* cams,
+                                                    gs_gaussian_grads out, AdamFused adam) {
+    using VW = float __attribute__((ext_vector_type(W)));
+    static_assert(kBlock == 256, "four waves per workgroup");
+    constexpr int NC = (DEG + 1) * (DEG + 1);
+    constexpr int KS = (NC + 3) / 4;   // coefficients per wave, at most
+    __shared__ float sP[4][3][W][64];
+    const int64_t n = g.n;
+    const int sub = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t i0 = ((int64_t)blockIdx.x * 64 + lane) * W;
+    const bool active = i0 < n;   // lanes past the end still meet the barrier
+    const float* f = adam.shf;
+    auto vload = [&](const float* base, int64_t q) { return *reinterpret_cast<const VW*>(base + q * n + i0); };
+    if (active) {
+        float mu[3][W], co[KS][3][W], gs[KS][3][W], R[W][3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const VW x = vload(g.means, q);
+#pragma unroll
+            for (int w = 0; w < W; ++w) mu[q][w] = x[w];
+        }
+#pragma unroll
+        for (int j = 0; j < KS; ++j) {
+            const int k = sub + 4 * j;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                VW x = {};
+                if (k < NC) x = vload(g.sh, 3 * k + c);
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    co[j][c][w] = x[w];
+                    gs[j][c][w] = 0.f;
+                }
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) R[w][0] = R[w][1] = R[w][2] = 0.f;
+        for (int v = 0; v < views; ++v) {
+            const Cam cam = load_cam(cams + v);
+            float cc[3];
+            camera_centre(cam, cc);
+            const VW c0 = vload(f, 3 + 3 * v), c1 = vload(f, 4 + 3 * v), c2 = vload(f, 5 + 3 * v);
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const float gce[3] = {c0[w], c1[w], c2[w]};
+                if (gce[0] == 0.0f && gce[1] == 0.0f && gce[2] == 0.0f) continue;
+                float d0 = mu[0][w] - cc[0], d1 = mu[1][w] - cc[1], d2 = mu[2][w] - cc[2];
+                const float il = 1.0f / __builtin_sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+                d0 *= il; d1 *= il; d2 *= il;
+                float Q[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                for (int j = 0; j < KS; ++j) {
+                    const int k = sub + 4 * j;
+                    if (k >= NC) break;
+                    const float Yk = sh_basis(k, d0, d1, d2);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) gs[j][c][w] += Yk * gce[c];
+                    if (DEG > 0) {
+                        const float wk = (gce[0] * co[j][0][w] + gce[1] * co[j][1][w]) + gce[2] * co[j][2][w];
+                        sh_grad_add(k, d0, d1, d2, wk, Q[0], Q[1], Q[2]);
+                    }
+                }
+                if (DEG > 0) {
+                    const float dd = Q[0] * d0 + Q[1] * d1 + Q[2] * d2;
+                    R[w][0] += (Q[0] - d0 * dd) * il;
+                    R[w][1] += (Q[1] - d1 * dd) * il;
+                    R[w][2] += (Q[2] - d2 * dd) * il;
+                }
+            }
+        }
+        const float ibc1 = FUSED ? adam.bc[0] : 0.f, ibc2 = FUSED ? adam.bc[1] : 0.f;
+#pragma unroll
+        for (int j = 0; j < KS; ++j) {
+            const int k = sub + 4 * j;
+            if (k >= NC) break;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int64_t idx = (int64_t)(3 * k + c) * n + i0;
+                VW r;
+                if (FUSED) {
+                    const gs_adam_group& G = adam.g[4];
+                    VW m = __builtin_nontemporal_load(reinterpret_cast<const VW*>(G.m + idx));
+                    VW v = __builtin_nontemporal_load(reinterpret_cast<const VW*>(G.v + idx));
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        float mw = m[w], vw = v[w];
+                        r[w] = adam_update(co[j][c][w], gs[j][c][w], mw, vw, G.lr, adam.b1, adam.b2, adam.eps,
+                                           ibc1, ibc2);
+                        m[w] = mw;
+                        v[w] = vw;
+                    }
+                    __builtin_nontemporal_store(r, reinterpret_cast<VW*>(G.param + idx));
+                    __builtin_nontemporal_store(m, reinterpret_cast<VW*>(G.m + idx));
+                    __builtin_nontemporal_store(v, reinterpret_cast<VW*>(G.v + idx));
+                } else {
+#pragma unroll
+                    for (int w = 0; w < W; ++w) r[w] = gs[j][c][w];
+                    *reinterpret_cast<VW*>(out.sh + idx) = r;
+                }
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) sP[sub][q][w][lane] = R[w][q];
+    }
+    __syncthreads();
+    if (!active || sub == 3) return;
+    const int q = sub;
+    const VW gpart = vload(f, q);
+    VW r;
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+        r[w] = gpart[w] + (((sP[0][q][w][lane] + sP[1][q][w][lane]) + sP[2][q][w][lane]) + sP[3][q][w][lane]);
+    const int64_t j = (int64_t)q * n + i0;
+    if (FUSED) {
+        const gs_adam_group& M = adam.g[0];
+        const float ibc1 = adam.bc[0], ibc2 = adam.bc[1];
+        VW p = __builtin_nontemporal_load(reinterpret_cast<const VW*>(M.param + j));
+        VW m = __builtin_nontemporal_load(reinterpret_cast<const VW*>(M.m + j));
+        VW v = __builtin_nontemporal_load(reinterpret_cast<const VW*>(M.v + j));
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            float mw = m[w], vw = v[w];
+            p[w] = adam_update(p[w], r[w], mw, vw, M.lr, adam.b1, adam.b2, adam.eps, ibc1, ibc2);
+            m[w] = mw;
+            v[w] = vw;
+        }
+        __builtin_nontemporal_store(p, reinterpret_cast<VW*>(M.param + j));
+        __builtin_nontemporal_store(m, reinterpret_cast<VW*>(M.m + j));
+        __builtin_nontemporal_store(v, reinterpret_cast<VW*>(M.v + j));
+    } else {
+        *reinterpret_cast<VW*>(out.means + j) = r;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_adam_sh(int64_t n, int sh_degree, const AdamFused& adam, hipStream_t s) {
@@ -662,6 +822,41 @@ hipError_t launch_adam_sh(int64_t n, int sh_degree, const AdamFused& adam, hipSt
         default: GS_ASH(3); break;
     }
 #undef GS_ASH
+    return hipGetLastError();
+}
+
+hipError_t launch_sh_views(const gs_gaussians& g, int32_t views, const gs_camera* cams,
+                           const gs_gaussian_grads& grads, const AdamFused& adam, int fused, hipStream_t s) {
+    const int64_t n = g.n;
+    if (n == 0) return hipSuccess;
+    if (!adam.shf || views < 2) return hipErrorInvalidValue;
+    uintptr_t bases = (uintptr_t)adam.shf | (uintptr_t)g.means | (uintptr_t)g.sh;
+    if (fused)
+        bases |= (uintptr_t)adam.g[4].param | (uintptr_t)adam.g[4].m | (uintptr_t)adam.g[4].v |
+                 (uintptr_t)adam.g[0].param | (uintptr_t)adam.g[0].m | (uintptr_t)adam.g[0].v;
+    else
+        bases |= (uintptr_t)grads.sh | (uintptr_t)grads.means;
+    const int per = (n % kShViewsW == 0 && bases % (4 * kShViewsW) == 0) ? kShViewsW : 1;
+    const unsigned grid = (unsigned)(((n + per - 1) / per + 63) / 64);   // 64 groups of `per` per workgroup
+#define GS_SHV(D, WW)                                                                                          \
+    if (fused)                                                                                                 \
+        hipLaunchKernelGGL((k_sh_views<D, WW, true>), dim3(grid), dim3(kBlock), 0, s, g, views, cams, grads, adam); \
+    else                                                                                                       \
+        hipLaunchKernelGGL((k_sh_views<D, WW, false>), dim3(grid), dim3(kBlock), 0, s, g, views, cams, grads, adam)
+#define GS_SHVD(D)            \
+    if (per == kShViewsW) {   \
+        GS_SHV(D, kShViewsW); \
+    } else {                  \
+        GS_SHV(D, 1);         \
+    }
+    switch (g.sh_degree) {
+        case 0: GS_SHVD(0); break;
+        case 1: GS_SHVD(1); break;
+        case 2: GS_SHVD(2); break;
+        default: GS_SHVD(3); break;
+    }
+#undef GS_SHVD
+#undef GS_SHV
     return hipGetLastError();
 }
 
@@ -697,7 +892,7 @@ void project_bwd_launch(const gs_gaussians& g, int32_t views, const gs_camera* c
         hipLaunchKernelGGL((k_project_bwd<D, F, true, false>), dim3(grid), dim3(kBlock), 0, s, g, views, cams, dil,
                            grad2d, rec, grads, adam);
     else
-        hipLaunchKernelGGL((k_project_bwd<D, F, false, false>), dim3(grid), dim3(kBlock), 0, s, g, views, cams, dil,
+        hipLaunchKernelGGL((k_project_bwd<D, F, false, true>), dim3(grid), dim3(kBlock), 0, s, g, views, cams, dil,
                            grad2d, rec, grads, adam);
 }
 
@@ -724,9 +919,12 @@ hipError_t project_bwd(const gs_gaussians& g, int32_t views, const gs_camera* ca
 }  // namespace
 
 hipError_t launch_project_bwd(const gs_gaussians& g, int32_t views, const gs_camera* cams, const gs_options& o,
-                              const float* grad2d, const Record* rec, gs_gaussian_grads grads, hipStream_t s) {
+                              const float* grad2d, const Record* rec, gs_gaussian_grads grads, float* planes,
+                              hipStream_t s) {
     AdamFused none;
     memset(&none, 0, sizeof(none));
+    none.shf = planes;
+    if (views > 1 && !planes) return hipErrorInvalidValue;
     return project_bwd(g, views, cams, o, grad2d, rec, grads, none, 0, s);
 }
 
