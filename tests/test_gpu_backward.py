@@ -1,4 +1,6 @@
 """GPU parity of the adjoint: gradients vs the FP64 oracle gradient and FP64 central differences."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -139,9 +141,15 @@ def test_autograd_function_and_activation(oracle_mod):
     U.grad_close(med.grad.cpu().numpy().reshape(-1), ref["medium"], 1e-3, "medium")
 
 
-def test_multiview_grad_sums_views(oracle_mod):
+@pytest.mark.parametrize("n,deg", [(2000, 3), (2001, 3), (1000, 2), (1001, 1), (1000, 0)])
+def test_multiview_grad_sums_views(oracle_mod, n, deg):
+    """Several views: the gradients are the sums of the views' oracle gradients (the SH part and the
+    means' SH term come from k_sh_views; odd n takes its one-Gaussian-per-lane form).  Lower SH
+    degrees keep the first (deg + 1)^2 coefficients of the degree-3 scene."""
     O = oracle_mod
-    sc = synth.make_scene(3, n=2000, n_views=3, view_sizes=[(64, 48), (80, 40), (48, 48)])
+    sc = synth.make_scene(3, n=n, n_views=3, view_sizes=[(64, 48), (80, 40), (48, 48)])
+    if deg < 3:
+        sc = dataclasses.replace(sc, sh=np.ascontiguousarray(sc.sh[:3 * (deg + 1) ** 2]), sh_degree=deg)
     rast = U.make_rast(sc)
     rgb, depth, alpha, ctx, d = U.forward(sc, rast)
     rng = np.random.default_rng(5)
@@ -149,7 +157,7 @@ def test_multiview_grad_sums_views(oracle_mod):
     g_rgb = torch.cat([torch.from_numpy(G.T.reshape(-1).astype(np.float32)) for G in Gs]).cuda()
     out = rast.backward(ctx, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["medium"], g_rgb)
     got = dict(zip(FIELDS + ("medium",), [t.cpu().numpy().astype(np.float64) for t in out]))
-    U.say("multiview grad")
+    U.say(f"multiview grad n={n} sh degree {deg}")
     ref = {f: 0.0 for f in FIELDS}
     for v, cam in enumerate(sc.cameras):
         r = O.backward(sc, cam, sc.medium[v], Gs[v])

@@ -122,18 +122,19 @@ def _state(ts):
                                                                          else ())] for g in ts.groups}
 
 
-@pytest.mark.parametrize("views,n", [(1, 400), (1, 401), (2, 400)])
+@pytest.mark.parametrize("views,n", [(1, 400), (1, 401), (2, 400), (2, 401), (3, 402)])
 def test_fused_adam_matches_separate_kernels(views, n):
     """gs_render_backward_adam (Adam inside the projection adjoint) against gs_render_backward followed
     by gs_adam_step_device.  One 16x16 tile per view rendered by one wave accumulates every 2D gradient
     in a fixed order, so the two paths see identical gradients and must agree bit for bit.  One view
-    takes the SH step in its own kernel from the gradient's two factors; two views step every group
-    inside the projection adjoint.  n = 401 takes the SH kernel's one-Gaussian-per-thread form (the
-    16-byte form needs n % 4 == 0)."""
+    takes the SH step in its own kernel from the gradient's two factors; several views take the SH
+    part and the means' and SH steps in k_sh_views, which the gradient path also runs.  Odd n takes
+    the SH kernels' one-Gaussian-per-thread forms (the vector forms need n % 4 == 0 for one view,
+    n % 2 == 0 for several)."""
     if views == 1:
         sc = synth.make_scene(1, n=n, width=16, height=16)
     else:
-        sc = synth.make_scene(3, n=n, n_views=2, view_sizes=[(16, 16), (16, 16)])
+        sc = synth.make_scene(3, n=n, n_views=views, view_sizes=[(16, 16)] * views)
     a = _make(sc, lr_scale=1.0)
     b = TrainStepUnfused(sc)
     a.size_capacity()
