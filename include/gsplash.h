@@ -274,11 +274,15 @@ typedef struct gs_adam_group {
  * (Sec. Optimization): the adjoint of gs_render_backward, but instead of writing
  * the parameter gradients it applies one Adam step -- as gs_adam_step_device,
  * same step counter semantics -- to the raw parameters in registers, so the
- * gradients of the Gaussians never reach memory.  With one view the SH gradient
- * of a Gaussian is the outer product of the SH basis at its view direction and
- * its colour gradient: the projection adjoint then steps the other groups and
- * keeps those six factors in the workspace, and a second kernel steps the SH
- * coefficients from them.  Results equal gs_render_backward followed by
+ * gradients of the Gaussians never reach memory.  The SH gradient of a
+ * Gaussian is, per view, the outer product of the SH basis at its view
+ * direction and its colour gradient: the projection adjoint steps the other
+ * groups and keeps those factors in the workspace (one view: direction and
+ * colour gradient; several views: each view's colour gradient), and a second
+ * kernel steps the SH coefficients and the means from them (with several views
+ * gs_render_backward runs the same kernel to write those gradients).  For the
+ * same 2D gradients -- the compositing adjoint's atomic sums may differ in order
+ * from call to call -- results equal gs_render_backward followed by
  * gs_adam_step_device bit for bit.
  *   groups[6] : HOST array, in this order: means (count 3n, activation 0),
  *               log-scales (3n, activation 1, activated = the scales g->scales
