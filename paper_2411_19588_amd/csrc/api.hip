@@ -151,8 +151,7 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     L->w_grad2d = w.take(nv * kGrad2D * 4);
     L->w_medpart = w.take(T * 9 * 4 + 256);   // + persistent-mode tile counter of the backward
     L->w_adam = w.take(16);                    // bias corrections of a fused Adam step
-    L->w_rowspan = w.take(rows * 8);           // alive columns per tile row (later depth phases)
-    L->w_rowbits = w.take((size_t)rows * L->row_words * 8);   // and their bit masks
+    L->w_rowbits = w.take((size_t)rows * L->row_words * 8);   // alive columns per tile row (later phases)
     L->w_nzr = w.take(nv * 4);                 // later phases: the entries with pairs, in depth order
     // the split SH adjoint's planes (one view: fused Adam only)
     L->w_shf = w.take((size_t)n * (n_views == 1 ? kShf : 3 + 3 * (size_t)n_views) * 4);
@@ -328,7 +327,7 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
     float* dsum = at<float>(saved, L.s_dsum);
     float* wsum = at<float>(saved, L.s_wsum);
     const CullArgs cull{rec, log2f(o.alpha_min), o.tile_w, o.tile_h, o.tile_cull};
-    const AliveRows ar{at<uint2>(workspace, L.w_rowspan), at<uint64_t>(workspace, L.w_rowbits),
+    const AliveRows ar{at<uint64_t>(workspace, L.w_rowbits),
                        (uint32_t)L.row_words, at<uint32_t>(workspace, L.w_nzr)};
     for (int ph = 0; ph < L.phases; ++ph) {
         if (ph > 0) {

@@ -119,7 +119,6 @@ __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restri
                                                        const uint32_t* __restrict__ counts,
                                                        const uint2* __restrict__ rects, int64_t nv, int64_t n,
                                                        const ViewInfo* __restrict__ vt,
-                                                       const uint2* __restrict__ rowspan,
                                                        const uint64_t* __restrict__ rowbits, uint32_t row_words,
                                                        const SavedHeader* __restrict__ hdr, int phase,
                                                        uint32_t* __restrict__ pcounts) {
@@ -137,15 +136,12 @@ __global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restri
             c = counts[e];
         } else {
             // every alive tile of the rectangle (the emission marks the culled ones, as in phase 0):
-            // one popcount per 64 columns of each row's alive span
+            // one popcount per 64 columns of each row of the rectangle
             const uint2 rc = rects[e];
             const ViewInfo vi = vt[e / (uint64_t)n];
             const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
-            for (uint32_t ty = y0; ty <= y1; ++ty) {
-                const uint2 sp = rowspan[vi.row_base + ty];
-                const uint32_t lo = max(x0, sp.x), hi = min(x1, sp.y);
-                if (lo <= hi) c += alive_in(rowbits + (size_t)(vi.row_base + ty) * row_words, lo, hi);
-            }
+            for (uint32_t ty = y0; ty <= y1; ++ty)
+                c += alive_in(rowbits + (size_t)(vi.row_base + ty) * row_words, x0, x1);
         }
     }
     pcounts[r] = c;
@@ -425,7 +421,6 @@ __global__ __launch_bounds__(kBlock) void k_emit_spans(const uint32_t* __restric
                                                       const uint32_t* __restrict__ emit_start,
                                                       const uint2* __restrict__ rects, int64_t n,
                                                       const ViewInfo* __restrict__ vt,
-                                                      const uint2* __restrict__ rowspan,
                                                       const uint64_t* __restrict__ rowbits, uint32_t row_words,
                                                       const SavedHeader* __restrict__ hdr, int phase,
                                                       CullArgs cull, uint32_t n_tiles,
@@ -473,9 +468,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_spans(const uint32_t* __restric
         const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
         int32_t st = s_off[j];
         for (uint32_t ty = y0; ty <= y1 && st < span; ++ty) {
-            const uint2 sp = rowspan[vi.row_base + ty];
-            const uint32_t lo = max(x0, sp.x), hi = min(x1, sp.y);
-            if (lo > hi) continue;
+            const uint32_t lo = x0, hi = x1;
             const int32_t c = (int32_t)alive_in(rowbits + (size_t)(vi.row_base + ty) * row_words, lo, hi);
             if (c == 0) continue;
             if (st + c > 0) {
@@ -536,32 +529,21 @@ __global__ __launch_bounds__(kBlock) void k_emit_spans(const uint32_t* __restric
     }
 }
 
-// One wave per global tile row: the first and last column whose tile is still alive.
+// One wave per global tile row: the bit masks of the columns whose tile is still alive.
 __global__ __launch_bounds__(64) void k_alive_rows(const ViewInfo* __restrict__ vt, int32_t views,
-                                                  const uint32_t* __restrict__ alive, uint2* __restrict__ rowspan,
+                                                  const uint32_t* __restrict__ alive,
                                                   uint64_t* __restrict__ rowbits, uint32_t row_words) {
     const uint32_t r = blockIdx.x;
     int v = 0;
     while (v + 1 < views && r >= vt[v + 1].row_base) ++v;
     const ViewInfo vi = vt[v];
     const uint32_t ty = r - vi.row_base;
-    uint32_t lo = 0xFFFFFFFFu, hi = 0;
     for (uint32_t w = 0; w < row_words; ++w) {   // bit b of word w: column 64 w + b is alive
         const uint32_t tx = w * 64 + threadIdx.x;
         const bool a = tx < (uint32_t)vi.tiles_x && alive[vi.tile_base + ty * (uint32_t)vi.tiles_x + tx] != 0u;
         const uint64_t m = __ballot(a);
         if (threadIdx.x == 0) rowbits[(size_t)r * row_words + w] = m;
-        if (a) {
-            lo = min(lo, tx);
-            hi = max(hi, tx);
-        }
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        lo = min(lo, (uint32_t)__shfl_xor((int)lo, off));
-        hi = max(hi, (uint32_t)__shfl_xor((int)hi, off));
-    }
-    if (threadIdx.x == 0) rowspan[r] = lo == 0xFFFFFFFFu ? make_uint2(1u, 0u) : make_uint2(lo, hi);
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t* p, uint32_t value, int64_t count) {
@@ -620,7 +602,7 @@ hipError_t launch_phase_count(const uint32_t* order, const uint32_t* counts, con
                               const SavedHeader* hdr, int phase, uint32_t* pcounts, hipStream_t s) {
     if (nv == 0) return hipSuccess;
     const unsigned grid = (unsigned)((nv + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_phase_count, dim3(grid), dim3(kBlock), 0, s, order, counts, rects, nv, n, vt, ar.span,
+    hipLaunchKernelGGL(k_phase_count, dim3(grid), dim3(kBlock), 0, s, order, counts, rects, nv, n, vt,
                        ar.bits, ar.words, hdr, phase, pcounts);
     return hipGetLastError();
 }
@@ -628,7 +610,7 @@ hipError_t launch_phase_count(const uint32_t* order, const uint32_t* counts, con
 hipError_t launch_alive_rows(const ViewInfo* vt, int32_t views, int64_t rows, const uint32_t* alive,
                              const AliveRows& ar, hipStream_t s) {
     if (rows == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_alive_rows, dim3((unsigned)rows), dim3(64), 0, s, vt, views, alive, ar.span, ar.bits,
+    hipLaunchKernelGGL(k_alive_rows, dim3((unsigned)rows), dim3(64), 0, s, vt, views, alive, ar.bits,
                        ar.words);
     return hipGetLastError();
 }
@@ -662,7 +644,7 @@ hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uin
     } else {
         const uint64_t* nz_total = blocksums + 2 * count_scan_blocks(nv);
         hipLaunchKernelGGL(k_emit_spans, dim3(grid), dim3(kBlock), 0, s, order, offsets, ar.nzr, nz_total,
-                           emit_start, rects, n, vt, ar.span, ar.bits, ar.words, hdr, phase, cull, n_tiles,
+                           emit_start, rects, n, vt, ar.bits, ar.words, hdr, phase, cull, n_tiles,
                            tiles_out, vals_out);
     }
     return hipGetLastError();

@@ -78,7 +78,7 @@ struct Layout {
     size_t s_tfinal, s_nlast, s_done, s_cair, s_dsum, s_wsum, saved_bytes;
     // workspace offsets (bytes)
     size_t w_counts, w_rects, w_dkeys, w_dvals, w_dkeys2, w_dvals2, w_pcounts, w_offsets, w_blocksums, w_emit_start;
-    size_t w_tiles_a, w_vals_a, w_tiles_b, w_vals_b, w_hist, w_grad2d, w_medpart, w_adam, w_rowspan, w_rowbits, w_nzr, w_shf, workspace_bytes;
+    size_t w_tiles_a, w_vals_a, w_tiles_b, w_vals_b, w_hist, w_grad2d, w_medpart, w_adam, w_rowbits, w_nzr, w_shf, workspace_bytes;
 };
 
 int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_camera* cams, Layout* L);
@@ -157,11 +157,9 @@ struct CullArgs {
     int32_t enabled;
 };
 
-// Per global tile row, after a phase: the first and last alive column (x > y when the row has
-// none), and bit masks of the alive columns (`words` 64-bit words per row); and the compact list
-// of a later phase's entries with pairs (depth ranks, in depth order).
+// Per global tile row, after a phase: bit masks of the alive columns (`words` 64-bit words per
+// row); and the compact list of a later phase's entries with pairs (depth ranks, in depth order).
 struct AliveRows {
-    uint2* span;
     uint64_t* bits;
     uint32_t words;
     uint32_t* nzr;   // [nv]
