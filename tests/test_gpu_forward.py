@@ -319,6 +319,28 @@ def test_pair_overflow_reported_and_recovered(oracle_mod, phases):
     assert torch.equal(rgb, ref[0])
 
 
+def test_pair_overflow_in_a_later_phase():
+    """A capacity that holds exactly phase 0's stored pairs overflows in a later phase (whose pairs
+    the balanced later-phase emission writes): the status reports it, the needed count exceeds the
+    capacity, and the checked path grows the capacity and renders the reference images."""
+    sc = synth.make_scene(3, n=2000, n_views=3, view_sizes=[(64, 48), (80, 40), (48, 48)])
+    d = U.to_dev(sc)
+    args = (d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], sc.sh_degree, d["medium"])
+    U.say("pair overflow in a later phase")
+    rast = U.make_rast(sc, max_pairs=1, phases=3, phase0_shift=6)
+    _, _, _, ctx = rast.forward(*args, check=False)
+    st, need0 = rast.read_status(ctx.saved)
+    assert st & N.GS_STATUS_PAIR_OVERFLOW and need0 > 1   # phase 0's stored pairs
+    rast = U.make_rast(sc, max_pairs=need0, phases=3, phase0_shift=6)
+    _, _, _, ctx = rast.forward(*args, check=False)
+    st, need = rast.read_status(ctx.saved)
+    assert st & N.GS_STATUS_PAIR_OVERFLOW and need > need0
+    rgb, depth, alpha, ctx = rast.forward(*args)
+    assert ctx.max_pairs >= need
+    ref = U.forward(sc, U.make_rast(sc, phases=3, phase0_shift=6))[:3]
+    assert torch.equal(rgb, ref[0]) and torch.equal(depth, ref[1]) and torch.equal(alpha, ref[2])
+
+
 def test_nonfinite_input_flagged_and_culled(oracle_mod):
     sc = synth.make_scene(0, n=300, width=64, height=64)
     bad = synth.Scene(**{**sc.__dict__, "means": sc.means.copy()})
