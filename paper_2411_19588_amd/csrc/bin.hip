@@ -11,7 +11,9 @@
 // phase ranges gives exactly the (depth, index)-ordered list of full binning,
 // cut after the phase in which the tile's last pixel terminated; compositing
 // never reads past that point, so the images are identical, while scenes whose
-// near Gaussians saturate the tiles skip sorting almost every pair.
+// near Gaussians saturate the tiles skip sorting almost every pair.  Every
+// emission is balanced over output pairs: a workgroup writes a fixed span of
+// 1024 pairs, whatever the sizes of the rectangles behind them.
 //
 // Exact tile culling (optional).  The rectangle bounds the ellipse q <= kappa,
 // but a Gaussian of opacity o only blends where o exp(-q/2) >= alpha_min, and the

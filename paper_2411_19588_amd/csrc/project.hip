@@ -2,6 +2,9 @@
 // from rotation and scale; EWA affine projection of the covariance; SH colour)
 // and its adjoint.  One thread per Gaussian loops over the views, so the
 // structure-of-arrays parameters are read once per launch with coalesced loads.
+// The SH part of the adjoint runs in its own kernel from factors the adjoint
+// stores (k_adam_sh for one view, k_sh_views for several), which reads each SH
+// coefficient once and spreads a Gaussian's coefficients over four waves.
 //
 // The key path (view depth, 2D mean, diagonal of the 2D covariance, tile
 // rectangle) is a fixed sequence of separately rounded FP32 operations: this
