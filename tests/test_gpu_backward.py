@@ -7,6 +7,7 @@ import torch
 
 from paper_2411_19588_amd import rasterizer as R
 from paper_2411_19588_amd import synth
+from paper_2411_19588_amd import _native as N
 from tests import gpu_util as U
 
 pytestmark = pytest.mark.gpu
@@ -158,6 +159,31 @@ def test_multiview_grad_sums_views(oracle_mod, n, deg):
     out = rast.backward(ctx, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["medium"], g_rgb)
     got = dict(zip(FIELDS + ("medium",), [t.cpu().numpy().astype(np.float64) for t in out]))
     U.say(f"multiview grad n={n} sh degree {deg}")
+    ref = {f: 0.0 for f in FIELDS}
+    for v, cam in enumerate(sc.cameras):
+        r = O.backward(sc, cam, sc.medium[v], Gs[v])
+        for f in FIELDS:
+            ref[f] = ref[f] + r[f]
+        U.grad_close(got["medium"][v], r["medium"], 1e-3, f"medium view {v}")
+    for f in FIELDS:
+        U.grad_close(got[f], ref[f], 1e-3, f)
+
+
+def test_multiview_grad_max_views(oracle_mod):
+    """GS_MAX_VIEWS views: the gradients (k_sh_views with 3 + 3 * 64 planes) are the sums of the
+    views' oracle gradients, and each view's medium gradient is its own."""
+    O = oracle_mod
+    V = N.GS_MAX_VIEWS
+    sizes = [(16 + 8 * (v % 3), 16 + 8 * (v % 2)) for v in range(V)]
+    sc = synth.make_scene(3, n=600, n_views=V, view_sizes=sizes)
+    rast = U.make_rast(sc)
+    rgb, depth, alpha, ctx, d = U.forward(sc, rast)
+    rng = np.random.default_rng(9)
+    Gs = [U.unambiguous(O, sc, v, rng.normal(size=(c.width * c.height, 3)))[0] for v, c in enumerate(sc.cameras)]
+    g_rgb = torch.cat([torch.from_numpy(G.T.reshape(-1).astype(np.float32)) for G in Gs]).cuda()
+    out = rast.backward(ctx, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["medium"], g_rgb)
+    got = dict(zip(FIELDS + ("medium",), [t.cpu().numpy().astype(np.float64) for t in out]))
+    U.say(f"multiview grad {V} views")
     ref = {f: 0.0 for f in FIELDS}
     for v, cam in enumerate(sc.cameras):
         r = O.backward(sc, cam, sc.medium[v], Gs[v])

@@ -257,6 +257,18 @@ def test_image_multiview(oracle_mod):
         _image_match(sc, rast, oracle_mod, v=v)
 
 
+def test_image_max_views(oracle_mod):
+    """GS_MAX_VIEWS views of uneven small sizes in one pipeline (the largest view table): every
+    view's image against the oracle, in the automatic several-view schedule."""
+    V = N.GS_MAX_VIEWS
+    sizes = [(16 + 8 * (v % 3), 16 + 8 * (v % 2)) for v in range(V)]
+    sc = synth.make_scene(3, n=600, n_views=V, view_sizes=sizes)
+    rast = U.make_rast(sc)
+    U.say(f"image {V} views")
+    for v in range(V):
+        _image_match(sc, rast, oracle_mod, v=v)
+
+
 @pytest.mark.parametrize("cfg", [dict(lds_batch=256), dict(lds_batch=128), dict(persistent=True),
                                  dict(pixels_per_lane=1), dict(pixels_per_lane=4, lds_batch=64),
                                  dict(pixels_per_lane=1, persistent=True, lds_batch=128),
