@@ -66,6 +66,27 @@ def test_image_full_size_24_views_sampled(oracle_mod):
         U.compare_pixels(*U.gather_view(rgb, depth, alpha, rast, v, pix), orc)
 
 
+def test_image_full_size_3m_4_views_sampled(oracle_mod):
+    """The full-scale training workload's forward (3M Gaussians SH 3, 4 views at 1920x1080) in the
+    default launch configuration and automatic several-view schedule: 250 random pixels, the four
+    corners and the ragged last tile row of every view against the FP64 oracle."""
+    O = oracle_mod
+    sc = synth.make_scene(4)
+    rast = R.Rasterizer(sc.cameras, R.RasterConfig())
+    rgb, depth, alpha, ctx, _ = U.forward(sc, rast)
+    st, _ = rast.read_status(ctx.saved)
+    assert st == 0
+    rng = np.random.default_rng(13)
+    U.say(f"full-size 3M Gaussians, {len(sc.cameras)} views x 270 sampled pixels, schedule {rast.schedule(sc.n)}")
+    for v, cam in enumerate(sc.cameras):
+        pix = np.stack([rng.integers(0, cam.width, 250), rng.integers(0, cam.height, 250)], 1)
+        corners = np.array([[0, 0], [cam.width - 1, 0], [0, cam.height - 1], [cam.width - 1, cam.height - 1]])
+        last_row = np.stack([rng.integers(0, cam.width, 16), np.full(16, cam.height - 1)], 1)
+        pix = np.ascontiguousarray(np.concatenate([pix, corners, last_row]).astype(np.int32))
+        orc = O.render(sc, cam, sc.medium[v], pixels=pix, variants=4)
+        U.compare_pixels(*U.gather_view(rgb, depth, alpha, rast, v, pix), orc)
+
+
 def _crop_pixels():
     x0, y0, w, h = CROP
     ys, xs = np.meshgrid(np.arange(y0, y0 + h), np.arange(x0, x0 + w), indexing="ij")
