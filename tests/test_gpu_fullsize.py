@@ -1,7 +1,7 @@
-"""Parity at the full size of the 1M-Gaussian 1920x1080 workload, in the launch configuration
-the benchmark times: sampled pixels of the image against the FP64 oracle, and gradients of a
-loss on a 64x64 crop for 200 sampled Gaussians against the oracle's exact gradient and FP64
-central differences."""
+"""Parity at full size: the 1M-Gaussian 1920x1080 workload in the launch configuration the
+benchmark times (sampled pixels of the image against the FP64 oracle, and gradients of a loss on
+a 64x64 crop for 200 sampled Gaussians against the oracle's exact gradient and FP64 central
+differences), the 24-view batched workload and the 3M-Gaussian 4-view workload."""
 import numpy as np
 import pytest
 import torch
@@ -143,3 +143,48 @@ def test_grad_full_size_crop(oracle_mod, scene):
             checked += 1
     U.say(f"  finite differences checked {checked}")
     assert checked >= 8
+
+
+def test_grad_full_size_crop_4_views(oracle_mod):
+    """The 3M-Gaussian, 4-view workload (default launch configuration, automatic schedule): the
+    gradient of a loss on a 64x64 crop of view 1, zero upstream gradient elsewhere and in the other
+    views, through the several-view adjoint (the SH part in k_sh_views), against the oracle's exact
+    gradient for 200 sampled Gaussians; each view's medium gradient (zero but for view 1)."""
+    O = oracle_mod
+    sc = synth.make_scene(4)
+    v = 1
+    cam = sc.cameras[v]
+    pix = _crop_pixels()
+    rng = np.random.default_rng(14)
+    Gc = rng.normal(size=(len(pix), 3))
+    amb = O.render(sc, cam, sc.medium[v], pixels=pix, variants=1)["nvar"] > 0
+    Gc[amb] = 0.0
+    U.say(f"full-size 4-view crop gradient (view {v}), ambiguous crop pixels {int(amb.sum())}")
+    rast = R.Rasterizer(sc.cameras, R.RasterConfig())
+    rgb, depth, alpha, ctx, d = U.forward(sc, rast)
+    planes = []
+    for w, c in enumerate(sc.cameras):
+        G = np.zeros((c.height, c.width, 3))
+        if w == v:
+            G[pix[:, 1], pix[:, 0]] = Gc
+        planes.append(np.ascontiguousarray(G.transpose(2, 0, 1)).reshape(-1))
+    g_rgb = torch.from_numpy(np.concatenate(planes).astype(np.float32)).cuda()
+    out = rast.backward(ctx, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["medium"], g_rgb, None)
+    torch.cuda.synchronize()
+    got = dict(zip(FIELDS + ("medium",), [t.cpu().numpy().astype(np.float64) for t in out]))
+    ref = O.backward(sc, cam, sc.medium[v], Gc, pixels=pix)
+    live = np.nonzero(np.abs(ref["g2d"]).sum(axis=1) > 0)[0]
+    assert live.size >= 50, live.size
+    if live.size >= 200:
+        pick = np.sort(rng.choice(live, 200, replace=False))
+    else:
+        rest = rng.choice(np.setdiff1d(np.arange(sc.n), live), 200 - live.size, replace=False)
+        pick = np.sort(np.concatenate([live, rest]))
+    U.say(f"  {live.size} Gaussians reach the crop; checking 200")
+    for f in FIELDS:
+        U.grad_close(got[f][..., pick], ref[f][..., pick], 1e-3, f)
+    med = got["medium"].reshape(len(sc.cameras), 9)
+    U.grad_close(med[v], ref["medium"], 1e-3, "medium")
+    assert np.all(np.delete(med, v, axis=0) == 0.0)
+    dead = np.setdiff1d(np.arange(sc.n), live)[:5000]
+    assert np.all(got["opacity"][dead] == 0.0)
