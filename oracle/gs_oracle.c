@@ -16,7 +16,10 @@
  *     per colour channel.
  *   - Estimating Dense Depth Maps, eq. (Depth): z is the alpha-weighted mean
  *     depth of the contributors; Implementation section: optional logistic map
- *     z = 2/(1+exp(-0.1 zhat)) - 1.
+ *     z = 2/(1+exp(-0.1 zhat)) - 1, either inside the medium term or only on the
+ *     depth image shown for visualisation.
+ *   - eq. (scattering_approx): the clean image J is the in-air composite C_air
+ *     before attenuation; it is an output with its own upstream gradient.
  *   - Appendix "Partial Derivatives": gradients of the medium terms.  The
  *     oracle's backward is the exact derivative of its own forward (the printed
  *     appendix omits the factor z in dL/dB_d and dL/dB_b and the dependence of
@@ -62,6 +65,7 @@ typedef struct {
     float dilation_f32;   /* EWA dilation as the FP32 key path sees it */
     double alpha_min, alpha_max, t_min, dilation;
     double band;          /* relative margin under which a decision is "ambiguous" */
+    int32_t depth_output; /* depth image: 0 = the z the medium uses; 1 = logistic map of zhat */
 } orc_opts;
 
 /* ------------------------------------------------------------------------ */
@@ -428,16 +432,21 @@ static void walk_pixel(const walk_ctx* ctx, double px, double py, const decision
     out->D = D; out->W = W; out->T = T; out->n = n; out->hash = mix64(h, (uint64_t)n);
 }
 
-/* Medium epilogue (eq. 3dgs_uw with eq. Depth).  Writes rgb[3], depth, alpha. */
+/* Logistic map of the Implementation section: 2/(1 + e^{-0.1 zhat}) - 1. */
+static double logistic_depth(double zh) { return 2.0 / (1.0 + exp(-0.1 * zh)) - 1.0; }
+
+/* Medium epilogue (eq. 3dgs_uw with eq. Depth).  Writes rgb[3], depth, alpha.  The depth
+ * image is the z the medium uses, or (depth_output 1) the logistic map of zhat that the
+ * Implementation section applies for visualisation. */
 static void medium_epilogue(const walk_out* w, const double* med, const orc_opts* o, double* rgb, double* depth, double* alpha)
 {
     const double *Bd = med, *Bb = med + 3, *Binf = med + 6;
     if (w->W > 0.0) {
         double zh = w->D / w->W;
-        double z = o->depth_mode == 1 ? 2.0 / (1.0 + exp(-0.1 * zh)) - 1.0 : zh;
+        double z = o->depth_mode == 1 ? logistic_depth(zh) : zh;
         for (int c = 0; c < 3; ++c)
             rgb[c] = w->C[c] * exp(-Bd[c] * z) + Binf[c] * (1.0 - exp(-Bb[c] * z));
-        *depth = z;
+        *depth = o->depth_output == 1 ? logistic_depth(zh) : z;
     } else {
         for (int c = 0; c < 3; ++c) {
             if (o->depth_mode == 1) rgb[c] = Binf[c] * (1.0 - exp(-Bb[c]));
@@ -521,10 +530,14 @@ void orc_render(const orc_scene* S, const orc_cam* cam, const double* medium, co
 /* where Q_xy is the single off-diagonal conic entry (q = Qxx dx^2 +          */
 /* 2 Qxy dx dy + Qyy dy^2), and the medium gradient gmed[9] =                 */
 /* (dB_d[3], dB_b[3], dB_inf[3]).  Both are ACCUMULATED (+=).                 */
+/* Upstream gradients: of the attenuated colour C_uw, of the depth image and  */
+/* (grad_cair) of the in-air composite C_air, the clean image J of            */
+/* eq. (scattering_approx) that the medium attenuates.                        */
 /* ------------------------------------------------------------------------ */
 void orc_backward_pixels(const orc_scene* S, const orc_cam* cam, const double* medium, const orc_opts* o,
                          int64_t npix, const int32_t* pix, const double* grad_rgb /*[npix][3]*/,
-                         const double* grad_depth /*[npix] or NULL*/, double* g2d, double* gmed)
+                         const double* grad_depth /*[npix] or NULL*/, const double* grad_cair /*[npix][3] or NULL*/,
+                         double* g2d, double* gmed)
 {
     walk_ctx ctx;
     proj64* P;
@@ -563,8 +576,8 @@ void orc_backward_pixels(const orc_scene* S, const orc_cam* cam, const double* m
                 continue;
             }
             double zh = w.D / w.W;
-            double z = o->depth_mode == 1 ? 2.0 / (1.0 + exp(-0.1 * zh)) - 1.0 : zh;
-            double A[3], Sx[3], dz = Gz;
+            double z = o->depth_mode == 1 ? logistic_depth(zh) : zh;
+            double A[3], Sx[3], dz = 0.0;
             for (int c = 0; c < 3; ++c) {
                 A[c] = exp(-Bd[c] * z);
                 Sx[c] = exp(-Bb[c] * z);
@@ -573,9 +586,18 @@ void orc_backward_pixels(const orc_scene* S, const orc_cam* cam, const double* m
                 pm[6 + c] = G[c] * (1.0 - Sx[c]);
                 dz += G[c] * (-Bd[c] * w.C[c] * A[c] + Binf[c] * Bb[c] * Sx[c]);
             }
+            /* d(logistic)/d(zhat) = 0.05 (1 - y^2) for y = tanh(0.05 zhat) */
             double dzh = o->depth_mode == 1 ? dz * 0.05 * (1.0 - z * z) : dz;
+            if (o->depth_output == 1) {
+                double y = logistic_depth(zh);
+                dzh += Gz * 0.05 * (1.0 - y * y);
+            } else {
+                dzh += o->depth_mode == 1 ? Gz * 0.05 * (1.0 - z * z) : Gz;
+            }
             /* upstream gradient of the accumulators (C_air[3], D, W) */
-            double gC[3] = {G[0] * A[0], G[1] * A[1], G[2] * A[2]};
+            const double* GJ = grad_cair ? grad_cair + 3 * k : NULL;
+            double gC[3];
+            for (int c = 0; c < 3; ++c) gC[c] = G[c] * A[c] + (GJ ? GJ[c] : 0.0);
             double gD = dzh / w.W;
             double gW = -dzh * zh / w.W;
             int64_t n = w.n;

@@ -12,7 +12,9 @@ Functions (each cites the paper passage it follows):
   key, with pairs emitted in ascending Gaussian index so equal keys keep index
   order.
 * :func:`render` -- brute-force per-pixel evaluation over *all* Gaussians of
-  eq. (3dgs_orig), eq. (opacity_impact), eq. (3dgs_uw) and eq. (Depth) in FP64.
+  eq. (3dgs_orig), eq. (opacity_impact), eq. (3dgs_uw) and eq. (Depth) in FP64;
+  also the clean image J = C_air of eq. (scattering_approx) and, optionally, the
+  logistic depth map of the Implementation section as the depth image.
 * :func:`backward` -- exact FP64 derivative of :func:`render`; medium terms as
   in the appendix "Partial Derivatives" with the missing factor z restored.
 * :func:`fd_grad` -- central differences of :func:`render` (the pin for
@@ -61,7 +63,7 @@ class OrcOpts(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("depth_mode", ctypes.c_int32),
                 ("sh_degree", ctypes.c_int32), ("kappa_f32", ctypes.c_float), ("dilation_f32", ctypes.c_float),
                 ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double), ("t_min", ctypes.c_double),
-                ("dilation", ctypes.c_double), ("band", ctypes.c_double)]
+                ("dilation", ctypes.c_double), ("band", ctypes.c_double), ("depth_output", ctypes.c_int32)]
 
 
 class OrcScene(ctypes.Structure):
@@ -82,7 +84,7 @@ def lib():
         L.orc_render.argtypes = [ctypes.POINTER(OrcScene), ctypes.POINTER(OrcCam), P, ctypes.POINTER(OrcOpts),
                                  i64, P, P, P, P, P, P, P, P, ctypes.c_int32, P, P]
         L.orc_backward_pixels.argtypes = [ctypes.POINTER(OrcScene), ctypes.POINTER(OrcCam), P,
-                                          ctypes.POINTER(OrcOpts), i64, P, P, P, P, P]
+                                          ctypes.POINTER(OrcOpts), i64, P, P, P, P, P, P]
         L.orc_backward_project.argtypes = [ctypes.POINTER(OrcScene), ctypes.POINTER(OrcCam),
                                            ctypes.POINTER(OrcOpts), P, P, P, P, P, P]
         L.orc_sh_basis.argtypes = [ctypes.c_int, i64, P, P]
@@ -103,11 +105,12 @@ class Options:
     kappa: float = 11.1
     depth_mode: int = 0
     band: float = 1e-4
+    depth_output: int = 0     # 0: depth image = the medium's z; 1: logistic map of zhat (visualisation)
 
     def c(self, sh_degree: int) -> OrcOpts:
         return OrcOpts(self.tile_w, self.tile_h, self.depth_mode, sh_degree, np.float32(self.kappa),
                        np.float32(self.dilation), self.alpha_min, self.alpha_max, self.t_min,
-                       float(np.float32(self.dilation)), self.band)
+                       float(np.float32(self.dilation)), self.band, self.depth_output)
 
 
 def _cam(c) -> OrcCam:
@@ -261,10 +264,11 @@ def image(out, cam):
 # Backward (appendix "Partial Derivatives", completed)
 # ---------------------------------------------------------------------------
 def backward(scene, cam, medium, grad_rgb, grad_depth=None, opts: Options = Options(),
-             pixels: Optional[np.ndarray] = None, **over):
-    """Exact FP64 gradients of sum(grad_rgb * rgb) + sum(grad_depth * depth).
+             pixels: Optional[np.ndarray] = None, grad_cair=None, **over):
+    """Exact FP64 gradients of sum(grad_rgb * rgb) + sum(grad_depth * depth) + sum(grad_cair * cair).
 
-    grad_rgb: (P, 3) for the pixel list (or full frame in row-major order).
+    grad_rgb: (P, 3) for the pixel list (or full frame in row-major order); grad_cair (P, 3)
+    is the upstream gradient of the clean image J = C_air of eq. (scattering_approx).
     Returns SoA gradients: means (3,N), scales (3,N), quats (4,N), opacity (N,),
     sh (ncoef*3, N), medium (9,), plus g2d (N, 10) of the 2D quantities.
     """
@@ -274,6 +278,7 @@ def backward(scene, cam, medium, grad_rgb, grad_depth=None, opts: Options = Opti
     med = np.ascontiguousarray(np.asarray(medium, np.float64).reshape(9))
     grgb = np.ascontiguousarray(np.asarray(grad_rgb, np.float64).reshape(P, 3))
     gdep = None if grad_depth is None else np.ascontiguousarray(np.asarray(grad_depth, np.float64).reshape(P))
+    gcair = None if grad_cair is None else np.ascontiguousarray(np.asarray(grad_cair, np.float64).reshape(P, 3))
     n = S.n
     g2d = np.zeros((n, 10))
     gmed = np.zeros(9)
@@ -281,7 +286,8 @@ def backward(scene, cam, medium, grad_rgb, grad_depth=None, opts: Options = Opti
     c = _cam(cam)
     L = lib()
     L.orc_backward_pixels(ctypes.byref(S.c), ctypes.byref(c), _ptr(med), ctypes.byref(o), P, _ptr(pix),
-                          _ptr(grgb), _ptr(gdep) if gdep is not None else None, _ptr(g2d), _ptr(gmed))
+                          _ptr(grgb), _ptr(gdep) if gdep is not None else None,
+                          _ptr(gcair) if gcair is not None else None, _ptr(g2d), _ptr(gmed))
     ncoef = (S.sh_degree + 1) ** 2
     dm, ds, dq, do, dsh = (np.zeros((n, 3)), np.zeros((n, 3)), np.zeros((n, 4)), np.zeros(n),
                            np.zeros((n, ncoef * 3)))
@@ -291,18 +297,21 @@ def backward(scene, cam, medium, grad_rgb, grad_depth=None, opts: Options = Opti
                 medium=gmed, g2d=g2d)
 
 
-def loss_linear(scene, cam, medium, grad_rgb, grad_depth=None, opts: Options = Options(), pixels=None, **over):
-    """L = <G, C_uw> + <G_z, z> with the forward above; returns (L, hashes, color clamp flags)."""
+def loss_linear(scene, cam, medium, grad_rgb, grad_depth=None, opts: Options = Options(), pixels=None,
+                grad_cair=None, **over):
+    """L = <G, C_uw> + <G_z, z> + <G_J, C_air> with the forward above; returns (L, hashes, color clamp flags)."""
     out = render(scene, cam, medium, opts, pixels, **over)
     L = float(np.sum(out["rgb"] * np.asarray(grad_rgb).reshape(-1, 3)))
     if grad_depth is not None:
         L += float(np.sum(out["depth"] * np.asarray(grad_depth).reshape(-1)))
+    if grad_cair is not None:
+        L += float(np.sum(out["cair"] * np.asarray(grad_cair).reshape(-1, 3)))
     pr = project(scene, cam, opts, **over)
     return L, out["hash"], pr["color_clamp"]
 
 
 def fd_grad(scene, cam, medium, grad_rgb, field: str, index, grad_depth=None, opts: Options = Options(),
-            pixels=None, rel_h: float = 1e-6):
+            pixels=None, rel_h: float = 1e-6, grad_cair=None):
     """Central difference of loss_linear w.r.t. one FP64 scalar (field, index).
 
     `field` is one of means/scales/quats/opacity/sh/medium; `index` a tuple into
@@ -325,7 +334,7 @@ def fd_grad(scene, cam, medium, grad_rgb, field: str, index, grad_depth=None, op
             m2[index] = x0 + sgn * h
         else:
             over[field][index] = x0 + sgn * h
-        L, hs, cc = loss_linear(scene, cam, m2, grad_rgb, grad_depth, opts, pixels, **over)
+        L, hs, cc = loss_linear(scene, cam, m2, grad_rgb, grad_depth, opts, pixels, grad_cair, **over)
         vals.append(L)
         sigs.append((hs.copy(), cc.copy()))
     ok = np.array_equal(sigs[0][0], sigs[1][0]) and np.array_equal(sigs[0][1], sigs[1][1])

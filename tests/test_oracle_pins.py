@@ -289,6 +289,39 @@ def test_cair_linear_in_colour(oracle_mod):
     np.testing.assert_allclose(half["cair"], 0.5 * base["cair"], rtol=1e-12, atol=1e-15)
 
 
+def test_clean_image_single_gaussian_closed_form(oracle_mod):
+    """J = C_air of eq. (scattering_approx): c alpha for one Gaussian, whatever the medium."""
+    O = oracle_mod
+    f, d, s, o = 40.0, 2.5, 0.05, 0.7
+    c = np.array([0.3, 0.6, 0.9])
+    med = np.array([0.2, 0.3, 0.4, 0.1, 0.25, 0.45, 0.05, 0.15, 0.28], np.float32)
+    cam = _cam(24, 20, f, cx=12.0, cy=10.0)
+    sc = _scene([[0, 0, d]], [[s, s, s]], [[1, 0, 0, 0]], [o], colors=[c], medium=med)
+    out = O.render(sc, cam, med)
+    cc = _colour_of(sc, 0)
+    for k, (u, v) in enumerate(O.all_pixels(cam)):
+        r2 = (u + 0.5 - 12.0) ** 2 + (v + 0.5 - 10.0) ** 2
+        a = _alpha_iso(float(np.float32(o)), f, s, d, r2)
+        np.testing.assert_allclose(out["cair"][k], cc * a if a >= 1 / 255 else 0.0, rtol=1e-12, atol=1e-15)
+
+
+def test_logistic_depth_output_for_visualisation(oracle_mod):
+    """depth_output 1 maps only the depth image (tanh(0.05 zhat)); the colour keeps the metric z."""
+    O = oracle_mod
+    sc = synth.make_scene(0, n=200, width=32, height=32)
+    cam = sc.cameras[0]
+    a = O.render(sc, cam, sc.medium[0])
+    b = O.render(sc, cam, sc.medium[0], opts=O.Options(depth_output=1))
+    np.testing.assert_array_equal(b["rgb"], a["rgb"])
+    full = a["alpha"] > 0
+    assert full.sum() > 100
+    np.testing.assert_allclose(b["depth"][full], np.tanh(0.05 * a["depth"][full]), rtol=1e-12)
+    np.testing.assert_array_equal(b["depth"][~full], 0.0)
+    # with the logistic map also in the medium, the depth image is the same map
+    c = O.render(sc, cam, sc.medium[0], opts=O.Options(depth_mode=1, depth_output=1))
+    np.testing.assert_allclose(c["depth"], b["depth"], rtol=1e-15, atol=0)
+
+
 def test_logistic_depth_mode(oracle_mod):
     O = oracle_mod
     sc = synth.make_scene(0, n=200, width=32, height=32)
@@ -336,19 +369,25 @@ def test_keys_sorted_and_coverage(oracle_mod):
 
 
 # --------------------------------------------------------------------------- gradients vs central differences
-@pytest.mark.parametrize("depth_mode,with_gz,deg", [(0, False, 3), (0, True, 1), (1, True, 3)])
-def test_backward_matches_central_differences(oracle_mod, depth_mode, with_gz, deg):
+@pytest.mark.parametrize("depth_mode,with_gz,deg,with_gj,depth_output",
+                         [(0, False, 3, False, 0), (0, True, 1, False, 0), (1, True, 3, False, 0),
+                          (0, True, 2, True, 1), (1, True, 1, True, 1), (1, False, 0, True, 0)])
+def test_backward_matches_central_differences(oracle_mod, depth_mode, with_gz, deg, with_gj, depth_output):
+    """Every parameter's exact gradient against FP64 central differences, for upstream gradients on
+    the attenuated colour, the depth image (metric or logistic, either in the medium or only on
+    the image) and the clean image J = C_air."""
     O = oracle_mod
     sc = synth.custom_scene(seed=11 + depth_mode + deg, n=25, sh_degree=deg, width=24, height=20, f=30.0,
                             log_scale_mean=-2.0, sh_std=0.3)
     cam = sc.cameras[0]
-    opts = O.Options(depth_mode=depth_mode)
+    opts = O.Options(depth_mode=depth_mode, depth_output=depth_output)
     rng = np.random.default_rng(3)
     P = cam.width * cam.height
     G = rng.normal(size=(P, 3))
     Gz = rng.normal(size=P) if with_gz else None
+    GJ = rng.normal(size=(P, 3)) if with_gj else None
     med = sc.medium[0].astype(np.float64)
-    an = O.backward(sc, cam, med, G, Gz, opts)
+    an = O.backward(sc, cam, med, G, Gz, opts, grad_cair=GJ)
     checked = 0
     fields = dict(means=(3,), scales=(3,), quats=(4,), opacity=(), sh=((deg + 1) ** 2 * 3,))
     live = np.nonzero(np.any(an["g2d"] != 0, axis=1))[0]
@@ -357,7 +396,7 @@ def test_backward_matches_central_differences(oracle_mod, depth_mode, with_gz, d
         for field, shp in fields.items():
             idxs = [(g,)] if not shp else [(r, g) for r in range(shp[0])]
             for idx in idxs:
-                fd, ok = O.fd_grad(sc, cam, med, G, field, idx, Gz, opts)
+                fd, ok = O.fd_grad(sc, cam, med, G, field, idx, Gz, opts, grad_cair=GJ)
                 if not ok:
                     continue
                 a = an[field][idx]
@@ -365,7 +404,7 @@ def test_backward_matches_central_differences(oracle_mod, depth_mode, with_gz, d
                     (field, idx, a, fd)
                 checked += 1
     for j in range(9):
-        fd, ok = O.fd_grad(sc, cam, med, G, "medium", j, Gz, opts)
+        fd, ok = O.fd_grad(sc, cam, med, G, "medium", j, Gz, opts, grad_cair=GJ)
         if ok:
             assert abs(an["medium"][j] - fd) <= 2e-6 * max(1.0, abs(fd)), (j, an["medium"][j], fd)
             checked += 1
