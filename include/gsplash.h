@@ -123,7 +123,8 @@ typedef struct gs_options {
     float t_min;                         /* 1e-4: stop before blending a Gaussian that would leave T < t_min */
     float dilation;                      /* 0.3: added to the diagonal of the 2D covariance (EWA low-pass) */
     float kappa;                         /* 11.1: tile rectangle = bounding box of q <= kappa (> 2 ln 255) */
-    int32_t depth_mode;                  /* 0: z = alpha-weighted depth; 1: z = 2/(1+exp(-0.1 z)) - 1 */
+    int32_t depth_mode;                  /* z the medium term uses: 0 = alpha-weighted depth zhat;
+                                            1 = 2/(1+exp(-0.1 zhat)) - 1 (Implementation section) */
     int32_t tile_cull;                   /* 1 (default): drop a (Gaussian, tile) pair of the rectangle when no
                                             pixel centre of the tile can reach alpha >= alpha_min (a bound
                                             with a rounding margin; images are identical); 0: every tile of
@@ -141,6 +142,10 @@ typedef struct gs_options {
                                             per tile, rounded and clamped to 2..12 (about one Gaussian
                                             per tile first); 6 for several.  Images are identical for
                                             every value. */
+    int32_t depth_output;                /* depth image: 0 (default) = the z of depth_mode; 1 = the logistic
+                                            map 2/(1+exp(-0.1 zhat)) - 1 of the Implementation section, for
+                                            visualisation, whatever depth_mode the medium uses */
+    int32_t reserved;
     int64_t max_pairs;                   /* capacity of the stored (Gaussian, tile) pair list, <= GS_MAX_PAIRS */
     void* timer;                         /* optional gs_timer* receiving per-kernel HIP events; NULL = none */
 } gs_options;
@@ -167,30 +172,39 @@ int gs_workspace_query(const gs_options* opts, int64_t n, int32_t n_views, const
  *                after the poses are updated in place; sizes must not change).
  *   dev_medium : DEVICE [n_views] medium coefficients.
  *   out_rgb    : [sum 3 W H] attenuated colour C_uw (CHW per view);
- *   out_depth  : [sum W H] z (0 where no Gaussian contributes; such pixels are
- *                treated as at infinite range: C_uw = B_inf where B_b > 0);
- *   out_alpha  : [sum W H] accumulated opacity sum_i alpha_i T_i.
+ *   out_depth  : [sum W H] the depth image (opts.depth_output: the z of the
+ *                medium term, or its logistic map for visualisation); 0 where no
+ *                Gaussian contributes (such pixels are treated as at infinite
+ *                range: C_uw = B_inf where B_b > 0);
+ *   out_alpha  : [sum W H] accumulated opacity sum_i alpha_i T_i;
+ *   out_restored : [sum 3 W H] or NULL: the clean image J of
+ *                eq. (scattering_approx), i.e. the in-air composite
+ *                C_air = sum_i c_i alpha_i T_i before the medium's attenuation
+ *                and backscatter (0 where no Gaussian contributes), CHW per view.
  *   saved      : forward context (>= saved_bytes) used by gs_render_backward,
  *                gs_read_status and gs_export_keys.
  * Returns GS_OK or a GS_ERR_* code; capacity overflow is reported
  * asynchronously through gs_read_status (outputs are then not valid). */
 int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_views,
                       const gs_camera* host_cams, const gs_camera* dev_cams, const gs_medium* dev_medium,
-                      float* out_rgb, float* out_depth, float* out_alpha,
+                      float* out_rgb, float* out_depth, float* out_alpha, float* out_restored,
                       void* saved, size_t saved_bytes, void* workspace, size_t workspace_bytes,
                       gs_stream_t stream);
 
 /* Adjoint of gs_render_forward for L with upstream gradients grad_rgb (same
- * layout as out_rgb) and grad_depth (same layout as out_depth, may be NULL).
+ * layout as out_rgb), grad_depth (same layout as out_depth, may be NULL) and
+ * grad_restored (same layout as out_restored, may be NULL).
  * Transmittance is recomputed from the saved final transmittance rather than
  * storing per-pixel Gaussian lists.  Writes gradients w.r.t. every Gaussian
  * parameter (activated scales and opacity) into `grads` (overwritten) and
  * grad_medium [n_views][9] = (dB_d[3], dB_b[3], dB_inf[3]) (overwritten).
  * opts, g, n_views, cameras and medium must equal those of the forward call
- * that produced `saved`. */
+ * that produced `saved`.  If that forward overflowed the pair capacity
+ * (GS_STATUS_PAIR_OVERFLOW), the adjoint kernels do nothing and every
+ * gradient written is zero. */
 int gs_render_backward(const gs_options* opts, const gs_gaussians* g, int32_t n_views,
                        const gs_camera* host_cams, const gs_camera* dev_cams, const gs_medium* dev_medium,
-                       const float* grad_rgb, const float* grad_depth,
+                       const float* grad_rgb, const float* grad_depth, const float* grad_restored,
                        const void* saved, size_t saved_bytes, gs_gaussian_grads* grads, float* grad_medium,
                        void* workspace, size_t workspace_bytes, gs_stream_t stream);
 
@@ -243,6 +257,10 @@ int64_t gs_tile_count(const gs_options* opts, int32_t n_views, const gs_camera* 
 int gs_activate(int64_t n, const float* log_scales, const float* logits, float* scales, float* opacity,
                 gs_stream_t stream);
 
+/* Activation of one parameter group (the A0 step for a gs_adam_group):
+ * y[i] = x[i] (activation 0), exp(x[i]) (1) or 1/(1+exp(-x[i])) (2), i < count. */
+int gs_activation(int64_t count, int32_t activation, const float* x, float* y, gs_stream_t stream);
+
 /* Chain gradients through gs_activate: g_log_scales = g_scales * scales,
  * g_logits = g_opacity * opacity * (1 - opacity) (scales/opacity activated). */
 int gs_activate_backward(int64_t n, const float* scales, const float* opacity, const float* g_scales,
@@ -253,6 +271,26 @@ int gs_activate_backward(int64_t n, const float* scales, const float* opacity, c
  * (grad may be NULL). */
 int gs_l1_loss(int64_t count, const float* pred, const float* target, float* loss, float* grad,
                gs_stream_t stream);
+
+/* Image loss of eq. (3DGSoriginalLoss) / (OurFinalLoss) for packed views (the
+ * layout of out_rgb; host_cams fixes the view sizes):
+ *     L = sum_v [ (1 - lambda) L1_v + lambda (1 - SSIM_v) ],
+ * L1_v = mean |pred - target| over the view's 3 W H values, SSIM_v = mean of the
+ * SSIM map over them (Wang et al., cited for D-SSIM; per colour channel, an
+ * 11 x 11 Gaussian window of standard deviation 1.5, zero padding outside the
+ * image, C1 = 0.01^2, C2 = 0.03^2 for values in [0, 1]).  The paper sets
+ * lambda = 0.3 (appendix "Experimental Setup").
+ *   loss : DEVICE [n_views + 1] or NULL: each view's L_v, then L.
+ *   grad : DEVICE, layout of pred, or NULL: dL/dpred (overwritten).
+ *   workspace : DEVICE scratch of gs_loss_workspace_query bytes (per-tile
+ *              partial sums; the loss is their fixed-order sum, deterministic).
+ * One pass reads pred and target and writes grad; no intermediate map reaches
+ * memory.  Returns GS_ERR_INVALID_ARGUMENT (bad sizes, lambda outside [0, 1],
+ * both outputs NULL) or GS_ERR_WORKSPACE_TOO_SMALL before any device work. */
+int gs_loss_workspace_query(int32_t n_views, const gs_camera* host_cams, size_t* workspace_bytes);
+int gs_l1_dssim_loss(int32_t n_views, const gs_camera* host_cams, const float* pred, const float* target,
+                     float lambda, float* loss, float* grad, void* workspace, size_t workspace_bytes,
+                     gs_stream_t stream);
 
 /* One parameter group of the fused Adam step (Sec. Optimization: Adam with
  * the 3DGS learning rates, medium at the colour learning rate). */
@@ -269,6 +307,19 @@ typedef struct gs_adam_group {
                                             activated value of the current param on entry. */
     int32_t reserved;
 } gs_adam_group;
+
+/* Device-side training state of the Adam entry points: int32[2], zeroed by the
+ * caller before the first step.
+ *   state[0] : the Adam step counter t (incremented by each step that runs).
+ *   state[1] : sticky skip flag.  A step whose forward context reports
+ *              GS_STATUS_PAIR_OVERFLOW (its render was truncated) is not
+ *              applied: the counter, parameters, moments and activated copies
+ *              stay unchanged and GS_STATUS_PAIR_OVERFLOW is OR-ed into
+ *              state[1].  While state[1] != 0 every later step is skipped too,
+ *              so a replayed graph cannot apply a bad step after an overflow;
+ *              only the caller clears it (after growing the capacity). */
+#define GS_STATE_STEP 0
+#define GS_STATE_SKIP 1
 
 /* Training-step adjoint with the optimizer fused into the projection adjoint
  * (Sec. Optimization): the adjoint of gs_render_backward, but instead of writing
@@ -292,14 +343,18 @@ typedef struct gs_adam_group {
  *               must be the groups' params.  Each group's `grad`
  *               is ignored except the medium group's, which receives the medium
  *               gradient [n_views][9].
- *   step_counter : DEVICE int32, incremented first; the incremented value is t.
- * Only the m, v, param and activated arrays are written (plus workspace).
+ *   state      : DEVICE int32[2] training state (see GS_STATE_*): the step
+ *                counter is incremented first and the incremented value is t;
+ *                a forward that overflowed the pair capacity skips the step.
+ * Only the m, v, param and activated arrays are written (plus workspace, state
+ * and the medium group's grad).
  * Returns GS_ERR_INVALID_ARGUMENT on any mismatch; otherwise as gs_render_backward. */
 int gs_render_backward_adam(const gs_options* opts, const gs_gaussians* g, int32_t n_views,
                             const gs_camera* host_cams, const gs_camera* dev_cams, const gs_medium* dev_medium,
-                            const float* grad_rgb, const float* grad_depth, const void* saved, size_t saved_bytes,
-                            const gs_adam_group* groups, float beta1, float beta2, float eps, int32_t* step_counter,
-                            void* workspace, size_t workspace_bytes, gs_stream_t stream);
+                            const float* grad_rgb, const float* grad_depth, const float* grad_restored,
+                            const void* saved, size_t saved_bytes, const gs_adam_group* groups, float beta1,
+                            float beta2, float eps, int32_t* state, void* workspace, size_t workspace_bytes,
+                            gs_stream_t stream);
 
 /* Fused Adam update (beta1, beta2, eps, bias correction at `step` >= 1) over
  * up to 8 groups in one launch. */
@@ -307,10 +362,13 @@ int gs_adam_step(const gs_adam_group* host_groups, int32_t n_groups, float beta1
                  int32_t step, gs_stream_t stream);
 
 /* As gs_adam_step, for replay from a captured graph: the step number lives in
- * device memory.  *step_counter (DEVICE int32) is incremented first and the
- * incremented value is the step used for bias correction (start it at 0). */
+ * device memory.  state (DEVICE int32[2], see GS_STATE_*): state[0] is
+ * incremented first and the incremented value is the step used for bias
+ * correction (start it at 0).  saved (nullable) is the forward context the
+ * gradients came from: when it reports GS_STATUS_PAIR_OVERFLOW, or state[1] is
+ * already set, the step is skipped and the flag is kept in state[1]. */
 int gs_adam_step_device(const gs_adam_group* host_groups, int32_t n_groups, float beta1, float beta2, float eps,
-                        int32_t* step_counter, gs_stream_t stream);
+                        int32_t* state, const void* saved, gs_stream_t stream);
 
 /* HIP graph capture of any sequence of the enqueue-only calls above (for
  * callers that replay a fixed pipeline, e.g. a training step over fixed views).

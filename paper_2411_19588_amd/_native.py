@@ -24,6 +24,8 @@ GS_MAX_PHASES = 8
 GS_FETCH_DEFAULT = 0
 GS_FETCH_LDS = 1
 GS_FETCH_SCALAR = 2
+GS_STATE_STEP = 0
+GS_STATE_SKIP = 1
 
 _ERRORS = {GS_ERR_INVALID_ARGUMENT: "invalid argument", GS_ERR_UNSUPPORTED: "unsupported",
            GS_ERR_WORKSPACE_TOO_SMALL: "workspace too small", GS_ERR_HIP: "HIP runtime error"}
@@ -58,8 +60,8 @@ class GsOptions(ctypes.Structure):
                 ("record_fetch", ctypes.c_int32), ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("t_min", ctypes.c_float), ("dilation", ctypes.c_float), ("kappa", ctypes.c_float),
                 ("depth_mode", ctypes.c_int32), ("tile_cull", ctypes.c_int32),
-                ("phases", ctypes.c_int32), ("phase0_shift", ctypes.c_int32), ("max_pairs", ctypes.c_int64),
-                ("timer", ctypes.c_void_p)]
+                ("phases", ctypes.c_int32), ("phase0_shift", ctypes.c_int32), ("depth_output", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("max_pairs", ctypes.c_int64), ("timer", ctypes.c_void_p)]
 
 
 class GsAdamGroup(ctypes.Structure):
@@ -79,12 +81,12 @@ PROTOTYPES = {
     "gs_workspace_query": (ctypes.c_int, [ctypes.POINTER(GsOptions), _I64, _I32, ctypes.POINTER(GsCamera),
                                           ctypes.POINTER(_SZ), ctypes.POINTER(_SZ)]),
     "gs_render_forward": (ctypes.c_int, [ctypes.POINTER(GsOptions), ctypes.POINTER(GsGaussians), _I32,
-                                         ctypes.POINTER(GsCamera), _P, _P, _P, _P, _P, _P, _SZ, _P, _SZ, _P]),
+                                         ctypes.POINTER(GsCamera), _P, _P, _P, _P, _P, _P, _P, _SZ, _P, _SZ, _P]),
     "gs_render_backward": (ctypes.c_int, [ctypes.POINTER(GsOptions), ctypes.POINTER(GsGaussians), _I32,
-                                          ctypes.POINTER(GsCamera), _P, _P, _P, _P, _P, _SZ,
+                                          ctypes.POINTER(GsCamera), _P, _P, _P, _P, _P, _P, _SZ,
                                           ctypes.POINTER(GsGaussianGrads), _P, _P, _SZ, _P]),
     "gs_render_backward_adam": (ctypes.c_int, [ctypes.POINTER(GsOptions), ctypes.POINTER(GsGaussians), _I32,
-                                               ctypes.POINTER(GsCamera), _P, _P, _P, _P, _P, _SZ,
+                                               ctypes.POINTER(GsCamera), _P, _P, _P, _P, _P, _P, _SZ,
                                                ctypes.POINTER(GsAdamGroup), ctypes.c_float, ctypes.c_float,
                                                ctypes.c_float, _P, _P, _SZ, _P]),
     "gs_read_status": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_I64), _P]),
@@ -96,12 +98,16 @@ PROTOTYPES = {
     "gs_schedule": (ctypes.c_int, [ctypes.POINTER(GsOptions), _I64, _I32, ctypes.POINTER(GsCamera),
                                    ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "gs_activate": (ctypes.c_int, [_I64, _P, _P, _P, _P, _P]),
+    "gs_activation": (ctypes.c_int, [_I64, _I32, _P, _P, _P]),
     "gs_activate_backward": (ctypes.c_int, [_I64, _P, _P, _P, _P, _P, _P, _P]),
     "gs_l1_loss": (ctypes.c_int, [_I64, _P, _P, _P, _P, _P]),
+    "gs_loss_workspace_query": (ctypes.c_int, [_I32, ctypes.POINTER(GsCamera), ctypes.POINTER(_SZ)]),
+    "gs_l1_dssim_loss": (ctypes.c_int, [_I32, ctypes.POINTER(GsCamera), _P, _P, ctypes.c_float, _P, _P, _P, _SZ,
+                                        _P]),
     "gs_adam_step": (ctypes.c_int, [ctypes.POINTER(GsAdamGroup), _I32, ctypes.c_float, ctypes.c_float,
                                     ctypes.c_float, _I32, _P]),
     "gs_adam_step_device": (ctypes.c_int, [ctypes.POINTER(GsAdamGroup), _I32, ctypes.c_float, ctypes.c_float,
-                                           ctypes.c_float, _P, _P]),
+                                           ctypes.c_float, _P, _P, _P]),
     "gs_graph_begin": (ctypes.c_int, [_P]),
     "gs_graph_end": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
     "gs_graph_launch": (ctypes.c_int, [_P, _P]),

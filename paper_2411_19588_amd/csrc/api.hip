@@ -45,6 +45,7 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     if (!finite_pos(o->t_min) || !(o->t_min < 1.0f)) return GS_ERR_INVALID_ARGUMENT;
     if (!(o->dilation >= 0.0f && o->dilation < 1e30f) || !finite_pos(o->kappa)) return GS_ERR_INVALID_ARGUMENT;
     if (o->depth_mode != 0 && o->depth_mode != 1) return GS_ERR_INVALID_ARGUMENT;
+    if (o->depth_output != 0 && o->depth_output != 1) return GS_ERR_INVALID_ARGUMENT;
     if (o->persistent != 0 && o->persistent != 1) return GS_ERR_INVALID_ARGUMENT;
     if (o->pixels_per_lane != 0 && o->pixels_per_lane != 1 && (t8 || (o->pixels_per_lane != 2 && o->pixels_per_lane != 4)))
         return GS_ERR_INVALID_ARGUMENT;
@@ -235,13 +236,14 @@ void gs_default_options(gs_options* o) {
     o->dilation = 0.3f;
     o->kappa = 11.1f;
     o->depth_mode = 0;
+    o->depth_output = 0;
     o->phases = 0;         // automatic, by view count
     o->phase0_shift = 0;
     o->max_pairs = 1LL << 24;
     o->timer = nullptr;
 }
 
-const char* gs_version(void) { return "gsplash 0.2 (gfx950)"; }
+const char* gs_version(void) { return "gsplash 0.3 (gfx950)"; }
 
 int gs_workspace_query(const gs_options* opts, int64_t n, int32_t n_views, const gs_camera* host_cams,
                        size_t* workspace_bytes, size_t* saved_bytes) {
@@ -271,8 +273,8 @@ int64_t gs_tile_count(const gs_options* opts, int32_t n_views, const gs_camera* 
 
 int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_views, const gs_camera* host_cams,
                       const gs_camera* dev_cams, const gs_medium* dev_medium, float* out_rgb, float* out_depth,
-                      float* out_alpha, void* saved, size_t saved_bytes, void* workspace, size_t workspace_bytes,
-                      gs_stream_t stream) {
+                      float* out_alpha, float* out_restored, void* saved, size_t saved_bytes, void* workspace,
+                      size_t workspace_bytes, gs_stream_t stream) {
     int rc = check_gaussians(g);
     if (rc != GS_OK) return rc;
     Layout L;
@@ -357,7 +359,7 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
         timer_end(T, s);
         timer_begin(T, "composite_fwd", s);
         GS_TRY(launch_composite_fwd(o, L, ph, vt, dev_medium, rec, ranges, vals, hdr, alive, out_rgb, out_depth,
-                                    out_alpha, tfinal, nlast, done, cair, dsum, wsum, s));
+                                    out_alpha, out_restored, tfinal, nlast, done, cair, dsum, wsum, s));
         timer_end(T, s);
     }
     return GS_OK;
@@ -365,8 +367,9 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
 
 int gs_render_backward(const gs_options* opts, const gs_gaussians* g, int32_t n_views, const gs_camera* host_cams,
                        const gs_camera* dev_cams, const gs_medium* dev_medium, const float* grad_rgb,
-                       const float* grad_depth, const void* saved, size_t saved_bytes, gs_gaussian_grads* grads,
-                       float* grad_medium, void* workspace, size_t workspace_bytes, gs_stream_t stream) {
+                       const float* grad_depth, const float* grad_restored, const void* saved, size_t saved_bytes,
+                       gs_gaussian_grads* grads, float* grad_medium, void* workspace, size_t workspace_bytes,
+                       gs_stream_t stream) {
     int rc = check_gaussians(g);
     if (rc != GS_OK) return rc;
     Layout L;
@@ -384,18 +387,21 @@ int gs_render_backward(const gs_options* opts, const gs_gaussians* g, int32_t n_
     const ViewInfo* vt = reinterpret_cast<const ViewInfo*>(hdr + 1);
     float* grad2d = at<float>(workspace, L.w_grad2d);
     float* medpart = at<float>(workspace, L.w_medpart);
+    // a truncated forward (pair overflow) gives no gradient: the 2D gradients stay zero
+    const Guard guard{&hdr->status, GS_STATUS_PAIR_OVERFLOW};
 
     timer_begin(T, "zero_grad2d", s);
     GS_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, L.nv * kGrad2D, s));
     timer_end(T, s);
     timer_begin(T, "composite_bwd", s);
     GS_TRY(launch_composite_bwd(o, L, vt, dev_medium, at<Record>(saved, L.s_records), at<uint2>(saved, L.s_ranges),
-                                at<uint32_t>(saved, L.s_vals), grad_rgb, grad_depth, at<float>(saved, L.s_tfinal),
-                                at<uint32_t>(saved, L.s_nlast), at<float>(saved, L.s_cair),
-                                at<float>(saved, L.s_dsum), at<float>(saved, L.s_wsum), grad2d, medpart, s));
+                                at<uint32_t>(saved, L.s_vals), grad_rgb, grad_depth, grad_restored,
+                                at<float>(saved, L.s_tfinal), at<uint32_t>(saved, L.s_nlast),
+                                at<float>(saved, L.s_cair), at<float>(saved, L.s_dsum), at<float>(saved, L.s_wsum),
+                                grad2d, medpart, guard, s));
     timer_end(T, s);
     timer_begin(T, "medium_reduce", s);
-    GS_TRY(launch_medium_reduce(vt, n_views, medpart, grad_medium, nullptr, 0.f, 0.f, 0.f, nullptr, s));
+    GS_TRY(launch_medium_reduce(vt, n_views, medpart, grad_medium, nullptr, 0.f, 0.f, 0.f, nullptr, guard, s));
     timer_end(T, s);
     timer_begin(T, "project_bwd", s);
     float* planes = at<float>(workspace, L.w_shf);
@@ -414,15 +420,16 @@ int gs_render_backward(const gs_options* opts, const gs_gaussians* g, int32_t n_
 
 int gs_render_backward_adam(const gs_options* opts, const gs_gaussians* g, int32_t n_views,
                             const gs_camera* host_cams, const gs_camera* dev_cams, const gs_medium* dev_medium,
-                            const float* grad_rgb, const float* grad_depth, const void* saved, size_t saved_bytes,
-                            const gs_adam_group* groups, float beta1, float beta2, float eps, int32_t* step_counter,
-                            void* workspace, size_t workspace_bytes, gs_stream_t stream) {
+                            const float* grad_rgb, const float* grad_depth, const float* grad_restored,
+                            const void* saved, size_t saved_bytes, const gs_adam_group* groups, float beta1,
+                            float beta2, float eps, int32_t* state, void* workspace, size_t workspace_bytes,
+                            gs_stream_t stream) {
     int rc = check_gaussians(g);
     if (rc != GS_OK) return rc;
     Layout L;
     rc = compute_layout(opts, g->n, n_views, host_cams, &L);
     if (rc != GS_OK) return rc;
-    if (!dev_cams || !dev_medium || !grad_rgb || !saved || !groups || !step_counter || !workspace)
+    if (!dev_cams || !dev_medium || !grad_rgb || !saved || !groups || !state || !workspace)
         return GS_ERR_INVALID_ARGUMENT;
     if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f))
         return GS_ERR_INVALID_ARGUMENT;
@@ -449,20 +456,24 @@ int gs_render_backward_adam(const gs_options* opts, const gs_gaussians* g, int32
     float* grad2d = at<float>(workspace, L.w_grad2d);
     float* medpart = at<float>(workspace, L.w_medpart);
     float* bc = at<float>(workspace, L.w_adam);
+    // the step is skipped when this forward overflowed or the caller's sticky flag is set:
+    // k_adam_prep folds both into state[1], which every later kernel of the step reads
+    const Guard guard{reinterpret_cast<const uint32_t*>(state + GS_STATE_SKIP), 0xFFFFFFFFu};
 
-    GS_TRY(launch_adam_prep(step_counter, beta1, beta2, bc, s));
+    GS_TRY(launch_adam_prep(state, &hdr->status, beta1, beta2, bc, s));
     timer_begin(T, "zero_grad2d", s);
     GS_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, L.nv * kGrad2D, s));
     timer_end(T, s);
     timer_begin(T, "composite_bwd", s);
     GS_TRY(launch_composite_bwd(o, L, vt, dev_medium, at<Record>(saved, L.s_records), at<uint2>(saved, L.s_ranges),
-                                at<uint32_t>(saved, L.s_vals), grad_rgb, grad_depth, at<float>(saved, L.s_tfinal),
-                                at<uint32_t>(saved, L.s_nlast), at<float>(saved, L.s_cair),
-                                at<float>(saved, L.s_dsum), at<float>(saved, L.s_wsum), grad2d, medpart, s));
+                                at<uint32_t>(saved, L.s_vals), grad_rgb, grad_depth, grad_restored,
+                                at<float>(saved, L.s_tfinal), at<uint32_t>(saved, L.s_nlast),
+                                at<float>(saved, L.s_cair), at<float>(saved, L.s_dsum), at<float>(saved, L.s_wsum),
+                                grad2d, medpart, guard, s));
     timer_end(T, s);
     timer_begin(T, "medium_reduce", s);
     GS_TRY(launch_medium_reduce(vt, n_views, medpart, const_cast<float*>(groups[5].grad), &groups[5], beta1, beta2,
-                                eps, bc, s));
+                                eps, bc, guard, s));
     timer_end(T, s);
     AdamFused ad;
     memset(&ad, 0, sizeof(ad));
@@ -471,6 +482,7 @@ int gs_render_backward_adam(const gs_options* opts, const gs_gaussians* g, int32
     ad.b2 = beta2;
     ad.eps = eps;
     ad.bc = bc;
+    ad.guard = guard;
     // the SH part of the adjoint and the SH and means steps run from planes the adjoint stores
     ad.shf = at<float>(workspace, L.w_shf);
     timer_begin(T, "project_bwd", s);

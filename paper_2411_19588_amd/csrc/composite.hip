@@ -49,6 +49,7 @@ struct FwdArgs {
     float* out_rgb;
     float* out_depth;
     float* out_alpha;
+    float* out_restored;      // nullable: C_air, CHW per view
     float* tfinal;
     uint32_t* nlast;
     uint8_t* done;
@@ -57,7 +58,7 @@ struct FwdArgs {
     float* wsum;
     int64_t pixels;
     float amin, amax, tmin;
-    int32_t depth_mode;
+    int32_t depth_mode, depth_output;
 };
 
 struct BwdArgs {
@@ -72,6 +73,7 @@ struct BwdArgs {
     uint32_t* queue;
     const float* grad_rgb;
     const float* grad_depth;
+    const float* grad_restored;   // nullable
     const float* tfinal;
     const uint32_t* nlast;
     const float* cair;
@@ -81,7 +83,8 @@ struct BwdArgs {
     float* medpart;
     int64_t pixels;
     float amin, amax, tmin;
-    int32_t depth_mode;
+    int32_t depth_mode, depth_output;
+    Guard guard;
 };
 
 // Splat fields used by the blend, in registers (scalar registers in scalar-fetch mode).
@@ -138,6 +141,12 @@ __device__ __forceinline__ int find_view(const ViewInfo* vt, int views, uint32_t
 
 __device__ __forceinline__ float depth_map(float zh, int mode) {
     return mode == 1 ? 2.0f / (1.0f + expf(-0.1f * zh)) - 1.0f : zh;
+}
+
+// Derivative of the depth image w.r.t. zhat when the image is depth_map(zhat, mode) = y:
+// 0.05 (1 - y^2) for the logistic map (tanh(0.05 zhat)), 1 for the metric depth.
+__device__ __forceinline__ float depth_map_slope(float y, int mode) {
+    return mode == 1 ? 0.05f * (1.0f - y * y) : 1.0f;
 }
 
 __device__ __forceinline__ float dpp_f(float v, int ctrl) {
@@ -417,11 +426,12 @@ __global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_fwd
                 float out[3], z;
                 if (W[k] > 0.0f) {
                     const float zh = D[k] / W[k];
-                    z = depth_map(zh, a.depth_mode);
+                    const float zm = depth_map(zh, a.depth_mode);
                     const float Cc[3] = {C0[k], C1[k], C2[k]};
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
-                        out[c] = Cc[c] * expf(-m.Bd[c] * z) + m.Binf[c] * (1.0f - expf(-m.Bb[c] * z));
+                        out[c] = Cc[c] * expf(-m.Bd[c] * zm) + m.Binf[c] * (1.0f - expf(-m.Bb[c] * zm));
+                    z = a.depth_output == 1 ? depth_map(zh, 1) : zm;
                 } else {
                     z = 0.0f;
 #pragma unroll
@@ -434,6 +444,12 @@ __global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_fwd
                 rgb[2 * plane] = out[2];
                 a.out_depth[p] = z;
                 a.out_alpha[p] = W[k];
+                if (a.out_restored) {
+                    float* J = a.out_restored + 3 * vi.pix_base + (int64_t)py * vi.width + px;
+                    J[0] = C0[k];
+                    J[plane] = C1[k];
+                    J[2 * plane] = C2[k];
+                }
             }
         }
         const bool tile_alive = block_any<NW>(wave_alive, s_flag[2]);
@@ -547,6 +563,7 @@ __global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_bwd
     __shared__ uint32_t s_tile;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ox = (wave % S::NWX) * S::SW, oy = (wave / S::NWX) * S::SH;
+    if (guard_set(a.guard)) return;   // the forward was truncated: no gradient (uniform exit)
     for (uint32_t iter = 0;; ++iter) {
         const uint32_t tile = fetch_tile<NW, PERSISTENT>(a.queue, iter, &s_tile);
         if (tile >= a.tiles) break;
@@ -578,7 +595,7 @@ __global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_bwd
                 const float Cc[3] = {a.cair[p], a.cair[a.pixels + p], a.cair[2 * a.pixels + p]};
                 const float zh = a.dsum[p] / W;
                 const float z = depth_map(zh, a.depth_mode);
-                float dz = a.grad_depth ? a.grad_depth[p] : 0.0f;
+                float dz = 0.0f;
                 float A[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -589,10 +606,23 @@ __global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_bwd
                     pm[6 + c] += G[c] * (1.0f - Sb);
                     dz += G[c] * (m.Binf[c] * m.Bb[c] * Sb - m.Bd[c] * Cc[c] * A[c]);
                 }
-                const float dzh = a.depth_mode == 1 ? dz * 0.05f * (1.0f - z * z) : dz;
-                gC0[k] = G[0] * A[0];
-                gC1[k] = G[1] * A[1];
-                gC2[k] = G[2] * A[2];
+                // the medium's z and the depth image, each through its own map of zhat
+                float dzh = dz * depth_map_slope(z, a.depth_mode);
+                if (a.grad_depth) {
+                    const int dm = a.depth_output == 1 ? 1 : a.depth_mode;
+                    const float zo = a.depth_output == 1 ? depth_map(zh, 1) : z;
+                    dzh = fmaf(a.grad_depth[p], depth_map_slope(zo, dm), dzh);
+                }
+                float GJ[3] = {0.0f, 0.0f, 0.0f};
+                if (a.grad_restored) {
+                    const float* gj = a.grad_restored + 3 * vi.pix_base + (int64_t)py * vi.width + px;
+                    GJ[0] = gj[0];
+                    GJ[1] = gj[plane];
+                    GJ[2] = gj[2 * plane];
+                }
+                gC0[k] = fmaf(G[0], A[0], GJ[0]);
+                gC1[k] = fmaf(G[1], A[1], GJ[1]);
+                gC2[k] = fmaf(G[2], A[2], GJ[2]);
                 gD[k] = dzh / W;
                 gW[k] = -dzh * zh / W;
                 T[k] = a.tfinal[p];
@@ -830,6 +860,7 @@ struct MediumAdam {
     float b1, b2, eps;
     const float* bc;
     int32_t enabled;
+    Guard guard;
 };
 
 constexpr int kMedThreads = 9 * 64;   // thread t always reads component t % 9 of the [tiles][9] partials
@@ -841,6 +872,10 @@ __global__ __launch_bounds__(kMedThreads) void k_medium_reduce(const ViewInfo* _
     __shared__ float red[kMedThreads];
     const int v = blockIdx.x, tid = threadIdx.x;
     const ViewInfo vi = vt[v];
+    if (guard_set(ad.guard)) {   // truncated forward: no gradient and no step
+        if (tid < 9) grad_medium[v * 9 + tid] = 0.0f;
+        return;
+    }
     const float* p = medpart + (int64_t)vi.tile_base * 9;
     const int64_t total = (int64_t)vi.n_tiles * 9;
     float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -942,24 +977,25 @@ __global__ void k_stats_init(unsigned long long* out) {
 hipError_t launch_composite_fwd(const gs_options& o, const Layout& L, int phase, const ViewInfo* vt,
                                 const gs_medium* med, const Record* rec, const uint2* ranges, const uint32_t* vals,
                                 SavedHeader* hdr, uint32_t* alive, float* out_rgb, float* out_depth,
-                                float* out_alpha, float* tfinal, uint32_t* nlast, uint8_t* done, float* cair,
-                                float* dsum, float* wsum, hipStream_t s) {
+                                float* out_alpha, float* out_restored, float* tfinal, uint32_t* nlast, uint8_t* done,
+                                float* cair, float* dsum, float* wsum, hipStream_t s) {
     if (L.tiles == 0) return hipSuccess;
     FwdArgs a{vt, L.views, (uint32_t)L.tiles, phase, L.phases - 1, med, rec, ranges + (size_t)phase * L.tiles, vals,
-              &hdr->queue[phase], alive, &hdr->phase_alive[phase], out_rgb, out_depth, out_alpha, tfinal, nlast,
-              done, cair, dsum, wsum, L.pixels, o.alpha_min, o.alpha_max, o.t_min, o.depth_mode};
+              &hdr->queue[phase], alive, &hdr->phase_alive[phase], out_rgb, out_depth, out_alpha, out_restored,
+              tfinal, nlast, done, cair, dsum, wsum, L.pixels, o.alpha_min, o.alpha_max, o.t_min, o.depth_mode,
+              o.depth_output};
     return dispatch_shape<FwdRun>(o, a, o.persistent != 0, false, s);
 }
 
 hipError_t launch_composite_bwd(const gs_options& o, const Layout& L, const ViewInfo* vt, const gs_medium* med,
                                 const Record* rec, const uint2* ranges, const uint32_t* vals, const float* grad_rgb,
-                                const float* grad_depth, const float* tfinal, const uint32_t* nlast,
-                                const float* cair, const float* dsum, const float* wsum, float* grad2d,
-                                float* medpart, hipStream_t s) {
+                                const float* grad_depth, const float* grad_restored, const float* tfinal,
+                                const uint32_t* nlast, const float* cair, const float* dsum, const float* wsum,
+                                float* grad2d, float* medpart, const Guard& guard, hipStream_t s) {
     if (L.tiles == 0) return hipSuccess;
     BwdArgs a{vt, L.views, (uint32_t)L.tiles, L.phases, med, rec, ranges, vals, nullptr, grad_rgb, grad_depth,
-              tfinal, nlast, cair, dsum, wsum, grad2d, medpart, L.pixels, o.alpha_min, o.alpha_max, o.t_min,
-              o.depth_mode};
+              grad_restored, tfinal, nlast, cair, dsum, wsum, grad2d, medpart, L.pixels, o.alpha_min, o.alpha_max,
+              o.t_min, o.depth_mode, o.depth_output, guard};
     // the backward's persistent-mode tile counter lives after the medium partials
     a.queue = reinterpret_cast<uint32_t*>(medpart + L.tiles * 9);
     const bool pers = o.persistent != 0;
@@ -972,9 +1008,10 @@ hipError_t launch_composite_bwd(const gs_options& o, const Layout& L, const View
 
 hipError_t launch_medium_reduce(const ViewInfo* vt, int32_t views, const float* medpart, float* grad_medium,
                                 const gs_adam_group* adam, float b1, float b2, float eps, const float* bc,
-                                hipStream_t s) {
+                                const Guard& guard, hipStream_t s) {
     MediumAdam ad;
     memset(&ad, 0, sizeof(ad));
+    ad.guard = guard;
     if (adam) {
         ad.g = *adam;
         ad.b1 = b1;

@@ -83,6 +83,16 @@ struct Layout {
 
 int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_camera* cams, Layout* L);
 
+// The adjoint and optimizer kernels of a step do nothing when (*word & mask) != 0: the forward
+// they belong to overflowed the pair capacity (its render is truncated), or an earlier step of
+// a training run did (the sticky flag of the caller's training state).  word may be null.
+struct Guard {
+    const uint32_t* word;
+    uint32_t mask;
+};
+
+__device__ __forceinline__ bool guard_set(const Guard& g) { return g.word != nullptr && (*g.word & g.mask) != 0u; }
+
 // ---------------------------------------------------------------------------
 // Kernel launchers (each enqueues on `s` and returns hipGetLastError()).
 hipError_t launch_view_table(const ViewTable& t, int phases, ViewInfo* dst, SavedHeader* hdr, hipStream_t s);
@@ -119,6 +129,7 @@ struct AdamFused {
     float b1, b2, eps;
     const float* bc;
     float* shf;
+    Guard guard;   // fused steps: skip the step when set
 };
 
 hipError_t launch_project_bwd_adam(const gs_gaussians& g, int32_t views, const gs_camera* cams, const gs_options& o,
@@ -134,8 +145,10 @@ hipError_t launch_adam_sh(int64_t n, int sh_degree, const AdamFused& adam, hipSt
 constexpr int kShViewsW = 2;
 hipError_t launch_sh_views(const gs_gaussians& g, int32_t views, const gs_camera* cams,
                            const gs_gaussian_grads& grads, const AdamFused& adam, int fused, hipStream_t s);
-// step += 1 and bc = (1 / (1 - b1^step), 1 / (1 - b2^step)) on the device.
-hipError_t launch_adam_prep(int32_t* step, float b1, float b2, float* bc, hipStream_t s);
+// Training state (int32[2]: step, sticky skip flag) of a fused step: when *status reports a pair
+// overflow or state[1] is already set, state[1] |= the overflow bit and the step is skipped;
+// otherwise state[0] += 1 and bc = (1 / (1 - b1^step), 1 / (1 - b2^step)) on the device.
+hipError_t launch_adam_prep(int32_t* state, const uint32_t* status, float b1, float b2, float* bc, hipStream_t s);
 // Stable LSD radix sort of (key, value) u32 pairs over bits [bit0, bit0+nbits).  n is read from n_dev
 // (or n_host if n_dev is null).  Returns in *out_in_b whether the result sits in the B buffers.
 // With use_drop, keys equal to drop_key are left out; with n_kept the number of kept pairs is
@@ -187,27 +200,35 @@ hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uin
 // Copy the phase's tile-sorted values behind the earlier phases' and record its tile ranges.
 hipError_t launch_commit(const uint32_t* sorted_tiles, const uint32_t* sorted_vals, const SavedHeader* hdr,
                          int phase, int64_t tiles, int64_t max_pairs, uint32_t* vals, uint2* ranges, hipStream_t s);
+// out_restored (nullable): the in-air composite C_air per pixel, CHW per view like out_rgb.
 hipError_t launch_composite_fwd(const gs_options& o, const Layout& L, int phase, const ViewInfo* vt,
                                 const gs_medium* med, const Record* rec, const uint2* ranges, const uint32_t* vals,
                                 SavedHeader* hdr, uint32_t* alive, float* out_rgb, float* out_depth,
-                                float* out_alpha, float* tfinal, uint32_t* nlast, uint8_t* done, float* cair,
-                                float* dsum, float* wsum, hipStream_t s);
+                                float* out_alpha, float* out_restored, float* tfinal, uint32_t* nlast, uint8_t* done,
+                                float* cair, float* dsum, float* wsum, hipStream_t s);
+// grad_restored (nullable): upstream gradient of C_air, added to the colour accumulators' gradient.
 hipError_t launch_composite_bwd(const gs_options& o, const Layout& L, const ViewInfo* vt, const gs_medium* med,
                                 const Record* rec, const uint2* ranges, const uint32_t* vals, const float* grad_rgb,
-                                const float* grad_depth, const float* tfinal, const uint32_t* nlast,
-                                const float* cair, const float* dsum, const float* wsum, float* grad2d,
-                                float* medpart, hipStream_t s);
+                                const float* grad_depth, const float* grad_restored, const float* tfinal,
+                                const uint32_t* nlast, const float* cair, const float* dsum, const float* wsum,
+                                float* grad2d, float* medpart, const Guard& guard, hipStream_t s);
 // Per-view sums of the tiles' medium partials into grad_medium [views][9]; with `adam`, also one
 // Adam step of the medium parameters (group with count 9 * views) using the device bias corrections.
+// When the guard is set, grad_medium is zeroed and no step is taken.
 hipError_t launch_medium_reduce(const ViewInfo* vt, int32_t views, const float* medpart, float* grad_medium,
                                 const gs_adam_group* adam, float b1, float b2, float eps, const float* bc,
-                                hipStream_t s);
+                                const Guard& guard, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 hipError_t launch_export_keys(const Layout& L, const uint2* ranges, const uint32_t* vals, const uint32_t* depth_keys,
                               int64_t capacity, uint64_t* keys, uint32_t* values, hipStream_t s);
 hipError_t launch_forward_stats(const gs_options& o, const Layout& L, const ViewInfo* vt, const uint2* ranges,
                                 const uint32_t* vals, const Record* rec, const uint32_t* nlast, const uint8_t* done,
                                 unsigned long long* out, hipStream_t s);
+
+// Image loss (loss.hip): bytes of the per-tile partial sums, and the fused L1 + D-SSIM pass.
+int loss_partial_bytes(int32_t n_views, const gs_camera* cams, size_t* bytes);
+int launch_l1_dssim(int32_t n_views, const gs_camera* cams, const float* pred, const float* target, float lambda,
+                    float* loss, float* grad, float* partial, size_t partial_bytes, hipStream_t s);
 
 // Timer hooks (no-ops when timer == nullptr).
 void timer_begin(void* timer, const char* name, hipStream_t s);

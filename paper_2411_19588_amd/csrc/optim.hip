@@ -34,6 +34,16 @@ __global__ __launch_bounds__(kBlock) void k_activate_bwd(int64_t n, const float*
     }
 }
 
+// One group's activation (the Adam groups' encoding): 0 copy, 1 exp, 2 sigmoid.
+__global__ __launch_bounds__(kBlock) void k_activation(int64_t count, int32_t act, const float* __restrict__ x,
+                                                      float* __restrict__ y) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += stride) {
+        const float v = x[i];
+        y[i] = act == 1 ? expf(v) : (act == 2 ? sigmoidf_(v) : v);
+    }
+}
+
 __global__ void k_zero1(float* p) { *p = 0.0f; }
 
 // Few large workgroups: each adds its partial loss with one atomic on the single loss word,
@@ -85,13 +95,25 @@ struct AdamArgs {
     int32_t block0[kMaxGroups + 1];  // first workgroup of each group (one flat grid over all groups)
     float b1, b2, eps, ibc1, ibc2;   // 1 / (1 - beta^t)
     const int32_t* step_dev;         // if set, bias corrections come from this device step number
+                                     // (state[0]) and the step is skipped while state[1] != 0
 };
 
-__global__ void k_step_inc(int32_t* step) { *step += 1; }
+// Start of a device-counted step: a forward that overflowed the pair capacity (status, may be
+// null) sets the sticky skip flag; the counter advances only for a step that runs.
+__device__ __forceinline__ bool step_begin(int32_t* state, const uint32_t* status) {
+    const uint32_t st = status ? *status : 0u;
+    uint32_t skip = (uint32_t)state[GS_STATE_SKIP] | (st & GS_STATUS_PAIR_OVERFLOW);
+    state[GS_STATE_SKIP] = (int32_t)skip;
+    if (skip) return false;
+    state[GS_STATE_STEP] += 1;
+    return true;
+}
 
-__global__ void k_adam_prep(int32_t* step, float b1, float b2, float* bc) {
-    const int32_t t = *step + 1;
-    *step = t;
+__global__ void k_step_prep(int32_t* state, const uint32_t* status) { (void)step_begin(state, status); }
+
+__global__ void k_adam_prep(int32_t* state, const uint32_t* status, float b1, float b2, float* bc) {
+    if (!step_begin(state, status)) return;
+    const int32_t t = state[GS_STATE_STEP];
     bc[0] = 1.0f / (1.0f - powf(b1, (float)t));
     bc[1] = 1.0f / (1.0f - powf(b2, (float)t));
 }
@@ -128,7 +150,8 @@ __global__ __launch_bounds__(kBlock) void k_adam(AdamArgs a) {
     // everything read from the argument block with constant indices (no private copy)
     float ibc1 = a.ibc1, ibc2 = a.ibc2;
     if (a.step_dev) {
-        const float t = (float)*a.step_dev;
+        if (a.step_dev[GS_STATE_SKIP] != 0) return;   // skipped step (uniform exit)
+        const float t = (float)a.step_dev[GS_STATE_STEP];
         ibc1 = 1.0f / (1.0f - powf(a.b1, t));
         ibc2 = 1.0f / (1.0f - powf(a.b2, t));
     }
@@ -201,8 +224,8 @@ unsigned grid_for(int64_t n) {
 
 }  // namespace
 
-hipError_t launch_adam_prep(int32_t* step, float b1, float b2, float* bc, hipStream_t s) {
-    hipLaunchKernelGGL(k_adam_prep, dim3(1), dim3(1), 0, s, step, b1, b2, bc);
+hipError_t launch_adam_prep(int32_t* state, const uint32_t* status, float b1, float b2, float* bc, hipStream_t s) {
+    hipLaunchKernelGGL(k_adam_prep, dim3(1), dim3(1), 0, s, state, status, b1, b2, bc);
     return hipGetLastError();
 }
 
@@ -218,6 +241,14 @@ int gs_activate(int64_t n, const float* log_scales, const float* logits, float* 
     if (n == 0) return GS_OK;
     hipLaunchKernelGGL(k_activate, dim3(grid_for(3 * n)), dim3(kBlock), 0, static_cast<hipStream_t>(stream), n,
                        log_scales, logits, scales, opacity);
+    return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
+}
+
+int gs_activation(int64_t count, int32_t activation, const float* x, float* y, gs_stream_t stream) {
+    if (count < 0 || activation < 0 || activation > 2 || (count > 0 && (!x || !y))) return GS_ERR_INVALID_ARGUMENT;
+    if (count == 0) return GS_OK;
+    hipLaunchKernelGGL(k_activation, dim3(grid_for(count)), dim3(kBlock), 0, static_cast<hipStream_t>(stream), count,
+                       activation, x, y);
     return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }
 
@@ -245,7 +276,7 @@ int gs_l1_loss(int64_t count, const float* pred, const float* target, float* los
 }
 
 static int adam_launch(const gs_adam_group* host_groups, int32_t n_groups, float beta1, float beta2, float eps,
-                       int32_t step, int32_t* step_dev, gs_stream_t stream) {
+                       int32_t step, int32_t* step_dev, const void* saved, gs_stream_t stream) {
     if (!host_groups || n_groups < 1 || n_groups > kMaxGroups || (!step_dev && step < 1))
         return GS_ERR_INVALID_ARGUMENT;
     if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f))
@@ -269,7 +300,10 @@ static int adam_launch(const gs_adam_group* host_groups, int32_t n_groups, float
         a.ibc2 = (float)(1.0 / (1.0 - __builtin_pow((double)beta2, (double)step)));
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (step_dev) hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(1), 0, s, step_dev);
+    // the status word is the first field of the forward context's header
+    if (step_dev)
+        hipLaunchKernelGGL(k_step_prep, dim3(1), dim3(1), 0, s, step_dev,
+                           saved ? &static_cast<const SavedHeader*>(saved)->status : nullptr);
     int64_t blocks = 0;
     for (int k = 0; k < n_groups; ++k) {
         a.block0[k] = (int32_t)blocks;
@@ -283,13 +317,13 @@ static int adam_launch(const gs_adam_group* host_groups, int32_t n_groups, float
 
 int gs_adam_step(const gs_adam_group* host_groups, int32_t n_groups, float beta1, float beta2, float eps,
                  int32_t step, gs_stream_t stream) {
-    return adam_launch(host_groups, n_groups, beta1, beta2, eps, step, nullptr, stream);
+    return adam_launch(host_groups, n_groups, beta1, beta2, eps, step, nullptr, nullptr, stream);
 }
 
 int gs_adam_step_device(const gs_adam_group* host_groups, int32_t n_groups, float beta1, float beta2, float eps,
-                        int32_t* step_counter, gs_stream_t stream) {
-    if (!step_counter) return GS_ERR_INVALID_ARGUMENT;
-    return adam_launch(host_groups, n_groups, beta1, beta2, eps, 0, step_counter, stream);
+                        int32_t* state, const void* saved, gs_stream_t stream) {
+    if (!state) return GS_ERR_INVALID_ARGUMENT;
+    return adam_launch(host_groups, n_groups, beta1, beta2, eps, 0, state, saved, stream);
 }
 
 int gs_graph_begin(gs_stream_t stream) {

@@ -314,6 +314,7 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
     const int64_t n = g.n;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (FUSED && guard_set(adam.guard)) return;   // skipped training step: nothing changes
     const float mx = g.means[i], my = g.means[n + i], mz = g.means[2 * n + i];
     const float s[3] = {g.scales[i], g.scales[n + i], g.scales[2 * n + i]};
     const float qw = g.quats[i], qx = g.quats[n + i], qy = g.quats[2 * n + i], qz = g.quats[3 * n + i];
@@ -587,6 +588,7 @@ template <int DEG, int W>
 __global__ __launch_bounds__(kBlock) void k_adam_sh(int64_t n, AdamFused adam) {
     using VW = float __attribute__((ext_vector_type(W)));
     static_assert(kBlock == 256, "four waves per workgroup");
+    if (guard_set(adam.guard)) return;   // skipped training step (the whole workgroup leaves)
     __shared__ float sP[4][3][W][64];
     const int sub = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t i0 = ((int64_t)blockIdx.x * 64 + lane) * W;
@@ -669,6 +671,7 @@ __global__ __launch_bounds__(kBlock) void k_sh_views(gs_gaussians g, int32_t vie
                                                     gs_gaussian_grads out, AdamFused adam) {
     using VW = float __attribute__((ext_vector_type(W)));
     static_assert(kBlock == 256, "four waves per workgroup");
+    if (FUSED && guard_set(adam.guard)) return;   // skipped training step (the whole workgroup leaves)
     constexpr int NC = (DEG + 1) * (DEG + 1);
     constexpr int KS = (NC + 3) / 4;   // coefficients per wave, at most
     __shared__ float sP[4][3][W][64];

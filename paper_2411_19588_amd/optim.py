@@ -43,8 +43,13 @@ class Group:
         self.m = z() if self.m is None else self.m
         self.v = z() if self.v is None else self.v
         if self.activation and self.activated is None:
-            # one-time set-up of the activated copy; every step refreshes it in the kernel
-            self.activated = torch.exp(self.param) if self.activation == "exp" else torch.sigmoid(self.param)
+            # one-time set-up of the activated copy (gs_activation); every step refreshes it in the kernel
+            self.activated = torch.empty_like(self.param)
+            s = torch.cuda.current_stream(self.param.device)
+            N.check("gs_activation", N.lib().gs_activation(self.param.numel(), _ACT[self.activation],
+                                                           ctypes.c_void_p(self.param.data_ptr()),
+                                                           ctypes.c_void_p(self.activated.data_ptr()),
+                                                           ctypes.c_void_p(s.cuda_stream)))
 
 
 class FusedAdam:

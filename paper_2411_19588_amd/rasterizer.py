@@ -30,7 +30,8 @@ class RasterConfig:
     t_min: float = 1e-4
     dilation: float = 0.3
     kappa: float = 11.1
-    depth_mode: int = 0
+    depth_mode: int = 0               # z of the medium term: 0 metric, 1 logistic map
+    depth_output: int = 0             # depth image: 0 the medium's z, 1 the logistic map (visualisation)
     tile_cull: bool = True            # drop (Gaussian, tile) pairs that cannot reach alpha_min
     phases: int = 0                   # 0 = automatic (the library's gs_schedule)
     phase0_shift: int = 0             # 0 = automatic
@@ -50,6 +51,7 @@ class RasterConfig:
         o.dilation = self.dilation
         o.kappa = self.kappa
         o.depth_mode = int(self.depth_mode)
+        o.depth_output = int(self.depth_output)
         o.tile_cull = 1 if self.tile_cull else 0
         o.phases = int(self.phases)
         o.phase0_shift = int(self.phase0_shift)
@@ -79,6 +81,11 @@ class ForwardContext:
     max_pairs: int
     n: int
     sh_degree: int
+    # the cameras of this forward (a device copy and the host array): the adjoint must see the
+    # poses the forward used even if the rasterizer's cameras are changed in between
+    dev_cams: Optional[torch.Tensor] = None
+    host_cams: Optional[ctypes.Array] = None
+    restored: Optional[torch.Tensor] = None   # the clean image J = C_air, when requested
 
 
 class Rasterizer:
@@ -148,12 +155,13 @@ class Rasterizer:
         return N.GsGaussians(n, sh_degree, 0, _ptr(means), _ptr(scales), _ptr(quats), _ptr(opacity), _ptr(sh))
 
     def forward(self, means, scales, quats, opacity, sh, sh_degree: int, medium: torch.Tensor,
-                check: bool = True, max_pairs: Optional[int] = None, stream=None):
+                check: bool = True, max_pairs: Optional[int] = None, stream=None, restored: bool = False):
         """Render all views.  Returns (rgb, depth, alpha, ForwardContext).
 
         With check=True the status word is read after the forward (one host
         synchronisation); on pair-capacity overflow the capacity is grown to
-        what the forward needed and the render is repeated.
+        what the forward needed and the render is repeated.  With restored=True
+        the clean image J = C_air (packed like rgb) is returned in ctx.restored.
         """
         means, scales, quats, opacity, sh = map(_f32, (means, scales, quats, opacity, sh))
         medium = _f32(medium)
@@ -168,10 +176,12 @@ class Rasterizer:
             rgb = torch.empty(3 * self.total_pixels, dtype=torch.float32, device=self.device)
             depth = torch.empty(self.total_pixels, dtype=torch.float32, device=self.device)
             alpha = torch.empty(self.total_pixels, dtype=torch.float32, device=self.device)
+            rest = torch.empty(3 * self.total_pixels, dtype=torch.float32, device=self.device) if restored else None
             o = self.config.to_c(mp, self.timer)
             N.check("gs_render_forward", L.gs_render_forward(
                 ctypes.byref(o), ctypes.byref(g), self.n_views, self.host_cams, _ptr(self.dev_cams), _ptr(medium),
-                _ptr(rgb), _ptr(depth), _ptr(alpha), _ptr(saved), sv_b, _ptr(ws), ws_b, _stream(stream)))
+                _ptr(rgb), _ptr(depth), _ptr(alpha), _ptr(rest), _ptr(saved), sv_b, _ptr(ws), ws_b,
+                _stream(stream)))
             if not check:
                 break
             status, needed = self.read_status(saved, stream)
@@ -182,18 +192,25 @@ class Rasterizer:
                 self.max_pairs = mp
                 continue
             break
-        return rgb, depth, alpha, ForwardContext(saved, mp, n, sh_degree)
+        host_copy = (N.GsCamera * self.n_views)()
+        ctypes.memmove(host_copy, self.host_cams, ctypes.sizeof(host_copy))
+        return rgb, depth, alpha, ForwardContext(saved, mp, n, sh_degree, self.dev_cams.clone(), host_copy, rest)
 
     def backward(self, ctx: ForwardContext, means, scales, quats, opacity, sh, medium, grad_rgb,
-                 grad_depth=None, stream=None, out=None):
+                 grad_depth=None, stream=None, out=None, grad_restored=None):
         """Adjoint of forward(); returns (d_means, d_scales, d_quats, d_opacity, d_sh, d_medium).
 
-        `out` may supply those six tensors (contiguous float32, same shapes) to be overwritten.
+        The cameras are those the forward used (kept in `ctx`).  `out` may supply those six
+        tensors (contiguous float32, same shapes) to be overwritten.  grad_restored is the
+        upstream gradient of the clean image J (packed like rgb), or None.
         """
         means, scales, quats, opacity, sh = map(_f32, (means, scales, quats, opacity, sh))
         medium = _f32(medium)
         grad_rgb = _f32(grad_rgb)
         grad_depth = None if grad_depth is None else _f32(grad_depth)
+        grad_restored = None if grad_restored is None else _f32(grad_restored)
+        host_cams = self.host_cams if ctx.host_cams is None else ctx.host_cams
+        dev_cams = self.dev_cams if ctx.dev_cams is None else ctx.dev_cams
         n = ctx.n
         ws_b, sv_b = self.sizes_for(n, ctx.max_pairs)
         ws = self.workspace(ws_b)
@@ -209,9 +226,9 @@ class Rasterizer:
         grads = N.GsGaussianGrads(*[_ptr(t) for t in outs])
         o = self.config.to_c(ctx.max_pairs, self.timer)
         N.check("gs_render_backward", N.lib().gs_render_backward(
-            ctypes.byref(o), ctypes.byref(g), self.n_views, self.host_cams, _ptr(self.dev_cams), _ptr(medium),
-            _ptr(grad_rgb), _ptr(grad_depth), _ptr(ctx.saved), sv_b, ctypes.byref(grads), _ptr(gmed), _ptr(ws),
-            ws_b, _stream(stream)))
+            ctypes.byref(o), ctypes.byref(g), self.n_views, host_cams, _ptr(dev_cams), _ptr(medium),
+            _ptr(grad_rgb), _ptr(grad_depth), _ptr(grad_restored), _ptr(ctx.saved), sv_b, ctypes.byref(grads),
+            _ptr(gmed), _ptr(ws), ws_b, _stream(stream)))
         return (*outs, gmed)
 
     def read_status(self, saved: torch.Tensor, stream=None) -> Tuple[int, int]:
@@ -259,22 +276,26 @@ class Rasterizer:
 
 class _RenderFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, means, scales, quats, opacity, sh, medium, rast: Rasterizer, sh_degree: int):
-        rgb, depth, alpha, fctx = rast.forward(means, scales, quats, opacity, sh, sh_degree, medium)
+    def forward(ctx, means, scales, quats, opacity, sh, medium, rast: Rasterizer, sh_degree: int,
+                restored: bool = False):
+        rgb, depth, alpha, fctx = rast.forward(means, scales, quats, opacity, sh, sh_degree, medium,
+                                               restored=restored)
         ctx.save_for_backward(means, scales, quats, opacity, sh, medium)
         ctx.rast = rast
         ctx.fctx = fctx
         ctx.mark_non_differentiable(alpha)
+        if restored:
+            return rgb, depth, alpha, fctx.restored
         return rgb, depth, alpha
 
     @staticmethod
-    def backward(ctx, g_rgb, g_depth, g_alpha):
+    def backward(ctx, g_rgb, g_depth, g_alpha, g_restored=None):
         means, scales, quats, opacity, sh, medium = ctx.saved_tensors
         if g_rgb is None:
             g_rgb = torch.zeros(3 * ctx.rast.total_pixels, dtype=torch.float32, device=means.device)
         gm, gs_, gq, go, gsh, gmed = ctx.rast.backward(ctx.fctx, means, scales, quats, opacity, sh, medium,
-                                                       g_rgb, g_depth)
-        return gm, gs_, gq, go, gsh, gmed.view_as(medium), None, None
+                                                       g_rgb, g_depth, grad_restored=g_restored)
+        return gm, gs_, gq, go, gsh, gmed.view_as(medium), None, None, None
 
 
 class _ActivateFn(torch.autograd.Function):
@@ -309,14 +330,15 @@ def activate(log_scales: torch.Tensor, logits: torch.Tensor):
     return _ActivateFn.apply(log_scales, logits)
 
 
-def render(means, scales, quats, opacity, sh, medium, rast: Rasterizer, sh_degree: int):
+def render(means, scales, quats, opacity, sh, medium, rast: Rasterizer, sh_degree: int, restored: bool = False):
     """Differentiable render of all views of `rast`.
 
     means [3,N], scales [3,N] (activated), quats [4,N], opacity [N] (activated),
-    sh [(deg+1)^2*3, N], medium [V,9].  Returns packed (rgb, depth, alpha);
-    gradients flow to every input but alpha (non-differentiable output).
+    sh [(deg+1)^2*3, N], medium [V,9].  Returns packed (rgb, depth, alpha), and with
+    restored=True also the clean image J = C_air (packed like rgb, eq. scattering_approx);
+    gradients flow from every output but alpha (non-differentiable) to every input.
     """
-    return _RenderFn.apply(means, scales, quats, opacity, sh, medium, rast, sh_degree)
+    return _RenderFn.apply(means, scales, quats, opacity, sh, medium, rast, sh_degree, restored)
 
 
 def l1_loss(pred: torch.Tensor, target: torch.Tensor, with_loss: bool = True):
@@ -327,4 +349,25 @@ def l1_loss(pred: torch.Tensor, target: torch.Tensor, with_loss: bool = True):
     loss = torch.empty(1, dtype=torch.float32, device=pred.device) if with_loss else None
     N.check("gs_l1_loss", N.lib().gs_l1_loss(pred.numel(), _ptr(pred), _ptr(target), _ptr(loss), _ptr(grad),
                                               _stream()))
+    return loss, grad
+
+
+def l1_dssim_loss(pred: torch.Tensor, target: torch.Tensor, rast: Rasterizer, lam: float = 0.3,
+                  with_loss: bool = True, workspace: Optional[torch.Tensor] = None):
+    """(loss [V + 1] or None, grad) of sum_v (1 - lam) L1_v + lam D-SSIM_v via gs_l1_dssim_loss.
+
+    pred and target are packed like the rasterizer's rgb output; loss holds each view's term and
+    then their sum (eq. 3DGSoriginalLoss with lambda = 0.3 in the paper)."""
+    pred = _f32(pred)
+    target = _f32(target)
+    L = N.lib()
+    need = ctypes.c_size_t()
+    N.check("gs_loss_workspace_query", L.gs_loss_workspace_query(rast.n_views, rast.host_cams, ctypes.byref(need)))
+    if workspace is None or workspace.numel() < need.value:
+        workspace = torch.empty(max(need.value, 256), dtype=torch.uint8, device=pred.device)
+    grad = torch.empty_like(pred)
+    loss = torch.empty(rast.n_views + 1, dtype=torch.float32, device=pred.device) if with_loss else None
+    N.check("gs_l1_dssim_loss", L.gs_l1_dssim_loss(rast.n_views, rast.host_cams, _ptr(pred), _ptr(target), float(lam),
+                                                   _ptr(loss), _ptr(grad), _ptr(workspace), workspace.numel(),
+                                                   _stream()))
     return loss, grad

@@ -4,14 +4,19 @@ forward (projection, depth-progressive binning, compositing with the medium)
 -> L1 loss and its gradient -> adjoint -> Adam with the activation epilogue
 (Sec. Optimization), all enqueued on one stream through the C ABI with fixed
 pointers, so the whole step can be captured into a HIP graph and replayed.
-By default the adjoint writes the gradients and the separate Adam kernel
-updates every parameter group in one launch; `fused=True` runs the Adam step
-inside the projection adjoint instead (gs_render_backward_adam: the Gaussians'
-gradients never reach memory, but that kernel's register use leaves it two
-waves per SIMD, and on the 1M-Gaussian benchmark it is slower than the two
-kernels).  Raw
-parameters: means, log-scales, quaternions, opacity logits, SH and the per-view
-medium coefficients.
+With `fused=True` (what the benchmark trains with: faster on the 1M-Gaussian
+1080p step) the Adam step runs inside the projection adjoint
+(gs_render_backward_adam: the Gaussians' gradients never reach memory, and the
+SH coefficients and means are stepped by a second kernel from the two factors
+of their gradient); with `fused=False` the adjoint writes the gradients and
+one flat Adam launch updates every group.  Raw parameters: means, log-scales,
+quaternions, opacity logits, SH and the per-view medium coefficients.
+
+A step whose forward overflows the pair capacity is not applied: the device
+training state (`state`, int32[2]: step counter, sticky skip flag) records it,
+every later step is skipped too until `clear_skip()` (after the capacity has
+been grown), so a replayed graph never updates the parameters from a truncated
+render.
 """
 from __future__ import annotations
 
@@ -57,14 +62,10 @@ class TrainStep:
         self.alpha = torch.empty(P, dtype=torch.float32, device=dev)
         self.grad_rgb = torch.empty(3 * P, dtype=torch.float32, device=dev)
         self.loss = torch.empty(1, dtype=torch.float32, device=dev)
-        self.step_counter = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.state = torch.zeros(2, dtype=torch.int32, device=dev)   # (Adam step, sticky skip flag)
         self.graph = None
         self.timer = None
-        # A0: activated scales and opacities for the first forward
-        s = torch.cuda.current_stream(dev)
-        N.check("gs_activate", N.lib().gs_activate(self.n, _vp(self.G["log_scales"].param),
-                                                   _vp(self.G["logits"].param), _vp(self.G["log_scales"].activated),
-                                                   _vp(self.G["logits"].activated), ctypes.c_void_p(s.cuda_stream)))
+        # A0: the groups hold the activated scales and opacities for the first forward (gs_activation)
         self._gauss = N.GsGaussians(self.n, self.sh_degree, 0, _vp(self.G["means"].param),
                                     _vp(self.G["log_scales"].activated), _vp(self.G["quats"].param),
                                     _vp(self.G["logits"].activated), _vp(self.G["sh"].param))
@@ -110,7 +111,7 @@ class TrainStep:
         N.check("gs_render_forward", N.lib().gs_render_forward(
             ctypes.byref(self.opts), ctypes.byref(self._gauss), self.rast.n_views, self.rast.host_cams,
             _vp(self.rast.dev_cams), _vp(self.G["medium"].param), _vp(self.rgb), _vp(self.depth), _vp(self.alpha),
-            _vp(self.saved), self.saved.numel(), _vp(self.ws), self.ws.numel(), sp))
+            None, _vp(self.saved), self.saved.numel(), _vp(self.ws), self.ws.numel(), sp))
 
     def enqueue(self, stream=None) -> None:
         """Enqueue one training step on `stream` (no host synchronisation)."""
@@ -123,17 +124,31 @@ class TrainStep:
         if self.fused:
             N.check("gs_render_backward_adam", L.gs_render_backward_adam(
                 ctypes.byref(self.opts), ctypes.byref(self._gauss), self.rast.n_views, self.rast.host_cams,
-                _vp(self.rast.dev_cams), _vp(self.G["medium"].param), _vp(self.grad_rgb), None, _vp(self.saved),
-                self.saved.numel(), self._adam, 0.9, 0.999, 1e-8, _vp(self.step_counter), _vp(self.ws),
+                _vp(self.rast.dev_cams), _vp(self.G["medium"].param), _vp(self.grad_rgb), None, None,
+                _vp(self.saved), self.saved.numel(), self._adam, 0.9, 0.999, 1e-8, _vp(self.state), _vp(self.ws),
                 self.ws.numel(), sp))
             return
         N.check("gs_render_backward", L.gs_render_backward(
             ctypes.byref(self.opts), ctypes.byref(self._gauss), self.rast.n_views, self.rast.host_cams,
-            _vp(self.rast.dev_cams), _vp(self.G["medium"].param), _vp(self.grad_rgb), None, _vp(self.saved),
+            _vp(self.rast.dev_cams), _vp(self.G["medium"].param), _vp(self.grad_rgb), None, None, _vp(self.saved),
             self.saved.numel(), ctypes.byref(self._grads), _vp(self.G["medium"].grad), _vp(self.ws),
             self.ws.numel(), sp))
         N.check("gs_adam_step_device", L.gs_adam_step_device(self._adam, len(self.groups), 0.9, 0.999, 1e-8,
-                                                             _vp(self.step_counter), sp))
+                                                             _vp(self.state), _vp(self.saved), sp))
+
+    # ------------------------------------------------------------------ training state
+    @property
+    def step_counter(self) -> torch.Tensor:
+        """The device Adam step counter (a view of state[0])."""
+        return self.state[N.GS_STATE_STEP:N.GS_STATE_STEP + 1]
+
+    def skipped(self) -> int:
+        """Sticky skip flag (GS_STATUS_* bits of the overflow that stopped the updates; synchronises)."""
+        return int(self.state[N.GS_STATE_SKIP].item())
+
+    def clear_skip(self) -> None:
+        """Let steps apply again (after the capacity has been grown to what the forward needs)."""
+        self.state[N.GS_STATE_SKIP].zero_()
 
     # ------------------------------------------------------------------ graph
     def capture(self, stream: torch.cuda.Stream) -> None:
@@ -231,7 +246,7 @@ class RenderStep:
     def _forward(self, stream) -> None:
         N.check("gs_render_forward", N.lib().gs_render_forward(
             ctypes.byref(self.opts), ctypes.byref(self._gauss), self.rast.n_views, self.rast.host_cams,
-            _vp(self.rast.dev_cams), _vp(self.medium), _vp(self.rgb), _vp(self.depth), _vp(self.alpha),
+            _vp(self.rast.dev_cams), _vp(self.medium), _vp(self.rgb), _vp(self.depth), _vp(self.alpha), None,
             _vp(self.saved), self.saved.numel(), _vp(self.ws), self.ws.numel(), ctypes.c_void_p(stream.cuda_stream)))
 
     def enqueue(self, stream=None) -> None:
@@ -243,7 +258,7 @@ class RenderStep:
                                            _vp(self.grad_rgb), sp))
         N.check("gs_render_backward", L.gs_render_backward(
             ctypes.byref(self.opts), ctypes.byref(self._gauss), self.rast.n_views, self.rast.host_cams,
-            _vp(self.rast.dev_cams), _vp(self.medium), _vp(self.grad_rgb), None, _vp(self.saved),
+            _vp(self.rast.dev_cams), _vp(self.medium), _vp(self.grad_rgb), None, None, _vp(self.saved),
             self.saved.numel(), ctypes.byref(self._grads), _vp(self.grad_medium), _vp(self.ws), self.ws.numel(),
             sp))
 

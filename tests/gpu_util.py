@@ -68,7 +68,10 @@ def compare_pixels(gpu_rgb, gpu_depth, gpu_alpha, orc, tol=IMG_TOL, max_ambiguou
         k = int(np.nonzero(~ok)[0][0])
         raise AssertionError(f"{n_bad} pixels differ (first {k}: gpu {got[k]} oracle {ref[k]} err {err[k]:.3g})")
     assert n_var <= max(1, max_ambiguous_frac * len(ref)), f"{n_var} ambiguous pixels"
-    return int(np.count_nonzero(err <= tol)), n_var, worst
+    n_main = int(np.count_nonzero(err <= tol))
+    say(f"  image parity: {len(ref)} pixels, {n_main} match the oracle, {n_var} match a near-threshold "
+        f"variant, worst error {worst:.2e}")
+    return n_main, n_var, worst
 
 
 def pixel_list(w, h):
@@ -101,6 +104,7 @@ def unambiguous(O, scene, v, G, opts=None, Gz=None):
     if Gz is not None:
         Gz = np.array(Gz, copy=True)
         Gz[amb] = 0.0
+    say(f"  gradient parity: {int(amb.sum())} of {len(amb)} pixels masked (near-threshold decision)")
     return G, Gz, int(amb.sum())
 
 
@@ -117,3 +121,157 @@ def grad_close(got, ref, rel=1e-3, name=""):
         raise AssertionError(f"{name}: {int(bad.sum())}/{ref.size} elements off, block rel {blk:.3g}, "
                              f"worst at {idx}: got {got[idx]} ref {ref[idx]} (rms {rms:.3g})")
     return blk
+
+
+def first_moment_check(O, sc, ts, view, crop, stream, rel=1e-3):
+    """After one training step, m = (1 - beta1) g: compare m / (1 - beta1) of every group with the oracle's
+    gradient of the same L1 loss.  The target equals the GPU image outside `crop` (x0, y0, w, h) of
+    `view` and at the crop's pixels whose forward has a near-threshold decision, so the L1 gradient
+    sign(C - target) / numel is zero there and the oracle needs only the crop's other pixels."""
+    x0, y0, w, h = crop
+    cam = sc.cameras[view]
+    with torch.cuda.stream(stream):
+        ts._forward(stream)
+        torch.cuda.synchronize()
+    img = [x.detach().cpu().numpy() for x, _, _ in ts.rast.split(ts.rgb, ts.depth, ts.alpha)]
+    tgt = [x.copy() for x in img]
+    pix = np.stack(np.meshgrid(np.arange(x0, x0 + w), np.arange(y0, y0 + h), indexing="xy"), -1).reshape(-1, 2)
+    pix = np.ascontiguousarray(pix.astype(np.int32))
+    amb = O.render(sc, cam, sc.medium[view], pixels=pix, variants=1)["nvar"] > 0
+    rnd = np.random.default_rng(31).uniform(size=(len(pix), 3)).astype(np.float32)
+    keep = ~amb
+    tgt[view][:, pix[keep, 1], pix[keep, 0]] = rnd[keep].T
+    ts.target.copy_(torch.cat([torch.from_numpy(t).reshape(-1) for t in tgt]).to(ts.target.device))
+    with torch.cuda.stream(stream):
+        ts.enqueue(stream)
+        torch.cuda.synchronize()
+    assert ts.skipped() == 0 and int(ts.step_counter.item()) == 1
+    numel = 3 * ts.rast.total_pixels
+    g_img = img[view][:, pix[:, 1], pix[:, 0]].T.astype(np.float64)
+    G = np.sign(g_img - tgt[view][:, pix[:, 1], pix[:, 0]].T.astype(np.float64)) / numel
+    U.say(f"  first moments: {int(keep.sum())} crop pixels with a gradient, {int(amb.sum())} ambiguous")
+    ref = O.backward(sc, cam, sc.medium[view], G, pixels=pix)
+    b1 = np.float32(1.0) - np.float32(0.9)
+    m = {g.name: g.m.detach().cpu().numpy().astype(np.float64) / float(b1) for g in ts.groups}
+    s = sc.scales.astype(np.float64)
+    o = sc.opacity.astype(np.float64)
+    live = np.nonzero(np.any(ref["g2d"] != 0, axis=1))[0]
+    assert live.size > 20
+    others = np.setdiff1d(np.random.default_rng(37).choice(sc.n, 200, replace=False), live)
+    idx = np.concatenate([live, others])
+    U.grad_close(m["means"][:, idx], ref["means"][:, idx], rel, "means")
+    U.grad_close(m["log_scales"][:, idx], (ref["scales"] * s)[:, idx], rel, "log_scales")
+    U.grad_close(m["quats"][:, idx], ref["quats"][:, idx], rel, "quats")
+    U.grad_close(m["logits"][idx], (ref["opacity"] * o * (1 - o))[idx], rel, "logits")
+    U.grad_close(m["sh"][:, idx], ref["sh"][:, idx], rel, "sh")
+    U.grad_close(m["medium"].reshape(-1, 9)[view], ref["medium"], rel, "medium")
+    for v in range(len(sc.cameras)):
+        if v != view:
+            assert np.all(m["medium"].reshape(-1, 9)[v] == 0.0)
+    return live.size
+
+
+def crop_pixels(crop):
+    """Integer pixels (P, 2) of the rectangle crop = (x0, y0, w, h), row-major."""
+    x0, y0, w, h = crop
+    ys, xs = np.meshgrid(np.arange(y0, y0 + h), np.arange(x0, x0 + w), indexing="ij")
+    return np.ascontiguousarray(np.stack([xs.ravel(), ys.ravel()], 1).astype(np.int32))
+
+
+FIELDS = ("means", "scales", "quats", "opacity", "sh")
+
+
+def crop_grad_check(O, sc, rast, view, crop, seed, rel=1e-3, n_pick=200):
+    """Gradient of L = <G, C_uw> with G ~ N(0, 1) on the crop of `view` (zero elsewhere, in the other views
+    and at the crop's near-threshold pixels) through the GPU adjoint, against the oracle's exact gradient
+    for n_pick sampled Gaussians (every Gaussian that reaches the crop, or a sample of them, plus others
+    whose gradient must be exactly zero) and every view's medium gradient.  Returns
+    (got, ref, Gc, pix, live)."""
+    cam = sc.cameras[view]
+    pix = crop_pixels(crop)
+    rng = np.random.default_rng(seed)
+    Gc = rng.normal(size=(len(pix), 3))
+    amb = O.render(sc, cam, sc.medium[view], pixels=pix, variants=1)["nvar"] > 0
+    Gc[amb] = 0.0
+    say(f"  crop {crop} of view {view}: {int(amb.sum())} of {len(pix)} pixels masked (near-threshold decision)")
+    rgb, depth, alpha, ctx, d = forward(sc, rast)
+    st, _ = rast.read_status(ctx.saved)
+    assert st == 0
+    planes = []
+    for w, c in enumerate(sc.cameras):
+        G = np.zeros((c.height, c.width, 3))
+        if w == view:
+            G[pix[:, 1], pix[:, 0]] = Gc
+        planes.append(np.ascontiguousarray(G.transpose(2, 0, 1)).reshape(-1))
+    g_rgb = torch.from_numpy(np.concatenate(planes).astype(np.float32)).to(DEV)
+    out = rast.backward(ctx, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["medium"], g_rgb, None)
+    torch.cuda.synchronize()
+    got = dict(zip(FIELDS + ("medium",), [t.cpu().numpy().astype(np.float64) for t in out]))
+    ref = O.backward(sc, cam, sc.medium[view], Gc, pixels=pix)
+    live = np.nonzero(np.abs(ref["g2d"]).sum(axis=1) > 0)[0]
+    assert live.size >= 20, live.size
+    if live.size >= n_pick:
+        pick = np.sort(rng.choice(live, n_pick, replace=False))
+    else:
+        rest = rng.choice(np.setdiff1d(np.arange(sc.n), live), n_pick - live.size, replace=False)
+        pick = np.sort(np.concatenate([live, rest]))
+    say(f"  {live.size} Gaussians reach the crop; checking {n_pick}")
+    for f in FIELDS:
+        grad_close(got[f][..., pick], ref[f][..., pick], rel, f)
+    med = got["medium"].reshape(len(sc.cameras), 9)
+    grad_close(med[view], ref["medium"], rel, "medium")
+    assert np.all(np.delete(med, view, axis=0) == 0.0)
+    dead = np.setdiff1d(np.arange(sc.n), live)[:5000]
+    assert np.all(got["opacity"][dead] == 0.0)
+    return got, ref, Gc, pix, live
+
+
+def fd_crop_check(O, sc, view, crop, Gc, got, ref, live, n_gauss, tile=16, rel=1e-3):
+    """FP64 central differences of the oracle for every parameter (59 at SH degree 3) of the n_gauss
+    Gaussians with the largest opacity gradient on the crop, against the GPU gradient `got`.
+
+    Each difference re-renders only what can change: the Gaussians whose FP32 tile rectangle meets the
+    crop's tiles (ascending index, so depth ties keep their order; checked to render the crop exactly
+    as the full scene does) over the crop pixels inside the perturbed Gaussian's own rectangle (no other
+    pixel can reach alpha >= 1/255 for it, the coverage invariant the oracle pins)."""
+    cam = sc.cameras[view]
+    x0, y0, w, h = crop
+    pix = crop_pixels(crop)
+    _, rect, culled = O.key_path(sc, cam)
+    tx0, ty0, tx1, ty1 = x0 // tile, y0 // tile, (x0 + w - 1) // tile, (y0 + h - 1) // tile
+    touch = (~culled) & (rect[:, 0] <= tx1) & (rect[:, 2] >= tx0) & (rect[:, 1] <= ty1) & (rect[:, 3] >= ty0)
+    idx = np.nonzero(touch)[0]
+    from paper_2411_19588_amd import synth
+    sub = synth.Scene(means=sc.means[:, idx], log_scales=sc.log_scales[:, idx], scales=sc.scales[:, idx],
+                      quats=sc.quats[:, idx], logits=sc.logits[idx], opacity=sc.opacity[idx], sh=sc.sh[:, idx],
+                      sh_degree=sc.sh_degree, cameras=[cam], medium=sc.medium[view:view + 1])
+    med = sc.medium[view].astype(np.float64)
+    full = O.render(sc, cam, med, pixels=pix)
+    part = O.render(sub, cam, med, pixels=pix)
+    for key in ("rgb", "depth", "alpha"):
+        assert np.array_equal(full[key], part[key]), key
+    pos = {int(g): j for j, g in enumerate(idx)}
+    order = live[np.argsort(-np.abs(ref["opacity"][live]))][:n_gauss]
+    ncoef3 = (sc.sh_degree + 1) ** 2 * 3
+    rows = dict(means=3, scales=3, quats=4, opacity=0, sh=ncoef3)
+    scale = {f: float(np.sqrt(np.mean(ref[f][..., live] ** 2))) for f in rows}
+    checked = total = 0
+    for g in order:
+        j = pos[int(g)]
+        gx0, gy0, gx1, gy1 = rect[g]
+        inside = ((pix[:, 0] // tile >= gx0) & (pix[:, 0] // tile <= gx1) &
+                  (pix[:, 1] // tile >= gy0) & (pix[:, 1] // tile <= gy1))
+        p_g, G_g = np.ascontiguousarray(pix[inside]), Gc[inside]
+        for f, nr in rows.items():
+            for r in (range(nr) if nr else [None]):
+                total += 1
+                fd, ok = O.fd_grad(sub, cam, med, G_g, f, (j,) if r is None else (r, j), pixels=p_g)
+                if not ok:
+                    continue
+                gv = got[f][g] if r is None else got[f][r, g]
+                assert abs(gv - fd) <= rel * abs(fd) + rel * scale[f], (f, r, int(g), gv, fd)
+                checked += 1
+    say(f"  finite differences: {checked} of {total} parameters of {len(order)} Gaussians "
+        f"({idx.size} Gaussians re-rendered per difference)")
+    assert checked >= 0.8 * total
+    return checked

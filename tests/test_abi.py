@@ -117,7 +117,8 @@ def test_workspace_query_and_tile_count():
     ("pixels_per_lane", 8, N.GS_ERR_INVALID_ARGUMENT), ("record_fetch", 3, N.GS_ERR_INVALID_ARGUMENT),
     ("record_fetch", -1, N.GS_ERR_INVALID_ARGUMENT), ("phase0_shift", 21, N.GS_ERR_INVALID_ARGUMENT),
     ("phase0_shift", -1, N.GS_ERR_INVALID_ARGUMENT), ("tile_cull", 2, N.GS_ERR_INVALID_ARGUMENT),
-    ("phases", 9, N.GS_ERR_INVALID_ARGUMENT), ("phases", -1, N.GS_ERR_INVALID_ARGUMENT)])
+    ("phases", 9, N.GS_ERR_INVALID_ARGUMENT), ("phases", -1, N.GS_ERR_INVALID_ARGUMENT),
+    ("depth_output", 2, N.GS_ERR_INVALID_ARGUMENT), ("depth_output", -1, N.GS_ERR_INVALID_ARGUMENT)])
 def test_bad_options_rejected(field, value, code):
     sc = synth.make_scene(0, n=10)
     cams = N.camera_array(sc.cameras)
@@ -133,19 +134,25 @@ def test_bad_arguments_rejected_before_any_device_work():
     cams = N.camera_array(sc.cameras)
     o = N.default_options()
     g = N.GsGaussians(10, 0, 0, None, None, None, None, None)     # null parameter arrays
-    rc = L.gs_render_forward(ctypes.byref(o), ctypes.byref(g), 1, cams, None, None, None, None, None, None, 0,
-                             None, 0, None)
+    rc = L.gs_render_forward(ctypes.byref(o), ctypes.byref(g), 1, cams, None, None, None, None, None, None, None,
+                             0, None, 0, None)
     assert rc == N.GS_ERR_INVALID_ARGUMENT
     g = N.GsGaussians(10, 4, 0, 1, 1, 1, 1, 1)                     # SH degree 4
-    rc = L.gs_render_forward(ctypes.byref(o), ctypes.byref(g), 1, cams, 1, 1, 1, 1, 1, 1, 1 << 40, 1, 1 << 40, None)
+    rc = L.gs_render_forward(ctypes.byref(o), ctypes.byref(g), 1, cams, 1, 1, 1, 1, 1, None, 1, 1 << 40, 1, 1 << 40,
+                             None)
     assert rc == N.GS_ERR_INVALID_ARGUMENT
     g = N.GsGaussians(10, 0, 0, 1, 1, 1, 1, 1)
-    rc = L.gs_render_forward(ctypes.byref(o), ctypes.byref(g), 1, cams, 1, 1, 1, 1, 1, 1, 16, 1, 16, None)
+    rc = L.gs_render_forward(ctypes.byref(o), ctypes.byref(g), 1, cams, 1, 1, 1, 1, 1, None, 1, 16, 1, 16, None)
     assert rc == N.GS_ERR_WORKSPACE_TOO_SMALL
-    rc = L.gs_render_forward(ctypes.byref(o), ctypes.byref(g), 0, cams, 1, 1, 1, 1, 1, 1, 16, 1, 16, None)
+    rc = L.gs_render_forward(ctypes.byref(o), ctypes.byref(g), 0, cams, 1, 1, 1, 1, 1, None, 1, 16, 1, 16, None)
     assert rc == N.GS_ERR_INVALID_ARGUMENT
     assert L.gs_read_status(None, None, None, None) == N.GS_ERR_INVALID_ARGUMENT
     assert L.gs_activate(-1, None, None, None, None, None) == N.GS_ERR_INVALID_ARGUMENT
+    assert L.gs_activation(5, 3, 1, 1, None) == N.GS_ERR_INVALID_ARGUMENT
+    assert L.gs_activation(5, 1, None, 1, None) == N.GS_ERR_INVALID_ARGUMENT
+    assert L.gs_activation(0, 1, None, None, None) == N.GS_OK
+    assert L.gs_adam_step_device((N.GsAdamGroup * 1)(), 1, 0.9, 0.999, 1e-8, None, None, None) == \
+        N.GS_ERR_INVALID_ARGUMENT
     assert L.gs_l1_loss(0, None, None, None, None, None) == N.GS_ERR_INVALID_ARGUMENT
     grp = (N.GsAdamGroup * 1)()
     grp[0].count = 5
@@ -183,7 +190,8 @@ def test_fused_backward_adam_rejects_mismatched_groups():
 
     def call(arr, medium=0x8000):
         return L.gs_render_backward_adam(ctypes.byref(o), ctypes.byref(g), 1, cams, 0xC000, medium, 0xD000, None,
-                                         0xE000, 1 << 40, arr, 0.9, 0.999, 1e-8, 0xF000, 0x10000, 1 << 40, None)
+                                         None, 0xE000, 1 << 40, arr, 0.9, 0.999, 1e-8, 0xF000, 0x10000, 1 << 40,
+                                         None)
 
     bad = [dict(g0=("count", 3 * n + 1)), dict(g1=("activation", 0)), dict(g3=("activated", 0x4004)),
            dict(g4=("param", 0x5004)), dict(g5=("grad", None)), dict(g2=("m", None))]

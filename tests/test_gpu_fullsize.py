@@ -1,7 +1,9 @@
-"""Parity at full size: the 1M-Gaussian 1920x1080 workload in the launch configuration the
-benchmark times (sampled pixels of the image against the FP64 oracle, and gradients of a loss on
-a 64x64 crop for 200 sampled Gaussians against the oracle's exact gradient and FP64 central
-differences), the 24-view batched workload and the 3M-Gaussian 4-view workload."""
+"""Parity at full size, in the launch configurations the benchmark times: sampled pixels of every
+image against the FP64 oracle, and gradients of a loss on a 64x64 crop for 200 sampled Gaussians
+against the oracle's exact gradient (and FP64 central differences for every parameter of the
+crop's most influential Gaussians), for the 300k-Gaussian 1600x1067 training workload, the
+1M-Gaussian 1920x1080 workload, the 24-view batched workload and the 3M-Gaussian 4-view
+workload; and the first moments of one full-scale fused training step."""
 import numpy as np
 import pytest
 import torch
@@ -87,62 +89,63 @@ def test_image_full_size_3m_4_views_sampled(oracle_mod):
         U.compare_pixels(*U.gather_view(rgb, depth, alpha, rast, v, pix), orc)
 
 
-def _crop_pixels():
-    x0, y0, w, h = CROP
-    ys, xs = np.meshgrid(np.arange(y0, y0 + h), np.arange(x0, x0 + w), indexing="ij")
-    return np.ascontiguousarray(np.stack([xs.ravel(), ys.ravel()], 1).astype(np.int32))
+AUTOTUNED_24 = dict(tile=16, pixels_per_lane=4, record_fetch="scalar", lds_batch=256, persistent=False, phases=4,
+                   phase0_shift=6)
 
 
+def test_image_full_size_config1_sampled(oracle_mod):
+    """The 300k-Gaussian training workload (SH 3, one 1600x1067 view) in the default launch
+    configuration and automatic schedule: 6,000 random pixels, the ragged last tile row (1067 = 66 x 16
+    + 11) and the corners against the FP64 oracle."""
+    O = oracle_mod
+    sc = synth.make_scene(1)
+    cam = sc.cameras[0]
+    rast = R.Rasterizer(sc.cameras, R.RasterConfig())
+    rgb, depth, alpha, ctx, _ = U.forward(sc, rast)
+    st, _ = rast.read_status(ctx.saved)
+    assert st == 0
+    rng = np.random.default_rng(15)
+    pix = np.stack([rng.integers(0, cam.width, 6000), rng.integers(0, cam.height, 6000)], 1)
+    edge = np.stack([rng.integers(0, cam.width, 500), rng.integers(cam.height - 11, cam.height, 500)], 1)
+    corners = np.array([[0, 0], [cam.width - 1, 0], [0, cam.height - 1], [cam.width - 1, cam.height - 1]])
+    pix = np.ascontiguousarray(np.concatenate([pix, edge, corners]).astype(np.int32))
+    U.say(f"full-size 300k Gaussians 1600x1067, {len(pix)} sampled pixels, schedule {rast.schedule(sc.n)}")
+    orc = O.render(sc, cam, sc.medium[0], pixels=pix, variants=4)
+    U.compare_pixels(*U.gather_view(rgb, depth, alpha, rast, 0, pix), orc)
+
+
+@pytest.mark.timeout(600)
 def test_grad_full_size_crop(oracle_mod, scene):
+    """1M Gaussians, 1920x1080, the benchmark's launch configuration: the crop gradient for 200 sampled
+    Gaussians, and central differences of all 59 parameters of the 20 Gaussians with the largest
+    opacity gradient."""
     O = oracle_mod
     sc = scene
-    cam = sc.cameras[0]
-    pix = _crop_pixels()
-    rng = np.random.default_rng(12)
-    Gc = rng.normal(size=(len(pix), 3))
-    amb = O.render(sc, cam, sc.medium[0], pixels=pix, variants=1)["nvar"] > 0
-    Gc[amb] = 0.0
-    U.say(f"full-size crop gradient, ambiguous crop pixels {int(amb.sum())}")
-    # GPU: full-frame upstream gradient, zero outside the crop
-    G = np.zeros((cam.height, cam.width, 3))
-    G[pix[:, 1], pix[:, 0]] = Gc
-    rast = _bench_rast(sc)
-    rgb, depth, alpha, ctx, d = U.forward(sc, rast)
-    g_rgb = torch.from_numpy(np.ascontiguousarray(G.transpose(2, 0, 1)).astype(np.float32)).reshape(-1).cuda()
-    out = rast.backward(ctx, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["medium"], g_rgb, None)
-    torch.cuda.synchronize()
-    got = dict(zip(FIELDS + ("medium",), [t.cpu().numpy().astype(np.float64) for t in out]))
-    ref = O.backward(sc, cam, sc.medium[0], Gc, pixels=pix)
-    # 200 sampled Gaussians: every Gaussian that reaches the crop (about 100-150: the large
-    # near Gaussians saturate it), the rest drawn from those that do not (exact zeros)
-    live = np.nonzero(np.abs(ref["g2d"]).sum(axis=1) > 0)[0]
-    assert live.size >= 50, live.size
-    if live.size >= 200:
-        pick = np.sort(rng.choice(live, 200, replace=False))
-    else:
-        rest = rng.choice(np.setdiff1d(np.arange(sc.n), live), 200 - live.size, replace=False)
-        pick = np.sort(np.concatenate([live, rest]))
-    U.say(f"  {live.size} Gaussians reach the crop; checking 200")
-    for f in FIELDS:
-        U.grad_close(got[f][..., pick], ref[f][..., pick], 1e-3, f)
-    U.grad_close(got["medium"].reshape(-1), ref["medium"], 1e-3, "medium")
-    # Gaussians outside the crop's lists get exactly zero
-    dead = np.setdiff1d(np.arange(sc.n), live)[:5000]
-    assert np.all(got["opacity"][dead] == 0.0)
-    # FP64 central differences of the oracle forward for a few of the sampled Gaussians
-    med = sc.medium[0].astype(np.float64)
-    order = pick[np.argsort(-np.abs(ref["opacity"][pick]))][:5]
-    checked = 0
-    for g in order:
-        for f, idx in (("opacity", (g,)), ("means", (0, g)), ("sh", (0, g))):
-            fd, ok = O.fd_grad(sc, cam, med, Gc, f, idx, pixels=pix)
-            if not ok:
-                continue
-            scale = np.sqrt(np.mean(ref[f][..., pick] ** 2))
-            assert abs(got[f][idx] - fd) <= 1e-3 * abs(fd) + 1e-3 * scale, (f, idx, got[f][idx], fd)
-            checked += 1
-    U.say(f"  finite differences checked {checked}")
-    assert checked >= 8
+    U.say("full-size crop gradient, 1M Gaussians 1920x1080")
+    got, ref, Gc, pix, live = U.crop_grad_check(O, sc, _bench_rast(sc), 0, CROP, 12)
+    U.fd_crop_check(O, sc, 0, CROP, Gc, got, ref, live, 20)
+
+
+@pytest.mark.timeout(600)
+def test_grad_full_size_config1_crop(oracle_mod):
+    """300k Gaussians, 1600x1067: the crop gradient (a crop reaching into the ragged last tile row) for 200
+    sampled Gaussians, and central differences of every parameter of 10 of them."""
+    O = oracle_mod
+    sc = synth.make_scene(1)
+    crop = (760, 1067 - 64, 64, 64)
+    U.say("full-size crop gradient, 300k Gaussians 1600x1067")
+    got, ref, Gc, pix, live = U.crop_grad_check(O, sc, R.Rasterizer(sc.cameras, R.RasterConfig()), 0, crop, 16)
+    U.fd_crop_check(O, sc, 0, crop, Gc, got, ref, live, 10)
+
+
+def test_grad_full_size_crop_24_views(oracle_mod):
+    """The batched workload (1M Gaussians, 24 views of uneven resolution) in the autotuner's launch
+    configuration: the crop gradient on one 1920x1080 view, zero upstream gradient in the other 23."""
+    O = oracle_mod
+    sc = synth.make_scene(3)
+    v = next(i for i, c in enumerate(sc.cameras) if (c.width, c.height) == (1920, 1080))
+    U.say(f"full-size 24-view crop gradient (view {v})")
+    U.crop_grad_check(O, sc, R.Rasterizer(sc.cameras, R.RasterConfig(**AUTOTUNED_24)), v, CROP, 18)
 
 
 def test_grad_full_size_crop_4_views(oracle_mod):
@@ -152,39 +155,22 @@ def test_grad_full_size_crop_4_views(oracle_mod):
     gradient for 200 sampled Gaussians; each view's medium gradient (zero but for view 1)."""
     O = oracle_mod
     sc = synth.make_scene(4)
-    v = 1
-    cam = sc.cameras[v]
-    pix = _crop_pixels()
-    rng = np.random.default_rng(14)
-    Gc = rng.normal(size=(len(pix), 3))
-    amb = O.render(sc, cam, sc.medium[v], pixels=pix, variants=1)["nvar"] > 0
-    Gc[amb] = 0.0
-    U.say(f"full-size 4-view crop gradient (view {v}), ambiguous crop pixels {int(amb.sum())}")
-    rast = R.Rasterizer(sc.cameras, R.RasterConfig())
-    rgb, depth, alpha, ctx, d = U.forward(sc, rast)
-    planes = []
-    for w, c in enumerate(sc.cameras):
-        G = np.zeros((c.height, c.width, 3))
-        if w == v:
-            G[pix[:, 1], pix[:, 0]] = Gc
-        planes.append(np.ascontiguousarray(G.transpose(2, 0, 1)).reshape(-1))
-    g_rgb = torch.from_numpy(np.concatenate(planes).astype(np.float32)).cuda()
-    out = rast.backward(ctx, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["medium"], g_rgb, None)
-    torch.cuda.synchronize()
-    got = dict(zip(FIELDS + ("medium",), [t.cpu().numpy().astype(np.float64) for t in out]))
-    ref = O.backward(sc, cam, sc.medium[v], Gc, pixels=pix)
-    live = np.nonzero(np.abs(ref["g2d"]).sum(axis=1) > 0)[0]
-    assert live.size >= 50, live.size
-    if live.size >= 200:
-        pick = np.sort(rng.choice(live, 200, replace=False))
-    else:
-        rest = rng.choice(np.setdiff1d(np.arange(sc.n), live), 200 - live.size, replace=False)
-        pick = np.sort(np.concatenate([live, rest]))
-    U.say(f"  {live.size} Gaussians reach the crop; checking 200")
-    for f in FIELDS:
-        U.grad_close(got[f][..., pick], ref[f][..., pick], 1e-3, f)
-    med = got["medium"].reshape(len(sc.cameras), 9)
-    U.grad_close(med[v], ref["medium"], 1e-3, "medium")
-    assert np.all(np.delete(med, v, axis=0) == 0.0)
-    dead = np.setdiff1d(np.arange(sc.n), live)[:5000]
-    assert np.all(got["opacity"][dead] == 0.0)
+    U.say("full-size 4-view crop gradient (view 1)")
+    U.crop_grad_check(O, sc, R.Rasterizer(sc.cameras, R.RasterConfig()), 1, CROP, 14)
+
+
+def test_fused_training_step_full_size_3m_4_views_first_moments(oracle_mod):
+    """One step of the full-scale training workload (3M Gaussians SH 3, 4 views at 1920x1080, Adam fused
+    into the adjoint, as the benchmark trains): the first moments m = (1 - beta1) g of every group against
+    the oracle's gradient of the L1 loss, with the target equal to the rendered image outside a 64x64
+    crop of view 2."""
+    from paper_2411_19588_amd.trainer import TrainStep
+    O = oracle_mod
+    sc = synth.make_scene(4)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a))
+    ts = TrainStep(t(sc.means), t(sc.log_scales), t(sc.quats), t(sc.logits), t(sc.sh), t(sc.medium),
+                   sc.sh_degree, sc.cameras, torch.cat([t(x).reshape(-1) for x in sc.targets]), R.RasterConfig(),
+                   fused=True)
+    ts.size_capacity()
+    U.say("full-size fused training step, first moments vs oracle (view 2)")
+    U.first_moment_check(O, sc, ts, 2, CROP, torch.cuda.Stream())
