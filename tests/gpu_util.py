@@ -149,7 +149,7 @@ def first_moment_check(O, sc, ts, view, crop, stream, rel=1e-3):
     numel = 3 * ts.rast.total_pixels
     g_img = img[view][:, pix[:, 1], pix[:, 0]].T.astype(np.float64)
     G = np.sign(g_img - tgt[view][:, pix[:, 1], pix[:, 0]].T.astype(np.float64)) / numel
-    U.say(f"  first moments: {int(keep.sum())} crop pixels with a gradient, {int(amb.sum())} ambiguous")
+    say(f"  first moments: {int(keep.sum())} crop pixels with a gradient, {int(amb.sum())} ambiguous")
     ref = O.backward(sc, cam, sc.medium[view], G, pixels=pix)
     b1 = np.float32(1.0) - np.float32(0.9)
     m = {g.name: g.m.detach().cpu().numpy().astype(np.float64) / float(b1) for g in ts.groups}
@@ -159,12 +159,12 @@ def first_moment_check(O, sc, ts, view, crop, stream, rel=1e-3):
     assert live.size > 20
     others = np.setdiff1d(np.random.default_rng(37).choice(sc.n, 200, replace=False), live)
     idx = np.concatenate([live, others])
-    U.grad_close(m["means"][:, idx], ref["means"][:, idx], rel, "means")
-    U.grad_close(m["log_scales"][:, idx], (ref["scales"] * s)[:, idx], rel, "log_scales")
-    U.grad_close(m["quats"][:, idx], ref["quats"][:, idx], rel, "quats")
-    U.grad_close(m["logits"][idx], (ref["opacity"] * o * (1 - o))[idx], rel, "logits")
-    U.grad_close(m["sh"][:, idx], ref["sh"][:, idx], rel, "sh")
-    U.grad_close(m["medium"].reshape(-1, 9)[view], ref["medium"], rel, "medium")
+    grad_close(m["means"][:, idx], ref["means"][:, idx], rel, "means")
+    grad_close(m["log_scales"][:, idx], (ref["scales"] * s)[:, idx], rel, "log_scales")
+    grad_close(m["quats"][:, idx], ref["quats"][:, idx], rel, "quats")
+    grad_close(m["logits"][idx], (ref["opacity"] * o * (1 - o))[idx], rel, "logits")
+    grad_close(m["sh"][:, idx], ref["sh"][:, idx], rel, "sh")
+    grad_close(m["medium"].reshape(-1, 9)[view], ref["medium"], rel, "medium")
     for v in range(len(sc.cameras)):
         if v != view:
             assert np.all(m["medium"].reshape(-1, 9)[v] == 0.0)
