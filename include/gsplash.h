@@ -16,7 +16,8 @@
  *     structure-of-arrays planes: plane k of an [K][n] array starts at k * n.
  *   - The caller owns every buffer, including the workspace and the `saved`
  *     forward context; the library allocates and frees no device memory and
- *     keeps no global mutable state.
+ *     keeps no global mutable state, apart from the fixed scratch array of
+ *     gs_l1_dssim_loss_noalloc.
  *   - Every compute call only enqueues work on `stream` (a hipStream_t) and
  *     never synchronises the host, so a forward/backward sequence can be
  *     captured into a HIP graph.  gs_read_status is the only synchronising call.
@@ -291,6 +292,23 @@ int gs_loss_workspace_query(int32_t n_views, const gs_camera* host_cams, size_t*
 int gs_l1_dssim_loss(int32_t n_views, const gs_camera* host_cams, const float* pred, const float* target,
                      float lambda, float* loss, float* grad, void* workspace, size_t workspace_bytes,
                      gs_stream_t stream);
+
+/* gs_l1_dssim_loss without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, outputs and kernels; the
+ * per-tile partial sums go to a library-owned device array of 8 MiB (2^20
+ * workgroups: up to 64 views of 1920 x 1080), of which each GPU the library
+ * runs on holds its own copy until the process ends.  The array's address is
+ * looked up once per device, on the first call with that device current;
+ * `stream` must belong to the current device.  Calls no allocating routine.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (two streams, or two host threads) race and may return wrong losses; the
+ * gradient does not use the array.  Returns GS_ERR_WORKSPACE_TOO_SMALL (nothing
+ * enqueued) when the views need more than 2^20 workgroups (32 x 16 pixels of
+ * one channel each), GS_ERR_HIP if the array's address cannot be found, and
+ * otherwise what gs_l1_dssim_loss returns. */
+int gs_l1_dssim_loss_noalloc(int32_t n_views, const gs_camera* host_cams, const float* pred, const float* target,
+                             float lambda, float* loss, float* grad, gs_stream_t stream);
 
 /* One parameter group of the fused Adam step (Sec. Optimization: Adam with
  * the 3DGS learning rates, medium at the colour learning rate). */

@@ -104,6 +104,8 @@ PROTOTYPES = {
     "gs_loss_workspace_query": (ctypes.c_int, [_I32, ctypes.POINTER(GsCamera), ctypes.POINTER(_SZ)]),
     "gs_l1_dssim_loss": (ctypes.c_int, [_I32, ctypes.POINTER(GsCamera), _P, _P, ctypes.c_float, _P, _P, _P, _SZ,
                                         _P]),
+    "gs_l1_dssim_loss_noalloc": (ctypes.c_int, [_I32, ctypes.POINTER(GsCamera), _P, _P, ctypes.c_float, _P, _P,
+                                                _P]),
     "gs_adam_step": (ctypes.c_int, [ctypes.POINTER(GsAdamGroup), _I32, ctypes.c_float, ctypes.c_float,
                                     ctypes.c_float, _I32, _P]),
     "gs_adam_step_device": (ctypes.c_int, [ctypes.POINTER(GsAdamGroup), _I32, ctypes.c_float, ctypes.c_float,

@@ -16,6 +16,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "internal.h"
 
 namespace gs {
@@ -287,11 +289,51 @@ int launch_l1_dssim(int32_t n_views, const gs_camera* cams, const float* pred, c
     return hipGetLastError() == hipSuccess ? GS_OK : GS_ERR_HIP;
 }
 
+// Scratch of gs_l1_dssim_loss_noalloc: the per-workgroup partial sums live in a file-scope
+// device array (each device holds its own copy until the process ends), so that entry point
+// allocates nothing.  2^20 workgroups (8 MiB) cover 64 views of 1920 x 1080 (783,360).
+constexpr int64_t kNoAllocMaxBlocks = 1LL << 20;
+static __device__ __align__(256) float scratch[2 * kNoAllocMaxBlocks];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+float* g_scratch_ptr[kMaxDevices];   // device address of `scratch` per device, found once
+
+// The device address of `scratch` on the current device.  In host code the array's name is a
+// host-side stand-in, so its address must come from hipGetSymbolAddress (once per device, with
+// that device current); every later use goes through the returned pointer.
+int scratch_address(float** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return GS_ERR_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return GS_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GS_ERR_HIP;
+        g_scratch_ptr[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return GS_OK;
+}
+
 }  // namespace gs
 
 using namespace gs;
 
 extern "C" {
+
+int gs_l1_dssim_loss_noalloc(int32_t n_views, const gs_camera* host_cams, const float* pred, const float* target,
+                             float lambda, float* loss, float* grad, gs_stream_t stream) {
+    size_t need = 0;
+    int rc = loss_partial_bytes(n_views, host_cams, &need);
+    if (rc != GS_OK) return rc;
+    if (need > (size_t)kNoAllocMaxBlocks * 2 * sizeof(float)) return GS_ERR_WORKSPACE_TOO_SMALL;
+    float* partial = nullptr;
+    rc = scratch_address(&partial);
+    if (rc != GS_OK) return rc;
+    return launch_l1_dssim(n_views, host_cams, pred, target, lambda, loss, grad, partial,
+                           (size_t)kNoAllocMaxBlocks * 2 * sizeof(float), static_cast<hipStream_t>(stream));
+}
 
 int gs_loss_workspace_query(int32_t n_views, const gs_camera* host_cams, size_t* workspace_bytes) {
     if (!workspace_bytes) return GS_ERR_INVALID_ARGUMENT;
