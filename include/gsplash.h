@@ -310,6 +310,60 @@ int gs_l1_dssim_loss(int32_t n_views, const gs_camera* host_cams, const float* p
 int gs_l1_dssim_loss_noalloc(int32_t n_views, const gs_camera* host_cams, const float* pred, const float* target,
                              float lambda, float* loss, float* grad, gs_stream_t stream);
 
+/* Backscatter estimation (Sec. Optimization; appendix "Backscatter Estimation",
+ * Alg. 1 and Alg. 2): per view, rough estimates of the veiling light B_inf and
+ * the backscatter attenuation B_b from an observed image and the rendered
+ * depth z of eq. (Depth), which the L_best term of eq. (OurFinalLoss) then pulls
+ * the learned medium towards (re-estimated every 500 iterations in the paper).
+ * Steps per view:
+ *   1. image and depth resized bilinearly to resize_height rows (width
+ *      floor(W rows / H + 1/2); 0 or H = no resize; half-pixel centres, edges
+ *      clamped), negative values set to 0;
+ *   2. the pixels with a depth (z > 0) cut into edges - 1 evenly spaced depth
+ *      clusters between their smallest and largest depth; in a cluster of n
+ *      pixels the ceil(p_dark n) pixels of smallest r^2 + g^2 + b^2 (ties: lower
+ *      pixel index) are its dark pixels;
+ *   3. the dark pixels' depth range cut into intervals - 1 evenly spaced
+ *      intervals ([e_i, e_{i+1}), the last closed); per channel and interval the
+ *      smallest dark value (ties: lower pixel index) and its depth form a point;
+ *   4. per channel, the bounded least-squares fit of B_inf (1 - exp(-B_b z)) to
+ *      the points, B_inf in [0, 1], B_b in [0, 5] (0, 0 without points).
+ * Every decision of steps 1-3 is taken in FP32 with a fixed operation order
+ * (stated in the source); the fit is FP64. */
+typedef struct gs_backscatter_options {
+    float p_dark;                        /* 0.01: share of each cluster kept as dark pixels, in (0, 1] */
+    int32_t edges;                       /* 10: cluster edges (edges - 1 clusters), 2..33 */
+    int32_t intervals;                   /* 25: interval edges of Alg. 1 (intervals - 1 intervals), 2..257 */
+    int32_t resize_height;               /* 300: rows after the resize; 0 = full resolution */
+} gs_backscatter_options;
+
+void gs_default_backscatter_options(gs_backscatter_options* opts);
+/* Host-only: bytes of the workspace gs_estimate_backscatter needs for these views. */
+int gs_backscatter_workspace_query(const gs_backscatter_options* opts, int32_t n_views, const gs_camera* host_cams,
+                                   size_t* workspace_bytes);
+/*   image  : DEVICE, packed like out_rgb (the observed images, CHW per view).
+ *   depth  : DEVICE, packed like out_depth (rendered depth, 0 = no depth).
+ *   est    : DEVICE [n_views][6] out: B_inf_hat[3], B_b_hat[3] per view.
+ *   points : DEVICE [n_views][3][intervals - 1][2] or NULL: (depth, value) of
+ *            each interval's point, NaN for an interval without dark pixels.
+ *   cost   : DEVICE [n_views][3] or NULL: the fit's residual sum of squares.
+ *   workspace : DEVICE scratch of gs_backscatter_workspace_query bytes.
+ * Only the camera sizes of host_cams are used.  Images must be finite.
+ * Returns GS_ERR_INVALID_ARGUMENT / GS_ERR_WORKSPACE_TOO_SMALL before any
+ * device work. */
+int gs_estimate_backscatter(const gs_backscatter_options* opts, int32_t n_views, const gs_camera* host_cams,
+                            const float* image, const float* depth, float* est, float* points, float* cost,
+                            void* workspace, size_t workspace_bytes, gs_stream_t stream);
+/* L_best of eq. (OurFinalLoss) times lambda (lambda_est of the paper):
+ *   loss = lambda sum_v (|B_inf - B_inf_hat|_1 + |B_b - B_b_hat|_1)
+ * medium : DEVICE [n_views][9] (B_d, B_b, B_inf per view, as gs_medium);
+ * est    : DEVICE [n_views][6] from gs_estimate_backscatter;
+ * loss   : DEVICE [1] or NULL;
+ * grad_medium : DEVICE [n_views][9] or NULL: lambda sign(B - B_hat) is ADDED
+ *               to the B_b and B_inf entries (B_d untouched). */
+int gs_backscatter_prior(int32_t n_views, const float* medium, const float* est, float lambda, float* loss,
+                         float* grad_medium, gs_stream_t stream);
+
 /* One parameter group of the fused Adam step (Sec. Optimization: Adam with
  * the 3DGS learning rates, medium at the colour learning rate). */
 typedef struct gs_adam_group {

@@ -70,6 +70,11 @@ class GsAdamGroup(ctypes.Structure):
                 ("lr", ctypes.c_float), ("activation", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class GsBackscatterOptions(ctypes.Structure):
+    _fields_ = [("p_dark", ctypes.c_float), ("edges", ctypes.c_int32), ("intervals", ctypes.c_int32),
+                ("resize_height", ctypes.c_int32)]
+
+
 # Every symbol declared in include/gsplash.h, with (restype, argtypes).
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -106,6 +111,12 @@ PROTOTYPES = {
                                         _P]),
     "gs_l1_dssim_loss_noalloc": (ctypes.c_int, [_I32, ctypes.POINTER(GsCamera), _P, _P, ctypes.c_float, _P, _P,
                                                 _P]),
+    "gs_default_backscatter_options": (None, [ctypes.POINTER(GsBackscatterOptions)]),
+    "gs_backscatter_workspace_query": (ctypes.c_int, [ctypes.POINTER(GsBackscatterOptions), _I32,
+                                                      ctypes.POINTER(GsCamera), ctypes.POINTER(_SZ)]),
+    "gs_estimate_backscatter": (ctypes.c_int, [ctypes.POINTER(GsBackscatterOptions), _I32, ctypes.POINTER(GsCamera),
+                                               _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "gs_backscatter_prior": (ctypes.c_int, [_I32, _P, _P, ctypes.c_float, _P, _P, _P]),
     "gs_adam_step": (ctypes.c_int, [ctypes.POINTER(GsAdamGroup), _I32, ctypes.c_float, ctypes.c_float,
                                     ctypes.c_float, _I32, _P]),
     "gs_adam_step_device": (ctypes.c_int, [ctypes.POINTER(GsAdamGroup), _I32, ctypes.c_float, ctypes.c_float,
