@@ -104,7 +104,7 @@ class Options:
     dilation: float = 0.3
     kappa: float = 11.1
     depth_mode: int = 0
-    band: float = 1e-4
+    band: float = 1e-5       # relative margin around a threshold inside which a decision is flagged
     depth_output: int = 0     # 0: depth image = the medium's z; 1: logistic map of zhat (visualisation)
 
     def c(self, sh_degree: int) -> OrcOpts:
