@@ -149,6 +149,19 @@ typedef struct gs_options {
     int32_t reserved;
     int64_t max_pairs;                   /* capacity of the stored (Gaussian, tile) pair list, <= GS_MAX_PAIRS */
     void* timer;                         /* optional gs_timer* receiving per-kernel HIP events; NULL = none */
+    /* Loss terms on the parameters that the backward entry points add to the
+     * gradients they produce (0 / NULL = none; gs_default_options sets none): */
+    const float* medium_prior;           /* DEVICE [n_views][6] (B_inf_hat[3], B_b_hat[3]) from
+                                            gs_estimate_backscatter: the medium gradient gets
+                                            prior_lambda sign(B - B_hat) on its B_inf and B_b entries
+                                            (lambda_est L_best of eq. (OurFinalLoss)) */
+    float prior_lambda;
+    float reg_opacity;                   /* lambda_o: the loss gets lambda_o mean_i(opacity_i), so each
+                                            Gaussian's opacity gradient gets lambda_o / n */
+    float reg_scale;                     /* lambda_s: the loss gets lambda_s mean over the 3 n activated
+                                            scale entries, so each gets lambda_s / (3 n) (the regularisers
+                                            of the MCMC densification the paper adopts, Sec. Implementation) */
+    int32_t reserved2;
 } gs_options;
 
 /* Fill `opts` with the defaults above (phases and phase0_shift automatic, max_pairs = 1 << 24). */

@@ -241,6 +241,10 @@ void gs_default_options(gs_options* o) {
     o->phase0_shift = 0;
     o->max_pairs = 1LL << 24;
     o->timer = nullptr;
+    o->medium_prior = nullptr;   // no loss terms beyond the image's
+    o->prior_lambda = 0.0f;
+    o->reg_opacity = 0.0f;
+    o->reg_scale = 0.0f;
 }
 
 const char* gs_version(void) { return "gsplash 0.3 (gfx950)"; }
@@ -401,7 +405,8 @@ int gs_render_backward(const gs_options* opts, const gs_gaussians* g, int32_t n_
                                 grad2d, medpart, guard, s));
     timer_end(T, s);
     timer_begin(T, "medium_reduce", s);
-    GS_TRY(launch_medium_reduce(vt, n_views, medpart, grad_medium, nullptr, 0.f, 0.f, 0.f, nullptr, guard, s));
+    GS_TRY(launch_medium_reduce(vt, n_views, medpart, grad_medium, reinterpret_cast<const float*>(dev_medium), o,
+                                nullptr, 0.f, 0.f, 0.f, nullptr, guard, s));
     timer_end(T, s);
     timer_begin(T, "project_bwd", s);
     float* planes = at<float>(workspace, L.w_shf);
@@ -472,8 +477,8 @@ int gs_render_backward_adam(const gs_options* opts, const gs_gaussians* g, int32
                                 grad2d, medpart, guard, s));
     timer_end(T, s);
     timer_begin(T, "medium_reduce", s);
-    GS_TRY(launch_medium_reduce(vt, n_views, medpart, const_cast<float*>(groups[5].grad), &groups[5], beta1, beta2,
-                                eps, bc, guard, s));
+    GS_TRY(launch_medium_reduce(vt, n_views, medpart, const_cast<float*>(groups[5].grad), groups[5].param, o,
+                                &groups[5], beta1, beta2, eps, bc, guard, s));
     timer_end(T, s);
     AdamFused ad;
     memset(&ad, 0, sizeof(ad));

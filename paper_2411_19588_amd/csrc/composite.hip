@@ -861,6 +861,9 @@ struct MediumAdam {
     const float* bc;
     int32_t enabled;
     Guard guard;
+    const float* medium;   // [views][9] medium values (read by the prior)
+    const float* prior;    // [views][6] (B_inf_hat, B_b_hat) or null
+    float prior_lambda;
 };
 
 constexpr int kMedThreads = 9 * 64;   // thread t always reads component t % 9 of the [tiles][9] partials
@@ -892,7 +895,11 @@ __global__ __launch_bounds__(kMedThreads) void k_medium_reduce(const ViewInfo* _
         __syncthreads();
     }
     if (tid < 9) {
-        const float gm = red[tid];
+        float gm = red[tid];
+        if (ad.prior && tid >= 3) {   // L_best: lambda sign(B - B_hat) on B_b (slots 3-5) and B_inf (6-8)
+            const float d = ad.medium[v * 9 + tid] - ad.prior[v * 6 + (tid < 6 ? tid : tid - 6)];
+            gm += d > 0.0f ? ad.prior_lambda : (d < 0.0f ? -ad.prior_lambda : 0.0f);
+        }
         grad_medium[v * 9 + tid] = gm;
         if (ad.enabled) {
             const int j = v * 9 + tid;
@@ -1007,11 +1014,14 @@ hipError_t launch_composite_bwd(const gs_options& o, const Layout& L, const View
 }
 
 hipError_t launch_medium_reduce(const ViewInfo* vt, int32_t views, const float* medpart, float* grad_medium,
-                                const gs_adam_group* adam, float b1, float b2, float eps, const float* bc,
-                                const Guard& guard, hipStream_t s) {
+                                const float* medium, const gs_options& o, const gs_adam_group* adam, float b1,
+                                float b2, float eps, const float* bc, const Guard& guard, hipStream_t s) {
     MediumAdam ad;
     memset(&ad, 0, sizeof(ad));
     ad.guard = guard;
+    ad.medium = medium;
+    ad.prior = o.medium_prior;
+    ad.prior_lambda = o.prior_lambda;
     if (adam) {
         ad.g = *adam;
         ad.b1 = b1;

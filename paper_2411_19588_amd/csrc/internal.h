@@ -130,6 +130,7 @@ struct AdamFused {
     const float* bc;
     float* shf;
     Guard guard;   // fused steps: skip the step when set
+    float reg_o, reg_s;   // regulariser gradients added to every opacity and scale entry (set by the launchers)
 };
 
 hipError_t launch_project_bwd_adam(const gs_gaussians& g, int32_t views, const gs_camera* cams, const gs_options& o,
@@ -215,9 +216,11 @@ hipError_t launch_composite_bwd(const gs_options& o, const Layout& L, const View
 // Per-view sums of the tiles' medium partials into grad_medium [views][9]; with `adam`, also one
 // Adam step of the medium parameters (group with count 9 * views) using the device bias corrections.
 // When the guard is set, grad_medium is zeroed and no step is taken.
+// medium: [views][9] values of the medium; with o.medium_prior set the reduction adds
+// o.prior_lambda sign(B - B_hat) to the B_inf and B_b gradients before the step.
 hipError_t launch_medium_reduce(const ViewInfo* vt, int32_t views, const float* medpart, float* grad_medium,
-                                const gs_adam_group* adam, float b1, float b2, float eps, const float* bc,
-                                const Guard& guard, hipStream_t s);
+                                const float* medium, const gs_options& o, const gs_adam_group* adam, float b1,
+                                float b2, float eps, const float* bc, const Guard& guard, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 hipError_t launch_export_keys(const Layout& L, const uint2* ranges, const uint32_t* vals, const uint32_t* depth_keys,
                               int64_t capacity, uint64_t* keys, uint32_t* values, hipStream_t s);

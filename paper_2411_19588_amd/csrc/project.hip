@@ -461,6 +461,10 @@ __global__ __launch_bounds__(kBlock) void k_project_bwd(gs_gaussians g, int32_t 
             gmu[2] += (gd[2] - d2 * dd) * il;
         }
     }
+    // regularisers on the activated opacity and scales (once per Gaussian, whatever its views)
+    gop += adam.reg_o;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gsc[k] += adam.reg_s;
     // SH gradient element j = 3 k + channel (one view)
     auto shg = [&](int j) { return Y1[j / 3] * gc1[j % 3]; };
     if (MULTI) {   // k_sh_views adds the SH term
@@ -903,9 +907,13 @@ void project_bwd_launch(const gs_gaussians& g, int32_t views, const gs_camera* c
 }
 
 hipError_t project_bwd(const gs_gaussians& g, int32_t views, const gs_camera* cams, const gs_options& o,
-                       const float* grad2d, const Record* rec, const gs_gaussian_grads& grads, const AdamFused& adam,
+                       const float* grad2d, const Record* rec, const gs_gaussian_grads& grads, const AdamFused& adam_in,
                        int fused, hipStream_t s) {
     if (g.n == 0) return hipSuccess;
+    AdamFused adam = adam_in;
+    // lambda_o mean(o) and lambda_s mean(s) over n and 3 n entries (FP64 quotient rounded once)
+    adam.reg_o = (float)((double)o.reg_opacity / (double)g.n);
+    adam.reg_s = (float)((double)o.reg_scale / (3.0 * (double)g.n));
     const unsigned grid = (unsigned)((g.n + kBlock - 1) / kBlock);
 #define GS_PB(D)                                                                                     \
     if (fused)                                                                                       \

@@ -36,8 +36,11 @@ class RasterConfig:
     phases: int = 0                   # 0 = automatic (the library's gs_schedule)
     phase0_shift: int = 0             # 0 = automatic
     max_pairs: int = 1 << 22
+    reg_opacity: float = 0.0          # lambda_o of the opacity regulariser lambda_o mean(o) (0 = off)
+    reg_scale: float = 0.0            # lambda_s of the scale regulariser lambda_s mean(s) (0 = off)
 
-    def to_c(self, max_pairs: Optional[int] = None, timer=None) -> N.GsOptions:
+    def to_c(self, max_pairs: Optional[int] = None, timer=None, prior: Optional[torch.Tensor] = None,
+             prior_lambda: float = 0.0) -> N.GsOptions:
         o = N.default_options()
         o.tile_w = o.tile_h = int(self.tile)
         o.lds_batch = int(self.lds_batch)
@@ -57,6 +60,13 @@ class RasterConfig:
         o.phase0_shift = int(self.phase0_shift)
         o.max_pairs = int(self.max_pairs if max_pairs is None else max_pairs)
         o.timer = timer
+        o.reg_opacity = float(self.reg_opacity)
+        o.reg_scale = float(self.reg_scale)
+        if prior is not None:
+            if prior.dtype != torch.float32 or not prior.is_contiguous():
+                raise ValueError("the medium prior must be a contiguous float32 [views, 6] tensor")
+            o.medium_prior = prior.data_ptr()
+            o.prior_lambda = float(prior_lambda)
         return o
 
 
@@ -113,6 +123,10 @@ class Rasterizer:
         self.max_pairs = int(config.max_pairs)
         self._ws: Optional[torch.Tensor] = None
         self.timer = None
+        # L_best of eq. (OurFinalLoss): [views, 6] estimates (B_inf_hat, B_b_hat) the backward pulls
+        # the medium towards with weight prior_lambda (None = no prior)
+        self.medium_prior: Optional[torch.Tensor] = None
+        self.prior_lambda = 0.0
 
     # ---------------------------------------------------------------- cameras
     def set_cameras(self, cameras: Sequence) -> None:
@@ -224,7 +238,7 @@ class Rasterizer:
             gmed = torch.empty((self.n_views, 9), dtype=torch.float32, device=self.device)
         g = self._gaussians(means, scales, quats, opacity, sh, ctx.sh_degree)
         grads = N.GsGaussianGrads(*[_ptr(t) for t in outs])
-        o = self.config.to_c(ctx.max_pairs, self.timer)
+        o = self.config.to_c(ctx.max_pairs, self.timer, self.medium_prior, self.prior_lambda)
         N.check("gs_render_backward", N.lib().gs_render_backward(
             ctypes.byref(o), ctypes.byref(g), self.n_views, host_cams, _ptr(dev_cams), _ptr(medium),
             _ptr(grad_rgb), _ptr(grad_depth), _ptr(grad_restored), _ptr(ctx.saved), sv_b, ctypes.byref(grads),

@@ -12,6 +12,14 @@ of their gradient); with `fused=False` the adjoint writes the gradients and
 one flat Adam launch updates every group.  Raw parameters: means, log-scales,
 quaternions, opacity logits, SH and the per-view medium coefficients.
 
+The image loss is L1 (`loss="l1"`, the benchmark's) or eq. (OurFinalLoss)'s
+(1 - lambda) L1 + lambda D-SSIM with lambda = 0.3 (`loss="l1_dssim"`, one fused
+pass); with `prior_lambda > 0` the backward adds lambda_est L_best, pulling the
+medium towards the backscatter estimates in `prior_est`, which
+`estimate_backscatter()` recomputes from the targets and the last rendered depth
+(every 500 iterations in the paper; outside any captured graph).  The MCMC
+regularisers come from the rasterizer options (`reg_opacity`, `reg_scale`).
+
 A step whose forward overflows the pair capacity is not applied: the device
 training state (`state`, int32[2]: step counter, sticky skip flag) records it,
 every later step is skipped too until `clear_skip()` (after the capacity has
@@ -37,7 +45,8 @@ def _vp(t: Optional[torch.Tensor]):
 class TrainStep:
     def __init__(self, means, log_scales, quats, logits, sh, medium, sh_degree: int, cameras: Sequence,
                  targets: torch.Tensor, config: RasterConfig = RasterConfig(), max_pairs: Optional[int] = None,
-                 lr: Optional[dict] = None, device="cuda", fused: bool = False):
+                 lr: Optional[dict] = None, device="cuda", fused: bool = False, loss: str = "l1",
+                 ssim_lambda: float = 0.3, prior_lambda: float = 0.0):
         dev = torch.device(device)
         lr = dict(OPT.LR, **(lr or {}))
         f32 = lambda t: t.to(dev, torch.float32).contiguous()
@@ -65,6 +74,22 @@ class TrainStep:
         self.state = torch.zeros(2, dtype=torch.int32, device=dev)   # (Adam step, sticky skip flag)
         self.graph = None
         self.timer = None
+        if loss not in ("l1", "l1_dssim"):
+            raise ValueError("loss must be 'l1' or 'l1_dssim'")
+        self.loss_kind = loss
+        self.ssim_lambda = float(ssim_lambda)
+        self.loss_views = torch.empty(self.rast.n_views + 1, dtype=torch.float32, device=dev)
+        self.loss_ws = None
+        if loss == "l1_dssim":
+            need = ctypes.c_size_t()
+            N.check("gs_loss_workspace_query", N.lib().gs_loss_workspace_query(self.rast.n_views, self.rast.host_cams,
+                                                                               ctypes.byref(need)))
+            self.loss_ws = torch.empty(max(need.value, 256), dtype=torch.uint8, device=dev)
+        # L_best: fixed buffer of the estimates (its address is baked into a captured graph)
+        self.prior_lambda = float(prior_lambda)
+        self.prior_est = torch.zeros(self.rast.n_views, 6, dtype=torch.float32, device=dev) \
+            if self.prior_lambda > 0 else None
+        self._estimator = None
         # A0: the groups hold the activated scales and opacities for the first forward (gs_activation)
         self._gauss = N.GsGaussians(self.n, self.sh_degree, 0, _vp(self.G["means"].param),
                                     _vp(self.G["log_scales"].activated), _vp(self.G["quats"].param),
@@ -84,10 +109,20 @@ class TrainStep:
         """(Re)allocate the workspace and forward context for `max_pairs` stored pairs (drops any graph)."""
         self.destroy_graph()
         self.max_pairs = int(max_pairs)
-        self.opts = self.rast.config.to_c(self.max_pairs)
+        self.opts = self.rast.config.to_c(self.max_pairs, None, self.prior_est, self.prior_lambda)
         ws, sv = self.rast.sizes_for(self.n, self.max_pairs)
         self.ws = torch.empty(max(ws, 256), dtype=torch.uint8, device=self.device)
         self.saved = torch.empty(max(sv, 256), dtype=torch.uint8, device=self.device)
+
+    def estimate_backscatter(self, cfg=None) -> torch.Tensor:
+        """Recompute prior_est (Alg. 1 and Alg. 2) from the targets and the depth of the last forward."""
+        if self.prior_est is None:
+            raise RuntimeError("construct the step with prior_lambda > 0 to use the backscatter prior")
+        from .backscatter import BackscatterEstimator
+        if self._estimator is None or cfg is not None:
+            self._estimator = BackscatterEstimator(self.rast, cfg)
+        self.prior_est.copy_(self._estimator(self.target, self.depth))
+        return self.prior_est
 
     def size_capacity(self, headroom: float = 1.25) -> int:
         """Run one eager forward (growing the capacity until it fits) and leave `headroom` over its need."""
@@ -119,8 +154,13 @@ class TrainStep:
         sp = ctypes.c_void_p(stream.cuda_stream)
         L = N.lib()
         self._forward(stream)
-        N.check("gs_l1_loss", L.gs_l1_loss(self.rgb.numel(), _vp(self.rgb), _vp(self.target), _vp(self.loss),
-                                           _vp(self.grad_rgb), sp))
+        if self.loss_kind == "l1":
+            N.check("gs_l1_loss", L.gs_l1_loss(self.rgb.numel(), _vp(self.rgb), _vp(self.target), _vp(self.loss),
+                                               _vp(self.grad_rgb), sp))
+        else:
+            N.check("gs_l1_dssim_loss", L.gs_l1_dssim_loss(
+                self.rast.n_views, self.rast.host_cams, _vp(self.rgb), _vp(self.target), self.ssim_lambda,
+                _vp(self.loss_views), _vp(self.grad_rgb), _vp(self.loss_ws), self.loss_ws.numel(), sp))
         if self.fused:
             N.check("gs_render_backward_adam", L.gs_render_backward_adam(
                 ctypes.byref(self.opts), ctypes.byref(self._gauss), self.rast.n_views, self.rast.host_cams,

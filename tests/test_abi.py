@@ -32,7 +32,8 @@ def test_every_declared_symbol_is_exported_and_bound():
 def test_struct_layouts_match_header(tmp_path):
     """sizeof/offsetof of every ABI struct, as a C compiler sees the header, equal the ctypes mirrors."""
     structs = {"gs_camera": N.GsCamera, "gs_gaussians": N.GsGaussians, "gs_gaussian_grads": N.GsGaussianGrads,
-               "gs_options": N.GsOptions, "gs_adam_group": N.GsAdamGroup}
+               "gs_options": N.GsOptions, "gs_adam_group": N.GsAdamGroup,
+               "gs_backscatter_options": N.GsBackscatterOptions}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gsplash.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -56,6 +57,10 @@ def test_default_options_and_version():
     assert (o.tile_w, o.tile_h, o.lds_batch) == (16, 16, 64)
     assert o.alpha_min == pytest.approx(1 / 255) and o.alpha_max == pytest.approx(0.99)
     assert o.t_min == pytest.approx(1e-4) and o.kappa == pytest.approx(11.1)
+    assert o.medium_prior is None and o.prior_lambda == 0 and o.reg_opacity == 0 and o.reg_scale == 0
+    b = N.GsBackscatterOptions()
+    N.lib().gs_default_backscatter_options(ctypes.byref(b))
+    assert (b.edges, b.intervals, b.resize_height) == (10, 25, 300) and b.p_dark == pytest.approx(0.01)
     assert b"gfx950" in N.lib().gs_version()
 
 
@@ -198,3 +203,31 @@ def test_fused_backward_adam_rejects_mismatched_groups():
     for change in bad:
         assert call(groups(**change)) == N.GS_ERR_INVALID_ARGUMENT, change
     assert call(groups(), medium=0x8004) == N.GS_ERR_INVALID_ARGUMENT
+
+
+def test_backscatter_argument_checks():
+    """Host-only validation of the backscatter entry points (nothing is enqueued on error)."""
+    L = N.lib()
+    cams = N.camera_array([synth.Camera(w, h, float(w), float(w), w / 2, h / 2, np.eye(3, dtype=np.float32),
+                                        np.zeros(3, np.float32)) for w, h in ((1920, 1080), (640, 480))])
+    o = N.GsBackscatterOptions()
+    L.gs_default_backscatter_options(ctypes.byref(o))
+    need = ctypes.c_size_t()
+    assert L.gs_backscatter_workspace_query(ctypes.byref(o), 2, cams, ctypes.byref(need)) == N.GS_OK
+    # 533 x 300 + 400 x 300 resized pixels: image, depth, segment, 4 sort buffers
+    assert need.value >= (533 * 300 + 400 * 300) * 9 * 4
+    for field, bad in (("edges", 1), ("edges", 34), ("intervals", 1), ("intervals", 258), ("p_dark", 0.0),
+                       ("p_dark", 1.5), ("resize_height", -1)):
+        b = N.GsBackscatterOptions.from_buffer_copy(o)
+        setattr(b, field, bad)
+        assert L.gs_backscatter_workspace_query(ctypes.byref(b), 2, cams, ctypes.byref(need)) == \
+            N.GS_ERR_INVALID_ARGUMENT, field
+    assert L.gs_backscatter_workspace_query(ctypes.byref(o), 0, cams, ctypes.byref(need)) == N.GS_ERR_INVALID_ARGUMENT
+    p = ctypes.c_void_p(16)
+    assert L.gs_estimate_backscatter(ctypes.byref(o), 2, cams, None, p, p, None, None, p, 1 << 30, None) == \
+        N.GS_ERR_INVALID_ARGUMENT
+    assert L.gs_estimate_backscatter(ctypes.byref(o), 2, cams, p, p, p, None, None, p, 16, None) == \
+        N.GS_ERR_WORKSPACE_TOO_SMALL
+    assert L.gs_backscatter_prior(0, p, p, 0.1, p, p, None) == N.GS_ERR_INVALID_ARGUMENT
+    assert L.gs_backscatter_prior(2, p, p, -1.0, p, p, None) == N.GS_ERR_INVALID_ARGUMENT
+    assert L.gs_backscatter_prior(2, p, p, 0.1, None, None, None) == N.GS_ERR_INVALID_ARGUMENT
