@@ -377,6 +377,66 @@ int gs_estimate_backscatter(const gs_backscatter_options* opts, int32_t n_views,
 int gs_backscatter_prior(int32_t n_views, const float* medium, const float* est, float lambda, float* loss,
                          float* grad_medium, gs_stream_t stream);
 
+/* MCMC densification (Sec. Implementation: the paper replaces the densification
+ * of 3DGS with the MCMC approach of the work it cites; appendix "Experimental
+ * Setup": every 100 iterations, minimum opacity 0.1).  The cited rules are not
+ * in the paper; this library reads them as:
+ *   - relocation: every dead Gaussian (opacity <= dead_opacity), in index order,
+ *     takes a copy of a live Gaussian drawn with probability proportional to
+ *     opacity;
+ *   - addition: gs_mcmc_add_count(n, capacity, 1.05) copies of Gaussians drawn
+ *     proportionally to opacity over all n are appended;
+ *   - a Gaussian drawn c times becomes N = c + 1 identical Gaussians with
+ *     opacity o' = 1 - (1 - o)^(1/N) (N stacked copies keep o on a ray) and
+ *     scales s o / S(N, o'), S(N, a) = sum_{m=1..N} sum_{k<m} C(m-1, k) (-1)^k
+ *     a^(k+1) / sqrt(k+1) (keeps the integral of the stacked opacity profile);
+ *     N is capped at 51 and o' kept in [0.005, 1 - 2^-23]; computed in FP64;
+ *   - the Adam moments of every rewritten Gaussian restart at 0;
+ *   - between densifications the means take Langevin noise (gs_mcmc_noise);
+ *   - the opacity and scale regularisers are gs_options.reg_opacity / reg_scale.
+ * Random numbers are inputs.  Draw j uses the u32 draws[j]: with integer
+ * weights w_i = floor(o_i 2^24) (0 for dead Gaussians in relocation), P their
+ * sum and P_i their exclusive prefix sums, it picks the i with
+ * P_i <= floor(draws[j] P / 2^32) < P_i + w_i (exact integer arithmetic). */
+typedef struct gs_mcmc_state {
+    int64_t n;                           /* Gaussians; every plane is [K][n] */
+    int32_t sh_degree;                   /* 0..3 */
+    int32_t reserved;
+    float* param[5];                     /* raw parameters: means [3], log-scales [3], quaternions [4],
+                                            opacity logits [1], SH [(sh_degree+1)^2 * 3] planes */
+    float* m[5];                         /* first Adam moments, same layouts */
+    float* v[5];                         /* second Adam moments, same layouts */
+    float* scales;                       /* activated scales [3][n] (exp of the log-scales) */
+    float* opacity;                      /* activated opacity [n] (sigmoid of the logits) */
+} gs_mcmc_state;
+
+/* max(0, min(capacity, floor(growth n)) - n): the Gaussians one addition appends. */
+int64_t gs_mcmc_add_count(int64_t n, int64_t capacity, double growth);
+/* Host-only: workspace bytes for a state of n Gaussians and n_draws draws
+ * (relocation: n_draws = n; addition: the appended count). */
+int gs_mcmc_workspace_query(int64_t n, int64_t n_draws, size_t* workspace_bytes);
+/* Relocation, in place.  draws: DEVICE u32 [n] (the j-th dead Gaussian uses
+ * draws[j]); sources: DEVICE u32 [n] or NULL, receives each dead Gaussian's
+ * source; taken: DEVICE u32 [1] or NULL, receives the number of relocated
+ * Gaussians (0 when no Gaussian is live).  dead_opacity in [0, 1). */
+int gs_mcmc_relocate(gs_mcmc_state* state, float dead_opacity, const uint32_t* draws, uint32_t* sources,
+                     uint32_t* taken, void* workspace, size_t workspace_bytes, gs_stream_t stream);
+/* Addition, out of place: dst (dst->n = src->n + k, same sh_degree, buffers
+ * disjoint from src's) receives src's Gaussians with the drawn ones split and
+ * the k copies appended at n .. n + k - 1 (copy j of the source of draws[j]).
+ * sources, taken as in gs_mcmc_relocate; when no Gaussian of src has a
+ * non-zero weight, *taken = 0 and dst's appended entries are unspecified (keep
+ * src). */
+int gs_mcmc_add(const gs_mcmc_state* src, gs_mcmc_state* dst, const uint32_t* draws, uint32_t* sources,
+                uint32_t* taken, void* workspace, size_t workspace_bytes, gs_stream_t stream);
+/* Langevin noise on the means (in place), for each Gaussian:
+ *   mu += lr_means noise_lr sigmoid(100 ((1 - o) - 0.995)) R diag(s^2) R^T eta
+ * with R the rotation of the normalised quaternion, s the activated scales, o
+ * the activated opacity, eta DEVICE [3][n] standard normal draws (an input);
+ * noise_lr = 5e5 in this library's reading.  FP32. */
+int gs_mcmc_noise(int64_t n, float* means, const float* quats, const float* scales, const float* opacity,
+                  const float* eta, float lr_means, float noise_lr, gs_stream_t stream);
+
 /* One parameter group of the fused Adam step (Sec. Optimization: Adam with
  * the 3DGS learning rates, medium at the colour learning rate). */
 typedef struct gs_adam_group {

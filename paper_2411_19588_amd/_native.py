@@ -77,6 +77,12 @@ class GsBackscatterOptions(ctypes.Structure):
                 ("resize_height", ctypes.c_int32)]
 
 
+class GsMcmcState(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("param", ctypes.c_void_p * 5), ("m", ctypes.c_void_p * 5), ("v", ctypes.c_void_p * 5),
+                ("scales", ctypes.c_void_p), ("opacity", ctypes.c_void_p)]
+
+
 # Every symbol declared in include/gsplash.h, with (restype, argtypes).
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -119,6 +125,12 @@ PROTOTYPES = {
     "gs_estimate_backscatter": (ctypes.c_int, [ctypes.POINTER(GsBackscatterOptions), _I32, ctypes.POINTER(GsCamera),
                                                _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "gs_backscatter_prior": (ctypes.c_int, [_I32, _P, _P, ctypes.c_float, _P, _P, _P]),
+    "gs_mcmc_add_count": (_I64, [_I64, _I64, ctypes.c_double]),
+    "gs_mcmc_workspace_query": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(_SZ)]),
+    "gs_mcmc_relocate": (ctypes.c_int, [ctypes.POINTER(GsMcmcState), ctypes.c_float, _P, _P, _P, _P, _SZ, _P]),
+    "gs_mcmc_add": (ctypes.c_int, [ctypes.POINTER(GsMcmcState), ctypes.POINTER(GsMcmcState), _P, _P, _P, _P, _SZ,
+                                   _P]),
+    "gs_mcmc_noise": (ctypes.c_int, [_I64, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float, _P]),
     "gs_adam_step": (ctypes.c_int, [ctypes.POINTER(GsAdamGroup), _I32, ctypes.c_float, ctypes.c_float,
                                     ctypes.c_float, _I32, _P]),
     "gs_adam_step_device": (ctypes.c_int, [ctypes.POINTER(GsAdamGroup), _I32, ctypes.c_float, ctypes.c_float,

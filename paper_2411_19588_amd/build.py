@@ -21,7 +21,8 @@ SRC = os.path.join(HERE, "csrc")
 INC = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libgsplash.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "project.hip", "sort.hip", "bin.hip", "composite.hip", "optim.hip", "loss.hip", "backscatter.hip"]
+SOURCES = ["api.hip", "project.hip", "sort.hip", "bin.hip", "composite.hip", "optim.hip", "loss.hip", "backscatter.hip",
+           "mcmc.hip"]
 ARCH = os.environ.get("GS_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

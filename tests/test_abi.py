@@ -33,7 +33,7 @@ def test_struct_layouts_match_header(tmp_path):
     """sizeof/offsetof of every ABI struct, as a C compiler sees the header, equal the ctypes mirrors."""
     structs = {"gs_camera": N.GsCamera, "gs_gaussians": N.GsGaussians, "gs_gaussian_grads": N.GsGaussianGrads,
                "gs_options": N.GsOptions, "gs_adam_group": N.GsAdamGroup,
-               "gs_backscatter_options": N.GsBackscatterOptions}
+               "gs_backscatter_options": N.GsBackscatterOptions, "gs_mcmc_state": N.GsMcmcState}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gsplash.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -231,3 +231,34 @@ def test_backscatter_argument_checks():
     assert L.gs_backscatter_prior(0, p, p, 0.1, p, p, None) == N.GS_ERR_INVALID_ARGUMENT
     assert L.gs_backscatter_prior(2, p, p, -1.0, p, p, None) == N.GS_ERR_INVALID_ARGUMENT
     assert L.gs_backscatter_prior(2, p, p, 0.1, None, None, None) == N.GS_ERR_INVALID_ARGUMENT
+
+
+def test_mcmc_add_count_and_argument_checks():
+    """gs_mcmc_add_count (host) against the oracle's count; MCMC entry points reject bad arguments
+    before any device work."""
+    from oracle import mcmc as M
+    L = N.lib()
+    for n, cap in ((1000, 5000), (1000, 1030), (1000, 1000), (1000, 900), (3_000_000, 3_100_000), (19, 100), (1, 10)):
+        assert L.gs_mcmc_add_count(n, cap, ctypes.c_double(1.05)) == M.add_count(n, cap), (n, cap)
+    need = ctypes.c_size_t()
+    assert L.gs_mcmc_workspace_query(1000, 1000, ctypes.byref(need)) == N.GS_OK and need.value >= 1000 * 20
+    assert L.gs_mcmc_workspace_query(0, 10, ctypes.byref(need)) == N.GS_ERR_INVALID_ARGUMENT
+    st = N.GsMcmcState()
+    st.n = 100
+    st.sh_degree = 1
+    p = 4096
+    for k in range(5):
+        st.param[k] = st.m[k] = st.v[k] = p
+    st.scales = st.opacity = p
+    d = ctypes.c_void_p(p)
+    assert L.gs_mcmc_relocate(ctypes.byref(st), 0.1, None, None, None, d, 1 << 30, None) == N.GS_ERR_INVALID_ARGUMENT
+    assert L.gs_mcmc_relocate(ctypes.byref(st), 1.5, d, None, None, d, 1 << 30, None) == N.GS_ERR_INVALID_ARGUMENT
+    assert L.gs_mcmc_relocate(ctypes.byref(st), 0.1, d, None, None, d, 16, None) == N.GS_ERR_WORKSPACE_TOO_SMALL
+    bad = N.GsMcmcState.from_buffer_copy(st)
+    bad.sh_degree = 4
+    assert L.gs_mcmc_relocate(ctypes.byref(bad), 0.1, d, None, None, d, 1 << 30, None) == N.GS_ERR_INVALID_ARGUMENT
+    small = N.GsMcmcState.from_buffer_copy(st)
+    small.n = 50
+    assert L.gs_mcmc_add(ctypes.byref(st), ctypes.byref(small), d, None, None, d, 1 << 30, None) == \
+        N.GS_ERR_INVALID_ARGUMENT
+    assert L.gs_mcmc_noise(-1, d, d, d, d, d, 1.0, 1.0, None) == N.GS_ERR_INVALID_ARGUMENT
