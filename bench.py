@@ -1,27 +1,30 @@
 #!/usr/bin/env python3
 """Benchmark of the underwater Gaussian rasterizer on one MI355X.
 
-Workload (default): 1,000,000 Gaussians, SH degree 3, one 1920x1080 view, the
-synthetic scene of the "differentiation check" configuration (same
-distributions as the 300k-Gaussian training configuration, seeded), per-view
-medium coefficients, L1 loss against a seeded random target.
+Workload (`value`): 1,000,000 Gaussians, SH degree 3, one 1920x1080 view, the synthetic scene of
+the "differentiation check" configuration (same distributions as the 300k-Gaussian training
+configuration, seeded), per-view medium coefficients, L1 loss against a seeded random target.
 
-One timed step = a full training step of the hot path, every part in the HIP
-library:
+One timed step = a full training step of the hot path, every part in the HIP library:
     forward  : projection -> depth sort -> pair emission -> tile sort -> ranges
                -> per-tile compositing with the medium and depth epilogue
     loss     : L1 loss value and gradient
     backward : per-tile adjoint -> medium reduction -> projection adjoint
-    update   : Adam over every Gaussian and medium parameter group in one
-               launch, whose epilogue applies the activations (exp scales,
-               sigmoid opacity) that the next step's forward consumes.
-Inputs are resident in HBM before the timed region.  `value` = rendered pixels
-per second of such steps (Mpix/s).
+    update   : Adam over every Gaussian and medium parameter group (fused into the adjoint),
+               whose epilogue applies the activations the next step's forward consumes.
+Every learning rate is 0 while timing: Adam still reads and writes every parameter and moment,
+but the scene stays the configuration's, so the per-kernel event times, the graph-replay time and
+the evaluation counts all describe one scene.  Inputs are resident in HBM before the timed region.
+`value` = rendered pixels per second of such steps (Mpix/s), from HIP-graph replays.
 
-Also reported: per-kernel times measured with HIP events on the launch stream
-over the timed steps, the roofline of the dominant kernel, and the CPU oracle
-timed on a bounded pixel sample of the same frame.  Prints ONE JSON line on
-stdout; progress goes to stderr.
+Also reported (one JSON line on stdout; progress on stderr): per-kernel times from HIP events on
+the launch stream with algorithmic work, GB/s against 8 TB/s and against a measured device copy;
+the roofline of the dominant kernel; the compositing kernels' HBM fraction; forward-only rates at
+1920x1080 and at 1384x918 (the paper's TableDB view size) beside the paper's FPS; the 300k-Gaussian
+and the 3M-Gaussian 4-view training steps; the backscatter estimate, the fused L1 + D-SSIM loss
+pass and the MCMC densification kernels; the 24-view batched pipeline against one pipeline per
+view; and the CPU oracle on the host cores (a pixel sample, and the 1,000-Gaussian frame on one
+core).
 """
 from __future__ import annotations
 
@@ -30,6 +33,8 @@ import ctypes
 import hashlib
 import json
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -47,6 +52,10 @@ VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 FLOPS_ALPHA = 12
 FLOPS_BLEND_FWD = 12
 FLOPS_BLEND_BWD = 49
+# The paper's rendering speed on its own hardware (context only; another machine and a real scene).
+PAPER_FPS = {"fps": 161, "hardware": "NVIDIA GeForce RTX 4090", "scene": "TableDB",
+             "size": "1384x918", "source": "Sec. Experiments, table of rendering and training times"}
+ZERO_LR = {k: 0.0 for k in ("means", "scales", "quats", "opacity", "sh", "medium")}
 
 
 def log(msg: str) -> None:
@@ -59,15 +68,17 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=2,
-                    help="synthetic workload (2: 1M Gaussians, 1920x1080; 4: 3M Gaussians, 4 views at 1920x1080)")
+                    help="synthetic workload of the main record (2: 1M Gaussians, 1920x1080; 1: 300k, 1600x1067; "
+                         "4: 3M Gaussians, 4 views at 1920x1080)")
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--lds-batch", type=int, default=64)
     ap.add_argument("--persistent", action="store_true")
     ap.add_argument("--no-tile-cull", action="store_true", help="bin every tile of each rectangle")
     ap.add_argument("--separate-adam", dest="fused_adam", action="store_false",
                     help="the projection adjoint writes the gradients and the flat Adam kernel updates the "
-                         "parameters (default: Adam fused into the adjoint, the SH coefficients stepped from "
-                         "the two factors of their gradient)")
+                         "parameters (default: Adam fused into the adjoint)")
+    ap.add_argument("--train", action="store_true",
+                    help="time with the method's learning rates (the scene then changes from step to step)")
     ap.add_argument("--ppl", type=int, default=0, help="pixels per lane in compositing (0 = library default)")
     ap.add_argument("--fetch", choices=["default", "lds", "scalar"], default="default",
                     help="how compositing waves receive the records")
@@ -81,7 +92,11 @@ def parse():
     ap.add_argument("--eager", action="store_true", help="time eager launches only (no HIP graph replay)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 24-view batched-vs-per-view forward+backward comparison")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the main record (no forward-only, other configurations or next rows)")
     ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--markers", action="store_true",
+                    help="enqueue empty k_marker kernels around the timed regions (for profiler traces)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (read MIB, write MIB) three times, to "
                          "calibrate the HBM byte counters of a profiler, and exit")
@@ -167,109 +182,6 @@ def traffic_for(kernel: str):
         return None
 
 
-def cpu_baseline(scene, target, stride: int):
-    from oracle import oracle as O
-    cam = scene.cameras[0]
-    ys, xs = np.meshgrid(np.arange(stride // 2, cam.height, stride), np.arange(stride // 2, cam.width, stride),
-                         indexing="ij")
-    pix = np.ascontiguousarray(np.stack([xs.ravel(), ys.ravel()], 1).astype(np.int32))
-    t0 = time.perf_counter()
-    out = O.render(scene, cam, scene.medium[0], pixels=pix)
-    tgt = target[:, pix[:, 1], pix[:, 0]].T.astype(np.float64)
-    G = np.sign(out["rgb"] - tgt) / (3.0 * cam.width * cam.height)
-    O.backward(scene, cam, scene.medium[0], G, pixels=pix)
-    dt = time.perf_counter() - t0
-    return {"value": len(pix) / dt / 1e6, "unit": "Mpix/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"{len(pix)} pixels (every {stride}th pixel in x and y) of the {cam.width}x{cam.height} frame, "
-                      f"FP64 brute-force forward + exact backward incl. per-call projection and depth sort; "
-                      f"{dt:.1f} s"}
-
-
-def batched_compare(args, dev):
-    """24 views of uneven resolution (1M Gaussians, SH 3): forward + L1 + backward of all views
-    in one pipeline (launch shape and depth-phase schedule from the autotuner, one HIP graph)
-    against one pipeline per view (24 forward + backward sequences in one HIP graph, same
-    configuration).  The per-view side leaves the gradients per view (the batched side sums them over
-    the views in its projection adjoint), so it is timed doing less work than the batched one."""
-    import torch
-    from paper_2411_19588_amd import _native as N
-    from paper_2411_19588_amd import autotune as A
-    from paper_2411_19588_amd import rasterizer as R
-    from paper_2411_19588_amd import synth
-    from paper_2411_19588_amd.trainer import RenderStep
-
-    sc = synth.make_scene(3)
-    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-    params = dict(means=t(sc.means), scales=t(sc.scales), quats=t(sc.quats), opacity=t(sc.opacity), sh=t(sc.sh))
-    med = t(sc.medium)
-    tgts = [t(x).reshape(-1) for x in sc.targets]
-    tgt_all = torch.cat(tgts)
-    sizes = [(c.width, c.height) for c in sc.cameras]
-    P = sum(w * h for w, h in sizes)
-    log(f"batched: {len(sizes)} views, {P} pixels; autotuning the launch shape")
-    measure = A.render_step_timer(params, sc.sh_degree, sc.cameras, med, tgt_all, reps=3, device=dev)
-    t0 = time.perf_counter()
-    cfg = A.tune_all(measure, R.RasterConfig(), log=log)
-    tune_s = time.perf_counter() - t0
-    shape = {k: getattr(cfg, k) for k in A.FIELDS}
-    log(f"autotuned shape {shape} ({tune_s:.1f} s)")
-    stream = torch.cuda.Stream(device=dev)
-    K = args.batched_steps
-
-    def time_graph(enqueue_all, warm):
-        with torch.cuda.stream(stream):
-            sp = ctypes.c_void_p(stream.cuda_stream)
-            g = ctypes.c_void_p()
-            N.check("gs_graph_begin", N.lib().gs_graph_begin(sp))
-            try:
-                enqueue_all(stream)
-            finally:
-                rc = N.lib().gs_graph_end(sp, ctypes.byref(g))
-            N.check("gs_graph_end", rc)
-            for _ in range(warm):
-                N.lib().gs_graph_launch(g, sp)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            for _ in range(K):
-                N.check("gs_graph_launch", N.lib().gs_graph_launch(g, sp))
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t1) * 1e3 / K
-            N.lib().gs_graph_destroy(g)
-        return ms
-
-    bs = RenderStep(params, sc.sh_degree, sc.cameras, med, tgt_all, cfg, device=dev)
-    with torch.cuda.stream(stream):
-        bs.size_capacity(1.25)
-    batched_ms = time_graph(lambda s_: bs.enqueue(s_), 2)
-    st, _ = bs.status(stream)
-    del bs
-    log(f"batched: {batched_ms:.3f} ms per forward+backward of {len(sizes)} views")
-    per = []
-    for v, cam in enumerate(sc.cameras):
-        rs = RenderStep(params, sc.sh_degree, [cam], med[v:v + 1], tgts[v], cfg, device=dev)
-        with torch.cuda.stream(stream):
-            rs.size_capacity(1.25)
-        per.append(rs)
-
-    def all_views(s_):
-        for rs in per:
-            rs.enqueue(s_)
-
-    per_ms = time_graph(all_views, 2)
-    st_pv = max(rs.status(stream)[0] for rs in per)
-    del per
-    torch.cuda.empty_cache()
-    log(f"per-view: {per_ms:.3f} ms; speedup {per_ms / batched_ms:.2f}x")
-    if st or st_pv:
-        raise SystemExit(f"batched comparison reported status {st} / {st_pv}")
-    return {"workload": f"{sc.n} Gaussians SH{sc.sh_degree}, {len(sizes)} views of uneven resolution "
-                        f"({P} pixels), forward + L1 + backward",
-            "views": len(sizes), "pixels": P, "batched_ms": round(batched_ms, 3), "per_view_ms": round(per_ms, 3),
-            "speedup": round(per_ms / batched_ms, 3), "batched_mpix_s": round(P / (batched_ms * 1e-3) / 1e6, 1),
-            "per_view_mpix_s": round(P / (per_ms * 1e-3) / 1e6, 1), "shape": shape,
-            "autotune_s": round(tune_s, 1)}
-
-
 KERNELS = ["project_fwd", "depth_sort_hist", "depth_sort_scan", "depth_sort_scatter", "alive_rows", "phase_count",
            "count_scan", "emit", "tile_sort_hist", "tile_sort_scan", "tile_sort_scatter", "commit", "composite_fwd",
            "zero_grad2d", "composite_bwd", "medium_reduce", "project_bwd", "adam_sh", "sh_views"]
@@ -286,6 +198,486 @@ def read_timer(N, timer):
     return out
 
 
+# ------------------------------------------------------------------------------------------ helpers
+class Ctx:
+    """Shared handles: torch, the binding, the device, one non-default stream."""
+
+    def __init__(self, args):
+        import torch
+        from paper_2411_19588_amd import _native as N
+        self.torch = torch
+        self.N = N
+        self.args = args
+        self.dev = torch.device("cuda:0")
+        torch.cuda.set_device(self.dev)
+        self.stream = torch.cuda.Stream(device=self.dev)   # default priority
+
+    def marker(self, i: int) -> None:
+        if self.args.markers:
+            self.N.check("gs_profile_marker", self.N.lib().gs_profile_marker(i, ctypes.c_void_p(self.stream.cuda_stream)))
+
+    def sync(self) -> None:
+        self.torch.cuda.synchronize()
+
+
+def make_train(C: Ctx, sc, cfg, fused=True, train=False, **kw):
+    from paper_2411_19588_amd.trainer import TrainStep
+    t = lambda a: C.torch.from_numpy(np.ascontiguousarray(a))
+    return TrainStep(t(sc.means), t(sc.log_scales), t(sc.quats), t(sc.logits), t(sc.sh), t(sc.medium), sc.sh_degree,
+                     sc.cameras, C.torch.cat([t(x).reshape(-1) for x in sc.targets]), cfg, device=C.dev,
+                     fused=fused, lr=None if train else ZERO_LR, **kw)
+
+
+def time_graph(C: Ctx, enqueue, steps: int, warm: int, marker: int = 0) -> float:
+    """Capture enqueue(stream) once into a HIP graph, replay `warm` times, then time `steps`
+    replays bracketed by synchronisations; milliseconds per replay."""
+    N = C.N
+    with C.torch.cuda.stream(C.stream):
+        sp = ctypes.c_void_p(C.stream.cuda_stream)
+        g = ctypes.c_void_p()
+        N.check("gs_graph_begin", N.lib().gs_graph_begin(sp))
+        try:
+            enqueue(C.stream)
+        finally:
+            rc = N.lib().gs_graph_end(sp, ctypes.byref(g))
+        N.check("gs_graph_end", rc)
+        try:
+            for _ in range(warm):
+                N.check("gs_graph_launch", N.lib().gs_graph_launch(g, sp))
+            if marker:
+                C.marker(marker)
+            C.sync()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                N.check("gs_graph_launch", N.lib().gs_graph_launch(g, sp))
+            C.sync()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            if marker:
+                C.marker(marker + 1)
+        finally:
+            N.lib().gs_graph_destroy(g)
+    return ms
+
+
+def time_events(C: Ctx, fn, reps: int = 5, warm: int = 2) -> float:
+    """Median milliseconds of fn(stream) between HIP events on the launch stream."""
+    torch = C.torch
+    with torch.cuda.stream(C.stream):
+        for _ in range(warm):
+            fn(C.stream)
+        out = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(C.stream)
+            fn(C.stream)
+            b.record(C.stream)
+            b.synchronize()
+            out.append(a.elapsed_time(b))
+    return sorted(out)[len(out) // 2]
+
+
+def copy_ceiling(C: Ctx, mib: int = 1024) -> dict:
+    """A plain device copy (one elementwise kernel reading and writing `mib` MiB): the practical ceiling
+    of the HBM-bound kernels."""
+    torch = C.torch
+    n = mib * (1 << 20) // 4
+    x = torch.rand(n, device=C.dev)
+    y = torch.empty_like(x)
+    ms = time_events(C, lambda s: torch.mul(x, 1.0, out=y), reps=5, warm=2)
+    del x, y
+    return {"bytes": 2 * n * 4, "ms": round(ms, 4), "gbs": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}
+
+
+def kernel_table(kernels: dict, steps: int, sc, K_live: int, P: int, tiles: int, fused: bool, E: int, Cb: int,
+                 copy_gbs: float) -> dict:
+    """Per kernel: ms per step, launches per step, algorithmic work and its rate against the peaks."""
+    ncoef = (sc.sh_degree + 1) ** 2
+    out = {}
+    for nm, kv in kernels.items():
+        per_step = kv["launches"] // steps
+        row = {"ms_per_step": round(kv["ms_total"] / steps, 4), "launches_per_step": per_step,
+               "ms_avg": round(kv["ms_avg"], 4)}
+        f = kernel_flops(nm, E, Cb)
+        if f is not None:
+            tf = f / (kv["ms_total"] / steps * 1e-3) / 1e12
+            row.update(bound="alu", alg_flops_per_step=f, tflops=round(tf, 2), frac=round(tf / VALU_PEAK_TFLOPS, 4))
+        b = kernel_bytes(nm, sc.n, sc.n_views, K_live, P, tiles, ncoef, per_step, fused)
+        if b is not None:
+            gbs = b / (kv["ms_avg"] * 1e-3) / 1e9
+            row.update(alg_bytes=int(b), gbs=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+            if copy_gbs:
+                row["copy_frac"] = round(gbs / copy_gbs, 4)
+            row.setdefault("bound", "hbm")
+        out[nm] = row
+    return out
+
+
+def forward_stats(C: Ctx, ts):
+    N = C.N
+    stats = (ctypes.c_int64 * 5)()
+    N.check("gs_forward_stats", N.lib().gs_forward_stats(ctypes.byref(ts.opts), ts.n, ts.rast.n_views,
+                                                         ts.rast.host_cams, ctypes.c_void_p(ts.saved.data_ptr()),
+                                                         ts.saved.numel(), stats,
+                                                         ctypes.c_void_p(C.stream.cuda_stream)))
+    return [int(x) for x in stats]
+
+
+# ------------------------------------------------------------------------------------------ sections
+def main_record(C: Ctx, sc, cfg, copy_gbs: float):
+    """The training step of `sc`: eager steps with per-kernel events, then graph replays (value)."""
+    torch, N, args = C.torch, C.N, C.args
+    from paper_2411_19588_amd import rasterizer as R
+    ts = make_train(C, sc, cfg, fused=args.fused_adam, train=args.train)
+    log("sizing the pair list")
+    need = ts.size_capacity(1.25)
+    log(f"stored pairs {need}, capacity {ts.max_pairs}")
+    C.sync()
+    with torch.cuda.stream(C.stream):
+        log(f"eager warmup {args.warmup}")
+        for _ in range(args.warmup):
+            ts.enqueue(C.stream)
+        C.sync()
+        timer = None
+        if not args.no_timer:
+            timer = N.lib().gs_timer_create(80 * (args.steps + 1))
+            ts.timer = timer
+        C.marker(1)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ts.enqueue(C.stream)
+        C.sync()
+        eager_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        C.marker(2)
+        ts.timer = None
+        kernels = read_timer(N, timer) if timer is not None else {}
+        if timer is not None:
+            N.lib().gs_timer_destroy(timer)
+        log(f"eager: {eager_ms:.3f} ms/step")
+    ms = eager_ms
+    if not args.eager:
+        ms = time_graph(C, ts.enqueue, args.steps, args.warmup, marker=3)
+        log(f"graph: {ms:.3f} ms/step")
+    st, K = ts.status(C.stream)
+    if st & N.GS_STATUS_PAIR_OVERFLOW or ts.skipped():
+        raise SystemExit(f"pair capacity overflowed during the timed steps ({K} > {ts.max_pairs})")
+    stats = forward_stats(C, ts)
+    _, _, rng = ts.rast.export_keys(R.ForwardContext(ts.saved, ts.max_pairs, ts.n, sc.sh_degree), C.stream)
+    rng = rng.to(torch.int64)
+    phases, shift = ts.rast.schedule(ts.n)
+    phase_pairs = [int((rng[p, :, 1] - rng[p, :, 0]).sum().item()) for p in range(phases)]
+    # full (single-phase) binning pair count of the same scene, for K/N (the method's rectangle binning)
+    full = R.Rasterizer(sc.cameras, R.RasterConfig(phases=1, tile_cull=False, max_pairs=int(K * 8)), device=C.dev)
+    g = ts.G
+    _, _, _, fctx = full.forward(g["means"].param, g["log_scales"].activated, g["quats"].param,
+                                 g["logits"].activated, g["sh"].param, sc.sh_degree, g["medium"].param)
+    _, K_full = full.read_status(fctx.saved)
+    del fctx, full
+    P = ts.rast.total_pixels
+    tiles = ts.rast.tile_count()
+    E, Cb, K_live = stats[1], stats[4], stats[0]
+    log(f"loss {ts.loss.item():.5f}; stored pairs {K}, full-binning pairs {K_full} (K/N {K_full / sc.n:.1f}), "
+        f"E/pixel {E / P:.1f}, blended/pixel {Cb / P:.1f}, live pairs {K_live}, per phase {phase_pairs}")
+    table = kernel_table(kernels, args.steps, sc, K_live, P, tiles, args.fused_adam, E, Cb, copy_gbs)
+    info = dict(ts=ts, ms=ms, eager_ms=eager_ms, kernels=table, K=K, K_full=K_full, K_live=K_live, E=E, Cb=Cb,
+                phases=phases, shift=shift, phase_pairs=phase_pairs, P=P, tiles=tiles)
+    return info
+
+
+def roofline(info: dict) -> dict:
+    kern = info["kernels"]
+    if not kern:
+        return None
+    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+    kd = kern[dom]
+    if kd.get("bound") == "alu":
+        return {"kernel": dom, "bound": "alu", "achieved": kd["tflops"], "peak": round(VALU_PEAK_TFLOPS, 4),
+                "unit": "TFLOP/s", "frac": kd["frac"], "traffic": traffic_for(dom),
+                "alg_flops_per_launch": kd["alg_flops_per_step"] / max(1, kd["launches_per_step"]),
+                "avg_launch_ms": kd["ms_avg"]}
+    return {"kernel": dom, "bound": "hbm", "achieved": kd.get("gbs"), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": kd.get("hbm_frac"), "traffic": traffic_for(dom), "alg_bytes_per_launch": kd.get("alg_bytes"),
+            "avg_launch_ms": kd["ms_avg"]}
+
+
+def composite_hbm(info: dict) -> dict:
+    """The compositing kernels' HBM rate (measured bytes when the committed counters match the
+    source, else algorithmic bytes) against 8 TB/s; their binding limit is the VALU issue rate."""
+    out = {}
+    for nm in ("composite_fwd", "composite_bwd"):
+        kd = info["kernels"].get(nm)
+        if not kd:
+            continue
+        tb = traffic_for(nm)
+        b = tb if tb is not None else kd.get("alg_bytes")
+        if b is None:
+            continue
+        gbs = b / (kd["ms_avg"] * 1e-3) / 1e9
+        out[nm] = {"bytes_per_launch": int(b), "bytes_kind": "measured" if tb is not None else "algorithmic",
+                   "gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                   "valu_frac_algorithmic": kd.get("frac")}
+    return out
+
+
+def forward_only(C: Ctx, ts, steps: int, warm: int, label: str) -> dict:
+    ms = time_graph(C, ts._forward, steps, warm)
+    P = ts.rast.total_pixels
+    w, h = ts.rast.sizes[0]
+    log(f"forward only {label}: {ms:.3f} ms, {P / (ms * 1e-3) / 1e6:.0f} Mpix/s")
+    return {"workload": label, "ms": round(ms, 4), "mpix_s": round(P / (ms * 1e-3) / 1e6, 1),
+            "fps": round(1e3 / ms, 1) if ts.rast.n_views == 1 else None}
+
+
+def next_rows(C: Ctx, ts) -> dict:
+    """The loss pass, the backscatter estimate (Alg. 1 / Alg. 2) and, elsewhere, MCMC."""
+    torch, N = C.torch, C.N
+    from paper_2411_19588_amd.backscatter import BackscatterEstimator
+    need = ctypes.c_size_t()
+    N.check("gs_loss_workspace_query", N.lib().gs_loss_workspace_query(ts.rast.n_views, ts.rast.host_cams,
+                                                                       ctypes.byref(need)))
+    ws = torch.empty(max(need.value, 256), dtype=torch.uint8, device=C.dev)
+    lv = torch.empty(ts.rast.n_views + 1, dtype=torch.float32, device=C.dev)
+    grad = torch.empty_like(ts.rgb)
+    P = ts.rast.total_pixels
+
+    def loss(s):
+        N.check("gs_l1_dssim_loss", N.lib().gs_l1_dssim_loss(
+            ts.rast.n_views, ts.rast.host_cams, ctypes.c_void_p(ts.rgb.data_ptr()),
+            ctypes.c_void_p(ts.target.data_ptr()), 0.3, ctypes.c_void_p(lv.data_ptr()),
+            ctypes.c_void_p(grad.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+            ctypes.c_void_p(s.cuda_stream)))
+
+    loss_ms = time_events(C, loss, reps=7)
+    est = BackscatterEstimator(ts.rast)
+    bs_ms = time_events(C, lambda s: est(ts.target, ts.depth), reps=5)
+    est_full = BackscatterEstimator(ts.rast, type(est.cfg)(resize_height=0))
+    bs_full_ms = time_events(C, lambda s: est_full(ts.target, ts.depth), reps=5)
+    lb = 3 * P * 4 * 3          # pred and target read, gradient written
+    log(f"L1 + D-SSIM pass {loss_ms:.3f} ms; backscatter estimate {bs_ms:.3f} ms (300 rows), "
+        f"{bs_full_ms:.3f} ms (full resolution)")
+    return {"l1_dssim_loss": {"ms": round(loss_ms, 4), "alg_bytes": lb,
+                              "gbs": round(lb / (loss_ms * 1e-3) / 1e9, 1),
+                              "hbm_frac": round(lb / (loss_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+            "backscatter_estimate": {"ms_resize_300": round(bs_ms, 4), "ms_full_resolution": round(bs_full_ms, 4),
+                                     "estimates": [round(float(x), 5) for x in est.est.reshape(-1).tolist()]}}
+
+
+def train_step_ms(C: Ctx, sc, cfg, steps: int, warm: int, timer: bool, copy_gbs: float, label: str) -> dict:
+    torch, N = C.torch, C.N
+    ts = make_train(C, sc, cfg, fused=True)
+    ts.size_capacity(1.25)
+    out = {"workload": label}
+    with torch.cuda.stream(C.stream):
+        for _ in range(warm):
+            ts.enqueue(C.stream)
+        C.sync()
+        if timer:
+            tm = N.lib().gs_timer_create(200 * (steps + 1))
+            ts.timer = tm
+            for _ in range(steps):
+                ts.enqueue(C.stream)
+            C.sync()
+            ts.timer = None
+            kernels = read_timer(N, tm)
+            N.lib().gs_timer_destroy(tm)
+    ms = time_graph(C, ts.enqueue, steps, warm)
+    st, K = ts.status(C.stream)
+    if st or ts.skipped():
+        raise SystemExit(f"{label}: status {st}")
+    P = ts.rast.total_pixels
+    out.update(ms_per_step=round(ms, 4), mpix_s=round(P / (ms * 1e-3) / 1e6, 1), pairs_stored=int(K))
+    if timer:
+        stats = forward_stats(C, ts)
+        out["schedule"] = list(ts.rast.schedule(ts.n))
+        out["kernels"] = kernel_table(kernels, steps, sc, stats[0], P, ts.rast.tile_count(), True, stats[1],
+                                      stats[4], copy_gbs)
+    log(f"{label}: {ms:.3f} ms/step")
+    return out, ts
+
+
+def mcmc_rows(C: Ctx, ts) -> dict:
+    """Relocation and addition on a training step's Gaussians (the draws seeded)."""
+    torch = C.torch
+    from paper_2411_19588_amd import mcmc as MC
+    g = ts.G
+    t = {}
+    for name in MC.GROUPS:
+        t[name] = g[name].param
+        t["m_" + name] = g[name].m
+        t["v_" + name] = g[name].v
+    t["scales"] = g["log_scales"].activated
+    t["opacity"] = g["logits"].activated
+    n = ts.n
+    dz = MC.Densifier(C.dev, seed=7)
+    draws = dz.draws(n)
+    dead = int((t["opacity"] <= MC.DEAD_OPACITY).sum().item())
+    with torch.cuda.stream(C.stream):
+        C.sync()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(C.stream)
+        _, taken = MC.relocate(t, ts.sh_degree, draws)
+        b.record(C.stream)
+        b.synchronize()
+        rel_ms = a.elapsed_time(b)
+        cap = int(n * 1.05)
+        a.record(C.stream)
+        out, _, taken_a = MC.add(t, ts.sh_degree, cap, draws)
+        b.record(C.stream)
+        b.synchronize()
+        add_ms = a.elapsed_time(b)
+    planes = sum(int(np.prod(x.shape[:-1])) if x.dim() > 1 else 1 for x in t.values())
+    moved = 2 * planes * 4 * n + 2 * planes * 4 * int(taken_a.item())   # relayout read + write, appended copies
+    log(f"MCMC: relocation of {int(taken.item())} dead ({dead}) in {rel_ms:.3f} ms; addition of "
+        f"{int(taken_a.item())} in {add_ms:.3f} ms")
+    del out
+    return {"gaussians": n, "planes_per_gaussian": planes, "relocate_ms": round(rel_ms, 4),
+            "relocated": int(taken.item()), "add_ms": round(add_ms, 4), "added": int(taken_a.item()),
+            "add_alg_bytes": moved, "add_gbs": round(moved / (add_ms * 1e-3) / 1e9, 1)}
+
+
+def batched_compare(C: Ctx):
+    """24 views of uneven resolution (1M Gaussians, SH 3): forward + L1 + backward of all views
+    in one pipeline (launch shape and depth-phase schedule from the autotuner, one HIP graph)
+    against one pipeline per view (24 forward + backward sequences in one HIP graph, the same
+    launch shape, each view's own automatic one-view schedule).  The batched pipeline sums the
+    gradients over the views in its projection adjoint; the per-view side is reported without and
+    with that sum (the 24 gradient sets added on the device between HIP events)."""
+    torch, N, args = C.torch, C.N, C.args
+    from dataclasses import replace
+    from paper_2411_19588_amd import autotune as A
+    from paper_2411_19588_amd import rasterizer as R
+    from paper_2411_19588_amd import synth
+    from paper_2411_19588_amd.trainer import RenderStep
+
+    sc = synth.make_scene(3)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(C.dev)
+    params = dict(means=t(sc.means), scales=t(sc.scales), quats=t(sc.quats), opacity=t(sc.opacity), sh=t(sc.sh))
+    med = t(sc.medium)
+    tgts = [t(x).reshape(-1) for x in sc.targets]
+    tgt_all = torch.cat(tgts)
+    sizes = [(c.width, c.height) for c in sc.cameras]
+    P = sum(w * h for w, h in sizes)
+    log(f"batched: {len(sizes)} views, {P} pixels; autotuning the launch shape")
+    measure = A.render_step_timer(params, sc.sh_degree, sc.cameras, med, tgt_all, reps=3, device=C.dev)
+    t0 = time.perf_counter()
+    cfg = A.tune_all(measure, R.RasterConfig(), log=log)
+    tune_s = time.perf_counter() - t0
+    shape = {k: getattr(cfg, k) for k in A.FIELDS}
+    log(f"autotuned shape {shape} ({tune_s:.1f} s)")
+    K = args.batched_steps
+
+    def batched(c):
+        bs = RenderStep(params, sc.sh_degree, sc.cameras, med, tgt_all, c, device=C.dev)
+        with torch.cuda.stream(C.stream):
+            bs.size_capacity(1.25)
+        ms = time_graph(C, bs.enqueue, K, 2)
+        st, _ = bs.status(C.stream)
+        del bs
+        if st:
+            raise SystemExit(f"batched comparison reported status {st}")
+        return ms
+
+    batched_ms = batched(cfg)
+    pers_cfg = replace(cfg, persistent=not cfg.persistent)
+    other_ms = batched(pers_cfg)
+    pers_ms, nonpers_ms = (batched_ms, other_ms) if cfg.persistent else (other_ms, batched_ms)
+    log(f"batched: {batched_ms:.3f} ms (persistent {pers_ms:.3f}, one workgroup per tile {nonpers_ms:.3f})")
+    pv_cfg = replace(cfg, phases=0, phase0_shift=0)     # each view's automatic one-view schedule
+    per = []
+    for v, cam in enumerate(sc.cameras):
+        rs = RenderStep(params, sc.sh_degree, [cam], med[v:v + 1], tgts[v], pv_cfg, device=C.dev)
+        with torch.cuda.stream(C.stream):
+            rs.size_capacity(1.25)
+        per.append(rs)
+
+    def all_views(s_):
+        for rs in per:
+            rs.enqueue(s_)
+
+    per_ms = time_graph(C, all_views, K, 2)
+    st_pv = max(rs.status(C.stream)[0] for rs in per)
+    total = {k: torch.zeros_like(v) for k, v in per[0].grads.items()}
+
+    def sum_views(s_):
+        for rs in per:
+            for k, v in rs.grads.items():
+                total[k].add_(v)
+
+    sum_ms = time_events(C, sum_views, reps=3, warm=1)
+    del per, total
+    torch.cuda.empty_cache()
+    log(f"per-view: {per_ms:.3f} ms (+ {sum_ms:.3f} ms to sum the gradients); speedup {per_ms / batched_ms:.2f}x, "
+        f"{(per_ms + sum_ms) / batched_ms:.2f}x with the sum")
+    if st_pv:
+        raise SystemExit(f"per-view pipelines reported status {st_pv}")
+    return {"workload": f"{sc.n} Gaussians SH{sc.sh_degree}, {len(sizes)} views of uneven resolution "
+                        f"({P} pixels), forward + L1 + backward",
+            "views": len(sizes), "pixels": P, "batched_ms": round(batched_ms, 3),
+            "batched_persistent_ms": round(pers_ms, 3), "batched_per_tile_workgroups_ms": round(nonpers_ms, 3),
+            "per_view_ms": round(per_ms, 3), "per_view_gradient_sum_ms": round(sum_ms, 3),
+            "speedup": round(per_ms / batched_ms, 3), "speedup_with_sum": round((per_ms + sum_ms) / batched_ms, 3),
+            "batched_mpix_s": round(P / (batched_ms * 1e-3) / 1e6, 1),
+            "per_view_mpix_s": round(P / (per_ms * 1e-3) / 1e6, 1), "shape": shape,
+            "per_view_schedule": "automatic one-view schedule per view", "autotune_s": round(tune_s, 1)}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(scene, target, stride: int):
+    from oracle import oracle as O
+    cam = scene.cameras[0]
+    ys, xs = np.meshgrid(np.arange(stride // 2, cam.height, stride), np.arange(stride // 2, cam.width, stride),
+                         indexing="ij")
+    pix = np.ascontiguousarray(np.stack([xs.ravel(), ys.ravel()], 1).astype(np.int32))
+    t0 = time.perf_counter()
+    out = O.render(scene, cam, scene.medium[0], pixels=pix)
+    tgt = target[:, pix[:, 1], pix[:, 0]].T.astype(np.float64)
+    G = np.sign(out["rgb"] - tgt) / (3.0 * cam.width * cam.height)
+    O.backward(scene, cam, scene.medium[0], G, pixels=pix)
+    dt = time.perf_counter() - t0
+    return {"value": len(pix) / dt / 1e6, "unit": "Mpix/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{len(pix)} pixels (every {stride}th pixel in x and y) of the {cam.width}x{cam.height} frame, "
+                      f"FP64 brute-force forward + exact backward incl. per-call projection and depth sort; "
+                      f"{dt:.1f} s", "cpu_model": cpu_model()}
+
+
+ONE_CORE = r"""
+import json, sys, time
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+from oracle import oracle as O
+from paper_2411_19588_amd import synth
+sc = synth.make_scene(0)
+cam = sc.cameras[0]
+t0 = time.perf_counter()
+out = O.render(sc, cam, sc.medium[0])
+G = np.sign(out["rgb"] - sc.targets[0].reshape(3, -1).T) / (3.0 * cam.width * cam.height)
+O.backward(sc, cam, sc.medium[0], G)
+dt = time.perf_counter() - t0
+print(json.dumps({"seconds": dt, "pixels": cam.width * cam.height, "threads": O.num_threads()}))
+"""
+
+
+def one_core_config0() -> dict:
+    """The oracle on the 1,000-Gaussian 128x128 frame (forward + backward) on one thread, in a child process."""
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", ONE_CORE, ROOT], env=env, capture_output=True, text=True, timeout=300)
+    if r.returncode != 0:
+        return {"error": r.stderr[-400:]}
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    return {"workload": "1000 Gaussians SH0, 128x128, forward + exact backward (full frame)",
+            "seconds": round(d["seconds"], 3), "mpix_s": round(d["pixels"] / d["seconds"] / 1e6, 5),
+            "cores": d["threads"]}
+
+
+# ------------------------------------------------------------------------------------------ main
 def main():
     args = parse()
     if args.gpus != 1:
@@ -295,151 +687,85 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2411_19588_amd import _native as N
     from paper_2411_19588_amd import rasterizer as R
     from paper_2411_19588_amd import synth
-    from paper_2411_19588_amd.trainer import TrainStep
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+    C = Ctx(args)
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 4
-        x = torch.rand(n, device=dev)
+        x = torch.rand(n, device=C.dev)
         y = torch.empty_like(x)
         for _ in range(3):
             torch.mul(x, 1.0, out=y)     # one elementwise kernel: reads n*4 bytes, writes n*4 bytes
-        torch.cuda.synchronize()
+        C.sync()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         torch.mul(x, 1.0, out=y)
         e1.record()
-        torch.cuda.synchronize()
+        C.sync()
         ms = e0.elapsed_time(e1)
         print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 4,
                           "copy_ms": round(ms, 4), "copy_gbs": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}))
         return
+
+    copy = copy_ceiling(C)
+    log(f"device copy of 1 GiB: {copy['gbs']} GB/s")
     log(f"building scene (config {args.config})")
     sc = synth.make_scene(args.config)
     cam = sc.cameras[0]
-    P = sum(c.width * c.height for c in sc.cameras)
     sizes = sorted({(c.width, c.height) for c in sc.cameras})
-    ncoef = (sc.sh_degree + 1) ** 2
-    t = lambda a: torch.from_numpy(np.ascontiguousarray(a))
     cfg = R.RasterConfig(tile=args.tile, lds_batch=args.lds_batch, persistent=args.persistent, phases=args.phases,
-                         phase0_shift=args.phase0_shift,
-                         pixels_per_lane=args.ppl, record_fetch=args.fetch, tile_cull=not args.no_tile_cull)
-    ts = TrainStep(t(sc.means), t(sc.log_scales), t(sc.quats), t(sc.logits), t(sc.sh), t(sc.medium), sc.sh_degree,
-                   sc.cameras, torch.cat([t(x).reshape(-1) for x in sc.targets]), cfg, device=dev,
-                   fused=args.fused_adam)
-    log("sizing the pair list")
-    need = ts.size_capacity(1.25)
-    log(f"stored pairs {need}, capacity {ts.max_pairs}")
-    stream = torch.cuda.Stream(device=dev)          # default priority
-    torch.cuda.synchronize()
-
-    # ---- eager steps, with HIP events around every kernel
-    with torch.cuda.stream(stream):
-        log(f"eager warmup {args.warmup}")
-        for _ in range(args.warmup):
-            ts.enqueue(stream)
-        torch.cuda.synchronize()
-        timer = None
-        if not args.no_timer:
-            timer = N.lib().gs_timer_create(80 * (args.steps + 1))
-            ts.timer = timer
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            ts.enqueue(stream)
-        torch.cuda.synchronize()
-        eager_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-        ts.timer = None
-        kernels = read_timer(N, timer) if timer is not None else {}
-        if timer is not None:
-            N.lib().gs_timer_destroy(timer)
-        log(f"eager: {eager_ms:.3f} ms/step")
-
-        # ---- the same step captured once into a HIP graph and replayed
-        ms = eager_ms
-        if not args.eager:
-            ts.capture(stream)
-            for _ in range(args.warmup):
-                ts.replay(stream)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(args.steps):
-                ts.replay(stream)
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) * 1e3 / args.steps
-            log(f"graph: {ms:.3f} ms/step")
-    st, K = ts.status(stream)
-    if st & N.GS_STATUS_PAIR_OVERFLOW:
-        raise SystemExit(f"pair capacity overflowed during the timed steps ({K} > {ts.max_pairs})")
-    stats = (ctypes.c_int64 * 5)()
-    N.check("gs_forward_stats", N.lib().gs_forward_stats(ctypes.byref(ts.opts), ts.n, ts.rast.n_views,
-                                                         ts.rast.host_cams,
-                                                         ctypes.c_void_p(ts.saved.data_ptr()), ts.saved.numel(),
-                                                         stats, ctypes.c_void_p(stream.cuda_stream)))
-    # pairs per depth phase (from the stored per-phase tile ranges)
-    _, _, rng = ts.rast.export_keys(R.ForwardContext(ts.saved, ts.max_pairs, ts.n, sc.sh_degree), stream)
-    rng = rng.to(torch.int64)
-    phases, shift = ts.rast.schedule(ts.n)
-    phase_pairs = [int((rng[p, :, 1] - rng[p, :, 0]).sum().item()) for p in range(phases)]
-    log(f"live pairs per phase: {phase_pairs}")
-    # full (single-phase) binning pair count of the same scene, for K/N
-    # (the method's rectangle binning, no culling)
-    full = R.Rasterizer(sc.cameras, R.RasterConfig(phases=1, tile_cull=False, max_pairs=int(K * 8)), device=dev)
-    g = ts.G
-    _, _, _, fctx = full.forward(g["means"].param, g["log_scales"].activated, g["quats"].param,
-                                 g["logits"].activated, g["sh"].param, sc.sh_degree, g["medium"].param)
-    _, K_full = full.read_status(fctx.saved)
-    del fctx, full
-    log(f"loss {ts.loss.item():.5f}; stored pairs {K}, full-binning pairs {K_full} (K/N {K_full / sc.n:.1f}), "
-        f"E/pixel {stats[1] / P:.1f}, blended/pixel {stats[4] / P:.1f}, live pairs {stats[0]}")
-
-    tiles = ts.rast.tile_count()
-    E, Cb, K_live = int(stats[1]), int(stats[4]), int(stats[0])
-    roof = None
-    if kernels:
-        dom = max(kernels, key=lambda k: kernels[k]["ms_total"])
-        for nm, kv in kernels.items():
-            per_step = kv["launches"] // args.steps
-            f = kernel_flops(nm, E, Cb)
-            if f is not None:
-                kv["alg_flops"] = f / max(1, per_step)
-                kv["tflops"] = f / (kv["ms_total"] / args.steps * 1e-3) / 1e12
-                continue
-            b = kernel_bytes(nm, sc.n, sc.n_views, K_live, P, tiles, ncoef, per_step, args.fused_adam)
-            if b is not None:
-                kv["alg_bytes"] = b
-                kv["gbs"] = b / (kv["ms_avg"] * 1e-3) / 1e9
-        kd = kernels[dom]
-        if "tflops" in kd:
-            roof = {"kernel": dom, "bound": "alu", "achieved": round(kd["tflops"], 2), "peak": VALU_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(kd["tflops"] / VALU_PEAK_TFLOPS, 4),
-                    "traffic": traffic_for(dom), "alg_flops_per_launch": kd["alg_flops"],
-                    "avg_launch_ms": round(kd["ms_avg"], 4)}
-        else:
-            achieved = kd.get("gbs")
-            roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                    "traffic": traffic_for(dom), "alg_bytes_per_launch": kd.get("alg_bytes"),
-                    "avg_launch_ms": round(kd["ms_avg"], 4)}
-        log("per-kernel ms/step: " + ", ".join(f"{k} {v['ms_total'] / args.steps:.3f}" for k, v in kernels.items()))
-        log("compositing TFLOP/s: " + ", ".join(f"{k} {v['tflops']:.2f}" for k, v in kernels.items() if "tflops" in v))
+                         phase0_shift=args.phase0_shift, pixels_per_lane=args.ppl, record_fetch=args.fetch,
+                         tile_cull=not args.no_tile_cull)
+    info = main_record(C, sc, cfg, copy["gbs"])
+    ts = info["ts"]
+    P, ms = info["P"], info["ms"]
+    roof = roofline(info)
+    extras = {}
+    if not args.no_extras:
+        extras["forward_only"] = forward_only(C, ts, args.steps, args.warmup,
+                                              f"{sc.n} Gaussians SH{sc.sh_degree}, {cam.width}x{cam.height}")
+        extras.update(next_rows(C, ts))
+    del ts
+    info.pop("ts")
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        scp = synth.make_scene(2, width=1384, height=918)
+        tsp = make_train(C, scp, R.RasterConfig())
+        tsp.size_capacity(1.25)
+        fp = forward_only(C, tsp, args.steps, args.warmup, f"{scp.n} Gaussians SH3, 1384x918 (the paper's TableDB "
+                                                           "view size; synthetic scene)")
+        fp["paper"] = PAPER_FPS
+        extras["forward_only_1384x918"] = fp
+        del tsp, scp
+        sc1 = synth.make_scene(1)
+        extras["train_300k_1600x1067"], ts1 = train_step_ms(
+            C, sc1, R.RasterConfig(), args.steps, args.warmup, False, copy["gbs"],
+            "300000 Gaussians SH3, 1600x1067, training step (forward + L1 + backward + Adam)")
+        del ts1, sc1
+        torch.cuda.empty_cache()
+        log("building the 3M-Gaussian 4-view scene")
+        sc4 = synth.make_scene(4)
+        extras["train_3m_4x1080p"], ts4 = train_step_ms(
+            C, sc4, R.RasterConfig(), 10, 3, True, copy["gbs"],
+            "3000000 Gaussians SH3, 4 views at 1920x1080 with per-view medium, training step "
+            "(forward + L1 + backward + fused Adam)")
+        extras["mcmc_3m"] = mcmc_rows(C, ts4)
+        del ts4, sc4
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a pixel sample")
         cpu = cpu_baseline(sc, sc.targets[0], args.cpu_stride)
-        log(f"oracle {cpu['value'] * 1e6:.0f} pix/s on {cpu['cores']} threads")
+        log(f"oracle {cpu['value'] * 1e6:.0f} pix/s on {cpu['cores']} threads ({cpu['cpu_model']})")
+        cpu["one_core_1000_gaussians"] = one_core_config0()
+        log(f"oracle on one core: {cpu['one_core_1000_gaussians']}")
 
     batched = None
     if not args.no_batched:
-        del ts
-        torch.cuda.empty_cache()
-        batched = batched_compare(args, dev)
+        batched = batched_compare(C)
 
     rec = {
         "metric": "fwd+bwd Mpix/s at 1M Gaussians 1080p; batched-views vs per-view speedup",
@@ -458,19 +784,25 @@ def main():
                                f"{' + '.join(f'{w}x{h}' for w, h in sizes)}, {sc.n_views} view(s), "
                                "training step (forward + L1 + backward + Adam)",
                    "n_gaussians": sc.n, "sh_degree": sc.sh_degree, "width": cam.width, "height": cam.height,
-                   "views": sc.n_views, "tile": args.tile, "lds_batch": args.lds_batch, "persistent": bool(args.persistent),
-                   "pixels_per_lane": args.ppl, "record_fetch": args.fetch,
-                   "phases": phases, "phase0_shift": shift, "mode": "eager" if args.eager else "hip_graph",
-                   "pairs_stored": int(K), "pairs_full_binning": int(K_full),
-                   "pairs_per_gaussian": round(K_full / sc.n, 2), "pairs_live": int(stats[0]),
-                   "pairs_live_per_phase": phase_pairs,
-                   "evals_per_pixel": round(stats[1] / P, 1), "blends_per_pixel": round(stats[4] / P, 1),
+                   "views": sc.n_views, "tile": args.tile, "lds_batch": args.lds_batch,
+                   "persistent": bool(args.persistent), "pixels_per_lane": args.ppl, "record_fetch": args.fetch,
+                   "phases": info["phases"], "phase0_shift": info["shift"],
+                   "mode": "eager" if args.eager else "hip_graph",
+                   "learning_rates": "paper's (scene changes while timed)" if args.train else
+                   "0 (Adam reads and writes every byte; the scene stays fixed)",
+                   "pairs_stored": int(info["K"]), "pairs_full_binning": int(info["K_full"]),
+                   "pairs_per_gaussian": round(info["K_full"] / sc.n, 2), "pairs_live": int(info["K_live"]),
+                   "pairs_live_per_phase": info["phase_pairs"],
+                   "evals_per_pixel": round(info["E"] / P, 1), "blends_per_pixel": round(info["Cb"] / P, 1),
                    "tile_cull": bool(cfg.tile_cull), "adam": "fused" if args.fused_adam else "separate"},
-        "eager_ms_per_step": round(eager_ms, 4),
+        "eager_ms_per_step": round(info["eager_ms"], 4),
         "roofline": roof,
         "cpu_baseline": cpu,
         "batched": batched,
-        "kernels_ms_per_step": {k: round(v["ms_total"] / args.steps, 4) for k, v in kernels.items()},
+        "copy_ceiling": copy,
+        "composite_hbm": composite_hbm(info),
+        "kernels": info["kernels"],
+        "extras": extras,
     }
     print(json.dumps(rec), flush=True)
 

@@ -535,6 +535,11 @@ void gs_timer_destroy(void* timer);
 void gs_timer_reset(void* timer);
 int gs_timer_read(void* timer, const char* kernel, double* total_ms, int32_t* launches);
 
+/* Enqueues one empty kernel named k_marker (one thread; `id` is its only
+ * argument), so that a profiler's kernel trace can tell apart the phases of a
+ * run (set-up, warm-up, timed steps) by the markers between them. */
+int gs_profile_marker(int32_t id, gs_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

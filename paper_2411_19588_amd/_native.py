@@ -139,6 +139,7 @@ PROTOTYPES = {
     "gs_graph_end": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
     "gs_graph_launch": (ctypes.c_int, [_P, _P]),
     "gs_graph_destroy": (ctypes.c_int, [_P]),
+    "gs_profile_marker": (ctypes.c_int, [_I32, _P]),
     "gs_timer_create": (_P, [_I32]),
     "gs_timer_destroy": (None, [_P]),
     "gs_timer_reset": (None, [_P]),
