@@ -89,6 +89,8 @@ def parse():
                     help="depth-progressive binning phases (1 = full binning; 0 = automatic by view count)")
     ap.add_argument("--phase0-shift", type=int, default=0,
                     help="first depth phase = nearest 1/2^shift of the visible Gaussians (0 = library default)")
+    ap.add_argument("--phase-growth", type=int, default=0,
+                    help="log2 of the later depth phases' growth (0 = library default, 4x)")
     ap.add_argument("--eager", action="store_true", help="time eager launches only (no HIP graph replay)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 24-view batched-vs-per-view forward+backward comparison")
@@ -577,11 +579,12 @@ def batched_compare(C: Ctx):
         return ms
 
     batched_ms = batched(cfg)
-    pers_cfg = replace(cfg, persistent=not cfg.persistent)
-    other_ms = batched(pers_cfg)
-    pers_ms, nonpers_ms = (batched_ms, other_ms) if cfg.persistent else (other_ms, batched_ms)
-    log(f"batched: {batched_ms:.3f} ms (persistent {pers_ms:.3f}, one workgroup per tile {nonpers_ms:.3f})")
-    pv_cfg = replace(cfg, phases=0, phase0_shift=0)     # each view's automatic one-view schedule
+    modes = {}
+    for pm in (0, 1, 2):   # one workgroup per tile; persistent queue in tile order; longest list first
+        modes[pm] = batched_ms if pm == int(cfg.persistent) else batched(replace(cfg, persistent=pm))
+    log(f"batched: {batched_ms:.3f} ms (one workgroup per tile {modes[0]:.3f}, persistent queue {modes[1]:.3f}, "
+        f"longest-first queue {modes[2]:.3f})")
+    pv_cfg = replace(cfg, phases=0, phase0_shift=0, phase_growth=0)   # each view's automatic one-view schedule
     per = []
     for v, cam in enumerate(sc.cameras):
         rs = RenderStep(params, sc.sh_degree, [cam], med[v:v + 1], tgts[v], pv_cfg, device=C.dev)
@@ -612,7 +615,8 @@ def batched_compare(C: Ctx):
     return {"workload": f"{sc.n} Gaussians SH{sc.sh_degree}, {len(sizes)} views of uneven resolution "
                         f"({P} pixels), forward + L1 + backward",
             "views": len(sizes), "pixels": P, "batched_ms": round(batched_ms, 3),
-            "batched_persistent_ms": round(pers_ms, 3), "batched_per_tile_workgroups_ms": round(nonpers_ms, 3),
+            "batched_per_tile_workgroups_ms": round(modes[0], 3), "batched_persistent_ms": round(modes[1], 3),
+            "batched_persistent_longest_first_ms": round(modes[2], 3),
             "per_view_ms": round(per_ms, 3), "per_view_gradient_sum_ms": round(sum_ms, 3),
             "speedup": round(per_ms / batched_ms, 3), "speedup_with_sum": round((per_ms + sum_ms) / batched_ms, 3),
             "batched_mpix_s": round(P / (batched_ms * 1e-3) / 1e6, 1),
@@ -716,7 +720,8 @@ def main():
     cam = sc.cameras[0]
     sizes = sorted({(c.width, c.height) for c in sc.cameras})
     cfg = R.RasterConfig(tile=args.tile, lds_batch=args.lds_batch, persistent=args.persistent, phases=args.phases,
-                         phase0_shift=args.phase0_shift, pixels_per_lane=args.ppl, record_fetch=args.fetch,
+                         phase0_shift=args.phase0_shift, phase_growth=args.phase_growth,
+                         pixels_per_lane=args.ppl, record_fetch=args.fetch,
                          tile_cull=not args.no_tile_cull)
     info = main_record(C, sc, cfg, copy["gbs"])
     ts = info["ts"]
@@ -787,6 +792,7 @@ def main():
                    "views": sc.n_views, "tile": args.tile, "lds_batch": args.lds_batch,
                    "persistent": bool(args.persistent), "pixels_per_lane": args.ppl, "record_fetch": args.fetch,
                    "phases": info["phases"], "phase0_shift": info["shift"],
+                   "phase_growth": args.phase_growth or 2,
                    "mode": "eager" if args.eager else "hip_graph",
                    "learning_rates": "paper's (scene changes while timed)" if args.train else
                    "0 (Adam reads and writes every byte; the scene stays fixed)",

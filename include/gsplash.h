@@ -110,7 +110,10 @@ typedef struct gs_gaussian_grads {
 typedef struct gs_options {
     int32_t tile_w, tile_h;              /* 16x16 (default) or 8x8 pixels per tile */
     int32_t lds_batch;                   /* records staged in LDS per batch: 64 (default), 128 or 256 */
-    int32_t persistent;                  /* 0: one workgroup per tile; 1: persistent workgroups pull tiles from a queue */
+    int32_t persistent;                  /* 0: one workgroup per tile; 1: persistent workgroups pull tiles from a
+                                            queue in tile order; 2: the same queue ordered longest list first
+                                            (power-of-two buckets of each tile's list length, by a stable radix
+                                            sort before each pass).  Images are identical for every value. */
     int32_t pixels_per_lane;             /* 16x16 tiles: pixels each lane blends, 1 (four waves per tile, 8x8
                                             each), 2 (two waves, 16x8 each) or 4 (one wave); 8x8 tiles: 1;
                                             0 = per-pass default (forward 2, backward 4).  Images are
@@ -146,7 +149,10 @@ typedef struct gs_options {
     int32_t depth_output;                /* depth image: 0 (default) = the z of depth_mode; 1 = the logistic
                                             map 2/(1+exp(-0.1 zhat)) - 1 of the Implementation section, for
                                             visualisation, whatever depth_mode the medium uses */
-    int32_t reserved;
+    int32_t phase_growth;                /* log2 of the growth of the depth phases' rank ranges: phase p
+                                            (but the last) ends at the nearest 1/2^(shift - growth p) of
+                                            the visible Gaussians: 1 (2x), 2 (4x), 3 (8x) or 4 (16x);
+                                            0 (default) = 2.  Images are identical for every value. */
     int64_t max_pairs;                   /* capacity of the stored (Gaussian, tile) pair list, <= GS_MAX_PAIRS */
     void* timer;                         /* optional gs_timer* receiving per-kernel HIP events; NULL = none */
     /* Loss terms on the parameters that the backward entry points add to the

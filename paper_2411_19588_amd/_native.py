@@ -61,7 +61,7 @@ class GsOptions(ctypes.Structure):
                 ("t_min", ctypes.c_float), ("dilation", ctypes.c_float), ("kappa", ctypes.c_float),
                 ("depth_mode", ctypes.c_int32), ("tile_cull", ctypes.c_int32),
                 ("phases", ctypes.c_int32), ("phase0_shift", ctypes.c_int32), ("depth_output", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("max_pairs", ctypes.c_int64), ("timer", ctypes.c_void_p),
+                ("phase_growth", ctypes.c_int32), ("max_pairs", ctypes.c_int64), ("timer", ctypes.c_void_p),
                 ("medium_prior", ctypes.c_void_p), ("prior_lambda", ctypes.c_float), ("reg_opacity", ctypes.c_float),
                 ("reg_scale", ctypes.c_float), ("reserved2", ctypes.c_int32)]
 

@@ -20,11 +20,11 @@ from typing import Callable, Dict, Iterable, List, Optional, Sequence
 from .rasterizer import RasterConfig
 
 SHAPE_FIELDS = ("tile", "pixels_per_lane", "record_fetch", "lds_batch", "persistent")
-SCHEDULE_FIELDS = ("phases", "phase0_shift")
+SCHEDULE_FIELDS = ("phases", "phase0_shift", "phase_growth")
 FIELDS = SHAPE_FIELDS + SCHEDULE_FIELDS
 
 
-def candidates(tiles=(16, 8), persistent=(False, True)) -> List[dict]:
+def candidates(tiles=(16, 8), persistent=(0, 1, 2)) -> List[dict]:
     """Launch shapes worth timing (8x8 tiles take one pixel per lane and 64-record batches)."""
     out = []
     for tile in tiles:
@@ -41,10 +41,12 @@ def candidates(tiles=(16, 8), persistent=(False, True)) -> List[dict]:
 
 
 def schedules() -> List[dict]:
-    """Depth-phase schedules worth timing: the nearest 1/2^shift of the Gaussians first."""
-    return [dict(phases=p, phase0_shift=sh)
-            for p, sh in ((2, 5), (2, 6), (2, 7), (3, 5), (3, 6), (4, 6), (4, 7), (5, 7), (5, 8), (6, 10),
-                          (8, 14))]
+    """Depth-phase schedules worth timing: the nearest 1/2^shift of the Gaussians first, each later
+    phase 2^growth times wider."""
+    return [dict(phases=p, phase0_shift=sh, phase_growth=g)
+            for p, sh, g in ((2, 5, 2), (2, 6, 2), (2, 7, 2), (3, 5, 2), (3, 6, 2), (4, 6, 2), (4, 7, 2), (5, 7, 2),
+                             (5, 8, 2), (6, 10, 2), (8, 14, 2), (5, 6, 1), (6, 7, 1), (7, 8, 1), (8, 9, 1),
+                             (3, 6, 3), (4, 8, 3))]
 
 
 def workload_key(device_name: str, n: int, sh_degree: int, sizes: Sequence) -> str:

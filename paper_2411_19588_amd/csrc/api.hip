@@ -46,13 +46,14 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     if (!(o->dilation >= 0.0f && o->dilation < 1e30f) || !finite_pos(o->kappa)) return GS_ERR_INVALID_ARGUMENT;
     if (o->depth_mode != 0 && o->depth_mode != 1) return GS_ERR_INVALID_ARGUMENT;
     if (o->depth_output != 0 && o->depth_output != 1) return GS_ERR_INVALID_ARGUMENT;
-    if (o->persistent != 0 && o->persistent != 1) return GS_ERR_INVALID_ARGUMENT;
+    if (o->persistent < 0 || o->persistent > 2) return GS_ERR_INVALID_ARGUMENT;
     if (o->pixels_per_lane != 0 && o->pixels_per_lane != 1 && (t8 || (o->pixels_per_lane != 2 && o->pixels_per_lane != 4)))
         return GS_ERR_INVALID_ARGUMENT;
     if (o->record_fetch < GS_FETCH_DEFAULT || o->record_fetch > GS_FETCH_SCALAR) return GS_ERR_INVALID_ARGUMENT;
     if (o->tile_cull != 0 && o->tile_cull != 1) return GS_ERR_INVALID_ARGUMENT;
     if (o->phases < 0 || o->phases > GS_MAX_PHASES) return GS_ERR_INVALID_ARGUMENT;
     if (o->phase0_shift < 0 || o->phase0_shift > 20) return GS_ERR_INVALID_ARGUMENT;
+    if (o->phase_growth < 0 || o->phase_growth > 4) return GS_ERR_INVALID_ARGUMENT;
     if (o->max_pairs < 0 || o->max_pairs > GS_MAX_PAIRS) return GS_ERR_INVALID_ARGUMENT;
     if (n * (int64_t)n_views >= (int64_t)0xFFFFFFFFLL) return GS_ERR_INVALID_ARGUMENT;
 
@@ -88,6 +89,7 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     // automatic schedule: one view bins first the nearest ~1 Gaussian per tile (shift = log2 of the
     // Gaussians per tile, rounded); several views use a fixed 4-phase schedule
     L->phases = o->phases != 0 ? o->phases : (n_views == 1 ? kAutoPhasesOneView : kAutoPhasesViews);
+    L->phase_growth = o->phase_growth != 0 ? o->phase_growth : kAutoGrowth;
     if (o->phase0_shift != 0) {
         L->phase0_shift = o->phase0_shift;
     } else if (n_views == 1) {
@@ -114,6 +116,7 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     };
     L->pair_parts = parts_for(o->max_pairs);
     L->depth_parts = parts_for(L->nv);
+    L->queue_parts = parts_for(tiles);
 
     const size_t nv = (size_t)L->nv, P = (size_t)pixels, K = (size_t)o->max_pairs, T = (size_t)tiles;
     Cursor s;
@@ -133,7 +136,7 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
 
     Cursor w;
     const size_t nb = (nv + kBlock * 16 - 1) / (kBlock * 16) + 1;
-    const int parts = L->pair_parts > L->depth_parts ? L->pair_parts : L->depth_parts;
+    const int parts = std::max(L->queue_parts, std::max(L->pair_parts, L->depth_parts));
     L->w_counts = w.take(nv * 4);
     L->w_rects = w.take(nv * 8);
     L->w_dkeys = w.take(nv * 4);
@@ -156,6 +159,7 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     L->w_nzr = w.take(nv * 4);                 // later phases: the entries with pairs, in depth order
     // the split SH adjoint's planes (one view: fused Adam only)
     L->w_shf = w.take((size_t)n * (n_views == 1 ? kShf : 3 + 3 * (size_t)n_views) * 4);
+    L->w_queue = w.take(4 * T * 4);             // persistent longest-first queue: sort keys and tile ids
     L->workspace_bytes = w.at;
     return GS_OK;
 }
@@ -328,7 +332,7 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
         GS_TRY(radix_sort_u32(dk, dv, dk2, dv2, nullptr, (uint32_t)L.nv, 0, 32, L.depth_parts, hist, &in_b,
                               "depth_sort", T, s, 1, 0xFFFFFFFFu, &hdr->visible));   // entries with no tile left out
     const uint32_t* order = in_b ? dv2 : dv;
-    GS_TRY(launch_visible(L.phases, L.phase0_shift, hdr, s));
+    GS_TRY(launch_visible(L.phases, L.phase0_shift, L.phase_growth, hdr, s));
     float* tfinal = at<float>(saved, L.s_tfinal);
     uint32_t* nlast = at<uint32_t>(saved, L.s_nlast);
     uint8_t* done = at<uint8_t>(saved, L.s_done);
@@ -364,9 +368,12 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
         GS_TRY(launch_commit(tb ? tiles_b : tiles_a, tb ? vals_b : vals_a, hdr, ph, L.tiles, L.max_pairs, vals,
                              ranges, s));
         timer_end(T, s);
+        const uint32_t* order = nullptr;
+        if (o.persistent == 2)
+            GS_TRY(build_queue(L, ranges, ph, ph + 1, at<uint32_t>(workspace, L.w_queue), hist, &order, T, s));
         timer_begin(T, "composite_fwd", s);
         GS_TRY(launch_composite_fwd(o, L, ph, vt, dev_medium, rec, ranges, vals, hdr, alive, out_rgb, out_depth,
-                                    out_alpha, out_restored, tfinal, nlast, done, cair, dsum, wsum, s));
+                                    out_alpha, out_restored, tfinal, nlast, done, cair, dsum, wsum, order, s));
         timer_end(T, s);
     }
     return GS_OK;
@@ -400,12 +407,16 @@ int gs_render_backward(const gs_options* opts, const gs_gaussians* g, int32_t n_
     timer_begin(T, "zero_grad2d", s);
     GS_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, L.nv * kGrad2D, s));
     timer_end(T, s);
+    const uint32_t* order = nullptr;
+    if (o.persistent == 2)
+        GS_TRY(build_queue(L, at<uint2>(saved, L.s_ranges), 0, L.phases, at<uint32_t>(workspace, L.w_queue),
+                           at<uint32_t>(workspace, L.w_hist), &order, T, s));
     timer_begin(T, "composite_bwd", s);
     GS_TRY(launch_composite_bwd(o, L, vt, dev_medium, at<Record>(saved, L.s_records), at<uint2>(saved, L.s_ranges),
                                 at<uint32_t>(saved, L.s_vals), grad_rgb, grad_depth, grad_restored,
                                 at<float>(saved, L.s_tfinal), at<uint32_t>(saved, L.s_nlast),
                                 at<float>(saved, L.s_cair), at<float>(saved, L.s_dsum), at<float>(saved, L.s_wsum),
-                                grad2d, medpart, guard, s));
+                                grad2d, medpart, guard, order, s));
     timer_end(T, s);
     timer_begin(T, "medium_reduce", s);
     GS_TRY(launch_medium_reduce(vt, n_views, medpart, grad_medium, reinterpret_cast<const float*>(dev_medium), o,
@@ -472,12 +483,16 @@ int gs_render_backward_adam(const gs_options* opts, const gs_gaussians* g, int32
     timer_begin(T, "zero_grad2d", s);
     GS_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, L.nv * kGrad2D, s));
     timer_end(T, s);
+    const uint32_t* order = nullptr;
+    if (o.persistent == 2)
+        GS_TRY(build_queue(L, at<uint2>(saved, L.s_ranges), 0, L.phases, at<uint32_t>(workspace, L.w_queue),
+                           at<uint32_t>(workspace, L.w_hist), &order, T, s));
     timer_begin(T, "composite_bwd", s);
     GS_TRY(launch_composite_bwd(o, L, vt, dev_medium, at<Record>(saved, L.s_records), at<uint2>(saved, L.s_ranges),
                                 at<uint32_t>(saved, L.s_vals), grad_rgb, grad_depth, grad_restored,
                                 at<float>(saved, L.s_tfinal), at<uint32_t>(saved, L.s_nlast),
                                 at<float>(saved, L.s_cair), at<float>(saved, L.s_dsum), at<float>(saved, L.s_wsum),
-                                grad2d, medpart, guard, s));
+                                grad2d, medpart, guard, order, s));
     timer_end(T, s);
     timer_begin(T, "medium_reduce", s);
     GS_TRY(launch_medium_reduce(vt, n_views, medpart, const_cast<float*>(groups[5].grad), groups[5].param, o,

@@ -89,11 +89,11 @@ __global__ void k_view_table(ViewTable t, ViewInfo* dst, SavedHeader* hdr) {
 // of visible entries it kept; phase p < phases - 1 covers depth ranks up to
 // ceil(visible / 2^(shift - 2p)) (the whole range once the exponent reaches 0), the last phase
 // the rest.
-__global__ void k_visible(int phases, int shift, SavedHeader* hdr) {
+__global__ void k_visible(int phases, int shift, int growth, SavedHeader* hdr) {
     const uint32_t V = hdr->visible;
     hdr->phase_rank[0] = 0;
     for (int p = 0; p < phases; ++p) {
-        const int e = shift - 2 * p;
+        const int e = shift - growth * p;
         uint32_t r = V;
         if (p + 1 < phases && e > 0) r = (uint32_t)(((uint64_t)V + (1ull << e) - 1) >> e);
         hdr->phase_rank[p + 1] = r;
@@ -594,8 +594,8 @@ hipError_t launch_view_table(const ViewTable& t, int phases, ViewInfo* dst, Save
     return hipGetLastError();
 }
 
-hipError_t launch_visible(int phases, int phase0_shift, SavedHeader* hdr, hipStream_t s) {
-    hipLaunchKernelGGL(k_visible, dim3(1), dim3(1), 0, s, phases, phase0_shift, hdr);
+hipError_t launch_visible(int phases, int phase0_shift, int growth, SavedHeader* hdr, hipStream_t s) {
+    hipLaunchKernelGGL(k_visible, dim3(1), dim3(1), 0, s, phases, phase0_shift, growth, hdr);
     return hipGetLastError();
 }
 

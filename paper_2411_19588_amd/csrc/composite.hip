@@ -44,6 +44,7 @@ struct FwdArgs {
     const uint2* ranges;      // this phase's tile ranges
     const uint32_t* vals;
     uint32_t* queue;
+    const uint32_t* order;    // persistent mode: tile of each queue position (null: index order)
     uint32_t* alive;
     uint32_t* alive_count;
     float* out_rgb;
@@ -71,6 +72,7 @@ struct BwdArgs {
     const uint2* ranges;      // [phases][tiles]
     const uint32_t* vals;
     uint32_t* queue;
+    const uint32_t* order;    // persistent mode: tile of each queue position (null: index order)
     const float* grad_rgb;
     const float* grad_depth;
     const float* grad_restored;   // nullable
@@ -227,22 +229,45 @@ struct Shape {
     static_assert(SW * R == 64 && TW % SW == 0 && TH % SH == 0 && NW >= 1 && NW <= 4, "tile split");
 };
 
-// Next tile of this workgroup: its block index (one tile per workgroup), or the next value
-// of the persistent queue.  The value is wave-uniform by construction (read into a scalar
+// Next tile of this workgroup: its block index (one tile per workgroup), or the tile at the
+// next position of the persistent queue (the position itself, or order[position] for the
+// longest-first queue).  The value is wave-uniform by construction (read into a scalar
 // register), so every branch on it is uniform and the loop that pulls tiles has a uniform
-// exit; a value >= the tile count ends the loop.
+// exit; a position >= the tile count ends the loop.
 template <int NW, bool PERSISTENT>
-__device__ __forceinline__ uint32_t fetch_tile(uint32_t* queue, uint32_t iter, uint32_t* s_tile) {
+__device__ __forceinline__ uint32_t fetch_tile(uint32_t* queue, const uint32_t* order, uint32_t tiles, uint32_t iter,
+                                               uint32_t* s_tile) {
     if (!PERSISTENT) return iter == 0 ? (uint32_t)blockIdx.x : 0xFFFFFFFFu;
+    uint32_t pos;
     if (NW == 1) {
         uint32_t t = 0;
         if (threadIdx.x == 0) t = atomicAdd(queue, 1u);
-        return (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)t, 0));
+        pos = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)t, 0));
+    } else {
+        __syncthreads();   // every wave has read the previous value
+        if (threadIdx.x == 0) *s_tile = atomicAdd(queue, 1u);
+        __syncthreads();
+        pos = (uint32_t)__builtin_amdgcn_readfirstlane((int)*s_tile);
     }
-    __syncthreads();   // every wave has read the previous value
-    if (threadIdx.x == 0) *s_tile = atomicAdd(queue, 1u);
-    __syncthreads();
-    return (uint32_t)__builtin_amdgcn_readfirstlane((int)*s_tile);
+    if (pos >= tiles || order == nullptr) return pos;
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)order[pos]);
+}
+
+// Keys of the longest-first queue: the work of a tile is its list length in this phase
+// (forward) or summed over the phases (adjoint); the key is 32 - bit_length(length), so an
+// ascending stable sort puts the longest lists first in power-of-two buckets, ties in tile order.
+__global__ __launch_bounds__(kBlock) void k_queue_keys(const uint2* __restrict__ ranges, int phase0, int phase1,
+                                                     uint32_t tiles, uint32_t* __restrict__ keys,
+                                                     uint32_t* __restrict__ vals) {
+    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= tiles) return;
+    uint32_t len = 0;
+    for (int p = phase0; p < phase1; ++p) {
+        const uint2 rg = ranges[(size_t)p * tiles + t];
+        len += rg.y > rg.x ? rg.y - rg.x : 0u;
+    }
+    keys[t] = (uint32_t)__clz(len);   // 32 - bit_length
+    vals[t] = t;
 }
 
 // OR of a per-wave flag over the workgroup (a barrier; `slot` must not be reused before
@@ -307,7 +332,7 @@ __global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_fwd
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ox = (wave % S::NWX) * S::SW, oy = (wave / S::NWX) * S::SH;
     for (uint32_t iter = 0;; ++iter) {
-        const uint32_t tile = fetch_tile<NW, PERSISTENT>(a.queue, iter, &s_tile);
+        const uint32_t tile = fetch_tile<NW, PERSISTENT>(a.queue, a.order, a.tiles, iter, &s_tile);
         if (tile >= a.tiles) break;
         if (a.phase > 0 && a.alive[tile] == 0u) continue;   // every pixel terminated in an earlier phase
         const int v = find_view(a.vt, a.views, tile);
@@ -565,7 +590,7 @@ __global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_bwd
     const int ox = (wave % S::NWX) * S::SW, oy = (wave / S::NWX) * S::SH;
     if (guard_set(a.guard)) return;   // the forward was truncated: no gradient (uniform exit)
     for (uint32_t iter = 0;; ++iter) {
-        const uint32_t tile = fetch_tile<NW, PERSISTENT>(a.queue, iter, &s_tile);
+        const uint32_t tile = fetch_tile<NW, PERSISTENT>(a.queue, a.order, a.tiles, iter, &s_tile);
         if (tile >= a.tiles) break;
         const int v = find_view(a.vt, a.views, tile);
         const ViewInfo vi = a.vt[v];
@@ -981,16 +1006,31 @@ __global__ void k_stats_init(unsigned long long* out) {
 
 }  // namespace
 
+hipError_t build_queue(const Layout& L, const uint2* ranges, int p0, int p1, uint32_t* qbuf, uint32_t* hist,
+                       const uint32_t** order, void* timer, hipStream_t s) {
+    const uint32_t T = (uint32_t)L.tiles;
+    uint32_t *ka = qbuf, *va = qbuf + T, *kb = qbuf + 2 * (size_t)T, *vb = qbuf + 3 * (size_t)T;
+    timer_begin(timer, "queue_keys", s);
+    hipLaunchKernelGGL(k_queue_keys, dim3((T + kBlock - 1) / kBlock), dim3(kBlock), 0, s, ranges, p0, p1, T, ka, va);
+    timer_end(timer, s);
+    int in_b = 0;
+    const hipError_t e = radix_sort_u32(ka, va, kb, vb, nullptr, T, 0, 6, L.queue_parts, hist, &in_b, "queue_sort",
+                                        timer, s);
+    if (e != hipSuccess) return e;
+    *order = in_b ? vb : va;
+    return hipGetLastError();
+}
+
 hipError_t launch_composite_fwd(const gs_options& o, const Layout& L, int phase, const ViewInfo* vt,
                                 const gs_medium* med, const Record* rec, const uint2* ranges, const uint32_t* vals,
                                 SavedHeader* hdr, uint32_t* alive, float* out_rgb, float* out_depth,
                                 float* out_alpha, float* out_restored, float* tfinal, uint32_t* nlast, uint8_t* done,
-                                float* cair, float* dsum, float* wsum, hipStream_t s) {
+                                float* cair, float* dsum, float* wsum, const uint32_t* order, hipStream_t s) {
     if (L.tiles == 0) return hipSuccess;
     FwdArgs a{vt, L.views, (uint32_t)L.tiles, phase, L.phases - 1, med, rec, ranges + (size_t)phase * L.tiles, vals,
-              &hdr->queue[phase], alive, &hdr->phase_alive[phase], out_rgb, out_depth, out_alpha, out_restored,
-              tfinal, nlast, done, cair, dsum, wsum, L.pixels, o.alpha_min, o.alpha_max, o.t_min, o.depth_mode,
-              o.depth_output};
+              &hdr->queue[phase], order, alive, &hdr->phase_alive[phase], out_rgb, out_depth, out_alpha,
+              out_restored, tfinal, nlast, done, cair, dsum, wsum, L.pixels, o.alpha_min, o.alpha_max, o.t_min,
+              o.depth_mode, o.depth_output};
     return dispatch_shape<FwdRun>(o, a, o.persistent != 0, false, s);
 }
 
@@ -998,11 +1038,12 @@ hipError_t launch_composite_bwd(const gs_options& o, const Layout& L, const View
                                 const Record* rec, const uint2* ranges, const uint32_t* vals, const float* grad_rgb,
                                 const float* grad_depth, const float* grad_restored, const float* tfinal,
                                 const uint32_t* nlast, const float* cair, const float* dsum, const float* wsum,
-                                float* grad2d, float* medpart, const Guard& guard, hipStream_t s) {
+                                float* grad2d, float* medpart, const Guard& guard, const uint32_t* order,
+                                hipStream_t s) {
     if (L.tiles == 0) return hipSuccess;
-    BwdArgs a{vt, L.views, (uint32_t)L.tiles, L.phases, med, rec, ranges, vals, nullptr, grad_rgb, grad_depth,
-              grad_restored, tfinal, nlast, cair, dsum, wsum, grad2d, medpart, L.pixels, o.alpha_min, o.alpha_max,
-              o.t_min, o.depth_mode, o.depth_output, guard};
+    BwdArgs a{vt, L.views, (uint32_t)L.tiles, L.phases, med, rec, ranges, vals, nullptr, order, grad_rgb,
+              grad_depth, grad_restored, tfinal, nlast, cair, dsum, wsum, grad2d, medpart, L.pixels, o.alpha_min,
+              o.alpha_max, o.t_min, o.depth_mode, o.depth_output, guard};
     // the backward's persistent-mode tile counter lives after the medium partials
     a.queue = reinterpret_cast<uint32_t*>(medpart + L.tiles * 9);
     const bool pers = o.persistent != 0;

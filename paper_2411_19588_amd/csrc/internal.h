@@ -22,6 +22,7 @@ constexpr int kGrad2D = 10;              // per-(Gaussian, view) 2D gradient: m(
 // the nearest 1/64.
 constexpr int kAutoPhasesOneView = 2, kAutoShiftMin = 2, kAutoShiftMax = 12;
 constexpr int kAutoPhasesViews = 4, kAutoShiftViews = 6;
+constexpr int kAutoGrowth = 2;           // later phases 4x wider than the one before
 // Compositing launch shape when gs_options leaves it unset (16x16 tiles).
 constexpr int kDefaultPixelsPerLaneFwd = 2;   // two waves per tile
 constexpr int kDefaultRecordFetchFwd = GS_FETCH_LDS;
@@ -70,15 +71,16 @@ struct SavedHeader {
 
 struct Layout {
     int64_t n, nv, pixels, tiles, rows, row_words, max_pairs;
-    int32_t views, phases, phase0_shift;
-    int32_t tile_w, tile_h, tile_bits, tile_passes, pair_parts, depth_parts;
+    int32_t views, phases, phase0_shift, phase_growth;
+    int32_t tile_w, tile_h, tile_bits, tile_passes, pair_parts, depth_parts, queue_parts;
     ViewTable table;
     // saved context offsets (bytes)
     size_t s_header, s_records, s_depth_keys, s_ranges, s_vals, s_alive;
     size_t s_tfinal, s_nlast, s_done, s_cair, s_dsum, s_wsum, saved_bytes;
     // workspace offsets (bytes)
     size_t w_counts, w_rects, w_dkeys, w_dvals, w_dkeys2, w_dvals2, w_pcounts, w_offsets, w_blocksums, w_emit_start;
-    size_t w_tiles_a, w_vals_a, w_tiles_b, w_vals_b, w_hist, w_grad2d, w_medpart, w_adam, w_rowbits, w_nzr, w_shf, workspace_bytes;
+    size_t w_tiles_a, w_vals_a, w_tiles_b, w_vals_b, w_hist, w_grad2d, w_medpart, w_adam, w_rowbits, w_nzr, w_shf, w_queue;
+    size_t workspace_bytes;
 };
 
 int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_camera* cams, Layout* L);
@@ -159,7 +161,7 @@ hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, 
                           int* out_in_b, const char* tag, void* timer, hipStream_t s, int use_drop = 0,
                           uint32_t drop_key = 0, uint32_t* n_kept = nullptr);
 // Phase rank ranges from the number of visible entries the depth sort kept.
-hipError_t launch_visible(int phases, int phase0_shift, SavedHeader* hdr, hipStream_t s);
+hipError_t launch_visible(int phases, int phase0_shift, int growth, SavedHeader* hdr, hipStream_t s);
 // Per-entry pair counts of phase p (by depth rank): whole rectangles in phase 0, only the tiles
 // still alive in later phases, 0 outside the phase's ranks.
 // Exact tile culling: a (Gaussian, tile) pair of the rectangle is dropped when no pixel centre
@@ -206,13 +208,19 @@ hipError_t launch_composite_fwd(const gs_options& o, const Layout& L, int phase,
                                 const gs_medium* med, const Record* rec, const uint2* ranges, const uint32_t* vals,
                                 SavedHeader* hdr, uint32_t* alive, float* out_rgb, float* out_depth,
                                 float* out_alpha, float* out_restored, float* tfinal, uint32_t* nlast, uint8_t* done,
-                                float* cair, float* dsum, float* wsum, hipStream_t s);
+                                float* cair, float* dsum, float* wsum, const uint32_t* order, hipStream_t s);
+// Longest-first order of a persistent pass (opts.persistent = 2) over the phases [p0, p1) of
+// `ranges` ([phases][tiles]): per-tile keys 32 - bit_length(list length), a stable 6-bit radix
+// sort, and in *order the tile ids, longest lists first (inside qbuf, 4 * tiles u32).
+hipError_t build_queue(const Layout& L, const uint2* ranges, int p0, int p1, uint32_t* qbuf, uint32_t* hist,
+                       const uint32_t** order, void* timer, hipStream_t s);
 // grad_restored (nullable): upstream gradient of C_air, added to the colour accumulators' gradient.
 hipError_t launch_composite_bwd(const gs_options& o, const Layout& L, const ViewInfo* vt, const gs_medium* med,
                                 const Record* rec, const uint2* ranges, const uint32_t* vals, const float* grad_rgb,
                                 const float* grad_depth, const float* grad_restored, const float* tfinal,
                                 const uint32_t* nlast, const float* cair, const float* dsum, const float* wsum,
-                                float* grad2d, float* medpart, const Guard& guard, hipStream_t s);
+                                float* grad2d, float* medpart, const Guard& guard, const uint32_t* order,
+                                hipStream_t s);
 // Per-view sums of the tiles' medium partials into grad_medium [views][9]; with `adam`, also one
 // Adam step of the medium parameters (group with count 9 * views) using the device bias corrections.
 // When the guard is set, grad_medium is zeroed and no step is taken.

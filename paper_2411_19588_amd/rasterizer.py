@@ -22,7 +22,7 @@ class RasterConfig:
     0.99, termination at T < 1e-4, EWA dilation 0.3, extent kappa 11.1."""
     tile: int = 16
     lds_batch: int = 64
-    persistent: bool = False
+    persistent: int = 0               # 0 one workgroup per tile; 1 persistent queue; 2 longest list first
     pixels_per_lane: int = 0          # 0 = library default
     record_fetch: str = "default"     # "default", "lds" or "scalar"
     alpha_min: float = 1.0 / 255.0
@@ -35,6 +35,7 @@ class RasterConfig:
     tile_cull: bool = True            # drop (Gaussian, tile) pairs that cannot reach alpha_min
     phases: int = 0                   # 0 = automatic (the library's gs_schedule)
     phase0_shift: int = 0             # 0 = automatic
+    phase_growth: int = 0             # log2 of the later phases' growth; 0 = automatic (4x)
     max_pairs: int = 1 << 22
     reg_opacity: float = 0.0          # lambda_o of the opacity regulariser lambda_o mean(o) (0 = off)
     reg_scale: float = 0.0            # lambda_s of the scale regulariser lambda_s mean(s) (0 = off)
@@ -44,7 +45,7 @@ class RasterConfig:
         o = N.default_options()
         o.tile_w = o.tile_h = int(self.tile)
         o.lds_batch = int(self.lds_batch)
-        o.persistent = 1 if self.persistent else 0
+        o.persistent = int(self.persistent)
         o.pixels_per_lane = int(self.pixels_per_lane)
         o.record_fetch = {"default": N.GS_FETCH_DEFAULT, "lds": N.GS_FETCH_LDS,
                           "scalar": N.GS_FETCH_SCALAR}[self.record_fetch]
@@ -58,6 +59,7 @@ class RasterConfig:
         o.tile_cull = 1 if self.tile_cull else 0
         o.phases = int(self.phases)
         o.phase0_shift = int(self.phase0_shift)
+        o.phase_growth = int(self.phase_growth)
         o.max_pairs = int(self.max_pairs if max_pairs is None else max_pairs)
         o.timer = timer
         o.reg_opacity = float(self.reg_opacity)

@@ -68,7 +68,9 @@ def test_grad_vs_oracle_sh_degree0_config0(oracle_mod):
                                  dict(record_fetch="scalar", pixels_per_lane=1),
                                  dict(record_fetch="scalar", pixels_per_lane=2, persistent=True),
                                  dict(record_fetch="scalar", pixels_per_lane=4),
-                                 dict(tile=8, lds_batch=64, record_fetch="scalar", persistent=True)])
+                                 dict(tile=8, lds_batch=64, record_fetch="scalar", persistent=True),
+                                 dict(persistent=2), dict(persistent=2, record_fetch="lds", pixels_per_lane=2),
+                                 dict(persistent=2, phases=3, phase0_shift=5)])
 def test_grad_launch_variants(oracle_mod, cfg):
     O = oracle_mod
     sc = synth.make_scene(1, n=3000, width=96, height=64)

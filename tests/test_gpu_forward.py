@@ -278,7 +278,9 @@ def test_image_max_views(oracle_mod):
                                  dict(record_fetch="scalar", pixels_per_lane=4, persistent=True),
                                  dict(record_fetch="scalar", pixels_per_lane=1, persistent=True),
                                  dict(tile=8, lds_batch=64), dict(tile=8, lds_batch=64, persistent=True),
-                                 dict(tile=8, lds_batch=64, record_fetch="scalar")])
+                                 dict(tile=8, lds_batch=64, record_fetch="scalar"), dict(persistent=2),
+                                 dict(persistent=2, pixels_per_lane=4, record_fetch="scalar", phases=3, phase0_shift=6),
+                                 dict(persistent=2, tile=8, lds_batch=64)])
 def test_launch_variants_bitwise_equal(cfg):
     """Every tile shape / split / batch / record fetch / persistent variant walks each pixel's
     Gaussians in the same order with the same operations, so the images are bitwise identical."""
@@ -367,3 +369,15 @@ def test_nonfinite_input_flagged_and_culled(oracle_mod):
                             sh=sc.sh[:, keep], sh_degree=0, cameras=sc.cameras, medium=sc.medium)
     ref = U.forward(ref_scene, U.make_rast(ref_scene))[:3]
     assert torch.equal(rgb, ref[0])
+
+
+def test_longest_first_queue_several_views_bitwise_equal():
+    """The longest-first persistent queue (tiles of every view sorted by list length before each
+    phase's pass) renders the same images as one workgroup per tile, over views of uneven size."""
+    sizes = [(203, 141), (97, 61), (160, 120)]
+    sc = synth.make_scene(3, n=8000, n_views=3, view_sizes=sizes)
+    U.say("longest-first queue, 3 views")
+    base = U.forward(sc, U.make_rast(sc, phases=3, phase0_shift=5))[:3]
+    other = U.forward(sc, U.make_rast(sc, phases=3, phase0_shift=5, persistent=2))[:3]
+    for a, b in zip(base, other):
+        assert torch.equal(a, b)
