@@ -502,24 +502,25 @@ __device__ __forceinline__ bool blend_adjoint(const Splat& s, float fpx, float f
     constexpr bool kLaneSums = PPL >= 2;
     float P = 0.0f, Q = 0.0f, U = 0.0f;
     bool any = false;
+    // Branch-free over the lane's pixels: a pixel past its last contributor, or where the splat's
+    // alpha is below alpha_min, takes w = dalpha = 0 (its sums gain exact zeros) and keeps T.
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
-        if (idx >= my_last[k]) continue;
         float dy;
         const float pw = splat_power(s, ct, fpy0 + (float)(k * R), dy);
         const float ev = __builtin_amdgcn_exp2f(pw);
         const float araw = s.o * ev;
         const float alpha = fminf(amax, araw);
-        if (alpha < amin) continue;
-        any = true;
+        const bool act = idx < my_last[k] && alpha >= amin;
+        any = any || act;
         const float rom = __builtin_amdgcn_rcpf(1.0f - alpha);
         const float Ti = T[k] * rom;
-        const float w = alpha * Ti;
+        const float w = act ? alpha * Ti : 0.0f;
         const float gf = fmaf(gC0[k], s.r, fmaf(gC1[k], s.g, fmaf(gC2[k], s.b, fmaf(gD[k], s.d, gW[k]))));
         // a clamped alpha does not depend on the opacity or the exponent
-        const float dalpha = araw <= amax ? fmaf(Ti, gf, -S[k] * rom) : 0.0f;
+        const float dalpha = (act && araw <= amax) ? fmaf(Ti, gf, -S[k] * rom) : 0.0f;
         S[k] = fmaf(gf, w, S[k]);
-        T[k] = Ti;
+        T[k] = act ? Ti : T[k];
         g10[6] = fmaf(gC0[k], w, g10[6]);
         g10[7] = fmaf(gC1[k], w, g10[7]);
         g10[8] = fmaf(gC2[k], w, g10[8]);
