@@ -5,10 +5,10 @@
 // Each pass is reduce-then-scan over a FIXED number of partitions `parts`; the
 // element count is read from device memory, so the launch shapes never depend
 // on data and a whole forward can be captured into a graph.
-//   1. k_hist:      each partition counts its digits.  Lanes of a wave64 that
-//                   share a digit are found by intersecting one ballot per
-//                   digit bit; one lane adds the group's count (no contention
-//                   on runs of equal keys).
+//   1. k_hist:      each partition counts its digits with LDS atomics (the
+//                   counts need no ranks); a wave whose valid keys all share one
+//                   digit adds them with one atomic.  The next radix tile's keys
+//                   are loaded while the current one is counted.
 //   2. k_scan_rows: one workgroup per digit scans that digit's row of the
 //                   digit-major [radix][parts] table and records the row total.
 // A key of b bits takes ceil(b / 9) passes of at most 9 bits, split evenly: 8-bit
@@ -16,9 +16,11 @@
 // 17-bit tile ids (up to 131071 tiles) take two passes instead of three.
 //   3. k_scatter:   each partition turns the row totals into digit bases, then
 //                   re-reads its range tile by tile (2048 keys), ranks keys
-//                   stably inside each wave with the same ballots, combines the
-//                   four waves through LDS, reorders the tile in LDS by digit and
-//                   writes it out in digit runs (coalesced).
+//                   stably inside each wave (lanes that share a digit are found by
+//                   intersecting one ballot per digit bit), combines the four
+//                   waves through LDS, reorders the tile in LDS by digit and
+//                   writes it out in digit runs (coalesced).  The next tile's keys
+//                   and values are loaded while the current one is written out.
 #include <string>
 
 #include "internal.h"
@@ -62,20 +64,34 @@ __global__ __launch_bounds__(kBlock) void k_hist(const uint32_t* __restrict__ ke
     const uint32_t mask = (1u << nbits) - 1u;
     uint32_t t0, t1;
     part_range(n, parts, blockIdx.x, t0, t1);
-    for (uint32_t t = t0; t < t1; ++t) {
+    uint32_t key[kSortItems];
+    auto load_tile = [&](uint32_t t) {   // all loads in flight before any count
         const uint32_t base = t * kSortTile;
-        uint32_t key[kSortItems];
 #pragma unroll
-        for (int k = 0; k < kSortItems; ++k) {   // all loads in flight before any ballot
+        for (int k = 0; k < kSortItems; ++k) {
             const uint32_t idx = base + k * kBlock + tid;
             key[k] = idx < n ? keys[idx] : 0u;
         }
+    };
+    if (t0 < t1) load_tile(t0);
+    for (uint32_t t = t0; t < t1; ++t) {
+        const uint32_t base = t * kSortTile;
+        uint32_t cur[kSortItems];
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) cur[k] = key[k];
+        if (t + 1 < t1) load_tile(t + 1);
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
-            const bool valid = base + k * kBlock + tid < n && !(use_drop && key[k] == drop);
-            const uint32_t digit = (key[k] >> shift) & mask;
-            const uint64_t m = match_digit(digit, nbits, __ballot(valid));
-            if (valid && lane == __ffsll((unsigned long long)m) - 1) atomicAdd(&h[digit], (uint32_t)__popcll(m));
+            const bool valid = base + k * kBlock + tid < n && !(use_drop && cur[k] == drop);
+            const uint32_t digit = (cur[k] >> shift) & mask;
+            const uint64_t vm = __ballot(valid);
+            const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)digit);
+            const uint64_t same = __ballot(valid && digit == d0);
+            if (same == vm) {   // one digit in the whole wave (runs of equal keys): one atomic
+                if (vm != 0ull && lane == 0) atomicAdd(&h[d0], (uint32_t)__popcll(vm));
+            } else if (valid) {
+                atomicAdd(&h[digit], 1u);
+            }
         }
     }
     __syncthreads();
@@ -178,19 +194,24 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
     uint32_t t0, t1;
     part_range(n, parts, blockIdx.x, t0, t1);
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    // wave w ranks elements [tbase + w*512, tbase + (w+1)*512) of a tile in order: item k, lane l.
+    uint32_t key[kSortItems], val[kSortItems];
+    auto load_tile = [&](uint32_t t) {   // all loads in flight before the ranking
+        const uint32_t wb = t * kSortTile + (uint32_t)wave * 64u * kSortItems;
+#pragma unroll
+        for (int k = 0; k < kSortItems; ++k) {
+            const uint32_t idx = wb + k * 64 + lane;
+            key[k] = idx < n ? kin[idx] : 0u;
+            val[k] = idx < n ? vin[idx] : 0u;
+        }
+    };
+    if (t0 < t1) load_tile(t0);
     for (uint32_t t = t0; t < t1; ++t) {
         for (int i = tid; i < 4 * D; i += kBlock) (&wcnt[0][0])[i] = 0;
         __syncthreads();
         const uint32_t tbase = t * kSortTile;
-        // wave w ranks elements [tbase + w*512, tbase + (w+1)*512) in order: item k, lane l.
         const uint32_t wbase = tbase + (uint32_t)wave * 64u * kSortItems;
-        uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
-#pragma unroll
-        for (int k = 0; k < kSortItems; ++k) {   // all loads in flight before the ranking
-            const uint32_t idx = wbase + k * 64 + lane;
-            key[k] = idx < n ? kin[idx] : 0u;
-            val[k] = idx < n ? vin[idx] : 0u;
-        }
+        uint32_t rank[kSortItems];
 #pragma unroll
         for (int k = 0; k < kSortItems; ++k) {
             const uint32_t idx = wbase + k * 64 + lane;
@@ -244,6 +265,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
                 }
             }
         }
+        if (t + 1 < t1) load_tile(t + 1);   // in flight while this tile is written out
         // LDS slot i of digit d goes to global slot (run[d] - tstart[d]) + i
 #pragma unroll
         for (int j = 0; j < DPT; ++j) run[tid * DPT + j] = gbase[j] - tsj[j];
