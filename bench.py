@@ -122,9 +122,8 @@ def kernel_bytes(name: str, n: int, views: int, K: int, P: int, tiles: int, ncoe
         "project_fwd": param + NV * (48 + 4 + 8 + 4 + 8),
         "depth_sort_hist": NV * 4,                 # per digit pass: keys read
         "depth_sort_scatter": NV * 16,             # per digit pass: keys and values read and written
-        "alive_rows": tiles * 4 + tiles // 4,      # alive flags read, a span per tile row written
-        "phase_count": NV * 8,                     # per phase: order + count (or rectangle) per entry
-        "count_scan": NV * (4 + 4 + 8),            # per phase: two passes over the counts, offsets write
+        # per phase: order + count (or rectangle) per entry, counts written and read back, offsets
+        "count_scan": NV * (8 + 4 + 4 + 8),
         "emit": (K * 8) / per_step + NV * 4,
         # every digit pass of every phase's tile sort moves that phase's pairs
         "tile_sort_hist": (K * 4 * tile_passes) / per_step,
@@ -184,7 +183,7 @@ def traffic_for(kernel: str):
         return None
 
 
-KERNELS = ["project_fwd", "depth_sort_hist", "depth_sort_scan", "depth_sort_scatter", "alive_rows", "phase_count",
+KERNELS = ["project_fwd", "depth_sort_hist", "depth_sort_scan", "depth_sort_scatter",
            "count_scan", "emit", "tile_sort_hist", "tile_sort_scan", "tile_sort_scatter", "commit", "composite_fwd",
            "zero_grad2d", "composite_bwd", "medium_reduce", "project_bwd", "adam_sh", "sh_views"]
 

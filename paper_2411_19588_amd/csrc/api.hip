@@ -135,7 +135,7 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     L->saved_bytes = s.at;
 
     Cursor w;
-    const size_t nb = (nv + kBlock * 16 - 1) / (kBlock * 16) + 1;
+    const size_t nb = (size_t)count_scan_blocks((int64_t)nv) + 1;
     const int parts = std::max(L->queue_parts, std::max(L->pair_parts, L->depth_parts));
     L->w_counts = w.take(nv * 4);
     L->w_rects = w.take(nv * 8);
@@ -155,7 +155,7 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     L->w_grad2d = w.take(nv * kGrad2D * 4);
     L->w_medpart = w.take(T * 9 * 4 + 256);   // + persistent-mode tile counter of the backward
     L->w_adam = w.take(16);                    // bias corrections of a fused Adam step
-    L->w_rowbits = w.take((size_t)rows * L->row_words * 8);   // alive columns per tile row (later phases)
+    L->w_rowbits = w.take(2 * (size_t)rows * L->row_words * 8);   // alive columns per tile row, two buffers
     L->w_nzr = w.take(nv * 4);                 // later phases: the entries with pairs, in depth order
     // the split SH adjoint's planes (one view: fused Adam only)
     L->w_shf = w.take((size_t)n * (n_views == 1 ? kShf : 3 + 3 * (size_t)n_views) * 4);
@@ -321,8 +321,8 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
     uint32_t* vals_b = at<uint32_t>(workspace, L.w_vals_b);
     uint32_t* hist = at<uint32_t>(workspace, L.w_hist);
 
-    GS_TRY(launch_view_table(L.table, L.phases, vt, hdr, s));
-    GS_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(ranges), 0u, (int64_t)GS_MAX_PHASES * L.tiles * 2, s));
+    GS_TRY(launch_view_table(L.table, vt, hdr, reinterpret_cast<uint32_t*>(ranges), (int64_t)L.phases * L.tiles * 2,
+                             s));
     timer_begin(T, "project_fwd", s);
     GS_TRY(launch_project_fwd(*g, n_views, dev_cams, vt, o, rec, counts, rects, depth_keys, dk, dv, hdr, s));
     timer_end(T, s);
@@ -332,7 +332,7 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
         GS_TRY(radix_sort_u32(dk, dv, dk2, dv2, nullptr, (uint32_t)L.nv, 0, 32, L.depth_parts, hist, &in_b,
                               "depth_sort", T, s, 1, 0xFFFFFFFFu, &hdr->visible));   // entries with no tile left out
     const uint32_t* order = in_b ? dv2 : dv;
-    GS_TRY(launch_visible(L.phases, L.phase0_shift, L.phase_growth, hdr, s));
+    const PhaseSched ps{L.phases, L.phase0_shift, L.phase_growth};
     float* tfinal = at<float>(saved, L.s_tfinal);
     uint32_t* nlast = at<uint32_t>(saved, L.s_nlast);
     uint8_t* done = at<uint8_t>(saved, L.s_done);
@@ -340,19 +340,15 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
     float* dsum = at<float>(saved, L.s_dsum);
     float* wsum = at<float>(saved, L.s_wsum);
     const CullArgs cull{rec, log2f(o.alpha_min), o.tile_w, o.tile_h, o.tile_cull};
-    const AliveRows ar{at<uint64_t>(workspace, L.w_rowbits),
-                       (uint32_t)L.row_words, at<uint32_t>(workspace, L.w_nzr)};
+    // alive-column masks: phase p > 0 reads buffer p & 1, which the compositing of phase p - 1 set
+    const int64_t bits_words = L.rows * L.row_words;
+    uint64_t* bits = at<uint64_t>(workspace, L.w_rowbits);
     for (int ph = 0; ph < L.phases; ++ph) {
-        if (ph > 0) {
-            timer_begin(T, "alive_rows", s);
-            GS_TRY(launch_alive_rows(vt, L.views, L.rows, alive, ar, s));
-            timer_end(T, s);
-        }
-        timer_begin(T, "phase_count", s);
-        GS_TRY(launch_phase_count(order, counts, rects, L.nv, L.n, vt, ar, hdr, ph, pcounts, s));
-        timer_end(T, s);
+        const AliveRows ar{bits + (ph & 1) * bits_words, (uint32_t)L.row_words, at<uint32_t>(workspace, L.w_nzr)};
+        uint64_t* next_bits = ph + 1 < L.phases ? bits + ((ph + 1) & 1) * bits_words : nullptr;
         timer_begin(T, "count_scan", s);
-        GS_TRY(launch_count_scan(pcounts, L.nv, offsets, blocksums, hdr, ph, L.max_pairs, emit_start, ar.nzr, s));
+        GS_TRY(launch_count_scan(order, counts, rects, L.nv, L.n, vt, ar, next_bits, bits_words, ps, hdr, ph, pcounts,
+                                 offsets, blocksums, L.max_pairs, emit_start, s));
         timer_end(T, s);
         timer_begin(T, "emit", s);
         GS_TRY(launch_emit(order, offsets, emit_start, blocksums, rects, L.nv, L.n, vt, ar, hdr, ph, L.max_pairs,
@@ -373,7 +369,8 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
             GS_TRY(build_queue(L, ranges, ph, ph + 1, at<uint32_t>(workspace, L.w_queue), hist, &order, T, s));
         timer_begin(T, "composite_fwd", s);
         GS_TRY(launch_composite_fwd(o, L, ph, vt, dev_medium, rec, ranges, vals, hdr, alive, out_rgb, out_depth,
-                                    out_alpha, out_restored, tfinal, nlast, done, cair, dsum, wsum, order, s));
+                                    out_alpha, out_restored, tfinal, nlast, done, cair, dsum, wsum, order, next_bits,
+                                    s));
         timer_end(T, s);
     }
     return GS_OK;
@@ -475,13 +472,13 @@ int gs_render_backward_adam(const gs_options* opts, const gs_gaussians* g, int32
     float* grad2d = at<float>(workspace, L.w_grad2d);
     float* medpart = at<float>(workspace, L.w_medpart);
     float* bc = at<float>(workspace, L.w_adam);
-    // the step is skipped when this forward overflowed or the caller's sticky flag is set:
-    // k_adam_prep folds both into state[1], which every later kernel of the step reads
+    // the step is skipped when this forward overflowed or the caller's sticky flag is set: the
+    // step start folds both into state[1], which every later kernel of the step reads
     const Guard guard{reinterpret_cast<const uint32_t*>(state + GS_STATE_SKIP), 0xFFFFFFFFu};
 
-    GS_TRY(launch_adam_prep(state, &hdr->status, beta1, beta2, bc, s));
     timer_begin(T, "zero_grad2d", s);
-    GS_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, L.nv * kGrad2D, s));
+    GS_TRY(launch_zero_adam_prep(reinterpret_cast<uint32_t*>(grad2d), L.nv * kGrad2D, state, &hdr->status, beta1,
+                                 beta2, bc, s));
     timer_end(T, s);
     const uint32_t* order = nullptr;
     if (o.persistent == 2)

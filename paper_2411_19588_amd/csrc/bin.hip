@@ -27,7 +27,8 @@
 namespace gs {
 namespace {
 
-constexpr int kScanChunk = kBlock * 16;
+constexpr int kScanChunk = 1024;                  // depth ranks per block of the count scan
+constexpr int kDownItems = kScanChunk / kBlock;   // consecutive ranks per thread of the down-sweep
 constexpr int kEmitItems = 4;
 constexpr int kEmitSpan = kBlock * kEmitItems;
 
@@ -63,8 +64,11 @@ __device__ __forceinline__ bool tile_may_contribute(const float4& ra, const floa
     return !(best + 4e-6f * mag + 1e-4f < limit);
 }
 
-__global__ void k_view_table(ViewTable t, ViewInfo* dst, SavedHeader* hdr) {
+__global__ __launch_bounds__(kBlock) void k_view_table(ViewTable t, ViewInfo* dst, SavedHeader* hdr, uint32_t* fill,
+                                                      int64_t fill_count) {
     const int i = threadIdx.x;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + i; j < fill_count; j += (int64_t)gridDim.x * kBlock) fill[j] = 0u;
+    if (blockIdx.x != 0) return;
     if (i < t.count) dst[i] = t.v[i];
     if (i == 0) {
         hdr->status = 0;
@@ -85,19 +89,21 @@ __global__ void k_view_table(ViewTable t, ViewInfo* dst, SavedHeader* hdr) {
     }
 }
 
-// The depth sort left out the entries that touch no tile (key 0xFFFFFFFF) and wrote the number
-// of visible entries it kept; phase p < phases - 1 covers depth ranks up to
-// ceil(visible / 2^(shift - 2p)) (the whole range once the exponent reaches 0), the last phase
-// the rest.
-__global__ void k_visible(int phases, int shift, int growth, SavedHeader* hdr) {
+// The depth sort left out the entries that touch no tile (key 0xFFFFFFFF) and wrote the number V
+// of visible entries it kept; phase p < phases - 1 ends at depth rank ceil(V / 2^(shift - growth p))
+// (at V once the exponent reaches 0), the last phase at V.
+__device__ __forceinline__ uint32_t phase_end(uint32_t V, const PhaseSched& ps, int p) {
+    const int e = ps.shift - ps.growth * p;
+    if (p + 1 < ps.phases && e > 0) return (uint32_t)(((uint64_t)V + (1ull << e) - 1) >> e);
+    return V;
+}
+
+// Depth ranks [r0, r1) of a phase.
+__device__ __forceinline__ void phase_ranks(const SavedHeader* hdr, const PhaseSched& ps, int phase, uint32_t& r0,
+                                            uint32_t& r1) {
     const uint32_t V = hdr->visible;
-    hdr->phase_rank[0] = 0;
-    for (int p = 0; p < phases; ++p) {
-        const int e = shift - growth * p;
-        uint32_t r = V;
-        if (p + 1 < phases && e > 0) r = (uint32_t)(((uint64_t)V + (1ull << e) - 1) >> e);
-        hdr->phase_rank[p + 1] = r;
-    }
+    r0 = phase == 0 ? 0u : phase_end(V, ps, phase - 1);
+    r1 = phase_end(V, ps, phase);
 }
 
 // A later phase after which no tile was left alive emits nothing: the scan kernels skip it.
@@ -117,115 +123,202 @@ __device__ __forceinline__ uint32_t alive_in(const uint64_t* __restrict__ bits, 
     return c;
 }
 
-__global__ __launch_bounds__(kBlock) void k_phase_count(const uint32_t* __restrict__ order,
-                                                       const uint32_t* __restrict__ counts,
-                                                       const uint2* __restrict__ rects, int64_t nv, int64_t n,
-                                                       const ViewInfo* __restrict__ vt,
-                                                       const uint64_t* __restrict__ rowbits, uint32_t row_words,
-                                                       const SavedHeader* __restrict__ hdr, int phase,
-                                                       uint32_t* __restrict__ pcounts) {
-    if (phase_empty(hdr, phase)) return;   // no tile left: nothing reads this phase's counts
-    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (r >= nv) return;
-    const uint32_t r0 = hdr->phase_rank[phase], r1 = hdr->phase_rank[phase + 1];
-    // outside the phase's ranks nothing is written: the scans and the emission read counts only
-    // inside them
-    if ((uint64_t)r < r0 || (uint64_t)r >= r1) return;
-    uint32_t c = 0;
-    if (!hdr->stop) {
-        const uint32_t e = order[r];
-        if (phase == 0) {
-            c = counts[e];
-        } else {
-            // every alive tile of the rectangle (the emission marks the culled ones, as in phase 0):
-            // one popcount per 64 columns of each row of the rectangle
-            const uint2 rc = rects[e];
-            const ViewInfo vi = vt[e / (uint64_t)n];
-            const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
-            for (uint32_t ty = y0; ty <= y1; ++ty)
-                c += alive_in(rowbits + (size_t)(vi.row_base + ty) * row_words, x0, x1);
-        }
-    }
-    pcounts[r] = c;
-}
 
-// Per chunk of kScanChunk ranks: the sum of the phase's counts (blocksums[b]) and the number of
-// non-zero ones (blocksums[nb + b]).
-__global__ __launch_bounds__(kBlock) void k_count_reduce(const uint32_t* __restrict__ pcounts, int64_t nv,
-                                                        const SavedHeader* __restrict__ hdr, int phase,
-                                                        uint64_t* __restrict__ blocksums, int nb) {
-    __shared__ uint64_t red[kBlock];
-    __shared__ uint32_t zred[kBlock];
+// Per chunk of kScanChunk depth ranks: the phase's per-entry pair counts (pcounts, written only
+// inside the phase's ranks: the scan and the emission read them only there), their sum
+// (blocksums[b]) and the number of non-zero ones (blocksums[nb + b]).  One rank per thread, so
+// that many waves overlap the gathers of the later phases' row loops.
+constexpr int kCountThreads = 1024;
+constexpr int kCountItems = kScanChunk / kCountThreads;
+
+__global__ __launch_bounds__(kCountThreads) void k_phase_counts(const uint32_t* __restrict__ order,
+                                                               const uint32_t* __restrict__ counts,
+                                                               const uint2* __restrict__ rects, int64_t nv, int64_t n,
+                                                               const ViewInfo* __restrict__ vt,
+                                                               const uint64_t* __restrict__ rowbits,
+                                                               uint32_t row_words, const SavedHeader* __restrict__ hdr,
+                                                               int phase, PhaseSched ps,
+                                                               uint32_t* __restrict__ pcounts,
+                                                               uint64_t* __restrict__ blocksums, int nb) {
+    __shared__ uint64_t red[kCountThreads / 64];
+    __shared__ uint32_t zred[kCountThreads / 64];
+    const int tid = threadIdx.x;
     const int64_t b0 = (int64_t)blockIdx.x * kScanChunk;
-    const int64_t r0 = hdr->phase_rank[phase], r1 = hdr->phase_rank[phase + 1];
-    if (phase_empty(hdr, phase) || b0 + kScanChunk <= r0 || b0 >= r1) {   // no count of the phase here
-        if (threadIdx.x == 0) {
+    uint32_t r0, r1;
+    phase_ranks(hdr, ps, phase, r0, r1);
+    if (phase_empty(hdr, phase) || b0 + kScanChunk <= (int64_t)r0 || b0 >= (int64_t)r1) {   // nothing here
+        if (tid == 0) {
             blocksums[blockIdx.x] = 0;
             blocksums[nb + blockIdx.x] = 0;
         }
         return;
     }
+    const bool stop = hdr->stop != 0u;   // after an overflow every count is 0
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    uint32_t e[kCountItems], c[kCountItems];
+#pragma unroll
+    for (int k = 0; k < kCountItems; ++k) {   // all entry loads in flight before the gathers
+        const int64_t r = b0 + k * kCountThreads + tid;
+        e[k] = r < nv && r >= (int64_t)r0 && r < (int64_t)r1 && !stop ? order[r] : kNone;
+    }
+    if (phase == 0) {   // whole rectangles
+#pragma unroll
+        for (int k = 0; k < kCountItems; ++k) c[k] = e[k] != kNone ? counts[e[k]] : 0u;
+    } else {
+        // every alive tile of the rectangle (the emission marks the culled ones, as in phase 0): one
+        // popcount per 64 columns of each row of the rectangle
+#pragma unroll
+        for (int k = 0; k < kCountItems; ++k) {
+            c[k] = 0u;
+            if (e[k] == kNone) continue;
+            const uint2 rc = rects[e[k]];
+            const uint32_t rb = vt[e[k] / (uint32_t)n].row_base;
+            const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
+            for (uint32_t ty = y0; ty <= y1; ++ty) c[k] += alive_in(rowbits + (size_t)(rb + ty) * row_words, x0, x1);
+        }
+    }
     uint64_t s = 0;
     uint32_t z = 0;
-    for (int k = 0; k < 16; ++k) {
-        const int64_t r = b0 + k * kBlock + threadIdx.x;
-        if (r < nv && r >= r0 && r < r1) {
-            const uint32_t c = pcounts[r];
-            s += c;
-            z += c != 0u;
+#pragma unroll
+    for (int k = 0; k < kCountItems; ++k) {
+        const int64_t r = b0 + k * kCountThreads + tid;
+        if (r < nv && r >= (int64_t)r0 && r < (int64_t)r1) {
+            pcounts[r] = c[k];
+            s += c[k];
+            z += c[k] != 0u;
         }
     }
-    red[threadIdx.x] = s;
-    zred[threadIdx.x] = z;
+    for (int off = 32; off > 0; off >>= 1) {
+        s += (uint64_t)__shfl_xor((long long)s, off);
+        z += (uint32_t)__shfl_xor((int)z, off);
+    }
+    if ((tid & 63) == 0) {
+        red[tid >> 6] = s;
+        zred[tid >> 6] = z;
+    }
     __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) {
-            red[threadIdx.x] += red[threadIdx.x + off];
-            zred[threadIdx.x] += zred[threadIdx.x + off];
+    if (tid == 0) {
+        uint64_t ts = 0;
+        uint32_t tz = 0;
+        for (int w = 0; w < kCountThreads / 64; ++w) {
+            ts += red[w];
+            tz += zred[w];
         }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        blocksums[blockIdx.x] = red[0];
-        blocksums[nb + blockIdx.x] = zred[0];
+        blocksums[blockIdx.x] = ts;
+        blocksums[nb + blockIdx.x] = tz;
     }
 }
 
-// Exclusive scans of the block sums and of the block non-zero counts (one workgroup; the number
-// of non-zero counts goes to blocksums[2 nb]), then the phase's base, count and capacity check.
-__global__ __launch_bounds__(1024) void k_count_blocks(uint64_t* blocksums, int nb, SavedHeader* hdr, int phase,
-                                                      int64_t max_pairs) {
-    __shared__ uint64_t sums[1024], zsums[1024];
-    const int tid = threadIdx.x;
-    const int per = (nb + 1023) / 1024;
-    const int b = tid * per, e = min(nb, b + per);
-    uint64_t s = 0, z = 0;
-    for (int i = b; i < e; ++i) {
-        s += blocksums[i];
-        z += blocksums[nb + i];
+// Exclusive scan over a 1024-thread workgroup of one (u64, u32) pair per thread, in place; the
+// totals go to ts, tz.  Wave scans by lane shuffles, then the 16 wave totals through LDS.
+__device__ __forceinline__ void block_scan_1024(uint64_t& s, uint32_t& z, uint64_t* ws, uint32_t* wz, uint64_t& ts,
+                                                uint32_t& tz) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint64_t is = s;
+    uint32_t iz = z;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t ys = (uint64_t)__shfl_up((long long)is, off);
+        const uint32_t yz = (uint32_t)__shfl_up((int)iz, off);
+        if (lane >= off) {
+            is += ys;
+            iz += yz;
+        }
     }
-    sums[tid] = s;
-    zsums[tid] = z;
+    if (lane == 63) {
+        ws[wave] = is;
+        wz[wave] = iz;
+    }
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint64_t v = tid >= off ? sums[tid - off] : 0ull;
-        const uint64_t w = tid >= off ? zsums[tid - off] : 0ull;
-        __syncthreads();
-        sums[tid] += v;
-        zsums[tid] += w;
-        __syncthreads();
+    uint64_t bs = 0;
+    uint32_t bz = 0;
+    ts = 0;
+    tz = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+        const uint64_t a = ws[w];
+        const uint32_t c = wz[w];
+        bs += w < wave ? a : 0ull;
+        bz += w < wave ? c : 0u;
+        ts += a;
+        tz += c;
     }
-    uint64_t run = sums[tid] - s, zrun = zsums[tid] - z;
-    for (int i = b; i < e; ++i) {
-        const uint64_t v = blocksums[i], w = blocksums[nb + i];
-        blocksums[i] = run;
-        blocksums[nb + i] = zrun;
-        run += v;
-        zrun += w;
+    __syncthreads();   // ws and wz are reused by the next scan
+    s = bs + is - s;
+    z = bz + iz - z;
+}
+
+// Exclusive scans of the block sums and of the block non-zero counts (one workgroup; the number
+// of non-zero counts goes to blocksums[2 nb]), then the phase's ranks, base, count and capacity
+// check; zero_bits (nullable) is cleared for the alive masks the phase's compositing sets (the
+// phase's own emission reads the other buffer).  Groups of 8 x 1024 sums are staged in LDS by
+// coalesced loads (all in flight); each thread sums 8 consecutive ones, one workgroup scan per
+// group gives their bases.
+__global__ __launch_bounds__(1024) void k_count_blocks(uint64_t* blocksums, int nb, SavedHeader* hdr, int phase,
+                                                      PhaseSched ps, int64_t max_pairs, uint64_t* zero_bits,
+                                                      int64_t zero_words) {
+    constexpr int kItems = 8;
+    constexpr int kGroup = 1024 * kItems;
+    __shared__ uint64_t lv[kGroup];
+    __shared__ uint32_t lw[kGroup];
+    __shared__ uint64_t ws[16];
+    __shared__ uint32_t wz[16];
+    const int tid = threadIdx.x;
+    if (zero_bits)
+        for (int64_t i = tid; i < zero_words; i += 1024) zero_bits[i] = 0ull;
+    uint64_t carry = 0;
+    uint32_t zcarry = 0;
+    for (int g0 = 0; g0 < nb; g0 += kGroup) {
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const int i = k * 1024 + tid;
+            lv[i] = g0 + i < nb ? blocksums[g0 + i] : 0ull;
+            lw[i] = g0 + i < nb ? (uint32_t)blocksums[nb + g0 + i] : 0u;
+        }
+        __syncthreads();
+        uint64_t s = 0;
+        uint32_t z = 0;
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            s += lv[tid * kItems + j];
+            z += lw[tid * kItems + j];
+        }
+        uint64_t ts;
+        uint32_t tz;
+        block_scan_1024(s, z, ws, wz, ts, tz);
+        uint64_t run = carry + s;
+        uint32_t zrun = zcarry + z;
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const uint64_t x = lv[tid * kItems + j];
+            const uint32_t y = lw[tid * kItems + j];
+            lv[tid * kItems + j] = run;
+            lw[tid * kItems + j] = zrun;
+            run += x;
+            zrun += y;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const int i = k * 1024 + tid;
+            if (g0 + i < nb) {
+                blocksums[g0 + i] = lv[i];
+                blocksums[nb + g0 + i] = lw[i];
+            }
+        }
+        carry += ts;
+        zcarry += tz;
+        __syncthreads();   // lv and lw are refilled by the next group
     }
-    if (tid == 1023) blocksums[2 * nb] = zsums[1023];
+    if (tid == 1023) blocksums[2 * nb] = zcarry;
+    if (tid == 0) {   // kept for inspection: the kernels derive the ranks themselves
+        uint32_t r0, r1;
+        phase_ranks(hdr, ps, phase, r0, r1);
+        hdr->phase_rank[phase] = r0;
+        hdr->phase_rank[phase + 1] = r1;
+    }
     if (tid == 1023 && !hdr->stop) {   // after an overflow the header keeps what the failing phase needed
-        const uint64_t total = sums[1023];
+        const uint64_t total = carry;
         const uint64_t base = hdr->pair_count;
         hdr->phase_base[phase] = (uint32_t)base;
         if (base + total > (uint64_t)max_pairs) {
@@ -243,23 +336,25 @@ __global__ __launch_bounds__(1024) void k_count_blocks(uint64_t* blocksums, int 
 
 __global__ __launch_bounds__(kBlock) void k_count_down(const uint32_t* __restrict__ pcounts, int64_t nv,
                                                       const uint64_t* __restrict__ blocksums,
-                                                      const SavedHeader* __restrict__ hdr, int phase,
+                                                      const SavedHeader* __restrict__ hdr, int phase, PhaseSched ps,
                                                       uint64_t* __restrict__ offsets, uint32_t* __restrict__ emit_start,
                                                       int64_t n_spans, int nb, uint32_t* __restrict__ nzr) {
     __shared__ uint64_t part[kBlock];
     __shared__ uint32_t zpart[kBlock];
     if (phase_empty(hdr, phase)) return;   // every count is 0: no entry reads its offset
     // offsets are read inside the phase's ranks, and by the phase-0 emission up to one span past them
-    const int64_t r0 = hdr->phase_rank[phase], r1 = hdr->phase_rank[phase + 1];
+    uint32_t ur0, ur1;
+    phase_ranks(hdr, ps, phase, ur0, ur1);
+    const int64_t r0 = ur0, r1 = ur1;
     const int64_t cb = (int64_t)blockIdx.x * kScanChunk;
     if (cb + kScanChunk <= r0 || cb >= r1 + kEmitSpan + 1) return;
     const int tid = threadIdx.x;
-    const int64_t b0 = cb + (int64_t)tid * 16;   // 16 consecutive per thread
-    uint32_t c[16];
+    const int64_t b0 = cb + (int64_t)tid * kDownItems;   // consecutive ranks per thread
+    uint32_t c[kDownItems];
     uint64_t s = 0;
     uint32_t z = 0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
+    for (int k = 0; k < kDownItems; ++k) {
         const int64_t r = b0 + k;
         c[k] = r < nv && r >= r0 && r < r1 ? pcounts[r] : 0u;
         s += c[k];
@@ -279,7 +374,7 @@ __global__ __launch_bounds__(kBlock) void k_count_down(const uint32_t* __restric
     uint64_t run = blocksums[blockIdx.x] + part[tid] - s;
     uint32_t zrun = (uint32_t)blocksums[nb + blockIdx.x] + zpart[tid] - z;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
+    for (int k = 0; k < kDownItems; ++k) {
         const int64_t r = b0 + k;
         if (r < nv) {
             offsets[r] = run;
@@ -532,22 +627,6 @@ __global__ __launch_bounds__(kBlock) void k_emit_spans(const uint32_t* __restric
 }
 
 // One wave per global tile row: the bit masks of the columns whose tile is still alive.
-__global__ __launch_bounds__(64) void k_alive_rows(const ViewInfo* __restrict__ vt, int32_t views,
-                                                  const uint32_t* __restrict__ alive,
-                                                  uint64_t* __restrict__ rowbits, uint32_t row_words) {
-    const uint32_t r = blockIdx.x;
-    int v = 0;
-    while (v + 1 < views && r >= vt[v + 1].row_base) ++v;
-    const ViewInfo vi = vt[v];
-    const uint32_t ty = r - vi.row_base;
-    for (uint32_t w = 0; w < row_words; ++w) {   // bit b of word w: column 64 w + b is alive
-        const uint32_t tx = w * 64 + threadIdx.x;
-        const bool a = tx < (uint32_t)vi.tiles_x && alive[vi.tile_base + ty * (uint32_t)vi.tiles_x + tx] != 0u;
-        const uint64_t m = __ballot(a);
-        if (threadIdx.x == 0) rowbits[(size_t)r * row_words + w] = m;
-    }
-}
-
 __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t* p, uint32_t value, int64_t count) {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock)
         p[i] = value;
@@ -588,48 +667,32 @@ __global__ __launch_bounds__(kBlock) void k_export(const uint2* __restrict__ ran
 
 }  // namespace
 
-hipError_t launch_view_table(const ViewTable& t, int phases, ViewInfo* dst, SavedHeader* hdr, hipStream_t s) {
-    (void)phases;
-    hipLaunchKernelGGL(k_view_table, dim3(1), dim3(GS_MAX_VIEWS), 0, s, t, dst, hdr);
-    return hipGetLastError();
-}
-
-hipError_t launch_visible(int phases, int phase0_shift, int growth, SavedHeader* hdr, hipStream_t s) {
-    hipLaunchKernelGGL(k_visible, dim3(1), dim3(1), 0, s, phases, phase0_shift, growth, hdr);
-    return hipGetLastError();
-}
-
-hipError_t launch_phase_count(const uint32_t* order, const uint32_t* counts, const uint2* rects, int64_t nv,
-                              int64_t n, const ViewInfo* vt, const AliveRows& ar,
-                              const SavedHeader* hdr, int phase, uint32_t* pcounts, hipStream_t s) {
-    if (nv == 0) return hipSuccess;
-    const unsigned grid = (unsigned)((nv + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_phase_count, dim3(grid), dim3(kBlock), 0, s, order, counts, rects, nv, n, vt,
-                       ar.bits, ar.words, hdr, phase, pcounts);
-    return hipGetLastError();
-}
-
-hipError_t launch_alive_rows(const ViewInfo* vt, int32_t views, int64_t rows, const uint32_t* alive,
-                             const AliveRows& ar, hipStream_t s) {
-    if (rows == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_alive_rows, dim3((unsigned)rows), dim3(64), 0, s, vt, views, alive, ar.bits,
-                       ar.words);
+hipError_t launch_view_table(const ViewTable& t, ViewInfo* dst, SavedHeader* hdr, uint32_t* fill, int64_t fill_count,
+                             hipStream_t s) {
+    int64_t g = (fill_count + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_view_table, dim3((unsigned)g), dim3(kBlock), 0, s, t, dst, hdr, fill, fill_count);
     return hipGetLastError();
 }
 
 int64_t count_scan_blocks(int64_t nv) { return (nv + kScanChunk - 1) / kScanChunk; }
 
-hipError_t launch_count_scan(const uint32_t* pcounts, int64_t nv, uint64_t* offsets, uint64_t* blocksums,
-                             SavedHeader* hdr, int phase, int64_t max_pairs, uint32_t* emit_start, uint32_t* nzr,
-                             hipStream_t s) {
+hipError_t launch_count_scan(const uint32_t* order, const uint32_t* counts, const uint2* rects, int64_t nv,
+                             int64_t n, const ViewInfo* vt, const AliveRows& ar, uint64_t* zero_bits,
+                             int64_t zero_words, const PhaseSched& ps, SavedHeader* hdr, int phase,
+                             uint32_t* pcounts, uint64_t* offsets, uint64_t* blocksums, int64_t max_pairs,
+                             uint32_t* emit_start, hipStream_t s) {
     const int nb = (int)count_scan_blocks(nv);
     const int64_t n_spans = max_pairs / kEmitSpan + 2;
     if (nb > 0)
-        hipLaunchKernelGGL(k_count_reduce, dim3(nb), dim3(kBlock), 0, s, pcounts, nv, hdr, phase, blocksums, nb);
-    hipLaunchKernelGGL(k_count_blocks, dim3(1), dim3(1024), 0, s, blocksums, nb, hdr, phase, max_pairs);
+        hipLaunchKernelGGL(k_phase_counts, dim3(nb), dim3(kCountThreads), 0, s, order, counts, rects, nv, n, vt, ar.bits,
+                           ar.words, hdr, phase, ps, pcounts, blocksums, nb);
+    hipLaunchKernelGGL(k_count_blocks, dim3(1), dim3(1024), 0, s, blocksums, nb, hdr, phase, ps, max_pairs, zero_bits,
+                       zero_words);
     if (nb > 0)
-        hipLaunchKernelGGL(k_count_down, dim3(nb), dim3(kBlock), 0, s, pcounts, nv, blocksums, hdr, phase, offsets,
-                           emit_start, n_spans, nb, nzr);
+        hipLaunchKernelGGL(k_count_down, dim3(nb), dim3(kBlock), 0, s, pcounts, nv, blocksums, hdr, phase, ps,
+                           offsets, emit_start, n_spans, nb, ar.nzr);
     return hipGetLastError();
 }
 

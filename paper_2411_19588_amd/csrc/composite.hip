@@ -47,6 +47,8 @@ struct FwdArgs {
     const uint32_t* order;    // persistent mode: tile of each queue position (null: index order)
     uint32_t* alive;
     uint32_t* alive_count;
+    uint64_t* rowbits;        // nullable: per global tile row, the bits of the tiles left alive
+    uint32_t row_words;
     float* out_rgb;
     float* out_depth;
     float* out_alpha;
@@ -480,7 +482,15 @@ __global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_fwd
         const bool tile_alive = block_any<NW>(wave_alive, s_flag[2]);
         if (tid == 0) {
             a.alive[tile] = tile_alive ? 1u : 0u;
-            if (tile_alive) atomicAdd(a.alive_count, 1u);
+            if (tile_alive) {
+                atomicAdd(a.alive_count, 1u);
+                if (a.rowbits) {
+                    const uint32_t tx = lt % (uint32_t)vi.tiles_x, ty = lt / (uint32_t)vi.tiles_x;
+                    atomicOr(reinterpret_cast<unsigned long long*>(a.rowbits) +
+                                 (size_t)(vi.row_base + ty) * a.row_words + (tx >> 6),
+                             1ull << (tx & 63));
+                }
+            }
         }
     }
 }
@@ -1026,10 +1036,12 @@ hipError_t launch_composite_fwd(const gs_options& o, const Layout& L, int phase,
                                 const gs_medium* med, const Record* rec, const uint2* ranges, const uint32_t* vals,
                                 SavedHeader* hdr, uint32_t* alive, float* out_rgb, float* out_depth,
                                 float* out_alpha, float* out_restored, float* tfinal, uint32_t* nlast, uint8_t* done,
-                                float* cair, float* dsum, float* wsum, const uint32_t* order, hipStream_t s) {
+                                float* cair, float* dsum, float* wsum, const uint32_t* order, uint64_t* rowbits,
+                                hipStream_t s) {
     if (L.tiles == 0) return hipSuccess;
     FwdArgs a{vt, L.views, (uint32_t)L.tiles, phase, L.phases - 1, med, rec, ranges + (size_t)phase * L.tiles, vals,
-              &hdr->queue[phase], order, alive, &hdr->phase_alive[phase], out_rgb, out_depth, out_alpha,
+              &hdr->queue[phase], order, alive, &hdr->phase_alive[phase], rowbits, (uint32_t)L.row_words, out_rgb,
+              out_depth, out_alpha,
               out_restored, tfinal, nlast, done, cair, dsum, wsum, L.pixels, o.alpha_min, o.alpha_max, o.t_min,
               o.depth_mode, o.depth_output};
     return dispatch_shape<FwdRun>(o, a, o.persistent != 0, false, s);

@@ -97,7 +97,9 @@ __device__ __forceinline__ bool guard_set(const Guard& g) { return g.word != nul
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (each enqueues on `s` and returns hipGetLastError()).
-hipError_t launch_view_table(const ViewTable& t, int phases, ViewInfo* dst, SavedHeader* hdr, hipStream_t s);
+// The view table and a cleared header; fill[0, fill_count) is zeroed by the same launch.
+hipError_t launch_view_table(const ViewTable& t, ViewInfo* dst, SavedHeader* hdr, uint32_t* fill, int64_t fill_count,
+                             hipStream_t s);
 hipError_t launch_project_fwd(const gs_gaussians& g, int32_t views, const gs_camera* cams, const ViewInfo* vt,
                               const gs_options& o, Record* rec, uint32_t* counts, uint2* rects,
                               uint32_t* depth_keys, uint32_t* dkeys_sort, uint32_t* dvals_sort,
@@ -148,10 +150,12 @@ hipError_t launch_adam_sh(int64_t n, int sh_degree, const AdamFused& adam, hipSt
 constexpr int kShViewsW = 2;
 hipError_t launch_sh_views(const gs_gaussians& g, int32_t views, const gs_camera* cams,
                            const gs_gaussian_grads& grads, const AdamFused& adam, int fused, hipStream_t s);
-// Training state (int32[2]: step, sticky skip flag) of a fused step: when *status reports a pair
-// overflow or state[1] is already set, state[1] |= the overflow bit and the step is skipped;
-// otherwise state[0] += 1 and bc = (1 / (1 - b1^step), 1 / (1 - b2^step)) on the device.
-hipError_t launch_adam_prep(int32_t* state, const uint32_t* status, float b1, float b2, float* bc, hipStream_t s);
+// Zeroes p[0, count) and starts a fused step on its training state (int32[2]: step, sticky skip
+// flag): when *status reports a pair overflow or state[1] is already set, state[1] |= the overflow
+// bit and the step is skipped; otherwise state[0] += 1 and bc = (1 / (1 - b1^step),
+// 1 / (1 - b2^step)) on the device.
+hipError_t launch_zero_adam_prep(uint32_t* p, int64_t count, int32_t* state, const uint32_t* status, float b1,
+                                 float b2, float* bc, hipStream_t s);
 // Stable LSD radix sort of (key, value) u32 pairs over bits [bit0, bit0+nbits).  n is read from n_dev
 // (or n_host if n_dev is null).  Returns in *out_in_b whether the result sits in the B buffers.
 // With use_drop, keys equal to drop_key are left out; with n_kept the number of kept pairs is
@@ -160,10 +164,12 @@ hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, 
                           const uint32_t* n_dev, uint32_t n_host, int bit0, int nbits, int parts, uint32_t* hist,
                           int* out_in_b, const char* tag, void* timer, hipStream_t s, int use_drop = 0,
                           uint32_t drop_key = 0, uint32_t* n_kept = nullptr);
-// Phase rank ranges from the number of visible entries the depth sort kept.
-hipError_t launch_visible(int phases, int phase0_shift, int growth, SavedHeader* hdr, hipStream_t s);
-// Per-entry pair counts of phase p (by depth rank): whole rectangles in phase 0, only the tiles
-// still alive in later phases, 0 outside the phase's ranks.
+// Depth-phase schedule.  With V visible entries (the depth sort's count of kept keys), phase
+// p < phases - 1 ends at depth rank ceil(V / 2^(shift - growth p)) (at V once the exponent
+// reaches 0) and the last phase at V; every kernel that needs a phase's ranks derives them from V.
+struct PhaseSched {
+    int32_t phases, shift, growth;
+};
 // Exact tile culling: a (Gaussian, tile) pair of the rectangle is dropped when no pixel centre
 // of the tile can reach alpha >= alpha_min (see tile_may_contribute).
 struct CullArgs {
@@ -174,25 +180,26 @@ struct CullArgs {
 };
 
 // Per global tile row, after a phase: bit masks of the alive columns (`words` 64-bit words per
-// row); and the compact list of a later phase's entries with pairs (depth ranks, in depth order).
+// row), set by that phase's compositing; and the compact list of a later phase's entries with
+// pairs (depth ranks, in depth order).
 struct AliveRows {
     uint64_t* bits;
     uint32_t words;
     uint32_t* nzr;   // [nv]
 };
-hipError_t launch_phase_count(const uint32_t* order, const uint32_t* counts, const uint2* rects, int64_t nv,
-                              int64_t n, const ViewInfo* vt, const AliveRows& ar,
-                              const SavedHeader* hdr, int phase, uint32_t* pcounts, hipStream_t s);
-hipError_t launch_alive_rows(const ViewInfo* vt, int32_t views, int64_t rows, const uint32_t* alive,
-                             const AliveRows& ar, hipStream_t s);
-// Exclusive scan of pcounts into offsets (u64) and the phase's pair count and base in hdr (with the
-// capacity check); for each emission span of 1024 pairs the entry that owns its first pair (its
-// depth rank in phase 0, its position in the compact list `nzr` of entries with pairs later).
-// blocksums holds 2 count_scan_blocks(nv) + 1 values; the last is the length of that list.
+// Per-entry pair counts of phase p (by depth rank) into pcounts -- whole rectangles in phase 0,
+// only the tiles alive in ar.bits in later phases, 0 outside the phase's ranks -- and their
+// exclusive scan into offsets (u64), the phase's pair count and base in hdr (with the capacity
+// check); for each emission span of 1024 pairs the entry that owns its first pair (its depth rank
+// in phase 0, its position in the compact list `nzr` of entries with pairs later).  blocksums
+// holds 2 count_scan_blocks(nv) + 1 values; the last is the length of that list.  zero_bits
+// (nullable, zero_words words) is cleared for the alive masks this phase's compositing sets.
 int64_t count_scan_blocks(int64_t nv);
-hipError_t launch_count_scan(const uint32_t* pcounts, int64_t nv, uint64_t* offsets, uint64_t* blocksums,
-                             SavedHeader* hdr, int phase, int64_t max_pairs, uint32_t* emit_start, uint32_t* nzr,
-                             hipStream_t s);
+hipError_t launch_count_scan(const uint32_t* order, const uint32_t* counts, const uint2* rects, int64_t nv,
+                             int64_t n, const ViewInfo* vt, const AliveRows& ar, uint64_t* zero_bits,
+                             int64_t zero_words, const PhaseSched& ps, SavedHeader* hdr, int phase,
+                             uint32_t* pcounts, uint64_t* offsets, uint64_t* blocksums, int64_t max_pairs,
+                             uint32_t* emit_start, hipStream_t s);
 // Phase 0 writes every pair of each rectangle, later phases the pairs of the alive tiles; a culled
 // pair gets the tile id n_tiles, which the tile sort's first pass leaves out.
 hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uint32_t* emit_start,
@@ -204,11 +211,13 @@ hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uin
 hipError_t launch_commit(const uint32_t* sorted_tiles, const uint32_t* sorted_vals, const SavedHeader* hdr,
                          int phase, int64_t tiles, int64_t max_pairs, uint32_t* vals, uint2* ranges, hipStream_t s);
 // out_restored (nullable): the in-air composite C_air per pixel, CHW per view like out_rgb.
+// rowbits (nullable, zeroed beforehand): the bit of every tile left alive is set there.
 hipError_t launch_composite_fwd(const gs_options& o, const Layout& L, int phase, const ViewInfo* vt,
                                 const gs_medium* med, const Record* rec, const uint2* ranges, const uint32_t* vals,
                                 SavedHeader* hdr, uint32_t* alive, float* out_rgb, float* out_depth,
                                 float* out_alpha, float* out_restored, float* tfinal, uint32_t* nlast, uint8_t* done,
-                                float* cair, float* dsum, float* wsum, const uint32_t* order, hipStream_t s);
+                                float* cair, float* dsum, float* wsum, const uint32_t* order, uint64_t* rowbits,
+                                hipStream_t s);
 // Longest-first order of a persistent pass (opts.persistent = 2) over the phases [p0, p1) of
 // `ranges` ([phases][tiles]): per-tile keys 32 - bit_length(list length), a stable 6-bit radix
 // sort, and in *order the tile ids, longest lists first (inside qbuf, 4 * tiles u32).

@@ -111,8 +111,13 @@ __device__ __forceinline__ bool step_begin(int32_t* state, const uint32_t* statu
 
 __global__ void k_step_prep(int32_t* state, const uint32_t* status) { (void)step_begin(state, status); }
 
-__global__ void k_adam_prep(int32_t* state, const uint32_t* status, float b1, float b2, float* bc) {
-    if (!step_begin(state, status)) return;
+// Zeroes p[0, count) (the 2D gradients the adjoint accumulates into) and, in workgroup 0, starts
+// the device-counted step: bias corrections of the step that runs in bc.
+__global__ __launch_bounds__(kBlock) void k_zero_adam_prep(uint32_t* p, int64_t count, int32_t* state,
+                                                          const uint32_t* status, float b1, float b2, float* bc) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock)
+        p[i] = 0u;
+    if (blockIdx.x != 0 || threadIdx.x != 0 || !step_begin(state, status)) return;
     const int32_t t = state[GS_STATE_STEP];
     bc[0] = 1.0f / (1.0f - powf(b1, (float)t));
     bc[1] = 1.0f / (1.0f - powf(b2, (float)t));
@@ -224,8 +229,12 @@ unsigned grid_for(int64_t n) {
 
 }  // namespace
 
-hipError_t launch_adam_prep(int32_t* state, const uint32_t* status, float b1, float b2, float* bc, hipStream_t s) {
-    hipLaunchKernelGGL(k_adam_prep, dim3(1), dim3(1), 0, s, state, status, b1, b2, bc);
+hipError_t launch_zero_adam_prep(uint32_t* p, int64_t count, int32_t* state, const uint32_t* status, float b1,
+                                 float b2, float* bc, hipStream_t s) {
+    int64_t g = (count + kBlock - 1) / kBlock;
+    if (g < 1) g = 1;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_zero_adam_prep, dim3((unsigned)g), dim3(kBlock), 0, s, p, count, state, status, b1, b2, bc);
     return hipGetLastError();
 }
 
