@@ -146,7 +146,7 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     L->w_pcounts = w.take(nv * 4);
     L->w_offsets = w.take((nv + 1) * 8);
     L->w_blocksums = w.take((2 * nb + 1) * 8);   // chunk sums, chunk non-zero counts, list length
-    L->w_emit_start = w.take(((size_t)o->max_pairs / 1024 + 2) * 4);   // first entry of each emission span
+    L->w_emit_start = w.take(((size_t)o->max_pairs / kEmitSpan0 + 2) * 4);   // first entry of each emission span
     L->w_tiles_a = w.take(K * 4);
     L->w_vals_a = w.take(K * 4);
     L->w_tiles_b = w.take(K * 4);

@@ -29,8 +29,6 @@ namespace {
 
 constexpr int kScanChunk = 1024;                  // depth ranks per block of the count scan
 constexpr int kDownItems = kScanChunk / kBlock;   // consecutive ranks per thread of the down-sweep
-constexpr int kEmitItems = 4;
-constexpr int kEmitSpan = kBlock * kEmitItems;
 
 // Whether the splat `r` may reach alpha >= alpha_min at a pixel centre of tile (tx, ty): false
 // only when the maximum of the (concave) exponent A dx^2 + B dx dy + C dy^2 over the
@@ -347,9 +345,10 @@ __global__ __launch_bounds__(kBlock) void k_count_down(const uint32_t* __restric
     phase_ranks(hdr, ps, phase, ur0, ur1);
     const int64_t r0 = ur0, r1 = ur1;
     const int64_t cb = (int64_t)blockIdx.x * kScanChunk;
-    if (cb + kScanChunk <= r0 || cb >= r1 + kEmitSpan + 1) return;
+    if (cb + kScanChunk <= r0 || cb >= r1 + kEmitSpanLater + 1) return;
     const int tid = threadIdx.x;
     const int64_t b0 = cb + (int64_t)tid * kDownItems;   // consecutive ranks per thread
+    const int64_t span = phase == 0 ? kEmitSpan0 : kEmitSpanLater;   // pairs per emission workgroup
     uint32_t c[kDownItems];
     uint64_t s = 0;
     uint32_t z = 0;
@@ -383,8 +382,8 @@ __global__ __launch_bounds__(kBlock) void k_count_down(const uint32_t* __restric
                 if (phase > 0) nzr[zrun] = (uint32_t)r;
                 // emission spans whose first pair falls inside this entry's pairs [run, run + c):
                 // their first entry (a depth rank in phase 0, a position in the compact list later)
-                for (int64_t b = (int64_t)((run + kEmitSpan - 1) / kEmitSpan);
-                     b * kEmitSpan < (int64_t)(run + c[k]) && b < n_spans; ++b)
+                for (int64_t b = (int64_t)((run + span - 1) / span); b * span < (int64_t)(run + c[k]) && b < n_spans;
+                     ++b)
                     emit_start[b] = phase == 0 ? (uint32_t)r : zrun;
                 ++zrun;
             }
@@ -394,7 +393,7 @@ __global__ __launch_bounds__(kBlock) void k_count_down(const uint32_t* __restric
 }
 
 // Phase-0 pair emission (every tile of each rectangle).  Workgroup b writes output pairs
-// [b*kEmitSpan, (b+1)*kEmitSpan): it stages the entries (in depth order) whose tile lists
+// [b*kEmitSpan0, (b+1)*kEmitSpan0): it stages the entries (in depth order) whose tile lists
 // overlap that span in LDS -- the first one is emit_start[b] -- and each thread produces
 // consecutive output slots, so writes are coalesced and every workgroup does the same amount
 // of work whatever the rectangle sizes.  Entries of phase 0 all have a non-empty rectangle,
@@ -408,22 +407,22 @@ __global__ __launch_bounds__(kBlock) void k_emit_rects(const uint32_t* __restric
                                                       CullArgs cull, uint32_t n_tiles,
                                                       uint32_t* __restrict__ tiles_out,
                                                       uint32_t* __restrict__ vals_out) {
-    __shared__ int32_t s_off[kEmitSpan + 1];
-    __shared__ uint32_t s_e[kEmitSpan + 1], s_base[kEmitSpan + 1], s_w[kEmitSpan + 1], s_tx[kEmitSpan + 1];
-    __shared__ uint32_t s_xy[kEmitSpan + 1];
-    __shared__ float s_iw[kEmitSpan + 1];
-    __shared__ uint16_t s_view[kEmitSpan + 1];    // culling: view of each entry of the span
+    __shared__ int32_t s_off[kEmitSpan0 + 1];
+    __shared__ uint32_t s_e[kEmitSpan0 + 1], s_base[kEmitSpan0 + 1], s_w[kEmitSpan0 + 1], s_tx[kEmitSpan0 + 1];
+    __shared__ uint32_t s_xy[kEmitSpan0 + 1];
+    __shared__ float s_iw[kEmitSpan0 + 1];
+    __shared__ uint16_t s_view[kEmitSpan0 + 1];    // culling: view of each entry of the span
     const uint64_t K = hdr->phase_count[phase];
-    const uint64_t p0 = (uint64_t)blockIdx.x * kEmitSpan;
+    const uint64_t p0 = (uint64_t)blockIdx.x * kEmitSpan0;
     if (K == 0 || p0 >= K) return;
-    const uint64_t p1 = min(p0 + (uint64_t)kEmitSpan, K);
+    const uint64_t p1 = min(p0 + (uint64_t)kEmitSpan0, K);
     const int tid = threadIdx.x;
     const int64_t r0 = emit_start[blockIdx.x];
     int nent = 0;
-    for (int i0 = 0; i0 < kEmitSpan + 1; i0 += kBlock) {
+    for (int i0 = 0; i0 < kEmitSpan0 + 1; i0 += kBlock) {
         const int i = i0 + tid;
         const int64_t r = r0 + i;
-        const bool own = i < kEmitSpan + 1 && r < nv && (i == 0 || offsets[r] < p1);
+        const bool own = i < kEmitSpan0 + 1 && r < nv && (i == 0 || offsets[r] < p1);
         if (own) {
             const uint32_t e = order[r];
             const uint2 rc = rects[e];
@@ -443,7 +442,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_rects(const uint32_t* __restric
     }
     const int span = (int)(p1 - p0);
 #pragma unroll
-    for (int k = 0; k < kEmitItems; ++k) {
+    for (int k = 0; k < (kEmitSpan0 / kBlock); ++k) {
         const int q = k * kBlock + tid;
         if (q >= span) break;
         int lo = 0, hi = nent;   // last i with s_off[i] <= q
@@ -506,8 +505,8 @@ __device__ __forceinline__ uint32_t kth_alive(const uint64_t* __restrict__ bits,
 }
 
 // Later-phase pair emission (the alive tiles of each rectangle, rows then columns), balanced
-// over output pairs like the phase-0 emission: workgroup b writes pairs [b*kEmitSpan,
-// (b+1)*kEmitSpan).  It stages the entries with pairs in that span (from the compact list of the
+// over output pairs like the phase-0 emission: workgroup b writes pairs [b*kEmitSpanLater,
+// (b+1)*kEmitSpanLater).  It stages the entries with pairs in that span (from the compact list of the
 // entries with a non-zero count, starting at emit_start[b]), splits them into rows with alive
 // tiles -- one item per row, stored at its first pair in the span -- and gives each pair its row
 // by a running maximum over the item positions and its column as the k-th alive one of the row.
@@ -523,28 +522,28 @@ __global__ __launch_bounds__(kBlock) void k_emit_spans(const uint32_t* __restric
                                                       CullArgs cull, uint32_t n_tiles,
                                                       uint32_t* __restrict__ tiles_out,
                                                       uint32_t* __restrict__ vals_out) {
-    __shared__ int32_t s_off[kEmitSpan + 1];   // entry: first pair, relative to the span
-    __shared__ uint32_t s_e[kEmitSpan + 1];    // entry: (view, Gaussian) index
-    __shared__ int32_t s_cover[kEmitSpan];     // item position at its first pair, -1 elsewhere; then the running max
-    __shared__ int32_t s_ist[kEmitSpan];       // item: first pair, relative to the span (< 0 for a row begun before)
-    __shared__ uint32_t s_ilohi[kEmitSpan];    // item: column range lo | hi << 16
-    __shared__ uint32_t s_ijy[kEmitSpan];      // item: entry slot | tile row << 16
+    __shared__ int32_t s_off[kEmitSpanLater + 1];   // entry: first pair, relative to the span
+    __shared__ uint32_t s_e[kEmitSpanLater + 1];    // entry: (view, Gaussian) index
+    __shared__ int32_t s_cover[kEmitSpanLater];     // item position at its first pair, -1 elsewhere; then the running max
+    __shared__ int32_t s_ist[kEmitSpanLater];       // item: first pair, relative to the span (< 0 for a row begun before)
+    __shared__ uint32_t s_ilohi[kEmitSpanLater];    // item: column range lo | hi << 16
+    __shared__ uint32_t s_ijy[kEmitSpanLater];      // item: entry slot | tile row << 16
     __shared__ int32_t s_wmax[kBlock / 64];
     const uint64_t K = hdr->phase_count[phase];
-    const uint64_t p0 = (uint64_t)blockIdx.x * kEmitSpan;
+    const uint64_t p0 = (uint64_t)blockIdx.x * kEmitSpanLater;
     if (K == 0 || p0 >= K) return;
-    const int span = (int)min((uint64_t)kEmitSpan, K - p0);
+    const int span = (int)min((uint64_t)kEmitSpanLater, K - p0);
     const uint64_t p1 = p0 + (uint64_t)span;
     const int tid = threadIdx.x, lane = tid & 63;
     const uint64_t i0 = emit_start[blockIdx.x], nz = *nz_total;
     // entries: every one after the first starts inside the span, and each has a pair, so at most
-    // kEmitSpan + 1 of them
+    // kEmitSpanLater + 1 of them
     int nent = 0;
-    for (int j0 = 0; j0 < kEmitSpan + 1; j0 += kBlock) {
+    for (int j0 = 0; j0 < kEmitSpanLater + 1; j0 += kBlock) {
         const int j = j0 + tid;
         const uint64_t idx = i0 + (uint64_t)j;
         bool own = false;
-        if (j < kEmitSpan + 1 && idx < nz) {
+        if (j < kEmitSpanLater + 1 && idx < nz) {
             const uint32_t r = nzr[idx];
             const uint64_t off = offsets[r];
             own = j == 0 || off < p1;
@@ -555,7 +554,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_spans(const uint32_t* __restric
         }
         nent += __syncthreads_count(own);
     }
-    for (int q = tid; q < kEmitSpan; q += kBlock) s_cover[q] = -1;
+    for (int q = tid; q < kEmitSpanLater; q += kBlock) s_cover[q] = -1;
     __syncthreads();
     // items: the rows with alive tiles of each entry that reach into the span
     for (int j = tid; j < nent; j += kBlock) {
@@ -580,6 +579,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_spans(const uint32_t* __restric
     }
     __syncthreads();
     // running maximum over the span: each pair's item is the last one that starts at or before it
+    constexpr int kEmitItems = kEmitSpanLater / kBlock;
     int v[kEmitItems];
     int m = -1;
 #pragma unroll
@@ -684,7 +684,7 @@ hipError_t launch_count_scan(const uint32_t* order, const uint32_t* counts, cons
                              uint32_t* pcounts, uint64_t* offsets, uint64_t* blocksums, int64_t max_pairs,
                              uint32_t* emit_start, hipStream_t s) {
     const int nb = (int)count_scan_blocks(nv);
-    const int64_t n_spans = max_pairs / kEmitSpan + 2;
+    const int64_t n_spans = max_pairs / kEmitSpan0 + 2;
     if (nb > 0)
         hipLaunchKernelGGL(k_phase_counts, dim3(nb), dim3(kCountThreads), 0, s, order, counts, rects, nv, n, vt, ar.bits,
                            ar.words, hdr, phase, ps, pcounts, blocksums, nb);
@@ -702,7 +702,8 @@ hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uin
                        const CullArgs& cull, uint32_t n_tiles, uint32_t* tiles_out, uint32_t* vals_out,
                        hipStream_t s) {
     if (nv == 0 || max_pairs == 0) return hipSuccess;
-    const unsigned grid = (unsigned)((max_pairs + kEmitSpan - 1) / kEmitSpan);
+    const int64_t span = phase == 0 ? kEmitSpan0 : kEmitSpanLater;
+    const unsigned grid = (unsigned)((max_pairs + span - 1) / span);
     if (phase == 0) {
         hipLaunchKernelGGL(k_emit_rects, dim3(grid), dim3(kBlock), 0, s, order, offsets, emit_start, rects, nv, n, vt,
                            hdr, phase, cull, n_tiles, tiles_out, vals_out);

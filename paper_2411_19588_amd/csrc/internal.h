@@ -16,6 +16,10 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kMaxRadixBits = 9;          // widest digit (a pass of a 17- or 18-bit key)
 constexpr int kMaxRadix = 1 << kMaxRadixBits;
 constexpr int kMaxSortParts = 1024;      // 2048 and 4096 measured no faster on 24M keys
+// Pairs per emission workgroup: phase 0 (whole rectangles) 512, later phases 1024 (each measured
+// fastest).
+constexpr int kEmitSpan0 = kBlock * 2;
+constexpr int kEmitSpanLater = kBlock * 4;
 constexpr int kGrad2D = 10;              // per-(Gaussian, view) 2D gradient: m(2), conic'(3), o, rgb(3), depth
 // Automatic depth-phase schedule (options phases / phase0_shift = 0), chosen by measurement: one
 // view, 2 phases from the nearest 1/128 of the visible Gaussians; several views, 4 phases from
