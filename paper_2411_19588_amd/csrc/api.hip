@@ -152,8 +152,9 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     L->w_tiles_b = w.take(K * 4);
     L->w_vals_b = w.take(K * 4);
     L->w_hist = w.take(((size_t)kMaxRadix * parts + kMaxRadix) * 4);   // + per-digit row totals
-    L->w_grad2d = w.take(nv * kGrad2D * 4);
+    L->w_grad2d = w.take(nv * kGrad2D * 4 + GS_MAX_VIEWS * 4);   // + the medium reduction's per-view counters
     L->w_medpart = w.take(T * 9 * 4 + 256);   // + persistent-mode tile counter of the backward
+    L->w_medsum = w.take((size_t)n_views * kMedSlices * 9 * 4);   // per-view slice sums of the medium partials
     L->w_adam = w.take(16);                    // bias corrections of a fused Adam step
     L->w_rowbits = w.take(2 * (size_t)rows * L->row_words * 8);   // alive columns per tile row, two buffers
     L->w_nzr = w.take(nv * 4);                 // later phases: the entries with pairs, in depth order
@@ -397,12 +398,13 @@ int gs_render_backward(const gs_options* opts, const gs_gaussians* g, int32_t n_
     const SavedHeader* hdr = at<SavedHeader>(saved, L.s_header);
     const ViewInfo* vt = reinterpret_cast<const ViewInfo*>(hdr + 1);
     float* grad2d = at<float>(workspace, L.w_grad2d);
+    uint32_t* med_done = reinterpret_cast<uint32_t*>(grad2d) + L.nv * kGrad2D;   // zeroed with grad2d
     float* medpart = at<float>(workspace, L.w_medpart);
     // a truncated forward (pair overflow) gives no gradient: the 2D gradients stay zero
     const Guard guard{&hdr->status, GS_STATUS_PAIR_OVERFLOW};
 
     timer_begin(T, "zero_grad2d", s);
-    GS_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, L.nv * kGrad2D, s));
+    GS_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, L.nv * kGrad2D + GS_MAX_VIEWS, s));
     timer_end(T, s);
     const uint32_t* order = nullptr;
     if (o.persistent == 2)
@@ -416,8 +418,9 @@ int gs_render_backward(const gs_options* opts, const gs_gaussians* g, int32_t n_
                                 grad2d, medpart, guard, order, s));
     timer_end(T, s);
     timer_begin(T, "medium_reduce", s);
-    GS_TRY(launch_medium_reduce(vt, n_views, medpart, grad_medium, reinterpret_cast<const float*>(dev_medium), o,
-                                nullptr, 0.f, 0.f, 0.f, nullptr, guard, s));
+    GS_TRY(launch_medium_reduce(vt, n_views, medpart, at<float>(workspace, L.w_medsum), med_done, grad_medium,
+                                reinterpret_cast<const float*>(dev_medium), o, nullptr, 0.f, 0.f, 0.f, nullptr, guard,
+                                s));
     timer_end(T, s);
     timer_begin(T, "project_bwd", s);
     float* planes = at<float>(workspace, L.w_shf);
@@ -470,6 +473,7 @@ int gs_render_backward_adam(const gs_options* opts, const gs_gaussians* g, int32
     const SavedHeader* hdr = at<SavedHeader>(saved, L.s_header);
     const ViewInfo* vt = reinterpret_cast<const ViewInfo*>(hdr + 1);
     float* grad2d = at<float>(workspace, L.w_grad2d);
+    uint32_t* med_done = reinterpret_cast<uint32_t*>(grad2d) + L.nv * kGrad2D;   // zeroed with grad2d
     float* medpart = at<float>(workspace, L.w_medpart);
     float* bc = at<float>(workspace, L.w_adam);
     // the step is skipped when this forward overflowed or the caller's sticky flag is set: the
@@ -477,8 +481,8 @@ int gs_render_backward_adam(const gs_options* opts, const gs_gaussians* g, int32
     const Guard guard{reinterpret_cast<const uint32_t*>(state + GS_STATE_SKIP), 0xFFFFFFFFu};
 
     timer_begin(T, "zero_grad2d", s);
-    GS_TRY(launch_zero_adam_prep(reinterpret_cast<uint32_t*>(grad2d), L.nv * kGrad2D, state, &hdr->status, beta1,
-                                 beta2, bc, s));
+    GS_TRY(launch_zero_adam_prep(reinterpret_cast<uint32_t*>(grad2d), L.nv * kGrad2D + GS_MAX_VIEWS, state,
+                                 &hdr->status, beta1, beta2, bc, s));
     timer_end(T, s);
     const uint32_t* order = nullptr;
     if (o.persistent == 2)
@@ -492,8 +496,9 @@ int gs_render_backward_adam(const gs_options* opts, const gs_gaussians* g, int32
                                 grad2d, medpart, guard, order, s));
     timer_end(T, s);
     timer_begin(T, "medium_reduce", s);
-    GS_TRY(launch_medium_reduce(vt, n_views, medpart, const_cast<float*>(groups[5].grad), groups[5].param, o,
-                                &groups[5], beta1, beta2, eps, bc, guard, s));
+    GS_TRY(launch_medium_reduce(vt, n_views, medpart, at<float>(workspace, L.w_medsum), med_done,
+                                const_cast<float*>(groups[5].grad), groups[5].param, o, &groups[5], beta1, beta2, eps,
+                                bc, guard, s));
     timer_end(T, s);
     AdamFused ad;
     memset(&ad, 0, sizeof(ad));

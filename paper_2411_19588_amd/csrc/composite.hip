@@ -904,19 +904,26 @@ struct MediumAdam {
 
 constexpr int kMedThreads = 9 * 64;   // thread t always reads component t % 9 of the [tiles][9] partials
 
+// kMedSlices workgroups per view; deterministic: each reduces a fixed slice of the view's tiles with
+// fixed per-thread strides and a fixed tree, and the last slice to finish (a per-view counter,
+// zeroed with the 2D gradients at the start of the backward) adds the kMedSlices slice sums in
+// slice order and takes the step.
 __global__ __launch_bounds__(kMedThreads) void k_medium_reduce(const ViewInfo* __restrict__ vt,
                                                               const float* __restrict__ medpart,
+                                                              float* __restrict__ medsum, uint32_t* __restrict__ done,
                                                               float* __restrict__ grad_medium, MediumAdam ad) {
-    // one workgroup per view; deterministic: fixed per-thread strides and a fixed tree
     __shared__ float red[kMedThreads];
-    const int v = blockIdx.x, tid = threadIdx.x;
+    __shared__ uint32_t s_last;
+    const int v = blockIdx.x / kMedSlices, slice = blockIdx.x % kMedSlices, tid = threadIdx.x;
     const ViewInfo vi = vt[v];
     if (guard_set(ad.guard)) {   // truncated forward: no gradient and no step
-        if (tid < 9) grad_medium[v * 9 + tid] = 0.0f;
+        if (slice == 0 && tid < 9) grad_medium[v * 9 + tid] = 0.0f;
         return;
     }
-    const float* p = medpart + (int64_t)vi.tile_base * 9;
-    const int64_t total = (int64_t)vi.n_tiles * 9;
+    const uint32_t per = (vi.n_tiles + kMedSlices - 1) / kMedSlices;
+    const uint32_t t0 = min(vi.n_tiles, per * (uint32_t)slice), t1 = min(vi.n_tiles, t0 + per);
+    const float* p = medpart + ((int64_t)vi.tile_base + t0) * 9;
+    const int64_t total = (int64_t)(t1 - t0) * 9;
     float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     int64_t i = tid;
     for (; i + 7 * kMedThreads < total; i += 8 * kMedThreads)   // eight coalesced loads in flight
@@ -930,8 +937,18 @@ __global__ __launch_bounds__(kMedThreads) void k_medium_reduce(const ViewInfo* _
         if (tid < 9 * off) red[tid] += red[tid + 9 * off];
         __syncthreads();
     }
+    float* ms = medsum + (int64_t)v * kMedSlices * 9;
+    if (tid < 9) __hip_atomic_store(ms + slice * 9 + tid, red[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();   // the slice sum is visible before the counter moves
+    __syncthreads();
+    if (tid == 0) s_last = atomicAdd(done + v, 1u) == (uint32_t)(kMedSlices - 1) ? 1u : 0u;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
     if (tid < 9) {
-        float gm = red[tid];
+        float gm = 0.0f;
+        for (int k = 0; k < kMedSlices; ++k)
+            gm += __hip_atomic_load(ms + k * 9 + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (ad.prior && tid >= 3) {   // L_best: lambda sign(B - B_hat) on B_b (slots 3-5) and B_inf (6-8)
             const float d = ad.medium[v * 9 + tid] - ad.prior[v * 6 + (tid < 6 ? tid : tid - 6)];
             gm += d > 0.0f ? ad.prior_lambda : (d < 0.0f ? -ad.prior_lambda : 0.0f);
@@ -1067,9 +1084,10 @@ hipError_t launch_composite_bwd(const gs_options& o, const Layout& L, const View
     return dispatch_shape<BwdRun>(o, a, pers, true, s);
 }
 
-hipError_t launch_medium_reduce(const ViewInfo* vt, int32_t views, const float* medpart, float* grad_medium,
-                                const float* medium, const gs_options& o, const gs_adam_group* adam, float b1,
-                                float b2, float eps, const float* bc, const Guard& guard, hipStream_t s) {
+hipError_t launch_medium_reduce(const ViewInfo* vt, int32_t views, const float* medpart, float* medsum,
+                                uint32_t* done, float* grad_medium, const float* medium, const gs_options& o,
+                                const gs_adam_group* adam, float b1, float b2, float eps, const float* bc,
+                                const Guard& guard, hipStream_t s) {
     MediumAdam ad;
     memset(&ad, 0, sizeof(ad));
     ad.guard = guard;
@@ -1084,7 +1102,8 @@ hipError_t launch_medium_reduce(const ViewInfo* vt, int32_t views, const float* 
         ad.bc = bc;
         ad.enabled = 1;
     }
-    hipLaunchKernelGGL(k_medium_reduce, dim3(views), dim3(kMedThreads), 0, s, vt, medpart, grad_medium, ad);
+    hipLaunchKernelGGL(k_medium_reduce, dim3(views * kMedSlices), dim3(kMedThreads), 0, s, vt, medpart, medsum, done,
+                       grad_medium, ad);
     return hipGetLastError();
 }
 

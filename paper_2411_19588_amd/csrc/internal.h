@@ -83,7 +83,8 @@ struct Layout {
     size_t s_tfinal, s_nlast, s_done, s_cair, s_dsum, s_wsum, saved_bytes;
     // workspace offsets (bytes)
     size_t w_counts, w_rects, w_dkeys, w_dvals, w_dkeys2, w_dvals2, w_pcounts, w_offsets, w_blocksums, w_emit_start;
-    size_t w_tiles_a, w_vals_a, w_tiles_b, w_vals_b, w_hist, w_grad2d, w_medpart, w_adam, w_rowbits, w_nzr, w_shf, w_queue;
+    size_t w_tiles_a, w_vals_a, w_tiles_b, w_vals_b, w_hist, w_grad2d, w_medpart, w_medsum, w_adam, w_rowbits, w_nzr,
+        w_shf, w_queue;
     size_t workspace_bytes;
 };
 
@@ -239,9 +240,12 @@ hipError_t launch_composite_bwd(const gs_options& o, const Layout& L, const View
 // When the guard is set, grad_medium is zeroed and no step is taken.
 // medium: [views][9] values of the medium; with o.medium_prior set the reduction adds
 // o.prior_lambda sign(B - B_hat) to the B_inf and B_b gradients before the step.
-hipError_t launch_medium_reduce(const ViewInfo* vt, int32_t views, const float* medpart, float* grad_medium,
-                                const float* medium, const gs_options& o, const gs_adam_group* adam, float b1,
-                                float b2, float eps, const float* bc, const Guard& guard, hipStream_t s);
+// medsum: [views][kMedSlices][9] floats of workspace; done: [views] counters, zero at the start.
+constexpr int kMedSlices = 16;
+hipError_t launch_medium_reduce(const ViewInfo* vt, int32_t views, const float* medpart, float* medsum,
+                                uint32_t* done, float* grad_medium, const float* medium, const gs_options& o,
+                                const gs_adam_group* adam, float b1, float b2, float eps, const float* bc,
+                                const Guard& guard, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 hipError_t launch_export_keys(const Layout& L, const uint2* ranges, const uint32_t* vals, const uint32_t* depth_keys,
                               int64_t capacity, uint64_t* keys, uint32_t* values, hipStream_t s);
