@@ -13,7 +13,7 @@
 // never reads past that point, so the images are identical, while scenes whose
 // near Gaussians saturate the tiles skip sorting almost every pair.  Every
 // emission is balanced over output pairs: a workgroup writes a fixed span of
-// 1024 pairs, whatever the sizes of the rectangles behind them.
+// pairs (512 in phase 0, 1024 later), whatever the sizes of the rectangles behind them.
 //
 // Exact tile culling (optional).  The rectangle bounds the ellipse q <= kappa,
 // but a Gaussian of opacity o only blends where o exp(-q/2) >= alpha_min, and the
