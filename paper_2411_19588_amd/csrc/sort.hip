@@ -40,15 +40,21 @@ __device__ __forceinline__ void part_range(uint32_t n, int parts, int p, uint32_
     t1 = min(tiles, t0 + per);
 }
 
-// Mask of the lanes (among `active`) whose digit equals this lane's digit.
-__device__ __forceinline__ uint64_t match_digit(uint32_t digit, int nbits, uint64_t active) {
-    uint64_t m = active;
-    for (int b = 0; b < nbits; ++b) {
-        const bool bit = (digit >> b) & 1u;
-        const uint64_t bal = __ballot(bit);
-        m &= bit ? bal : ~bal;
+// Mask of the lanes (among `active`) whose digit equals this lane's digit: per digit bit b, the
+// ballot B of the lanes with that bit set; a lane keeps B where its bit is set and ~B where it is
+// clear, i.e. m &= ~(B ^ s) with s the lane's bit sign-extended (one three-input op per half).
+template <int NBITS>
+__device__ __forceinline__ uint64_t match_digit(uint32_t digit, uint64_t active) {
+    uint32_t lo = (uint32_t)active, hi = (uint32_t)(active >> 32);
+#pragma unroll
+    for (int b = 0; b < NBITS; ++b) {
+        const int32_t si = (int32_t)(digit << (31 - b)) >> 31;   // the bit, sign-extended
+        const uint64_t bal = __ballot(si < 0);
+        const uint32_t s = (uint32_t)si;
+        lo &= ~((uint32_t)bal ^ s);
+        hi &= ~((uint32_t)(bal >> 32) ^ s);
     }
-    return m;
+    return ((uint64_t)hi << 32) | lo;
 }
 
 template <int D>
@@ -151,13 +157,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_rows(uint32_t* __restrict__ his
     if (tid == 0) totals[blockIdx.x] = total;
 }
 
-template <int D>
+template <int NBITS>
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                   const uint32_t* n_dev, uint32_t n_host, int shift, int nbits,
+                                                   const uint32_t* n_dev, uint32_t n_host, int shift,
                                                    int parts, const uint32_t* __restrict__ hist,
                                                    const uint32_t* __restrict__ totals, int use_drop,
                                                    uint32_t drop, uint32_t* __restrict__ n_kept) {
+    constexpr int D = NBITS > kRadixBits ? kMaxRadix : kRadix;
     constexpr int DPT = D / kBlock;   // digits per thread in the block scans: thread t owns t*DPT + j
     static_assert(DPT * kBlock == D && (DPT == 1 || DPT == 2), "256 or 512 digits");
     __shared__ uint32_t run[D];       // global write base of each digit for the next tile
@@ -166,14 +173,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
     __shared__ uint32_t scan_tmp[kBlock / 64];
     __shared__ uint32_t sk[kSortTile], sv[kSortTile];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const uint32_t mask = (1u << nbits) - 1u;
+    const uint32_t mask = (1u << NBITS) - 1u;
     const uint32_t n = load_n(n_dev, n_host);
     if (n == 0) {
         if (n_kept && blockIdx.x == 0 && tid == 0) *n_kept = 0;
         return;
     }
     {
-        // only the pass's 2^nbits digit rows were scanned
+        // only the pass's 2^NBITS digit rows were scanned
         uint32_t tv[DPT], sum = 0;
 #pragma unroll
         for (int j = 0; j < DPT; ++j) {
@@ -217,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
             const uint32_t idx = wbase + k * 64 + lane;
             const bool valid = idx < n && !(use_drop && key[k] == drop);
             const uint32_t digit = (key[k] >> shift) & mask;
-            const uint64_t match = match_digit(digit, nbits, __ballot(valid));
+            const uint64_t match = match_digit<NBITS>(digit, __ballot(valid));
             const uint32_t before = wcnt[wave][digit];
             rank[k] = before + __popcll(match & lt_mask);
             if (valid && lane == __ffsll((unsigned long long)match) - 1)
@@ -326,13 +333,18 @@ hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, 
         hipLaunchKernelGGL(k_scan_rows, dim3(1u << bits), dim3(kBlock), 0, s, hist, parts, totals, n_in, n_host);
         timer_end(timer, s);
         timer_begin(timer, tc.c_str(), s);
-        if (wide)
-            hipLaunchKernelGGL(k_scatter<kMaxRadix>, dim3(parts), dim3(kBlock), 0, s, kin, vin, kout, vout, n_in,
-                               n_host, shift, bits, parts, hist, totals, drop_now, drop_key,
-                               first ? n_kept : nullptr);
-        else
-            hipLaunchKernelGGL(k_scatter<kRadix>, dim3(parts), dim3(kBlock), 0, s, kin, vin, kout, vout, n_in, n_host,
-                               shift, bits, parts, hist, totals, drop_now, drop_key, first ? n_kept : nullptr);
+        uint32_t* kept = first ? n_kept : nullptr;
+        switch (bits) {   // the digit width is a template argument: the ranking unrolls per bit
+#define GS_SCATTER(B)                                                                                             \
+    case B:                                                                                                       \
+        hipLaunchKernelGGL(k_scatter<B>, dim3(parts), dim3(kBlock), 0, s, kin, vin, kout, vout, n_in, n_host, shift, \
+                           parts, hist, totals, drop_now, drop_key, kept);                                        \
+        break;
+            GS_SCATTER(1) GS_SCATTER(2) GS_SCATTER(3) GS_SCATTER(4) GS_SCATTER(5) GS_SCATTER(6) GS_SCATTER(7)
+            GS_SCATTER(8) GS_SCATTER(9)
+#undef GS_SCATTER
+            default: return hipErrorInvalidValue;
+        }
         timer_end(timer, s);
         in_b = !in_b;
         done += bits;
