@@ -358,7 +358,8 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
         // stable sort of the phase's pairs by tile id
         int tb = 0;
         if (L.max_pairs > 0)
-            GS_TRY(radix_sort_u32(tiles_a, vals_a, tiles_b, vals_b, &hdr->phase_count[ph], 0, 0, L.tile_bits,
+            GS_TRY(radix_sort_u32(tiles_a, vals_a, tiles_b, vals_b, &hdr->phase_count[ph], (uint32_t)L.max_pairs, 0,
+                                  L.tile_bits,
                                   L.pair_parts, hist, &tb, "tile_sort", T, s, 1, (uint32_t)L.tiles,
                                   &hdr->phase_live[ph]));
         timer_begin(T, "commit", s);

@@ -9,7 +9,8 @@
 namespace gs {
 
 constexpr int kBlock = 256;              // threads per workgroup for 1D kernels (4 wave64)
-constexpr int kSortItems = 8;            // keys per thread per radix tile (16 or 32 measured slower)
+constexpr int kSortItems = 8;            // keys per thread per radix tile below kLargeSortKeys keys
+constexpr int64_t kLargeSortKeys = 1 << 23;   // from here on, radix tiles of 16 keys per thread
 constexpr int kSortTile = kBlock * kSortItems;
 constexpr int kRadixBits = 8;             // digit width of most radix passes
 constexpr int kRadix = 1 << kRadixBits;
@@ -162,7 +163,8 @@ hipError_t launch_sh_views(const gs_gaussians& g, int32_t views, const gs_camera
 hipError_t launch_zero_adam_prep(uint32_t* p, int64_t count, int32_t* state, const uint32_t* status, float b1,
                                  float b2, float* bc, hipStream_t s);
 // Stable LSD radix sort of (key, value) u32 pairs over bits [bit0, bit0+nbits).  n is read from n_dev
-// (or n_host if n_dev is null).  Returns in *out_in_b whether the result sits in the B buffers.
+// (or n_host if n_dev is null); with n_dev, n_host is the largest n it can hold, which picks the
+// radix tile size.  Returns in *out_in_b whether the result sits in the B buffers.
 // With use_drop, keys equal to drop_key are left out; with n_kept the number of kept pairs is
 // written there (device), and the sorted output holds exactly those.
 hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b,

@@ -21,6 +21,7 @@
 //                   waves through LDS, reorders the tile in LDS by digit and
 //                   writes it out in digit runs (coalesced).  The next tile's keys
 //                   and values are loaded while the current one is written out.
+#include <algorithm>
 #include <string>
 
 #include "internal.h"
@@ -32,9 +33,10 @@ __device__ __forceinline__ uint32_t load_n(const uint32_t* n_dev, uint32_t n_hos
     return n_dev ? *n_dev : n_host;
 }
 
-// Partition p covers radix tiles [t0, t1) of kSortTile elements each.
+// Partition p covers radix tiles [t0, t1) of TILE elements each.
+template <int TILE>
 __device__ __forceinline__ void part_range(uint32_t n, int parts, int p, uint32_t& t0, uint32_t& t1) {
-    const uint32_t tiles = (n + kSortTile - 1) / kSortTile;
+    const uint32_t tiles = (n + TILE - 1) / TILE;
     const uint32_t per = (tiles + parts - 1) / parts;
     t0 = min(tiles, per * (uint32_t)p);
     t1 = min(tiles, t0 + per);
@@ -57,7 +59,7 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t digit, uint64_t active)
     return ((uint64_t)hi << 32) | lo;
 }
 
-template <int D>
+template <int D, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_hist(const uint32_t* __restrict__ keys, const uint32_t* n_dev,
                                                 uint32_t n_host, int shift, int nbits, int parts, int use_drop,
                                                 uint32_t drop, uint32_t* __restrict__ hist) {
@@ -69,25 +71,25 @@ __global__ __launch_bounds__(kBlock) void k_hist(const uint32_t* __restrict__ ke
     __syncthreads();
     const uint32_t mask = (1u << nbits) - 1u;
     uint32_t t0, t1;
-    part_range(n, parts, blockIdx.x, t0, t1);
-    uint32_t key[kSortItems];
+    part_range<kBlock * ITEMS>(n, parts, blockIdx.x, t0, t1);
+    uint32_t key[ITEMS];
     auto load_tile = [&](uint32_t t) {   // all loads in flight before any count
-        const uint32_t base = t * kSortTile;
+        const uint32_t base = t * (kBlock * ITEMS);
 #pragma unroll
-        for (int k = 0; k < kSortItems; ++k) {
+        for (int k = 0; k < ITEMS; ++k) {
             const uint32_t idx = base + k * kBlock + tid;
             key[k] = idx < n ? keys[idx] : 0u;
         }
     };
     if (t0 < t1) load_tile(t0);
     for (uint32_t t = t0; t < t1; ++t) {
-        const uint32_t base = t * kSortTile;
-        uint32_t cur[kSortItems];
+        const uint32_t base = t * (kBlock * ITEMS);
+        uint32_t cur[ITEMS];
 #pragma unroll
-        for (int k = 0; k < kSortItems; ++k) cur[k] = key[k];
+        for (int k = 0; k < ITEMS; ++k) cur[k] = key[k];
         if (t + 1 < t1) load_tile(t + 1);
 #pragma unroll
-        for (int k = 0; k < kSortItems; ++k) {
+        for (int k = 0; k < ITEMS; ++k) {
             const bool valid = base + k * kBlock + tid < n && !(use_drop && cur[k] == drop);
             const uint32_t digit = (cur[k] >> shift) & mask;
             const uint64_t vm = __ballot(valid);
@@ -157,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_rows(uint32_t* __restrict__ his
     if (tid == 0) totals[blockIdx.x] = total;
 }
 
-template <int NBITS>
+template <int NBITS, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                    const uint32_t* n_dev, uint32_t n_host, int shift,
@@ -165,13 +167,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
                                                    const uint32_t* __restrict__ totals, int use_drop,
                                                    uint32_t drop, uint32_t* __restrict__ n_kept) {
     constexpr int D = NBITS > kRadixBits ? kMaxRadix : kRadix;
+    constexpr int TILE = kBlock * ITEMS;
     constexpr int DPT = D / kBlock;   // digits per thread in the block scans: thread t owns t*DPT + j
     static_assert(DPT * kBlock == D && (DPT == 1 || DPT == 2), "256 or 512 digits");
     __shared__ uint32_t run[D];       // global write base of each digit for the next tile
     __shared__ uint32_t wcnt[4][D];   // per-wave digit counts, then per-wave digit offsets in the tile
     __shared__ uint32_t tstart[D];    // first slot of each digit in the LDS-ordered tile
     __shared__ uint32_t scan_tmp[kBlock / 64];
-    __shared__ uint32_t sk[kSortTile], sv[kSortTile];
+    __shared__ uint32_t sk[TILE], sv[TILE];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const uint32_t mask = (1u << NBITS) - 1u;
     const uint32_t n = load_n(n_dev, n_host);
@@ -199,14 +202,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
         if (n_kept && blockIdx.x == 0 && tid == 0) *n_kept = tot;   // keys kept (equal to drop: left out)
     }
     uint32_t t0, t1;
-    part_range(n, parts, blockIdx.x, t0, t1);
+    part_range<TILE>(n, parts, blockIdx.x, t0, t1);
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     // wave w ranks elements [tbase + w*512, tbase + (w+1)*512) of a tile in order: item k, lane l.
-    uint32_t key[kSortItems], val[kSortItems];
+    uint32_t key[ITEMS], val[ITEMS];
     auto load_tile = [&](uint32_t t) {   // all loads in flight before the ranking
-        const uint32_t wb = t * kSortTile + (uint32_t)wave * 64u * kSortItems;
+        const uint32_t wb = t * TILE + (uint32_t)wave * 64u * ITEMS;
 #pragma unroll
-        for (int k = 0; k < kSortItems; ++k) {
+        for (int k = 0; k < ITEMS; ++k) {
             const uint32_t idx = wb + k * 64 + lane;
             key[k] = idx < n ? kin[idx] : 0u;
             val[k] = idx < n ? vin[idx] : 0u;
@@ -216,11 +219,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
     for (uint32_t t = t0; t < t1; ++t) {
         for (int i = tid; i < 4 * D; i += kBlock) (&wcnt[0][0])[i] = 0;
         __syncthreads();
-        const uint32_t tbase = t * kSortTile;
-        const uint32_t wbase = tbase + (uint32_t)wave * 64u * kSortItems;
-        uint32_t rank[kSortItems];
+        const uint32_t tbase = t * TILE;
+        const uint32_t wbase = tbase + (uint32_t)wave * 64u * ITEMS;
+        uint32_t rank[ITEMS];
 #pragma unroll
-        for (int k = 0; k < kSortItems; ++k) {
+        for (int k = 0; k < ITEMS; ++k) {
             const uint32_t idx = wbase + k * 64 + lane;
             const bool valid = idx < n && !(use_drop && key[k] == drop);
             const uint32_t digit = (key[k] >> shift) & mask;
@@ -261,12 +264,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
         __syncthreads();
         // reorder the tile in LDS by digit (stable)
 #pragma unroll
-        for (int k = 0; k < kSortItems; ++k) {
+        for (int k = 0; k < ITEMS; ++k) {
             const uint32_t idx = wbase + k * 64 + lane;
             if (idx < n && !(use_drop && key[k] == drop)) {
                 const uint32_t digit = (key[k] >> shift) & mask;
                 const uint32_t lp = tstart[digit] + wcnt[wave][digit] + rank[k];
-                if (lp < (uint32_t)kSortTile) {   // always true: lp < tile count
+                if (lp < (uint32_t)TILE) {   // always true: lp < tile count
                     sk[lp] = key[k];
                     sv[lp] = val[k];
                 }
@@ -278,7 +281,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
         for (int j = 0; j < DPT; ++j) run[tid * DPT + j] = gbase[j] - tsj[j];
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < kSortItems; ++k) {
+        for (int k = 0; k < ITEMS; ++k) {
             const uint32_t i = k * kBlock + tid;
             if (i < tot) {   // the tile's kept keys, in digit order
                 const uint32_t kk = sk[i];
@@ -298,14 +301,16 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
 
 }  // namespace
 
-hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b,
-                          const uint32_t* n_dev, uint32_t n_host, int bit0, int nbits, int parts,
-                          uint32_t* hist, int* result_in_b, const char* tag, void* timer, hipStream_t s,
-                          int use_drop, uint32_t drop_key, uint32_t* n_kept) {
-    if (nbits < 1 || nbits > 32) return hipErrorInvalidValue;
+namespace {
+
+// The passes of one sort with radix tiles of kBlock * ITEMS keys over `parts` partitions.
+template <int ITEMS>
+hipError_t sort_passes(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, const uint32_t* n_dev,
+                       uint32_t n_host, int bit0, int nbits, int parts, uint32_t* hist, uint32_t* totals,
+                       int* result_in_b, const char* tag, void* timer, hipStream_t s, int use_drop, uint32_t drop_key,
+                       uint32_t* n_kept) {
     const std::string th = std::string(tag) + "_hist", ts = std::string(tag) + "_scan",
                       tc = std::string(tag) + "_scatter";
-    uint32_t* totals = hist + (size_t)kMaxRadix * parts;
     // ceil(nbits / 9) passes, the bits split as evenly as possible (at most 9 per pass)
     const int passes = (nbits + kMaxRadixBits - 1) / kMaxRadixBits;
     int in_b = 0, done = 0;
@@ -323,11 +328,11 @@ hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, 
         const bool wide = bits > kRadixBits;   // 512 digit counters
         timer_begin(timer, th.c_str(), s);
         if (wide)
-            hipLaunchKernelGGL(k_hist<kMaxRadix>, dim3(parts), dim3(kBlock), 0, s, kin, n_in, n_host, shift, bits,
-                               parts, drop_now, drop_key, hist);
+            hipLaunchKernelGGL((k_hist<kMaxRadix, ITEMS>), dim3(parts), dim3(kBlock), 0, s, kin, n_in, n_host, shift,
+                               bits, parts, drop_now, drop_key, hist);
         else
-            hipLaunchKernelGGL(k_hist<kRadix>, dim3(parts), dim3(kBlock), 0, s, kin, n_in, n_host, shift, bits, parts,
-                               drop_now, drop_key, hist);
+            hipLaunchKernelGGL((k_hist<kRadix, ITEMS>), dim3(parts), dim3(kBlock), 0, s, kin, n_in, n_host, shift,
+                               bits, parts, drop_now, drop_key, hist);
         timer_end(timer, s);
         timer_begin(timer, ts.c_str(), s);
         hipLaunchKernelGGL(k_scan_rows, dim3(1u << bits), dim3(kBlock), 0, s, hist, parts, totals, n_in, n_host);
@@ -335,10 +340,10 @@ hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, 
         timer_begin(timer, tc.c_str(), s);
         uint32_t* kept = first ? n_kept : nullptr;
         switch (bits) {   // the digit width is a template argument: the ranking unrolls per bit
-#define GS_SCATTER(B)                                                                                             \
-    case B:                                                                                                       \
-        hipLaunchKernelGGL(k_scatter<B>, dim3(parts), dim3(kBlock), 0, s, kin, vin, kout, vout, n_in, n_host, shift, \
-                           parts, hist, totals, drop_now, drop_key, kept);                                        \
+#define GS_SCATTER(B)                                                                                                \
+    case B:                                                                                                          \
+        hipLaunchKernelGGL((k_scatter<B, ITEMS>), dim3(parts), dim3(kBlock), 0, s, kin, vin, kout, vout, n_in, n_host, \
+                           shift, parts, hist, totals, drop_now, drop_key, kept);                                    \
         break;
             GS_SCATTER(1) GS_SCATTER(2) GS_SCATTER(3) GS_SCATTER(4) GS_SCATTER(5) GS_SCATTER(6) GS_SCATTER(7)
             GS_SCATTER(8) GS_SCATTER(9)
@@ -351,6 +356,27 @@ hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, 
     }
     *result_in_b = in_b;
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b,
+                          const uint32_t* n_dev, uint32_t n_host, int bit0, int nbits, int parts,
+                          uint32_t* hist, int* result_in_b, const char* tag, void* timer, hipStream_t s,
+                          int use_drop, uint32_t drop_key, uint32_t* n_kept) {
+    if (nbits < 1 || nbits > 32 || parts < 1) return hipErrorInvalidValue;
+    uint32_t* totals = hist + (size_t)kMaxRadix * parts;
+    // Large sorts take radix tiles of 4096 keys (longer digit runs per tile, so fuller write
+    // segments); smaller ones 2048, which fill the device with more partitions.  The partition
+    // count never exceeds the caller's, so the histogram table fits.
+    if (n_host >= kLargeSortKeys) {
+        constexpr int64_t tile = (int64_t)kBlock * 16;
+        const int p = (int)std::min<int64_t>(parts, std::max<int64_t>(1, ((int64_t)n_host + tile - 1) / tile));
+        return sort_passes<16>(keys_a, vals_a, keys_b, vals_b, n_dev, n_host, bit0, nbits, p, hist, totals,
+                               result_in_b, tag, timer, s, use_drop, drop_key, n_kept);
+    }
+    return sort_passes<kSortItems>(keys_a, vals_a, keys_b, vals_b, n_dev, n_host, bit0, nbits, parts, hist, totals,
+                                   result_in_b, tag, timer, s, use_drop, drop_key, n_kept);
 }
 
 }  // namespace gs

@@ -45,12 +45,14 @@ def test_keys_bitexact_config1_small(oracle_mod, tile):
     assert K > 20000
 
 
-def test_keys_bitexact_many_sort_tiles(oracle_mod):
-    """5.7e6 pairs at 1600x1067: the tile sort spans ~2800 tiles of 2048 keys, several per sort
-    workgroup, and its second digit pass covers 5 bits."""
+@pytest.mark.parametrize("capacity", [6_000_000, 9_000_000])
+def test_keys_bitexact_many_sort_tiles(oracle_mod, capacity):
+    """5.7e6 pairs at 1600x1067: the tile sort spans ~2800 radix tiles of 2048 keys, several per sort
+    workgroup, and its second digit pass covers 5 bits.  A capacity of 9e6 pairs (above the
+    8,388,608-key threshold) sorts in radix tiles of 4096 keys instead, two per workgroup."""
     sc = synth.make_scene(1, n=120000)
-    U.say("keys many sort tiles")
-    K = _keys_match(sc, U.make_rast(sc, phases=1, tile_cull=False, max_pairs=6_000_000), oracle_mod)
+    U.say(f"keys many sort tiles, capacity {capacity}")
+    K = _keys_match(sc, U.make_rast(sc, phases=1, tile_cull=False, max_pairs=capacity), oracle_mod)
     assert K > 5_000_000
 
 
