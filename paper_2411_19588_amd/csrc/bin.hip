@@ -426,7 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_rects(const uint32_t* __restric
         if (own) {
             const uint32_t e = order[r];
             const uint2 rc = rects[e];
-            const ViewInfo vi = vt[e / (uint64_t)n];
+            const ViewInfo vi = vt[e / (uint32_t)n];
             const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu;
             const uint32_t w = x1 - x0 + 1;
             s_off[i] = (int32_t)((int64_t)offsets[r] - (int64_t)p0);
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_rects(const uint32_t* __restric
             s_tx[i] = (uint32_t)vi.tiles_x;
             s_xy[i] = rc.x;
             s_iw[i] = 1.0f / (float)w;
-            s_view[i] = (uint16_t)(e / (uint64_t)n);
+            s_view[i] = (uint16_t)(e / (uint32_t)n);
         }
         nent += __syncthreads_count(own);
     }
@@ -490,11 +490,12 @@ __device__ __forceinline__ uint32_t select_bit(uint64_t m, uint32_t k) {
     return pos;
 }
 
-// Column of the k-th (from 0) alive tile of [lo, hi] in one tile row (hi if there are fewer).
+// Column of the k-th (from 0) alive tile of [lo, hi] in one tile row (hi if there are fewer);
+// w0 and w1 are the row's mask words lo / 64 and lo / 64 + 1, loaded by the caller.
 __device__ __forceinline__ uint32_t kth_alive(const uint64_t* __restrict__ bits, uint32_t lo, uint32_t hi,
-                                              uint32_t k) {
+                                              uint32_t k, uint64_t w0, uint64_t w1) {
     for (uint32_t w = lo >> 6; w <= (hi >> 6); ++w) {
-        uint64_t m = bits[w];
+        uint64_t m = w == (lo >> 6) ? w0 : (w == (lo >> 6) + 1 ? w1 : bits[w]);
         if (w == (lo >> 6)) m &= ~0ull << (lo & 63);
         if (w == (hi >> 6) && (hi & 63) != 63) m &= (2ull << (hi & 63)) - 1ull;
         const uint32_t c = (uint32_t)__popcll(m);
@@ -560,7 +561,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_spans(const uint32_t* __restric
     for (int j = tid; j < nent; j += kBlock) {
         const uint32_t e = s_e[j];
         const uint2 rc = rects[e];
-        const ViewInfo vi = vt[e / (uint64_t)n];
+        const ViewInfo vi = vt[e / (uint32_t)n];
         const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
         int32_t st = s_off[j];
         for (uint32_t ty = y0; ty <= y1 && st < span; ++ty) {
@@ -601,6 +602,8 @@ __global__ __launch_bounds__(kBlock) void k_emit_spans(const uint32_t* __restric
 #pragma unroll
     for (int k = 0; k < kEmitItems; ++k) s_cover[tid * kEmitItems + k] = max(before, v[k]);
     __syncthreads();
+    // Per pair, two rounds of loads: the view's fields with the splat's record, then the row's first
+    // two mask words (further words, for rows of more than 128 tiles, in the loop).
 #pragma unroll
     for (int k = 0; k < kEmitItems; ++k) {
         const int q = k * kBlock + tid;
@@ -612,15 +615,21 @@ __global__ __launch_bounds__(kBlock) void k_emit_spans(const uint32_t* __restric
             continue;
         }
         const uint32_t jy = s_ijy[pos], lohi = s_ilohi[pos];
-        const uint32_t e = s_e[jy & 0xFFFFu], ty = jy >> 16;
-        const ViewInfo vi = vt[e / (uint64_t)n];
-        const uint32_t tx = kth_alive(rowbits + (size_t)(vi.row_base + ty) * row_words, lohi & 0xFFFFu, lohi >> 16,
-                                      (uint32_t)(q - s_ist[pos]));
-        uint32_t tile = vi.tile_base + ty * (uint32_t)vi.tiles_x + tx;
-        if (cull.enabled) {   // a culled pair gets the out-of-range tile id: the tile sort leaves it out
+        const uint32_t e = s_e[jy & 0xFFFFu], ty = jy >> 16, lo = lohi & 0xFFFFu, hi = lohi >> 16;
+        const ViewInfo vi = vt[e / (uint32_t)n];
+        float4 ra;
+        float2 rb;
+        if (cull.enabled) {
             const Record* rp = cull.rec + e;
-            if (!tile_may_contribute(rp->a, make_float2(rp->b.x, rp->b.y), vi, tx, ty, cull)) tile = n_tiles;
+            ra = rp->a;
+            rb = make_float2(rp->b.x, rp->b.y);
         }
+        const uint64_t* row = rowbits + (size_t)(vi.row_base + ty) * row_words;
+        const uint64_t w0 = row[lo >> 6], w1 = (lo >> 6) < (hi >> 6) ? row[(lo >> 6) + 1] : 0ull;
+        const uint32_t tx = kth_alive(row, lo, hi, (uint32_t)(q - s_ist[pos]), w0, w1);
+        uint32_t tile = vi.tile_base + ty * (uint32_t)vi.tiles_x + tx;
+        // a culled pair gets the out-of-range tile id: the tile sort leaves it out
+        if (cull.enabled && !tile_may_contribute(ra, rb, vi, tx, ty, cull)) tile = n_tiles;
         tiles_out[p0 + q] = tile;
         vals_out[p0 + q] = e;
     }
