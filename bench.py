@@ -128,7 +128,7 @@ def kernel_bytes(name: str, n: int, views: int, K: int, P: int, tiles: int, ncoe
         # every digit pass of every phase's tile sort moves that phase's pairs
         "tile_sort_hist": (K * 4 * tile_passes) / per_step,
         "tile_sort_scatter": (K * 16 * tile_passes) / per_step,
-        "commit": (K * 12) / per_step,
+        "commit": (K * 4) / per_step,              # sorted tile ids read (neighbours cached); ranges written
         # outputs + saved state per pixel; the gathered records of traversed pairs are cache-resident
         "composite_fwd": (P * (12 + 4 + 4) + P * 29 + tiles * 8) / per_step,
         "composite_bwd": P * (12 + 28) + NV * 40 + tiles * 36,

@@ -358,13 +358,12 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
         // stable sort of the phase's pairs by tile id
         int tb = 0;
         if (L.max_pairs > 0)
+            // the values land behind the earlier phases' in the stored list
             GS_TRY(radix_sort_u32(tiles_a, vals_a, tiles_b, vals_b, &hdr->phase_count[ph], (uint32_t)L.max_pairs, 0,
-                                  L.tile_bits,
-                                  L.pair_parts, hist, &tb, "tile_sort", T, s, 1, (uint32_t)L.tiles,
-                                  &hdr->phase_live[ph]));
+                                  L.tile_bits, L.pair_parts, hist, &tb, "tile_sort", T, s, 1, (uint32_t)L.tiles,
+                                  &hdr->phase_live[ph], vals, &hdr->phase_base[ph]));
         timer_begin(T, "commit", s);
-        GS_TRY(launch_commit(tb ? tiles_b : tiles_a, tb ? vals_b : vals_a, hdr, ph, L.tiles, L.max_pairs, vals,
-                             ranges, s));
+        GS_TRY(launch_commit(tb ? tiles_b : tiles_a, hdr, ph, L.tiles, L.max_pairs, ranges, s));
         timer_end(T, s);
         const uint32_t* order = nullptr;
         if (o.persistent == 2)

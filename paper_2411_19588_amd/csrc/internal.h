@@ -166,11 +166,14 @@ hipError_t launch_zero_adam_prep(uint32_t* p, int64_t count, int32_t* state, con
 // (or n_host if n_dev is null); with n_dev, n_host is the largest n it can hold, which picks the
 // radix tile size.  Returns in *out_in_b whether the result sits in the B buffers.
 // With use_drop, keys equal to drop_key are left out; with n_kept the number of kept pairs is
-// written there (device), and the sorted output holds exactly those.
+// written there (device), and the sorted output holds exactly those.  With final_vals, the last
+// pass writes the sorted values to final_vals + *final_off (final_off on the device) instead of
+// the A/B value buffers; the sorted keys are where *out_in_b says.
 hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b,
                           const uint32_t* n_dev, uint32_t n_host, int bit0, int nbits, int parts, uint32_t* hist,
                           int* out_in_b, const char* tag, void* timer, hipStream_t s, int use_drop = 0,
-                          uint32_t drop_key = 0, uint32_t* n_kept = nullptr);
+                          uint32_t drop_key = 0, uint32_t* n_kept = nullptr, uint32_t* final_vals = nullptr,
+                          const uint32_t* final_off = nullptr);
 // Depth-phase schedule.  With V visible entries (the depth sort's count of kept keys), phase
 // p < phases - 1 ends at depth rank ceil(V / 2^(shift - growth p)) (at V once the exponent
 // reaches 0) and the last phase at V; every kernel that needs a phase's ranks derives them from V.
@@ -214,9 +217,10 @@ hipError_t launch_emit(const uint32_t* order, const uint64_t* offsets, const uin
                        const AliveRows& ar, const SavedHeader* hdr, int phase, int64_t max_pairs,
                        const CullArgs& cull, uint32_t n_tiles, uint32_t* tiles_out, uint32_t* vals_out,
                        hipStream_t s);
-// Copy the phase's tile-sorted values behind the earlier phases' and record its tile ranges.
-hipError_t launch_commit(const uint32_t* sorted_tiles, const uint32_t* sorted_vals, const SavedHeader* hdr,
-                         int phase, int64_t tiles, int64_t max_pairs, uint32_t* vals, uint2* ranges, hipStream_t s);
+// The phase's tile ranges from its tile-sorted keys (the tile sort wrote the values behind the
+// earlier phases').
+hipError_t launch_commit(const uint32_t* sorted_tiles, const SavedHeader* hdr, int phase, int64_t tiles,
+                         int64_t max_pairs, uint2* ranges, hipStream_t s);
 // out_restored (nullable): the in-air composite C_air per pixel, CHW per view like out_rgb.
 // rowbits (nullable, zeroed beforehand): the bit of every tile left alive is set there.
 hipError_t launch_composite_fwd(const gs_options& o, const Layout& L, int phase, const ViewInfo* vt,

@@ -162,6 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_rows(uint32_t* __restrict__ his
 template <int NBITS, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                   const uint32_t* __restrict__ vout_off,
                                                    const uint32_t* n_dev, uint32_t n_host, int shift,
                                                    int parts, const uint32_t* __restrict__ hist,
                                                    const uint32_t* __restrict__ totals, int use_drop,
@@ -182,6 +183,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
         if (n_kept && blockIdx.x == 0 && tid == 0) *n_kept = 0;
         return;
     }
+    const uint32_t vbase = vout_off ? *vout_off : 0u;   // values land at vout + vbase + position
     {
         // only the pass's 2^NBITS digit rows were scanned
         uint32_t tv[DPT], sum = 0;
@@ -288,7 +290,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint32_t* __restrict__
                 const uint32_t pos = run[(kk >> shift) & mask] + i;
                 if (pos < n) {   // always true when the histogram and ranking agree
                     kout[pos] = kk;
-                    vout[pos] = sv[i];
+                    vout[vbase + pos] = sv[i];
                 }
             }
         }
@@ -308,7 +310,7 @@ template <int ITEMS>
 hipError_t sort_passes(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, const uint32_t* n_dev,
                        uint32_t n_host, int bit0, int nbits, int parts, uint32_t* hist, uint32_t* totals,
                        int* result_in_b, const char* tag, void* timer, hipStream_t s, int use_drop, uint32_t drop_key,
-                       uint32_t* n_kept) {
+                       uint32_t* n_kept, uint32_t* final_vals, const uint32_t* final_off) {
     const std::string th = std::string(tag) + "_hist", ts = std::string(tag) + "_scan",
                       tc = std::string(tag) + "_scatter";
     // ceil(nbits / 9) passes, the bits split as evenly as possible (at most 9 per pass)
@@ -321,6 +323,11 @@ hipError_t sort_passes(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uin
         const uint32_t* vin = in_b ? vals_b : vals_a;
         uint32_t* kout = in_b ? keys_a : keys_b;
         uint32_t* vout = in_b ? vals_a : vals_b;
+        const uint32_t* voff = nullptr;
+        if (q == passes - 1 && final_vals) {   // the last pass writes the values to their destination
+            vout = final_vals;
+            voff = final_off;
+        }
         // the first pass leaves out the keys equal to drop_key; later passes sort the kept ones
         const bool first = q == 0;
         const int drop_now = first && use_drop ? 1 : 0;
@@ -342,8 +349,8 @@ hipError_t sort_passes(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uin
         switch (bits) {   // the digit width is a template argument: the ranking unrolls per bit
 #define GS_SCATTER(B)                                                                                                \
     case B:                                                                                                          \
-        hipLaunchKernelGGL((k_scatter<B, ITEMS>), dim3(parts), dim3(kBlock), 0, s, kin, vin, kout, vout, n_in, n_host, \
-                           shift, parts, hist, totals, drop_now, drop_key, kept);                                    \
+        hipLaunchKernelGGL((k_scatter<B, ITEMS>), dim3(parts), dim3(kBlock), 0, s, kin, vin, kout, vout, voff, n_in,   \
+                           n_host, shift, parts, hist, totals, drop_now, drop_key, kept);                            \
         break;
             GS_SCATTER(1) GS_SCATTER(2) GS_SCATTER(3) GS_SCATTER(4) GS_SCATTER(5) GS_SCATTER(6) GS_SCATTER(7)
             GS_SCATTER(8) GS_SCATTER(9)
@@ -363,8 +370,9 @@ hipError_t sort_passes(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uin
 hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b,
                           const uint32_t* n_dev, uint32_t n_host, int bit0, int nbits, int parts,
                           uint32_t* hist, int* result_in_b, const char* tag, void* timer, hipStream_t s,
-                          int use_drop, uint32_t drop_key, uint32_t* n_kept) {
-    if (nbits < 1 || nbits > 32 || parts < 1) return hipErrorInvalidValue;
+                          int use_drop, uint32_t drop_key, uint32_t* n_kept, uint32_t* final_vals,
+                          const uint32_t* final_off) {
+    if (nbits < 1 || nbits > 32 || parts < 1 || (final_vals && !final_off)) return hipErrorInvalidValue;
     uint32_t* totals = hist + (size_t)kMaxRadix * parts;
     // Large sorts take radix tiles of 4096 keys (longer digit runs per tile, so fuller write
     // segments); smaller ones 2048, which fill the device with more partitions.  The partition
@@ -373,10 +381,10 @@ hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, 
         constexpr int64_t tile = (int64_t)kBlock * 16;
         const int p = (int)std::min<int64_t>(parts, std::max<int64_t>(1, ((int64_t)n_host + tile - 1) / tile));
         return sort_passes<16>(keys_a, vals_a, keys_b, vals_b, n_dev, n_host, bit0, nbits, p, hist, totals,
-                               result_in_b, tag, timer, s, use_drop, drop_key, n_kept);
+                               result_in_b, tag, timer, s, use_drop, drop_key, n_kept, final_vals, final_off);
     }
     return sort_passes<kSortItems>(keys_a, vals_a, keys_b, vals_b, n_dev, n_host, bit0, nbits, parts, hist, totals,
-                                   result_in_b, tag, timer, s, use_drop, drop_key, n_kept);
+                                   result_in_b, tag, timer, s, use_drop, drop_key, n_kept, final_vals, final_off);
 }
 
 }  // namespace gs
