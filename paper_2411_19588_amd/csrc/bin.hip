@@ -68,6 +68,7 @@ __global__ __launch_bounds__(kBlock) void k_view_table(ViewTable t, ViewInfo* ds
     for (int64_t j = (int64_t)blockIdx.x * kBlock + i; j < fill_count; j += (int64_t)gridDim.x * kBlock) fill[j] = 0u;
     if (blockIdx.x != 0) return;
     if (i < t.count) dst[i] = t.v[i];
+    for (int j = i; j < GS_MAX_PHASES * GS_MAX_VIEWS; j += kBlock) (&hdr->view_alive[0][0])[j] = 0u;
     if (i == 0) {
         hdr->status = 0;
         hdr->pair_count = 0;
@@ -169,8 +170,10 @@ __global__ __launch_bounds__(kCountThreads) void k_phase_counts(const uint32_t* 
         for (int k = 0; k < kCountItems; ++k) {
             c[k] = 0u;
             if (e[k] == kNone) continue;
+            const uint32_t view = e[k] / (uint32_t)n;
+            if (hdr->view_alive[phase - 1][view] == 0u) continue;   // every tile of the view terminated
             const uint2 rc = rects[e[k]];
-            const uint32_t rb = vt[e[k] / (uint32_t)n].row_base;
+            const uint32_t rb = vt[view].row_base;
             const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
             for (uint32_t ty = y0; ty <= y1; ++ty) c[k] += alive_in(rowbits + (size_t)(rb + ty) * row_words, x0, x1);
         }

@@ -47,6 +47,7 @@ struct FwdArgs {
     const uint32_t* order;    // persistent mode: tile of each queue position (null: index order)
     uint32_t* alive;
     uint32_t* alive_count;
+    uint32_t* view_alive;     // [views]: tiles of each view left alive
     uint64_t* rowbits;        // nullable: per global tile row, the bits of the tiles left alive
     uint32_t row_words;
     float* out_rgb;
@@ -484,6 +485,7 @@ __global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_fwd
             a.alive[tile] = tile_alive ? 1u : 0u;
             if (tile_alive) {
                 atomicAdd(a.alive_count, 1u);
+                atomicAdd(a.view_alive + v, 1u);
                 if (a.rowbits) {
                     const uint32_t tx = lt % (uint32_t)vi.tiles_x, ty = lt / (uint32_t)vi.tiles_x;
                     atomicOr(reinterpret_cast<unsigned long long*>(a.rowbits) +
@@ -1057,7 +1059,8 @@ hipError_t launch_composite_fwd(const gs_options& o, const Layout& L, int phase,
                                 hipStream_t s) {
     if (L.tiles == 0) return hipSuccess;
     FwdArgs a{vt, L.views, (uint32_t)L.tiles, phase, L.phases - 1, med, rec, ranges + (size_t)phase * L.tiles, vals,
-              &hdr->queue[phase], order, alive, &hdr->phase_alive[phase], rowbits, (uint32_t)L.row_words, out_rgb,
+              &hdr->queue[phase], order, alive, &hdr->phase_alive[phase], hdr->view_alive[phase], rowbits,
+              (uint32_t)L.row_words, out_rgb,
               out_depth, out_alpha,
               out_restored, tfinal, nlast, done, cair, dsum, wsum, L.pixels, o.alpha_min, o.alpha_max, o.t_min,
               o.depth_mode, o.depth_output};

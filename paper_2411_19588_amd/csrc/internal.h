@@ -70,6 +70,7 @@ struct SavedHeader {
     uint32_t phase_alive[GS_MAX_PHASES];      // tiles with an unterminated pixel after phase p
     uint32_t phase_live[GS_MAX_PHASES];       // pairs of phase p kept by the tile sort (culled ones left out)
     uint32_t queue[GS_MAX_PHASES + 1];        // persistent-mode tile counters (forward phases)
+    uint32_t view_alive[GS_MAX_PHASES][GS_MAX_VIEWS];   // tiles of each view left alive after phase p
     unsigned long long stats[5];              // scratch of gs_forward_stats
     uint32_t pad[4];
 };
