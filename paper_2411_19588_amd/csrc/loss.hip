@@ -80,94 +80,142 @@ __global__ __launch_bounds__(kLossThreads) void k_l1_dssim(LossArgs a) {
         sy[r][c] = in ? Y[(int64_t)gy * W + gx] : 0.0f;
     }
     __syncthreads();
-    // ---- horizontal window sums of x, y, x^2, y^2, x y on every staged row, one-halo columns
-    for (int i = tid; i < kIH * kMW; i += kLossThreads) {
-        const int r = i / kMW, c = i - r * kMW;
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+    // The four window passes are register-blocked: a thread reads a run of LDS values once and
+    // forms several consecutive outputs from registers, each with the taps in order (the same
+    // FMA chain per output as a one-output-per-thread pass).
+    // ---- horizontal window sums of x, y, x^2, y^2, x y on every staged row, one-halo columns:
+    //      thread (row, run) forms kH1 consecutive columns
+    constexpr int kH1 = 6, kH1Runs = kMW / kH1;
+    static_assert(kH1Runs * kH1 == kMW && kIH * kH1Runs <= kLossThreads, "one pass");
+    if (tid < kIH * kH1Runs) {
+        const int r = tid / kH1Runs, c0 = (tid - r * kH1Runs) * kH1;
+        float xv[kH1 + kTaps - 1], yv[kH1 + kTaps - 1];
 #pragma unroll
-        for (int k = 0; k < kTaps; ++k) {
-            const float xv = sx[r][c + k], yv = sy[r][c + k], w = a.g[k];
-            s0 = fmaf(w, xv, s0);
-            s1 = fmaf(w, yv, s1);
-            s2 = fmaf(w, xv * xv, s2);
-            s3 = fmaf(w, yv * yv, s3);
-            s4 = fmaf(w, xv * yv, s4);
+        for (int j = 0; j < kH1 + kTaps - 1; ++j) {
+            xv[j] = sx[r][c0 + j];
+            yv[j] = sy[r][c0 + j];
         }
-        hm[0][r][c] = s0;
-        hm[1][r][c] = s1;
-        hm[2][r][c] = s2;
-        hm[3][r][c] = s3;
-        hm[4][r][c] = s4;
-    }
-    __syncthreads();
-    // ---- vertical sums, SSIM and its derivatives w.r.t. (m1, m2, m12) on the one-halo region
-    const float dscale = -a.lambda / (3.0f * (float)plane);   // dL/dS: L holds lambda (1 - mean S)
-    float s_sum = 0.0f;
-    for (int i = tid; i < kMH * kMW; i += kLossThreads) {
-        const int r = i / kMW, c = i - r * kMW;
-        const int gy = y0 - kR + r, gx = x0 - kR + c;
-        float da = 0.f, db = 0.f, dc = 0.f;
-        if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
-            float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int o = 0; o < kH1; ++o) {
+            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
 #pragma unroll
             for (int k = 0; k < kTaps; ++k) {
-                const float w = a.g[k];
-#pragma unroll
-                for (int q = 0; q < 5; ++q) m[q] = fmaf(w, hm[q][r + k][c], m[q]);
+                const float x = xv[o + k], y = yv[o + k], w = a.g[k];
+                s0 = fmaf(w, x, s0);
+                s1 = fmaf(w, y, s1);
+                s2 = fmaf(w, x * x, s2);
+                s3 = fmaf(w, y * y, s3);
+                s4 = fmaf(w, x * y, s4);
             }
-            const float mx = m[0], my = m[1];
-            const float sxx = m[2] - mx * mx, syy = m[3] - my * my, sxy = m[4] - mx * my;
-            const float A1 = fmaf(2.0f * mx, my, kC1), A2 = fmaf(2.0f, sxy, kC2);
-            const float B1 = fmaf(mx, mx, fmaf(my, my, kC1)), B2 = sxx + syy + kC2;
-            const float iden = 1.0f / (B1 * B2);
-            const float S = A1 * A2 * iden;
-            da = dscale * (2.0f * my * (A2 - A1) * iden - S * (2.0f * mx / B1 - 2.0f * mx / B2));
-            db = dscale * (-S / B2);
-            dc = dscale * (2.0f * A1 * iden);
-            if (r >= kR && r < kR + kTH && c >= kR && c < kR + kTW) s_sum += S;
+            hm[0][r][c0 + o] = s0;
+            hm[1][r][c0 + o] = s1;
+            hm[2][r][c0 + o] = s2;
+            hm[3][r][c0 + o] = s3;
+            hm[4][r][c0 + o] = s4;
         }
-        sd[0][r][c] = da;
-        sd[1][r][c] = db;
-        sd[2][r][c] = dc;
     }
     __syncthreads();
-    // ---- adjoint: horizontal sums of (a, b, c) on the one-halo rows, tile columns
-    for (int i = tid; i < kMH * kTW; i += kLossThreads) {
-        const int r = i / kTW, c = i - r * kTW;
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+    // ---- vertical sums, SSIM and its derivatives w.r.t. (m1, m2, m12) on the one-halo region:
+    //      thread (column, run) forms kV1 consecutive rows
+    const float dscale = -a.lambda / (3.0f * (float)plane);   // dL/dS: L holds lambda (1 - mean S)
+    float s_sum = 0.0f;
+    constexpr int kV1 = 7, kV1Runs = (kMH + kV1 - 1) / kV1;
+    static_assert(kMW * kV1Runs <= kLossThreads, "one pass");
+    if (tid < kMW * kV1Runs) {
+        const int c = tid % kMW, r0 = (tid / kMW) * kV1;
+        float m[5][kV1];
 #pragma unroll
-        for (int k = 0; k < kTaps; ++k) {
-            const float w = a.g[k];
-            s0 = fmaf(w, sd[0][r][c + k], s0);
-            s1 = fmaf(w, sd[1][r][c + k], s1);
-            s2 = fmaf(w, sd[2][r][c + k], s2);
+        for (int q = 0; q < 5; ++q) {
+            float col[kV1 + kTaps - 1];
+#pragma unroll
+            for (int j = 0; j < kV1 + kTaps - 1; ++j) col[j] = r0 + j < kIH ? hm[q][r0 + j][c] : 0.0f;
+#pragma unroll
+            for (int o = 0; o < kV1; ++o) {
+                float acc = 0.f;
+#pragma unroll
+                for (int k = 0; k < kTaps; ++k) acc = fmaf(a.g[k], col[o + k], acc);
+                m[q][o] = acc;
+            }
         }
-        hm[0][r][c] = s0;
-        hm[1][r][c] = s1;
-        hm[2][r][c] = s2;
+#pragma unroll
+        for (int o = 0; o < kV1; ++o) {
+            const int r = r0 + o;
+            if (r >= kMH) break;
+            const int gy = y0 - kR + r, gx = x0 - kR + c;
+            float da = 0.f, db = 0.f, dc = 0.f;
+            if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
+                const float mx = m[0][o], my = m[1][o];
+                const float sxx = m[2][o] - mx * mx, syy = m[3][o] - my * my, sxy = m[4][o] - mx * my;
+                const float A1 = fmaf(2.0f * mx, my, kC1), A2 = fmaf(2.0f, sxy, kC2);
+                const float B1 = fmaf(mx, mx, fmaf(my, my, kC1)), B2 = sxx + syy + kC2;
+                const float iden = 1.0f / (B1 * B2);
+                const float S = A1 * A2 * iden;
+                da = dscale * (2.0f * my * (A2 - A1) * iden - S * (2.0f * mx / B1 - 2.0f * mx / B2));
+                db = dscale * (-S / B2);
+                dc = dscale * (2.0f * A1 * iden);
+                if (r >= kR && r < kR + kTH && c >= kR && c < kR + kTW) s_sum += S;
+            }
+            sd[0][r][c] = da;
+            sd[1][r][c] = db;
+            sd[2][r][c] = dc;
+        }
     }
     __syncthreads();
-    // ---- vertical sums, the gradient and the tile's L1 sum
+    // ---- adjoint: horizontal sums of (a, b, c) on the one-halo rows, tile columns: thread (row,
+    //      run) forms kH2 consecutive columns
+    constexpr int kH2 = 4, kH2Runs = kTW / kH2;
+    static_assert(kH2Runs * kH2 == kTW && kMH * kH2Runs <= kLossThreads, "one pass");
+    if (tid < kMH * kH2Runs) {
+        const int r = tid / kH2Runs, c0 = (tid - r * kH2Runs) * kH2;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            float row[kH2 + kTaps - 1];
+#pragma unroll
+            for (int j = 0; j < kH2 + kTaps - 1; ++j) row[j] = sd[q][r][c0 + j];
+#pragma unroll
+            for (int o = 0; o < kH2; ++o) {
+                float acc = 0.f;
+#pragma unroll
+                for (int k = 0; k < kTaps; ++k) acc = fmaf(a.g[k], row[o + k], acc);
+                hm[q][r][c0 + o] = acc;
+            }
+        }
+    }
+    __syncthreads();
+    // ---- vertical sums, the gradient and the tile's L1 sum: thread (column, run) forms kV2
+    //      consecutive rows
     const float l1g = (1.0f - a.lambda) / (3.0f * (float)plane);
     float l_sum = 0.0f;
-    for (int i = tid; i < kTH * kTW; i += kLossThreads) {
-        const int r = i / kTW, c = i - r * kTW;
-        const int gy = y0 + r, gx = x0 + c;
-        if (gx >= W || gy >= H) continue;
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+    constexpr int kV2 = 2, kV2Runs = kTH / kV2;
+    static_assert(kV2Runs * kV2 == kTH && kTW * kV2Runs <= kLossThreads, "one pass");
+    if (tid < kTW * kV2Runs) {
+        const int c = tid % kTW, r0 = (tid / kTW) * kV2;
+        float g3[3][kV2];
 #pragma unroll
-        for (int k = 0; k < kTaps; ++k) {
-            const float w = a.g[k];
-            s0 = fmaf(w, hm[0][r + k][c], s0);
-            s1 = fmaf(w, hm[1][r + k][c], s1);
-            s2 = fmaf(w, hm[2][r + k][c], s2);
+        for (int q = 0; q < 3; ++q) {
+            float col[kV2 + kTaps - 1];
+#pragma unroll
+            for (int j = 0; j < kV2 + kTaps - 1; ++j) col[j] = hm[q][r0 + j][c];
+#pragma unroll
+            for (int o = 0; o < kV2; ++o) {
+                float acc = 0.f;
+#pragma unroll
+                for (int k = 0; k < kTaps; ++k) acc = fmaf(a.g[k], col[o + k], acc);
+                g3[q][o] = acc;
+            }
         }
-        const float xv = sx[r + 2 * kR][c + 2 * kR], yv = sy[r + 2 * kR][c + 2 * kR];
-        const float d = xv - yv;
-        l_sum += fabsf(d);
-        if (a.grad) {
-            const float sg = d > 0.0f ? l1g : (d < 0.0f ? -l1g : 0.0f);
-            a.grad[base + (int64_t)gy * W + gx] = sg + fmaf(2.0f * xv, s1, fmaf(yv, s2, s0));
+#pragma unroll
+        for (int o = 0; o < kV2; ++o) {
+            const int r = r0 + o;
+            const int gy = y0 + r, gx = x0 + c;
+            if (gx >= W || gy >= H) continue;
+            const float xv = sx[r + 2 * kR][c + 2 * kR], yv = sy[r + 2 * kR][c + 2 * kR];
+            const float d = xv - yv;
+            l_sum += fabsf(d);
+            if (a.grad) {
+                const float sg = d > 0.0f ? l1g : (d < 0.0f ? -l1g : 0.0f);
+                a.grad[base + (int64_t)gy * W + gx] = sg + fmaf(2.0f * xv, g3[1][o], fmaf(yv, g3[2][o], g3[0][o]));
+            }
         }
     }
     // ---- the tile's sums, reduced over the workgroup in a fixed order
