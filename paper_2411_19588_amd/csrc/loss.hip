@@ -51,9 +51,14 @@ struct LossArgs {
 };
 
 __global__ __launch_bounds__(kLossThreads) void k_l1_dssim(LossArgs a) {
-    __shared__ float sx[kIH][kIW], sy[kIH][kIW];
+    // x and y staged; after the first window pass the same memory holds (a, b, c) on the tile with
+    // one halo (three workgroups fit per CU)
+    __shared__ float stage[2 * kIH * kIW];
     __shared__ float hm[5][kIH][kMW];          // horizontal sums; reused for the adjoint's horizontal pass
-    __shared__ float sd[3][kMH][kMW];          // (a, b, c) on the tile with one halo
+    static_assert(3 * kMH * kMW <= 2 * kIH * kIW, "(a, b, c) fit in the staging memory");
+    float(*sx)[kIW] = reinterpret_cast<float(*)[kIW]>(stage);
+    float(*sy)[kIW] = reinterpret_cast<float(*)[kIW]>(stage + kIH * kIW);
+    float(*sd)[kMH][kMW] = reinterpret_cast<float(*)[kMH][kMW]>(stage);
     __shared__ float red[2][kLossThreads / 64];
     const int tid = threadIdx.x;
     const int blk = blockIdx.x;
@@ -209,7 +214,7 @@ __global__ __launch_bounds__(kLossThreads) void k_l1_dssim(LossArgs a) {
             const int r = r0 + o;
             const int gy = y0 + r, gx = x0 + c;
             if (gx >= W || gy >= H) continue;
-            const float xv = sx[r + 2 * kR][c + 2 * kR], yv = sy[r + 2 * kR][c + 2 * kR];
+            const float xv = X[(int64_t)gy * W + gx], yv = Y[(int64_t)gy * W + gx];
             const float d = xv - yv;
             l_sum += fabsf(d);
             if (a.grad) {
