@@ -155,9 +155,11 @@ __global__ __launch_bounds__(kLossThreads) void k_l1_dssim(LossArgs a) {
                 const float B1 = fmaf(mx, mx, fmaf(my, my, kC1)), B2 = sxx + syy + kC2;
                 const float iden = 1.0f / (B1 * B2);
                 const float S = A1 * A2 * iden;
-                da = dscale * (2.0f * my * (A2 - A1) * iden - S * (2.0f * mx / B1 - 2.0f * mx / B2));
-                db = dscale * (-S / B2);
-                dc = dscale * (2.0f * A1 * iden);
+                // 1/B1 = B2 iden and 1/B2 = B1 iden: one division per pixel
+                const float di = dscale * iden;
+                da = 2.0f * di * (my * (A2 - A1) - S * mx * (B2 - B1));
+                db = -di * S * B1;
+                dc = 2.0f * di * A1;
                 if (r >= kR && r < kR + kTH && c >= kR && c < kR + kTW) s_sum += S;
             }
             sd[0][r][c] = da;
