@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kLossThreads) void k_l1_dssim(LossArgs a) {
     //      thread (column, run) forms kV1 consecutive rows
     const float dscale = -a.lambda / (3.0f * (float)plane);   // dL/dS: L holds lambda (1 - mean S)
     float s_sum = 0.0f;
-    constexpr int kV1 = 7, kV1Runs = (kMH + kV1 - 1) / kV1;
+    constexpr int kV1 = 5, kV1Runs = (kMH + kV1 - 1) / kV1;
     static_assert(kMW * kV1Runs <= kLossThreads, "one pass");
     if (tid < kMW * kV1Runs) {
         const int c = tid % kMW, r0 = (tid / kMW) * kV1;
