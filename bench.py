@@ -462,9 +462,9 @@ def next_rows(C: Ctx, ts) -> dict:
                                      "estimates": [round(float(x), 5) for x in est.est.reshape(-1).tolist()]}}
 
 
-def train_step_ms(C: Ctx, sc, cfg, steps: int, warm: int, timer: bool, copy_gbs: float, label: str) -> dict:
+def train_step_ms(C: Ctx, sc, cfg, steps: int, warm: int, timer: bool, copy_gbs: float, label: str, **kw) -> dict:
     torch, N = C.torch, C.N
-    ts = make_train(C, sc, cfg, fused=True)
+    ts = make_train(C, sc, cfg, fused=True, **kw)
     ts.size_capacity(1.25)
     out = {"workload": label}
     with torch.cuda.stream(C.stream):
@@ -748,6 +748,12 @@ def main():
             C, sc1, R.RasterConfig(), args.steps, args.warmup, False, copy["gbs"],
             "300000 Gaussians SH3, 1600x1067, training step (forward + L1 + backward + Adam)")
         del ts1, sc1
+        torch.cuda.empty_cache()
+        extras["train_1m_1080p_l1_dssim"], tsd = train_step_ms(
+            C, sc, R.RasterConfig(), args.steps, args.warmup, False, copy["gbs"],
+            f"{sc.n} Gaussians SH{sc.sh_degree}, {cam.width}x{cam.height}, training step with the full image loss "
+            "(forward + (1 - 0.3) L1 + 0.3 D-SSIM + backward + Adam)", loss="l1_dssim", ssim_lambda=0.3)
+        del tsd
         torch.cuda.empty_cache()
         log("building the 3M-Gaussian 4-view scene")
         sc4 = synth.make_scene(4)
