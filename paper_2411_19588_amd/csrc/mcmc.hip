@@ -316,8 +316,26 @@ __global__ __launch_bounds__(kBlock) void k_mc_relayout(McPlanes a, McPlanes b, 
             to = b.opacity;
         }
     }
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-        to[i] = from[i];
+    const int64_t stride = (int64_t)gridDim.x * kBlock, t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int64_t done = 0;
+    if ((reinterpret_cast<uintptr_t>(from) & 15) == 0) {   // 16-byte loads (and stores where aligned)
+        const int64_t n4 = n / 4;
+        const float4* f4 = reinterpret_cast<const float4*>(from);
+        if ((reinterpret_cast<uintptr_t>(to) & 15) == 0) {
+            float4* d4 = reinterpret_cast<float4*>(to);
+            for (int64_t i = t0; i < n4; i += stride) d4[i] = f4[i];
+        } else {
+            for (int64_t i = t0; i < n4; i += stride) {
+                const float4 v = f4[i];
+                to[4 * i] = v.x;
+                to[4 * i + 1] = v.y;
+                to[4 * i + 2] = v.z;
+                to[4 * i + 3] = v.w;
+            }
+        }
+        done = 4 * n4;
+    }
+    for (int64_t i = done + t0; i < n; i += stride) to[i] = from[i];
 }
 
 __global__ __launch_bounds__(kBlock) void k_mc_noise(float* means, const float* __restrict__ quats,
