@@ -183,6 +183,27 @@ def traffic_for(kernel: str):
         return None
 
 
+def counters_measured():
+    """LDS bank-conflict ratio, active lanes and VALU issue share per kernel from the committed
+    rocprofv3 counter run of the default workload (profiles/lds_valu_counters.json); a kernel whose
+    source has changed since is left out, and the whole record is null without the file."""
+    p = os.path.join(ROOT, "profiles", "lds_valu_counters.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        t = json.load(open(p))
+        out = {}
+        for k, ent in t.items():
+            if k.startswith("_"):
+                continue
+            src = os.path.join(ROOT, "paper_2411_19588_amd", "csrc", ent["source"])
+            if source_hash(src) == ent["source_sha"]:
+                out[k] = {x: ent[x] for x in ("lds_bank_conflict_ratio", "active_lanes", "valu_issue_share")}
+        return out
+    except Exception:
+        return None
+
+
 KERNELS = ["project_fwd", "depth_sort_hist", "depth_sort_scan", "depth_sort_scatter",
            "count_scan", "emit", "tile_sort_hist", "tile_sort_scan", "tile_sort_scatter", "commit", "composite_fwd",
            "zero_grad2d", "composite_bwd", "medium_reduce", "project_bwd", "adam_sh", "sh_views"]
@@ -831,6 +852,7 @@ def main():
         "batched": batched,
         "copy_ceiling": copy,
         "composite_hbm": composite_hbm(info),
+        "counters": counters_measured() if args.config == 2 else None,
         "kernels": info["kernels"],
         "extras": extras,
     }
