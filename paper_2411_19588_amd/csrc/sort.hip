@@ -15,12 +15,14 @@
 // digits use 256 counters, 9-bit digits 512 (two per thread in the block scans), so
 // 17-bit tile ids (up to 131071 tiles) take two passes instead of three.
 //   3. k_scatter:   each partition turns the row totals into digit bases, then
-//                   re-reads its range tile by tile (2048 keys), ranks keys
-//                   stably inside each wave (lanes that share a digit are found by
-//                   intersecting one ballot per digit bit), combines the four
-//                   waves through LDS, reorders the tile in LDS by digit and
-//                   writes it out in digit runs (coalesced).  The next tile's keys
-//                   and values are loaded while the current one is written out.
+//                   re-reads its range tile by tile, ranks keys stably inside each
+//                   wave (lanes that share a digit are found by intersecting one
+//                   ballot per digit bit; the digit width is a template argument),
+//                   combines the four waves through LDS, reorders the tile in LDS
+//                   by digit and writes it out in digit runs (coalesced).  The next
+//                   tile's keys and values are loaded while the current one is
+//                   written out.  A radix tile holds 2048 keys, or 4096 for sorts of
+//                   kLargeSortKeys keys and more (fewer, longer digit runs per tile).
 #include <algorithm>
 #include <string>
 
