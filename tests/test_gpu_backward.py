@@ -239,3 +239,24 @@ def test_l1_loss_and_adam(oracle_mod):
     sc, oc = O.activate(opt.group("log_scales").param.cpu().numpy(), opt.group("logits").param.cpu().numpy())
     np.testing.assert_allclose(opt.group("log_scales").activated.cpu().numpy(), sc, rtol=2e-6)
     np.testing.assert_allclose(opt.group("logits").activated.cpu().numpy(), oc, rtol=2e-6)
+
+
+def test_medium_gradient_deterministic_across_backwards():
+    """The medium reduction is deterministic: each view's 16 workgroups sum fixed slices of its
+    tiles' partials in a fixed order, and the last one to finish adds the slice sums in slice
+    order.  Three backward calls on one forward of a multi-tile, three-view scene give bitwise
+    equal medium gradients (the Gaussians' gradients, accumulated by atomics, may differ in the
+    last bits), and the counters that pick the last slice start at zero on every call."""
+    sc = synth.make_scene(3, n=3000, n_views=3, view_sizes=[(203, 141), (96, 64), (130, 77)])
+    rast = U.make_rast(sc)
+    rgb, depth, alpha, ctx, d = U.forward(sc, rast)
+    g_rgb = torch.from_numpy(np.random.default_rng(3).normal(size=rgb.numel()).astype(np.float32)).cuda()
+    meds = []
+    for _ in range(3):
+        out = rast.backward(ctx, d["means"], d["scales"], d["quats"], d["opacity"], d["sh"], d["medium"], g_rgb)
+        torch.cuda.synchronize()
+        meds.append(out[5].cpu().numpy().copy())
+    assert np.abs(meds[0]).max() > 0.0
+    for m in meds[1:]:
+        assert np.array_equal(m, meds[0])
+    U.say(f"  medium gradient bitwise equal over 3 backwards: {meds[0].reshape(3, 9)[:, :3].tolist()}")
