@@ -176,6 +176,16 @@ __device__ __forceinline__ float swap16_add(float lo, float hi) {
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
+// The value that lane holds after wave_sum10, or -1: lanes with (lane & 3) == 0 hold one
+// total each, in an order fixed by the exchange pattern below.
+__device__ __forceinline__ int sum10_slot(int lane) {
+    const bool h2 = lane & 4, h3 = lane & 8, h4 = lane & 16, h5 = lane & 32;
+    int idx;
+    if (!h4) idx = h3 ? (h2 ? -1 : 2) : (h2 ? 1 : 0);
+    else idx = h3 ? -1 : (h2 ? 4 : 3);
+    return ((lane & 3) == 0 && idx >= 0) ? idx + (h5 ? 5 : 0) : -1;
+}
+
 // Sum 10 values over the 64 lanes.  Halving exchanges: at each step a lane keeps half of
 // its remaining values and adds the partner's copy of them (partners differ in lane bit
 // 5, 4, 3, 2), then the last quad is summed with quad permutes.  Afterwards the lanes with
@@ -201,12 +211,15 @@ __device__ __forceinline__ float wave_sum10(const float* v, int lane, int& which
     float d = (h2 ? c[1] : c[0]) + dpp_f(h2 ? c[0] : c[1], 0x141);
     d += dpp_f(d, 0x4E);   // quad_perm [2,3,0,1]
     d += dpp_f(d, 0xB1);   // quad_perm [1,0,3,2]
-    const bool h4 = lane & 16, h5 = lane & 32;
-    int idx;
-    if (!h4) idx = h3 ? (h2 ? -1 : 2) : (h2 ? 1 : 0);
-    else idx = h3 ? -1 : (h2 ? 4 : 3);
-    which = ((lane & 3) == 0 && idx >= 0) ? idx + (h5 ? 5 : 0) : -1;
+    which = sum10_slot(lane);
     return d;
+}
+
+// Scale of the wave sum that a lane holds in the adjoint: ln 2 for the five geometry terms
+// (accumulated without it), 1 otherwise; a function of the lane alone, set up once.
+__device__ __forceinline__ float adjoint_scale(int lane) {
+    const int which = sum10_slot(lane);
+    return (which >= 0 && which < 5) ? kLn2 : 1.0f;
 }
 
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
@@ -497,10 +510,10 @@ __global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_fwd
     }
 }
 
-// Adjoint of the blend of one splat for a lane's pixels, walking back to front: adds the
-// lane's terms to g10 = d/d(m_x, m_y, A, B, C, o, r, g, b, depth), the first five without
-// their common factor ln 2 (applied once to the wave's sums).  Returns whether any of the
-// lane's pixels was reached by the splat with alpha >= alpha_min.
+// Adjoint of the blend of one splat for a lane's pixels, walking back to front: writes the
+// lane's terms to g10 = d/d(m_x, m_y, A, B, C, o, r, g, b, depth), which must be zero on
+// entry, the first five without their common factor ln 2 (applied once to the wave's sums).
+// Returns whether any of the lane's pixels was reached by the splat with alpha >= alpha_min.
 template <int PPL, int R>
 __device__ __forceinline__ bool blend_adjoint(const Splat& s, float fpx, float fpy0, uint32_t idx,
                                               const uint32_t* my_last, float* T, float* S, const float* gC0,
@@ -540,10 +553,11 @@ __device__ __forceinline__ bool blend_adjoint(const Splat& s, float fpx, float f
         g10[5] = fmaf(dalpha, ev, g10[5]);
         const float dpw = dalpha * araw;   // d/d(exponent), without ln 2
         if constexpr (kLaneSums) {
+            // the first pixel's terms are taken as they are (an add to zero is not free)
             const float qd = dpw * dy;
-            P += dpw;
-            Q += qd;
-            U = fmaf(qd, dy, U);
+            P = k == 0 ? dpw : P + dpw;
+            Q = k == 0 ? qd : Q + qd;
+            U = k == 0 ? qd * dy : fmaf(qd, dy, U);
         } else {
             const float pdx = dpw * ct.dx, pdy = dpw * dy;
             g10[2] = fmaf(pdx, ct.dx, g10[2]);
@@ -557,7 +571,7 @@ __device__ __forceinline__ bool blend_adjoint(const Splat& s, float fpx, float f
         const float X = ct.dx * P;   // sum over the lane's pixels of dpw dx
         g10[2] = fmaf(ct.dx, X, g10[2]);
         g10[3] = fmaf(ct.dx, Q, g10[3]);
-        g10[4] += U;
+        g10[4] = U;
         g10[0] = fmaf(nA2, X, fmaf(nB, Q, g10[0]));
         g10[1] = fmaf(nB, X, fmaf(nC2, Q, g10[1]));
     }
@@ -566,10 +580,9 @@ __device__ __forceinline__ bool blend_adjoint(const Splat& s, float fpx, float f
 
 // Wave sum of a lane's 10 adjoint terms; the lanes that hold a total add it to the splat's
 // 2D gradient (entry e) with one atomic each.
-__device__ __forceinline__ void flush_adjoint(const float* g10, int lane, float* grad2d, uint32_t e) {
+__device__ __forceinline__ void flush_adjoint(const float* g10, int lane, float scale, float* grad2d, uint32_t e) {
     int which;
-    float t = wave_sum10(g10, lane, which);
-    if (which >= 0 && which < 5) t *= kLn2;
+    const float t = wave_sum10(g10, lane, which) * scale;
     if (which >= 0) unsafeAtomicAdd(grad2d + (size_t)e * kGrad2D + which, t);
 }
 
@@ -577,13 +590,13 @@ __device__ __forceinline__ void flush_adjoint(const float* g10, int lane, float*
 // per term into the splat's 2D gradient.
 template <int PPL, int R>
 __device__ __forceinline__ void adjoint_scalar(const BwdArgs& a, const Splat& s, uint32_t chunk, uint32_t b0, int j,
-                                               float fpx, float fpy0, int lane, const uint32_t* my_last, float* T,
-                                               float* Sx, const float* gC0, const float* gC1, const float* gC2,
-                                               const float* gD, const float* gW) {
+                                               float fpx, float fpy0, int lane, float scale, const uint32_t* my_last,
+                                               float* T, float* Sx, const float* gC0, const float* gC1,
+                                               const float* gC2, const float* gD, const float* gW) {
     float g10[10] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     const bool any = blend_adjoint<PPL, R>(s, fpx, fpy0, b0 + (uint32_t)j, my_last, T, Sx, gC0, gC1, gC2, gD, gW,
                                            g10, a.amin, a.amax);
-    if (__any(any)) flush_adjoint(g10, lane, a.grad2d, lane_index(chunk, (uint32_t)j));
+    if (__any(any)) flush_adjoint(g10, lane, scale, a.grad2d, lane_index(chunk, (uint32_t)j));
 }
 
 template <int TW, int TH, int PPL, int BATCH, bool SCALAR, bool PERSISTENT>
@@ -601,6 +614,7 @@ __global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_bwd
     __shared__ uint32_t s_tile;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ox = (wave % S::NWX) * S::SW, oy = (wave / S::NWX) * S::SH;
+    const float scale = adjoint_scale(lane);
     if (guard_set(a.guard)) return;   // the forward was truncated: no gradient (uniform exit)
     for (uint32_t iter = 0;; ++iter) {
         const uint32_t tile = fetch_tile<NW, PERSISTENT>(a.queue, a.order, a.tiles, iter, &s_tile);
@@ -680,7 +694,9 @@ __global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_bwd
             }
         }
         // ---- medium partial sums of this tile, and the furthest list position any pixel reached
-        const uint32_t wave_last = wave_max_u32(lane_last);
+        // the butterfly leaves the maximum in every lane; reading it into a scalar register makes
+        // the walk's bounds and list positions scalar values (no per-splat vector index arithmetic)
+        const uint32_t wave_last = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_max_u32(lane_last));
         uint32_t block_last = wave_last;
         {
             int which;
@@ -700,6 +716,7 @@ __global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_bwd
                 block_last = 0;
 #pragma unroll
                 for (int w = 0; w < NW; ++w) block_last = max(block_last, s_last[w]);
+                block_last = (uint32_t)__builtin_amdgcn_readfirstlane((int)block_last);
             }
         }
         // ---- reverse walk over the phases' ranges, last phase first
@@ -719,21 +736,21 @@ __global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_bwd
                         splat_ready(p1);
                         const Splat q0 = load_splat_scalar(a.rec, lane_index(chunk, (uint32_t)max(j - 2, 0)));
                         const Splat q1 = load_splat_scalar(a.rec, lane_index(chunk, (uint32_t)max(j - 3, 0)));
-                        adjoint_scalar<PPL, R>(a, p0, chunk, b0, j, fpx, fpy0, lane, my_last, T, Sx, gC0, gC1, gC2,
-                                               gD, gW);
+                        adjoint_scalar<PPL, R>(a, p0, chunk, b0, j, fpx, fpy0, lane, scale, my_last, T, Sx, gC0, gC1,
+                                               gC2, gD, gW);
                         if (j >= 1)
-                            adjoint_scalar<PPL, R>(a, p1, chunk, b0, j - 1, fpx, fpy0, lane, my_last, T, Sx, gC0, gC1,
-                                                   gC2, gD, gW);
+                            adjoint_scalar<PPL, R>(a, p1, chunk, b0, j - 1, fpx, fpy0, lane, scale, my_last, T, Sx,
+                                                   gC0, gC1, gC2, gD, gW);
                         splat_ready(q0);
                         splat_ready(q1);
                         p0 = load_splat_scalar(a.rec, lane_index(chunk, (uint32_t)max(j - 4, 0)));
                         p1 = load_splat_scalar(a.rec, lane_index(chunk, (uint32_t)max(j - 5, 0)));
                         if (j >= 2)
-                            adjoint_scalar<PPL, R>(a, q0, chunk, b0, j - 2, fpx, fpy0, lane, my_last, T, Sx, gC0, gC1,
-                                                   gC2, gD, gW);
+                            adjoint_scalar<PPL, R>(a, q0, chunk, b0, j - 2, fpx, fpy0, lane, scale, my_last, T, Sx,
+                                                   gC0, gC1, gC2, gD, gW);
                         if (j >= 3)
-                            adjoint_scalar<PPL, R>(a, q1, chunk, b0, j - 3, fpx, fpy0, lane, my_last, T, Sx, gC0, gC1,
-                                                   gC2, gD, gW);
+                            adjoint_scalar<PPL, R>(a, q1, chunk, b0, j - 3, fpx, fpy0, lane, scale, my_last, T, Sx,
+                                                   gC0, gC1, gC2, gD, gW);
                     }
                     b_end = b0;
                 }
@@ -768,13 +785,12 @@ __global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_bwd
                                                         g10, a.amin, a.amax);
                         }
                         if (NW == 1) {
-                            if (__any(any)) flush_adjoint(g10, lane, a.grad2d, se[j]);
+                            if (__any(any)) flush_adjoint(g10, lane, scale, a.grad2d, se[j]);
                         } else {
                             const int slot = j & (RED - 1);
                             if (__any(any)) {
                                 int which;
-                                float t = wave_sum10(g10, lane, which);
-                                if (which >= 0 && which < 5) t *= kLn2;
+                                const float t = wave_sum10(g10, lane, which) * scale;
                                 if (which >= 0) red[wave][slot][which] = t;
                             } else if (lane < kGrad2D) {
                                 red[wave][slot][lane] = 0.0f;
