@@ -33,12 +33,12 @@ constexpr int kDownItems = kScanChunk / kBlock;   // consecutive ranks per threa
 // Whether the splat `r` may reach alpha >= alpha_min at a pixel centre of tile (tx, ty): false
 // only when the maximum of the (concave) exponent A dx^2 + B dx dy + C dy^2 over the
 // rectangle spanned by the tile's pixel centres, plus a rounding margin, is below
-// log2(alpha_min) - log2(o).  The maximum is at the mean when it lies inside, else on an
-// edge, where the exponent is a 1D concave quadratic maximised at its clamped vertex.
-// Anything non-finite or degenerate keeps the pair.
+// log2(alpha_min) - log2(o), with log2 o as the record stores it.  The maximum is at the
+// mean when it lies inside, else on an edge, where the exponent is a 1D concave quadratic
+// maximised at its clamped vertex.  Anything non-finite or degenerate keeps the pair.
 __device__ __forceinline__ bool tile_may_contribute(const float4& ra, const float2& rb, const ViewInfo& vi,
                                                     uint32_t tx, uint32_t ty, const CullArgs& cu) {
-    const float A = ra.z, B = ra.w, C = rb.x, o = rb.y;
+    const float A = ra.z, B = ra.w, C = rb.x, lo = rb.y;
     if (!(A < 0.0f && C < 0.0f)) return true;
     const float x0 = (float)(tx * (uint32_t)cu.tile_w) + 0.5f;
     const float x1 = (float)min((tx + 1) * (uint32_t)cu.tile_w, (uint32_t)vi.width) - 0.5f;
@@ -58,7 +58,7 @@ __device__ __forceinline__ bool tile_may_contribute(const float4& ra, const floa
     }
     const float X = fmaxf(-xl, xr), Y = fmaxf(-yl, yr);
     const float mag = -A * X * X + fabsf(B) * X * Y - C * Y * Y;
-    const float limit = cu.log2_amin - log2f(o);
+    const float limit = cu.log2_amin - lo;
     return !(best + 4e-6f * mag + 1e-4f < limit);
 }
 

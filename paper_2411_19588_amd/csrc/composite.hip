@@ -92,23 +92,25 @@ struct BwdArgs {
     Guard guard;
 };
 
-// Splat fields used by the blend, in registers (scalar registers in scalar-fetch mode).
+// Splat fields used by the blend, in registers (scalar registers in scalar-fetch mode):
+// lo = log2 of the opacity, io = its reciprocal (read by the adjoint only).
 struct Splat {
-    float mx, my, A, B, C, o, r, g, b, d;
+    float mx, my, A, B, C, lo, r, g, b, d, io;
 };
 
-// alpha exponent of one splat at one pixel: log2 of exp(-q/2), with
+// alpha exponent of one splat at one pixel: log2 of o exp(-q/2), with
 // q = (p - m)^T Q (p - m) and the conic pre-scaled by -log2(e)/2 (A, C) and -log2(e) (B),
-// evaluated as A dx^2 + dy (B dx + C dy) so that a lane's pixels in one column share the
-// dx terms.  Forward and adjoint, and every launch shape, evaluate this same sequence
-// of (dx, dy), so they take identical decisions.
+// evaluated as (A dx^2 + log2 o) + dy (B dx + C dy) so that a lane's pixels in one column
+// share the dx terms (and alpha is exp2 of it, with no product by o).  Forward and adjoint,
+// and every launch shape, evaluate this same sequence of (dx, dy), so they take identical
+// decisions.
 struct ColTerms {
     float dx, bdx, adx2;
 };
 
 __device__ __forceinline__ ColTerms col_terms(const Splat& s, float fpx) {
     const float dx = fpx - s.mx;
-    return {dx, s.B * dx, (s.A * dx) * dx};
+    return {dx, s.B * dx, fmaf(s.A * dx, dx, s.lo)};
 }
 
 __device__ __forceinline__ float splat_power(const Splat& s, const ColTerms& c, float fpy, float& dy) {
@@ -122,20 +124,27 @@ typedef __attribute__((address_space(4))) const float ConstF;
 // are from the constant address space, which the compiler emits as scalar loads.
 __device__ __forceinline__ Splat load_splat_scalar(const Record* rec, uint32_t e) {
     const ConstF* p = (const ConstF*)(rec + e);
-    return {p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7], p[8], p[9]};
+    return {p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7], p[8], p[9], p[10]};
 }
 
 // Wait until a scalar-loaded splat has arrived (scalar loads complete out of order, so
 // the wait is placed here, before the next record's load is issued).
 __device__ __forceinline__ void splat_ready(const Splat& s) {
-    asm volatile("" ::"s"(s.mx), "s"(s.my), "s"(s.A), "s"(s.B), "s"(s.C), "s"(s.o), "s"(s.r), "s"(s.g), "s"(s.b),
-                 "s"(s.d));
+    asm volatile("" ::"s"(s.mx), "s"(s.my), "s"(s.A), "s"(s.B), "s"(s.C), "s"(s.lo), "s"(s.r), "s"(s.g), "s"(s.b),
+                 "s"(s.d), "s"(s.io));
 }
 
+// A record staged in LDS: the forward stages (b, depth) of the third float4 and leaves io
+// at 0 (it blends without it), the adjoint stages (b, depth, 1/o).
 __device__ __forceinline__ Splat splat_from_lds(const float4* sa, const float4* sb, const float2* sc, int j) {
     const float4 ra = sa[j], rb = sb[j];
     const float2 rc = sc[j];
-    return {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w, rc.x, rc.y};
+    return {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w, rc.x, rc.y, 0.0f};
+}
+
+__device__ __forceinline__ Splat splat_from_lds(const float4* sa, const float4* sb, const float4* sc, int j) {
+    const float4 ra = sa[j], rb = sb[j], rc = sc[j];
+    return {ra.x, ra.y, ra.z, ra.w, rb.x, rb.y, rb.z, rb.w, rc.x, rc.y, rc.z};
 }
 
 __device__ __forceinline__ int find_view(const ViewInfo* vt, int views, uint32_t tile) {
@@ -319,7 +328,7 @@ __device__ __forceinline__ void blend(const Splat& s, float fpx, float fpy0, uin
     for (int k = 0; k < PPL; ++k) {
         float dy;
         const float pw = splat_power(s, ct, fpy0 + (float)(k * R), dy);
-        const float alpha = fminf(amax, s.o * __builtin_amdgcn_exp2f(pw));
+        const float alpha = fminf(amax, __builtin_amdgcn_exp2f(pw));
         if (alpha >= amin) {
             const float Tn = T[k] * (1.0f - alpha);
             const bool use = Tn >= tmin;
@@ -523,7 +532,8 @@ __device__ __forceinline__ bool blend_adjoint(const Splat& s, float fpx, float f
     const float nA2 = -2.0f * s.A, nB = -s.B, nC2 = -2.0f * s.C;
     // With several pixels per lane, the exponent's derivatives are gathered per lane as
     // P = sum dpw, Q = sum dpw dy, U = sum dpw dy^2 (dx is the lane's column, the same for all
-    // its pixels) and turned into the five geometry terms once per splat.
+    // its pixels) and turned into the five geometry terms once per splat.  The opacity term
+    // is sum dalpha exp2(q') = P / o, with dpw = dalpha * alpha_raw and alpha_raw = o exp2(q').
     constexpr bool kLaneSums = PPL >= 2;
     float P = 0.0f, Q = 0.0f, U = 0.0f;
     bool any = false;
@@ -533,8 +543,7 @@ __device__ __forceinline__ bool blend_adjoint(const Splat& s, float fpx, float f
     for (int k = 0; k < PPL; ++k) {
         float dy;
         const float pw = splat_power(s, ct, fpy0 + (float)(k * R), dy);
-        const float ev = __builtin_amdgcn_exp2f(pw);
-        const float araw = s.o * ev;
+        const float araw = __builtin_amdgcn_exp2f(pw);
         const float alpha = fminf(amax, araw);
         const bool act = idx < my_last[k] && alpha >= amin;
         any = any || act;
@@ -550,7 +559,6 @@ __device__ __forceinline__ bool blend_adjoint(const Splat& s, float fpx, float f
         g10[7] = fmaf(gC1[k], w, g10[7]);
         g10[8] = fmaf(gC2[k], w, g10[8]);
         g10[9] = fmaf(gD[k], w, g10[9]);
-        g10[5] = fmaf(dalpha, ev, g10[5]);
         const float dpw = dalpha * araw;   // d/d(exponent), without ln 2
         if constexpr (kLaneSums) {
             // the first pixel's terms are taken as they are (an add to zero is not free)
@@ -560,6 +568,7 @@ __device__ __forceinline__ bool blend_adjoint(const Splat& s, float fpx, float f
             U = k == 0 ? qd * dy : fmaf(qd, dy, U);
         } else {
             const float pdx = dpw * ct.dx, pdy = dpw * dy;
+            g10[5] = fmaf(dpw, s.io, g10[5]);
             g10[2] = fmaf(pdx, ct.dx, g10[2]);
             g10[3] = fmaf(pdx, dy, g10[3]);
             g10[4] = fmaf(pdy, dy, g10[4]);
@@ -569,6 +578,7 @@ __device__ __forceinline__ bool blend_adjoint(const Splat& s, float fpx, float f
     }
     if constexpr (kLaneSums) {
         const float X = ct.dx * P;   // sum over the lane's pixels of dpw dx
+        g10[5] = P * s.io;
         g10[2] = fmaf(ct.dx, X, g10[2]);
         g10[3] = fmaf(ct.dx, Q, g10[3]);
         g10[4] = U;
@@ -606,7 +616,7 @@ __global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_bwd
     constexpr int LB = SCALAR ? 1 : BATCH;
     constexpr int RED = (!SCALAR && NW > 1) ? 64 : 1;   // records per cross-wave reduction
     __shared__ float4 sa[LB], sb[LB];
-    __shared__ float2 sc[LB];
+    __shared__ float4 sc[LB];
     __shared__ uint32_t se[LB];
     __shared__ float red[NW][RED][kGrad2D];
     __shared__ float s_med[NW][9];
@@ -770,7 +780,7 @@ __global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_bwd
                             const Record r = a.rec[e];
                             sa[i] = r.a;
                             sb[i] = r.b;
-                            sc[i] = make_float2(r.c.x, r.c.y);
+                            sc[i] = r.c;
                             se[i] = e;
                         }
                     }
@@ -1024,10 +1034,10 @@ __global__ __launch_bounds__(TW* TH) void k_forward_stats(const ViewInfo* __rest
             const uint2 rg = ranges[(size_t)ph * n_tiles + tile];
             for (uint32_t i = rg.x; i < min(rg.y, last); ++i) {
                 const Record r = rec[vals[i]];
-                const Splat sp{r.a.x, r.a.y, r.a.z, r.a.w, r.b.x, r.b.y, r.b.z, r.b.w, r.c.x, r.c.y};
+                const Splat sp{r.a.x, r.a.y, r.a.z, r.a.w, r.b.x, r.b.y, r.b.z, r.b.w, r.c.x, r.c.y, r.c.z};
                 float dy;
                 const float pw = splat_power(sp, col_terms(sp, fpx), fpy, dy);
-                blended += fminf(amax, sp.o * __builtin_amdgcn_exp2f(pw)) >= amin;
+                blended += fminf(amax, __builtin_amdgcn_exp2f(pw)) >= amin;
                 ++walked;
             }
         }

@@ -50,9 +50,10 @@ struct ViewTable {
 };
 
 // Projected splat, one per (view, Gaussian): 48 bytes, read as three float4.
-//   a = (m_x, m_y, A, B)   b = (C, opacity, r, g)   c = (b, depth, -, -)
-// with the conic pre-scaled so that alpha = o * exp2(A dx^2 + B dx dy + C dy^2),
-// A = -log2(e)/2 Qxx, B = -log2(e) Qxy, C = -log2(e)/2 Qyy.
+//   a = (m_x, m_y, A, B)   b = (C, log2 o, r, g)   c = (b, depth, 1/o, -)
+// with the conic pre-scaled so that alpha = exp2(A dx^2 + B dx dy + C dy^2 + log2 o),
+// A = -log2(e)/2 Qxx, B = -log2(e) Qxy, C = -log2(e)/2 Qyy.  An opacity o <= 0 stores
+// log2 o = -inf and 1/o = 0: the splat never blends.
 struct __align__(16) Record {
     float4 a, b, c;
 };

@@ -277,8 +277,9 @@ __global__ __launch_bounds__(kBlock) void k_project_fwd(gs_gaussians g, int32_t 
             }
             Record r;
             r.a = make_float4(P.px, P.py, A, B);
-            r.b = make_float4(C, op, col[0], col[1]);
-            r.c = make_float4(col[2], P.t[2], 0.0f, 0.0f);
+            const bool pos = op > 0.0f;
+            r.b = make_float4(C, pos ? log2f(op) : -INFINITY, col[0], col[1]);
+            r.c = make_float4(col[2], P.t[2], pos ? 1.0f / op : 0.0f, 0.0f);
             rec[e] = r;
         }
         counts[e] = cnt;
