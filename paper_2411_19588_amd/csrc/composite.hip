@@ -330,7 +330,7 @@ __device__ __forceinline__ void blend(const Splat& s, float fpx, float fpy0, uin
         const float pw = splat_power(s, ct, fpy0 + (float)(k * R), dy);
         const float alpha = fminf(amax, __builtin_amdgcn_exp2f(pw));
         if (alpha >= amin) {
-            const float Tn = T[k] * (1.0f - alpha);
+            const float Tn = fmaf(-alpha, T[k], T[k]);   // T (1 - alpha), rounded once
             const bool use = Tn >= tmin;
             const float w = use ? alpha * T[k] : 0.0f;
             C0[k] = fmaf(w, s.r, C0[k]);
@@ -538,7 +538,8 @@ __device__ __forceinline__ bool blend_adjoint(const Splat& s, float fpx, float f
     float P = 0.0f, Q = 0.0f, U = 0.0f;
     bool any = false;
     // Branch-free over the lane's pixels: a pixel past its last contributor, or where the splat's
-    // alpha is below alpha_min, takes w = dalpha = 0 (its sums gain exact zeros) and keeps T.
+    // alpha is below alpha_min, takes alpha = 0 and a raw alpha of 0, so that T (divided by
+    // exactly 1) and S stay as they are and every term it adds is an exact zero.
 #pragma unroll
     for (int k = 0; k < PPL; ++k) {
         float dy;
@@ -547,19 +548,21 @@ __device__ __forceinline__ bool blend_adjoint(const Splat& s, float fpx, float f
         const float alpha = fminf(amax, araw);
         const bool act = idx < my_last[k] && alpha >= amin;
         any = any || act;
-        const float rom = __builtin_amdgcn_rcpf(1.0f - alpha);
-        const float Ti = T[k] * rom;
-        const float w = act ? alpha * Ti : 0.0f;
-        const float gf = fmaf(gC0[k], s.r, fmaf(gC1[k], s.g, fmaf(gC2[k], s.b, fmaf(gD[k], s.d, gW[k]))));
+        const float ae = act ? alpha : 0.0f;
         // a clamped alpha does not depend on the opacity or the exponent
-        const float dalpha = (act && araw <= amax) ? fmaf(Ti, gf, -S[k] * rom) : 0.0f;
+        const float re = (act && araw <= amax) ? araw : 0.0f;
+        const float rom = __builtin_amdgcn_rcpf(1.0f - ae);
+        const float Ti = T[k] * rom;
+        const float w = ae * Ti;
+        const float gf = fmaf(gC0[k], s.r, fmaf(gC1[k], s.g, fmaf(gC2[k], s.b, fmaf(gD[k], s.d, gW[k]))));
+        const float dalpha = fmaf(Ti, gf, -S[k] * rom);
         S[k] = fmaf(gf, w, S[k]);
-        T[k] = act ? Ti : T[k];
+        T[k] = Ti;
         g10[6] = fmaf(gC0[k], w, g10[6]);
         g10[7] = fmaf(gC1[k], w, g10[7]);
         g10[8] = fmaf(gC2[k], w, g10[8]);
         g10[9] = fmaf(gD[k], w, g10[9]);
-        const float dpw = dalpha * araw;   // d/d(exponent), without ln 2
+        const float dpw = dalpha * re;   // d/d(exponent), without ln 2
         if constexpr (kLaneSums) {
             // the first pixel's terms are taken as they are (an add to zero is not free)
             const float qd = dpw * dy;
