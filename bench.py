@@ -92,6 +92,9 @@ def parse():
     ap.add_argument("--phase-growth", type=int, default=0,
                     help="log2 of the later depth phases' growth (0 = library default, 4x)")
     ap.add_argument("--eager", action="store_true", help="time eager launches only (no HIP graph replay)")
+    ap.add_argument("--all-phases", action="store_true",
+                    help="run every depth phase of the schedule (default: only the leading phases that a full "
+                         "render of the fixed scene needs, checked on the device at every step)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 24-view batched-vs-per-view forward+backward comparison")
     ap.add_argument("--no-extras", action="store_true",
@@ -353,6 +356,11 @@ def main_record(C: Ctx, sc, cfg, copy_gbs: float):
     log("sizing the pair list")
     need = ts.size_capacity(1.25)
     log(f"stored pairs {need}, capacity {ts.max_pairs}")
+    # the scene is fixed while timed (learning rates 0): run only the leading depth phases that a
+    # render with every phase needed; a step that would need more sets GS_STATUS_INCOMPLETE, is not
+    # applied, and ends the run below
+    limit = 0 if args.all_phases or args.train else ts.fit_phase_limit()
+    log(f"depth phases run: {limit or 'all'}")
     C.sync()
     with torch.cuda.stream(C.stream):
         log(f"eager warmup {args.warmup}")
@@ -380,8 +388,9 @@ def main_record(C: Ctx, sc, cfg, copy_gbs: float):
         ms = time_graph(C, ts.enqueue, args.steps, args.warmup, marker=3)
         log(f"graph: {ms:.3f} ms/step")
     st, K = ts.status(C.stream)
-    if st & N.GS_STATUS_PAIR_OVERFLOW or ts.skipped():
-        raise SystemExit(f"pair capacity overflowed during the timed steps ({K} > {ts.max_pairs})")
+    if st & N.GS_STATUS_TRUNCATED or ts.skipped():
+        raise SystemExit(f"a timed step rendered a truncated image (status {st}, skip flag {ts.skipped()}; "
+                         f"{K} stored pairs, capacity {ts.max_pairs})")
     stats = forward_stats(C, ts)
     _, _, rng = ts.rast.export_keys(R.ForwardContext(ts.saved, ts.max_pairs, ts.n, sc.sh_degree), C.stream)
     rng = rng.to(torch.int64)
@@ -401,7 +410,7 @@ def main_record(C: Ctx, sc, cfg, copy_gbs: float):
         f"E/pixel {E / P:.1f}, blended/pixel {Cb / P:.1f}, live pairs {K_live}, per phase {phase_pairs}")
     table = kernel_table(kernels, args.steps, sc, K_live, P, tiles, args.fused_adam, E, Cb, copy_gbs)
     info = dict(ts=ts, ms=ms, eager_ms=eager_ms, kernels=table, K=K, K_full=K_full, K_live=K_live, E=E, Cb=Cb,
-                phases=phases, shift=shift, phase_pairs=phase_pairs, P=P, tiles=tiles)
+                phases=phases, shift=shift, phase_pairs=phase_pairs, P=P, tiles=tiles, phase_limit=limit)
     return info
 
 
@@ -442,6 +451,9 @@ def composite_hbm(info: dict) -> dict:
 
 def forward_only(C: Ctx, ts, steps: int, warm: int, label: str) -> dict:
     ms = time_graph(C, ts._forward, steps, warm)
+    st, _ = ts.status(C.stream)
+    if st & C.N.GS_STATUS_TRUNCATED:
+        raise SystemExit(f"{label}: a timed forward rendered a truncated image (status {st})")
     P = ts.rast.total_pixels
     w, h = ts.rast.sizes[0]
     log(f"forward only {label}: {ms:.3f} ms, {P / (ms * 1e-3) / 1e6:.0f} Mpix/s")
@@ -487,6 +499,9 @@ def train_step_ms(C: Ctx, sc, cfg, steps: int, warm: int, timer: bool, copy_gbs:
     torch, N = C.torch, C.N
     ts = make_train(C, sc, cfg, fused=True, **kw)
     ts.size_capacity(1.25)
+    # the scene is fixed while timed: run only the leading depth phases a full render needs (the
+    # device flags any step that would need more, and such a step ends the run below)
+    limit = 0 if C.args.all_phases else ts.fit_phase_limit()
     out = {"workload": label}
     with torch.cuda.stream(C.stream):
         for _ in range(warm):
@@ -507,7 +522,7 @@ def train_step_ms(C: Ctx, sc, cfg, steps: int, warm: int, timer: bool, copy_gbs:
         raise SystemExit(f"{label}: status {st}")
     P = ts.rast.total_pixels
     out.update(ms_per_step=round(ms, 4), mpix_s=round(P / (ms * 1e-3) / 1e6, 1), pairs_stored=int(K),
-               schedule=list(ts.rast.schedule(ts.n)))
+               schedule=list(ts.rast.schedule(ts.n)), phase_limit=limit)
     if timer:
         stats = forward_stats(C, ts)
         out["kernels"] = kernel_table(kernels, steps, sc, stats[0], P, ts.rast.tile_count(), True, stats[1],
@@ -759,6 +774,8 @@ def main():
         scp = synth.make_scene(2, width=1384, height=918)
         tsp = make_train(C, scp, R.RasterConfig())
         tsp.size_capacity(1.25)
+        if not args.all_phases:
+            tsp.fit_phase_limit()
         fp = forward_only(C, tsp, args.steps, args.warmup, f"{scp.n} Gaussians SH3, 1384x918 (the paper's TableDB "
                                                            "view size; synthetic scene)")
         fp["paper"] = PAPER_FPS
@@ -838,6 +855,7 @@ def main():
                    "persistent": bool(args.persistent), "pixels_per_lane": args.ppl, "record_fetch": args.fetch,
                    "phases": info["phases"], "phase0_shift": info["shift"],
                    "phase_growth": args.phase_growth or 2,
+                   "phase_limit": info["phase_limit"],
                    "mode": "eager" if args.eager else "hip_graph",
                    "learning_rates": "paper's (scene changes while timed)" if args.train else
                    "0 (Adam reads and writes every byte; the scene stays fixed)",

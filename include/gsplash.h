@@ -20,10 +20,12 @@
  *     gs_l1_dssim_loss_noalloc.
  *   - Every compute call only enqueues work on `stream` (a hipStream_t) and
  *     never synchronises the host, so a forward/backward sequence can be
- *     captured into a HIP graph.  gs_read_status is the only synchronising call.
+ *     captured into a HIP graph.  Only gs_read_status and the queries that
+ *     say so (key export, statistics, gs_phases_needed) synchronise.
  *   - Synchronous errors are returned as GS_ERR_*; nothing is enqueued when an
- *     error is returned.  Asynchronous conditions (pair-capacity overflow,
- *     non-finite inputs) are recorded in a status word inside `saved`.
+ *     error is returned.  Asynchronous conditions (pair-capacity overflow, a
+ *     forward cut short by opts.phase_limit, non-finite inputs) are recorded
+ *     in a status word inside `saved`.
  *   - Views are packed in order: view v's pixels start at pixel offset
  *     P_v = sum_{u<v} width_u * height_u.  Per-view images are planar CHW:
  *     out_rgb[3 * P_v + c * (W*H) + y * W + x]; depth and alpha are
@@ -47,6 +49,11 @@ extern "C" {
 
 #define GS_STATUS_PAIR_OVERFLOW      1u  /* more (Gaussian, tile) pairs than opts.max_pairs */
 #define GS_STATUS_NONFINITE_INPUT    2u  /* a Gaussian had a non-finite parameter (it was culled) */
+#define GS_STATUS_INCOMPLETE         4u  /* opts.phase_limit ended the forward while a tile still had a pixel
+                                            above t_min and Gaussians were left unbinned */
+/* A forward reporting either of these rendered a truncated image: the backward
+ * entry points then produce no gradient and the Adam entry points skip the step. */
+#define GS_STATUS_TRUNCATED (GS_STATUS_PAIR_OVERFLOW | GS_STATUS_INCOMPLETE)
 
 #define GS_MAX_VIEWS                64
 #define GS_MAX_PAIRS         2147483647LL /* pair indices are 31-bit */
@@ -167,7 +174,14 @@ typedef struct gs_options {
     float reg_scale;                     /* lambda_s: the loss gets lambda_s mean over the 3 n activated
                                             scale entries, so each gets lambda_s / (3 n) (the regularisers
                                             of the MCMC densification the paper adopts, Sec. Implementation) */
-    int32_t reserved2;
+    int32_t phase_limit;                 /* 0 (default): run every depth phase of the schedule; 1..8: run only
+                                            the first phase_limit of them.  If a tile still has a pixel above
+                                            t_min after the last phase run while Gaussians are left unbinned,
+                                            the forward reports GS_STATUS_INCOMPLETE (its image is then
+                                            truncated); otherwise the image equals the full schedule's bit
+                                            for bit, since the phases left out would blend nothing.  For a
+                                            caller that replays a fixed scene: gs_phases_needed gives the
+                                            limit a full forward of it needed. */
 } gs_options;
 
 /* Fill `opts` with the defaults above (phases and phase0_shift automatic, max_pairs = 1 << 24). */
@@ -203,8 +217,9 @@ int gs_workspace_query(const gs_options* opts, int64_t n, int32_t n_views, const
  *                and backscatter (0 where no Gaussian contributes), CHW per view.
  *   saved      : forward context (>= saved_bytes) used by gs_render_backward,
  *                gs_read_status and gs_export_keys.
- * Returns GS_OK or a GS_ERR_* code; capacity overflow is reported
- * asynchronously through gs_read_status (outputs are then not valid). */
+ * Returns GS_OK or a GS_ERR_* code; capacity overflow and a forward cut short
+ * by opts.phase_limit are reported asynchronously through gs_read_status
+ * (GS_STATUS_TRUNCATED: the outputs are then not valid). */
 int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_views,
                       const gs_camera* host_cams, const gs_camera* dev_cams, const gs_medium* dev_medium,
                       float* out_rgb, float* out_depth, float* out_alpha, float* out_restored,
@@ -219,9 +234,10 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
  * parameter (activated scales and opacity) into `grads` (overwritten) and
  * grad_medium [n_views][9] = (dB_d[3], dB_b[3], dB_inf[3]) (overwritten).
  * opts, g, n_views, cameras and medium must equal those of the forward call
- * that produced `saved`.  If that forward overflowed the pair capacity
- * (GS_STATUS_PAIR_OVERFLOW), the adjoint kernels do nothing and every
- * gradient written is zero. */
+ * that produced `saved`.  If that forward's image was truncated
+ * (GS_STATUS_TRUNCATED: pair capacity overflow, or cut short by
+ * opts.phase_limit), the adjoint kernels do nothing and every gradient
+ * written is zero. */
 int gs_render_backward(const gs_options* opts, const gs_gaussians* g, int32_t n_views,
                        const gs_camera* host_cams, const gs_camera* dev_cams, const gs_medium* dev_medium,
                        const float* grad_rgb, const float* grad_depth, const float* grad_restored,
@@ -232,6 +248,15 @@ int gs_render_backward(const gs_options* opts, const gs_gaussians* g, int32_t n_
  * status_bits = OR of GS_STATUS_*, pairs_needed = pair count the last forward
  * produced (compare with opts.max_pairs).  Either output may be NULL. */
 int gs_read_status(const void* saved, uint32_t* status_bits, int64_t* pairs_needed, gs_stream_t stream);
+
+/* Synchronise `stream` and report in *phases (HOST) how many leading depth
+ * phases the forward that produced `saved` needed: the first phase after which
+ * no tile had a pixel above t_min, or no Gaussian was left unbinned, or else
+ * every phase of the schedule.  opts, n, n_views and host_cams must equal the
+ * forward's.  When that forward was itself cut short (GS_STATUS_INCOMPLETE),
+ * the value is one more than the phases it ran: a lower bound. */
+int gs_phases_needed(const gs_options* opts, int64_t n, int32_t n_views, const gs_camera* host_cams,
+                     const void* saved, size_t saved_bytes, int32_t* phases, gs_stream_t stream);
 
 /* Write the (tile, depth) key list of the last forward into caller buffers:
  * keys[k] = (global tile id << 32) | FP32 bits of the view depth, values[k] =
@@ -462,13 +487,14 @@ typedef struct gs_adam_group {
 /* Device-side training state of the Adam entry points: int32[2], zeroed by the
  * caller before the first step.
  *   state[0] : the Adam step counter t (incremented by each step that runs).
- *   state[1] : sticky skip flag.  A step whose forward context reports
- *              GS_STATUS_PAIR_OVERFLOW (its render was truncated) is not
+ *   state[1] : sticky skip flag.  A step whose forward context reports a
+ *              GS_STATUS_TRUNCATED bit (its render was truncated) is not
  *              applied: the counter, parameters, moments and activated copies
- *              stay unchanged and GS_STATUS_PAIR_OVERFLOW is OR-ed into
- *              state[1].  While state[1] != 0 every later step is skipped too,
- *              so a replayed graph cannot apply a bad step after an overflow;
- *              only the caller clears it (after growing the capacity). */
+ *              stay unchanged and that bit is OR-ed into state[1].  While
+ *              state[1] != 0 every later step is skipped too, so a replayed
+ *              graph cannot apply a bad step after a truncated render; only
+ *              the caller clears it (after growing the capacity, or lifting
+ *              opts.phase_limit). */
 #define GS_STATE_STEP 0
 #define GS_STATE_SKIP 1
 
@@ -496,7 +522,8 @@ typedef struct gs_adam_group {
  *               gradient [n_views][9].
  *   state      : DEVICE int32[2] training state (see GS_STATE_*): the step
  *                counter is incremented first and the incremented value is t;
- *                a forward that overflowed the pair capacity skips the step.
+ *                a forward whose image was truncated (GS_STATUS_TRUNCATED)
+ *                skips the step.
  * Only the m, v, param and activated arrays are written (plus workspace, state
  * and the medium group's grad).
  * Returns GS_ERR_INVALID_ARGUMENT on any mismatch; otherwise as gs_render_backward. */
@@ -516,8 +543,8 @@ int gs_adam_step(const gs_adam_group* host_groups, int32_t n_groups, float beta1
  * device memory.  state (DEVICE int32[2], see GS_STATE_*): state[0] is
  * incremented first and the incremented value is the step used for bias
  * correction (start it at 0).  saved (nullable) is the forward context the
- * gradients came from: when it reports GS_STATUS_PAIR_OVERFLOW, or state[1] is
- * already set, the step is skipped and the flag is kept in state[1]. */
+ * gradients came from: when it reports a GS_STATUS_TRUNCATED bit, or state[1]
+ * is already set, the step is skipped and the flag is kept in state[1]. */
 int gs_adam_step_device(const gs_adam_group* host_groups, int32_t n_groups, float beta1, float beta2, float eps,
                         int32_t* state, const void* saved, gs_stream_t stream);
 

@@ -18,6 +18,8 @@ GS_ERR_WORKSPACE_TOO_SMALL = -3
 GS_ERR_HIP = -4
 GS_STATUS_PAIR_OVERFLOW = 1
 GS_STATUS_NONFINITE_INPUT = 2
+GS_STATUS_INCOMPLETE = 4
+GS_STATUS_TRUNCATED = GS_STATUS_PAIR_OVERFLOW | GS_STATUS_INCOMPLETE
 GS_MAX_VIEWS = 64
 GS_MAX_PAIRS = 2_147_483_647
 GS_MAX_PHASES = 8
@@ -63,7 +65,7 @@ class GsOptions(ctypes.Structure):
                 ("phases", ctypes.c_int32), ("phase0_shift", ctypes.c_int32), ("depth_output", ctypes.c_int32),
                 ("phase_growth", ctypes.c_int32), ("max_pairs", ctypes.c_int64), ("timer", ctypes.c_void_p),
                 ("medium_prior", ctypes.c_void_p), ("prior_lambda", ctypes.c_float), ("reg_opacity", ctypes.c_float),
-                ("reg_scale", ctypes.c_float), ("reserved2", ctypes.c_int32)]
+                ("reg_scale", ctypes.c_float), ("phase_limit", ctypes.c_int32)]
 
 
 class GsAdamGroup(ctypes.Structure):
@@ -103,6 +105,8 @@ PROTOTYPES = {
                                                ctypes.POINTER(GsAdamGroup), ctypes.c_float, ctypes.c_float,
                                                ctypes.c_float, _P, _P, _SZ, _P]),
     "gs_read_status": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_I64), _P]),
+    "gs_phases_needed": (ctypes.c_int, [ctypes.POINTER(GsOptions), _I64, _I32, ctypes.POINTER(GsCamera), _P, _SZ,
+                                        ctypes.POINTER(_I32), _P]),
     "gs_export_keys": (ctypes.c_int, [ctypes.POINTER(GsOptions), _I64, _I32, ctypes.POINTER(GsCamera), _P, _SZ,
                                       _P, _P, _P, _I64, ctypes.POINTER(_I64), _P]),
     "gs_forward_stats": (ctypes.c_int, [ctypes.POINTER(GsOptions), _I64, _I32, ctypes.POINTER(GsCamera), _P, _SZ,

@@ -54,6 +54,7 @@ int compute_layout(const gs_options* o, int64_t n, int32_t n_views, const gs_cam
     if (o->phases < 0 || o->phases > GS_MAX_PHASES) return GS_ERR_INVALID_ARGUMENT;
     if (o->phase0_shift < 0 || o->phase0_shift > 20) return GS_ERR_INVALID_ARGUMENT;
     if (o->phase_growth < 0 || o->phase_growth > 4) return GS_ERR_INVALID_ARGUMENT;
+    if (o->phase_limit < 0 || o->phase_limit > GS_MAX_PHASES) return GS_ERR_INVALID_ARGUMENT;
     if (o->max_pairs < 0 || o->max_pairs > GS_MAX_PAIRS) return GS_ERR_INVALID_ARGUMENT;
     if (n * (int64_t)n_views >= (int64_t)0xFFFFFFFFLL) return GS_ERR_INVALID_ARGUMENT;
 
@@ -253,6 +254,7 @@ void gs_default_options(gs_options* o) {
     o->prior_lambda = 0.0f;
     o->reg_opacity = 0.0f;
     o->reg_scale = 0.0f;
+    o->phase_limit = 0;   // every phase of the schedule
 }
 
 const char* gs_version(void) { return "gsplash 0.3 (gfx950)"; }
@@ -344,9 +346,12 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
     // alive-column masks: phase p > 0 reads buffer p & 1, which the compositing of phase p - 1 set
     const int64_t bits_words = L.rows * L.row_words;
     uint64_t* bits = at<uint64_t>(workspace, L.w_rowbits);
-    for (int ph = 0; ph < L.phases; ++ph) {
+    // phases run: all of the schedule, or its first opts.phase_limit (the last one run checks that
+    // no tile is left alive with Gaussians unbinned; the backward reads the empty ranges of the rest)
+    const int run = o.phase_limit > 0 && o.phase_limit < L.phases ? o.phase_limit : L.phases;
+    for (int ph = 0; ph < run; ++ph) {
         const AliveRows ar{bits + (ph & 1) * bits_words, (uint32_t)L.row_words, at<uint32_t>(workspace, L.w_nzr)};
-        uint64_t* next_bits = ph + 1 < L.phases ? bits + ((ph + 1) & 1) * bits_words : nullptr;
+        uint64_t* next_bits = ph + 1 < run ? bits + ((ph + 1) & 1) * bits_words : nullptr;
         timer_begin(T, "count_scan", s);
         GS_TRY(launch_count_scan(order, counts, rects, L.nv, L.n, vt, ar, next_bits, bits_words, ps, hdr, ph, pcounts,
                                  offsets, blocksums, L.max_pairs, emit_start, s));
@@ -369,9 +374,9 @@ int gs_render_forward(const gs_options* opts, const gs_gaussians* g, int32_t n_v
         if (o.persistent == 2)
             GS_TRY(build_queue(L, ranges, ph, ph + 1, at<uint32_t>(workspace, L.w_queue), hist, &order, T, s));
         timer_begin(T, "composite_fwd", s);
-        GS_TRY(launch_composite_fwd(o, L, ph, vt, dev_medium, rec, ranges, vals, hdr, alive, out_rgb, out_depth,
-                                    out_alpha, out_restored, tfinal, nlast, done, cair, dsum, wsum, order, next_bits,
-                                    s));
+        GS_TRY(launch_composite_fwd(o, L, ph, run - 1, vt, dev_medium, rec, ranges, vals, hdr, alive, out_rgb,
+                                    out_depth, out_alpha, out_restored, tfinal, nlast, done, cair, dsum, wsum, order,
+                                    next_bits, s));
         timer_end(T, s);
     }
     return GS_OK;
@@ -400,8 +405,9 @@ int gs_render_backward(const gs_options* opts, const gs_gaussians* g, int32_t n_
     float* grad2d = at<float>(workspace, L.w_grad2d);
     uint32_t* med_done = reinterpret_cast<uint32_t*>(grad2d) + L.nv * kGrad2D;   // zeroed with grad2d
     float* medpart = at<float>(workspace, L.w_medpart);
-    // a truncated forward (pair overflow) gives no gradient: the 2D gradients stay zero
-    const Guard guard{&hdr->status, GS_STATUS_PAIR_OVERFLOW};
+    // a truncated forward (pair overflow, or cut short by phase_limit) gives no gradient: the 2D
+    // gradients stay zero
+    const Guard guard{&hdr->status, GS_STATUS_TRUNCATED};
 
     timer_begin(T, "zero_grad2d", s);
     GS_TRY(launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, L.nv * kGrad2D + GS_MAX_VIEWS, s));
@@ -535,6 +541,25 @@ int gs_read_status(const void* saved, uint32_t* status_bits, int64_t* pairs_need
     GS_TRY(hipStreamSynchronize(s));
     if (status_bits) *status_bits = h.status;
     if (pairs_needed) *pairs_needed = (int64_t)h.pairs_needed;
+    return GS_OK;
+}
+
+int gs_phases_needed(const gs_options* opts, int64_t n, int32_t n_views, const gs_camera* host_cams,
+                     const void* saved, size_t saved_bytes, int32_t* phases, gs_stream_t stream) {
+    Layout L;
+    const int rc = compute_layout(opts, n, n_views, host_cams, &L);
+    if (rc != GS_OK) return rc;
+    if (!saved || !phases) return GS_ERR_INVALID_ARGUMENT;
+    if (saved_bytes < L.saved_bytes) return GS_ERR_WORKSPACE_TOO_SMALL;
+    SavedHeader h;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GS_TRY(hipMemcpyAsync(&h, at<SavedHeader>(saved, L.s_header), sizeof(h), hipMemcpyDeviceToHost, s));
+    GS_TRY(hipStreamSynchronize(s));
+    // phase k - 1 ends at depth rank phase_rank[k] (recorded by each phase that ran with a tile
+    // alive); the forward needed phase k only while a tile was alive and Gaussians were left
+    int k = 1;
+    while (k < L.phases && h.phase_alive[k - 1] != 0 && h.phase_rank[k] < h.visible) ++k;
+    *phases = k;
     return GS_OK;
 }
 

@@ -50,6 +50,12 @@ struct FwdArgs {
     uint32_t* view_alive;     // [views]: tiles of each view left alive
     uint64_t* rowbits;        // nullable: per global tile row, the bits of the tiles left alive
     uint32_t row_words;
+    // status (nullable) is set when this phase ends a forward cut short by phase_limit: a tile
+    // left alive while *rank_end (the end of the depth ranks binned so far) < *visible (Gaussians
+    // are left unbinned) ORs GS_STATUS_INCOMPLETE into it
+    uint32_t* status;
+    const uint32_t* rank_end;
+    const uint32_t* visible;
     float* out_rgb;
     float* out_depth;
     float* out_alpha;
@@ -514,6 +520,7 @@ __global__ __launch_bounds__((Shape<TW, TH, PPL>::THREADS)) void k_composite_fwd
                                  (size_t)(vi.row_base + ty) * a.row_words + (tx >> 6),
                              1ull << (tx & 63));
                 }
+                if (a.status && *a.rank_end < *a.visible) atomicOr(a.status, GS_STATUS_INCOMPLETE);
             }
         }
     }
@@ -1080,19 +1087,19 @@ hipError_t build_queue(const Layout& L, const uint2* ranges, int p0, int p1, uin
     return hipGetLastError();
 }
 
-hipError_t launch_composite_fwd(const gs_options& o, const Layout& L, int phase, const ViewInfo* vt,
+hipError_t launch_composite_fwd(const gs_options& o, const Layout& L, int phase, int last_phase, const ViewInfo* vt,
                                 const gs_medium* med, const Record* rec, const uint2* ranges, const uint32_t* vals,
                                 SavedHeader* hdr, uint32_t* alive, float* out_rgb, float* out_depth,
                                 float* out_alpha, float* out_restored, float* tfinal, uint32_t* nlast, uint8_t* done,
                                 float* cair, float* dsum, float* wsum, const uint32_t* order, uint64_t* rowbits,
                                 hipStream_t s) {
     if (L.tiles == 0) return hipSuccess;
-    FwdArgs a{vt, L.views, (uint32_t)L.tiles, phase, L.phases - 1, med, rec, ranges + (size_t)phase * L.tiles, vals,
+    const bool cut = phase == last_phase && last_phase < L.phases - 1;
+    FwdArgs a{vt, L.views, (uint32_t)L.tiles, phase, last_phase, med, rec, ranges + (size_t)phase * L.tiles, vals,
               &hdr->queue[phase], order, alive, &hdr->phase_alive[phase], hdr->view_alive[phase], rowbits,
-              (uint32_t)L.row_words, out_rgb,
-              out_depth, out_alpha,
-              out_restored, tfinal, nlast, done, cair, dsum, wsum, L.pixels, o.alpha_min, o.alpha_max, o.t_min,
-              o.depth_mode, o.depth_output};
+              (uint32_t)L.row_words, cut ? &hdr->status : nullptr, &hdr->phase_rank[phase + 1], &hdr->visible,
+              out_rgb, out_depth, out_alpha, out_restored, tfinal, nlast, done, cair, dsum, wsum, L.pixels,
+              o.alpha_min, o.alpha_max, o.t_min, o.depth_mode, o.depth_output};
     return dispatch_shape<FwdRun>(o, a, o.persistent != 0, false, s);
 }
 

@@ -225,7 +225,10 @@ hipError_t launch_commit(const uint32_t* sorted_tiles, const SavedHeader* hdr, i
                          int64_t max_pairs, uint2* ranges, hipStream_t s);
 // out_restored (nullable): the in-air composite C_air per pixel, CHW per view like out_rgb.
 // rowbits (nullable, zeroed beforehand): the bit of every tile left alive is set there.
-hipError_t launch_composite_fwd(const gs_options& o, const Layout& L, int phase, const ViewInfo* vt,
+// last_phase: the last phase this forward runs (tiles write their outputs there); when it
+// is before the schedule's last phase, a tile left alive with Gaussians still unbinned sets
+// GS_STATUS_INCOMPLETE.
+hipError_t launch_composite_fwd(const gs_options& o, const Layout& L, int phase, int last_phase, const ViewInfo* vt,
                                 const gs_medium* med, const Record* rec, const uint2* ranges, const uint32_t* vals,
                                 SavedHeader* hdr, uint32_t* alive, float* out_rgb, float* out_depth,
                                 float* out_alpha, float* out_restored, float* tfinal, uint32_t* nlast, uint8_t* done,

@@ -98,11 +98,12 @@ struct AdamArgs {
                                      // (state[0]) and the step is skipped while state[1] != 0
 };
 
-// Start of a device-counted step: a forward that overflowed the pair capacity (status, may be
-// null) sets the sticky skip flag; the counter advances only for a step that runs.
+// Start of a device-counted step: a forward whose image was truncated (pair overflow, or cut
+// short by phase_limit; status may be null) sets the sticky skip flag; the counter advances
+// only for a step that runs.
 __device__ __forceinline__ bool step_begin(int32_t* state, const uint32_t* status) {
     const uint32_t st = status ? *status : 0u;
-    uint32_t skip = (uint32_t)state[GS_STATE_SKIP] | (st & GS_STATUS_PAIR_OVERFLOW);
+    uint32_t skip = (uint32_t)state[GS_STATE_SKIP] | (st & GS_STATUS_TRUNCATED);
     state[GS_STATE_SKIP] = (int32_t)skip;
     if (skip) return false;
     state[GS_STATE_STEP] += 1;

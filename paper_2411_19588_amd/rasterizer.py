@@ -36,6 +36,9 @@ class RasterConfig:
     phases: int = 0                   # 0 = automatic (the library's gs_schedule)
     phase0_shift: int = 0             # 0 = automatic
     phase_growth: int = 0             # log2 of the later phases' growth; 0 = automatic (4x)
+    phase_limit: int = 0              # run only the first phase_limit depth phases (0 = all); a forward
+                                      # left with an unterminated tile and unbinned Gaussians reports
+                                      # GS_STATUS_INCOMPLETE
     max_pairs: int = 1 << 22
     reg_opacity: float = 0.0          # lambda_o of the opacity regulariser lambda_o mean(o) (0 = off)
     reg_scale: float = 0.0            # lambda_s of the scale regulariser lambda_s mean(s) (0 = off)
@@ -60,6 +63,7 @@ class RasterConfig:
         o.phases = int(self.phases)
         o.phase0_shift = int(self.phase0_shift)
         o.phase_growth = int(self.phase_growth)
+        o.phase_limit = int(self.phase_limit)
         o.max_pairs = int(self.max_pairs if max_pairs is None else max_pairs)
         o.timer = timer
         o.reg_opacity = float(self.reg_opacity)
@@ -176,7 +180,8 @@ class Rasterizer:
 
         With check=True the status word is read after the forward (one host
         synchronisation); on pair-capacity overflow the capacity is grown to
-        what the forward needed and the render is repeated.  With restored=True
+        what the forward needed and the render is repeated, and a render that
+        config.phase_limit cut short is repeated with every phase.  With restored=True
         the clean image J = C_air (packed like rgb) is returned in ctx.restored.
         """
         means, scales, quats, opacity, sh = map(_f32, (means, scales, quats, opacity, sh))
@@ -185,6 +190,7 @@ class Rasterizer:
         mp = int(self.max_pairs if max_pairs is None else max_pairs)
         L = N.lib()
         g = self._gaussians(means, scales, quats, opacity, sh, sh_degree)
+        full = False   # set after a forward that config.phase_limit cut short: render every phase
         while True:
             ws_b, sv_b = self.sizes_for(n, mp)
             ws = self.workspace(ws_b)
@@ -194,6 +200,8 @@ class Rasterizer:
             alpha = torch.empty(self.total_pixels, dtype=torch.float32, device=self.device)
             rest = torch.empty(3 * self.total_pixels, dtype=torch.float32, device=self.device) if restored else None
             o = self.config.to_c(mp, self.timer)
+            if full:
+                o.phase_limit = 0
             N.check("gs_render_forward", L.gs_render_forward(
                 ctypes.byref(o), ctypes.byref(g), self.n_views, self.host_cams, _ptr(self.dev_cams), _ptr(medium),
                 _ptr(rgb), _ptr(depth), _ptr(alpha), _ptr(rest), _ptr(saved), sv_b, _ptr(ws), ws_b,
@@ -206,6 +214,9 @@ class Rasterizer:
                     raise RuntimeError(f"{needed} (Gaussian, tile) pairs exceed the 32-bit pair index")
                 mp = min(N.GS_MAX_PAIRS, int(needed * 1.25) + 1024)
                 self.max_pairs = mp
+                continue
+            if status & N.GS_STATUS_INCOMPLETE:
+                full = True
                 continue
             break
         host_copy = (N.GsCamera * self.n_views)()
@@ -253,6 +264,15 @@ class Rasterizer:
         N.check("gs_read_status", N.lib().gs_read_status(_ptr(saved), ctypes.byref(st), ctypes.byref(need),
                                                          _stream(stream)))
         return int(st.value), int(need.value)
+
+    def phases_needed(self, saved: torch.Tensor, n: int, max_pairs: int, stream=None) -> int:
+        """Leading depth phases the forward that wrote `saved` needed (gs_phases_needed; synchronises)."""
+        k = ctypes.c_int32()
+        o = self.config.to_c(max_pairs)
+        N.check("gs_phases_needed", N.lib().gs_phases_needed(ctypes.byref(o), int(n), self.n_views, self.host_cams,
+                                                             _ptr(saved), saved.numel(), ctypes.byref(k),
+                                                             _stream(stream)))
+        return int(k.value)
 
     def export_keys(self, ctx: ForwardContext, stream=None):
         """Stored (tile << 32 | depth bits) keys, values (view * n + index) and per-phase tile ranges

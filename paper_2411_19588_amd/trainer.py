@@ -24,11 +24,14 @@ A step whose forward overflows the pair capacity is not applied: the device
 training state (`state`, int32[2]: step counter, sticky skip flag) records it,
 every later step is skipped too until `clear_skip()` (after the capacity has
 been grown), so a replayed graph never updates the parameters from a truncated
-render.
+render.  The same holds for a forward that `set_phase_limit()` cut short while a
+tile was still unterminated (GS_STATUS_INCOMPLETE); `fit_phase_limit()` picks
+the limit from a render with every phase, for replays of a fixed scene.
 """
 from __future__ import annotations
 
 import ctypes
+import dataclasses
 from typing import Optional, Sequence
 
 import torch
@@ -138,6 +141,30 @@ class TrainStep:
         if want > self.max_pairs:
             self.set_capacity(want)
         return need
+
+    # ------------------------------------------------------------------ depth phases
+    def set_phase_limit(self, limit: int) -> None:
+        """Run only the first `limit` depth phases of the schedule (0 = all; drops any graph).  A
+        forward that the limit cuts short while a tile is unterminated and Gaussians are left
+        unbinned reports GS_STATUS_INCOMPLETE: its step is not applied and the sticky skip flag is
+        set, as after a pair-capacity overflow."""
+        self.destroy_graph()
+        self.rast.config = dataclasses.replace(self.rast.config, phase_limit=int(limit))
+        self.opts.phase_limit = int(limit)
+
+    def fit_phase_limit(self) -> int:
+        """Render once with every phase, then run only the leading phases that render needed
+        (gs_phases_needed): for replays of a fixed scene, the same images without the launches of
+        phases that would blend nothing.  Returns the limit."""
+        self.set_phase_limit(0)
+        s = torch.cuda.current_stream(self.device)
+        self._forward(s)
+        st, _ = self.rast.read_status(self.saved, s)
+        if st & N.GS_STATUS_PAIR_OVERFLOW:
+            raise RuntimeError("the forward overflowed the pair capacity: call size_capacity() first")
+        k = self.rast.phases_needed(self.saved, self.n, self.max_pairs, s)
+        self.set_phase_limit(k)
+        return k
 
     # ------------------------------------------------------------------ step
     def _forward(self, stream) -> None:

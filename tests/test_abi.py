@@ -58,6 +58,7 @@ def test_default_options_and_version():
     assert o.alpha_min == pytest.approx(1 / 255) and o.alpha_max == pytest.approx(0.99)
     assert o.t_min == pytest.approx(1e-4) and o.kappa == pytest.approx(11.1)
     assert o.medium_prior is None and o.prior_lambda == 0 and o.reg_opacity == 0 and o.reg_scale == 0
+    assert o.phase_limit == 0
     b = N.GsBackscatterOptions()
     N.lib().gs_default_backscatter_options(ctypes.byref(b))
     assert (b.edges, b.intervals, b.resize_height) == (10, 25, 300) and b.p_dark == pytest.approx(0.01)
@@ -123,7 +124,8 @@ def test_workspace_query_and_tile_count():
     ("record_fetch", -1, N.GS_ERR_INVALID_ARGUMENT), ("phase0_shift", 21, N.GS_ERR_INVALID_ARGUMENT),
     ("phase0_shift", -1, N.GS_ERR_INVALID_ARGUMENT), ("tile_cull", 2, N.GS_ERR_INVALID_ARGUMENT),
     ("phases", 9, N.GS_ERR_INVALID_ARGUMENT), ("phases", -1, N.GS_ERR_INVALID_ARGUMENT),
-    ("depth_output", 2, N.GS_ERR_INVALID_ARGUMENT), ("depth_output", -1, N.GS_ERR_INVALID_ARGUMENT)])
+    ("depth_output", 2, N.GS_ERR_INVALID_ARGUMENT), ("depth_output", -1, N.GS_ERR_INVALID_ARGUMENT),
+    ("phase_limit", 9, N.GS_ERR_INVALID_ARGUMENT), ("phase_limit", -1, N.GS_ERR_INVALID_ARGUMENT)])
 def test_bad_options_rejected(field, value, code):
     sc = synth.make_scene(0, n=10)
     cams = N.camera_array(sc.cameras)
@@ -152,6 +154,12 @@ def test_bad_arguments_rejected_before_any_device_work():
     rc = L.gs_render_forward(ctypes.byref(o), ctypes.byref(g), 0, cams, 1, 1, 1, 1, 1, None, 1, 16, 1, 16, None)
     assert rc == N.GS_ERR_INVALID_ARGUMENT
     assert L.gs_read_status(None, None, None, None) == N.GS_ERR_INVALID_ARGUMENT
+    k = ctypes.c_int32()
+    assert L.gs_phases_needed(ctypes.byref(o), 10, 1, cams, None, 1 << 40, ctypes.byref(k), None) == \
+        N.GS_ERR_INVALID_ARGUMENT
+    assert L.gs_phases_needed(ctypes.byref(o), 10, 1, cams, 1, 16, ctypes.byref(k), None) == \
+        N.GS_ERR_WORKSPACE_TOO_SMALL
+    assert L.gs_phases_needed(ctypes.byref(o), 10, 1, cams, 1, 1 << 40, None, None) == N.GS_ERR_INVALID_ARGUMENT
     assert L.gs_activate(-1, None, None, None, None, None) == N.GS_ERR_INVALID_ARGUMENT
     assert L.gs_activation(5, 3, 1, 1, None) == N.GS_ERR_INVALID_ARGUMENT
     assert L.gs_activation(5, 1, None, 1, None) == N.GS_ERR_INVALID_ARGUMENT
