@@ -60,6 +60,26 @@ def test_grad_vs_oracle_sh_degree0_config0(oracle_mod):
     _check_all(got, O.backward(sc, cam, sc.medium[0], G))
 
 
+def test_grad_vs_oracle_opacity_edge_values(oracle_mod):
+    """Opacities of 0, below 0, 1e-30 and 1 mixed in: the adjoint forms the opacity term as
+    (sum of dalpha * raw alpha) / o from the record's 1/o, which is 0 for o <= 0."""
+    O = oracle_mod
+    sc = synth.make_scene(0)
+    op = sc.opacity.copy()
+    op[0::7] = 0.0
+    op[1::7] = -0.25
+    op[2::7] = 1e-30
+    op[3::7] = 1.0
+    sc = dataclasses.replace(sc, opacity=op)
+    cam = sc.cameras[0]
+    G = np.random.default_rng(11).normal(size=(cam.width * cam.height, 3))
+    G, _, n_amb = U.unambiguous(O, sc, 0, G)
+    U.say(f"grad edge opacities, ambiguous pixels {n_amb}")
+    got = _gpu_grads(sc, U.make_rast(sc), G)
+    _check_all(got, O.backward(sc, cam, sc.medium[0], G))
+    assert np.all(got["opacity"][0::7] == 0.0) and np.all(got["opacity"][1::7] == 0.0)
+
+
 @pytest.mark.parametrize("cfg", [dict(lds_batch=256), dict(persistent=True), dict(tile=8, lds_batch=64),
                                  dict(record_fetch="lds"), dict(record_fetch="lds", pixels_per_lane=2, lds_batch=128),
                                  dict(record_fetch="lds", pixels_per_lane=4, persistent=True),

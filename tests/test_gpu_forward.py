@@ -1,4 +1,6 @@
 """GPU parity of the forward path: keys bit-exact, images within 1e-4 of the FP64 oracle."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -234,6 +236,25 @@ def _image_match(scene, rast, O, opts=None, v=0):
 def test_image_config0(oracle_mod):
     sc = synth.make_scene(0)
     U.say("image config0")
+    n_main, n_var, worst = _image_match(sc, U.make_rast(sc), oracle_mod)
+    U.say(f"  main {n_main} variant {n_var} worst {worst:.2e}")
+
+
+def _edge_opacity_scene():
+    """The 1,000-Gaussian scene with opacities of exactly 0, below 0, 1e-30 and 1 mixed in (the
+    record stores log2 o and 1/o: an opacity <= 0 stores -inf and 0 and must never blend)."""
+    sc = synth.make_scene(0)
+    op = sc.opacity.copy()
+    op[0::7] = 0.0
+    op[1::7] = -0.25
+    op[2::7] = 1e-30
+    op[3::7] = 1.0
+    return dataclasses.replace(sc, opacity=op)
+
+
+def test_image_opacity_edge_values(oracle_mod):
+    sc = _edge_opacity_scene()
+    U.say("image with edge opacities")
     n_main, n_var, worst = _image_match(sc, U.make_rast(sc), oracle_mod)
     U.say(f"  main {n_main} variant {n_var} worst {worst:.2e}")
 
