@@ -50,7 +50,10 @@ __device__ __forceinline__ bool tile_may_contribute(const float4& ra, const floa
     if (xl <= 0.0f && xr >= 0.0f && yl <= 0.0f && yr >= 0.0f) {
         best = 0.0f;
     } else {
-        const float hy = -0.5f * B / C, hx = -0.5f * B / A;   // vertex of the edge quadratics, per unit offset
+        // vertex of the edge quadratics, per unit offset.  A hardware reciprocal suffices: off the
+        // vertex by a few ulp, a concave quadratic falls below its maximum by a second-order
+        // amount (about C (eps y)^2), far inside the rounding margin below
+        const float hy = -0.5f * B * __builtin_amdgcn_rcpf(C), hx = -0.5f * B * __builtin_amdgcn_rcpf(A);
         best = expo(xl, fminf(fmaxf(hy * xl, yl), yr));
         best = fmaxf(best, expo(xr, fminf(fmaxf(hy * xr, yl), yr)));
         best = fmaxf(best, expo(fminf(fmaxf(hx * yl, xl), xr), yl));
@@ -130,13 +133,31 @@ __device__ __forceinline__ uint32_t alive_in(const uint64_t* __restrict__ bits, 
 constexpr int kCountThreads = 1024;
 constexpr int kCountItems = kScanChunk / kCountThreads;
 
+// Unsigned division by a divisor fixed for a launch: with m = ceil(2^32 / d) (d >= 2),
+// e m / 2^32 lies in [e / d, e / d + 1), so its floor is floor(e / d) or one more, which one
+// product tells apart.  d = 1 is marked by m = 0.
+struct DivU32 {
+    uint32_t d, m;
+};
+
+inline DivU32 make_divu32(uint32_t d) {
+    return {d, d > 1 ? (uint32_t)(((1ull << 32) + d - 1) / d) : 0u};
+}
+
+__device__ __forceinline__ uint32_t divu32(uint32_t e, const DivU32& v) {
+    if (v.m == 0u) return e;
+    uint32_t q = __umulhi(e, v.m);
+    if ((uint64_t)q * v.d > (uint64_t)e) --q;
+    return q;
+}
+
 __global__ __launch_bounds__(kCountThreads) void k_phase_counts(const uint32_t* __restrict__ order,
                                                                const uint32_t* __restrict__ counts,
                                                                const uint2* __restrict__ rects, int64_t nv, int64_t n,
                                                                const ViewInfo* __restrict__ vt,
                                                                const uint64_t* __restrict__ rowbits,
                                                                uint32_t row_words, const SavedHeader* __restrict__ hdr,
-                                                               int phase, PhaseSched ps,
+                                                               int phase, PhaseSched ps, DivU32 per_view,
                                                                uint32_t* __restrict__ pcounts,
                                                                uint64_t* __restrict__ blocksums, int nb) {
     __shared__ uint64_t red[kCountThreads / 64];
@@ -170,7 +191,7 @@ __global__ __launch_bounds__(kCountThreads) void k_phase_counts(const uint32_t* 
         for (int k = 0; k < kCountItems; ++k) {
             c[k] = 0u;
             if (e[k] == kNone) continue;
-            const uint32_t view = e[k] / (uint32_t)n;
+            const uint32_t view = divu32(e[k], per_view);   // e[k] / n
             if (hdr->view_alive[phase - 1][view] == 0u) continue;   // every tile of the view terminated
             const uint2 rc = rects[e[k]];
             const uint32_t rb = vt[view].row_base;
@@ -528,6 +549,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_spans(const uint32_t* __restric
                                                       uint32_t* __restrict__ vals_out) {
     __shared__ int32_t s_off[kEmitSpanLater + 1];   // entry: first pair, relative to the span
     __shared__ uint32_t s_e[kEmitSpanLater + 1];    // entry: (view, Gaussian) index
+    __shared__ uint8_t s_ev[kEmitSpanLater + 1];    // entry: its view (one division per entry, not per pair)
     __shared__ int32_t s_cover[kEmitSpanLater];     // item position at its first pair, -1 elsewhere; then the running max
     __shared__ int32_t s_ist[kEmitSpanLater];       // item: first pair, relative to the span (< 0 for a row begun before)
     __shared__ uint32_t s_ilohi[kEmitSpanLater];    // item: column range lo | hi << 16
@@ -564,7 +586,9 @@ __global__ __launch_bounds__(kBlock) void k_emit_spans(const uint32_t* __restric
     for (int j = tid; j < nent; j += kBlock) {
         const uint32_t e = s_e[j];
         const uint2 rc = rects[e];
-        const ViewInfo vi = vt[e / (uint32_t)n];
+        const uint32_t view = e / (uint32_t)n;
+        s_ev[j] = (uint8_t)view;
+        const ViewInfo vi = vt[view];
         const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu, y1 = rc.y >> 16;
         int32_t st = s_off[j];
         for (uint32_t ty = y0; ty <= y1 && st < span; ++ty) {
@@ -619,7 +643,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_spans(const uint32_t* __restric
         }
         const uint32_t jy = s_ijy[pos], lohi = s_ilohi[pos];
         const uint32_t e = s_e[jy & 0xFFFFu], ty = jy >> 16, lo = lohi & 0xFFFFu, hi = lohi >> 16;
-        const ViewInfo vi = vt[e / (uint32_t)n];
+        const ViewInfo vi = vt[s_ev[jy & 0xFFFFu]];
         float4 ra;
         float2 rb;
         if (cull.enabled) {
@@ -716,7 +740,7 @@ hipError_t launch_count_scan(const uint32_t* order, const uint32_t* counts, cons
     const int64_t n_spans = max_pairs / kEmitSpan0 + 2;
     if (nb > 0)
         hipLaunchKernelGGL(k_phase_counts, dim3(nb), dim3(kCountThreads), 0, s, order, counts, rects, nv, n, vt, ar.bits,
-                           ar.words, hdr, phase, ps, pcounts, blocksums, nb);
+                           ar.words, hdr, phase, ps, make_divu32((uint32_t)n), pcounts, blocksums, nb);
     hipLaunchKernelGGL(k_count_blocks, dim3(1), dim3(1024), 0, s, blocksums, nb, hdr, phase, ps, max_pairs, zero_bits,
                        zero_words);
     if (nb > 0)
