@@ -1,6 +1,8 @@
 """Running only the leading depth phases (gs_options.phase_limit): the same images and gradients
 as the full schedule when the phases left out would blend nothing, and a truncated render
 (GS_STATUS_INCOMPLETE) that gives no gradient and no Adam step when they would not."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -28,14 +30,19 @@ def _grads(sc, rast, ctx, d, seed=3):
     return [t.clone() for t in out]
 
 
-def test_limit_to_the_phases_needed_is_exact():
+@pytest.mark.parametrize("views", [1, 2])
+def test_limit_to_the_phases_needed_is_exact(views):
     """1M Gaussians of the 1080p training scene at 480x270 with a 3-phase schedule (nearest 1/128,
-    1/32, rest): the tiles terminate early, so fewer phases are needed; a render limited to them
-    reports no truncation, equals the full render bit for bit, and so does its gradient up to the
-    order of the float atomics."""
+    1/32, rest), as one view or as two views of the same pose with different media: the tiles
+    terminate early, so fewer phases are needed; a render limited to them reports no truncation,
+    equals the full render bit for bit, and so does its gradient up to the order of the float
+    atomics."""
     sc = synth.make_scene(2, width=480, height=270, with_target=False)
+    if views == 2:
+        med = np.stack([sc.medium[0], sc.medium[0][::-1].copy()]).astype(np.float32)
+        sc = dataclasses.replace(sc, cameras=[sc.cameras[0], sc.cameras[0]], medium=med)
     cfg = dict(phases=3, phase0_shift=7, phase_growth=2, max_pairs=1 << 24)
-    U.say("phase limit: full render")
+    U.say(f"phase limit: full render, {views} view(s)")
     rast, rgb, depth, alpha, ctx, d = _render(sc, **cfg)
     st, _ = rast.read_status(ctx.saved)
     assert st == 0
