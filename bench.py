@@ -391,6 +391,15 @@ def main_record(C: Ctx, sc, cfg, copy_gbs: float):
     if st & N.GS_STATUS_TRUNCATED or ts.skipped():
         raise SystemExit(f"a timed step rendered a truncated image (status {st}, skip flag {ts.skipped()}; "
                          f"{K} stored pairs, capacity {ts.max_pairs})")
+    ms_all = None
+    if limit and not args.eager:
+        # the same replays with every depth phase, for comparison (the limit is restored after)
+        ts.set_phase_limit(0)
+        ms_all = time_graph(C, ts.enqueue, args.steps, args.warmup)
+        log(f"graph, every depth phase: {ms_all:.3f} ms/step")
+        ts.set_phase_limit(limit)
+        ts.enqueue(C.stream)
+        C.sync()
     stats = forward_stats(C, ts)
     _, _, rng = ts.rast.export_keys(R.ForwardContext(ts.saved, ts.max_pairs, ts.n, sc.sh_degree), C.stream)
     rng = rng.to(torch.int64)
@@ -410,7 +419,8 @@ def main_record(C: Ctx, sc, cfg, copy_gbs: float):
         f"E/pixel {E / P:.1f}, blended/pixel {Cb / P:.1f}, live pairs {K_live}, per phase {phase_pairs}")
     table = kernel_table(kernels, args.steps, sc, K_live, P, tiles, args.fused_adam, E, Cb, copy_gbs)
     info = dict(ts=ts, ms=ms, eager_ms=eager_ms, kernels=table, K=K, K_full=K_full, K_live=K_live, E=E, Cb=Cb,
-                phases=phases, shift=shift, phase_pairs=phase_pairs, P=P, tiles=tiles, phase_limit=limit)
+                phases=phases, shift=shift, phase_pairs=phase_pairs, P=P, tiles=tiles, phase_limit=limit,
+                ms_all_phases=ms_all)
     return info
 
 
@@ -856,6 +866,7 @@ def main():
                    "phases": info["phases"], "phase0_shift": info["shift"],
                    "phase_growth": args.phase_growth or 2,
                    "phase_limit": info["phase_limit"],
+                   "ms_per_step_every_phase": round(info["ms_all_phases"], 4) if info["ms_all_phases"] else None,
                    "mode": "eager" if args.eager else "hip_graph",
                    "learning_rates": "paper's (scene changes while timed)" if args.train else
                    "0 (Adam reads and writes every byte; the scene stays fixed)",
